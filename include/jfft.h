@@ -1,0 +1,170 @@
+/*
+ * jfft.h -- C ABI of the MI355X (gfx950) J-FFT solver: preconditioned
+ * conjugate gradients for the periodic small-strain linear-elastic cell
+ * problem on a regular grid, with the Green-Jacobi preconditioner
+ *     M^-1 = J^1/2 F^-1 G^ F J^1/2
+ * of Ladecky et al., "Jacobi-accelerated FFT-based solver for smooth
+ * high-contrast data" (arXiv:2508.02613), Sec. 3.3, eq. prec_lin_systemJG_2.
+ *
+ * Discretisation (Sec. 2.1, eq. disc_wf / lin_system_exp): bilinear quads
+ * (2D, plane strain) or trilinear hexes (3D) with 2^d Gauss points, nodal
+ * unknowns u in R^{d N}, stiffness K = B^T W C(E) B with C_e = E_e C^,
+ * C^ isotropic.  Pixel-wise constant material: E_e is the value of the element
+ * whose lowest-index corner is node e (Sec. 4, material data sampling).
+ *
+ * Conventions shared by every entry point:
+ *   - Grid: n[0] x n[1] (x n[2]) nodes, x fastest; periodic; lengths len[a]
+ *     (NULL = unit cell); every n[a] must be even (Algorithm 2 needs it) and
+ *     a product of 2, 3, 5 (FFT radices), 2 <= n[a] <= 512.
+ *   - Device arrays are raw device pointers on the cell's device, allocated
+ *     and owned by the caller.  Scalar fields E have N = prod n[a] doubles;
+ *     vector fields have d*N doubles, component-major ([a][node]).
+ *   - Mandel notation, order (11,22,33,23,13,12) in 3D and (11,22,12) in 2D,
+ *     shear entries carry sqrt(2).
+ *   - All device work is stream-ordered on the stream given at creation; the
+ *     entry points that return host values synchronise that stream.
+ *   - No entry point throws; each returns a jfft_status.  jfft_last_error()
+ *     returns a thread-local message describing the last failure.
+ *   - A cell is not thread-safe.  Distinct cells may be used from distinct
+ *     threads on distinct streams.
+ */
+#ifndef JFFT_H
+#define JFFT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct jfft_cell_s *jfft_cell_t;
+
+typedef enum {
+  JFFT_OK = 0,
+  JFFT_E_INVALID = 1,       /* bad argument (dim, sizes, tol, NaN/negative E, nu) */
+  JFFT_E_ODD_GRID = 2,      /* Algorithm 2 (Sec. 3.2) needs an even node count per axis */
+  JFFT_E_NO_MATERIAL = 3,   /* jfft_set_material not called yet */
+  JFFT_E_NOT_CONVERGED = 4, /* maxit reached; the last iterate is still written */
+  JFFT_E_BREAKDOWN = 5,     /* p^T q <= 0 or a non-finite CG scalar */
+  JFFT_E_OOM = 6,           /* workspace too small or allocation failure */
+  JFFT_E_HIP = 7            /* a HIP runtime call failed */
+} jfft_status;
+
+typedef enum {
+  JFFT_PC_NONE = 0,         /* M^-1 = I */
+  JFFT_PC_GREEN = 1,        /* M^-1 = F^-1 G^ F (eq. prec_lin_systemG_FFT) */
+  JFFT_PC_JACOBI = 2,       /* M^-1 = diag(K)^-1 (eq. prec_lin_systemJ) */
+  JFFT_PC_GREEN_JACOBI = 3  /* M^-1 = J^1/2 F^-1 G^ F J^1/2 (eq. prec_lin_systemJG_2) */
+} jfft_precond;
+
+typedef enum {
+  JFFT_FP64 = 0,  /* every step in double precision */
+  JFFT_MIXED = 1  /* FP32 stencil/FFT/preconditioner/vectors, FP64 dots, alpha/beta,
+                     iterate and an outer iterative-refinement residual with an FP64 K */
+} jfft_precision;
+
+/* Per-solve report (host struct filled by jfft_solve). */
+typedef struct {
+  int iters;            /* PCG iterations = updates of u (FP64), or total inner iterations (MIXED) */
+  int outer;            /* iterative-refinement sweeps (MIXED), 1 for FP64 */
+  int status;           /* jfft_status of the solve */
+  double rel_res;       /* ||r_k|| / ||f|| of the recursive residual at stop (FP64 path) */
+  double rel_res_true;  /* ||f - K u|| / ||f|| recomputed with the FP64 stiffness after the solve */
+  double setup_ms;      /* device time of the right-hand side and start residual */
+  double loop_ms;       /* device time of the PCG loop (all sweeps) */
+  double post_ms;       /* device time of mean removal, true residual and stresses */
+} jfft_report;
+
+/* Create a cell for a dim-dimensional grid.  dim in {2, 3}; n[a] nodes per axis
+   (n[2] ignored in 2D); len = cell side lengths (NULL = 1); hip_stream is a
+   hipStream_t (NULL = default stream).  Allocates nothing on the device. */
+jfft_status jfft_create_cell(int dim, const int n[3], const double len[3], jfft_precision prec,
+                             jfft_precond pc, void *hip_stream, jfft_cell_t *out);
+
+/* Bytes of device workspace the cell needs (for caller-side allocation and
+   admission control). */
+jfft_status jfft_workspace_bytes(jfft_cell_t cell, size_t *bytes);
+
+/* Hand the cell a caller-owned device buffer of at least jfft_workspace_bytes
+   bytes (256-byte aligned).  The buffer must outlive every later call on the
+   cell.  Without a bound workspace the cell allocates its own at the first call
+   that needs it and frees it in jfft_destroy_cell. */
+jfft_status jfft_bind_workspace(jfft_cell_t cell, void *dev_ptr, size_t bytes);
+
+/* Material field (Sec. 4): E_dev[N] >= 0 per element (copied, no aliasing
+   survives), Poisson ratio nu in (-1, 0.5) for C^ with unit modulus.  Runs
+   Algorithm 2 (Sec. 3.2, d 2^d stiffness applications to unit combs) on the
+   device when the preconditioner uses J; the Green symbol G^ (Algorithm 1) is
+   evaluated per frequency from the closed-form Fourier symbol of K_ref with
+   C_ref = C^ (E_ref = 1). */
+jfft_status jfft_set_material(jfft_cell_t cell, const double *E_dev, double nu);
+
+/* Same with explicit Lame constants (lambda, mu) of C^, e.g. the paper's
+   reference law lambda^0 = 2/3, mu^0 = 1/2 (Sec. 4).  Requires mu > 0 and
+   lambda + 2 mu / d > 0. */
+jfft_status jfft_set_material_lame(jfft_cell_t cell, const double *E_dev, double lambda,
+                                   double mu);
+
+/* Solve K u = f(macro) with f = -B^T W C(E) macro (eq. lin_system_exp) by PCG
+   (Saad Alg. 9.1 in the split form of the footnote to eq.
+   prec_lin_system_general), stopping when ||r_k||_2 <= tol ||f||_2 for the
+   recursive residual, or after maxit iterations.
+     macro_strain: host, d* Mandel entries;
+     u0_dev: start vector [d][N] or NULL for u0 = 0;
+     u_dev:  out [d][N], the fluctuation with its per-component mean removed
+             (Sec. 5: Green-Jacobi iterates carry a mean);
+     sigma_dev: out [d*][2^d][N] quadrature-point stresses (Mandel) or NULL;
+     sigma_bar: host out, d* homogenised stresses (1/|Y|) sum w sigma_q;
+     report: host out (may be NULL).
+   A homogeneous material (||f|| <= 1e-13 ||f_abs||, f_abs assembled from
+   absolute element contributions) returns u = 0 after zero iterations.
+   Returns JFFT_OK, or JFFT_E_NOT_CONVERGED / JFFT_E_BREAKDOWN with the last
+   iterate still written. */
+jfft_status jfft_solve(jfft_cell_t cell, const double *macro_strain, double tol, int maxit,
+                       const double *u0_dev, double *u_dev, double *sigma_dev,
+                       double *sigma_bar, jfft_report *report);
+
+/* Operators, for verification and composition (all FP64, device in/out
+   [d][N], stream-ordered, no synchronisation):
+   out = K in (eq. lin_system_exp, the current material). */
+jfft_status jfft_apply_stiffness(jfft_cell_t cell, const double *in_dev, double *out_dev);
+/* out = M^-1 in for the cell's preconditioner. */
+jfft_status jfft_apply_precond(jfft_cell_t cell, const double *in_dev, double *out_dev);
+/* f = -B^T W C(E) macro (no mean projection). */
+jfft_status jfft_assemble_rhs(jfft_cell_t cell, const double *macro_strain, double *f_dev);
+/* diag(K) from Algorithm 2 before the void rule (zero entries kept). */
+jfft_status jfft_jacobi_diag(jfft_cell_t cell, double *diag_dev);
+
+/* Per-iteration scalar history of the last FP64 solve: alpha_k, beta_k and
+   ||r_k|| for k = 1..min(iters, cap) (host arrays of length cap, any may be
+   NULL).  History is recorded only when enabled before the solve, with
+   0 <= cap <= 4096. */
+jfft_status jfft_enable_history(jfft_cell_t cell, int cap);
+jfft_status jfft_get_history(jfft_cell_t cell, double *alpha, double *beta, double *res,
+                             int cap, int *count);
+
+/* Kernel timing: when enabled, every kernel launch of the cell is bracketed by
+   HIP events on the cell's stream and its duration accumulated per kernel
+   name.  jfft_kernel_stats returns (name, launches, total ms) of entry i;
+   *count receives the number of entries.  Names are static strings. */
+jfft_status jfft_enable_timing(jfft_cell_t cell, int on);
+jfft_status jfft_kernel_stats(jfft_cell_t cell, int i, const char **name, long *launches,
+                              double *total_ms, int *count);
+jfft_status jfft_reset_timing(jfft_cell_t cell);
+
+/* Value of the void rule replacement for exact zeros of diag(K) (Sec. 3.2,
+   default 1.0). */
+jfft_status jfft_set_void_value(jfft_cell_t cell, double value);
+
+/* Mixed precision controls: relative tolerance of each inner FP32 PCG solve
+   (default 1e-5) and the cap on refinement sweeps (default 30). */
+jfft_status jfft_set_mixed_params(jfft_cell_t cell, double inner_tol, int max_outer);
+
+void jfft_destroy_cell(jfft_cell_t cell);
+const char *jfft_last_error(void);
+const char *jfft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JFFT_H */

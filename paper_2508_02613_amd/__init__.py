@@ -1,0 +1,285 @@
+"""MI355X (gfx950) J-FFT solver: PCG with the Green-Jacobi preconditioner for
+periodic linear-elastic cell problems (arXiv 2508.02613).
+
+Thin Python binding over the C ABI in include/jfft.h (libjfft.so, built
+in-tree by paper_2508_02613_amd/build.py).  The binding only marshals
+arguments: every step of the solver runs in the library's HIP kernels.
+PyTorch provides device memory and streams.
+
+The library must be present: importing this package on a machine without the
+built library, or calling it without a GPU, raises instead of falling back to
+any CPU path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+__all__ = ["load_library", "Cell", "Report", "PC_NONE", "PC_GREEN", "PC_JACOBI",
+           "PC_GREEN_JACOBI", "FP64", "MIXED", "JfftError", "EXPORTED_SYMBOLS", "lame_from_nu"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libjfft.so")
+
+PC_NONE, PC_GREEN, PC_JACOBI, PC_GREEN_JACOBI = 0, 1, 2, 3
+FP64, MIXED = 0, 1
+_STATUS = {0: "ok", 1: "invalid", 2: "odd_grid", 3: "no_material", 4: "not_converged",
+           5: "breakdown", 6: "oom", 7: "hip"}
+
+_vp = C.c_void_p
+_dp = C.POINTER(C.c_double)
+
+
+class _Report(C.Structure):
+    _fields_ = [("iters", C.c_int), ("outer", C.c_int), ("status", C.c_int),
+                ("rel_res", C.c_double), ("rel_res_true", C.c_double),
+                ("setup_ms", C.c_double), ("loop_ms", C.c_double), ("post_ms", C.c_double)]
+
+
+# name -> (restype, argtypes); every symbol declared in include/jfft.h
+_SIGS = {
+    "jfft_create_cell": (C.c_int, [C.c_int, C.POINTER(C.c_int), _dp, C.c_int, C.c_int, _vp,
+                                   C.POINTER(_vp)]),
+    "jfft_workspace_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
+    "jfft_bind_workspace": (C.c_int, [_vp, _vp, C.c_size_t]),
+    "jfft_set_material": (C.c_int, [_vp, _vp, C.c_double]),
+    "jfft_set_material_lame": (C.c_int, [_vp, _vp, C.c_double, C.c_double]),
+    "jfft_solve": (C.c_int, [_vp, _dp, C.c_double, C.c_int, _vp, _vp, _vp, _dp,
+                             C.POINTER(_Report)]),
+    "jfft_apply_stiffness": (C.c_int, [_vp, _vp, _vp]),
+    "jfft_apply_precond": (C.c_int, [_vp, _vp, _vp]),
+    "jfft_assemble_rhs": (C.c_int, [_vp, _dp, _vp]),
+    "jfft_jacobi_diag": (C.c_int, [_vp, _vp]),
+    "jfft_enable_history": (C.c_int, [_vp, C.c_int]),
+    "jfft_get_history": (C.c_int, [_vp, _dp, _dp, _dp, C.c_int, C.POINTER(C.c_int)]),
+    "jfft_enable_timing": (C.c_int, [_vp, C.c_int]),
+    "jfft_kernel_stats": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_long),
+                                    _dp, C.POINTER(C.c_int)]),
+    "jfft_reset_timing": (C.c_int, [_vp]),
+    "jfft_set_void_value": (C.c_int, [_vp, C.c_double]),
+    "jfft_set_mixed_params": (C.c_int, [_vp, C.c_double, C.c_int]),
+    "jfft_destroy_cell": (None, [_vp]),
+    "jfft_last_error": (C.c_char_p, []),
+    "jfft_version": (C.c_char_p, []),
+}
+EXPORTED_SYMBOLS = tuple(_SIGS)
+
+_lib = None
+
+
+class JfftError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"jfft {_STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = _STATUS.get(status, str(status))
+
+
+def load_library(path: str | None = None):
+    """Load libjfft.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIBPATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} not found: build it with `python paper_2508_02613_amd/build.py` "
+                          "(the solver has no CPU fallback)")
+    lib = C.CDLL(p)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def lame_from_nu(nu: float):
+    return nu / ((1 + nu) * (1 - 2 * nu)), 1.0 / (2 * (1 + nu))
+
+
+def _check(st):
+    if st != 0:
+        msg = _lib.jfft_last_error().decode(errors="replace")
+        raise JfftError(st, msg)
+
+
+@dataclass
+class Report:
+    iters: int
+    outer: int
+    status: str
+    rel_res: float
+    rel_res_true: float
+    setup_ms: float
+    loop_ms: float
+    post_ms: float
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the J-FFT library needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Cell:
+    """One periodic cell on one GPU stream.
+
+    shape: (ny, nx) or (nz, ny, nx) node counts (x fastest, as the E arrays);
+    precision FP64 or MIXED; pc one of PC_*; stream a torch.cuda.Stream (None =
+    current stream).  The workspace is a torch uint8 tensor bound to the cell.
+    """
+
+    def __init__(self, shape, precision=FP64, pc=PC_GREEN_JACOBI, lengths=None, stream=None,
+                 device=None):
+        torch = _torch()
+        lib = load_library()
+        self.torch = torch
+        self.shape = tuple(int(s) for s in shape)
+        self.dim = len(self.shape)
+        self.device = torch.device(device if device is not None else "cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        n = (C.c_int * 3)(*(list(self.shape[::-1]) + [1] * (3 - self.dim)))
+        ln = None
+        if lengths is not None:
+            ln = (C.c_double * 3)(*(list(lengths) + [1.0] * (3 - self.dim)))
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.jfft_create_cell(self.dim, n, ln, int(precision), int(pc),
+                                        C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self._lib = lib
+        nb = C.c_size_t(0)
+        _check(lib.jfft_workspace_bytes(h, C.byref(nb)))
+        self.workspace_bytes = int(nb.value)
+        with torch.cuda.stream(self.stream):
+            self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        _check(lib.jfft_bind_workspace(h, C.c_void_p(aligned), self.workspace_bytes))
+        self.N = int(np.prod(self.shape))
+        self.ds = self.dim * (self.dim + 1) // 2
+
+    # ----------------------------------------------------------------- api
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.jfft_destroy_cell(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a, shape=None):
+        torch = self.torch
+        if isinstance(a, np.ndarray):
+            a = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64))
+        t = a.to(device=self.device, dtype=torch.float64).contiguous()
+        if shape is not None:
+            assert tuple(t.shape) == tuple(shape), (t.shape, shape)
+        return t
+
+    def set_material(self, E, nu=None, lame=None):
+        E = self._dev(E, self.shape)
+        self._E = E
+        if lame is not None:
+            _check(self._lib.jfft_set_material_lame(self._h, _ptr(E), float(lame[0]), float(lame[1])))
+        else:
+            _check(self._lib.jfft_set_material(self._h, _ptr(E), float(nu)))
+
+    def set_void_value(self, v):
+        _check(self._lib.jfft_set_void_value(self._h, float(v)))
+
+    def set_mixed_params(self, inner_tol=1e-5, max_outer=30):
+        _check(self._lib.jfft_set_mixed_params(self._h, float(inner_tol), int(max_outer)))
+
+    def solve(self, macro, tol=1e-8, maxit=1000, u0=None, want_sigma=False, out=None):
+        """Returns (u [d, ...] device tensor, sigma_bar numpy, Report, sigma or None)."""
+        torch = self.torch
+        vshape = (self.dim,) + self.shape
+        u = out if out is not None else torch.empty(vshape, dtype=torch.float64, device=self.device)
+        sig = None
+        if want_sigma:
+            sig = torch.empty((self.ds, 2 ** self.dim) + self.shape, dtype=torch.float64,
+                              device=self.device)
+        u0t = self._dev(u0, vshape) if u0 is not None else None
+        m = (C.c_double * self.ds)(*[float(v) for v in np.asarray(macro, dtype=float)])
+        sbar = (C.c_double * self.ds)()
+        rep = _Report()
+        st = self._lib.jfft_solve(self._h, m, float(tol), int(maxit), _ptr(u0t), _ptr(u),
+                                  _ptr(sig), sbar, C.byref(rep))
+        if st not in (0, 4, 5):
+            _check(st)
+        r = Report(rep.iters, rep.outer, _STATUS.get(rep.status, str(rep.status)), rep.rel_res,
+                   rep.rel_res_true, rep.setup_ms, rep.loop_ms, rep.post_ms)
+        return u, np.array(sbar[:]), r, sig
+
+    def apply_stiffness(self, x):
+        x = self._dev(x, (self.dim,) + self.shape)
+        out = self.torch.empty_like(x)
+        _check(self._lib.jfft_apply_stiffness(self._h, _ptr(x), _ptr(out)))
+        self.stream.synchronize()
+        return out
+
+    def apply_precond(self, x):
+        x = self._dev(x, (self.dim,) + self.shape)
+        out = self.torch.empty_like(x)
+        _check(self._lib.jfft_apply_precond(self._h, _ptr(x), _ptr(out)))
+        self.stream.synchronize()
+        return out
+
+    def assemble_rhs(self, macro):
+        out = self.torch.empty((self.dim,) + self.shape, dtype=self.torch.float64, device=self.device)
+        m = (C.c_double * self.ds)(*[float(v) for v in np.asarray(macro, dtype=float)])
+        _check(self._lib.jfft_assemble_rhs(self._h, m, _ptr(out)))
+        self.stream.synchronize()
+        return out
+
+    def jacobi_diag(self):
+        out = self.torch.empty((self.dim,) + self.shape, dtype=self.torch.float64, device=self.device)
+        _check(self._lib.jfft_jacobi_diag(self._h, _ptr(out)))
+        self.stream.synchronize()
+        return out
+
+    def enable_history(self, cap):
+        _check(self._lib.jfft_enable_history(self._h, int(cap)))
+
+    def history(self, cap):
+        a = np.zeros(cap)
+        b = np.zeros(cap)
+        r = np.zeros(cap)
+        cnt = C.c_int(0)
+        _check(self._lib.jfft_get_history(self._h, a.ctypes.data_as(_dp), b.ctypes.data_as(_dp),
+                                          r.ctypes.data_as(_dp), int(cap), C.byref(cnt)))
+        k = cnt.value
+        return a[:k], b[:k], r[:k]
+
+    def enable_timing(self, on=True):
+        _check(self._lib.jfft_enable_timing(self._h, 1 if on else 0))
+
+    def reset_timing(self):
+        _check(self._lib.jfft_reset_timing(self._h))
+
+    def kernel_stats(self):
+        """{kernel name: (launches, total ms)} measured with HIP events on the cell's stream."""
+        cnt = C.c_int(0)
+        _check(self._lib.jfft_kernel_stats(self._h, -1, None, None, None, C.byref(cnt)))
+        out = {}
+        for i in range(cnt.value):
+            nm = C.c_char_p()
+            la = C.c_long(0)
+            ms = C.c_double(0)
+            _check(self._lib.jfft_kernel_stats(self._h, i, C.byref(nm), C.byref(la), C.byref(ms),
+                                               None))
+            if la.value:
+                out[nm.value.decode()] = (int(la.value), float(ms.value))
+        return out

@@ -1,0 +1,673 @@
+// FFT passes of the Green-Jacobi preconditioner
+//     z = J^1/2 F^-1 G^ F J^1/2 r      (Sec. 3.3, eq. prec_lin_systemJG_2)
+// on the half spectrum of the real fields (x is the real-to-complex axis).
+//
+// Every pass keeps a tile of lines in LDS and runs a self-sorting
+// mixed-radix Stockham FFT (radices 2, 3, 4, 5, 8) on it:
+//   x pass   : real rows of n points -> complex rows of n/2 points (two real
+//              samples per complex value), Stockham FFT, then the split into
+//              the n/2 + 1 half-spectrum bins.  Fused: r <- r - alpha q,
+//              ||r||^2, the J^1/2 scaling.  The inverse x pass undoes it and
+//              fuses the outer J^1/2 scaling and the r.z partial sums.
+//   y pass   : strided C2C along y on tiles of W consecutive x bins.
+//   last axis: C2C along z (3D) or y (2D), the d x d Green multiply at every
+//              frequency of the tile (held in registers for all components),
+//              and the inverse C2C, in one kernel (one spectrum round trip
+//              instead of three).
+// The transforms are unnormalised; 1/N is folded into G^.
+#pragma once
+#include "jfft_common.h"
+#include "stencil.h"
+
+namespace jfft {
+
+constexpr int FFT_THREADS = 256;
+constexpr int FFT_MAXPT = 16;  // max complex points per thread in one tile
+
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  C r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) {
+  C r;
+  r.x = a.x + b.x;
+  r.y = a.y + b.y;
+  return r;
+}
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) {
+  C r;
+  r.x = a.x - b.x;
+  r.y = a.y - b.y;
+  return r;
+}
+// multiply by -i (forward) or +i (inverse)
+template <bool INV, typename C>
+__device__ __forceinline__ C mul_mi(C a) {
+  C r;
+  if (INV) {
+    r.x = -a.y;
+    r.y = a.x;
+  } else {
+    r.x = a.y;
+    r.y = -a.x;
+  }
+  return r;
+}
+
+// In-register DFT of R points, forward (exp(-2 pi i jk/R)) or inverse (+).
+template <typename Real, int R, bool INV>
+struct Dft;
+
+template <typename Real, bool INV>
+struct Dft<Real, 2, INV> {
+  using C = typename CxT<Real>::T;
+  __device__ __forceinline__ static void run(C *v) {
+    C a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <typename Real, bool INV>
+struct Dft<Real, 4, INV> {
+  using C = typename CxT<Real>::T;
+  __device__ __forceinline__ static void run(C *v) {
+    C s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    C s13 = cadd(v[1], v[3]), d13 = mul_mi<INV>(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+  }
+};
+
+template <typename Real, bool INV>
+struct Dft<Real, 8, INV> {
+  using C = typename CxT<Real>::T;
+  __device__ __forceinline__ static void run(C *v) {
+    C e[4] = {v[0], v[2], v[4], v[6]};
+    C o[4] = {v[1], v[3], v[5], v[7]};
+    Dft<Real, 4, INV>::run(e);
+    Dft<Real, 4, INV>::run(o);
+    const Real r = (Real)0.70710678118654752440084436210485;
+    // o[k] *= w8^k, w8 = exp(-+ 2 pi i / 8)
+    C t1, t3;
+    if (!INV) {
+      t1.x = r * (o[1].x + o[1].y);
+      t1.y = r * (o[1].y - o[1].x);
+      t3.x = r * (o[3].y - o[3].x);
+      t3.y = -r * (o[3].x + o[3].y);
+    } else {
+      t1.x = r * (o[1].x - o[1].y);
+      t1.y = r * (o[1].y + o[1].x);
+      t3.x = -r * (o[3].x + o[3].y);
+      t3.y = r * (o[3].x - o[3].y);
+    }
+    C t2 = mul_mi<INV>(o[2]);
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], t1);
+    v[5] = csub(e[1], t1);
+    v[2] = cadd(e[2], t2);
+    v[6] = csub(e[2], t2);
+    v[3] = cadd(e[3], t3);
+    v[7] = csub(e[3], t3);
+  }
+};
+
+template <typename Real, bool INV>
+struct Dft<Real, 3, INV> {
+  using C = typename CxT<Real>::T;
+  __device__ __forceinline__ static void run(C *v) {
+    const Real h = (Real)0.5, s = (Real)0.86602540378443864676372317075294;
+    C t1 = cadd(v[1], v[2]);
+    C t2 = csub(v[1], v[2]);
+    C m;
+    m.x = v[0].x - h * t1.x;
+    m.y = v[0].y - h * t1.y;
+    C j = mul_mi<INV>(t2);  // -+ i (v1 - v2)
+    j.x *= s;
+    j.y *= s;
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd(m, j);
+    v[2] = csub(m, j);
+  }
+};
+
+template <typename Real, bool INV>
+struct Dft<Real, 5, INV> {
+  using C = typename CxT<Real>::T;
+  __device__ __forceinline__ static void run(C *v) {
+    const Real c1 = (Real)0.30901699437494742410229341718282;   // cos 2pi/5
+    const Real c2 = (Real)-0.80901699437494742410229341718282;  // cos 4pi/5
+    const Real s1 = (Real)0.95105651629515357211643933337938;   // sin 2pi/5
+    const Real s2 = (Real)0.58778525229247312916870595463907;   // sin 4pi/5
+    C t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    C t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    C a1, a2, b1, b2;
+    a1.x = v[0].x + c1 * t1.x + c2 * t2.x;
+    a1.y = v[0].y + c1 * t1.y + c2 * t2.y;
+    a2.x = v[0].x + c2 * t1.x + c1 * t2.x;
+    a2.y = v[0].y + c2 * t1.y + c1 * t2.y;
+    C u1, u2;
+    u1.x = s1 * t3.x + s2 * t4.x;
+    u1.y = s1 * t3.y + s2 * t4.y;
+    u2.x = s2 * t3.x - s1 * t4.x;
+    u2.y = s2 * t3.y - s1 * t4.y;
+    b1 = mul_mi<INV>(u1);
+    b2 = mul_mi<INV>(u2);
+    v[0] = cadd(v[0], cadd(t1, t2));
+    v[1] = cadd(a1, b1);
+    v[4] = csub(a1, b1);
+    v[2] = cadd(a2, b2);
+    v[3] = csub(a2, b2);
+  }
+};
+
+// One Stockham stage of radix R on T lines of length L held in LDS:
+// element (point p, line c) at buf[p * sp + c * sc].  Stage input stride
+// L / R, current sub-transform length p (product of earlier radices).
+// tw[j * tws] = exp(-2 pi i j / L).  All threads read their butterflies,
+// synchronise, then write, so one buffer suffices.
+template <typename Real, int R, bool INV>
+__device__ __forceinline__ void stockham_stage(typename CxT<Real>::T *buf, int L, int W, int p,
+                                               int sp, int sc, const typename CxT<Real>::T *tw,
+                                               int tws, bool i_fastest) {
+  using C = typename CxT<Real>::T;
+  constexpr int MB = (FFT_MAXPT + R - 1) / R;
+  const int m = L / R;
+  const int nb = m * W;
+  const int step = L / (p * R);
+  C v[MB][R];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int f = threadIdx.x + b * FFT_THREADS;
+    if (f < nb) {
+      const int i = i_fastest ? f % m : f / W;
+      const int c = i_fastest ? f / m : f % W;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = buf[(i + r * m) * sp + c * sc];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int f = threadIdx.x + b * FFT_THREADS;
+    if (f < nb) {
+      const int i = i_fastest ? f % m : f / W;
+      const int c = i_fastest ? f / m : f % W;
+      const int k = i % p;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        C t = tw[(r * k * step) * tws];
+        if (INV) t.y = -t.y;
+        v[b][r] = cmul(v[b][r], t);
+      }
+      Dft<Real, R, INV>::run(v[b]);
+      const int j = (i / p) * p * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[(j + r * p) * sp + c * sc] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename Real, bool INV>
+__device__ void lds_fft(typename CxT<Real>::T *buf, const FftPlan &pl, int W, int sp, int sc,
+                        const typename CxT<Real>::T *tw, int tws, bool i_fastest) {
+  int p = 1;
+  for (int s = 0; s < pl.nst; ++s) {
+    const int R = pl.radix[s];
+    switch (R) {
+      case 8: stockham_stage<Real, 8, INV>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
+      case 4: stockham_stage<Real, 4, INV>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
+      case 2: stockham_stage<Real, 2, INV>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
+      case 3: stockham_stage<Real, 3, INV>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
+      case 5: stockham_stage<Real, 5, INV>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
+      default: break;
+    }
+    p *= R;
+  }
+}
+
+template <typename Real>
+__device__ __forceinline__ void load_twiddles(typename CxT<Real>::T *sm, const double2 *g, int n) {
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    typename CxT<Real>::T t;
+    t.x = (Real)g[j].x;
+    t.y = (Real)g[j].y;
+    sm[j] = t;
+  }
+}
+
+// ------------------------------------------------------------ x passes ---
+template <typename Real>
+struct XArgs {
+  Real *r;             // residual (updated in place when UPDATE)
+  const Real *q;       // K p (UPDATE)
+  const Real *Jh;      // J^1/2 [d][N] (USE_J)
+  Real *out;           // inverse pass: z
+  typename CxT<Real>::T *spec;  // half spectrum [d][nz][ny][mxp]
+  double *partA;       // ||r||^2 partials (forward), r.z partials (inverse)
+  const CgState *st;
+  const double2 *tw;   // exp(-2 pi i j / nx), j < nx
+  FftPlan plan;        // length nx / 2
+  int nx, mx, mxp;
+  long long nrows;     // d * ny * nz
+  int rows_per_block;
+  int check_done;
+};
+
+// Forward: r <- r - alpha q (UPDATE), s = J^1/2 r (USE_J), X = rfft(s) per row.
+template <typename Real, bool UPDATE, bool USE_J>
+__global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
+  using C = typename CxT<Real>::T;
+  using R2 = typename CxT<Real>::R2;
+  if (a.check_done && a.st->done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *tw = reinterpret_cast<C *>(smem_raw);
+  C *buf = tw + a.nx;
+  __shared__ double red[8];
+  const int m = a.nx / 2;
+  const int RB = a.rows_per_block;
+  const int sc = m + 1;  // LDS row stride
+  const long long row0 = (long long)blockIdx.x * RB;
+  load_twiddles<Real>(tw, a.tw, a.nx);
+  Real alpha = 0;
+  if (UPDATE) alpha = (Real)a.st->alpha;
+  double rr = 0.0;
+  for (int f = threadIdx.x; f < RB * m; f += FFT_THREADS) {
+    const int row = f / m, j = f % m;
+    const long long g = row0 + row;
+    C z;
+    z.x = 0;
+    z.y = 0;
+    if (g < a.nrows) {
+      const long long off = g * (long long)m + j;  // in pairs (R2 units)
+      R2 rv = reinterpret_cast<const R2 *>(a.r)[off];
+      if (UPDATE) {
+        const R2 qv = reinterpret_cast<const R2 *>(a.q)[off];
+        rv.x -= alpha * qv.x;
+        rv.y -= alpha * qv.y;
+        reinterpret_cast<R2 *>(a.r)[off] = rv;
+      }
+      rr += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
+      if (USE_J) {
+        const R2 jv = reinterpret_cast<const R2 *>(a.Jh)[off];
+        rv.x *= jv.x;
+        rv.y *= jv.y;
+      }
+      z.x = rv.x;
+      z.y = rv.y;
+    }
+    buf[row * sc + j] = z;
+  }
+  __syncthreads();
+  lds_fft<Real, false>(buf, a.plan, RB, 1, sc, tw, 2, true);
+  // split: X[k] = (Z[k] + conj Z[m-k])/2 - i w^k (Z[k] - conj Z[m-k])/2
+  const int half = m / 2 + 1;
+  for (int f = threadIdx.x; f < RB * half; f += FFT_THREADS) {
+    const int row = f / half, k = f % half;
+    const long long g = row0 + row;
+    if (g >= a.nrows) continue;
+    const C zk = buf[row * sc + (k % m)];
+    const C zm = buf[row * sc + ((m - k) % m)];
+    C *dst = a.spec + g * (long long)a.mxp;
+    // X[k]
+    {
+      C s, d;
+      s.x = (Real)0.5 * (zk.x + zm.x);
+      s.y = (Real)0.5 * (zk.y - zm.y);
+      d.x = (Real)0.5 * (zk.x - zm.x);
+      d.y = (Real)0.5 * (zk.y + zm.y);
+      const C w = tw[k];
+      // -i w d
+      const C wd = cmul(w, d);
+      C X;
+      X.x = s.x + wd.y;
+      X.y = s.y - wd.x;
+      dst[k] = X;
+    }
+    // X[m - k] (k = 0 gives the Nyquist bin X[m]; k = m/2 is its own partner)
+    if (k != m - k) {
+      const int k2 = m - k;
+      const C zk2 = buf[row * sc + (k2 % m)];
+      const C zm2 = buf[row * sc + ((m - k2) % m)];
+      C s, d;
+      s.x = (Real)0.5 * (zk2.x + zm2.x);
+      s.y = (Real)0.5 * (zk2.y - zm2.y);
+      d.x = (Real)0.5 * (zk2.x - zm2.x);
+      d.y = (Real)0.5 * (zk2.y + zm2.y);
+      const C w = tw[k2];
+      const C wd = cmul(w, d);
+      C X;
+      X.x = s.x + wd.y;
+      X.y = s.y - wd.x;
+      dst[k2] = X;
+    }
+  }
+  const double s = block_sum<FFT_THREADS>(rr, red);
+  if (threadIdx.x == 0 && a.partA) a.partA[blockIdx.x] = s;
+}
+
+// Inverse: t = irfft(X) (unnormalised), z = J^1/2 t (USE_J); partials of r.z.
+template <typename Real, bool USE_J>
+__global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
+  using C = typename CxT<Real>::T;
+  using R2 = typename CxT<Real>::R2;
+  if (a.check_done && a.st->done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *tw = reinterpret_cast<C *>(smem_raw);
+  C *buf = tw + a.nx;
+  __shared__ double red[8];
+  const int m = a.nx / 2;
+  const int RB = a.rows_per_block;
+  const int sc = m + 1;
+  const long long row0 = (long long)blockIdx.x * RB;
+  load_twiddles<Real>(tw, a.tw, a.nx);
+  for (int f = threadIdx.x; f < RB * (m + 1); f += FFT_THREADS) {
+    const int row = f / (m + 1), k = f % (m + 1);
+    const long long g = row0 + row;
+    C v;
+    v.x = 0;
+    v.y = 0;
+    if (g < a.nrows) v = a.spec[g * (long long)a.mxp + k];
+    buf[row * sc + k] = v;
+  }
+  __syncthreads();
+  // Z[k] = (X[k] + conj X[m-k]) + i conj(w^k) (X[k] - conj X[m-k]), k < m.
+  // A thread owns the pair (k, m - k) of one row: it reads and writes only
+  // those two slots, so no barrier is needed inside the loop.
+  const int half = m / 2 + 1;
+  for (int f = threadIdx.x; f < RB * half; f += FFT_THREADS) {
+    const int row = f / half, k = f % half;
+    const C xa = buf[row * sc + k];
+    const C xb = buf[row * sc + (m - k)];
+    C zk[2];
+    int kk[2];
+    int cnt = 0;
+    for (int t = 0; t < 2; ++t) {
+      const int q = t == 0 ? k : m - k;
+      if (t == 1 && (q == k || q == m)) break;  // self pair, or k = 0 (no Z[m])
+      const C xk = t == 0 ? xa : xb;
+      const C xm = t == 0 ? xb : xa;
+      C e, d;
+      e.x = xk.x + xm.x;
+      e.y = xk.y - xm.y;
+      d.x = xk.x - xm.x;
+      d.y = xk.y + xm.y;
+      C wc = tw[q];
+      wc.y = -wc.y;
+      const C o = cmul(wc, d);
+      zk[cnt].x = e.x - o.y;  // e + i o
+      zk[cnt].y = e.y + o.x;
+      kk[cnt] = q;
+      ++cnt;
+    }
+    for (int t = 0; t < cnt; ++t) buf[row * sc + kk[t]] = zk[t];
+  }
+  __syncthreads();
+  lds_fft<Real, true>(buf, a.plan, RB, 1, sc, tw, 2, true);
+  double rz = 0.0;
+  for (int f = threadIdx.x; f < RB * m; f += FFT_THREADS) {
+    const int row = f / m, j = f % m;
+    const long long g = row0 + row;
+    if (g >= a.nrows) continue;
+    const long long off = g * (long long)m + j;
+    const C z = buf[row * sc + j];
+    R2 t;
+    t.x = z.x;
+    t.y = z.y;
+    if (USE_J) {
+      const R2 jv = reinterpret_cast<const R2 *>(a.Jh)[off];
+      t.x *= jv.x;
+      t.y *= jv.y;
+    }
+    reinterpret_cast<R2 *>(a.out)[off] = t;
+    if (a.partA) {
+      const R2 rv = reinterpret_cast<const R2 *>(a.r)[off];
+      rz += (double)rv.x * (double)t.x + (double)rv.y * (double)t.y;
+    }
+  }
+  const double s = block_sum<FFT_THREADS>(rz, red);
+  if (threadIdx.x == 0 && a.partA) a.partA[blockIdx.x] = s;
+}
+
+// ------------------------------------------------- strided C2C passes ----
+constexpr int FFT_W = 8;  // x bins per tile of a strided pass
+
+template <typename Real>
+struct YArgs {
+  typename CxT<Real>::T *spec;
+  const CgState *st;
+  const double2 *tw;  // exp(-2 pi i j / L)
+  FftPlan plan;
+  int mx, mxp, ny, nz;
+  int check_done;
+};
+
+// C2C along y for one (component, z) plane, tile of FFT_W x bins.
+template <typename Real, bool INV>
+__global__ void __launch_bounds__(FFT_THREADS) k_ypass(YArgs<Real> a) {
+  using C = typename CxT<Real>::T;
+  if (a.check_done && a.st->done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *tw = reinterpret_cast<C *>(smem_raw);
+  const int L = a.ny;
+  C *buf = tw + L;
+  load_twiddles<Real>(tw, a.tw, L);
+  const int kx0 = blockIdx.x * FFT_W;
+  const long long plane = (long long)blockIdx.z * a.nz + blockIdx.y;  // comp * nz + z
+  C *base = a.spec + plane * (long long)a.ny * a.mxp;
+  for (int f = threadIdx.x; f < L * FFT_W; f += FFT_THREADS) {
+    const int col = f % FFT_W, y = f / FFT_W;
+    C v;
+    v.x = 0;
+    v.y = 0;
+    if (kx0 + col < a.mx) v = base[(long long)y * a.mxp + kx0 + col];
+    buf[y * FFT_W + col] = v;
+  }
+  __syncthreads();
+  lds_fft<Real, INV>(buf, a.plan, FFT_W, FFT_W, 1, tw, 1, false);
+  for (int f = threadIdx.x; f < L * FFT_W; f += FFT_THREADS) {
+    const int col = f % FFT_W, y = f / FFT_W;
+    if (kx0 + col < a.mx) base[(long long)y * a.mxp + kx0 + col] = buf[y * FFT_W + col];
+  }
+}
+
+template <typename Real>
+struct GArgs {
+  typename CxT<Real>::T *spec;
+  const CgState *st;
+  const double2 *tw;  // exp(-2 pi i j / L), L = length of the last axis
+  FftPlan plan;
+  AxisTables tx, ty, tz;  // Fourier tables of K_ref
+  double lam, mu;         // reference Lame constants
+  double invN;            // 1 / N (normalisation of the unnormalised transforms)
+  int dim, mx, mxp, ny, nz;
+  int check_done;
+};
+
+// Green multiply at one frequency: zh = G^(k) sh with G^ = K^_ref(k)^-1 / N,
+// G^(0) = 0 (Alg. 1 step 3).  K^_ref of Q1 elements with exact Gauss
+// integration is real symmetric:
+//   K_ii = (lam + 2 mu) a_i prod_{j != i} b_j + mu sum_{j != i} a_j prod_{l != j} b_l
+//   K_ij = (lam + mu) s_i s_j prod_{l != i, j} b_l.
+template <typename C>
+__device__ __forceinline__ void green3(const double (&A)[3], const double (&B)[3],
+                                       const double (&S)[3], double lam, double mu, double invN,
+                                       bool zero, C (&v)[3]) {
+  if (zero) {
+    for (int i = 0; i < 3; ++i) v[i].x = v[i].y = 0;
+    return;
+  }
+  const double l2m = lam + 2.0 * mu, lm = lam + mu;
+  const double abb = A[0] * B[1] * B[2], bab = B[0] * A[1] * B[2], bba = B[0] * B[1] * A[2];
+  const double k00 = l2m * abb + mu * (bab + bba);
+  const double k11 = l2m * bab + mu * (abb + bba);
+  const double k22 = l2m * bba + mu * (abb + bab);
+  const double k01 = lm * S[0] * S[1] * B[2];
+  const double k02 = lm * S[0] * B[1] * S[2];
+  const double k12 = lm * B[0] * S[1] * S[2];
+  // symmetric inverse by cofactors
+  const double c00 = k11 * k22 - k12 * k12;
+  const double c01 = k02 * k12 - k01 * k22;
+  const double c02 = k01 * k12 - k02 * k11;
+  const double c11 = k00 * k22 - k02 * k02;
+  const double c12 = k01 * k02 - k00 * k12;
+  const double c22 = k00 * k11 - k01 * k01;
+  const double det = k00 * c00 + k01 * c01 + k02 * c02;
+  const double sc = invN / det;
+  const double g00 = c00 * sc, g01 = c01 * sc, g02 = c02 * sc;
+  const double g11 = c11 * sc, g12 = c12 * sc, g22 = c22 * sc;
+  const double x0 = v[0].x, x1 = v[1].x, x2 = v[2].x;
+  const double y0 = v[0].y, y1 = v[1].y, y2 = v[2].y;
+  v[0].x = g00 * x0 + g01 * x1 + g02 * x2;
+  v[0].y = g00 * y0 + g01 * y1 + g02 * y2;
+  v[1].x = g01 * x0 + g11 * x1 + g12 * x2;
+  v[1].y = g01 * y0 + g11 * y1 + g12 * y2;
+  v[2].x = g02 * x0 + g12 * x1 + g22 * x2;
+  v[2].y = g02 * y0 + g12 * y1 + g22 * y2;
+}
+
+template <typename C>
+__device__ __forceinline__ void green2(const double (&A)[2], const double (&B)[2],
+                                       const double (&S)[2], double lam, double mu, double invN,
+                                       bool zero, C (&v)[2]) {
+  if (zero) {
+    for (int i = 0; i < 2; ++i) v[i].x = v[i].y = 0;
+    return;
+  }
+  const double l2m = lam + 2.0 * mu, lm = lam + mu;
+  const double k00 = l2m * A[0] * B[1] + mu * B[0] * A[1];
+  const double k11 = mu * A[0] * B[1] + l2m * B[0] * A[1];
+  const double k01 = lm * S[0] * S[1];
+  const double sc = invN / (k00 * k11 - k01 * k01);
+  const double g00 = k11 * sc, g11 = k00 * sc, g01 = -k01 * sc;
+  const double x0 = v[0].x, x1 = v[1].x, y0 = v[0].y, y1 = v[1].y;
+  v[0].x = g00 * x0 + g01 * x1;
+  v[0].y = g00 * y0 + g01 * y1;
+  v[1].x = g01 * x0 + g11 * x1;
+  v[1].y = g01 * y0 + g11 * y1;
+}
+
+// Last axis: forward C2C, Green multiply, inverse C2C for every component of
+// a tile of FFT_W x bins (3D: at one ky; 2D: the whole y axis).
+template <typename Real, int DIM, int PPT>
+__global__ void __launch_bounds__(FFT_THREADS) k_green_axis(GArgs<Real> a) {
+  using C = typename CxT<Real>::T;
+  if (a.check_done && a.st->done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *tw = reinterpret_cast<C *>(smem_raw);
+  const int L = DIM == 3 ? a.nz : a.ny;
+  C *buf = tw + L;
+  load_twiddles<Real>(tw, a.tw, L);
+  const int kx0 = blockIdx.x * FFT_W;
+  const int ky = DIM == 3 ? blockIdx.y : 0;
+  // line (kx, ky) along the last axis: component c, position t
+  const long long comp_stride = (long long)a.nz * a.ny * a.mxp;
+  const long long axis_stride = DIM == 3 ? (long long)a.ny * a.mxp : (long long)a.mxp;
+  C *base = a.spec + (DIM == 3 ? (long long)ky * a.mxp : 0) + kx0;
+  // PPT: points per thread kept across components (L * FFT_W <= PPT * FFT_THREADS)
+  C stash[DIM][PPT];
+  const int npts = L * FFT_W;
+  for (int c = 0; c < DIM; ++c) {
+    for (int f = threadIdx.x; f < npts; f += FFT_THREADS) {
+      const int col = f % FFT_W, t = f / FFT_W;
+      C v;
+      v.x = 0;
+      v.y = 0;
+      if (kx0 + col < a.mx) v = base[c * comp_stride + (long long)t * axis_stride + col];
+      buf[f] = v;
+    }
+    __syncthreads();
+    lds_fft<Real, false>(buf, a.plan, FFT_W, FFT_W, 1, tw, 1, false);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int f = threadIdx.x + j * FFT_THREADS;
+      if (f < npts) stash[c][j] = buf[f];
+    }
+    __syncthreads();
+  }
+  // Green multiply on the points this thread holds
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int f = threadIdx.x + j * FFT_THREADS;
+    if (f < npts) {
+      const int col = f % FFT_W, t = f / FFT_W;
+      const int kx = min(kx0 + col, a.mx - 1);
+      if (DIM == 3) {
+        const double A[3] = {a.tx.a[kx], a.ty.a[ky], a.tz.a[t]};
+        const double B[3] = {a.tx.b[kx], a.ty.b[ky], a.tz.b[t]};
+        const double S[3] = {a.tx.s[kx], a.ty.s[ky], a.tz.s[t]};
+        C v[3] = {stash[0][j], stash[1][j], stash[2][j]};
+        green3(A, B, S, a.lam, a.mu, a.invN, kx == 0 && ky == 0 && t == 0, v);
+        for (int c = 0; c < 3; ++c) stash[c][j] = v[c];
+      } else {
+        const double A[2] = {a.tx.a[kx], a.ty.a[t]};
+        const double B[2] = {a.tx.b[kx], a.ty.b[t]};
+        const double S[2] = {a.tx.s[kx], a.ty.s[t]};
+        C v[2] = {stash[0][j], stash[1][j]};
+        green2(A, B, S, a.lam, a.mu, a.invN, kx == 0 && t == 0, v);
+        for (int c = 0; c < 2; ++c) stash[c][j] = v[c];
+      }
+    }
+  }
+  for (int c = 0; c < DIM; ++c) {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int f = threadIdx.x + j * FFT_THREADS;
+      if (f < npts) buf[f] = stash[c][j];
+    }
+    __syncthreads();
+    lds_fft<Real, true>(buf, a.plan, FFT_W, FFT_W, 1, tw, 1, false);
+    for (int f = threadIdx.x; f < npts; f += FFT_THREADS) {
+      const int col = f % FFT_W, t = f / FFT_W;
+      if (kx0 + col < a.mx) base[c * comp_stride + (long long)t * axis_stride + col] = buf[f];
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------- diagonal / identity preconditioner -
+// r <- r - alpha q (UPDATE), z = Jinv r (JACOBI) or z = r (NONE); partials of
+// ||r||^2 (partA) and r.z (partB).
+template <typename Real, bool UPDATE, bool JACOBI>
+__global__ void __launch_bounds__(256) k_diag_pc(Real *r, const Real *q, const Real *Jh, Real *z,
+                                                 long long n, const CgState *st, int check_done,
+                                                 double *partA, double *partB) {
+  if (check_done && st->done) return;
+  __shared__ double red[8];
+  Real alpha = 0;
+  if (UPDATE) alpha = (Real)st->alpha;
+  double rr = 0.0, rz = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    Real rv = r[i];
+    if (UPDATE) {
+      rv -= alpha * q[i];
+      r[i] = rv;
+    }
+    Real zv = rv;
+    if (JACOBI) {
+      const Real j = Jh[i];
+      zv = rv * j * j;
+    }
+    z[i] = zv;
+    rr += (double)rv * (double)rv;
+    rz += (double)rv * (double)zv;
+  }
+  const double s1 = block_sum<256>(rr, red);
+  const double s2 = block_sum<256>(rz, red);
+  if (threadIdx.x == 0) {
+    if (partA) partA[blockIdx.x] = s1;
+    if (partB) partB[blockIdx.x] = s2;
+  }
+}
+
+}  // namespace jfft

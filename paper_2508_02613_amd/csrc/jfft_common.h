@@ -1,0 +1,91 @@
+// Internal declarations shared by the HIP translation units of libjfft.
+// Device code targets gfx950 (CDNA4, 64-wide wavefronts) only.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace jfft {
+
+template <typename Real>
+struct CxT;
+template <>
+struct CxT<double> {
+  using T = double2;
+  using R2 = double2;
+};
+template <>
+struct CxT<float> {
+  using T = float2;
+  using R2 = float2;
+};
+
+// CG scalars kept on the device so that the whole loop runs without host
+// round trips; written only by the single-block control kernels.
+struct CgState {
+  double rz;        // r_k . z_k
+  double pq;        // p_k . K p_k
+  double alpha;     // alpha_k (also the pending u update factor)
+  double beta;      // beta_k
+  double rr;        // ||r_k||^2
+  double tol2;      // stopping threshold on ||r_k||^2
+  double scratch[2];
+  int iter;         // completed updates of u
+  int maxit;
+  int done;         // 1 once stopped (later kernels of the loop return at once)
+  int status;       // jfft_status value at stop
+  int first;        // 1 until the first search direction exists
+  int pending;      // 1 while alpha * p is owed to u
+  int hist_cap;     // history capacity (0 = off)
+  int pad;
+};
+
+// Fourier tables of one axis for the Green symbol of K_ref (Q1 elements,
+// exact 2-point Gauss integration): a = (2 - 2 cos t)/h, b = h (2 + cos t)/3,
+// s = sin t, t = 2 pi k / n.
+struct AxisTables {
+  const double *a, *b, *s;
+};
+
+constexpr int kMaxStages = 12;
+struct FftPlan {
+  int L;      // transform length
+  int nst;    // number of Stockham stages
+  int radix[kMaxStages];
+};
+
+// Geometry and constants passed by value to kernels.
+struct GridDev {
+  int dim;
+  int nx, ny, nz;     // nz = 1 in 2D
+  long long N;        // nodes = elements
+  int mx;             // nx / 2 + 1 half-spectrum entries per x row
+  int mxp;            // row stride of the half spectrum (complex entries)
+  double ihx, ihy, ihz;  // 1 / h
+  double w;           // Gauss weight = element volume / 2^d
+  double vol;         // |Y|
+};
+
+// Kernel identifiers for timing.
+enum KernelId {
+  KID_STIFF_CG = 0,
+  KID_STIFF_APPLY,
+  KID_STIFF_COMB,
+  KID_XFWD,
+  KID_YFWD,
+  KID_GREEN,
+  KID_YINV,
+  KID_XINV,
+  KID_DIAGPC,
+  KID_CTRL,
+  KID_RHS,
+  KID_VEC,
+  KID_REDUCE,
+  KID_STRESS,
+  KID_SETUP,
+  KID_COUNT
+};
+extern const char *const kKernelNames[KID_COUNT];
+
+}  // namespace jfft
