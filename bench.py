@@ -1,0 +1,296 @@
+"""Benchmark: DOF-iterations/s of J-FFT PCG on a 256^3 periodic cell (one MI355X).
+
+One step = one pass of the whole hot path on one synthetic input resident in
+HBM: set the material (copy E, Algorithm 2 diagonal, J^1/2), assemble the
+right-hand side, run PCG with the Green-Jacobi preconditioner to a true
+relative residual of 1e-8, remove the mean and evaluate the homogenised
+stress.  The headline path is the mixed-precision solver (FP32 stencil, FFT,
+preconditioner and vectors; FP64 dots, alpha/beta, iterate and an FP64
+iterative-refinement residual); the plain FP64 solver is timed on the same
+input and reported beside it.
+
+value = DOF x PCG iterations (all inner iterations) / wall time of the timed
+steps, with DOF = 3 n^3.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256]
+                       [--contrast 1e4] [--no-cpu] [--no-fp64]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--contrast", type=float, default=1e4)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
+    return ap.parse_args()
+
+
+def copy_probe():
+    """A plain device-to-device copy of exactly 2^30 bytes, five times: the
+    reference against which rocprofv3 FETCH_SIZE / WRITE_SIZE are scaled."""
+    import torch
+
+    x = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 2 ** 30, "copy_probe_bytes_written": 2 ** 30,
+                      "launches": 5}), flush=True)
+
+
+def spectrum_ratio(n):
+    m = n // 2
+    return (m + 1) / (2.0 * m)
+
+
+def algorithmic_bytes(kernel, dim, N, n_x, real_bytes):
+    """Bytes a kernel must move per launch in the fused design (each array
+    read or written once): fields of d components, half spectrum of d
+    components, element moduli."""
+    field = dim * N * real_bytes
+    spec = dim * N * spectrum_ratio(n_x) * 2 * real_bytes
+    scalar = N * real_bytes
+    table = {
+        # z, p_old, u read; u, p_new, q written; E read
+        "stiffness_cg": 6 * field + scalar,
+        "stiffness_apply": 2 * field + scalar,
+        # r, q, J^1/2 read; r written; spectrum written
+        "fft_x_forward": 4 * field + spec,
+        "fft_y_forward": 2 * spec,
+        "fft_green_axis": 2 * spec,
+        "fft_y_inverse": 2 * spec,
+        # spectrum, J^1/2, r read; z written
+        "fft_x_inverse": spec + 3 * field,
+        "diag_precond": 5 * field,
+    }
+    return table.get(kernel)
+
+
+# precision of each kernel name in the mixed path
+MIXED_KERNEL_BYTES = {"stiffness_apply": 8}
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2508_02613_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload_key, kernel):
+    """HBM traffic per launch from committed rocprofv3 counter summaries,
+    only if they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except Exception:
+        return None
+    ent = data.get(workload_key, {}).get(kernel)
+    if not ent or ent.get("source_sha") != source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def run_gpu(args, precision_name, E, nu, macro, tol, maxit):
+    import torch
+
+    import paper_2508_02613_amd as pkg
+
+    prec = pkg.MIXED if precision_name == "mixed" else pkg.FP64
+    shape = E.shape
+    stream = torch.cuda.current_stream()
+    cell = pkg.Cell(shape, precision=prec, pc=pkg.PC_GREEN_JACOBI, stream=stream)
+    Ed = torch.from_numpy(E).to("cuda")
+    u = torch.empty((3,) + shape, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+
+    def step():
+        cell.set_material(Ed, nu=nu)
+        return cell.solve(macro, tol=tol, maxit=maxit, out=u)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    cell.reset_timing()
+    cell.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for _ in range(args.steps):
+        _, sbar, rep, _ = step()
+        reps.append(rep)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = cell.kernel_stats()
+    cell.enable_timing(False)
+    cell.close()
+    wall = t1 - t0
+    iters = sum(r.iters for r in reps)
+    return {"wall_s": wall, "iters": iters, "reps": reps, "stats": stats, "sigma_bar": sbar}
+
+
+def cpu_baseline(E, macro, nu):
+    """The oracle, timed on one PCG iteration's operators (K p and the
+    Green-Jacobi preconditioner with its naive DFT) on the full 256^3 input.
+    Its one-off set-up (Algorithm 1 DFTs of 9 fields, Algorithm 2 with 24
+    element-loop stiffness applications) is not part of the sample; the
+    per-iteration cost does not depend on the values of G^ and diag, so the
+    sample passes placeholders of the right shape for them."""
+    import oracle
+
+    lam, mu = oracle.lame_from_nu(nu)
+    shape = E.shape
+    dim = len(shape)
+    rng = np.random.default_rng(0)
+    p = rng.standard_normal((dim,) + shape)
+    G = np.zeros((dim, dim) + shape, dtype=complex)
+    G[0, 0] = 1.0
+    diag = np.ones((dim,) + shape)
+    t0 = time.perf_counter()
+    q = oracle.stiffness(E, p, lam, mu)
+    t1 = time.perf_counter()
+    z, _ = oracle.precond(oracle.PC_GREEN_JACOBI, q, diag=diag, G=G)
+    t2 = time.perf_counter()
+    # dots and updates of one iteration (numpy, same order of work)
+    a = float((p * q).sum())
+    p += a * z
+    t3 = time.perf_counter()
+    per_iter = t3 - t0
+    dofs = dim * E.size
+    return {
+        "value": dofs / per_iter,
+        "unit": "DOF·it/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"one PCG iteration of the FP64 C oracle (element-loop K·p {t1 - t0:.1f} s, "
+                   f"Green-Jacobi M^-1 with naive separable DFT {t2 - t1:.1f} s, dots/axpys "
+                   f"{t3 - t2:.1f} s) on the same {shape[0]}^3 input; set-up excluded"),
+        "seconds_per_iteration": per_iter,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU: --gpus {args.gpus} is not supported (this "
+              "solver build targets a single MI355X; see DESIGN.md for how the path would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    if args.copy_probe:
+        copy_probe()
+        return
+    import jfft_inputs as ji
+
+    n = args.n
+    shape = (n, n, n)
+    E = ji.grf_field(shape, args.contrast, seed=args.seed, ell=0.1)
+    nu = 0.3
+    macro = ji.unit_macro_strain(3, 0)
+    tol, maxit = 1e-8, 20000
+    N = E.size
+    dofs = 3 * N
+    workload = (f"3D periodic cell {n}^3 nodes, trilinear hex Q1 with 8 Gauss points, "
+                f"smooth Gaussian-random-field E (ell 0.1, contrast {args.contrast:g}, seed "
+                f"{args.seed}), nu 0.3, macro strain e11, Green-Jacobi (J-FFT) PCG to "
+                f"relative residual 1e-8")
+    results = {}
+    if not args.no_mixed:
+        results["mixed"] = run_gpu(args, "mixed", E, nu, macro, tol, maxit)
+    if not args.no_fp64:
+        results["fp64"] = run_gpu(args, "fp64", E, nu, macro, tol, maxit)
+    head = "mixed" if "mixed" in results else "fp64"
+    R = results[head]
+    value = dofs * R["iters"] / R["wall_s"]
+    ms_per_step = 1e3 * R["wall_s"] / args.steps
+
+    # roofline of the dominant kernel (largest total event time in the timed steps)
+    stats = R["stats"]
+    dom = max((k for k in stats if algorithmic_bytes(k, 3, N, n, 4) is not None),
+              key=lambda k: stats[k][1])
+    launches, tot_ms = stats[dom]
+    rb = 4 if head == "mixed" else 8
+    if head == "mixed":
+        rb = MIXED_KERNEL_BYTES.get(dom, 4)
+    bytes_launch = algorithmic_bytes(dom, 3, N, n, rb)
+    avg_ms = tot_ms / launches
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    wkey = f"{head}_{n}"
+    traffic = load_traffic(wkey, dom)
+    line = {
+        "metric": "DOF·iterations/s (J-FFT PCG, 256³)",
+        "value": value,
+        "unit": "DOF·it/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "n": n, "dofs": dofs, "precision": head,
+                   "preconditioner": "green_jacobi", "contrast": args.contrast, "tol": tol},
+        "iters_per_step": R["iters"] / args.steps,
+        "outer_sweeps": R["reps"][-1].outer,
+        "rel_res_true": R["reps"][-1].rel_res_true,
+        "loop_ms": R["reps"][-1].loop_ms,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "avg_ms": avg_ms, "launches": launches,
+                     "algorithmic_bytes_per_launch": bytes_launch},
+        "kernels_ms_per_step": {k: v[1] / args.steps for k, v in sorted(stats.items())},
+    }
+    if "fp64" in results and head != "fp64":
+        F = results["fp64"]
+        line["fp64"] = {"value": dofs * F["iters"] / F["wall_s"],
+                        "ms_per_step": 1e3 * F["wall_s"] / args.steps,
+                        "iters_per_step": F["iters"] / args.steps,
+                        "rel_res_true": F["reps"][-1].rel_res_true,
+                        "loop_ms": F["reps"][-1].loop_ms,
+                        "sigma_bar_rel_diff_vs_mixed": float(
+                            np.abs(F["sigma_bar"] - R["sigma_bar"]).max()
+                            / np.abs(F["sigma_bar"]).max()),
+                        "kernels_ms_per_step": {k: v[1] / args.steps
+                                                for k, v in sorted(F["stats"].items())}}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(E, macro, nu)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

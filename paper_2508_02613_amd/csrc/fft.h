@@ -22,7 +22,11 @@
 namespace jfft {
 
 constexpr int FFT_THREADS = 256;
-constexpr int FFT_MAXPT = 16;  // max complex points per thread in one tile
+// max complex points per thread in one tile (2048 per 256-thread block)
+template <typename Real>
+struct MaxPt {
+  static constexpr int value = 8;
+};
 
 template <typename C>
 __device__ __forceinline__ C cmul(C a, C b) {
@@ -179,7 +183,7 @@ __device__ __forceinline__ void stockham_stage(typename CxT<Real>::T *buf, int L
                                                int sp, int sc, const typename CxT<Real>::T *tw,
                                                int tws, bool i_fastest) {
   using C = typename CxT<Real>::T;
-  constexpr int MB = (FFT_MAXPT + R - 1) / R;
+  constexpr int MB = (MaxPt<Real>::value + R - 1) / R;
   const int m = L / R;
   const int nb = m * W;
   const int step = L / (p * R);
@@ -439,7 +443,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
 }
 
 // ------------------------------------------------- strided C2C passes ----
-constexpr int FFT_W = 8;  // x bins per tile of a strided pass
+constexpr int FFT_WMAX = 16;  // x bins per tile of a strided pass (fewer for long axes)
 
 template <typename Real>
 struct YArgs {
@@ -448,35 +452,67 @@ struct YArgs {
   const double2 *tw;  // exp(-2 pi i j / L)
   FftPlan plan;
   int mx, mxp, ny, nz;
+  int W;  // x bins per tile, L * W <= MaxPt * FFT_THREADS
   int check_done;
 };
 
-// C2C along y for one (component, z) plane, tile of FFT_W x bins.
+// C2C along y on tiles of W x bins of one (component, z) plane.  Blocks are
+// persistent over tiles; the next tile's loads are in flight in registers
+// while the current tile is transformed in LDS.
 template <typename Real, bool INV>
 __global__ void __launch_bounds__(FFT_THREADS) k_ypass(YArgs<Real> a) {
   using C = typename CxT<Real>::T;
+  constexpr int PPT = MaxPt<Real>::value;
   if (a.check_done && a.st->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   const int L = a.ny;
+  const int W = a.W;
   C *buf = tw + L;
   load_twiddles<Real>(tw, a.tw, L);
-  const int kx0 = blockIdx.x * FFT_W;
-  const long long plane = (long long)blockIdx.z * a.nz + blockIdx.y;  // comp * nz + z
-  C *base = a.spec + plane * (long long)a.ny * a.mxp;
-  for (int f = threadIdx.x; f < L * FFT_W; f += FFT_THREADS) {
-    const int col = f % FFT_W, y = f / FFT_W;
-    C v;
-    v.x = 0;
-    v.y = 0;
-    if (kx0 + col < a.mx) v = base[(long long)y * a.mxp + kx0 + col];
-    buf[y * FFT_W + col] = v;
-  }
-  __syncthreads();
-  lds_fft<Real, INV>(buf, a.plan, FFT_W, FFT_W, 1, tw, 1, false);
-  for (int f = threadIdx.x; f < L * FFT_W; f += FFT_THREADS) {
-    const int col = f % FFT_W, y = f / FFT_W;
-    if (kx0 + col < a.mx) base[(long long)y * a.mxp + kx0 + col] = buf[y * FFT_W + col];
+  const int ntx = (a.mx + W - 1) / W;
+  const long long ntiles = (long long)ntx * a.nz * gridDim.y;  // gridDim.y = components
+  const int npts = L * W;
+  C pre[PPT];
+  auto tile_base = [&](long long t, int &kx0) {
+    kx0 = (int)(t % ntx) * W;
+    const long long plane = t / ntx + (long long)blockIdx.y * a.nz;  // comp * nz + z
+    return a.spec + plane * (long long)a.ny * a.mxp;
+  };
+  auto load = [&](long long t) {
+    int kx0;
+    const C *base = tile_base(t, kx0);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int f = threadIdx.x + j * FFT_THREADS;
+      const int col = f % W, y = f / W;
+      C v;
+      v.x = 0;
+      v.y = 0;
+      if (f < npts && kx0 + col < a.mx) v = base[(long long)y * a.mxp + kx0 + col];
+      pre[j] = v;
+    }
+  };
+  long long t = blockIdx.x;
+  const long long per_comp = (long long)ntx * a.nz;
+  (void)ntiles;
+  if (t < per_comp) load(t);
+  for (; t < per_comp; t += gridDim.x) {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int f = threadIdx.x + j * FFT_THREADS;
+      if (f < npts) buf[f] = pre[j];
+    }
+    __syncthreads();
+    if (t + gridDim.x < per_comp) load(t + gridDim.x);
+    lds_fft<Real, INV>(buf, a.plan, W, W, 1, tw, 1, false);
+    int kx0;
+    C *base = tile_base(t, kx0);
+    for (int f = threadIdx.x; f < npts; f += FFT_THREADS) {
+      const int col = f % W, y = f / W;
+      if (kx0 + col < a.mx) base[(long long)y * a.mxp + kx0 + col] = buf[f];
+    }
+    __syncthreads();
   }
 }
 
@@ -490,6 +526,7 @@ struct GArgs {
   double lam, mu;         // reference Lame constants
   double invN;            // 1 / N (normalisation of the unnormalised transforms)
   int dim, mx, mxp, ny, nz;
+  int W;                  // x bins per tile
   int check_done;
 };
 
@@ -557,8 +594,8 @@ __device__ __forceinline__ void green2(const double (&A)[2], const double (&B)[2
 }
 
 // Last axis: forward C2C, Green multiply, inverse C2C for every component of
-// a tile of FFT_W x bins (3D: at one ky; 2D: the whole y axis).
-template <typename Real, int DIM, int PPT>
+// a tile of W x bins (3D: at one ky; 2D: the whole y axis).
+template <typename Real, int DIM>
 __global__ void __launch_bounds__(FFT_THREADS) k_green_axis(GArgs<Real> a) {
   using C = typename CxT<Real>::T;
   if (a.check_done && a.st->done) return;
@@ -567,18 +604,19 @@ __global__ void __launch_bounds__(FFT_THREADS) k_green_axis(GArgs<Real> a) {
   const int L = DIM == 3 ? a.nz : a.ny;
   C *buf = tw + L;
   load_twiddles<Real>(tw, a.tw, L);
-  const int kx0 = blockIdx.x * FFT_W;
+  const int W = a.W;
+  const int kx0 = blockIdx.x * W;
   const int ky = DIM == 3 ? blockIdx.y : 0;
   // line (kx, ky) along the last axis: component c, position t
   const long long comp_stride = (long long)a.nz * a.ny * a.mxp;
   const long long axis_stride = DIM == 3 ? (long long)a.ny * a.mxp : (long long)a.mxp;
   C *base = a.spec + (DIM == 3 ? (long long)ky * a.mxp : 0) + kx0;
-  // PPT: points per thread kept across components (L * FFT_W <= PPT * FFT_THREADS)
+  constexpr int PPT = MaxPt<Real>::value;  // points per thread kept across components
   C stash[DIM][PPT];
-  const int npts = L * FFT_W;
+  const int npts = L * W;
   for (int c = 0; c < DIM; ++c) {
     for (int f = threadIdx.x; f < npts; f += FFT_THREADS) {
-      const int col = f % FFT_W, t = f / FFT_W;
+      const int col = f % W, t = f / W;
       C v;
       v.x = 0;
       v.y = 0;
@@ -586,7 +624,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_green_axis(GArgs<Real> a) {
       buf[f] = v;
     }
     __syncthreads();
-    lds_fft<Real, false>(buf, a.plan, FFT_W, FFT_W, 1, tw, 1, false);
+    lds_fft<Real, false>(buf, a.plan, W, W, 1, tw, 1, false);
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const int f = threadIdx.x + j * FFT_THREADS;
@@ -599,7 +637,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_green_axis(GArgs<Real> a) {
   for (int j = 0; j < PPT; ++j) {
     const int f = threadIdx.x + j * FFT_THREADS;
     if (f < npts) {
-      const int col = f % FFT_W, t = f / FFT_W;
+      const int col = f % W, t = f / W;
       const int kx = min(kx0 + col, a.mx - 1);
       if (DIM == 3) {
         const double A[3] = {a.tx.a[kx], a.ty.a[ky], a.tz.a[t]};
@@ -625,9 +663,9 @@ __global__ void __launch_bounds__(FFT_THREADS) k_green_axis(GArgs<Real> a) {
       if (f < npts) buf[f] = stash[c][j];
     }
     __syncthreads();
-    lds_fft<Real, true>(buf, a.plan, FFT_W, FFT_W, 1, tw, 1, false);
+    lds_fft<Real, true>(buf, a.plan, W, W, 1, tw, 1, false);
     for (int f = threadIdx.x; f < npts; f += FFT_THREADS) {
-      const int col = f % FFT_W, t = f / FFT_W;
+      const int col = f % W, t = f / W;
       if (kx0 + col < a.mx) base[c * comp_stride + (long long)t * axis_stride + col] = buf[f];
     }
     __syncthreads();

@@ -16,7 +16,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/jfft.h"
+#include "jfft.h"
 #include "cg.h"
 #include "fft.h"
 #include "jfft_common.h"
@@ -217,7 +217,18 @@ struct Layout {
   }
 };
 
-int x_rows_per_block(int m) { return std::max(1, std::min(64, 2048 / std::max(1, m))); }
+template <typename Real>
+int x_rows_per_block(int m) {
+  return std::max(1, std::min(64, MaxPt<Real>::value * FFT_THREADS / std::max(1, m)));
+}
+
+// x bins per tile of a strided pass over an axis of length L: 128-byte row
+// segments (8 double or 16 float complex bins), fewer for long axes
+template <typename Real>
+int tile_width(int L) {
+  const int w = 128 / (int)sizeof(typename CxT<Real>::T);
+  return std::max(1, std::min(w, MaxPt<Real>::value * FFT_THREADS / L));
+}
 
 // Compute (or apply) the workspace layout.  When base == nullptr only the size
 // is computed.
@@ -276,7 +287,7 @@ long long max_partials(jfft_cell_s *c) {
   mx = std::max(mx, tiles * ((g.nz + c->tz - 1) / c->tz));
   const int m = g.nx / 2;
   const long long rows = (long long)c->dim * g.ny * g.nz;
-  mx = std::max(mx, (rows + x_rows_per_block(m) - 1) / x_rows_per_block(m));
+  mx = std::max(mx, (rows + x_rows_per_block<double>(m) - 1) / x_rows_per_block<double>(m));
   mx = std::max(mx, (g.N + 255) / 256 * 6);  // stress partials [ds][blocks]
   return mx;
 }
@@ -366,7 +377,7 @@ jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a) {
   const int kid = MODE == SM_CG ? KID_STIFF_CG : (MODE == SM_APPLY ? KID_STIFF_APPLY : KID_STIFF_COMB);
   dim3 gr = stencil_grid(c);
   if (c->dim == 3) {
-    LAUNCH(c, kid, k_stiffness3d<Real, MODE><<<gr, STENCIL_THREADS, 0, c->stream>>>(a));
+    LAUNCH(c, kid, k_stiffness3d<Real, MODE><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a));
   } else {
     LAUNCH(c, kid, k_stiffness2d<Real, MODE><<<gr, STENCIL_THREADS, 0, c->stream>>>(a));
   }
@@ -408,7 +419,7 @@ jfft_status launch_xfwd(jfft_cell_s *c, Real *r, const Real *q, const Real *Jh,
   a.mxp = c->g.mxp;
   a.nrows = (long long)c->dim * c->g.ny * c->g.nz;
   const int m = c->g.nx / 2;
-  a.rows_per_block = x_rows_per_block(m);
+  a.rows_per_block = x_rows_per_block<Real>(m);
   a.check_done = check_done ? 1 : 0;
   const long long nb = (a.nrows + a.rows_per_block - 1) / a.rows_per_block;
   const size_t smem = sizeof(C) * (c->g.nx + (size_t)a.rows_per_block * (m + 1));
@@ -453,7 +464,7 @@ jfft_status launch_xinv(jfft_cell_s *c, const Real *r, const Real *Jh,
   a.mxp = c->g.mxp;
   a.nrows = (long long)c->dim * c->g.ny * c->g.nz;
   const int m = c->g.nx / 2;
-  a.rows_per_block = x_rows_per_block(m);
+  a.rows_per_block = x_rows_per_block<Real>(m);
   a.check_done = check_done ? 1 : 0;
   const long long nb = (a.nrows + a.rows_per_block - 1) / a.rows_per_block;
   const size_t smem = sizeof(C) * (c->g.nx + (size_t)a.rows_per_block * (m + 1));
@@ -481,8 +492,12 @@ jfft_status launch_ypass(jfft_cell_s *c, typename CxT<Real>::T *spec, bool inv, 
   a.ny = c->g.ny;
   a.nz = c->g.nz;
   a.check_done = check_done ? 1 : 0;
-  dim3 gr((c->g.mx + FFT_W - 1) / FFT_W, c->g.nz, c->dim);
-  const size_t smem = sizeof(C) * ((size_t)c->g.ny + (size_t)c->g.ny * FFT_W);
+  a.W = tile_width<Real>(c->g.ny);
+  // persistent blocks: a few per CU, each walking tiles of one component
+  const long long per_comp = (long long)((c->g.mx + a.W - 1) / a.W) * c->g.nz;
+  const long long want = std::max<long long>(1, 2048 / c->dim);
+  dim3 gr((unsigned)std::min(per_comp, want), c->dim, 1);
+  const size_t smem = sizeof(C) * ((size_t)c->g.ny + (size_t)c->g.ny * a.W);
   if (inv) {
     set_smem(k_ypass<Real, true>, smem);
     LAUNCH(c, KID_YINV, k_ypass<Real, true><<<gr, FFT_THREADS, smem, c->stream>>>(a));
@@ -515,25 +530,15 @@ jfft_status launch_green(jfft_cell_s *c, typename CxT<Real>::T *spec, bool check
   a.nz = c->g.nz;
   a.check_done = check_done ? 1 : 0;
   const int L = c->dim == 3 ? c->g.nz : c->g.ny;
-  dim3 gr((c->g.mx + FFT_W - 1) / FFT_W, c->dim == 3 ? c->g.ny : 1, 1);
-  const size_t smem = sizeof(C) * ((size_t)L + (size_t)L * FFT_W);
-  const bool big = (long long)L * FFT_W > 8 * FFT_THREADS;
+  a.W = tile_width<Real>(L);
+  dim3 gr((c->g.mx + a.W - 1) / a.W, c->dim == 3 ? c->g.ny : 1, 1);
+  const size_t smem = sizeof(C) * ((size_t)L + (size_t)L * a.W);
   if (c->dim == 3) {
-    if (big) {
-      set_smem(k_green_axis<Real, 3, 16>, smem);
-      LAUNCH(c, KID_GREEN, k_green_axis<Real, 3, 16><<<gr, FFT_THREADS, smem, c->stream>>>(a));
-    } else {
-      set_smem(k_green_axis<Real, 3, 8>, smem);
-      LAUNCH(c, KID_GREEN, k_green_axis<Real, 3, 8><<<gr, FFT_THREADS, smem, c->stream>>>(a));
-    }
+    set_smem(k_green_axis<Real, 3>, smem);
+    LAUNCH(c, KID_GREEN, k_green_axis<Real, 3><<<gr, FFT_THREADS, smem, c->stream>>>(a));
   } else {
-    if (big) {
-      set_smem(k_green_axis<Real, 2, 16>, smem);
-      LAUNCH(c, KID_GREEN, k_green_axis<Real, 2, 16><<<gr, FFT_THREADS, smem, c->stream>>>(a));
-    } else {
-      set_smem(k_green_axis<Real, 2, 8>, smem);
-      LAUNCH(c, KID_GREEN, k_green_axis<Real, 2, 8><<<gr, FFT_THREADS, smem, c->stream>>>(a));
-    }
+    set_smem(k_green_axis<Real, 2>, smem);
+    LAUNCH(c, KID_GREEN, k_green_axis<Real, 2><<<gr, FFT_THREADS, smem, c->stream>>>(a));
   }
   return JFFT_OK;
 }
@@ -879,7 +884,7 @@ jfft_status jfft_create_cell(int dim, const int n[3], const double len[3], jfft_
   g.nz = c->n[2];
   g.N = (long long)g.nx * g.ny * g.nz;
   g.mx = g.nx / 2 + 1;
-  g.mxp = g.mx;
+  g.mxp = (g.mx + 15) / 16 * 16;  // rows of the half spectrum start on 128/256-byte boundaries
   double evol = 1.0;
   g.vol = 1.0;
   double hs[3];
