@@ -81,8 +81,23 @@ typedef struct {
 jfft_status jfft_create_cell(int dim, const int n[3], const double len[3], jfft_precision prec,
                              jfft_precond pc, void *hip_stream, jfft_cell_t *out);
 
-/* Bytes of device workspace the cell needs (for caller-side allocation and
-   admission control). */
+/* Create a group of `batch` cells of identical grid, lengths, precision and
+   preconditioner on one stream, for throughput on many small cells (Sec. 4
+   workloads run one solve per cell and load case).  Each cell of the group has
+   its own material, macro strain, CG scalars and stopping test; every kernel
+   launch serves the whole group, and a cell that has stopped skips its share.
+   1 <= batch <= 65535.  jfft_create_cell is this call with batch = 1.  Only
+   jfft_solve_batch and the material, history, timing and option calls accept
+   a group with batch > 1; the single-cell operators reject it. */
+jfft_status jfft_create_batch(int dim, const int n[3], const double len[3], jfft_precision prec,
+                              jfft_precond pc, int batch, void *hip_stream, jfft_cell_t *out);
+
+/* Number of cells in the group (1 for jfft_create_cell handles). */
+jfft_status jfft_batch_size(jfft_cell_t cell, int *batch);
+
+/* Bytes of device workspace the cell (or the whole group: the figure grows
+   linearly with batch) needs, for caller-side allocation and admission
+   control. */
 jfft_status jfft_workspace_bytes(jfft_cell_t cell, size_t *bytes);
 
 /* Hand the cell a caller-owned device buffer of at least jfft_workspace_bytes
@@ -92,7 +107,8 @@ jfft_status jfft_workspace_bytes(jfft_cell_t cell, size_t *bytes);
 jfft_status jfft_bind_workspace(jfft_cell_t cell, void *dev_ptr, size_t bytes);
 
 /* Material field (Sec. 4): E_dev[N] >= 0 per element (copied, no aliasing
-   survives), Poisson ratio nu in (-1, 0.5) for C^ with unit modulus.  Runs
+   survives; a group takes E_dev[batch][N], one field per cell), Poisson ratio
+   nu in (-1, 0.5) for C^ with unit modulus, shared by the group.  Runs
    Algorithm 2 (Sec. 3.2, d 2^d stiffness applications to unit combs) on the
    device when the preconditioner uses J; the Green symbol G^ (Algorithm 1) is
    evaluated per frequency from the closed-form Fourier symbol of K_ref with
@@ -124,6 +140,31 @@ jfft_status jfft_solve(jfft_cell_t cell, const double *macro_strain, double tol,
                        const double *u0_dev, double *u_dev, double *sigma_dev,
                        double *sigma_bar, jfft_report *report);
 
+/* jfft_solve for every cell of a group at once.  Arrays are those of
+   jfft_solve with a leading cell index:
+     macro_strains: host [batch][d*];
+     u0_dev: [batch][d][N] or NULL;  u_dev: out [batch][d][N];
+     sigma_dev: out [batch][d*][2^d][N] or NULL;
+     sigma_bars: host out [batch][d*];  reports: host out [batch] or NULL.
+   tol and maxit apply to every cell; each cell stops on its own test.  Returns
+   JFFT_OK when every cell converged, else JFFT_E_BREAKDOWN if any cell broke
+   down, else JFFT_E_NOT_CONVERGED; per-cell outcomes are in reports[i].status.
+   The results of a cell do not depend on the other cells of the group. */
+jfft_status jfft_solve_batch(jfft_cell_t cell, const double *macro_strains, double tol, int maxit,
+                             const double *u0_dev, double *u_dev, double *sigma_dev,
+                             double *sigma_bars, jfft_report *reports);
+
+/* Launch mode of the PCG loop.  iterations = 0 (default): kernels are
+   launched one by one and the host polls the stop flags after 2, 4, ..., 32
+   iterations.  An even iterations in [2, 64]: the loop body of that many
+   iterations is captured once into a HIP graph (hipStreamBeginCapture on the
+   cell's stream) and replayed between polls; iterations past a cell's stop
+   cost only their launches.  Needs a stream other than the legacy default
+   stream; kernel timing (jfft_enable_timing) switches graph replay off.  The
+   graph is rebuilt after a change of material, history capacity or this
+   setting. */
+jfft_status jfft_set_graph_iterations(jfft_cell_t cell, int iterations);
+
 /* Operators, for verification and composition (all FP64, device in/out
    [d][N], stream-ordered, no synchronisation):
    out = K in (eq. lin_system_exp, the current material). */
@@ -137,11 +178,14 @@ jfft_status jfft_jacobi_diag(jfft_cell_t cell, double *diag_dev);
 
 /* Per-iteration scalar history of the last FP64 solve: alpha_k, beta_k and
    ||r_k|| for k = 1..min(iters, cap) (host arrays of length cap, any may be
-   NULL).  History is recorded only when enabled before the solve, with
+   NULL); the final iteration forms no beta, its entry is NaN.  History is recorded only when enabled before the solve, with
    0 <= cap <= 4096. */
 jfft_status jfft_enable_history(jfft_cell_t cell, int cap);
 jfft_status jfft_get_history(jfft_cell_t cell, double *alpha, double *beta, double *res,
                              int cap, int *count);
+/* The same for cell `index` of a group (jfft_get_history reads cell 0). */
+jfft_status jfft_get_batch_history(jfft_cell_t cell, int index, double *alpha, double *beta,
+                                   double *res, int cap, int *count);
 
 /* Kernel timing: when enabled, every kernel launch of the cell is bracketed by
    HIP events on the cell's stream and its duration accumulated per kernel

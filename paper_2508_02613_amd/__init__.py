@@ -43,18 +43,26 @@ class _Report(C.Structure):
 _SIGS = {
     "jfft_create_cell": (C.c_int, [C.c_int, C.POINTER(C.c_int), _dp, C.c_int, C.c_int, _vp,
                                    C.POINTER(_vp)]),
+    "jfft_create_batch": (C.c_int, [C.c_int, C.POINTER(C.c_int), _dp, C.c_int, C.c_int, C.c_int,
+                                    _vp, C.POINTER(_vp)]),
+    "jfft_batch_size": (C.c_int, [_vp, C.POINTER(C.c_int)]),
     "jfft_workspace_bytes": (C.c_int, [_vp, C.POINTER(C.c_size_t)]),
     "jfft_bind_workspace": (C.c_int, [_vp, _vp, C.c_size_t]),
     "jfft_set_material": (C.c_int, [_vp, _vp, C.c_double]),
     "jfft_set_material_lame": (C.c_int, [_vp, _vp, C.c_double, C.c_double]),
     "jfft_solve": (C.c_int, [_vp, _dp, C.c_double, C.c_int, _vp, _vp, _vp, _dp,
                              C.POINTER(_Report)]),
+    "jfft_solve_batch": (C.c_int, [_vp, _dp, C.c_double, C.c_int, _vp, _vp, _vp, _dp,
+                                   C.POINTER(_Report)]),
+    "jfft_set_graph_iterations": (C.c_int, [_vp, C.c_int]),
     "jfft_apply_stiffness": (C.c_int, [_vp, _vp, _vp]),
     "jfft_apply_precond": (C.c_int, [_vp, _vp, _vp]),
     "jfft_assemble_rhs": (C.c_int, [_vp, _dp, _vp]),
     "jfft_jacobi_diag": (C.c_int, [_vp, _vp]),
     "jfft_enable_history": (C.c_int, [_vp, C.c_int]),
     "jfft_get_history": (C.c_int, [_vp, _dp, _dp, _dp, C.c_int, C.POINTER(C.c_int)]),
+    "jfft_get_batch_history": (C.c_int, [_vp, C.c_int, _dp, _dp, _dp, C.c_int,
+                                         C.POINTER(C.c_int)]),
     "jfft_enable_timing": (C.c_int, [_vp, C.c_int]),
     "jfft_kernel_stats": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_long),
                                     _dp, C.POINTER(C.c_int)]),
@@ -118,6 +126,11 @@ class Report:
     post_ms: float
 
 
+def _report(rep):
+    return Report(rep.iters, rep.outer, _STATUS.get(rep.status, str(rep.status)), rep.rel_res,
+                  rep.rel_res_true, rep.setup_ms, rep.loop_ms, rep.post_ms)
+
+
 def _torch():
     import torch
     if not torch.cuda.is_available():
@@ -130,15 +143,18 @@ def _ptr(t):
 
 
 class Cell:
-    """One periodic cell on one GPU stream.
+    """One periodic cell, or a group of `batch` cells of one shape, on one GPU
+    stream.
 
     shape: (ny, nx) or (nz, ny, nx) node counts (x fastest, as the E arrays);
     precision FP64 or MIXED; pc one of PC_*; stream a torch.cuda.Stream (None =
     current stream).  The workspace is a torch uint8 tensor bound to the cell.
+    With batch > 1, material fields and results carry a leading cell index and
+    solve_batch replaces solve.
     """
 
     def __init__(self, shape, precision=FP64, pc=PC_GREEN_JACOBI, lengths=None, stream=None,
-                 device=None):
+                 device=None, batch=1):
         torch = _torch()
         lib = load_library()
         self.torch = torch
@@ -152,8 +168,9 @@ class Cell:
             ln = (C.c_double * 3)(*(list(lengths) + [1.0] * (3 - self.dim)))
         h = C.c_void_p()
         with torch.cuda.device(self.device):
-            _check(lib.jfft_create_cell(self.dim, n, ln, int(precision), int(pc),
-                                        C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+            _check(lib.jfft_create_batch(self.dim, n, ln, int(precision), int(pc), int(batch),
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.batch = int(batch)
         self._h = h
         self._lib = lib
         nb = C.c_size_t(0)
@@ -189,7 +206,7 @@ class Cell:
         return t
 
     def set_material(self, E, nu=None, lame=None):
-        E = self._dev(E, self.shape)
+        E = self._dev(E, self.shape if self.batch == 1 else (self.batch,) + self.shape)
         self._E = E
         if lame is not None:
             _check(self._lib.jfft_set_material_lame(self._h, _ptr(E), float(lame[0]), float(lame[1])))
@@ -219,9 +236,33 @@ class Cell:
                                   _ptr(sig), sbar, C.byref(rep))
         if st not in (0, 4, 5):
             _check(st)
-        r = Report(rep.iters, rep.outer, _STATUS.get(rep.status, str(rep.status)), rep.rel_res,
-                   rep.rel_res_true, rep.setup_ms, rep.loop_ms, rep.post_ms)
-        return u, np.array(sbar[:]), r, sig
+        return u, np.array(sbar[:]), _report(rep), sig
+
+    def solve_batch(self, macros, tol=1e-8, maxit=1000, u0=None, want_sigma=False, out=None):
+        """All cells of the group: macros [B, d*].  Returns (u [B, d, ...],
+        sigma_bar [B, d*], [Report] * B, sigma [B, d*, 2^d, ...] or None)."""
+        torch = self.torch
+        B = self.batch
+        vshape = (B, self.dim) + self.shape
+        u = out if out is not None else torch.empty(vshape, dtype=torch.float64, device=self.device)
+        sig = None
+        if want_sigma:
+            sig = torch.empty((B, self.ds, 2 ** self.dim) + self.shape, dtype=torch.float64,
+                              device=self.device)
+        u0t = self._dev(u0, vshape) if u0 is not None else None
+        mac = np.ascontiguousarray(np.asarray(macros, dtype=np.float64).reshape(B, self.ds))
+        sbar = np.zeros((B, self.ds))
+        reps = (_Report * B)()
+        st = self._lib.jfft_solve_batch(self._h, mac.ctypes.data_as(_dp), float(tol), int(maxit),
+                                        _ptr(u0t), _ptr(u), _ptr(sig), sbar.ctypes.data_as(_dp),
+                                        reps)
+        if st not in (0, 4, 5):
+            _check(st)
+        return u, sbar, [_report(r) for r in reps], sig
+
+    def set_graph_iterations(self, iterations):
+        """0: direct launches; even k in [2, 64]: replay k PCG iterations as one HIP graph."""
+        _check(self._lib.jfft_set_graph_iterations(self._h, int(iterations)))
 
     def apply_stiffness(self, x):
         x = self._dev(x, (self.dim,) + self.shape)
@@ -253,13 +294,14 @@ class Cell:
     def enable_history(self, cap):
         _check(self._lib.jfft_enable_history(self._h, int(cap)))
 
-    def history(self, cap):
+    def history(self, cap, index=0):
         a = np.zeros(cap)
         b = np.zeros(cap)
         r = np.zeros(cap)
         cnt = C.c_int(0)
-        _check(self._lib.jfft_get_history(self._h, a.ctypes.data_as(_dp), b.ctypes.data_as(_dp),
-                                          r.ctypes.data_as(_dp), int(cap), C.byref(cnt)))
+        _check(self._lib.jfft_get_batch_history(self._h, int(index), a.ctypes.data_as(_dp),
+                                                b.ctypes.data_as(_dp), r.ctypes.data_as(_dp),
+                                                int(cap), C.byref(cnt)))
         k = cnt.value
         return a[:k], b[:k], r[:k]
 

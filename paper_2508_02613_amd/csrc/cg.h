@@ -1,9 +1,11 @@
 // Preconditioned CG control (Saad Alg. 9.1 in the split form used by the
 // paper's footnote to eq. prec_lin_system_general) kept on the device:
-// single-block kernels reduce the per-block partial sums in a fixed order
-// (deterministic) and update the scalars alpha, beta, the iteration count and
-// the stop flag.  Every loop kernel returns at once when the flag is set, so
-// the host may queue iterations ahead of the convergence test.
+// single-block kernels (one block per cell of a batch) reduce the per-block
+// partial sums in a fixed order (deterministic) and update the scalars alpha,
+// beta, the iteration count and the stop flag.  Every loop kernel returns at
+// once when its cell's flag is set, so the host may queue (or replay as a
+// graph) iterations ahead of the convergence test, and cells of a batch stop
+// independently.
 #pragma once
 #include "jfft_common.h"
 #include "stencil.h"
@@ -26,13 +28,25 @@ struct History {
   double *alpha, *beta, *res;
 };
 
+__device__ __forceinline__ void shift_hist(History &h, int cell, long long cs) {
+  h.alpha = cshift(h.alpha, cell, cs);
+  h.beta = cshift(h.beta, cell, cs);
+  h.res = cshift(h.res, cell, cs);
+}
+
 // alpha_k = (r.z) / (p.q); breakdown if p.q <= 0 or alpha not finite.
-__global__ void k_cg_alpha(CgState *st, const double *part, long long n, History h) {
+// parity: which of the two search-direction buffers holds p_k.
+__global__ void k_cg_alpha(CgState *st, const double *part, long long n, History h, int parity,
+                           long long cs) {
   __shared__ double sm[8];
+  st = cshift(st, blockIdx.x, cs);
+  part = cshift(part, blockIdx.x, cs);
+  shift_hist(h, blockIdx.x, cs);
   if (st->done) return;
   const double pq = fixed_sum(part, n, sm);
   if (threadIdx.x == 0) {
     st->pq = pq;
+    st->parity = parity;
     const double alpha = st->rz / pq;
     if (!(pq > 0.0) || !isfinite(alpha)) {
       st->done = 1;
@@ -47,8 +61,11 @@ __global__ void k_cg_alpha(CgState *st, const double *part, long long n, History
 }
 
 // ||r_{k+1}||^2; count the update of u; stop on tolerance or maxit.
-__global__ void k_cg_rr(CgState *st, const double *part, long long n, History h) {
+__global__ void k_cg_rr(CgState *st, const double *part, long long n, History h, long long cs) {
   __shared__ double sm[8];
+  st = cshift(st, blockIdx.x, cs);
+  part = cshift(part, blockIdx.x, cs);
+  shift_hist(h, blockIdx.x, cs);
   if (st->done) return;
   const double rr = fixed_sum(part, n, sm);
   if (threadIdx.x == 0) {
@@ -62,12 +79,17 @@ __global__ void k_cg_rr(CgState *st, const double *part, long long n, History h)
       st->done = 1;
       st->status = ST_NOT_CONVERGED;
     }
+    // the last iteration forms no beta: its history entry is NaN
+    if (st->done && h.beta && st->iter - 1 < st->hist_cap) h.beta[st->iter - 1] = __builtin_nan("");
   }
 }
 
 // beta_k = (r.z)_new / (r.z)_old.
-__global__ void k_cg_beta(CgState *st, const double *part, long long n, History h) {
+__global__ void k_cg_beta(CgState *st, const double *part, long long n, History h, long long cs) {
   __shared__ double sm[8];
+  st = cshift(st, blockIdx.x, cs);
+  part = cshift(part, blockIdx.x, cs);
+  shift_hist(h, blockIdx.x, cs);
   if (st->done) return;
   const double rz = fixed_sum(part, n, sm);
   if (threadIdx.x == 0) {
@@ -84,23 +106,70 @@ __global__ void k_cg_beta(CgState *st, const double *part, long long n, History 
   }
 }
 
+// ||f||^2 and ||f_abs||^2 from partials; the homogeneous-material test.
+__global__ void k_solve_norms(CgState *st, const double *partF, const double *partA, long long n,
+                              long long cs) {
+  __shared__ double sm[8];
+  st = cshift(st, blockIdx.x, cs);
+  partF = cshift(partF, blockIdx.x, cs);
+  partA = cshift(partA, blockIdx.x, cs);
+  const double f2 = fixed_sum(partF, n, sm);
+  const double a2 = fixed_sum(partA, n, sm);
+  if (threadIdx.x == 0) {
+    st->fnorm2 = f2;
+    st->fabs2 = a2;
+    st->homog = (sqrt(f2) <= 1e-13 * sqrt(a2)) ? 1 : 0;
+    st->outer_done = st->homog;
+    st->outer = 0;
+    st->total_iters = 0;
+    st->final_status = ST_OK;
+    st->rn = sqrt(f2);
+  }
+}
+
+// Inner PCG set-up.  FP64 solve (mixed = 0): stop at ||r|| <= tol ||f||.
+// Mixed inner solve on r / ||r|| (mixed = 1): stop at relative
+// max(inner_tol, tol ||f|| / (2 ||r||)).  Cells already finished (homogeneous
+// material, or refinement converged) start in the stopped state.
+__global__ void k_cg_init(CgState *st, double tol, double inner_tol, int mixed, int maxit,
+                          int hist_cap, long long cs) {
+  st = cshift(st, blockIdx.x, cs);
+  if (threadIdx.x != 0) return;
+  double t2;
+  int mx = maxit;
+  if (mixed) {
+    const double rel = fmax(inner_tol, 0.5 * tol * sqrt(st->fnorm2) / st->rn);
+    t2 = rel * rel;
+    mx = maxit - st->total_iters;
+    if (mx < 1) mx = 1;
+  } else {
+    t2 = tol * tol * st->fnorm2;
+  }
+  st->tol2 = t2;
+  st->maxit = mx;
+  st->hist_cap = hist_cap;
+  st->iter = 0;
+  st->done = st->outer_done;
+  st->status = ST_OK;
+  st->pending = 0;
+  st->first = 1;
+  st->parity = 0;
+}
+
 // Start of the loop: rr0 and rz0 from partials; stop at once when
 // ||r_0||^2 <= tol2 (or maxit == 0).
 __global__ void k_cg_start(CgState *st, const double *partRR, long long nRR, const double *partRZ,
-                           long long nRZ) {
+                           long long nRZ, long long cs) {
   __shared__ double sm[8];
+  st = cshift(st, blockIdx.x, cs);
+  partRR = cshift(partRR, blockIdx.x, cs);
+  partRZ = cshift(partRZ, blockIdx.x, cs);
   const double rr = fixed_sum(partRR, nRR, sm);
   const double rz = fixed_sum(partRZ, nRZ, sm);
   if (threadIdx.x == 0) {
+    if (st->done) return;  // finished before this solve
     st->rr = rr;
     st->rz = rz;
-    st->first = 1;
-    st->pending = 0;
-    st->iter = 0;
-    st->beta = 0.0;
-    st->alpha = 0.0;
-    st->done = 0;
-    st->status = ST_OK;
     if (rr <= st->tol2) {
       st->done = 1;
     } else if (st->maxit <= 0) {
@@ -110,9 +179,57 @@ __global__ void k_cg_start(CgState *st, const double *partRR, long long nRR, con
   }
 }
 
-// Generic fixed-order reduction of `count` groups of n partials each into out[g].
-__global__ void k_reduce_groups(const double *part, long long n, int count, double *out) {
+// Mixed precision: the FP64 residual ||f - K u|| of this sweep decides
+// whether refinement continues.  (The first sweep starts from u = u0.)
+__global__ void k_outer_check(CgState *st, const double *part, long long n, double tol,
+                              int max_outer, int maxit, long long cs) {
   __shared__ double sm[8];
+  st = cshift(st, blockIdx.x, cs);
+  part = cshift(part, blockIdx.x, cs);
+  const double rr = fixed_sum(part, n, sm);
+  if (threadIdx.x == 0) {
+    if (st->outer_done) return;
+    const double rn = sqrt(rr);
+    st->rn = rn;
+    if (rn <= tol * sqrt(st->fnorm2)) {
+      st->outer_done = 1;
+      st->final_status = ST_OK;
+    } else if (st->outer >= max_outer || st->total_iters >= maxit) {
+      st->outer_done = 1;
+      st->final_status = ST_NOT_CONVERGED;
+    }
+  }
+}
+
+// After an inner solve: count it; a breakdown before any progress ends the
+// refinement.
+__global__ void k_outer_update(CgState *st, long long cs) {
+  st = cshift(st, blockIdx.x, cs);
+  if (threadIdx.x != 0 || st->outer_done) return;
+  st->outer += 1;
+  st->total_iters += st->iter;
+  if (st->status == ST_BREAKDOWN && st->iter == 0) {
+    st->outer_done = 1;
+    st->final_status = ST_BREAKDOWN;
+  }
+}
+
+// FP64 solve: final status from the loop state.
+__global__ void k_fp64_final(CgState *st, long long cs) {
+  st = cshift(st, blockIdx.x, cs);
+  if (threadIdx.x != 0) return;
+  st->total_iters = st->iter;
+  st->outer = st->homog ? 0 : 1;
+  st->final_status = st->homog ? ST_OK : st->status;
+}
+
+// Generic fixed-order reduction of `count` groups of n partials each into out[g]
+// (one block per cell).
+__global__ void k_reduce_groups(const double *part, long long n, int count, double *out,
+                                long long cs) {
+  __shared__ double sm[8];
+  part = cshift(part, blockIdx.x, cs);
+  out = cshift(out, blockIdx.x, cs);
   for (int g = 0; g < count; ++g) {
     const double s = fixed_sum(part + (long long)g * n, n, sm);
     if (threadIdx.x == 0) out[g] = s;
@@ -120,20 +237,34 @@ __global__ void k_reduce_groups(const double *part, long long n, int count, doub
 }
 
 // ------------------------------------------------------ vector kernels ---
-// u += alpha p if an update is pending (after the loop stopped).
+// All take the cell from blockIdx.y (blockIdx.z where y is the component).
+
+// u += alpha p_k if an update is pending (after the loop stopped); p_k is
+// the buffer recorded in st->parity.
 template <typename Real>
-__global__ void k_finish_u(Real *u, const Real *p, long long n, const CgState *st) {
+__global__ void k_finish_u(Real *u, const Real *p0, const Real *p1, long long n, const CgState *st,
+                           long long cs) {
+  const int cell = blockIdx.y;
+  st = cshift(st, cell, cs);
   if (!st->pending) return;
+  u = cshift(u, cell, cs);
+  const Real *p = cshift(st->parity ? p1 : p0, cell, cs);
   const Real alpha = (Real)st->alpha;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     u[i] += alpha * p[i];
 }
 
-// out = a - b, with partial sums of out.out.
+// out = a - b (out may be NULL), with partial sums of (a - b)^2.
 template <typename Real>
-__global__ void k_sub_norm(const Real *a, const Real *b, Real *out, long long n, double *part) {
+__global__ void k_sub_norm(const Real *a, const Real *b, Real *out, long long n, double *part,
+                           long long cs) {
   __shared__ double red[8];
+  const int cell = blockIdx.y;
+  a = cshift(a, cell, cs);
+  b = cshift(b, cell, cs);
+  out = cshift(out, cell, cs);
+  part = cshift(part, cell, cs);
   double acc = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -147,8 +278,12 @@ __global__ void k_sub_norm(const Real *a, const Real *b, Real *out, long long n,
 
 // Partial sums of x.y (y may equal x).
 template <typename Real>
-__global__ void k_dot(const Real *x, const Real *y, long long n, double *part) {
+__global__ void k_dot(const Real *x, const Real *y, long long n, double *part, long long cs) {
   __shared__ double red[8];
+  const int cell = blockIdx.y;
+  x = cshift(x, cell, cs);
+  y = cshift(y, cell, cs);
+  part = cshift(part, cell, cs);
   double acc = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -157,11 +292,14 @@ __global__ void k_dot(const Real *x, const Real *y, long long n, double *part) {
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// Per-component partial sums of x: part[c * nblk + b].
+// Per-component partial sums of x: part[c * nblk + b] (component blockIdx.y,
+// cell blockIdx.z).
 template <typename Real>
-__global__ void k_comp_sum(const Real *x, long long N, double *part) {
+__global__ void k_comp_sum(const Real *x, long long N, double *part, long long cs) {
   __shared__ double red[8];
   const int c = blockIdx.y;
+  x = cshift(x, blockIdx.z, cs);
+  part = cshift(part, blockIdx.z, cs);
   double acc = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x)
@@ -172,31 +310,52 @@ __global__ void k_comp_sum(const Real *x, long long N, double *part) {
 
 // x[c] -= sums[c] / N.
 template <typename Real>
-__global__ void k_sub_mean(Real *x, long long N, const double *sums) {
+__global__ void k_sub_mean(Real *x, long long N, const double *sums, long long cs) {
   const int c = blockIdx.y;
+  x = cshift(x, blockIdx.z, cs);
+  sums = cshift(sums, blockIdx.z, cs);
   const Real m = (Real)(sums[c] / (double)N);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x)
     x[c * N + i] -= m;
 }
 
+// b = a between arrays with their own cell strides.
 template <typename Real>
-__global__ void k_copy(const Real *a, Real *b, long long n) {
+__global__ void k_copy(const Real *a, long long as, Real *b, long long bs, long long n) {
+  a = cshift(a, blockIdx.y, as);
+  b = cshift(b, blockIdx.y, bs);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     b[i] = a[i];
 }
 
 template <typename Real>
-__global__ void k_fill(Real *a, Real v, long long n) {
+__global__ void k_fill(Real *a, Real v, long long n, long long cs) {
+  a = cshift(a, blockIdx.y, cs);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     a[i] = v;
 }
 
+// u = u0 unless the cell's material is homogeneous (then u = 0).
+__global__ void k_start_vector(const double *u0, long long u0s, double *u, long long n,
+                               const CgState *st, long long cs) {
+  const int cell = blockIdx.y;
+  st = cshift(st, cell, cs);
+  u = cshift(u, cell, cs);
+  if (u0) u0 = cshift(u0, cell, u0s);
+  const bool zero = st->homog || !u0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    u[i] = zero ? 0.0 : u0[i];
+}
+
 // J^1/2 = diag^-1/2 after the void rule (exact zeros -> void_value).
 template <typename Real>
-__global__ void k_jhalf(const double *diag, Real *Jh, long long n, double void_value) {
+__global__ void k_jhalf(const double *diag, Real *Jh, long long n, double void_value, long long cs) {
+  diag = cshift(diag, blockIdx.y, cs);
+  Jh = cshift(Jh, blockIdx.y, cs);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     double d = diag[i];
@@ -205,9 +364,11 @@ __global__ void k_jhalf(const double *diag, Real *Jh, long long n, double void_v
   }
 }
 
-// Element moduli: validity check (finite, >= 0) by partial counts of bad entries.
-__global__ void k_check_E(const double *E, long long n, double *part) {
+// Element moduli: partial counts of bad entries (negative or non-finite).
+__global__ void k_check_E(const double *E, long long es, long long n, double *part, long long cs) {
   __shared__ double red[8];
+  E = cshift(E, blockIdx.y, es);
+  part = cshift(part, blockIdx.y, cs);
   double bad = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
@@ -218,16 +379,29 @@ __global__ void k_check_E(const double *E, long long n, double *part) {
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// Conversions for the mixed-precision path.
+// b = a * scale; with st != NULL the scale is 1 / st->rn (mixed refinement).
 template <typename A, typename B>
-__global__ void k_convert(const A *a, B *b, long long n, double scale) {
+__global__ void k_convert(const A *a, B *b, long long n, double scale, const CgState *st,
+                          long long cs) {
+  a = cshift(a, blockIdx.y, cs);
+  b = cshift(b, blockIdx.y, cs);
+  if (st) {
+    st = cshift(st, blockIdx.y, cs);
+    scale = st->rn > 0.0 ? 1.0 / st->rn : 0.0;
+  }
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     b[i] = (B)((double)a[i] * scale);
 }
 
-// u64 += scale * c32 (iterative refinement correction).
-__global__ void k_axpy_f32_to_f64(const float *c, double *u, long long n, double scale) {
+// u64 += ||r|| c32 (iterative refinement correction) while refining.
+__global__ void k_axpy_f32_to_f64(const float *c, double *u, long long n, const CgState *st,
+                                  long long cs) {
+  st = cshift(st, blockIdx.y, cs);
+  if (st->outer_done) return;
+  c = cshift(c, blockIdx.y, cs);
+  u = cshift(u, blockIdx.y, cs);
+  const double scale = st->rn;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     u[i] += scale * (double)c[i];

@@ -262,16 +262,30 @@ struct XArgs {
   const double2 *tw;   // exp(-2 pi i j / nx), j < nx
   FftPlan plan;        // length nx / 2
   int nx, mx, mxp;
-  long long nrows;     // d * ny * nz
+  long long nrows;     // d * ny * nz rows per cell
   int rows_per_block;
   int check_done;
+  long long cs;        // bytes between the cells of a batch (cell = blockIdx.y)
 };
+
+template <typename Real>
+__device__ __forceinline__ void shift_x(XArgs<Real> &a) {
+  const int cell = blockIdx.y;
+  a.r = cshift(a.r, cell, a.cs);
+  a.q = cshift(a.q, cell, a.cs);
+  a.Jh = cshift(a.Jh, cell, a.cs);
+  a.out = cshift(a.out, cell, a.cs);
+  a.spec = cshift(a.spec, cell, a.cs);
+  a.partA = cshift(a.partA, cell, a.cs);
+  a.st = cshift(a.st, cell, a.cs);
+}
 
 // Forward: r <- r - alpha q (UPDATE), s = J^1/2 r (USE_J), X = rfft(s) per row.
 template <typename Real, bool UPDATE, bool USE_J>
 __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
   using C = typename CxT<Real>::T;
   using R2 = typename CxT<Real>::R2;
+  shift_x(a);
   if (a.check_done && a.st->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
@@ -364,6 +378,7 @@ template <typename Real, bool USE_J>
 __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
   using C = typename CxT<Real>::T;
   using R2 = typename CxT<Real>::R2;
+  shift_x(a);
   if (a.check_done && a.st->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
@@ -454,6 +469,7 @@ struct YArgs {
   int mx, mxp, ny, nz;
   int W;  // x bins per tile, L * W <= MaxPt * FFT_THREADS
   int check_done;
+  long long cs;  // bytes between the cells of a batch (cell = blockIdx.z)
 };
 
 // C2C along y on tiles of W x bins of one (component, z) plane.  Blocks are
@@ -463,6 +479,8 @@ template <typename Real, bool INV>
 __global__ void __launch_bounds__(FFT_THREADS) k_ypass(YArgs<Real> a) {
   using C = typename CxT<Real>::T;
   constexpr int PPT = MaxPt<Real>::value;
+  a.spec = cshift(a.spec, blockIdx.z, a.cs);
+  a.st = cshift(a.st, blockIdx.z, a.cs);
   if (a.check_done && a.st->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
@@ -528,6 +546,7 @@ struct GArgs {
   int dim, mx, mxp, ny, nz;
   int W;                  // x bins per tile
   int check_done;
+  long long cs;           // bytes between the cells of a batch (cell = blockIdx.z)
 };
 
 // Green multiply at one frequency: zh = G^(k) sh with G^ = K^_ref(k)^-1 / N,
@@ -598,6 +617,8 @@ __device__ __forceinline__ void green2(const double (&A)[2], const double (&B)[2
 template <typename Real, int DIM>
 __global__ void __launch_bounds__(FFT_THREADS) k_green_axis(GArgs<Real> a) {
   using C = typename CxT<Real>::T;
+  a.spec = cshift(a.spec, blockIdx.z, a.cs);
+  a.st = cshift(a.st, blockIdx.z, a.cs);
   if (a.check_done && a.st->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
@@ -678,7 +699,15 @@ __global__ void __launch_bounds__(FFT_THREADS) k_green_axis(GArgs<Real> a) {
 template <typename Real, bool UPDATE, bool JACOBI>
 __global__ void __launch_bounds__(256) k_diag_pc(Real *r, const Real *q, const Real *Jh, Real *z,
                                                  long long n, const CgState *st, int check_done,
-                                                 double *partA, double *partB) {
+                                                 double *partA, double *partB, long long cs) {
+  const int cell = blockIdx.y;
+  r = cshift(r, cell, cs);
+  q = cshift(q, cell, cs);
+  Jh = cshift(Jh, cell, cs);
+  z = cshift(z, cell, cs);
+  st = cshift(st, cell, cs);
+  partA = cshift(partA, cell, cs);
+  partB = cshift(partB, cell, cs);
   if (check_done && st->done) return;
   __shared__ double red[8];
   Real alpha = 0;

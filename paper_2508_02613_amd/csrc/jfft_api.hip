@@ -1,11 +1,20 @@
 // Host driver and C ABI of the MI355X J-FFT solver (see include/jfft.h).
 //
-// One cell = one periodic grid on one stream.  set_material copies E, runs
-// Algorithm 2 (d 2^d stiffness applications to unit combs, Sec. 3.2) on the
-// device and forms J^1/2.  solve assembles f, runs the PCG loop entirely on
-// the device (CG scalars live in device memory; the host only polls the stop
-// flag every few iterations), then removes the mean of u (Sec. 5), recomputes
-// the true residual and evaluates the stresses and sigma_bar.
+// A handle holds a group of B periodic cells of identical shape (B = 1 for
+// the single-cell entry points) on one stream.  Their workspace is one device
+// buffer of B equal slices plus a shared region of read-only tables; kernels
+// find their cell from a grid dimension and shift their pointers by the slice
+// stride, so one launch serves the whole group and every cell keeps its own
+// CG state and stops on its own.
+//
+// set_material copies E, runs Algorithm 2 (d 2^d stiffness applications to
+// unit combs, Sec. 3.2) and forms J^1/2.  solve assembles f, runs the PCG
+// loop entirely on the device (CG scalars in device memory; the host only
+// polls the stop flags every few iterations, optionally replaying the
+// iterations as a captured HIP graph), then removes the mean of u (Sec. 5),
+// recomputes the true residual with the FP64 stiffness and evaluates the
+// stresses and sigma_bar.  The mixed mode runs FP32 inner solves inside an
+// FP64 iterative-refinement loop whose decisions are also taken on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -13,12 +22,13 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
-#include "jfft.h"
 #include "cg.h"
 #include "fft.h"
+#include "jfft.h"
 #include "jfft_common.h"
 #include "stencil.h"
 
@@ -45,9 +55,16 @@ static jfft_status fail(jfft_status st, const std::string &msg) {
       return fail(JFFT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));           \
   } while (0)
 
+#define TRY(expr)                 \
+  do {                            \
+    jfft_status _s = (expr);      \
+    if (_s != JFFT_OK) return _s; \
+  } while (0)
+
 namespace {
 
 constexpr int kHistMax = 4096;
+constexpr int kSmall = 64;  // doubles of per-cell reduction results
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -72,11 +89,18 @@ bool factor_plan(int L, FftPlan &pl) {
   return true;
 }
 
+// Pointers of cell 0 for one precision.
 template <typename Real>
 struct PcgBufs {
   Real *u, *r, *z, *q, *p[2];
   const Real *E, *Jh;
   typename CxT<Real>::T *spec;
+};
+
+struct Tunables {
+  int tz = 32;          // z planes per stiffness block (3D)
+  int ygrid = 2048;     // persistent blocks of the y pass (all components and cells)
+  int graph_iters = 0;  // iterations per captured graph (0: launch kernels directly)
 };
 
 }  // namespace
@@ -89,36 +113,37 @@ struct jfft_cell_s {
   jfft_precond pc = JFFT_PC_GREEN_JACOBI;
   hipStream_t stream = nullptr;
   int device = 0;
+  int B = 1;  // cells in the group
   GridDev g{};
   FftPlan plan_x{}, plan_y{}, plan_z{};
-  int tz = 32;
+  Tunables tun;
 
-  // workspace
+  // workspace: B slices of `cs` bytes, then the shared tables
   unsigned char *ws = nullptr;
   size_t ws_bytes = 0;
+  long long cs = 0;
   bool ws_owned = false;
   bool ready = false;
 
-  // FP64 buffers
+  // per-cell buffers (pointers of cell 0)
   double *E = nullptr, *Jh = nullptr, *diag = nullptr, *f = nullptr, *r = nullptr, *z = nullptr,
-         *q = nullptr, *p[2] = {nullptr, nullptr};
+         *q = nullptr, *p[2] = {nullptr, nullptr}, *u = nullptr;
   double2 *spec = nullptr;
-  // FP32 buffers (MIXED)
   float *E32 = nullptr, *Jh32 = nullptr, *r32 = nullptr, *z32 = nullptr, *q32 = nullptr,
         *p32[2] = {nullptr, nullptr}, *c32 = nullptr;
   float2 *spec32 = nullptr;
-  // tables
-  double2 *tw[3] = {nullptr, nullptr, nullptr};
-  double *ftab[3][3] = {};
   double *F = nullptr, *macro = nullptr;
   CgState *st = nullptr;
   double *partA = nullptr, *partB = nullptr;
   long long npart = 0;
   double *small = nullptr;
   double *hist[3] = {nullptr, nullptr, nullptr};
-  int hist_cap = 0;  // entries recorded per solve (<= kHistMax)
+  int hist_cap = 0;
+  // shared tables
+  double2 *tw[3] = {nullptr, nullptr, nullptr};
+  double *ftab[3][3] = {};
 
-  // host pinned mirrors
+  // host pinned mirrors (B entries)
   CgState *st_h = nullptr;
   double *small_h = nullptr;
 
@@ -127,6 +152,11 @@ struct jfft_cell_s {
   double void_value = 1.0;
   double inner_tol = 1e-5;
   int max_outer = 30;
+
+  // captured iteration chunks
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};  // [0] FP64, [1] FP32 inner
+  int gexec_iters[2] = {0, 0};
+  bool capturing = false;
 
   // timing
   bool timing = false;
@@ -138,11 +168,20 @@ struct jfft_cell_s {
   std::vector<hipEvent_t> pool;
   double ktime[KID_COUNT] = {};
   long kcount[KID_COUNT] = {};
-
   hipEvent_t phase_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+
+  void drop_graphs() {
+    for (int k = 0; k < 2; ++k)
+      if (gexec[k]) {
+        (void)hipGraphExecDestroy(gexec[k]);
+        gexec[k] = nullptr;
+        gexec_iters[k] = 0;
+      }
+  }
 
   ~jfft_cell_s() {
     flush_timing();
+    drop_graphs();
     for (auto &e : pool) (void)hipEventDestroy(e);
     for (auto &e : phase_ev)
       if (e) (void)hipEventDestroy(e);
@@ -176,13 +215,13 @@ struct jfft_cell_s {
     pend.clear();
   }
   hipEvent_t tb(int) {
-    if (!timing) return nullptr;
+    if (!timing || capturing) return nullptr;
     hipEvent_t a = get_event();
     (void)hipEventRecord(a, stream);
     return a;
   }
   void te(int kid, hipEvent_t a) {
-    if (!timing || !a) return;
+    if (!timing || capturing || !a) return;
     hipEvent_t b = get_event();
     (void)hipEventRecord(b, stream);
     pend.push_back({kid, a, b});
@@ -203,6 +242,9 @@ struct jfft_cell_s {
 
 namespace {
 
+// Blocks per cell of the grid-stride vector kernels.  Like every other
+// reduction layout of the library it depends on the cell shape only, so a
+// cell gives bitwise the same results alone and inside any group.
 int vec_blocks(long long n) {
   long long b = (n + 255) / 256;
   return (int)std::max<long long>(1, std::min<long long>(b, 1024));
@@ -230,8 +272,11 @@ int tile_width(int L) {
   return std::max(1, std::min(w, MaxPt<Real>::value * FFT_THREADS / L));
 }
 
-// Compute (or apply) the workspace layout.  When base == nullptr only the size
-// is computed.
+bool useJ(const jfft_cell_s *c) { return c->pc == JFFT_PC_JACOBI || c->pc == JFFT_PC_GREEN_JACOBI; }
+bool useG(const jfft_cell_s *c) { return c->pc == JFFT_PC_GREEN || c->pc == JFFT_PC_GREEN_JACOBI; }
+
+// Slice layout (one cell) and the shared tables.  With base == nullptr only
+// sizes are computed; returns the total bytes.
 size_t layout_workspace(jfft_cell_s *c, unsigned char *base) {
   const long long N = c->g.N;
   const int d = c->dim;
@@ -244,47 +289,54 @@ size_t layout_workspace(jfft_cell_s *c, unsigned char *base) {
   };
   put(c->E, sizeof(double) * N);
   put(c->f, sizeof(double) * nd);
+  put(c->u, sizeof(double) * nd);
   put(c->r, sizeof(double) * nd);
   put(c->z, sizeof(double) * nd);
   put(c->q, sizeof(double) * nd);
   put(c->p[0], sizeof(double) * nd);
   put(c->p[1], sizeof(double) * nd);
-  const bool useJ = c->pc == JFFT_PC_JACOBI || c->pc == JFFT_PC_GREEN_JACOBI;
-  const bool useG = c->pc == JFFT_PC_GREEN || c->pc == JFFT_PC_GREEN_JACOBI;
   put(c->diag, sizeof(double) * nd);
-  if (useJ) put(c->Jh, sizeof(double) * nd);
-  if (useG) put(c->spec, sizeof(double2) * nspec);
+  if (useJ(c)) put(c->Jh, sizeof(double) * nd);
+  if (useG(c)) put(c->spec, sizeof(double2) * nspec);
   if (c->prec == JFFT_MIXED) {
     put(c->E32, sizeof(float) * N);
-    if (useJ) put(c->Jh32, sizeof(float) * nd);
+    if (useJ(c)) put(c->Jh32, sizeof(float) * nd);
     put(c->r32, sizeof(float) * nd);
     put(c->z32, sizeof(float) * nd);
     put(c->q32, sizeof(float) * nd);
     put(c->p32[0], sizeof(float) * nd);
     put(c->p32[1], sizeof(float) * nd);
     put(c->c32, sizeof(float) * nd);
-    if (useG) put(c->spec32, sizeof(float2) * nspec);
-  }
-  for (int a = 0; a < 3; ++a) {
-    const int n = a == 0 ? c->g.nx : (a == 1 ? c->g.ny : c->g.nz);
-    put(c->tw[a], sizeof(double2) * n);
-    for (int t = 0; t < 3; ++t) put(c->ftab[a][t], sizeof(double) * n);
+    if (useG(c)) put(c->spec32, sizeof(float2) * nspec);
   }
   put(c->F, sizeof(double) * 24);
   put(c->macro, sizeof(double) * 8);
   put(c->st, sizeof(CgState));
   put(c->partA, sizeof(double) * c->npart);
   put(c->partB, sizeof(double) * c->npart);
-  put(c->small, sizeof(double) * 64);
+  put(c->small, sizeof(double) * kSmall);
   for (int t = 0; t < 3; ++t) put(c->hist[t], sizeof(double) * kHistMax);
-  return L.off;
+  const size_t slice = align_up(L.off, 256);
+  if (base) c->cs = (long long)slice;
+  Layout T;
+  T.off = slice * (size_t)c->B;
+  for (int a = 0; a < 3; ++a) {
+    const int n = a == 0 ? c->g.nx : (a == 1 ? c->g.ny : c->g.nz);
+    size_t o = T.take(sizeof(double2) * n);
+    if (base) c->tw[a] = reinterpret_cast<double2 *>(base + o);
+    for (int t = 0; t < 3; ++t) {
+      o = T.take(sizeof(double) * n);
+      if (base) c->ftab[a][t] = reinterpret_cast<double *>(base + o);
+    }
+  }
+  return T.off;
 }
 
 long long max_partials(jfft_cell_s *c) {
   const GridDev &g = c->g;
-  long long mx = 4 * 1024;  // vector kernels, stress blocks (<= 1024 per group, up to 6 groups)
+  long long mx = 4 * 1024;  // vector kernels
   const long long tiles = (long long)((g.nx + TILE - 1) / TILE) * ((g.ny + TILE - 1) / TILE);
-  mx = std::max(mx, tiles * ((g.nz + c->tz - 1) / c->tz));
+  mx = std::max(mx, tiles * ((g.nz + 4 - 1) / 4));  // smallest z chunk used
   const int m = g.nx / 2;
   const long long rows = (long long)c->dim * g.ny * g.nz;
   mx = std::max(mx, (rows + x_rows_per_block<double>(m) - 1) / x_rows_per_block<double>(m));
@@ -298,27 +350,39 @@ jfft_status upload_tables(jfft_cell_s *c) {
   for (int a = 0; a < 3; ++a) {
     const int n = ns[a];
     std::vector<double2> tw(n);
-    std::vector<double> A(n), B(n), S(n);
+    std::vector<double> A(n), Bt(n), S(n);
     for (int j = 0; j < n; ++j) {
       const double t = 2.0 * M_PI * (double)j / (double)n;
       const double cs = std::cos(t), sn = std::sin(t);
       tw[j].x = cs;
       tw[j].y = -sn;
       A[j] = (2.0 - 2.0 * cs) / hs[a];
-      B[j] = hs[a] * (2.0 + cs) / 3.0;
+      Bt[j] = hs[a] * (2.0 + cs) / 3.0;
       S[j] = sn;
     }
-    HIP_TRY(hipMemcpyAsync(c->tw[a], tw.data(), sizeof(double2) * n, hipMemcpyHostToDevice,
-                           c->stream));
-    HIP_TRY(hipMemcpyAsync(c->ftab[a][0], A.data(), sizeof(double) * n, hipMemcpyHostToDevice,
-                           c->stream));
-    HIP_TRY(hipMemcpyAsync(c->ftab[a][1], B.data(), sizeof(double) * n, hipMemcpyHostToDevice,
-                           c->stream));
-    HIP_TRY(hipMemcpyAsync(c->ftab[a][2], S.data(), sizeof(double) * n, hipMemcpyHostToDevice,
-                           c->stream));
+    HIP_TRY(hipMemcpyAsync(c->tw[a], tw.data(), sizeof(double2) * n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->ftab[a][0], A.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->ftab[a][1], Bt.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->ftab[a][2], S.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
   }
   HIP_TRY(hipStreamSynchronize(c->stream));  // host vectors go out of scope
   return JFFT_OK;
+}
+
+// Kernels that may need more than 64 KiB of dynamic LDS (512-point axes in FP64).
+void set_smem_attributes() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    const int big = 160 * 1024;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_ypass<double, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_ypass<double, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_green_axis<double, 3>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_green_axis<double, 2>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  });
 }
 
 jfft_status ensure_ready(jfft_cell_s *c) {
@@ -335,8 +399,8 @@ jfft_status ensure_ready(jfft_cell_s *c) {
     return fail(JFFT_E_OOM, "bound workspace smaller than jfft_workspace_bytes");
   }
   layout_workspace(c, c->ws);
-  jfft_status s = upload_tables(c);
-  if (s) return s;
+  TRY(upload_tables(c));
+  c->drop_graphs();
   c->ready = true;
   return JFFT_OK;
 }
@@ -355,27 +419,25 @@ StencilArgs<Real> stencil_args(jfft_cell_s *c, const Real *E) {
   a.ny = c->g.ny;
   a.nz = c->g.nz;
   a.N = c->g.N;
-  a.tz = c->tz;
+  a.tz = c->dim == 3 ? std::min(c->tun.tz, c->g.nz) : 1;
+  a.nbz = c->dim == 3 ? (c->g.nz + a.tz - 1) / a.tz : 1;
+  a.cs = c->cs;
   a.st = c->st;
   return a;
 }
 
-dim3 stencil_grid(jfft_cell_s *c) {
+long long stencil_blocks_per_cell(jfft_cell_s *c) {
   const GridDev &g = c->g;
-  if (c->dim == 3)
-    return dim3((g.nx + TILE - 1) / TILE, (g.ny + TILE - 1) / TILE, (g.nz + c->tz - 1) / c->tz);
-  return dim3((g.nx + TILE - 1) / TILE, (g.ny + TILE - 1) / TILE, 1);
-}
-
-long long stencil_blocks(jfft_cell_s *c) {
-  dim3 gr = stencil_grid(c);
-  return (long long)gr.x * gr.y * gr.z;
+  const int tz = c->dim == 3 ? std::min(c->tun.tz, g.nz) : 1;
+  const int nbz = c->dim == 3 ? (g.nz + tz - 1) / tz : 1;
+  return (long long)((g.nx + TILE - 1) / TILE) * ((g.ny + TILE - 1) / TILE) * nbz;
 }
 
 template <typename Real, int MODE>
-jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a) {
+jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a, int cells) {
   const int kid = MODE == SM_CG ? KID_STIFF_CG : (MODE == SM_APPLY ? KID_STIFF_APPLY : KID_STIFF_COMB);
-  dim3 gr = stencil_grid(c);
+  const GridDev &g = c->g;
+  dim3 gr((g.nx + TILE - 1) / TILE, (g.ny + TILE - 1) / TILE, a.nbz * cells);
   if (c->dim == 3) {
     LAUNCH(c, kid, k_stiffness3d<Real, MODE><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a));
   } else {
@@ -384,19 +446,29 @@ jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a) {
   return JFFT_OK;
 }
 
+// out = K in for `cells` cells of the group (pointers of cell 0, slice stride).
 template <typename Real>
-jfft_status apply_K(jfft_cell_s *c, const Real *E, const Real *in, Real *out) {
+jfft_status apply_K(jfft_cell_s *c, const Real *E, const Real *in, Real *out, int cells) {
   StencilArgs<Real> a = stencil_args<Real>(c, E);
   a.in = in;
   a.out = out;
-  return launch_stiffness<Real, SM_APPLY>(c, a);
+  return launch_stiffness<Real, SM_APPLY>(c, a, cells);
 }
 
-template <typename K>
-void set_smem(K kernel, size_t bytes) {
-  if (bytes > 64 * 1024)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+template <typename Real>
+XArgs<Real> x_args(jfft_cell_s *c, bool check_done) {
+  XArgs<Real> a{};
+  a.st = c->st;
+  a.tw = c->tw[0];
+  a.plan = c->plan_x;
+  a.nx = c->g.nx;
+  a.mx = c->g.mx;
+  a.mxp = c->g.mxp;
+  a.nrows = (long long)c->dim * c->g.ny * c->g.nz;
+  a.rows_per_block = x_rows_per_block<Real>(c->g.nx / 2);
+  a.check_done = check_done ? 1 : 0;
+  a.cs = c->cs;
+  return a;
 }
 
 // Forward x pass: spec = rfft_x(J^1/2 (r - alpha q)), partA = ||r||^2 partials.
@@ -405,42 +477,27 @@ jfft_status launch_xfwd(jfft_cell_s *c, Real *r, const Real *q, const Real *Jh,
                         typename CxT<Real>::T *spec, double *partA, bool update, bool check_done,
                         long long *nblk) {
   using C = typename CxT<Real>::T;
-  XArgs<Real> a{};
+  XArgs<Real> a = x_args<Real>(c, check_done);
   a.r = r;
   a.q = q;
   a.Jh = Jh;
   a.spec = spec;
   a.partA = partA;
-  a.st = c->st;
-  a.tw = c->tw[0];
-  a.plan = c->plan_x;
-  a.nx = c->g.nx;
-  a.mx = c->g.mx;
-  a.mxp = c->g.mxp;
-  a.nrows = (long long)c->dim * c->g.ny * c->g.nz;
   const int m = c->g.nx / 2;
-  a.rows_per_block = x_rows_per_block<Real>(m);
-  a.check_done = check_done ? 1 : 0;
   const long long nb = (a.nrows + a.rows_per_block - 1) / a.rows_per_block;
   const size_t smem = sizeof(C) * (c->g.nx + (size_t)a.rows_per_block * (m + 1));
   *nblk = nb;
-  const bool useJ = Jh != nullptr;
+  dim3 gr((unsigned)nb, c->B);
   if (update) {
-    if (useJ) {
-      set_smem(k_xfwd<Real, true, true>, smem);
-      LAUNCH(c, KID_XFWD, k_xfwd<Real, true, true><<<(unsigned)nb, FFT_THREADS, smem, c->stream>>>(a));
-    } else {
-      set_smem(k_xfwd<Real, true, false>, smem);
-      LAUNCH(c, KID_XFWD, k_xfwd<Real, true, false><<<(unsigned)nb, FFT_THREADS, smem, c->stream>>>(a));
-    }
+    if (Jh)
+      LAUNCH(c, KID_XFWD, k_xfwd<Real, true, true><<<gr, FFT_THREADS, smem, c->stream>>>(a));
+    else
+      LAUNCH(c, KID_XFWD, k_xfwd<Real, true, false><<<gr, FFT_THREADS, smem, c->stream>>>(a));
   } else {
-    if (useJ) {
-      set_smem(k_xfwd<Real, false, true>, smem);
-      LAUNCH(c, KID_XFWD, k_xfwd<Real, false, true><<<(unsigned)nb, FFT_THREADS, smem, c->stream>>>(a));
-    } else {
-      set_smem(k_xfwd<Real, false, false>, smem);
-      LAUNCH(c, KID_XFWD, k_xfwd<Real, false, false><<<(unsigned)nb, FFT_THREADS, smem, c->stream>>>(a));
-    }
+    if (Jh)
+      LAUNCH(c, KID_XFWD, k_xfwd<Real, false, true><<<gr, FFT_THREADS, smem, c->stream>>>(a));
+    else
+      LAUNCH(c, KID_XFWD, k_xfwd<Real, false, false><<<gr, FFT_THREADS, smem, c->stream>>>(a));
   }
   return JFFT_OK;
 }
@@ -450,32 +507,21 @@ jfft_status launch_xinv(jfft_cell_s *c, const Real *r, const Real *Jh,
                         typename CxT<Real>::T *spec, Real *out, double *partB, bool check_done,
                         long long *nblk) {
   using C = typename CxT<Real>::T;
-  XArgs<Real> a{};
+  XArgs<Real> a = x_args<Real>(c, check_done);
   a.r = const_cast<Real *>(r);
   a.Jh = Jh;
   a.out = out;
   a.spec = spec;
   a.partA = partB;
-  a.st = c->st;
-  a.tw = c->tw[0];
-  a.plan = c->plan_x;
-  a.nx = c->g.nx;
-  a.mx = c->g.mx;
-  a.mxp = c->g.mxp;
-  a.nrows = (long long)c->dim * c->g.ny * c->g.nz;
   const int m = c->g.nx / 2;
-  a.rows_per_block = x_rows_per_block<Real>(m);
-  a.check_done = check_done ? 1 : 0;
   const long long nb = (a.nrows + a.rows_per_block - 1) / a.rows_per_block;
   const size_t smem = sizeof(C) * (c->g.nx + (size_t)a.rows_per_block * (m + 1));
   *nblk = nb;
-  if (Jh) {
-    set_smem(k_xinv<Real, true>, smem);
-    LAUNCH(c, KID_XINV, k_xinv<Real, true><<<(unsigned)nb, FFT_THREADS, smem, c->stream>>>(a));
-  } else {
-    set_smem(k_xinv<Real, false>, smem);
-    LAUNCH(c, KID_XINV, k_xinv<Real, false><<<(unsigned)nb, FFT_THREADS, smem, c->stream>>>(a));
-  }
+  dim3 gr((unsigned)nb, c->B);
+  if (Jh)
+    LAUNCH(c, KID_XINV, k_xinv<Real, true><<<gr, FFT_THREADS, smem, c->stream>>>(a));
+  else
+    LAUNCH(c, KID_XINV, k_xinv<Real, false><<<gr, FFT_THREADS, smem, c->stream>>>(a));
   return JFFT_OK;
 }
 
@@ -492,19 +538,17 @@ jfft_status launch_ypass(jfft_cell_s *c, typename CxT<Real>::T *spec, bool inv, 
   a.ny = c->g.ny;
   a.nz = c->g.nz;
   a.check_done = check_done ? 1 : 0;
+  a.cs = c->cs;
   a.W = tile_width<Real>(c->g.ny);
-  // persistent blocks: a few per CU, each walking tiles of one component
+  // persistent blocks, each walking tiles of one (component, cell)
   const long long per_comp = (long long)((c->g.mx + a.W - 1) / a.W) * c->g.nz;
-  const long long want = std::max<long long>(1, 2048 / c->dim);
-  dim3 gr((unsigned)std::min(per_comp, want), c->dim, 1);
+  const long long want = std::max<long long>(1, c->tun.ygrid / ((long long)c->dim * c->B));
+  dim3 gr((unsigned)std::min(per_comp, want), c->dim, c->B);
   const size_t smem = sizeof(C) * ((size_t)c->g.ny + (size_t)c->g.ny * a.W);
-  if (inv) {
-    set_smem(k_ypass<Real, true>, smem);
+  if (inv)
     LAUNCH(c, KID_YINV, k_ypass<Real, true><<<gr, FFT_THREADS, smem, c->stream>>>(a));
-  } else {
-    set_smem(k_ypass<Real, false>, smem);
+  else
     LAUNCH(c, KID_YFWD, k_ypass<Real, false><<<gr, FFT_THREADS, smem, c->stream>>>(a));
-  }
   return JFFT_OK;
 }
 
@@ -529,142 +573,173 @@ jfft_status launch_green(jfft_cell_s *c, typename CxT<Real>::T *spec, bool check
   a.ny = c->g.ny;
   a.nz = c->g.nz;
   a.check_done = check_done ? 1 : 0;
+  a.cs = c->cs;
   const int L = c->dim == 3 ? c->g.nz : c->g.ny;
   a.W = tile_width<Real>(L);
-  dim3 gr((c->g.mx + a.W - 1) / a.W, c->dim == 3 ? c->g.ny : 1, 1);
+  dim3 gr((c->g.mx + a.W - 1) / a.W, c->dim == 3 ? c->g.ny : 1, c->B);
   const size_t smem = sizeof(C) * ((size_t)L + (size_t)L * a.W);
-  if (c->dim == 3) {
-    set_smem(k_green_axis<Real, 3>, smem);
+  if (c->dim == 3)
     LAUNCH(c, KID_GREEN, k_green_axis<Real, 3><<<gr, FFT_THREADS, smem, c->stream>>>(a));
-  } else {
-    set_smem(k_green_axis<Real, 2>, smem);
+  else
     LAUNCH(c, KID_GREEN, k_green_axis<Real, 2><<<gr, FFT_THREADS, smem, c->stream>>>(a));
-  }
   return JFFT_OK;
 }
 
 // z = M^-1 r.  update: r <- r - alpha q first.  Partials: partA = ||r||^2,
-// partB = r.z.  With ctrl, the CG control kernels run between the pieces.
+// partB = r.z.  In the loop, the CG control kernels run between the pieces.
 template <typename Real>
 jfft_status precond(jfft_cell_s *c, Real *r, const Real *q, const Real *Jh, Real *z,
                     typename CxT<Real>::T *spec, bool update, bool in_loop, long long *nA,
                     long long *nB, History h) {
-  const bool useG = c->pc == JFFT_PC_GREEN || c->pc == JFFT_PC_GREEN_JACOBI;
-  const bool useJ = c->pc == JFFT_PC_JACOBI || c->pc == JFFT_PC_GREEN_JACOBI;
-  if (!useG) {
+  const int Bc = c->B;
+  if (!useG(c)) {
     const long long n = (long long)c->dim * c->g.N;
     const int nb = vec_blocks(n);
     *nA = *nB = nb;
     const int cd = in_loop ? 1 : 0;
+    dim3 gr(nb, Bc);
+    const Real *J = useJ(c) ? Jh : nullptr;
     if (update) {
-      if (useJ)
-        LAUNCH(c, KID_DIAGPC, k_diag_pc<Real, true, true><<<nb, 256, 0, c->stream>>>(r, q, Jh, z, n, c->st, cd, c->partA, c->partB));
+      if (J)
+        LAUNCH(c, KID_DIAGPC, k_diag_pc<Real, true, true><<<gr, 256, 0, c->stream>>>(r, q, J, z, n, c->st, cd, c->partA, c->partB, c->cs));
       else
-        LAUNCH(c, KID_DIAGPC, k_diag_pc<Real, true, false><<<nb, 256, 0, c->stream>>>(r, q, Jh, z, n, c->st, cd, c->partA, c->partB));
+        LAUNCH(c, KID_DIAGPC, k_diag_pc<Real, true, false><<<gr, 256, 0, c->stream>>>(r, q, J, z, n, c->st, cd, c->partA, c->partB, c->cs));
     } else {
-      if (useJ)
-        LAUNCH(c, KID_DIAGPC, k_diag_pc<Real, false, true><<<nb, 256, 0, c->stream>>>(r, q, Jh, z, n, c->st, cd, c->partA, c->partB));
+      if (J)
+        LAUNCH(c, KID_DIAGPC, k_diag_pc<Real, false, true><<<gr, 256, 0, c->stream>>>(r, q, J, z, n, c->st, cd, c->partA, c->partB, c->cs));
       else
-        LAUNCH(c, KID_DIAGPC, k_diag_pc<Real, false, false><<<nb, 256, 0, c->stream>>>(r, q, Jh, z, n, c->st, cd, c->partA, c->partB));
+        LAUNCH(c, KID_DIAGPC, k_diag_pc<Real, false, false><<<gr, 256, 0, c->stream>>>(r, q, J, z, n, c->st, cd, c->partA, c->partB, c->cs));
     }
     if (in_loop) {
-      LAUNCH(c, KID_CTRL, k_cg_rr<<<1, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, *nA, h));
-      LAUNCH(c, KID_CTRL, k_cg_beta<<<1, CTRL_THREADS, 0, c->stream>>>(c->st, c->partB, *nB, h));
+      LAUNCH(c, KID_CTRL, k_cg_rr<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, *nA, h, c->cs));
+      LAUNCH(c, KID_CTRL, k_cg_beta<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partB, *nB, h, c->cs));
     }
     return JFFT_OK;
   }
-  const Real *J = useJ ? Jh : nullptr;
-  jfft_status s = launch_xfwd<Real>(c, r, q, J, spec, c->partA, update, in_loop, nA);
-  if (s) return s;
-  if (in_loop) LAUNCH(c, KID_CTRL, k_cg_rr<<<1, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, *nA, h));
+  const Real *J = useJ(c) ? Jh : nullptr;
+  TRY(launch_xfwd<Real>(c, r, q, J, spec, c->partA, update, in_loop, nA));
+  if (in_loop) LAUNCH(c, KID_CTRL, k_cg_rr<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, *nA, h, c->cs));
   if (c->dim == 3) {
-    if ((s = launch_ypass<Real>(c, spec, false, in_loop))) return s;
-    if ((s = launch_green<Real>(c, spec, in_loop))) return s;
-    if ((s = launch_ypass<Real>(c, spec, true, in_loop))) return s;
+    TRY(launch_ypass<Real>(c, spec, false, in_loop));
+    TRY(launch_green<Real>(c, spec, in_loop));
+    TRY(launch_ypass<Real>(c, spec, true, in_loop));
   } else {
-    if ((s = launch_green<Real>(c, spec, in_loop))) return s;
+    TRY(launch_green<Real>(c, spec, in_loop));
   }
-  s = launch_xinv<Real>(c, r, J, spec, z, c->partB, in_loop, nB);
-  if (s) return s;
-  if (in_loop) LAUNCH(c, KID_CTRL, k_cg_beta<<<1, CTRL_THREADS, 0, c->stream>>>(c->st, c->partB, *nB, h));
+  TRY(launch_xinv<Real>(c, r, J, spec, z, c->partB, in_loop, nB));
+  if (in_loop) LAUNCH(c, KID_CTRL, k_cg_beta<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partB, *nB, h, c->cs));
   return JFFT_OK;
 }
 
-__global__ void k_cg_init(CgState *st, double tol2, int maxit, int hist_cap) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st->tol2 = tol2;
-    st->maxit = maxit;
-    st->hist_cap = hist_cap;
-    st->iter = 0;
-    st->done = 0;
-    st->status = 0;
-    st->pending = 0;
-    st->first = 1;
-  }
-}
-
-// PCG loop on prepared buffers: u holds the start vector, r = f - K u.
-// Returns after the device flag is set; the final state is in c->st_h.
+// One PCG iteration j (p_old = p[j & 1], p_new = p[(j + 1) & 1]).
 template <typename Real>
-jfft_status run_pcg(jfft_cell_s *c, const PcgBufs<Real> &b, double tol2, int maxit, bool record) {
-  History h{nullptr, nullptr, nullptr};
-  if (record && c->hist_cap > 0) h = {c->hist[0], c->hist[1], c->hist[2]};
-  long long nA = 0, nB = 0;
-  LAUNCH(c, KID_CTRL, k_cg_init<<<1, 1, 0, c->stream>>>(c->st, tol2, maxit, record ? c->hist_cap : 0));
-  jfft_status s = precond<Real>(c, b.r, nullptr, b.Jh, b.z, b.spec, false, false, &nA, &nB, h);
-  if (s) return s;
-  LAUNCH(c, KID_CTRL, k_cg_start<<<1, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nA, c->partB, nB));
-  const long long nK = stencil_blocks(c);
-  int it = 0;
-  int chunk = 2;
-  for (;;) {
-    for (int k = 0; k < chunk; ++k) {
-      ++it;
-      StencilArgs<Real> a = stencil_args<Real>(c, b.E);
-      a.in = b.p[it & 1];
-      a.zin = b.z;
-      a.pout = b.p[(it + 1) & 1];
-      a.u = b.u;
-      a.out = b.q;
-      a.partial = c->partA;
-      if ((s = launch_stiffness<Real, SM_CG>(c, a))) return s;
-      LAUNCH(c, KID_CTRL, k_cg_alpha<<<1, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nK, h));
-      if ((s = precond<Real>(c, b.r, b.q, b.Jh, b.z, b.spec, true, true, &nA, &nB, h))) return s;
-    }
-    HIP_TRY(hipMemcpyAsync(c->st_h, c->st, sizeof(CgState), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    if (c->st_h->done) break;
-    chunk = std::min(chunk * 2, 32);
-  }
-  // apply the owed update u += alpha p_k (p_k written by iteration iter)
-  const long long n = (long long)c->dim * c->g.N;
-  const Real *plast = b.p[(c->st_h->iter + 1) & 1];
-  LAUNCH(c, KID_VEC, k_finish_u<Real><<<vec_blocks(n), 256, 0, c->stream>>>(b.u, plast, n, c->st));
-  return JFFT_OK;
+jfft_status pcg_iteration(jfft_cell_s *c, const PcgBufs<Real> &b, int j, History h) {
+  StencilArgs<Real> a = stencil_args<Real>(c, b.E);
+  a.in = b.p[j & 1];
+  a.zin = b.z;
+  a.pout = b.p[(j + 1) & 1];
+  a.u = b.u;
+  a.out = b.q;
+  a.partial = c->partA;
+  TRY((launch_stiffness<Real, SM_CG>(c, a, c->B)));
+  const long long nK = stencil_blocks_per_cell(c);
+  LAUNCH(c, KID_CTRL, k_cg_alpha<<<c->B, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nK, h, (j + 1) & 1, c->cs));
+  long long nA, nB;
+  return precond<Real>(c, b.r, b.q, b.Jh, b.z, b.spec, true, true, &nA, &nB, h);
 }
 
-// Sum of n partials (one group) into small[slot]; no host sync.
-jfft_status reduce_to(jfft_cell_s *c, const double *part, long long n, int groups, int slot) {
-  LAUNCH(c, KID_REDUCE, k_reduce_groups<<<1, CTRL_THREADS, 0, c->stream>>>(part, n, groups, c->small + slot));
-  return JFFT_OK;
-}
-
-jfft_status fetch_small(jfft_cell_s *c, int count) {
-  HIP_TRY(hipMemcpyAsync(c->small_h, c->small, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+jfft_status fetch_states(jfft_cell_s *c) {
+  HIP_TRY(hipMemcpy2DAsync(c->st_h, sizeof(CgState), c->st, (size_t)c->cs, sizeof(CgState), c->B,
+                           hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return JFFT_OK;
 }
 
-jfft_status assemble_rhs(jfft_cell_s *c, const double *macro_h, double *f, double *fabs_out) {
-  const int ds = c->dim * (c->dim + 1) / 2;
-  HIP_TRY(hipMemcpyAsync(c->macro, macro_h, sizeof(double) * ds, hipMemcpyHostToDevice, c->stream));
-  LAUNCH(c, KID_RHS, k_unit_force<<<1, 1, 0, c->stream>>>(c->F, c->macro, c->dim, c->lam * c->g.w, c->mu * c->g.w, c->g.ihx, c->g.ihy, c->g.ihz));
-  const long long N = c->g.N;
-  LAUNCH(c, KID_RHS, k_rhs<double><<<(unsigned)((N + 255) / 256), 256, 0, c->stream>>>(c->E, c->F, f, fabs_out, c->dim, c->g.nx, c->g.ny, c->g.nz, N));
+// PCG loop on prepared buffers (u = start vector, r = f - K u) for every cell
+// of the group; returns when every cell's flag is set.
+template <typename Real>
+jfft_status run_pcg(jfft_cell_s *c, const PcgBufs<Real> &b, double tol, bool mixed, int maxit,
+                    bool record) {
+  History h{nullptr, nullptr, nullptr};
+  if (record && c->hist_cap > 0) h = {c->hist[0], c->hist[1], c->hist[2]};
+  long long nA = 0, nB = 0;
+  LAUNCH(c, KID_CTRL, k_cg_init<<<c->B, 1, 0, c->stream>>>(c->st, tol, c->inner_tol, mixed ? 1 : 0, maxit, record ? c->hist_cap : 0, c->cs));
+  TRY(precond<Real>(c, b.r, nullptr, b.Jh, b.z, b.spec, false, false, &nA, &nB, h));
+  LAUNCH(c, KID_CTRL, k_cg_start<<<c->B, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nA, c->partB, nB, c->cs));
+  const int gk = sizeof(Real) == 8 ? 0 : 1;
+  const int G = c->tun.graph_iters;
+  const bool graph = G > 0 && !c->timing;
+  if (graph && (!c->gexec[gk] || c->gexec_iters[gk] != G)) {
+    // capture G iterations once; their arguments never change (the buffers of
+    // this handle are fixed) and the CG state lives in device memory
+    if (c->gexec[gk]) {
+      (void)hipGraphExecDestroy(c->gexec[gk]);
+      c->gexec[gk] = nullptr;
+    }
+    hipGraph_t gr = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
+    jfft_status s = JFFT_OK;
+    for (int j = 1; j <= G && s == JFFT_OK; ++j) s = pcg_iteration<Real>(c, b, j, h);
+    c->capturing = false;
+    hipError_t e = hipStreamEndCapture(c->stream, &gr);
+    if (s) return s;
+    if (e != hipSuccess) return fail(JFFT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->gexec[gk], gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) return fail(JFFT_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    c->gexec_iters[gk] = G;
+  }
+  int it = 0;
+  int chunk = 2;
+  for (;;) {
+    if (graph) {
+      const int reps = std::max(1, chunk / G);
+      for (int k = 0; k < reps; ++k) HIP_TRY(hipGraphLaunch(c->gexec[gk], c->stream));
+    } else {
+      for (int k = 0; k < chunk; ++k) {
+        ++it;
+        TRY(pcg_iteration<Real>(c, b, it, h));
+      }
+    }
+    TRY(fetch_states(c));
+    bool done = true;
+    for (int i = 0; i < c->B; ++i) done = done && c->st_h[i].done;
+    if (done) break;
+    chunk = std::min(chunk * 2, 32);
+  }
+  // the owed update u += alpha p_k of every cell
+  const long long n = (long long)c->dim * c->g.N;
+  LAUNCH(c, KID_VEC, k_finish_u<Real><<<dim3(vec_blocks(n), c->B), 256, 0, c->stream>>>(b.u, b.p[0], b.p[1], n, c->st, c->cs));
   return JFFT_OK;
 }
 
-jfft_status run_alg2(jfft_cell_s *c, double *diag_out) {
+jfft_status reduce_to(jfft_cell_s *c, const double *part, long long n, int groups, int slot,
+                      int cells) {
+  LAUNCH(c, KID_REDUCE, k_reduce_groups<<<cells, CTRL_THREADS, 0, c->stream>>>(part, n, groups, c->small + slot, c->cs));
+  return JFFT_OK;
+}
+
+jfft_status fetch_small(jfft_cell_s *c) {
+  HIP_TRY(hipMemcpy2DAsync(c->small_h, sizeof(double) * kSmall, c->small, (size_t)c->cs,
+                           sizeof(double) * kSmall, c->B, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return JFFT_OK;
+}
+
+// Macro strains (host, [cells][d*]) into each cell's slice, then f (and |f|).
+jfft_status assemble_rhs(jfft_cell_s *c, const double *macros_h, double *f, double *fabs_out,
+                         int cells) {
+  const int ds = c->dim * (c->dim + 1) / 2;
+  HIP_TRY(hipMemcpy2DAsync(c->macro, (size_t)c->cs, macros_h, sizeof(double) * ds, sizeof(double) * ds,
+                           cells, hipMemcpyHostToDevice, c->stream));
+  LAUNCH(c, KID_RHS, k_unit_force<<<cells, 1, 0, c->stream>>>(c->F, c->macro, c->dim, c->lam * c->g.w, c->mu * c->g.w, c->g.ihx, c->g.ihy, c->g.ihz, c->cs));
+  const long long N = c->g.N;
+  LAUNCH(c, KID_RHS, k_rhs<double><<<dim3((unsigned)((N + 255) / 256), cells), 256, 0, c->stream>>>(c->E, c->F, f, fabs_out, c->dim, c->g.nx, c->g.ny, c->g.nz, N, c->cs));
+  return JFFT_OK;
+}
+
+jfft_status run_alg2(jfft_cell_s *c, double *diag_out, int cells) {
   StencilArgs<double> a = stencil_args<double>(c, c->E);
   a.diag = diag_out;
   const int nloc = 1 << c->dim;
@@ -672,8 +747,7 @@ jfft_status run_alg2(jfft_cell_s *c, double *diag_out) {
     for (int off = 0; off < nloc; ++off) {
       a.comb_comp = comp;
       a.comb_off = off;
-      jfft_status s = launch_stiffness<double, SM_COMB>(c, a);
-      if (s) return s;
+      TRY((launch_stiffness<double, SM_COMB>(c, a, cells)));
     }
   return JFFT_OK;
 }
@@ -682,27 +756,31 @@ jfft_status set_material_impl(jfft_cell_s *c, const double *E_dev, double lam, d
   if (!E_dev) return fail(JFFT_E_INVALID, "E_dev is NULL");
   if (!(mu > 0.0) || !(lam + 2.0 * mu / c->dim > 0.0) || !std::isfinite(lam) || !std::isfinite(mu))
     return fail(JFFT_E_INVALID, "Lame constants must satisfy mu > 0 and lambda + 2 mu / d > 0");
-  jfft_status s = ensure_ready(c);
-  if (s) return s;
+  TRY(ensure_ready(c));
+  c->has_material = false;
   c->lam = lam;
   c->mu = mu;
+  c->drop_graphs();  // kernel arguments carry lambda and mu
   const long long N = c->g.N;
+  const long long es = (long long)sizeof(double) * N;  // caller's layout [B][N]
   const int nb = vec_blocks(N);
-  LAUNCH(c, KID_SETUP, k_check_E<<<nb, 256, 0, c->stream>>>(E_dev, N, c->partA));
-  if ((s = reduce_to(c, c->partA, nb, 1, 0))) return s;
-  if ((s = fetch_small(c, 1))) return s;
-  if (c->small_h[0] != 0.0) return fail(JFFT_E_INVALID, "E contains negative or non-finite entries");
-  LAUNCH(c, KID_SETUP, k_copy<double><<<nb, 256, 0, c->stream>>>(E_dev, c->E, N));
+  LAUNCH(c, KID_SETUP, k_check_E<<<dim3(nb, c->B), 256, 0, c->stream>>>(E_dev, es, N, c->partA, c->cs));
+  TRY(reduce_to(c, c->partA, nb, 1, 0, c->B));
+  TRY(fetch_small(c));
+  for (int i = 0; i < c->B; ++i)
+    if (c->small_h[(size_t)i * kSmall] != 0.0)
+      return fail(JFFT_E_INVALID, "E contains negative or non-finite entries (cell " + std::to_string(i) + ")");
+  LAUNCH(c, KID_SETUP, k_copy<double><<<dim3(nb, c->B), 256, 0, c->stream>>>(E_dev, es, c->E, c->cs, N));
   const long long nd = (long long)c->dim * N;
-  const bool useJ = c->pc == JFFT_PC_JACOBI || c->pc == JFFT_PC_GREEN_JACOBI;
-  if (useJ) {
-    if ((s = run_alg2(c, c->diag))) return s;
-    LAUNCH(c, KID_SETUP, k_jhalf<double><<<vec_blocks(nd), 256, 0, c->stream>>>(c->diag, c->Jh, nd, c->void_value));
+  const int nbd = vec_blocks(nd);
+  if (useJ(c)) {
+    TRY(run_alg2(c, c->diag, c->B));
+    LAUNCH(c, KID_SETUP, k_jhalf<double><<<dim3(nbd, c->B), 256, 0, c->stream>>>(c->diag, c->Jh, nd, c->void_value, c->cs));
   }
   if (c->prec == JFFT_MIXED) {
-    LAUNCH(c, KID_SETUP, (k_convert<double, float><<<nb, 256, 0, c->stream>>>(c->E, c->E32, N, 1.0)));
-    if (useJ)
-      LAUNCH(c, KID_SETUP, k_jhalf<float><<<vec_blocks(nd), 256, 0, c->stream>>>(c->diag, c->Jh32, nd, c->void_value));
+    LAUNCH(c, KID_SETUP, (k_convert<double, float><<<dim3(nb, c->B), 256, 0, c->stream>>>(c->E, c->E32, N, 1.0, nullptr, c->cs)));
+    if (useJ(c))
+      LAUNCH(c, KID_SETUP, k_jhalf<float><<<dim3(nbd, c->B), 256, 0, c->stream>>>(c->diag, c->Jh32, nd, c->void_value, c->cs));
   }
   c->has_material = true;
   return JFFT_OK;
@@ -714,133 +792,115 @@ double elapsed_ms(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
-jfft_status post_process(jfft_cell_s *c, const double *macro_h, double *u, double *sigma_dev,
-                         double *sigma_bar, double fnorm, jfft_report *rep) {
+// True residual, mean removal (Sec. 5), stresses and sigma_bar; results to
+// the caller's arrays.
+jfft_status post_process(jfft_cell_s *c, double *u_out, double *sigma_dev, double *sigma_bar) {
   const long long N = c->g.N;
   const int d = c->dim;
   const long long nd = (long long)d * N;
   const int ds = d * (d + 1) / 2;
-  jfft_status s;
-  // true residual with the FP64 stiffness
-  if ((s = apply_K<double>(c, c->E, u, c->q))) return s;
+  const int Bc = c->B;
+  TRY(apply_K<double>(c, c->E, c->u, c->q, Bc));
   const int nb = vec_blocks(nd);
-  LAUNCH(c, KID_VEC, k_sub_norm<double><<<nb, 256, 0, c->stream>>>(c->f, c->q, nullptr, nd, c->partA));
-  if ((s = reduce_to(c, c->partA, nb, 1, 0))) return s;
-  // mean removal (Sec. 5)
+  LAUNCH(c, KID_VEC, k_sub_norm<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->q, nullptr, nd, c->partA, c->cs));
+  TRY(reduce_to(c, c->partA, nb, 1, 0, Bc));
   const int nbN = vec_blocks(N);
-  LAUNCH(c, KID_VEC, k_comp_sum<double><<<dim3(nbN, d), 256, 0, c->stream>>>(u, N, c->partB));
-  if ((s = reduce_to(c, c->partB, nbN, d, 8))) return s;
-  LAUNCH(c, KID_VEC, k_sub_mean<double><<<dim3(nbN, d), 256, 0, c->stream>>>(u, N, c->small + 8));
-  // stresses and sigma_bar
-  HIP_TRY(hipMemcpyAsync(c->macro, macro_h, sizeof(double) * ds, hipMemcpyHostToDevice, c->stream));
+  LAUNCH(c, KID_VEC, k_comp_sum<double><<<dim3(nbN, d, Bc), 256, 0, c->stream>>>(c->u, N, c->partB, c->cs));
+  TRY(reduce_to(c, c->partB, nbN, d, 8, Bc));
+  LAUNCH(c, KID_VEC, k_sub_mean<double><<<dim3(nbN, d, Bc), 256, 0, c->stream>>>(c->u, N, c->small + 8, c->cs));
   const unsigned nbs = (unsigned)((N + 255) / 256);
-  LAUNCH(c, KID_STRESS, k_stress<double><<<nbs, 256, 0, c->stream>>>(u, c->E, c->macro, c->lam, c->mu, c->g.w, c->g.ihx, c->g.ihy, c->g.ihz, d, c->g.nx, c->g.ny, c->g.nz, N, sigma_dev, c->partB));
-  if ((s = reduce_to(c, c->partB, nbs, ds, 16))) return s;
-  if ((s = fetch_small(c, 32))) return s;
-  if (rep) rep->rel_res_true = fnorm > 0 ? std::sqrt(c->small_h[0]) / fnorm : 0.0;
-  for (int r = 0; r < ds; ++r) sigma_bar[r] = c->small_h[16 + r] / c->g.vol;
+  const long long sig_cs = (long long)sizeof(double) * ds * (1 << d) * N;
+  LAUNCH(c, KID_STRESS, k_stress<double><<<dim3(nbs, Bc), 256, 0, c->stream>>>(c->u, c->E, c->macro, c->lam, c->mu, c->g.w, c->g.ihx, c->g.ihy, c->g.ihz, d, c->g.nx, c->g.ny, c->g.nz, N, sigma_dev, c->partB, c->cs, sig_cs));
+  TRY(reduce_to(c, c->partB, nbs, ds, 16, Bc));
+  // u to the caller's [B][d][N] array
+  LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->u, c->cs, u_out, (long long)sizeof(double) * nd, nd));
+  TRY(fetch_small(c));
+  for (int i = 0; i < Bc; ++i)
+    for (int r = 0; r < ds; ++r) sigma_bar[(size_t)i * ds + r] = c->small_h[(size_t)i * kSmall + 16 + r] / c->g.vol;
   return JFFT_OK;
 }
 
-jfft_status solve_impl(jfft_cell_s *c, const double *macro_h, double tol, int maxit,
-                       const double *u0, double *u, double *sigma_dev, double *sigma_bar,
-                       jfft_report *rep) {
+jfft_status solve_impl(jfft_cell_s *c, const double *macros_h, double tol, int maxit,
+                       const double *u0, double *u_out, double *sigma_dev, double *sigma_bar,
+                       jfft_report *reps) {
   if (!c->has_material) return fail(JFFT_E_NO_MATERIAL, "set the material first");
-  if (!macro_h || !u || !sigma_bar) return fail(JFFT_E_INVALID, "NULL macro_strain, u_dev or sigma_bar");
+  if (!macros_h || !u_out || !sigma_bar) return fail(JFFT_E_INVALID, "NULL macro_strain, u_dev or sigma_bar");
   if (!(tol > 0.0) || maxit < 0) return fail(JFFT_E_INVALID, "tol must be > 0 and maxit >= 0");
-  jfft_report lrep{};
-  jfft_report *R = rep ? rep : &lrep;
-  *R = jfft_report{};
   const long long N = c->g.N;
   const int d = c->dim;
   const long long nd = (long long)d * N;
-  jfft_status s;
+  const int Bc = c->B;
   for (auto &e : c->phase_ev)
     if (!e) HIP_TRY(hipEventCreate(&e));
   HIP_TRY(hipEventRecord(c->phase_ev[0], c->stream));
-  // f and |f|
-  if ((s = assemble_rhs(c, macro_h, c->f, c->q))) return s;
+  // f, |f| (into q), norms and the homogeneous test, all on the device
+  TRY(assemble_rhs(c, macros_h, c->f, c->q, Bc));
   const int nb = vec_blocks(nd);
-  LAUNCH(c, KID_VEC, k_dot<double><<<nb, 256, 0, c->stream>>>(c->f, c->f, nd, c->partA));
-  LAUNCH(c, KID_VEC, k_dot<double><<<nb, 256, 0, c->stream>>>(c->q, c->q, nd, c->partB));
-  if ((s = reduce_to(c, c->partA, nb, 1, 0))) return s;
-  if ((s = reduce_to(c, c->partB, nb, 1, 1))) return s;
-  if ((s = fetch_small(c, 2))) return s;
-  const double fnorm = std::sqrt(c->small_h[0]);
-  const double fabsnorm = std::sqrt(c->small_h[1]);
-  const bool homogeneous = fnorm <= 1e-13 * fabsnorm;
-  // start vector
-  if (u0 && !homogeneous) {
-    LAUNCH(c, KID_VEC, k_copy<double><<<nb, 256, 0, c->stream>>>(u0, u, nd));
-  } else {
-    LAUNCH(c, KID_VEC, k_fill<double><<<nb, 256, 0, c->stream>>>(u, 0.0, nd));
-  }
+  LAUNCH(c, KID_VEC, k_dot<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->f, nd, c->partA, c->cs));
+  LAUNCH(c, KID_VEC, k_dot<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->q, c->q, nd, c->partB, c->cs));
+  LAUNCH(c, KID_CTRL, k_solve_norms<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, c->partB, nb, c->cs));
+  LAUNCH(c, KID_VEC, k_start_vector<<<dim3(nb, Bc), 256, 0, c->stream>>>(u0, (long long)sizeof(double) * nd, c->u, nd, c->st, c->cs));
   HIP_TRY(hipEventRecord(c->phase_ev[1], c->stream));
-  int status = JFFT_OK;
-  if (homogeneous) {
-    R->iters = 0;
-    R->outer = 0;
-    R->rel_res = 0.0;
-  } else if (c->prec == JFFT_FP64) {
+  if (c->prec == JFFT_FP64) {
     if (u0) {
-      if ((s = apply_K<double>(c, c->E, u, c->q))) return s;
-      LAUNCH(c, KID_VEC, k_sub_norm<double><<<nb, 256, 0, c->stream>>>(c->f, c->q, c->r, nd, c->partA));
+      TRY(apply_K<double>(c, c->E, c->u, c->q, Bc));
+      LAUNCH(c, KID_VEC, k_sub_norm<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->q, c->r, nd, c->partA, c->cs));
     } else {
-      LAUNCH(c, KID_VEC, k_copy<double><<<nb, 256, 0, c->stream>>>(c->f, c->r, nd));
+      LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->cs, c->r, c->cs, nd));
     }
-    PcgBufs<double> b{u, c->r, c->z, c->q, {c->p[0], c->p[1]}, c->E, c->Jh, c->spec};
-    if ((s = run_pcg<double>(c, b, tol * tol * fnorm * fnorm, maxit, true))) return s;
-    R->iters = c->st_h->iter;
-    R->outer = 1;
-    R->rel_res = fnorm > 0 ? std::sqrt(c->st_h->rr) / fnorm : 0.0;
-    status = c->st_h->status;
+    PcgBufs<double> b{c->u, c->r, c->z, c->q, {c->p[0], c->p[1]}, c->E, c->Jh, c->spec};
+    TRY(run_pcg<double>(c, b, tol, false, maxit, true));
+    LAUNCH(c, KID_CTRL, k_fp64_final<<<Bc, 1, 0, c->stream>>>(c->st, c->cs));
   } else {
-    // mixed precision: FP64 residual and iterate, FP32 inner PCG
-    int total = 0, outer = 0;
-    status = JFFT_E_NOT_CONVERGED;
-    double rel = 0.0;
-    for (;;) {
-      if ((s = apply_K<double>(c, c->E, u, c->q))) return s;
-      LAUNCH(c, KID_VEC, k_sub_norm<double><<<nb, 256, 0, c->stream>>>(c->f, c->q, c->r, nd, c->partA));
-      if ((s = reduce_to(c, c->partA, nb, 1, 0))) return s;
-      if ((s = fetch_small(c, 1))) return s;
-      const double rn = std::sqrt(c->small_h[0]);
-      rel = fnorm > 0 ? rn / fnorm : 0.0;
-      if (rn <= tol * fnorm) {
-        status = JFFT_OK;
-        break;
+    // mixed precision: FP64 residual and iterate, FP32 inner PCG on r / ||r||
+    for (int sweep = 0;; ++sweep) {
+      if (sweep > 0 || u0) {
+        TRY(apply_K<double>(c, c->E, c->u, c->q, Bc));
+        LAUNCH(c, KID_VEC, k_sub_norm<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->q, c->r, nd, c->partA, c->cs));
+      } else {
+        LAUNCH(c, KID_VEC, k_sub_norm<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->u, c->r, nd, c->partA, c->cs));
       }
-      if (outer >= c->max_outer || total >= maxit) break;
-      const double scale = 1.0 / rn;
-      LAUNCH(c, KID_VEC, (k_convert<double, float><<<nb, 256, 0, c->stream>>>(c->r, c->r32, nd, scale)));
-      LAUNCH(c, KID_VEC, k_fill<float><<<nb, 256, 0, c->stream>>>(c->c32, 0.0f, nd));
+      LAUNCH(c, KID_CTRL, k_outer_check<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nb, tol, c->max_outer, maxit, c->cs));
+      TRY(fetch_states(c));
+      bool all = true;
+      for (int i = 0; i < Bc; ++i) all = all && c->st_h[i].outer_done;
+      if (all) break;
+      LAUNCH(c, KID_VEC, (k_convert<double, float><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->r, c->r32, nd, 1.0, c->st, c->cs)));
+      LAUNCH(c, KID_VEC, k_fill<float><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->c32, 0.0f, nd, c->cs));
       PcgBufs<float> b{c->c32, c->r32, c->z32, c->q32, {c->p32[0], c->p32[1]}, c->E32, c->Jh32, c->spec32};
-      const double itol = std::max(c->inner_tol, 0.5 * tol * fnorm / rn);
-      if ((s = run_pcg<float>(c, b, itol * itol, std::max(1, maxit - total), false))) return s;
-      total += c->st_h->iter;
-      ++outer;
-      LAUNCH(c, KID_VEC, k_axpy_f32_to_f64<<<nb, 256, 0, c->stream>>>(c->c32, u, nd, rn));
-      if (c->st_h->status == JFFT_E_BREAKDOWN && c->st_h->iter == 0) {
-        status = JFFT_E_BREAKDOWN;
-        break;
-      }
+      TRY(run_pcg<float>(c, b, tol, true, maxit, false));
+      LAUNCH(c, KID_CTRL, k_outer_update<<<Bc, 1, 0, c->stream>>>(c->st, c->cs));
+      LAUNCH(c, KID_VEC, k_axpy_f32_to_f64<<<dim3(nb, Bc), 256, 0, c->stream>>>(c->c32, c->u, nd, c->st, c->cs));
     }
-    R->iters = total;
-    R->outer = outer;
-    R->rel_res = rel;
   }
   HIP_TRY(hipEventRecord(c->phase_ev[2], c->stream));
-  if ((s = post_process(c, macro_h, u, sigma_dev, sigma_bar, fnorm, R))) return s;
-  if (homogeneous) R->rel_res_true = 0.0;
+  TRY(post_process(c, u_out, sigma_dev, sigma_bar));
   HIP_TRY(hipEventRecord(c->phase_ev[3], c->stream));
-  HIP_TRY(hipEventSynchronize(c->phase_ev[3]));
-  R->setup_ms = elapsed_ms(c->phase_ev[0], c->phase_ev[1]);
-  R->loop_ms = elapsed_ms(c->phase_ev[1], c->phase_ev[2]);
-  R->post_ms = elapsed_ms(c->phase_ev[2], c->phase_ev[3]);
-  R->status = status;
-  if (status == JFFT_E_NOT_CONVERGED) g_last_error = "PCG reached maxit";
-  if (status == JFFT_E_BREAKDOWN) g_last_error = "PCG breakdown (p.q <= 0 or non-finite scalar)";
-  return (jfft_status)status;
+  TRY(fetch_states(c));
+  const double setup_ms = elapsed_ms(c->phase_ev[0], c->phase_ev[1]);
+  const double loop_ms = elapsed_ms(c->phase_ev[1], c->phase_ev[2]);
+  const double post_ms = elapsed_ms(c->phase_ev[2], c->phase_ev[3]);
+  int worst = JFFT_OK;
+  for (int i = 0; i < Bc; ++i) {
+    const CgState &s = c->st_h[i];
+    const double fn = std::sqrt(s.fnorm2);
+    jfft_report R{};
+    R.iters = s.total_iters;
+    R.outer = s.outer;
+    R.status = s.final_status;
+    R.rel_res = (c->prec == JFFT_FP64) ? (fn > 0 && !s.homog ? std::sqrt(s.rr) / fn : 0.0)
+                                       : (fn > 0 && !s.homog ? s.rn / fn : 0.0);
+    R.rel_res_true = (fn > 0 && !s.homog) ? std::sqrt(c->small_h[(size_t)i * kSmall]) / fn : 0.0;
+    R.setup_ms = setup_ms;
+    R.loop_ms = loop_ms;
+    R.post_ms = post_ms;
+    if (reps) reps[i] = R;
+    if (s.final_status != JFFT_OK && worst == JFFT_OK) worst = s.final_status;
+    if (s.final_status == JFFT_E_BREAKDOWN) worst = JFFT_E_BREAKDOWN;
+  }
+  if (worst == JFFT_E_NOT_CONVERGED) g_last_error = "PCG reached maxit";
+  if (worst == JFFT_E_BREAKDOWN) g_last_error = "PCG breakdown (p.q <= 0 or non-finite scalar)";
+  return (jfft_status)worst;
 }
 
 bool supported_length(int n) {
@@ -849,18 +909,14 @@ bool supported_length(int n) {
   return factor_plan(n, p) && factor_plan(n / 2, p);
 }
 
-}  // namespace
-
-// ============================================================== C ABI ====
-extern "C" {
-
-jfft_status jfft_create_cell(int dim, const int n[3], const double len[3], jfft_precision prec,
-                             jfft_precond pc, void *hip_stream, jfft_cell_t *out) {
+jfft_status create_impl(int dim, const int n[3], const double len[3], jfft_precision prec,
+                        jfft_precond pc, int batch, void *hip_stream, jfft_cell_t *out) {
   if (!out || !n) return fail(JFFT_E_INVALID, "NULL argument");
   *out = nullptr;
   if (dim != 2 && dim != 3) return fail(JFFT_E_INVALID, "dim must be 2 or 3");
   if (prec != JFFT_FP64 && prec != JFFT_MIXED) return fail(JFFT_E_INVALID, "unknown precision");
   if (pc < JFFT_PC_NONE || pc > JFFT_PC_GREEN_JACOBI) return fail(JFFT_E_INVALID, "unknown preconditioner");
+  if (batch < 1 || batch > 65535) return fail(JFFT_E_INVALID, "batch must lie in [1, 65535]");
   for (int a = 0; a < dim; ++a) {
     if (n[a] % 2 != 0 && n[a] >= 2) return fail(JFFT_E_ODD_GRID, "node counts must be even");
     if (!supported_length(n[a]))
@@ -872,6 +928,7 @@ jfft_status jfft_create_cell(int dim, const int n[3], const double len[3], jfft_
   c->dim = dim;
   c->prec = prec;
   c->pc = pc;
+  c->B = batch;
   c->stream = static_cast<hipStream_t>(hip_stream);
   for (int a = 0; a < 3; ++a) {
     c->n[a] = a < dim ? n[a] : 1;
@@ -902,24 +959,49 @@ jfft_status jfft_create_cell(int dim, const int n[3], const double len[3], jfft_
   factor_plan(g.nx / 2, c->plan_x);
   factor_plan(g.ny, c->plan_y);
   factor_plan(g.nz, c->plan_z);
-  // z planes per stiffness block: enough blocks to fill 256 CUs several times
+  // z planes per stiffness block: enough blocks per cell to fill 256 CUs
+  // several times (from the shape alone, see vec_blocks)
   if (dim == 3) {
     const long long tiles = (long long)((g.nx + TILE - 1) / TILE) * ((g.ny + TILE - 1) / TILE);
     int tz = 32;
     while (tz > 4 && tiles * ((g.nz + tz - 1) / tz) < 2048) tz /= 2;
-    c->tz = std::min(tz, g.nz);
-  } else {
-    c->tz = 1;
+    c->tun.tz = std::min(tz, g.nz);
+    if ((long long)((g.nz + c->tun.tz - 1) / c->tun.tz) * batch > 65535) {
+      delete c;
+      return fail(JFFT_E_INVALID, "batch too large for this grid (stiffness grid z-dimension above 65535)");
+    }
   }
   c->npart = max_partials(c);
+  set_smem_attributes();
   hipError_t e = hipGetDevice(&c->device);
-  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&c->st_h), sizeof(CgState), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&c->small_h), sizeof(double) * 64, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&c->st_h), sizeof(CgState) * batch, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&c->small_h), sizeof(double) * kSmall * batch, hipHostMallocDefault);
   if (e != hipSuccess) {
     delete c;
     return fail(JFFT_E_HIP, std::string("create: ") + hipGetErrorString(e));
   }
   *out = c;
+  return JFFT_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI ====
+extern "C" {
+
+jfft_status jfft_create_cell(int dim, const int n[3], const double len[3], jfft_precision prec,
+                             jfft_precond pc, void *hip_stream, jfft_cell_t *out) {
+  return create_impl(dim, n, len, prec, pc, 1, hip_stream, out);
+}
+
+jfft_status jfft_create_batch(int dim, const int n[3], const double len[3], jfft_precision prec,
+                              jfft_precond pc, int batch, void *hip_stream, jfft_cell_t *out) {
+  return create_impl(dim, n, len, prec, pc, batch, hip_stream, out);
+}
+
+jfft_status jfft_batch_size(jfft_cell_t c, int *batch) {
+  if (!c || !batch) return fail(JFFT_E_INVALID, "NULL argument");
+  *batch = c->B;
   return JFFT_OK;
 }
 
@@ -963,30 +1045,42 @@ jfft_status jfft_solve(jfft_cell_t c, const double *macro_strain, double tol, in
                        const double *u0_dev, double *u_dev, double *sigma_dev, double *sigma_bar,
                        jfft_report *report) {
   if (!c) return fail(JFFT_E_INVALID, "NULL cell");
+  if (c->B != 1) return fail(JFFT_E_INVALID, "batched handle: use jfft_solve_batch");
   return solve_impl(c, macro_strain, tol, maxit, u0_dev, u_dev, sigma_dev, sigma_bar, report);
+}
+
+jfft_status jfft_solve_batch(jfft_cell_t c, const double *macro_strains, double tol, int maxit,
+                             const double *u0_dev, double *u_dev, double *sigma_dev,
+                             double *sigma_bars, jfft_report *reports) {
+  if (!c) return fail(JFFT_E_INVALID, "NULL cell");
+  return solve_impl(c, macro_strains, tol, maxit, u0_dev, u_dev, sigma_dev, sigma_bars, reports);
 }
 
 jfft_status jfft_apply_stiffness(jfft_cell_t c, const double *in_dev, double *out_dev) {
   if (!c || !in_dev || !out_dev) return fail(JFFT_E_INVALID, "NULL argument");
   if (!c->has_material) return fail(JFFT_E_NO_MATERIAL, "set the material first");
-  return apply_K<double>(c, c->E, in_dev, out_dev);
+  if (c->B != 1) return fail(JFFT_E_INVALID, "operator entry points take a single-cell handle");
+  return apply_K<double>(c, c->E, in_dev, out_dev, 1);
 }
 
 jfft_status jfft_apply_precond(jfft_cell_t c, const double *in_dev, double *out_dev) {
   if (!c || !in_dev || !out_dev) return fail(JFFT_E_INVALID, "NULL argument");
   if (!c->has_material) return fail(JFFT_E_NO_MATERIAL, "set the material first");
+  if (c->B != 1) return fail(JFFT_E_INVALID, "operator entry points take a single-cell handle");
   const long long nd = (long long)c->dim * c->g.N;
-  LAUNCH(c, KID_VEC, k_copy<double><<<vec_blocks(nd), 256, 0, c->stream>>>(in_dev, c->r, nd));
+  LAUNCH(c, KID_VEC, k_copy<double><<<dim3(vec_blocks(nd), 1), 256, 0, c->stream>>>(in_dev, 0, c->r, 0, nd));
   long long nA, nB;
   History h{nullptr, nullptr, nullptr};
-  return precond<double>(c, c->r, nullptr, c->Jh, out_dev, c->spec, false, false, &nA, &nB, h);
+  TRY(precond<double>(c, c->r, nullptr, c->Jh, c->z, c->spec, false, false, &nA, &nB, h));
+  LAUNCH(c, KID_VEC, k_copy<double><<<dim3(vec_blocks(nd), 1), 256, 0, c->stream>>>(c->z, 0, out_dev, 0, nd));
+  return JFFT_OK;
 }
 
 jfft_status jfft_assemble_rhs(jfft_cell_t c, const double *macro_strain, double *f_dev) {
   if (!c || !macro_strain || !f_dev) return fail(JFFT_E_INVALID, "NULL argument");
   if (!c->has_material) return fail(JFFT_E_NO_MATERIAL, "set the material first");
-  jfft_status s = assemble_rhs(c, macro_strain, f_dev, nullptr);
-  if (s) return s;
+  if (c->B != 1) return fail(JFFT_E_INVALID, "operator entry points take a single-cell handle");
+  TRY(assemble_rhs(c, macro_strain, f_dev, nullptr, 1));
   HIP_TRY(hipStreamSynchronize(c->stream));  // macro_strain is a host pointer
   return JFFT_OK;
 }
@@ -994,25 +1088,48 @@ jfft_status jfft_assemble_rhs(jfft_cell_t c, const double *macro_strain, double 
 jfft_status jfft_jacobi_diag(jfft_cell_t c, double *diag_dev) {
   if (!c || !diag_dev) return fail(JFFT_E_INVALID, "NULL argument");
   if (!c->has_material) return fail(JFFT_E_NO_MATERIAL, "set the material first");
-  return run_alg2(c, diag_dev);
+  if (c->B != 1) return fail(JFFT_E_INVALID, "operator entry points take a single-cell handle");
+  return run_alg2(c, diag_dev, 1);
 }
 
 jfft_status jfft_enable_history(jfft_cell_t c, int cap) {
   if (!c || cap < 0 || cap > kHistMax) return fail(JFFT_E_INVALID, "history capacity must lie in [0, 4096]");
   c->hist_cap = cap;
+  c->drop_graphs();
+  return JFFT_OK;
+}
+
+jfft_status jfft_get_batch_history(jfft_cell_t c, int index, double *alpha, double *beta,
+                                   double *res, int cap, int *count) {
+  if (!c) return fail(JFFT_E_INVALID, "NULL cell");
+  if (index < 0 || index >= c->B) return fail(JFFT_E_INVALID, "cell index out of range");
+  if (count) *count = 0;
+  if (!c->ready) return JFFT_OK;  // nothing solved yet
+  TRY(fetch_states(c));
+  // the device-side capacity is 0 when the last loop did not record (mixed inner solves)
+  const int k = std::min(std::min(cap, c->st_h[index].hist_cap), c->st_h[index].iter);
+  if (count) *count = k;
+  if (k <= 0) return JFFT_OK;
+  double *const dst[3] = {alpha, beta, res};
+  for (int t = 0; t < 3; ++t)
+    if (dst[t])
+      HIP_TRY(hipMemcpy(dst[t], reinterpret_cast<unsigned char *>(c->hist[t]) + (size_t)index * c->cs,
+                        sizeof(double) * k, hipMemcpyDeviceToHost));
   return JFFT_OK;
 }
 
 jfft_status jfft_get_history(jfft_cell_t c, double *alpha, double *beta, double *res, int cap,
                              int *count) {
-  if (!c) return fail(JFFT_E_INVALID, "NULL cell");
-  const int k = std::min(std::min(cap, c->hist_cap), c->st_h ? c->st_h->iter : 0);
-  if (count) *count = k;
-  if (k <= 0) return JFFT_OK;
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  if (alpha) HIP_TRY(hipMemcpy(alpha, c->hist[0], sizeof(double) * k, hipMemcpyDeviceToHost));
-  if (beta) HIP_TRY(hipMemcpy(beta, c->hist[1], sizeof(double) * k, hipMemcpyDeviceToHost));
-  if (res) HIP_TRY(hipMemcpy(res, c->hist[2], sizeof(double) * k, hipMemcpyDeviceToHost));
+  return jfft_get_batch_history(c, 0, alpha, beta, res, cap, count);
+}
+
+jfft_status jfft_set_graph_iterations(jfft_cell_t c, int iterations) {
+  if (!c || iterations < 0 || iterations > 64 || (iterations % 2))
+    return fail(JFFT_E_INVALID, "graph iterations must be an even number in [0, 64]");
+  if (iterations > 0 && c->stream == nullptr)
+    return fail(JFFT_E_INVALID, "graph replay needs a stream other than the legacy default stream");
+  c->tun.graph_iters = iterations;
+  c->drop_graphs();
   return JFFT_OK;
 }
 
@@ -1067,6 +1184,6 @@ void jfft_destroy_cell(jfft_cell_t c) {
 
 const char *jfft_last_error(void) { return g_last_error.c_str(); }
 
-const char *jfft_version(void) { return "jfft-mi355x 0.1 (gfx950)"; }
+const char *jfft_version(void) { return "jfft-mi355x 0.2 (gfx950)"; }
 
 }  // extern "C"

@@ -21,6 +21,16 @@ struct CxT<float> {
   using R2 = float2;
 };
 
+// Batches: a group of B cells of identical shape shares one workspace laid
+// out as B equal slices of `cs` bytes.  Kernels take the pointers of cell 0
+// and shift them to their cell (found from a grid dimension); read-only
+// tables shared by all cells are not shifted.
+template <typename T>
+__device__ __forceinline__ T *cshift(T *p, int cell, long long cs) {
+  return p ? reinterpret_cast<T *>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)((long long)cell * cs))
+           : p;
+}
+
 // CG scalars kept on the device so that the whole loop runs without host
 // round trips; written only by the single-block control kernels.
 struct CgState {
@@ -38,7 +48,17 @@ struct CgState {
   int first;        // 1 until the first search direction exists
   int pending;      // 1 while alpha * p is owed to u
   int hist_cap;     // history capacity (0 = off)
-  int pad;
+  int parity;       // parity of the loop iteration that wrote the latest p
+  // solve-level state (one per cell of a batch)
+  double fnorm2;    // ||f||^2
+  double fabs2;     // ||f_abs||^2 (scale of the homogeneous-material test)
+  double rn;        // ||r||, FP64 refinement residual of the current sweep
+  int homog;        // 1 if f vanishes to rounding: u = 0 after zero iterations
+  int outer_done;   // refinement finished (mixed precision)
+  int outer;        // refinement sweeps taken
+  int total_iters;  // inner iterations over all sweeps
+  int final_status; // jfft_status of the whole solve
+  int pad2[3];
 };
 
 // Fourier tables of one axis for the Green symbol of K_ref (Q1 elements,

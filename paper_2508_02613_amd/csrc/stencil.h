@@ -55,6 +55,8 @@ struct StencilArgs {
   Real *diag;            // COMB: diag(K) output
   int comb_comp, comb_off;  // COMB: component and sub-grid offset bits (x, y, z)
   int tz;                // z planes per block (3D)
+  int nbz;               // z blocks per cell (3D); gridDim.z = nbz * cells
+  long long cs;          // bytes between the cells of a batch
   Real lam, mu;          // Lame constants of C^ times the Gauss weight
   Real ihx, ihy, ihz;
   int nx, ny, nz;
@@ -75,6 +77,19 @@ __device__ __forceinline__ int xcd_logical_block(int b, int total) {
   const int q = total / kNumXcd, r = total % kNumXcd;
   const int k = b % kNumXcd, j = b / kNumXcd;
   return k * q + min(k, r) + j;
+}
+
+template <typename Real>
+__device__ __forceinline__ void shift_args(StencilArgs<Real> &a, int cell) {
+  a.in = cshift(a.in, cell, a.cs);
+  a.zin = cshift(a.zin, cell, a.cs);
+  a.pout = cshift(a.pout, cell, a.cs);
+  a.u = cshift(a.u, cell, a.cs);
+  a.E = cshift(a.E, cell, a.cs);
+  a.out = cshift(a.out, cell, a.cs);
+  a.partial = cshift(a.partial, cell, a.cs);
+  a.st = cshift(a.st, cell, a.cs);
+  a.diag = cshift(a.diag, cell, a.cs);
 }
 
 // ----------------------------------------------------------------- 3D ----
@@ -410,15 +425,19 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
 template <typename Real, int MODE>
 __global__ void __launch_bounds__(STENCIL3_THREADS)
     k_stiffness3d(StencilArgs<Real> a) {
-  if (MODE == SM_CG && a.st->done) return;
   __shared__ Real P[3][3][NNODE];  // ring of three node planes of the input vector
   __shared__ Real Y[24][NELEM];    // corner contributions of one element layer
   __shared__ double red[8];
 
   const int tid = threadIdx.x;
   const int nbx = gridDim.x, nby = gridDim.y;
-  const int lb = xcd_logical_block(blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z),
-                                   nbx * nby * gridDim.z);
+  const int per_cell = nbx * nby * a.nbz;
+  const int lbg = xcd_logical_block(blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z),
+                                    nbx * nby * gridDim.z);
+  const int cell = lbg / per_cell;
+  const int lb = lbg - cell * per_cell;
+  shift_args(a, cell);
+  if (MODE == SM_CG && a.st->done) return;
   const int bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
   const int x0 = bx * TILE, y0 = by * TILE;
   const int z0 = bz * a.tz;
@@ -676,12 +695,17 @@ __device__ __forceinline__ void elem_quad(const Real (&u)[2][4], Real Elam, Real
 template <typename Real, int MODE>
 __global__ void __launch_bounds__(STENCIL_THREADS)
     k_stiffness2d(StencilArgs<Real> a) {
-  if (MODE == SM_CG && a.st->done) return;
   __shared__ Real P[2][NNODE];
   __shared__ Real Y[8][NELEM];
   __shared__ double red[8];
   const int tid = threadIdx.x;
-  const int lb = xcd_logical_block(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int per_cell = gridDim.x * gridDim.y;
+  const int lbg = xcd_logical_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                    per_cell * gridDim.z);
+  const int cell = lbg / per_cell;
+  const int lb = lbg - cell * per_cell;
+  shift_args(a, cell);
+  if (MODE == SM_CG && a.st->done) return;
   const int x0 = (lb % gridDim.x) * TILE, y0 = (lb / gridDim.x) * TILE;
   const int nx = a.nx, ny = a.ny;
   const long long N = a.N;
@@ -775,7 +799,12 @@ __global__ void __launch_bounds__(STENCIL_THREADS)
 // fabs (optional) accumulates |E_e F| for the homogeneous-material test.
 template <typename Real>
 __global__ void k_rhs(const Real *E, const double *F /* [d][2^d] */, Real *f, Real *fabs_out,
-                      int dim, int nx, int ny, int nz, long long N) {
+                      int dim, int nx, int ny, int nz, long long N, long long cs) {
+  const int cell = blockIdx.y;
+  E = cshift(E, cell, cs);
+  F = cshift(F, cell, cs);
+  f = cshift(f, cell, cs);
+  fabs_out = cshift(fabs_out, cell, cs);
   const long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (node >= N) return;
   const int ix = (int)(node % nx);
@@ -803,8 +832,10 @@ __global__ void k_rhs(const Real *E, const double *F /* [d][2^d] */, Real *f, Re
 // F[i][c] = w sum_q sum_j sigma0_ij dphi_c/dx_j, sigma0 = C^ macro.  One
 // thread; evaluated with the same transposed factorisation as the stiffness.
 __global__ void k_unit_force(double *F, const double *macro, int dim, double lam, double mu,
-                             double ihx, double ihy, double ihz) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+                             double ihx, double ihy, double ihz, long long cs) {
+  if (threadIdx.x != 0) return;
+  F = cshift(F, blockIdx.x, cs);  // one block per cell
+  macro = cshift(macro, blockIdx.x, cs);
   const double r2 = 0.70710678118654752440;  // Mandel shear -> tensor
   if (dim == 3) {
     const double e11 = macro[0], e22 = macro[1], e33 = macro[2];
@@ -863,8 +894,15 @@ __global__ void k_unit_force(double *F, const double *macro, int dim, double lam
 template <typename Real>
 __global__ void k_stress(const Real *u, const Real *E, const double *macro, double lam, double mu,
                          double w, double ihx, double ihy, double ihz, int dim, int nx, int ny,
-                         int nz, long long N, double *sig, double *partial /* [ds][nblocks] */) {
+                         int nz, long long N, double *sig, double *partial /* [ds][nblocks] */,
+                         long long cs, long long sig_cs) {
   __shared__ double red[8];
+  const int cell = blockIdx.y;
+  u = cshift(u, cell, cs);
+  E = cshift(E, cell, cs);
+  macro = cshift(macro, cell, cs);
+  partial = cshift(partial, cell, cs);
+  sig = cshift(sig, cell, sig_cs);
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int ds = dim == 3 ? 6 : 3;
   double loc[6] = {0, 0, 0, 0, 0, 0};

@@ -552,7 +552,7 @@ def test_stiffness_at_node_matches_full():
         assert np.abs(oracle.stiffness_at_node(E, u, LAM, MU, node) - full[:, node]).max() <= 1e-13 * np.abs(full).max()
 
 
-def test_trend_green_vs_green_jacobi_config1():
+def test_trend_green_vs_green_jacobi_sine_contrast_32x32():
     """Smooth contrast-1e4 field on 32^2 (Sec. 1 / Sec. 6 trend): Green-Jacobi
     needs fewer iterations than Green.  Reported, and checked as a trend."""
     E = ji.sine_contrast_field(32)
