@@ -19,6 +19,8 @@ HEADERS = ["jfft_common.h", "stencil.h", "fft.h", "cg.h"]
 def hipcc_cmd(out: str, extra=()):
     return ["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
             "-shared", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wall", "-Werror=uninitialized", "-Werror=sometimes-uninitialized",
+            "-Werror=return-type",
             "-I", os.path.join(ROOT, "include"), *extra,
             *[os.path.join(CSRC, s) for s in SOURCES], "-o", out]
 

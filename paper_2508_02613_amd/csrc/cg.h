@@ -169,6 +169,7 @@ __global__ void k_cg_start(CgState *st, const double *partRR, long long nRR, con
   if (threadIdx.x == 0) {
     if (st->done) return;  // finished before this solve
     st->rr = rr;
+    st->rr0 = rr;
     st->rz = rz;
     if (rr <= st->tol2) {
       st->done = 1;

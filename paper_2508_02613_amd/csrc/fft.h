@@ -178,12 +178,13 @@ struct Dft<Real, 5, INV> {
 // L / R, current sub-transform length p (product of earlier radices).
 // tw[j * tws] = exp(-2 pi i j / L).  All threads read their butterflies,
 // synchronise, then write, so one buffer suffices.
-template <typename Real, int R, bool INV>
+// NPT bounds the points per thread (L * W <= NPT * FFT_THREADS).
+template <typename Real, int R, bool INV, int NPT>
 __device__ __forceinline__ void stockham_stage(typename CxT<Real>::T *buf, int L, int W, int p,
                                                int sp, int sc, const typename CxT<Real>::T *tw,
                                                int tws, bool i_fastest) {
   using C = typename CxT<Real>::T;
-  constexpr int MB = (MaxPt<Real>::value + R - 1) / R;
+  constexpr int MB = (NPT + R - 1) / R;
   const int m = L / R;
   const int nb = m * W;
   const int step = L / (p * R);
@@ -221,18 +222,18 @@ __device__ __forceinline__ void stockham_stage(typename CxT<Real>::T *buf, int L
   __syncthreads();
 }
 
-template <typename Real, bool INV>
+template <typename Real, bool INV, int NPT = MaxPt<Real>::value>
 __device__ void lds_fft(typename CxT<Real>::T *buf, const FftPlan &pl, int W, int sp, int sc,
                         const typename CxT<Real>::T *tw, int tws, bool i_fastest) {
   int p = 1;
   for (int s = 0; s < pl.nst; ++s) {
     const int R = pl.radix[s];
     switch (R) {
-      case 8: stockham_stage<Real, 8, INV>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
-      case 4: stockham_stage<Real, 4, INV>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
-      case 2: stockham_stage<Real, 2, INV>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
-      case 3: stockham_stage<Real, 3, INV>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
-      case 5: stockham_stage<Real, 5, INV>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
+      case 8: stockham_stage<Real, 8, INV, NPT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
+      case 4: stockham_stage<Real, 4, INV, NPT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
+      case 2: stockham_stage<Real, 2, INV, NPT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
+      case 3: stockham_stage<Real, 3, INV, NPT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
+      case 5: stockham_stage<Real, 5, INV, NPT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
       default: break;
     }
     p *= R;
@@ -268,25 +269,23 @@ struct XArgs {
   long long cs;        // bytes between the cells of a batch (cell = blockIdx.y)
 };
 
-template <typename Real>
-__device__ __forceinline__ void shift_x(XArgs<Real> &a) {
-  const int cell = blockIdx.y;
-  a.r = cshift(a.r, cell, a.cs);
-  a.q = cshift(a.q, cell, a.cs);
-  a.Jh = cshift(a.Jh, cell, a.cs);
-  a.out = cshift(a.out, cell, a.cs);
-  a.spec = cshift(a.spec, cell, a.cs);
-  a.partA = cshift(a.partA, cell, a.cs);
-  a.st = cshift(a.st, cell, a.cs);
-}
-
 // Forward: r <- r - alpha q (UPDATE), s = J^1/2 r (USE_J), X = rfft(s) per row.
 template <typename Real, bool UPDATE, bool USE_J>
 __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
   using C = typename CxT<Real>::T;
   using R2 = typename CxT<Real>::R2;
-  shift_x(a);
-  if (a.check_done && a.st->done) return;
+  // cell pointers as locals (see cshift)
+  const int cell = blockIdx.y;
+  Real *const r = cshift(a.r, cell, a.cs);
+  const Real *const q = cshift(a.q, cell, a.cs);
+  const Real *const Jh = cshift(a.Jh, cell, a.cs);
+  Real *const out = cshift(a.out, cell, a.cs);
+  C *const spec = cshift(a.spec, cell, a.cs);
+  double *const partA = cshift(a.partA, cell, a.cs);
+  const CgState *const st = cshift(a.st, cell, a.cs);
+  (void)q;
+  (void)out;
+  if (a.check_done && st->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *buf = tw + a.nx;
@@ -297,7 +296,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
   const long long row0 = (long long)blockIdx.x * RB;
   load_twiddles<Real>(tw, a.tw, a.nx);
   Real alpha = 0;
-  if (UPDATE) alpha = (Real)a.st->alpha;
+  if (UPDATE) alpha = (Real)st->alpha;
   double rr = 0.0;
   for (int f = threadIdx.x; f < RB * m; f += FFT_THREADS) {
     const int row = f / m, j = f % m;
@@ -307,16 +306,16 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
     z.y = 0;
     if (g < a.nrows) {
       const long long off = g * (long long)m + j;  // in pairs (R2 units)
-      R2 rv = reinterpret_cast<const R2 *>(a.r)[off];
+      R2 rv = reinterpret_cast<const R2 *>(r)[off];
       if (UPDATE) {
-        const R2 qv = reinterpret_cast<const R2 *>(a.q)[off];
+        const R2 qv = reinterpret_cast<const R2 *>(q)[off];
         rv.x -= alpha * qv.x;
         rv.y -= alpha * qv.y;
-        reinterpret_cast<R2 *>(a.r)[off] = rv;
+        reinterpret_cast<R2 *>(r)[off] = rv;
       }
       rr += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
       if (USE_J) {
-        const R2 jv = reinterpret_cast<const R2 *>(a.Jh)[off];
+        const R2 jv = reinterpret_cast<const R2 *>(Jh)[off];
         rv.x *= jv.x;
         rv.y *= jv.y;
       }
@@ -335,7 +334,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
     if (g >= a.nrows) continue;
     const C zk = buf[row * sc + (k % m)];
     const C zm = buf[row * sc + ((m - k) % m)];
-    C *dst = a.spec + g * (long long)a.mxp;
+    C *dst = spec + g * (long long)a.mxp;
     // X[k]
     {
       C s, d;
@@ -370,7 +369,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
     }
   }
   const double s = block_sum<FFT_THREADS>(rr, red);
-  if (threadIdx.x == 0 && a.partA) a.partA[blockIdx.x] = s;
+  if (threadIdx.x == 0 && partA) partA[blockIdx.x] = s;
 }
 
 // Inverse: t = irfft(X) (unnormalised), z = J^1/2 t (USE_J); partials of r.z.
@@ -378,8 +377,18 @@ template <typename Real, bool USE_J>
 __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
   using C = typename CxT<Real>::T;
   using R2 = typename CxT<Real>::R2;
-  shift_x(a);
-  if (a.check_done && a.st->done) return;
+  // cell pointers as locals (see cshift)
+  const int cell = blockIdx.y;
+  Real *const r = cshift(a.r, cell, a.cs);
+  const Real *const q = cshift(a.q, cell, a.cs);
+  const Real *const Jh = cshift(a.Jh, cell, a.cs);
+  Real *const out = cshift(a.out, cell, a.cs);
+  C *const spec = cshift(a.spec, cell, a.cs);
+  double *const partA = cshift(a.partA, cell, a.cs);
+  const CgState *const st = cshift(a.st, cell, a.cs);
+  (void)q;
+  (void)out;
+  if (a.check_done && st->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *buf = tw + a.nx;
@@ -395,7 +404,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
     C v;
     v.x = 0;
     v.y = 0;
-    if (g < a.nrows) v = a.spec[g * (long long)a.mxp + k];
+    if (g < a.nrows) v = spec[g * (long long)a.mxp + k];
     buf[row * sc + k] = v;
   }
   __syncthreads();
@@ -443,18 +452,18 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
     t.x = z.x;
     t.y = z.y;
     if (USE_J) {
-      const R2 jv = reinterpret_cast<const R2 *>(a.Jh)[off];
+      const R2 jv = reinterpret_cast<const R2 *>(Jh)[off];
       t.x *= jv.x;
       t.y *= jv.y;
     }
-    reinterpret_cast<R2 *>(a.out)[off] = t;
-    if (a.partA) {
-      const R2 rv = reinterpret_cast<const R2 *>(a.r)[off];
+    reinterpret_cast<R2 *>(out)[off] = t;
+    if (partA) {
+      const R2 rv = reinterpret_cast<const R2 *>(r)[off];
       rz += (double)rv.x * (double)t.x + (double)rv.y * (double)t.y;
     }
   }
   const double s = block_sum<FFT_THREADS>(rz, red);
-  if (threadIdx.x == 0 && a.partA) a.partA[blockIdx.x] = s;
+  if (threadIdx.x == 0 && partA) partA[blockIdx.x] = s;
 }
 
 // ------------------------------------------------- strided C2C passes ----
@@ -479,9 +488,8 @@ template <typename Real, bool INV>
 __global__ void __launch_bounds__(FFT_THREADS) k_ypass(YArgs<Real> a) {
   using C = typename CxT<Real>::T;
   constexpr int PPT = MaxPt<Real>::value;
-  a.spec = cshift(a.spec, blockIdx.z, a.cs);
-  a.st = cshift(a.st, blockIdx.z, a.cs);
-  if (a.check_done && a.st->done) return;
+  C *const spec = cshift(a.spec, blockIdx.z, a.cs);  // a local (see cshift)
+  if (a.check_done && cshift(a.st, blockIdx.z, a.cs)->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   const int L = a.ny;
@@ -495,7 +503,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_ypass(YArgs<Real> a) {
   auto tile_base = [&](long long t, int &kx0) {
     kx0 = (int)(t % ntx) * W;
     const long long plane = t / ntx + (long long)blockIdx.y * a.nz;  // comp * nz + z
-    return a.spec + plane * (long long)a.ny * a.mxp;
+    return spec + plane * (long long)a.ny * a.mxp;
   };
   auto load = [&](long long t) {
     int kx0;
@@ -612,83 +620,117 @@ __device__ __forceinline__ void green2(const double (&A)[2], const double (&B)[2
   v[1].y = g01 * y0 + g11 * y1;
 }
 
+// Points per thread and per component of the last-axis pass: tiles of L x W
+// with L * W <= GPT * FFT_THREADS (FP64 tiles are half as wide, so that the d
+// components of a tile fit the LDS of three blocks per CU).
+template <typename Real>
+struct GreenPt {
+  static constexpr int value = sizeof(Real) == 8 ? 4 : 8;
+};
+
 // Last axis: forward C2C, Green multiply, inverse C2C for every component of
-// a tile of W x bins (3D: at one ky; 2D: the whole y axis).
+// a tile of W x bins (3D: at one ky; 2D: the whole y axis).  The d components
+// of the tile sit in LDS side by side (point row t holds d * W values, component
+// major), so one Stockham transform covers all d * W lines.  Blocks are
+// persistent over the tiles of their cell, taken in an XCD-aware order so
+// that neighbouring tiles (which share cache lines) run under one L2; the
+// loads of the next tile are in flight in registers while the current one is
+// transformed.
 template <typename Real, int DIM>
 __global__ void __launch_bounds__(FFT_THREADS) k_green_axis(GArgs<Real> a) {
   using C = typename CxT<Real>::T;
-  a.spec = cshift(a.spec, blockIdx.z, a.cs);
-  a.st = cshift(a.st, blockIdx.z, a.cs);
-  if (a.check_done && a.st->done) return;
+  constexpr int PPT = GreenPt<Real>::value;
+  C *const spec = cshift(a.spec, blockIdx.z, a.cs);  // a local (see cshift)
+  if (a.check_done && cshift(a.st, blockIdx.z, a.cs)->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   const int L = DIM == 3 ? a.nz : a.ny;
-  C *buf = tw + L;
+  C *buf = tw + L;  // [L][DIM][W]
   load_twiddles<Real>(tw, a.tw, L);
   const int W = a.W;
-  const int kx0 = blockIdx.x * W;
-  const int ky = DIM == 3 ? blockIdx.y : 0;
-  // line (kx, ky) along the last axis: component c, position t
+  const int DW = DIM * W;
+  const int ntx = (a.mx + W - 1) / W;
+  const long long ntiles = (long long)ntx * (DIM == 3 ? a.ny : 1);
   const long long comp_stride = (long long)a.nz * a.ny * a.mxp;
   const long long axis_stride = DIM == 3 ? (long long)a.ny * a.mxp : (long long)a.mxp;
-  C *base = a.spec + (DIM == 3 ? (long long)ky * a.mxp : 0) + kx0;
-  constexpr int PPT = MaxPt<Real>::value;  // points per thread kept across components
-  C stash[DIM][PPT];
-  const int npts = L * W;
-  for (int c = 0; c < DIM; ++c) {
-    for (int f = threadIdx.x; f < npts; f += FFT_THREADS) {
-      const int col = f % W, t = f / W;
-      C v;
-      v.x = 0;
-      v.y = 0;
-      if (kx0 + col < a.mx) v = base[c * comp_stride + (long long)t * axis_stride + col];
-      buf[f] = v;
-    }
+  const int npts = L * W;  // per component
+  auto tile_base = [&](long long t, int &kx0, int &ky) {
+    kx0 = (int)(t % ntx) * W;
+    ky = (int)(t / ntx);
+    return spec + (DIM == 3 ? (long long)ky * a.mxp : 0) + kx0;
+  };
+  C pre[DIM][PPT];
+  auto load = [&](long long t) {
+    int kx0, ky;
+    const C *base = tile_base(t, kx0, ky);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const int f = threadIdx.x + j * FFT_THREADS;
+        const int col = f % W, z = f / W;
+        C v;
+        v.x = 0;
+        v.y = 0;
+        if (f < npts && kx0 + col < a.mx) v = base[c * comp_stride + (long long)z * axis_stride + col];
+        pre[c][j] = v;
+      }
+  };
+  const long long G = gridDim.x;
+  long long t = xcd_logical_block(blockIdx.x, (int)G);
+  if (t < ntiles) load(t);
+  for (; t < ntiles; t += G) {
+    int kx0, ky;
+    C *base = tile_base(t, kx0, ky);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const int f = threadIdx.x + j * FFT_THREADS;
+        if (f < npts) buf[(f / W) * DW + c * W + f % W] = pre[c][j];
+      }
     __syncthreads();
-    lds_fft<Real, false>(buf, a.plan, W, W, 1, tw, 1, false);
+    if (t + G < ntiles) load(t + G);
+    lds_fft<Real, false, DIM * PPT>(buf, a.plan, DW, DW, 1, tw, 1, false);
+    // Green multiply, frequency by frequency
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const int f = threadIdx.x + j * FFT_THREADS;
-      if (f < npts) stash[c][j] = buf[f];
-    }
-    __syncthreads();
-  }
-  // Green multiply on the points this thread holds
-#pragma unroll
-  for (int j = 0; j < PPT; ++j) {
-    const int f = threadIdx.x + j * FFT_THREADS;
-    if (f < npts) {
-      const int col = f % W, t = f / W;
-      const int kx = min(kx0 + col, a.mx - 1);
-      if (DIM == 3) {
-        const double A[3] = {a.tx.a[kx], a.ty.a[ky], a.tz.a[t]};
-        const double B[3] = {a.tx.b[kx], a.ty.b[ky], a.tz.b[t]};
-        const double S[3] = {a.tx.s[kx], a.ty.s[ky], a.tz.s[t]};
-        C v[3] = {stash[0][j], stash[1][j], stash[2][j]};
-        green3(A, B, S, a.lam, a.mu, a.invN, kx == 0 && ky == 0 && t == 0, v);
-        for (int c = 0; c < 3; ++c) stash[c][j] = v[c];
-      } else {
-        const double A[2] = {a.tx.a[kx], a.ty.a[t]};
-        const double B[2] = {a.tx.b[kx], a.ty.b[t]};
-        const double S[2] = {a.tx.s[kx], a.ty.s[t]};
-        C v[2] = {stash[0][j], stash[1][j]};
-        green2(A, B, S, a.lam, a.mu, a.invN, kx == 0 && t == 0, v);
-        for (int c = 0; c < 2; ++c) stash[c][j] = v[c];
+      if (f < npts) {
+        const int col = f % W, z = f / W;
+        const int kx = min(kx0 + col, a.mx - 1);
+        C *row = buf + z * DW + col;
+        if (DIM == 3) {
+          const double A[3] = {a.tx.a[kx], a.ty.a[ky], a.tz.a[z]};
+          const double B[3] = {a.tx.b[kx], a.ty.b[ky], a.tz.b[z]};
+          const double S[3] = {a.tx.s[kx], a.ty.s[ky], a.tz.s[z]};
+          C v[3] = {row[0], row[W], row[2 * W]};
+          green3(A, B, S, a.lam, a.mu, a.invN, kx == 0 && ky == 0 && z == 0, v);
+          row[0] = v[0];
+          row[W] = v[1];
+          row[2 * W] = v[2];
+        } else {
+          const double A[2] = {a.tx.a[kx], a.ty.a[z]};
+          const double B[2] = {a.tx.b[kx], a.ty.b[z]};
+          const double S[2] = {a.tx.s[kx], a.ty.s[z]};
+          C v[2] = {row[0], row[W]};
+          green2(A, B, S, a.lam, a.mu, a.invN, kx == 0 && z == 0, v);
+          row[0] = v[0];
+          row[W] = v[1];
+        }
       }
     }
-  }
-  for (int c = 0; c < DIM; ++c) {
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-      const int f = threadIdx.x + j * FFT_THREADS;
-      if (f < npts) buf[f] = stash[c][j];
-    }
     __syncthreads();
-    lds_fft<Real, true>(buf, a.plan, W, W, 1, tw, 1, false);
-    for (int f = threadIdx.x; f < npts; f += FFT_THREADS) {
-      const int col = f % W, t = f / W;
-      if (kx0 + col < a.mx) base[c * comp_stride + (long long)t * axis_stride + col] = buf[f];
-    }
+    lds_fft<Real, true, DIM * PPT>(buf, a.plan, DW, DW, 1, tw, 1, false);
+#pragma unroll
+    for (int c = 0; c < DIM; ++c)
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const int f = threadIdx.x + j * FFT_THREADS;
+        const int col = f % W, z = f / W;
+        if (f < npts && kx0 + col < a.mx)
+          base[c * comp_stride + (long long)z * axis_stride + col] = buf[z * DW + c * W + col];
+      }
     __syncthreads();
   }
 }

@@ -100,6 +100,7 @@ struct PcgBufs {
 struct Tunables {
   int tz = 32;          // z planes per stiffness block (3D)
   int ygrid = 2048;     // persistent blocks of the y pass (all components and cells)
+  int ggrid = 1024;     // persistent blocks of the last-axis Green pass (all cells)
   int graph_iters = 0;  // iterations per captured graph (0: launch kernels directly)
 };
 
@@ -270,6 +271,13 @@ template <typename Real>
 int tile_width(int L) {
   const int w = 128 / (int)sizeof(typename CxT<Real>::T);
   return std::max(1, std::min(w, MaxPt<Real>::value * FFT_THREADS / L));
+}
+
+// the same for the last-axis pass, whose tiles hold all d components in LDS
+template <typename Real>
+int green_tile_width(int L) {
+  const int w = 128 / (int)sizeof(typename CxT<Real>::T);
+  return std::max(1, std::min(w, GreenPt<Real>::value * FFT_THREADS / L));
 }
 
 bool useJ(const jfft_cell_s *c) { return c->pc == JFFT_PC_JACOBI || c->pc == JFFT_PC_GREEN_JACOBI; }
@@ -575,9 +583,12 @@ jfft_status launch_green(jfft_cell_s *c, typename CxT<Real>::T *spec, bool check
   a.check_done = check_done ? 1 : 0;
   a.cs = c->cs;
   const int L = c->dim == 3 ? c->g.nz : c->g.ny;
-  a.W = tile_width<Real>(L);
-  dim3 gr((c->g.mx + a.W - 1) / a.W, c->dim == 3 ? c->g.ny : 1, c->B);
-  const size_t smem = sizeof(C) * ((size_t)L + (size_t)L * a.W);
+  a.W = green_tile_width<Real>(L);
+  // persistent blocks, each walking tiles (x-bin range, ky) of one cell
+  const long long ntiles = (long long)((c->g.mx + a.W - 1) / a.W) * (c->dim == 3 ? c->g.ny : 1);
+  const long long want = std::max<long long>(1, c->tun.ggrid / c->B);
+  dim3 gr((unsigned)std::min(ntiles, want), 1, c->B);
+  const size_t smem = sizeof(C) * ((size_t)L + (size_t)c->dim * L * a.W);
   if (c->dim == 3)
     LAUNCH(c, KID_GREEN, k_green_axis<Real, 3><<<gr, FFT_THREADS, smem, c->stream>>>(a));
   else
@@ -648,6 +659,27 @@ jfft_status pcg_iteration(jfft_cell_s *c, const PcgBufs<Real> &b, int j, History
   return precond<Real>(c, b.r, b.q, b.Jh, b.z, b.spec, true, true, &nA, &nB, h);
 }
 
+// Iterations until the slowest running cell of the group stops, predicted
+// from its average convergence rate so far (||r||^2 decays about
+// geometrically), so that few launches go out after the stop; 0 when every
+// cell has stopped.  Launches past a cell's stop are harmless (its kernels
+// return at once) but cost launch time and would blur per-kernel timings.
+int predict_remaining(const jfft_cell_s *c) {
+  int need = 0;
+  for (int i = 0; i < c->B; ++i) {
+    const CgState &s = c->st_h[i];
+    if (s.done) continue;
+    int rem = 32;
+    if (s.iter > 0 && s.rr > 0.0 && s.rr0 > s.rr && s.tol2 > 0.0) {
+      const double rate = std::log(s.rr0 / s.rr) / s.iter;
+      rem = (int)std::ceil(0.85 * std::log(s.rr / s.tol2) / rate);
+    }
+    rem = std::max(1, std::min(rem, s.maxit - s.iter));
+    need = std::max(need, rem);
+  }
+  return need;
+}
+
 jfft_status fetch_states(jfft_cell_s *c) {
   HIP_TRY(hipMemcpy2DAsync(c->st_h, sizeof(CgState), c->st, (size_t)c->cs, sizeof(CgState), c->B,
                            hipMemcpyDeviceToHost, c->stream));
@@ -694,7 +726,7 @@ jfft_status run_pcg(jfft_cell_s *c, const PcgBufs<Real> &b, double tol, bool mix
   int chunk = 2;
   for (;;) {
     if (graph) {
-      const int reps = std::max(1, chunk / G);
+      const int reps = std::max(1, (chunk + G / 2) / G);
       for (int k = 0; k < reps; ++k) HIP_TRY(hipGraphLaunch(c->gexec[gk], c->stream));
     } else {
       for (int k = 0; k < chunk; ++k) {
@@ -703,10 +735,9 @@ jfft_status run_pcg(jfft_cell_s *c, const PcgBufs<Real> &b, double tol, bool mix
       }
     }
     TRY(fetch_states(c));
-    bool done = true;
-    for (int i = 0; i < c->B; ++i) done = done && c->st_h[i].done;
-    if (done) break;
-    chunk = std::min(chunk * 2, 32);
+    const int need = predict_remaining(c);
+    if (need == 0) break;
+    chunk = std::max(1, std::min(need, std::min(chunk * 2, 32)));
   }
   // the owed update u += alpha p_k of every cell
   const long long n = (long long)c->dim * c->g.N;

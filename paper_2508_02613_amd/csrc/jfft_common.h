@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 namespace jfft {
 
@@ -25,10 +26,17 @@ struct CxT<float> {
 // out as B equal slices of `cs` bytes.  Kernels take the pointers of cell 0
 // and shift them to their cell (found from a grid dimension); read-only
 // tables shared by all cells are not shifted.
+// The shift is byte-pointer arithmetic, not an integer round trip, and
+// kernels keep the shifted pointers in local variables rather than writing
+// them back into their by-value argument structs: either way the compiler
+// loses track of the global address space and falls back to flat accesses,
+// which share the LDS wait counter, so that every LDS wait also waits for the
+// outstanding HBM loads.
 template <typename T>
 __device__ __forceinline__ T *cshift(T *p, int cell, long long cs) {
-  return p ? reinterpret_cast<T *>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)((long long)cell * cs))
-           : p;
+  using Byte = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+  const long long off = p ? (long long)cell * cs : 0;  // NULL stays NULL
+  return reinterpret_cast<T *>(reinterpret_cast<Byte *>(p) + off);
 }
 
 // CG scalars kept on the device so that the whole loop runs without host
@@ -40,7 +48,8 @@ struct CgState {
   double beta;      // beta_k
   double rr;        // ||r_k||^2
   double tol2;      // stopping threshold on ||r_k||^2
-  double scratch[2];
+  double rr0;       // ||r_0||^2 of the current loop (host-side stop prediction)
+  double scratch;
   int iter;         // completed updates of u
   int maxit;
   int done;         // 1 once stopped (later kernels of the loop return at once)
