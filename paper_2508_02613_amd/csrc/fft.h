@@ -298,31 +298,48 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
   Real alpha = 0;
   if (UPDATE) alpha = (Real)st->alpha;
   double rr = 0.0;
-  for (int f = threadIdx.x; f < RB * m; f += FFT_THREADS) {
-    const int row = f / m, j = f % m;
-    const long long g = row0 + row;
+  // The block's RB rows are one contiguous run of RB * m pairs.  All loads
+  // are issued before any is used (fixed, unrolled slots), so that a thread
+  // has its whole share in flight at once.
+  constexpr int XP = MaxPt<Real>::value;  // RB * m <= XP * FFT_THREADS
+  const int tot = RB * m;
+  const long long base = row0 * m;
+  const long long lim = a.nrows * (long long)m;
+  // Loads are unconditional at clamped (valid) offsets: a predicated load
+  // makes the compiler wait for it at once.
+  R2 rv[XP], qv[XP], jv[XP];
+#pragma unroll
+  for (int j = 0; j < XP; ++j) {
+    const int f = threadIdx.x + j * FFT_THREADS;
+    const long long off = min(base + min(f, tot - 1), lim - 1);
+    rv[j] = reinterpret_cast<const R2 *>(r)[off];
+    if (UPDATE) qv[j] = reinterpret_cast<const R2 *>(q)[off];
+    if (USE_J) jv[j] = reinterpret_cast<const R2 *>(Jh)[off];
+  }
+#pragma unroll
+  for (int j = 0; j < XP; ++j) {
+    const int f = threadIdx.x + j * FFT_THREADS;
+    if (f >= tot) continue;
+    const long long off = base + f;
     C z;
     z.x = 0;
     z.y = 0;
-    if (g < a.nrows) {
-      const long long off = g * (long long)m + j;  // in pairs (R2 units)
-      R2 rv = reinterpret_cast<const R2 *>(r)[off];
+    if (off < lim) {
+      R2 v = rv[j];
       if (UPDATE) {
-        const R2 qv = reinterpret_cast<const R2 *>(q)[off];
-        rv.x -= alpha * qv.x;
-        rv.y -= alpha * qv.y;
-        reinterpret_cast<R2 *>(r)[off] = rv;
+        v.x -= alpha * qv[j].x;
+        v.y -= alpha * qv[j].y;
+        reinterpret_cast<R2 *>(r)[off] = v;
       }
-      rr += (double)rv.x * (double)rv.x + (double)rv.y * (double)rv.y;
+      rr += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
       if (USE_J) {
-        const R2 jv = reinterpret_cast<const R2 *>(Jh)[off];
-        rv.x *= jv.x;
-        rv.y *= jv.y;
+        v.x *= jv[j].x;
+        v.y *= jv[j].y;
       }
-      z.x = rv.x;
-      z.y = rv.y;
+      z.x = v.x;
+      z.y = v.y;
     }
-    buf[row * sc + j] = z;
+    buf[(f / m) * sc + f % m] = z;
   }
   __syncthreads();
   lds_fft<Real, false>(buf, a.plan, RB, 1, sc, tw, 2, true);
@@ -398,14 +415,41 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
   const int sc = m + 1;
   const long long row0 = (long long)blockIdx.x * RB;
   load_twiddles<Real>(tw, a.tw, a.nx);
-  for (int f = threadIdx.x; f < RB * (m + 1); f += FFT_THREADS) {
-    const int row = f / (m + 1), k = f % (m + 1);
-    const long long g = row0 + row;
-    C v;
-    v.x = 0;
-    v.y = 0;
-    if (g < a.nrows) v = spec[g * (long long)a.mxp + k];
-    buf[row * sc + k] = v;
+  // spectrum rows: all loads in flight at once (fixed, unrolled slots)
+  constexpr int XP = MaxPt<Real>::value;  // RB * m <= XP * FFT_THREADS
+  constexpr int SP = XP + 1;              // RB * (m + 1) <= SP * FFT_THREADS (RB <= 64)
+  {
+    const int tot = RB * (m + 1);
+    C sv[SP];
+#pragma unroll
+    for (int j = 0; j < SP; ++j) {  // unconditional loads at clamped (valid) positions
+      const int f = min(threadIdx.x + j * FFT_THREADS, tot - 1);
+      const int row = f / (m + 1), k = f % (m + 1);
+      const long long g = min(row0 + row, a.nrows - 1);
+      sv[j] = spec[g * (long long)a.mxp + k];
+    }
+#pragma unroll
+    for (int j = 0; j < SP; ++j) {
+      const int f = threadIdx.x + j * FFT_THREADS;
+      const int row = f / (m + 1), k = f % (m + 1);
+      if (f < tot) {
+        C v = sv[j];
+        if (row0 + row >= a.nrows) v.x = v.y = 0;
+        buf[row * sc + k] = v;
+      }
+    }
+  }
+  // J^1/2 and r for the epilogue: in flight during the transform
+  const int tot = RB * m;
+  const long long base = row0 * m;
+  const long long lim = a.nrows * (long long)m;
+  R2 jv[XP], rv[XP];
+#pragma unroll
+  for (int j = 0; j < XP; ++j) {  // unconditional loads at clamped (valid) offsets
+    const int f = threadIdx.x + j * FFT_THREADS;
+    const long long off = min(base + min(f, tot - 1), lim - 1);
+    if (USE_J) jv[j] = reinterpret_cast<const R2 *>(Jh)[off];
+    rv[j] = reinterpret_cast<const R2 *>(r)[off];
   }
   __syncthreads();
   // Z[k] = (X[k] + conj X[m-k]) + i conj(w^k) (X[k] - conj X[m-k]), k < m.
@@ -442,25 +486,21 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
   __syncthreads();
   lds_fft<Real, true>(buf, a.plan, RB, 1, sc, tw, 2, true);
   double rz = 0.0;
-  for (int f = threadIdx.x; f < RB * m; f += FFT_THREADS) {
-    const int row = f / m, j = f % m;
-    const long long g = row0 + row;
-    if (g >= a.nrows) continue;
-    const long long off = g * (long long)m + j;
-    const C z = buf[row * sc + j];
+#pragma unroll
+  for (int j = 0; j < XP; ++j) {
+    const int f = threadIdx.x + j * FFT_THREADS;
+    const long long off = base + f;
+    if (f >= tot || off >= lim) continue;
+    const C z = buf[(f / m) * sc + f % m];
     R2 t;
     t.x = z.x;
     t.y = z.y;
     if (USE_J) {
-      const R2 jv = reinterpret_cast<const R2 *>(Jh)[off];
-      t.x *= jv.x;
-      t.y *= jv.y;
+      t.x *= jv[j].x;
+      t.y *= jv[j].y;
     }
     reinterpret_cast<R2 *>(out)[off] = t;
-    if (partA) {
-      const R2 rv = reinterpret_cast<const R2 *>(r)[off];
-      rz += (double)rv.x * (double)t.x + (double)rv.y * (double)t.y;
-    }
+    if (partA) rz += (double)rv[j].x * (double)t.x + (double)rv[j].y * (double)t.y;
   }
   const double s = block_sum<FFT_THREADS>(rz, red);
   if (threadIdx.x == 0 && partA) partA[blockIdx.x] = s;
@@ -628,16 +668,16 @@ struct GreenPt {
   static constexpr int value = sizeof(Real) == 8 ? 4 : 8;
 };
 
-// Last axis: forward C2C, Green multiply, inverse C2C for every component of
-// a tile of W x bins (3D: at one ky; 2D: the whole y axis).  The d components
-// of the tile sit in LDS side by side (point row t holds d * W values, component
+// Last axis, LDS-resident form (FP64 path): forward C2C, Green multiply,
+// inverse C2C for every component of a tile of W x bins (3D: at one ky; 2D:
+// the whole y axis).  The d components of the tile sit in LDS side by side (point row t holds d * W values, component
 // major), so one Stockham transform covers all d * W lines.  Blocks are
 // persistent over the tiles of their cell, taken in an XCD-aware order so
 // that neighbouring tiles (which share cache lines) run under one L2; the
 // loads of the next tile are in flight in registers while the current one is
 // transformed.
 template <typename Real, int DIM>
-__global__ void __launch_bounds__(FFT_THREADS) k_green_axis(GArgs<Real> a) {
+__global__ void __launch_bounds__(FFT_THREADS) k_green_lds(GArgs<Real> a) {
   using C = typename CxT<Real>::T;
   constexpr int PPT = GreenPt<Real>::value;
   C *const spec = cshift(a.spec, blockIdx.z, a.cs);  // a local (see cshift)
@@ -731,6 +771,87 @@ __global__ void __launch_bounds__(FFT_THREADS) k_green_axis(GArgs<Real> a) {
         if (f < npts && kx0 + col < a.mx)
           base[c * comp_stride + (long long)z * axis_stride + col] = buf[z * DW + c * W + col];
       }
+    __syncthreads();
+  }
+}
+
+// Last axis: forward C2C, Green multiply, inverse C2C for every component of
+// a tile of W x bins (3D: at one ky; 2D: the whole y axis), one tile per
+// block, the transformed components held in registers (FP32 path).
+template <typename Real, int DIM>
+__global__ void __launch_bounds__(FFT_THREADS) k_green_axis(GArgs<Real> a) {
+  using C = typename CxT<Real>::T;
+  C *const spec = cshift(a.spec, blockIdx.z, a.cs);  // a local (see cshift)
+  if (a.check_done && cshift(a.st, blockIdx.z, a.cs)->done) return;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *tw = reinterpret_cast<C *>(smem_raw);
+  const int L = DIM == 3 ? a.nz : a.ny;
+  C *buf = tw + L;
+  load_twiddles<Real>(tw, a.tw, L);
+  const int W = a.W;
+  const int kx0 = blockIdx.x * W;
+  const int ky = DIM == 3 ? blockIdx.y : 0;
+  // line (kx, ky) along the last axis: component c, position t
+  const long long comp_stride = (long long)a.nz * a.ny * a.mxp;
+  const long long axis_stride = DIM == 3 ? (long long)a.ny * a.mxp : (long long)a.mxp;
+  C *base = spec + (DIM == 3 ? (long long)ky * a.mxp : 0) + kx0;
+  constexpr int PPT = MaxPt<Real>::value;  // points per thread kept across components
+  C stash[DIM][PPT];
+  const int npts = L * W;
+  for (int c = 0; c < DIM; ++c) {
+    for (int f = threadIdx.x; f < npts; f += FFT_THREADS) {
+      const int col = f % W, t = f / W;
+      C v;
+      v.x = 0;
+      v.y = 0;
+      if (kx0 + col < a.mx) v = base[c * comp_stride + (long long)t * axis_stride + col];
+      buf[f] = v;
+    }
+    __syncthreads();
+    lds_fft<Real, false>(buf, a.plan, W, W, 1, tw, 1, false);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int f = threadIdx.x + j * FFT_THREADS;
+      if (f < npts) stash[c][j] = buf[f];
+    }
+    __syncthreads();
+  }
+  // Green multiply on the points this thread holds
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int f = threadIdx.x + j * FFT_THREADS;
+    if (f < npts) {
+      const int col = f % W, t = f / W;
+      const int kx = min(kx0 + col, a.mx - 1);
+      if (DIM == 3) {
+        const double A[3] = {a.tx.a[kx], a.ty.a[ky], a.tz.a[t]};
+        const double B[3] = {a.tx.b[kx], a.ty.b[ky], a.tz.b[t]};
+        const double S[3] = {a.tx.s[kx], a.ty.s[ky], a.tz.s[t]};
+        C v[3] = {stash[0][j], stash[1][j], stash[2][j]};
+        green3(A, B, S, a.lam, a.mu, a.invN, kx == 0 && ky == 0 && t == 0, v);
+        for (int c = 0; c < 3; ++c) stash[c][j] = v[c];
+      } else {
+        const double A[2] = {a.tx.a[kx], a.ty.a[t]};
+        const double B[2] = {a.tx.b[kx], a.ty.b[t]};
+        const double S[2] = {a.tx.s[kx], a.ty.s[t]};
+        C v[2] = {stash[0][j], stash[1][j]};
+        green2(A, B, S, a.lam, a.mu, a.invN, kx == 0 && t == 0, v);
+        for (int c = 0; c < 2; ++c) stash[c][j] = v[c];
+      }
+    }
+  }
+  for (int c = 0; c < DIM; ++c) {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int f = threadIdx.x + j * FFT_THREADS;
+      if (f < npts) buf[f] = stash[c][j];
+    }
+    __syncthreads();
+    lds_fft<Real, true>(buf, a.plan, W, W, 1, tw, 1, false);
+    for (int f = threadIdx.x; f < npts; f += FFT_THREADS) {
+      const int col = f % W, t = f / W;
+      if (kx0 + col < a.mx) base[c * comp_stride + (long long)t * axis_stride + col] = buf[f];
+    }
     __syncthreads();
   }
 }

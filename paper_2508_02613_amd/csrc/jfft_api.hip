@@ -386,9 +386,9 @@ void set_smem_attributes() {
                               hipFuncAttributeMaxDynamicSharedMemorySize, big);
     (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_ypass<double, true>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_green_axis<double, 3>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_green_lds<double, 3>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_green_axis<double, 2>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_green_lds<double, 2>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, big);
   });
 }
@@ -583,16 +583,27 @@ jfft_status launch_green(jfft_cell_s *c, typename CxT<Real>::T *spec, bool check
   a.check_done = check_done ? 1 : 0;
   a.cs = c->cs;
   const int L = c->dim == 3 ? c->g.nz : c->g.ny;
-  a.W = green_tile_width<Real>(L);
-  // persistent blocks, each walking tiles (x-bin range, ky) of one cell
-  const long long ntiles = (long long)((c->g.mx + a.W - 1) / a.W) * (c->dim == 3 ? c->g.ny : 1);
-  const long long want = std::max<long long>(1, c->tun.ggrid / c->B);
-  dim3 gr((unsigned)std::min(ntiles, want), 1, c->B);
-  const size_t smem = sizeof(C) * ((size_t)L + (size_t)c->dim * L * a.W);
-  if (c->dim == 3)
-    LAUNCH(c, KID_GREEN, k_green_axis<Real, 3><<<gr, FFT_THREADS, smem, c->stream>>>(a));
-  else
-    LAUNCH(c, KID_GREEN, k_green_axis<Real, 2><<<gr, FFT_THREADS, smem, c->stream>>>(a));
+  if constexpr (sizeof(Real) == 8) {
+    // FP64: tiles with all components in LDS, persistent blocks
+    a.W = green_tile_width<Real>(L);
+    const long long ntiles = (long long)((c->g.mx + a.W - 1) / a.W) * (c->dim == 3 ? c->g.ny : 1);
+    const long long want = std::max<long long>(1, c->tun.ggrid / c->B);
+    dim3 gr((unsigned)std::min(ntiles, want), 1, c->B);
+    const size_t smem = sizeof(C) * ((size_t)L + (size_t)c->dim * L * a.W);
+    if (c->dim == 3)
+      LAUNCH(c, KID_GREEN, k_green_lds<Real, 3><<<gr, FFT_THREADS, smem, c->stream>>>(a));
+    else
+      LAUNCH(c, KID_GREEN, k_green_lds<Real, 2><<<gr, FFT_THREADS, smem, c->stream>>>(a));
+  } else {
+    // FP32: one tile per block, components in registers
+    a.W = tile_width<Real>(L);
+    dim3 gr((c->g.mx + a.W - 1) / a.W, c->dim == 3 ? c->g.ny : 1, c->B);
+    const size_t smem = sizeof(C) * ((size_t)L + (size_t)L * a.W);
+    if (c->dim == 3)
+      LAUNCH(c, KID_GREEN, k_green_axis<Real, 3><<<gr, FFT_THREADS, smem, c->stream>>>(a));
+    else
+      LAUNCH(c, KID_GREEN, k_green_axis<Real, 2><<<gr, FFT_THREADS, smem, c->stream>>>(a));
+  }
   return JFFT_OK;
 }
 
