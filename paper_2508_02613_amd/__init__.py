@@ -19,7 +19,8 @@ from dataclasses import dataclass
 import numpy as np
 
 __all__ = ["load_library", "Cell", "Report", "PC_NONE", "PC_GREEN", "PC_JACOBI",
-           "PC_GREEN_JACOBI", "FP64", "MIXED", "JfftError", "EXPORTED_SYMBOLS", "lame_from_nu"]
+           "PC_GREEN_JACOBI", "FP64", "MIXED", "JfftError", "EXPORTED_SYMBOLS", "lame_from_nu",
+           "effective_stiffness"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(_HERE, "libjfft.so")
@@ -325,3 +326,28 @@ class Cell:
             if la.value:
                 out[nm.value.decode()] = (int(la.value), float(ms.value))
         return out
+
+
+def effective_stiffness(E, nu=0.3, lame=None, tol=1e-8, maxit=20000, precision=FP64,
+                        pc=PC_GREEN_JACOBI, lengths=None, stream=None, graph_iterations=0):
+    """Homogenised Mandel stiffness of one periodic cell (Sec. 5).
+
+    The d* unit macro strains e_g are solved as one group of d* cells that
+    share the material field E; column g of the result is sigma_bar for e_g.
+    Returns (C [d*, d*] numpy array, [Report] per load case)."""
+    torch = _torch()
+    if isinstance(E, np.ndarray):
+        E = torch.from_numpy(np.ascontiguousarray(E, dtype=np.float64))
+    shape = tuple(E.shape)
+    dim = len(shape)
+    ds = dim * (dim + 1) // 2
+    grp = Cell(shape, precision=precision, pc=pc, lengths=lengths, stream=stream, batch=ds)
+    try:
+        if graph_iterations:
+            grp.set_graph_iterations(graph_iterations)
+        Ed = E.to(device=grp.device, dtype=torch.float64)
+        grp.set_material(Ed.unsqueeze(0).expand((ds,) + shape).contiguous(), nu=nu, lame=lame)
+        _, sbar, reps, _ = grp.solve_batch(np.eye(ds), tol=tol, maxit=maxit)
+    finally:
+        grp.close()
+    return np.ascontiguousarray(sbar.T), reps
