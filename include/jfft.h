@@ -161,8 +161,8 @@ jfft_status jfft_solve_batch(jfft_cell_t cell, const double *macro_strains, doub
    cell's stream) and replayed between polls; iterations past a cell's stop
    cost only their launches.  Needs a stream other than the legacy default
    stream; kernel timing (jfft_enable_timing) switches graph replay off.  The
-   graph is rebuilt after a change of material, history capacity or this
-   setting. */
+   graph is rebuilt after a change of the Lame constants, of the history
+   capacity or of this setting; a new E field alone keeps it. */
 jfft_status jfft_set_graph_iterations(jfft_cell_t cell, int iterations);
 
 /* Operators, for verification and composition (all FP64, device in/out

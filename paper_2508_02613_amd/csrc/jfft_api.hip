@@ -799,10 +799,12 @@ jfft_status set_material_impl(jfft_cell_s *c, const double *E_dev, double lam, d
   if (!(mu > 0.0) || !(lam + 2.0 * mu / c->dim > 0.0) || !std::isfinite(lam) || !std::isfinite(mu))
     return fail(JFFT_E_INVALID, "Lame constants must satisfy mu > 0 and lambda + 2 mu / d > 0");
   TRY(ensure_ready(c));
+  // captured iterations carry lambda and mu as kernel arguments; the moduli
+  // are read from the workspace, so a new E alone keeps them valid
+  if (c->lam != lam || c->mu != mu) c->drop_graphs();
   c->has_material = false;
   c->lam = lam;
   c->mu = mu;
-  c->drop_graphs();  // kernel arguments carry lambda and mu
   const long long N = c->g.N;
   const long long es = (long long)sizeof(double) * N;  // caller's layout [B][N]
   const int nb = vec_blocks(N);
