@@ -10,10 +10,14 @@ iterative-refinement residual); the plain FP64 solver is timed on the same
 input and reported beside it.
 
 value = DOF x PCG iterations (all inner iterations) / wall time of the timed
-steps, with DOF = 3 n^3.
+steps, with DOF = 3 n^3.  The same line carries the served-stream figures
+("serving": capacity, Poisson-arrival throughput, p50/p99 latency of
+homogenisation requests, mixed and FP64), the roofline of the dominant
+kernel and the CPU oracle baseline.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256]
-                       [--contrast 1e4] [--no-cpu] [--no-fp64]
+                       [--contrast 1e4] [--no-cpu] [--no-fp64] [--no-serve]
+       python bench.py --workload simp2d [--cells 512]   (batched 2D SIMP cells)
 """
 from __future__ import annotations
 
@@ -46,6 +50,12 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-stream measurement")
+    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--workload", default="grf256", choices=["grf256", "simp2d"],
+                    help="grf256: the headline 256^3 cell (+ served stream); simp2d: 512 "
+                         "batched 2D SIMP cells of uneven sizes")
+    ap.add_argument("--cells", type=int, default=512, help="simp2d: number of cells")
     return ap.parse_args()
 
 
@@ -198,6 +208,113 @@ def cpu_baseline(E, macro, nu):
     }
 
 
+def serve_requests(count, seed):
+    """Served-stream workload: 3D cells with side uniform from {32, 48, 64, 96,
+    128}, smooth GRF material (correlation length 0.1) with contrast
+    log-uniform in [1e2, 1e4]; each request asks for C_eff (6 load cases)."""
+    import jfft_inputs as ji
+    from paper_2508_02613_amd.serve import Request
+
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.choice((32, 48, 64, 96, 128)))
+        c = float(10 ** rng.uniform(2.0, 4.0))
+        out.append(Request(i, ji.grf_field((n, n, n), c, seed=seed * 100003 + i, ell=0.1)))
+    return out
+
+
+def run_serving(args):
+    """Saturated capacity (all requests at t = 0), then Poisson arrivals at
+    0.8 x that capacity, for the mixed and the FP64 solver at equal final
+    accuracy (true relative residual <= 1e-8 for every load case)."""
+    import paper_2508_02613_amd as pkg
+    from paper_2508_02613_amd.serve import Server
+
+    out = {"workload": (f"{args.serve_requests} requests, 3D side uniform from "
+                        "{32,48,64,96,128}, GRF contrast log-uniform 1e2-1e4, 6 load cases -> "
+                        "C_eff each; 4 workers, 64 GiB admission budget, merge <= 4 requests "
+                        "of side <= 64, 8 PCG iterations per graph"),
+           "unit": "requests/s (6 solves each); latency ms"}
+    for name, prec in (("mixed", pkg.MIXED), ("fp64", pkg.FP64)):
+        srv = Server(workers=4, budget_bytes=64 << 30, precision=prec, graph_iterations=8)
+        srv.run(serve_requests(8, 99), rate=None)  # warm-up: handles, graphs, kernels
+        sat = srv.run(serve_requests(args.serve_requests, 1), rate=None)
+        lam = 0.8 * sat["requests_per_s"]
+        po = srv.run(serve_requests(args.serve_requests, 2), rate=lam, seed=3)
+        srv.close()
+        out[name] = {"capacity_requests_per_s": sat["requests_per_s"],
+                     "capacity_solves_per_s": sat["solves_per_s"],
+                     "poisson_rate": lam, "requests_per_s": po["requests_per_s"],
+                     "solves_per_s": po["solves_per_s"], "p50_latency_ms": po["p50_latency_ms"],
+                     "p99_latency_ms": po["p99_latency_ms"], "mean_merged": po["mean_merged"],
+                     "all_ok": sat["all_ok"] and po["all_ok"],
+                     "max_rel_res_true": max(sat["max_rel_res_true"], po["max_rel_res_true"])}
+    return out
+
+
+def run_simp2d(args):
+    """Batch of 2D plane-strain SIMP cells of uneven sizes: sides uniform from
+    {64, 128, 256, 512}, E = rho^3 with rho in [1e-3, 1] from blurred noise
+    (4 px), nu 0.3, macro strain cycling e11, e22, e12; groups per size on
+    their own streams, mixed precision, 8 PCG iterations per captured graph.
+    Baseline: the same cells one at a time with the FP64 solver."""
+    import torch
+
+    import jfft_inputs as ji
+    import paper_2508_02613_amd as pkg
+    from paper_2508_02613_amd.groups import solve_cells
+
+    rng = np.random.default_rng(args.seed)
+    sizes = rng.choice((64, 128, 256, 512), size=args.cells)
+    fields = [ji.simp_field(int(n), seed=args.seed * 7919 + i) for i, n in enumerate(sizes)]
+    macros = [ji.unit_macro_strain(2, i % 3) for i in range(args.cells)]
+    dofs = np.array([2 * int(n) ** 2 for n in sizes])
+    for _ in range(args.warmup):
+        solve_cells(fields, macros, tol=1e-8, precision=pkg.MIXED, graph_iterations=8,
+                    want_u=False)
+    walls, its = [], None
+    for _ in range(args.steps):
+        res, wall = solve_cells(fields, macros, tol=1e-8, precision=pkg.MIXED,
+                                graph_iterations=8, want_u=False)
+        walls.append(wall)
+        its = np.array([r["report"].iters for r in res])
+        ok = all(r["report"].status == "ok" for r in res)
+        worst = max(r["report"].rel_res_true for r in res)
+    wall = float(np.mean(walls))
+    # one at a time, FP64, same cells and tolerance
+    t0 = time.perf_counter()
+    its64 = []
+    for E, m in zip(fields, macros):
+        cell = pkg.Cell(E.shape, precision=pkg.FP64)
+        cell.set_material(E, nu=0.3)
+        _, _, rep, _ = cell.solve(m, tol=1e-8, maxit=20000)
+        its64.append(rep.iters)
+        cell.close()
+    torch.cuda.synchronize()
+    wall64 = time.perf_counter() - t0
+    value = float((dofs * its).sum() / wall)
+    return {
+        "metric": "DOF·iterations/s (batched 2D SIMP cells, mixed precision)",
+        "value": value, "unit": "DOF·it/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": (f"{args.cells} 2D plane-strain cells, sides uniform from "
+                                "{64,128,256,512}, SIMP E = rho^3, rho in [1e-3, 1] (blurred "
+                                "noise, 4 px), nu 0.3, one macro strain each, Green-Jacobi "
+                                "PCG to 1e-8, groups per size on concurrent streams, 8 "
+                                "iterations per HIP graph"),
+                   "cells": args.cells, "total_dofs": int(dofs.sum())},
+        "cells_per_s": args.cells / wall,
+        "all_ok": ok, "max_rel_res_true": worst,
+        "iterations": {"mean": float(its.mean()), "max": int(its.max())},
+        "one_at_a_time_fp64": {"wall_s": wall64, "cells_per_s": args.cells / wall64,
+                               "value": float((dofs * np.array(its64)).sum() / wall64),
+                               "iterations_mean": float(np.mean(its64))},
+        "speedup_vs_one_at_a_time_fp64": wall64 / wall,
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -212,6 +329,9 @@ def main():
         sys.exit(1)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.workload == "simp2d":
+        print(json.dumps(run_simp2d(args)), flush=True)
         return
     import jfft_inputs as ji
 
@@ -253,7 +373,7 @@ def main():
     wkey = f"{head}_{n}"
     traffic = load_traffic(wkey, dom)
     line = {
-        "metric": "DOF·iterations/s (J-FFT PCG, 256³)",
+        "metric": "DOF·iterations/s (J-FFT PCG, 256³); served solves/s + p99 latency",
         "value": value,
         "unit": "DOF·it/s",
         "n_gpus": 1,
@@ -290,6 +410,8 @@ def main():
                             / np.abs(F["sigma_bar"]).max()),
                         "kernels_ms_per_step": {k: v[1] / args.steps
                                                 for k, v in sorted(F["stats"].items())}}
+    if not args.no_serve:
+        line["serving"] = run_serving(args)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(E, macro, nu)
     print(json.dumps(line), flush=True)
