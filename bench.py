@@ -52,7 +52,7 @@ def parse():
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream measurement")
     ap.add_argument("--serve-requests", type=int, default=40)
-    ap.add_argument("--workload", default="grf256", choices=["grf256", "simp2d"],
+    ap.add_argument("--workload", default="grf256", choices=["grf256", "simp2d", "contrast"],
                     help="grf256: the headline 256^3 cell (+ served stream); simp2d: 512 "
                          "batched 2D SIMP cells of uneven sizes")
     ap.add_argument("--cells", type=int, default=512, help="simp2d: number of cells")
@@ -315,6 +315,57 @@ def run_simp2d(args):
     }
 
 
+def run_contrast_sweep(args):
+    """256^3 GRF cells at contrasts 1e3, 1e4, 1e5: mixed vs FP64 solver on
+    e11 (iterations, DOF-iterations/s, relative difference of the mean-free
+    fluctuation), and the 6 x 6 C_eff of both solvers (six load cases as one
+    group) with their relative difference."""
+    import torch
+
+    import jfft_inputs as ji
+    import paper_2508_02613_amd as pkg
+
+    n = args.n
+    shape = (n, n, n)
+    macro = ji.unit_macro_strain(3, 0)
+    rows = []
+    for contrast in (1e3, 1e4, 1e5):
+        E = ji.grf_field(shape, contrast, seed=args.seed, ell=0.1)
+        Ed = torch.from_numpy(E).cuda()
+        row = {"contrast": contrast}
+        us = {}
+        for name, prec in (("mixed", pkg.MIXED), ("fp64", pkg.FP64)):
+            cell = pkg.Cell(shape, precision=prec)
+            cell.set_material(Ed, nu=0.3)
+            cell.solve(macro, tol=1e-8, maxit=20000)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, sbar, rep, _ = cell.solve(macro, tol=1e-8, maxit=20000)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            us[name] = u.clone()
+            cell.close()
+            row[name] = {"iters": rep.iters, "outer": rep.outer, "wall_ms": wall * 1e3,
+                         "loop_ms": rep.loop_ms, "rel_res_true": rep.rel_res_true,
+                         "dof_it_per_s": 3 * E.size * rep.iters / wall}
+        d = torch.linalg.vector_norm(us["mixed"] - us["fp64"]) / torch.linalg.vector_norm(us["fp64"])
+        row["u_rel_diff_mixed_vs_fp64"] = float(d)
+        del us
+        Cm, rm = pkg.effective_stiffness(Ed, nu=0.3, tol=1e-8, precision=pkg.MIXED)
+        C64, r64 = pkg.effective_stiffness(Ed, nu=0.3, tol=1e-8, precision=pkg.FP64)
+        row["ceff_rel_diff_mixed_vs_fp64"] = float(np.abs(Cm - C64).max() / np.abs(C64).max())
+        row["ceff_iters_mixed"] = [r.iters for r in rm]
+        row["ceff_iters_fp64"] = [r.iters for r in r64]
+        row["ceff_fp64_diag"] = [float(C64[i, i]) for i in range(6)]
+        rows.append(row)
+        torch.cuda.empty_cache()
+    return {"metric": "contrast sweep, 256^3 GRF cell (mixed vs FP64 J-FFT PCG)",
+            "config": {"workload": (f"{n}^3 GRF cells (ell 0.1, seed {args.seed}), contrasts "
+                                    "1e3/1e4/1e5, nu 0.3, tol 1e-8; e11 timed after one warm-up "
+                                    "solve; C_eff from six load cases as one group")},
+            "rows": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -332,6 +383,9 @@ def main():
         return
     if args.workload == "simp2d":
         print(json.dumps(run_simp2d(args)), flush=True)
+        return
+    if args.workload == "contrast":
+        print(json.dumps(run_contrast_sweep(args)), flush=True)
         return
     import jfft_inputs as ji
 
