@@ -12,13 +12,24 @@
 
 namespace jfft {
 
-constexpr int CTRL_THREADS = 256;
+constexpr int CTRL_THREADS = 1024;
+constexpr int CTRL_WAVES = CTRL_THREADS / 64;
 
-// Fixed-order sum of n partials by one block: thread t sums t, t + 256, ...
-// sequentially, then a fixed tree.  Result valid in thread 0.
+// Fixed-order sum of n partials by one block: thread t sums t, t + T, t + 2T,
+// ... (T = CTRL_THREADS) in that order, then a fixed tree.  Eight partials are
+// loaded at a time before they are added, so the loads overlap instead of
+// forming one dependent chain.  Result valid in thread 0.
 __device__ __forceinline__ double fixed_sum(const double *p, long long n, double *sm) {
   double v = 0.0;
-  for (long long i = threadIdx.x; i < n; i += CTRL_THREADS) v += p[i];
+  long long i = threadIdx.x;
+  for (; i + 7LL * CTRL_THREADS < n; i += 8LL * CTRL_THREADS) {
+    double t[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t[k] = p[i + (long long)k * CTRL_THREADS];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v += t[k];
+  }
+  for (; i < n; i += CTRL_THREADS) v += p[i];
   return block_sum<CTRL_THREADS>(v, sm);
 }
 
@@ -38,7 +49,7 @@ __device__ __forceinline__ void shift_hist(History &h, int cell, long long cs) {
 // parity: which of the two search-direction buffers holds p_k.
 __global__ void k_cg_alpha(CgState *st, const double *part, long long n, History h, int parity,
                            long long cs) {
-  __shared__ double sm[8];
+  __shared__ double sm[CTRL_WAVES];
   st = cshift(st, blockIdx.x, cs);
   part = cshift(part, blockIdx.x, cs);
   shift_hist(h, blockIdx.x, cs);
@@ -62,7 +73,7 @@ __global__ void k_cg_alpha(CgState *st, const double *part, long long n, History
 
 // ||r_{k+1}||^2; count the update of u; stop on tolerance or maxit.
 __global__ void k_cg_rr(CgState *st, const double *part, long long n, History h, long long cs) {
-  __shared__ double sm[8];
+  __shared__ double sm[CTRL_WAVES];
   st = cshift(st, blockIdx.x, cs);
   part = cshift(part, blockIdx.x, cs);
   shift_hist(h, blockIdx.x, cs);
@@ -86,7 +97,7 @@ __global__ void k_cg_rr(CgState *st, const double *part, long long n, History h,
 
 // beta_k = (r.z)_new / (r.z)_old.
 __global__ void k_cg_beta(CgState *st, const double *part, long long n, History h, long long cs) {
-  __shared__ double sm[8];
+  __shared__ double sm[CTRL_WAVES];
   st = cshift(st, blockIdx.x, cs);
   part = cshift(part, blockIdx.x, cs);
   shift_hist(h, blockIdx.x, cs);
@@ -109,7 +120,7 @@ __global__ void k_cg_beta(CgState *st, const double *part, long long n, History 
 // ||f||^2 and ||f_abs||^2 from partials; the homogeneous-material test.
 __global__ void k_solve_norms(CgState *st, const double *partF, const double *partA, long long n,
                               long long cs) {
-  __shared__ double sm[8];
+  __shared__ double sm[CTRL_WAVES];
   st = cshift(st, blockIdx.x, cs);
   partF = cshift(partF, blockIdx.x, cs);
   partA = cshift(partA, blockIdx.x, cs);
@@ -160,7 +171,7 @@ __global__ void k_cg_init(CgState *st, double tol, double inner_tol, int mixed, 
 // ||r_0||^2 <= tol2 (or maxit == 0).
 __global__ void k_cg_start(CgState *st, const double *partRR, long long nRR, const double *partRZ,
                            long long nRZ, long long cs) {
-  __shared__ double sm[8];
+  __shared__ double sm[CTRL_WAVES];
   st = cshift(st, blockIdx.x, cs);
   partRR = cshift(partRR, blockIdx.x, cs);
   partRZ = cshift(partRZ, blockIdx.x, cs);
@@ -184,7 +195,7 @@ __global__ void k_cg_start(CgState *st, const double *partRR, long long nRR, con
 // whether refinement continues.  (The first sweep starts from u = u0.)
 __global__ void k_outer_check(CgState *st, const double *part, long long n, double tol,
                               int max_outer, int maxit, long long cs) {
-  __shared__ double sm[8];
+  __shared__ double sm[CTRL_WAVES];
   st = cshift(st, blockIdx.x, cs);
   part = cshift(part, blockIdx.x, cs);
   const double rr = fixed_sum(part, n, sm);
@@ -228,7 +239,7 @@ __global__ void k_fp64_final(CgState *st, long long cs) {
 // (one block per cell).
 __global__ void k_reduce_groups(const double *part, long long n, int count, double *out,
                                 long long cs) {
-  __shared__ double sm[8];
+  __shared__ double sm[CTRL_WAVES];
   part = cshift(part, blockIdx.x, cs);
   out = cshift(out, blockIdx.x, cs);
   for (int g = 0; g < count; ++g) {
