@@ -178,8 +178,8 @@ struct Dft<Real, 5, INV> {
 // L / R, current sub-transform length p (product of earlier radices).
 // tw[j * tws] = exp(-2 pi i j / L).  All threads read their butterflies,
 // synchronise, then write, so one buffer suffices.
-// NPT bounds the points per thread (L * W <= NPT * FFT_THREADS).
-template <typename Real, int R, bool INV, int NPT>
+// NPT bounds the points per thread (L * W <= NPT * NT, NT = threads).
+template <typename Real, int R, bool INV, int NPT, int NT>
 __device__ __forceinline__ void stockham_stage(typename CxT<Real>::T *buf, int L, int W, int p,
                                                int sp, int sc, const typename CxT<Real>::T *tw,
                                                int tws, bool i_fastest) {
@@ -191,7 +191,7 @@ __device__ __forceinline__ void stockham_stage(typename CxT<Real>::T *buf, int L
   C v[MB][R];
 #pragma unroll
   for (int b = 0; b < MB; ++b) {
-    const int f = threadIdx.x + b * FFT_THREADS;
+    const int f = threadIdx.x + b * NT;
     if (f < nb) {
       const int i = i_fastest ? f % m : f / W;
       const int c = i_fastest ? f / m : f % W;
@@ -202,7 +202,7 @@ __device__ __forceinline__ void stockham_stage(typename CxT<Real>::T *buf, int L
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < MB; ++b) {
-    const int f = threadIdx.x + b * FFT_THREADS;
+    const int f = threadIdx.x + b * NT;
     if (f < nb) {
       const int i = i_fastest ? f % m : f / W;
       const int c = i_fastest ? f / m : f % W;
@@ -222,23 +222,38 @@ __device__ __forceinline__ void stockham_stage(typename CxT<Real>::T *buf, int L
   __syncthreads();
 }
 
-template <typename Real, bool INV, int NPT = MaxPt<Real>::value>
+template <typename Real, bool INV, int NPT = MaxPt<Real>::value, int NT = FFT_THREADS>
 __device__ void lds_fft(typename CxT<Real>::T *buf, const FftPlan &pl, int W, int sp, int sc,
                         const typename CxT<Real>::T *tw, int tws, bool i_fastest) {
   int p = 1;
   for (int s = 0; s < pl.nst; ++s) {
     const int R = pl.radix[s];
     switch (R) {
-      case 8: stockham_stage<Real, 8, INV, NPT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
-      case 4: stockham_stage<Real, 4, INV, NPT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
-      case 2: stockham_stage<Real, 2, INV, NPT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
-      case 3: stockham_stage<Real, 3, INV, NPT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
-      case 5: stockham_stage<Real, 5, INV, NPT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
+      case 8: stockham_stage<Real, 8, INV, NPT, NT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
+      case 4: stockham_stage<Real, 4, INV, NPT, NT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
+      case 2: stockham_stage<Real, 2, INV, NPT, NT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
+      case 3: stockham_stage<Real, 3, INV, NPT, NT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
+      case 5: stockham_stage<Real, 5, INV, NPT, NT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
       default: break;
     }
     p *= R;
   }
 }
+
+// Half-spectrum layout, tile-major: [d][nz][ntx][ny][TW] complex, where the
+// mx = nx/2 + 1 bins of an x row are cut into ntx tiles of TW = 8 bins.  A
+// y-pass tile (component, z, x-tile) is then one contiguous block, the x
+// passes read and write contiguous (rows x TW) chunks, and the z pass reads
+// whole 128-byte lines: one ky row of a tile in FP64, two adjacent ones in
+// FP32 (ZRows).  The bins past mx in the last tile are zero.
+template <typename Real>
+struct TileW {
+  static constexpr int value = 8;  // the x-pass index math below shifts by 3
+};
+template <typename Real>
+struct ZRows {
+  static constexpr int value = 128 / (TileW<Real>::value * (int)sizeof(typename CxT<Real>::T));
+};
 
 template <typename Real>
 __device__ __forceinline__ void load_twiddles(typename CxT<Real>::T *sm, const double2 *g, int n) {
@@ -257,16 +272,39 @@ struct XArgs {
   const Real *q;       // K p (UPDATE)
   const Real *Jh;      // J^1/2 [d][N] (USE_J)
   Real *out;           // inverse pass: z
-  typename CxT<Real>::T *spec;  // half spectrum [d][nz][ny][mxp]
+  typename CxT<Real>::T *spec;  // half spectrum, tile-major (see TileW)
   double *partA;       // ||r||^2 partials (forward), r.z partials (inverse)
   const CgState *st;
   const double2 *tw;   // exp(-2 pi i j / nx), j < nx
   FftPlan plan;        // length nx / 2
-  int nx, mx, mxp;
+  int nx, mx, ntx, ny;
   long long nrows;     // d * ny * nz rows per cell
-  int rows_per_block;
+  int rows_per_block;  // RB, a power of two
+  int log2_rb;
   int check_done;
   long long cs;        // bytes between the cells of a batch (cell = blockIdx.y)
+};
+
+// Tile-major addressing of the RB consecutive x rows of one block, rows
+// row0 + row = plane * ny + y: one 64-bit division per block, then 32-bit
+// steps (a block's rows may run into the next planes when ny < RB).
+template <int TW>
+struct RowTiles {
+  long long pl0;
+  int y0, ny, ntx;
+  __device__ __forceinline__ RowTiles(long long row0, int ny_, int ntx_) : ny(ny_), ntx(ntx_) {
+    pl0 = row0 / ny;
+    y0 = (int)(row0 - pl0 * ny);
+  }
+  __device__ __forceinline__ long long offset(int row, int kt, int w) const {
+    int y = y0 + row;
+    int dp = 0;
+    if (y >= ny) {
+      dp = y / ny;
+      y -= dp * ny;
+    }
+    return (((pl0 + dp) * ntx + kt) * ny + y) * TW + w;
+  }
 };
 
 // Forward: r <- r - alpha q (UPDATE), s = J^1/2 r (USE_J), X = rfft(s) per row.
@@ -343,46 +381,38 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
   }
   __syncthreads();
   lds_fft<Real, false>(buf, a.plan, RB, 1, sc, tw, 2, true);
-  // split: X[k] = (Z[k] + conj Z[m-k])/2 - i w^k (Z[k] - conj Z[m-k])/2
-  const int half = m / 2 + 1;
-  for (int f = threadIdx.x; f < RB * half; f += FFT_THREADS) {
-    const int row = f / half, k = f % half;
-    const long long g = row0 + row;
-    if (g >= a.nrows) continue;
-    const C zk = buf[row * sc + (k % m)];
-    const C zm = buf[row * sc + ((m - k) % m)];
-    C *dst = spec + g * (long long)a.mxp;
-    // X[k]
-    {
-      C s, d;
-      s.x = (Real)0.5 * (zk.x + zm.x);
-      s.y = (Real)0.5 * (zk.y - zm.y);
-      d.x = (Real)0.5 * (zk.x - zm.x);
-      d.y = (Real)0.5 * (zk.y + zm.y);
-      const C w = tw[k];
-      // -i w d
-      const C wd = cmul(w, d);
+  // split X[k] = (Z[k] + conj Z[m-k])/2 - i w^k (Z[k] - conj Z[m-k])/2 (Z
+  // indices mod m; k = m is the Nyquist bin), evaluated bin by bin in the
+  // order of the tile-major stores: a run of RB x TW consecutive complex
+  // values per x-tile; bins past mx are written as zero
+  {
+    constexpr int TW = TileW<Real>::value;
+    static_assert(TW == 8, "tile-major x-pass addressing assumes 8 bins per tile");
+    constexpr int SP = XP + 2;  // RB * ntx * TW <= RB * (m + TW) <= SP * FFT_THREADS
+    const int tot = (a.ntx * TW) << a.log2_rb;
+    const RowTiles<TW> rt(row0, a.ny, a.ntx);
+#pragma unroll
+    for (int j = 0; j < SP; ++j) {
+      const int f = threadIdx.x + j * FFT_THREADS;
+      const int w = f & (TW - 1), row = (f >> 3) & (RB - 1), kt = f >> (3 + a.log2_rb);
+      const int kx = kt * TW + w;
+      const long long g = row0 + row;
+      if (f >= tot || g >= a.nrows) continue;
       C X;
-      X.x = s.x + wd.y;
-      X.y = s.y - wd.x;
-      dst[k] = X;
-    }
-    // X[m - k] (k = 0 gives the Nyquist bin X[m]; k = m/2 is its own partner)
-    if (k != m - k) {
-      const int k2 = m - k;
-      const C zk2 = buf[row * sc + (k2 % m)];
-      const C zm2 = buf[row * sc + ((m - k2) % m)];
-      C s, d;
-      s.x = (Real)0.5 * (zk2.x + zm2.x);
-      s.y = (Real)0.5 * (zk2.y - zm2.y);
-      d.x = (Real)0.5 * (zk2.x - zm2.x);
-      d.y = (Real)0.5 * (zk2.y + zm2.y);
-      const C w = tw[k2];
-      const C wd = cmul(w, d);
-      C X;
-      X.x = s.x + wd.y;
-      X.y = s.y - wd.x;
-      dst[k2] = X;
+      X.x = 0;
+      X.y = 0;
+      if (kx < a.mx) {
+        const C zk = buf[row * sc + kx % m], zm = buf[row * sc + (m - kx) % m];
+        C sm, d;
+        sm.x = (Real)0.5 * (zk.x + zm.x);
+        sm.y = (Real)0.5 * (zk.y - zm.y);
+        d.x = (Real)0.5 * (zk.x - zm.x);
+        d.y = (Real)0.5 * (zk.y + zm.y);
+        const C wd = cmul(tw[kx], d);  // -i w^k d
+        X.x = sm.x + wd.y;
+        X.y = sm.y - wd.x;
+      }
+      spec[rt.offset(row, kt, w)] = X;
     }
   }
   const double s = block_sum<FFT_THREADS>(rr, red);
@@ -415,27 +445,32 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
   const int sc = m + 1;
   const long long row0 = (long long)blockIdx.x * RB;
   load_twiddles<Real>(tw, a.tw, a.nx);
-  // spectrum rows: all loads in flight at once (fixed, unrolled slots)
+  // spectrum chunks (RB x TW per x-tile): all loads in flight at once (fixed,
+  // unrolled slots at clamped, valid positions)
   constexpr int XP = MaxPt<Real>::value;  // RB * m <= XP * FFT_THREADS
-  constexpr int SP = XP + 1;              // RB * (m + 1) <= SP * FFT_THREADS (RB <= 64)
+  constexpr int TW = TileW<Real>::value;
+  static_assert(TW == 8, "tile-major x-pass addressing assumes 8 bins per tile");
+  constexpr int SP = XP + 2;              // RB * ntx * TW <= RB * (m + TW) <= SP * FFT_THREADS
   {
-    const int tot = RB * (m + 1);
+    const int tot = (a.ntx * TW) << a.log2_rb;
+    const RowTiles<TW> rt(row0, a.ny, a.ntx);
+    const int last_row = (int)min((long long)RB - 1, a.nrows - 1 - row0);
     C sv[SP];
 #pragma unroll
-    for (int j = 0; j < SP; ++j) {  // unconditional loads at clamped (valid) positions
-      const int f = min(threadIdx.x + j * FFT_THREADS, tot - 1);
-      const int row = f / (m + 1), k = f % (m + 1);
-      const long long g = min(row0 + row, a.nrows - 1);
-      sv[j] = spec[g * (long long)a.mxp + k];
+    for (int j = 0; j < SP; ++j) {
+      const int f = min((int)threadIdx.x + j * FFT_THREADS, tot - 1);
+      const int w = f & (TW - 1), row = min((f >> 3) & (RB - 1), last_row), kt = f >> (3 + a.log2_rb);
+      sv[j] = spec[rt.offset(row, kt, w)];
     }
 #pragma unroll
     for (int j = 0; j < SP; ++j) {
       const int f = threadIdx.x + j * FFT_THREADS;
-      const int row = f / (m + 1), k = f % (m + 1);
-      if (f < tot) {
+      const int w = f & (TW - 1), row = (f >> 3) & (RB - 1), kt = f >> (3 + a.log2_rb);
+      const int kx = kt * TW + w;
+      if (f < tot && kx <= m) {
         C v = sv[j];
         if (row0 + row >= a.nrows) v.x = v.y = 0;
-        buf[row * sc + k] = v;
+        buf[row * sc + kx] = v;
       }
     }
   }
@@ -507,76 +542,58 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
 }
 
 // ------------------------------------------------- strided C2C passes ----
-constexpr int FFT_WMAX = 16;  // x bins per tile of a strided pass (fewer for long axes)
-
 template <typename Real>
 struct YArgs {
   typename CxT<Real>::T *spec;
   const CgState *st;
   const double2 *tw;  // exp(-2 pi i j / L)
   FftPlan plan;
-  int mx, mxp, ny, nz;
-  int W;  // x bins per tile, L * W <= MaxPt * FFT_THREADS
+  int ntx, ny, nz;
   int check_done;
   long long cs;  // bytes between the cells of a batch (cell = blockIdx.z)
 };
 
-// C2C along y on tiles of W x bins of one (component, z) plane.  Blocks are
-// persistent over tiles; the next tile's loads are in flight in registers
-// while the current tile is transformed in LDS.
-template <typename Real, bool INV>
-__global__ void __launch_bounds__(FFT_THREADS) k_ypass(YArgs<Real> a) {
+// C2C along y on tiles (component, z, x-tile) of ny points x TW bins, each one
+// contiguous block of the tile-major spectrum.  Blocks are persistent over
+// tiles; the next tile's loads are in flight in registers while the current
+// tile is transformed in LDS.  ny * TW <= MaxPt * NT.
+template <typename Real, bool INV, int NT>
+__global__ void __launch_bounds__(NT) k_ypass(YArgs<Real> a) {
   using C = typename CxT<Real>::T;
   constexpr int PPT = MaxPt<Real>::value;
+  constexpr int TW = TileW<Real>::value;
   C *const spec = cshift(a.spec, blockIdx.z, a.cs);  // a local (see cshift)
   if (a.check_done && cshift(a.st, blockIdx.z, a.cs)->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   const int L = a.ny;
-  const int W = a.W;
   C *buf = tw + L;
   load_twiddles<Real>(tw, a.tw, L);
-  const int ntx = (a.mx + W - 1) / W;
-  const long long ntiles = (long long)ntx * a.nz * gridDim.y;  // gridDim.y = components
-  const int npts = L * W;
+  const int npts = L * TW;
+  const long long per_comp = (long long)a.nz * a.ntx;  // gridDim.y = components
+  C *const comp_base = spec + (long long)blockIdx.y * per_comp * npts;
   C pre[PPT];
-  auto tile_base = [&](long long t, int &kx0) {
-    kx0 = (int)(t % ntx) * W;
-    const long long plane = t / ntx + (long long)blockIdx.y * a.nz;  // comp * nz + z
-    return spec + plane * (long long)a.ny * a.mxp;
-  };
-  auto load = [&](long long t) {
-    int kx0;
-    const C *base = tile_base(t, kx0);
+  auto load = [&](long long t) {  // unconditional loads at clamped positions
+    const C *base = comp_base + t * npts;
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-      const int f = threadIdx.x + j * FFT_THREADS;
-      const int col = f % W, y = f / W;
-      C v;
-      v.x = 0;
-      v.y = 0;
-      if (f < npts && kx0 + col < a.mx) v = base[(long long)y * a.mxp + kx0 + col];
-      pre[j] = v;
-    }
+    for (int j = 0; j < PPT; ++j) pre[j] = base[min((int)threadIdx.x + j * NT, npts - 1)];
   };
   long long t = blockIdx.x;
-  const long long per_comp = (long long)ntx * a.nz;
-  (void)ntiles;
   if (t < per_comp) load(t);
   for (; t < per_comp; t += gridDim.x) {
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-      const int f = threadIdx.x + j * FFT_THREADS;
+      const int f = threadIdx.x + j * NT;
       if (f < npts) buf[f] = pre[j];
     }
     __syncthreads();
     if (t + gridDim.x < per_comp) load(t + gridDim.x);
-    lds_fft<Real, INV>(buf, a.plan, W, W, 1, tw, 1, false);
-    int kx0;
-    C *base = tile_base(t, kx0);
-    for (int f = threadIdx.x; f < npts; f += FFT_THREADS) {
-      const int col = f % W, y = f / W;
-      if (kx0 + col < a.mx) base[(long long)y * a.mxp + kx0 + col] = buf[f];
+    lds_fft<Real, INV, PPT, NT>(buf, a.plan, TW, TW, 1, tw, 1, false);
+    C *base = comp_base + t * npts;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int f = threadIdx.x + j * NT;
+      if (f < npts) base[f] = buf[f];
     }
     __syncthreads();
   }
@@ -591,8 +608,7 @@ struct GArgs {
   AxisTables tx, ty, tz;  // Fourier tables of K_ref
   double lam, mu;         // reference Lame constants
   double invN;            // 1 / N (normalisation of the unnormalised transforms)
-  int dim, mx, mxp, ny, nz;
-  int W;                  // x bins per tile
+  int dim, mx, ntx, ny, nz;
   int check_done;
   long long cs;           // bytes between the cells of a batch (cell = blockIdx.z)
 };
@@ -660,158 +676,57 @@ __device__ __forceinline__ void green2(const double (&A)[2], const double (&B)[2
   v[1].y = g01 * y0 + g11 * y1;
 }
 
-// Points per thread and per component of the last-axis pass: tiles of L x W
-// with L * W <= GPT * FFT_THREADS (FP64 tiles are half as wide, so that the d
-// components of a tile fit the LDS of three blocks per CU).
-template <typename Real>
-struct GreenPt {
-  static constexpr int value = sizeof(Real) == 8 ? 4 : 8;
-};
-
-// Last axis, LDS-resident form (FP64 path): forward C2C, Green multiply,
-// inverse C2C for every component of a tile of W x bins (3D: at one ky; 2D:
-// the whole y axis).  The d components of the tile sit in LDS side by side (point row t holds d * W values, component
-// major), so one Stockham transform covers all d * W lines.  Blocks are
-// persistent over the tiles of their cell, taken in an XCD-aware order so
-// that neighbouring tiles (which share cache lines) run under one L2; the
-// loads of the next tile are in flight in registers while the current one is
-// transformed.
-template <typename Real, int DIM>
-__global__ void __launch_bounds__(FFT_THREADS) k_green_lds(GArgs<Real> a) {
-  using C = typename CxT<Real>::T;
-  constexpr int PPT = GreenPt<Real>::value;
-  C *const spec = cshift(a.spec, blockIdx.z, a.cs);  // a local (see cshift)
-  if (a.check_done && cshift(a.st, blockIdx.z, a.cs)->done) return;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  C *tw = reinterpret_cast<C *>(smem_raw);
-  const int L = DIM == 3 ? a.nz : a.ny;
-  C *buf = tw + L;  // [L][DIM][W]
-  load_twiddles<Real>(tw, a.tw, L);
-  const int W = a.W;
-  const int DW = DIM * W;
-  const int ntx = (a.mx + W - 1) / W;
-  const long long ntiles = (long long)ntx * (DIM == 3 ? a.ny : 1);
-  const long long comp_stride = (long long)a.nz * a.ny * a.mxp;
-  const long long axis_stride = DIM == 3 ? (long long)a.ny * a.mxp : (long long)a.mxp;
-  const int npts = L * W;  // per component
-  auto tile_base = [&](long long t, int &kx0, int &ky) {
-    kx0 = (int)(t % ntx) * W;
-    ky = (int)(t / ntx);
-    return spec + (DIM == 3 ? (long long)ky * a.mxp : 0) + kx0;
-  };
-  C pre[DIM][PPT];
-  auto load = [&](long long t) {
-    int kx0, ky;
-    const C *base = tile_base(t, kx0, ky);
-#pragma unroll
-    for (int c = 0; c < DIM; ++c)
-#pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        const int f = threadIdx.x + j * FFT_THREADS;
-        const int col = f % W, z = f / W;
-        C v;
-        v.x = 0;
-        v.y = 0;
-        if (f < npts && kx0 + col < a.mx) v = base[c * comp_stride + (long long)z * axis_stride + col];
-        pre[c][j] = v;
-      }
-  };
-  const long long G = gridDim.x;
-  long long t = xcd_logical_block(blockIdx.x, (int)G);
-  if (t < ntiles) load(t);
-  for (; t < ntiles; t += G) {
-    int kx0, ky;
-    C *base = tile_base(t, kx0, ky);
-#pragma unroll
-    for (int c = 0; c < DIM; ++c)
-#pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        const int f = threadIdx.x + j * FFT_THREADS;
-        if (f < npts) buf[(f / W) * DW + c * W + f % W] = pre[c][j];
-      }
-    __syncthreads();
-    if (t + G < ntiles) load(t + G);
-    lds_fft<Real, false, DIM * PPT>(buf, a.plan, DW, DW, 1, tw, 1, false);
-    // Green multiply, frequency by frequency
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-      const int f = threadIdx.x + j * FFT_THREADS;
-      if (f < npts) {
-        const int col = f % W, z = f / W;
-        const int kx = min(kx0 + col, a.mx - 1);
-        C *row = buf + z * DW + col;
-        if (DIM == 3) {
-          const double A[3] = {a.tx.a[kx], a.ty.a[ky], a.tz.a[z]};
-          const double B[3] = {a.tx.b[kx], a.ty.b[ky], a.tz.b[z]};
-          const double S[3] = {a.tx.s[kx], a.ty.s[ky], a.tz.s[z]};
-          C v[3] = {row[0], row[W], row[2 * W]};
-          green3(A, B, S, a.lam, a.mu, a.invN, kx == 0 && ky == 0 && z == 0, v);
-          row[0] = v[0];
-          row[W] = v[1];
-          row[2 * W] = v[2];
-        } else {
-          const double A[2] = {a.tx.a[kx], a.ty.a[z]};
-          const double B[2] = {a.tx.b[kx], a.ty.b[z]};
-          const double S[2] = {a.tx.s[kx], a.ty.s[z]};
-          C v[2] = {row[0], row[W]};
-          green2(A, B, S, a.lam, a.mu, a.invN, kx == 0 && z == 0, v);
-          row[0] = v[0];
-          row[W] = v[1];
-        }
-      }
-    }
-    __syncthreads();
-    lds_fft<Real, true, DIM * PPT>(buf, a.plan, DW, DW, 1, tw, 1, false);
-#pragma unroll
-    for (int c = 0; c < DIM; ++c)
-#pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        const int f = threadIdx.x + j * FFT_THREADS;
-        const int col = f % W, z = f / W;
-        if (f < npts && kx0 + col < a.mx)
-          base[c * comp_stride + (long long)z * axis_stride + col] = buf[z * DW + c * W + col];
-      }
-    __syncthreads();
-  }
-}
-
 // Last axis: forward C2C, Green multiply, inverse C2C for every component of
-// a tile of W x bins (3D: at one ky; 2D: the whole y axis), one tile per
-// block, the transformed components held in registers (FP32 path).
-template <typename Real, int DIM>
-__global__ void __launch_bounds__(FFT_THREADS) k_green_axis(GArgs<Real> a) {
+// one tile: an x-tile (TW bins) at KY adjacent ky rows along z (3D; the KY *
+// TW complex values at one z are one contiguous 128-byte line for KY = 2), or
+// an x-tile along y (2D, KY = 1).  The transformed components stay in
+// registers for the Green multiply; the next component's loads are in flight
+// while the current one is transformed.  L * KY * TW <= MaxPt * NT.
+template <typename Real, int DIM, int KY, int NT>
+__global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
   using C = typename CxT<Real>::T;
+  constexpr int PPT = MaxPt<Real>::value;
+  constexpr int TW = TileW<Real>::value;
+  constexpr int LN = KY * TW;  // lines of the tile
   C *const spec = cshift(a.spec, blockIdx.z, a.cs);  // a local (see cshift)
   if (a.check_done && cshift(a.st, blockIdx.z, a.cs)->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   const int L = DIM == 3 ? a.nz : a.ny;
-  C *buf = tw + L;
+  C *buf = tw + L;  // [L][LN]
   load_twiddles<Real>(tw, a.tw, L);
-  const int W = a.W;
-  const int kx0 = blockIdx.x * W;
-  const int ky = DIM == 3 ? blockIdx.y : 0;
-  // line (kx, ky) along the last axis: component c, position t
-  const long long comp_stride = (long long)a.nz * a.ny * a.mxp;
-  const long long axis_stride = DIM == 3 ? (long long)a.ny * a.mxp : (long long)a.mxp;
-  C *base = spec + (DIM == 3 ? (long long)ky * a.mxp : 0) + kx0;
-  constexpr int PPT = MaxPt<Real>::value;  // points per thread kept across components
-  C stash[DIM][PPT];
-  const int npts = L * W;
-  for (int c = 0; c < DIM; ++c) {
-    for (int f = threadIdx.x; f < npts; f += FFT_THREADS) {
-      const int col = f % W, t = f / W;
-      C v;
-      v.x = 0;
-      v.y = 0;
-      if (kx0 + col < a.mx) v = base[c * comp_stride + (long long)t * axis_stride + col];
-      buf[f] = v;
-    }
-    __syncthreads();
-    lds_fft<Real, false>(buf, a.plan, W, W, 1, tw, 1, false);
+  const int kt = blockIdx.x % a.ntx;
+  const int ky0 = DIM == 3 ? (int)(blockIdx.x / a.ntx) * KY : 0;
+  // element (position t along the axis, line l) of component c:
+  //   base[c * comp_stride + t * axis_stride + l]
+  const long long comp_stride = (long long)a.nz * a.ntx * a.ny * TW;
+  const long long axis_stride = DIM == 3 ? (long long)a.ntx * a.ny * TW : TW;
+  C *const base = spec + (DIM == 3 ? ((long long)kt * a.ny + ky0) * TW : (long long)kt * a.ny * TW);
+  const int npts = L * LN;
+  C pre[PPT];
+  auto load = [&](int c) {  // unconditional loads at clamped positions
+    const C *bc = base + c * comp_stride;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-      const int f = threadIdx.x + j * FFT_THREADS;
+      const int f = min((int)threadIdx.x + j * NT, npts - 1);
+      pre[j] = bc[(long long)(f / LN) * axis_stride + f % LN];
+    }
+  };
+  C stash[DIM][PPT];
+  load(0);
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int f = threadIdx.x + j * NT;
+      if (f < npts) buf[f] = pre[j];
+    }
+    __syncthreads();
+    if (c + 1 < DIM) load(c + 1);
+    lds_fft<Real, false, PPT, NT>(buf, a.plan, LN, LN, 1, tw, 1, false);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int f = threadIdx.x + j * NT;
       if (f < npts) stash[c][j] = buf[f];
     }
     __syncthreads();
@@ -819,11 +734,12 @@ __global__ void __launch_bounds__(FFT_THREADS) k_green_axis(GArgs<Real> a) {
   // Green multiply on the points this thread holds
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
-    const int f = threadIdx.x + j * FFT_THREADS;
+    const int f = threadIdx.x + j * NT;
     if (f < npts) {
-      const int col = f % W, t = f / W;
-      const int kx = min(kx0 + col, a.mx - 1);
-      if (DIM == 3) {
+      const int t = f / LN, l = f % LN;
+      const int kx = min(kt * TW + l % TW, a.mx - 1);
+      if constexpr (DIM == 3) {
+        const int ky = ky0 + l / TW;
         const double A[3] = {a.tx.a[kx], a.ty.a[ky], a.tz.a[t]};
         const double B[3] = {a.tx.b[kx], a.ty.b[ky], a.tz.b[t]};
         const double S[3] = {a.tx.s[kx], a.ty.s[ky], a.tz.s[t]};
@@ -840,17 +756,20 @@ __global__ void __launch_bounds__(FFT_THREADS) k_green_axis(GArgs<Real> a) {
       }
     }
   }
+#pragma unroll
   for (int c = 0; c < DIM; ++c) {
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-      const int f = threadIdx.x + j * FFT_THREADS;
+      const int f = threadIdx.x + j * NT;
       if (f < npts) buf[f] = stash[c][j];
     }
     __syncthreads();
-    lds_fft<Real, true>(buf, a.plan, W, W, 1, tw, 1, false);
-    for (int f = threadIdx.x; f < npts; f += FFT_THREADS) {
-      const int col = f % W, t = f / W;
-      if (kx0 + col < a.mx) base[c * comp_stride + (long long)t * axis_stride + col] = buf[f];
+    lds_fft<Real, true, PPT, NT>(buf, a.plan, LN, LN, 1, tw, 1, false);
+    C *bc = base + c * comp_stride;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int f = threadIdx.x + j * NT;
+      if (f < npts) bc[(long long)(f / LN) * axis_stride + f % LN] = buf[f];
     }
     __syncthreads();
   }

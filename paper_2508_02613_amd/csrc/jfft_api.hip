@@ -100,7 +100,6 @@ struct PcgBufs {
 struct Tunables {
   int tz = 32;          // z planes per stiffness block (3D)
   int ygrid = 2048;     // persistent blocks of the y pass (all components and cells)
-  int ggrid = 1024;     // persistent blocks of the last-axis Green pass (all cells)
   int graph_iters = 0;  // iterations per captured graph (0: launch kernels directly)
 };
 
@@ -261,23 +260,21 @@ struct Layout {
 };
 
 template <typename Real>
-int x_rows_per_block(int m) {
-  return std::max(1, std::min(64, MaxPt<Real>::value * FFT_THREADS / std::max(1, m)));
+int x_rows_per_block(int m) {  // a power of two (tile-major index math uses shifts)
+  const int cap = std::max(1, std::min(64, MaxPt<Real>::value * FFT_THREADS / std::max(1, m)));
+  int rb = 1;
+  while (rb * 2 <= cap) rb *= 2;
+  return rb;
 }
 
-// x bins per tile of a strided pass over an axis of length L: 128-byte row
-// segments (8 double or 16 float complex bins), fewer for long axes
+// x-tiles per half-spectrum row and complex values per padded row
 template <typename Real>
-int tile_width(int L) {
-  const int w = 128 / (int)sizeof(typename CxT<Real>::T);
-  return std::max(1, std::min(w, MaxPt<Real>::value * FFT_THREADS / L));
+int ntx_of(const jfft_cell_s *c) {
+  return (c->g.mx + TileW<Real>::value - 1) / TileW<Real>::value;
 }
-
-// the same for the last-axis pass, whose tiles hold all d components in LDS
 template <typename Real>
-int green_tile_width(int L) {
-  const int w = 128 / (int)sizeof(typename CxT<Real>::T);
-  return std::max(1, std::min(w, GreenPt<Real>::value * FFT_THREADS / L));
+long long spec_row(const jfft_cell_s *c) {
+  return (long long)ntx_of<Real>(c) * TileW<Real>::value;
 }
 
 bool useJ(const jfft_cell_s *c) { return c->pc == JFFT_PC_JACOBI || c->pc == JFFT_PC_GREEN_JACOBI; }
@@ -289,7 +286,9 @@ size_t layout_workspace(jfft_cell_s *c, unsigned char *base) {
   const long long N = c->g.N;
   const int d = c->dim;
   const long long nd = (long long)d * N;
-  const long long nspec = (long long)d * c->g.nz * c->g.ny * c->g.mxp;
+  // tile-major half spectra: d * nz * ny * ntx * TW complex per precision
+  const long long nspec64 = (long long)d * c->g.nz * c->g.ny * spec_row<double>(c);
+  const long long nspec32 = (long long)d * c->g.nz * c->g.ny * spec_row<float>(c);
   Layout L;
   auto put = [&](auto *&ptr, size_t bytes) {
     size_t o = L.take(bytes);
@@ -305,7 +304,7 @@ size_t layout_workspace(jfft_cell_s *c, unsigned char *base) {
   put(c->p[1], sizeof(double) * nd);
   put(c->diag, sizeof(double) * nd);
   if (useJ(c)) put(c->Jh, sizeof(double) * nd);
-  if (useG(c)) put(c->spec, sizeof(double2) * nspec);
+  if (useG(c)) put(c->spec, sizeof(double2) * nspec64);
   if (c->prec == JFFT_MIXED) {
     put(c->E32, sizeof(float) * N);
     if (useJ(c)) put(c->Jh32, sizeof(float) * nd);
@@ -315,7 +314,7 @@ size_t layout_workspace(jfft_cell_s *c, unsigned char *base) {
     put(c->p32[0], sizeof(float) * nd);
     put(c->p32[1], sizeof(float) * nd);
     put(c->c32, sizeof(float) * nd);
-    if (useG(c)) put(c->spec32, sizeof(float2) * nspec);
+    if (useG(c)) put(c->spec32, sizeof(float2) * nspec32);
   }
   put(c->F, sizeof(double) * 24);
   put(c->macro, sizeof(double) * 8);
@@ -378,18 +377,32 @@ jfft_status upload_tables(jfft_cell_s *c) {
 }
 
 // Kernels that may need more than 64 KiB of dynamic LDS (512-point axes in FP64).
+template <typename K>
+void allow_big_lds(K *kernel) {
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+template <typename Real>
+void allow_big_lds_all() {
+  allow_big_lds(k_ypass<Real, false, 256>);
+  allow_big_lds(k_ypass<Real, true, 256>);
+  allow_big_lds(k_ypass<Real, false, 512>);
+  allow_big_lds(k_ypass<Real, true, 512>);
+  allow_big_lds(k_green_axis<Real, 3, 2, 256>);
+  allow_big_lds(k_green_axis<Real, 3, 2, 512>);
+  allow_big_lds(k_green_axis<Real, 3, 1, 256>);
+  allow_big_lds(k_green_axis<Real, 3, 1, 512>);
+  allow_big_lds(k_green_axis<Real, 2, 1, 256>);
+  allow_big_lds(k_green_axis<Real, 2, 1, 512>);
+}
+
+// Kernels that may need more than 64 KiB of dynamic LDS (512-point axes).
 void set_smem_attributes() {
   static std::once_flag once;
   std::call_once(once, [] {
-    const int big = 160 * 1024;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_ypass<double, false>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_ypass<double, true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_green_lds<double, 3>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_green_lds<double, 2>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    allow_big_lds_all<double>();
+    allow_big_lds_all<float>();
   });
 }
 
@@ -471,9 +484,12 @@ XArgs<Real> x_args(jfft_cell_s *c, bool check_done) {
   a.plan = c->plan_x;
   a.nx = c->g.nx;
   a.mx = c->g.mx;
-  a.mxp = c->g.mxp;
+  a.ntx = ntx_of<Real>(c);
+  a.ny = c->g.ny;
   a.nrows = (long long)c->dim * c->g.ny * c->g.nz;
   a.rows_per_block = x_rows_per_block<Real>(c->g.nx / 2);
+  a.log2_rb = 0;
+  while ((1 << a.log2_rb) < a.rows_per_block) ++a.log2_rb;
   a.check_done = check_done ? 1 : 0;
   a.cs = c->cs;
   return a;
@@ -533,6 +549,12 @@ jfft_status launch_xinv(jfft_cell_s *c, const Real *r, const Real *Jh,
   return JFFT_OK;
 }
 
+// threads for a tile of `pts` complex points (MaxPt points per thread)
+template <typename Real>
+int tile_threads(long long pts) {
+  return pts <= (long long)MaxPt<Real>::value * 256 ? 256 : 512;
+}
+
 template <typename Real>
 jfft_status launch_ypass(jfft_cell_s *c, typename CxT<Real>::T *spec, bool inv, bool check_done) {
   using C = typename CxT<Real>::T;
@@ -541,22 +563,25 @@ jfft_status launch_ypass(jfft_cell_s *c, typename CxT<Real>::T *spec, bool inv, 
   a.st = c->st;
   a.tw = c->tw[1];
   a.plan = c->plan_y;
-  a.mx = c->g.mx;
-  a.mxp = c->g.mxp;
+  a.ntx = ntx_of<Real>(c);
   a.ny = c->g.ny;
   a.nz = c->g.nz;
   a.check_done = check_done ? 1 : 0;
   a.cs = c->cs;
-  a.W = tile_width<Real>(c->g.ny);
   // persistent blocks, each walking tiles of one (component, cell)
-  const long long per_comp = (long long)((c->g.mx + a.W - 1) / a.W) * c->g.nz;
+  const long long per_comp = (long long)a.ntx * c->g.nz;
   const long long want = std::max<long long>(1, c->tun.ygrid / ((long long)c->dim * c->B));
   dim3 gr((unsigned)std::min(per_comp, want), c->dim, c->B);
-  const size_t smem = sizeof(C) * ((size_t)c->g.ny + (size_t)c->g.ny * a.W);
-  if (inv)
-    LAUNCH(c, KID_YINV, k_ypass<Real, true><<<gr, FFT_THREADS, smem, c->stream>>>(a));
-  else
-    LAUNCH(c, KID_YFWD, k_ypass<Real, false><<<gr, FFT_THREADS, smem, c->stream>>>(a));
+  const long long pts = (long long)c->g.ny * TileW<Real>::value;
+  const size_t smem = sizeof(C) * ((size_t)c->g.ny + (size_t)pts);
+  const int kid = inv ? KID_YINV : KID_YFWD;
+  if (tile_threads<Real>(pts) == 256) {
+    if (inv) LAUNCH(c, kid, k_ypass<Real, true, 256><<<gr, 256, smem, c->stream>>>(a));
+    else LAUNCH(c, kid, k_ypass<Real, false, 256><<<gr, 256, smem, c->stream>>>(a));
+  } else {
+    if (inv) LAUNCH(c, kid, k_ypass<Real, true, 512><<<gr, 512, smem, c->stream>>>(a));
+    else LAUNCH(c, kid, k_ypass<Real, false, 512><<<gr, 512, smem, c->stream>>>(a));
+  }
   return JFFT_OK;
 }
 
@@ -577,32 +602,38 @@ jfft_status launch_green(jfft_cell_s *c, typename CxT<Real>::T *spec, bool check
   a.invN = 1.0 / (double)c->g.N;
   a.dim = c->dim;
   a.mx = c->g.mx;
-  a.mxp = c->g.mxp;
+  a.ntx = ntx_of<Real>(c);
   a.ny = c->g.ny;
   a.nz = c->g.nz;
   a.check_done = check_done ? 1 : 0;
   a.cs = c->cs;
+  constexpr int TW = TileW<Real>::value;
   const int L = c->dim == 3 ? c->g.nz : c->g.ny;
-  if constexpr (sizeof(Real) == 8) {
-    // FP64: tiles with all components in LDS, persistent blocks
-    a.W = green_tile_width<Real>(L);
-    const long long ntiles = (long long)((c->g.mx + a.W - 1) / a.W) * (c->dim == 3 ? c->g.ny : 1);
-    const long long want = std::max<long long>(1, c->tun.ggrid / c->B);
-    dim3 gr((unsigned)std::min(ntiles, want), 1, c->B);
-    const size_t smem = sizeof(C) * ((size_t)L + (size_t)c->dim * L * a.W);
-    if (c->dim == 3)
-      LAUNCH(c, KID_GREEN, k_green_lds<Real, 3><<<gr, FFT_THREADS, smem, c->stream>>>(a));
+  if (c->dim == 3) {
+    // ky rows per tile for full 128-byte lines, while the tile fits 512 threads
+    const int KY = (long long)L * ZRows<Real>::value * TW <= (long long)MaxPt<Real>::value * 512
+                       ? ZRows<Real>::value
+                       : 1;
+    const long long pts = (long long)L * KY * TW;
+    const size_t smem = sizeof(C) * ((size_t)L + (size_t)pts);
+    dim3 gr((unsigned)(a.ntx * (c->g.ny / KY)), 1, c->B);
+    const int nt = tile_threads<Real>(pts);
+    if (KY == 2 && nt == 256)
+      LAUNCH(c, KID_GREEN, k_green_axis<Real, 3, 2, 256><<<gr, 256, smem, c->stream>>>(a));
+    else if (KY == 2)
+      LAUNCH(c, KID_GREEN, k_green_axis<Real, 3, 2, 512><<<gr, 512, smem, c->stream>>>(a));
+    else if (nt == 256)
+      LAUNCH(c, KID_GREEN, k_green_axis<Real, 3, 1, 256><<<gr, 256, smem, c->stream>>>(a));
     else
-      LAUNCH(c, KID_GREEN, k_green_lds<Real, 2><<<gr, FFT_THREADS, smem, c->stream>>>(a));
+      LAUNCH(c, KID_GREEN, k_green_axis<Real, 3, 1, 512><<<gr, 512, smem, c->stream>>>(a));
   } else {
-    // FP32: one tile per block, components in registers
-    a.W = tile_width<Real>(L);
-    dim3 gr((c->g.mx + a.W - 1) / a.W, c->dim == 3 ? c->g.ny : 1, c->B);
-    const size_t smem = sizeof(C) * ((size_t)L + (size_t)L * a.W);
-    if (c->dim == 3)
-      LAUNCH(c, KID_GREEN, k_green_axis<Real, 3><<<gr, FFT_THREADS, smem, c->stream>>>(a));
+    const long long pts = (long long)L * TW;
+    const size_t smem = sizeof(C) * ((size_t)L + (size_t)pts);
+    dim3 gr((unsigned)a.ntx, 1, c->B);
+    if (tile_threads<Real>(pts) == 256)
+      LAUNCH(c, KID_GREEN, k_green_axis<Real, 2, 1, 256><<<gr, 256, smem, c->stream>>>(a));
     else
-      LAUNCH(c, KID_GREEN, k_green_axis<Real, 2><<<gr, FFT_THREADS, smem, c->stream>>>(a));
+      LAUNCH(c, KID_GREEN, k_green_axis<Real, 2, 1, 512><<<gr, 512, smem, c->stream>>>(a));
   }
   return JFFT_OK;
 }
@@ -985,7 +1016,6 @@ jfft_status create_impl(int dim, const int n[3], const double len[3], jfft_preci
   g.nz = c->n[2];
   g.N = (long long)g.nx * g.ny * g.nz;
   g.mx = g.nx / 2 + 1;
-  g.mxp = (g.mx + 15) / 16 * 16;  // rows of the half spectrum start on 128/256-byte boundaries
   double evol = 1.0;
   g.vol = 1.0;
   double hs[3];

@@ -90,7 +90,6 @@ struct GridDev {
   int nx, ny, nz;     // nz = 1 in 2D
   long long N;        // nodes = elements
   int mx;             // nx / 2 + 1 half-spectrum entries per x row
-  int mxp;            // row stride of the half spectrum (complex entries)
   double ihx, ihy, ihz;  // 1 / h
   double w;           // Gauss weight = element volume / 2^d
   double vol;         // |Y|
