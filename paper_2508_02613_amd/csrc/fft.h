@@ -178,23 +178,35 @@ struct Dft<Real, 5, INV> {
 // L / R, current sub-transform length p (product of earlier radices).
 // tw[j * tws] = exp(-2 pi i j / L).  All threads read their butterflies,
 // synchronise, then write, so one buffer suffices.
-// NPT bounds the points per thread (L * W <= NPT * NT, NT = threads).
+// NPT bounds the points per thread (L * W <= NPT * NT, NT = threads).  mdv
+// and pdv divide by m = L / R and by p; the divisions by W (tile lines, a
+// constant where the caller's W is one) stay plain.
 template <typename Real, int R, bool INV, int NPT, int NT>
 __device__ __forceinline__ void stockham_stage(typename CxT<Real>::T *buf, int L, int W, int p,
                                                int sp, int sc, const typename CxT<Real>::T *tw,
-                                               int tws, bool i_fastest) {
+                                               int tws, bool i_fastest, const FastDiv &mdv,
+                                               const FastDiv &pdv) {
   using C = typename CxT<Real>::T;
   constexpr int MB = (NPT + R - 1) / R;
-  const int m = L / R;
+  const int m = mdv.d;
   const int nb = m * W;
   const int step = L / (p * R);
   C v[MB][R];
+  int iv[MB], cv[MB];
 #pragma unroll
   for (int b = 0; b < MB; ++b) {
     const int f = threadIdx.x + b * NT;
+    int i, c;
+    if (i_fastest) {
+      c = mdv.div(f);
+      i = f - c * m;
+    } else {
+      i = f / W;
+      c = f - i * W;
+    }
+    iv[b] = i;
+    cv[b] = c;
     if (f < nb) {
-      const int i = i_fastest ? f % m : f / W;
-      const int c = i_fastest ? f / m : f % W;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[b][r] = buf[(i + r * m) * sp + c * sc];
     }
@@ -204,9 +216,9 @@ __device__ __forceinline__ void stockham_stage(typename CxT<Real>::T *buf, int L
   for (int b = 0; b < MB; ++b) {
     const int f = threadIdx.x + b * NT;
     if (f < nb) {
-      const int i = i_fastest ? f % m : f / W;
-      const int c = i_fastest ? f / m : f % W;
-      const int k = i % p;
+      const int i = iv[b], c = cv[b];
+      const int ip = pdv.div(i);
+      const int k = i - ip * p;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
         C t = tw[(r * k * step) * tws];
@@ -214,7 +226,7 @@ __device__ __forceinline__ void stockham_stage(typename CxT<Real>::T *buf, int L
         v[b][r] = cmul(v[b][r], t);
       }
       Dft<Real, R, INV>::run(v[b]);
-      const int j = (i / p) * p * R + k;
+      const int j = ip * p * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[(j + r * p) * sp + c * sc] = v[b][r];
     }
@@ -229,11 +241,11 @@ __device__ void lds_fft(typename CxT<Real>::T *buf, const FftPlan &pl, int W, in
   for (int s = 0; s < pl.nst; ++s) {
     const int R = pl.radix[s];
     switch (R) {
-      case 8: stockham_stage<Real, 8, INV, NPT, NT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
-      case 4: stockham_stage<Real, 4, INV, NPT, NT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
-      case 2: stockham_stage<Real, 2, INV, NPT, NT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
-      case 3: stockham_stage<Real, 3, INV, NPT, NT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
-      case 5: stockham_stage<Real, 5, INV, NPT, NT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest); break;
+      case 8: stockham_stage<Real, 8, INV, NPT, NT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest, pl.mdiv[s], pl.pdiv[s]); break;
+      case 4: stockham_stage<Real, 4, INV, NPT, NT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest, pl.mdiv[s], pl.pdiv[s]); break;
+      case 2: stockham_stage<Real, 2, INV, NPT, NT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest, pl.mdiv[s], pl.pdiv[s]); break;
+      case 3: stockham_stage<Real, 3, INV, NPT, NT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest, pl.mdiv[s], pl.pdiv[s]); break;
+      case 5: stockham_stage<Real, 5, INV, NPT, NT>(buf, pl.L, W, p, sp, sc, tw, tws, i_fastest, pl.mdiv[s], pl.pdiv[s]); break;
       default: break;
     }
     p *= R;
@@ -281,6 +293,8 @@ struct XArgs {
   long long nrows;     // d * ny * nz rows per cell
   int rows_per_block;  // RB, a power of two
   int log2_rb;
+  FastDiv dm;          // m = nx / 2
+  FastDiv dhalf;       // m / 2 + 1 slot pairs per row
   int check_done;
   long long cs;        // bytes between the cells of a batch (cell = blockIdx.y)
 };
@@ -377,7 +391,8 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
       z.x = v.x;
       z.y = v.y;
     }
-    buf[(f / m) * sc + f % m] = z;
+    const int fr = a.dm.div(f);
+    buf[fr * sc + (f - fr * m)] = z;
   }
   __syncthreads();
   lds_fft<Real, false>(buf, a.plan, RB, 1, sc, tw, 2, true);
@@ -492,7 +507,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
   // those two slots, so no barrier is needed inside the loop.
   const int half = m / 2 + 1;
   for (int f = threadIdx.x; f < RB * half; f += FFT_THREADS) {
-    const int row = f / half, k = f % half;
+    const int row = a.dhalf.div(f), k = f - row * half;
     const C xa = buf[row * sc + k];
     const C xb = buf[row * sc + (m - k)];
     C zk[2];
@@ -526,7 +541,8 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
     const int f = threadIdx.x + j * FFT_THREADS;
     const long long off = base + f;
     if (f >= tot || off >= lim) continue;
-    const C z = buf[(f / m) * sc + f % m];
+    const int fr = a.dm.div(f);
+    const C z = buf[fr * sc + (f - fr * m)];
     R2 t;
     t.x = z.x;
     t.y = z.y;

@@ -86,6 +86,12 @@ bool factor_plan(int L, FftPlan &pl) {
     }
     if (!ok) return false;
   }
+  int p = 1;
+  for (int s = 0; s < pl.nst; ++s) {
+    pl.mdiv[s] = FastDiv(L / pl.radix[s]);
+    pl.pdiv[s] = FastDiv(p);
+    p *= pl.radix[s];
+  }
   return true;
 }
 
@@ -490,6 +496,8 @@ XArgs<Real> x_args(jfft_cell_s *c, bool check_done) {
   a.rows_per_block = x_rows_per_block<Real>(c->g.nx / 2);
   a.log2_rb = 0;
   while ((1 << a.log2_rb) < a.rows_per_block) ++a.log2_rb;
+  a.dm = FastDiv(c->g.nx / 2);
+  a.dhalf = FastDiv(c->g.nx / 4 + 1);
   a.check_done = check_done ? 1 : 0;
   a.cs = c->cs;
   return a;

@@ -77,11 +77,37 @@ struct AxisTables {
   const double *a, *b, *s;
 };
 
+// Division by a run-time constant d >= 1 through a multiply and a shift
+// (Granlund and Montgomery's method for invariant divisors): with
+// l = ceil(log2 d) and M = floor(2^32 (2^l - d) / d) + 1,
+// floor(n / d) = (umulhi(n, M) + n) >> l for 0 <= n < 2^31.  Integer division
+// by a run-time value is a long instruction sequence on the GPU; the FFT
+// index math divides by stage lengths, sub-transform sizes and row lengths.
+struct FastDiv {
+  unsigned mul;
+  int shift;
+  int d;
+  __host__ __device__ FastDiv() : mul(1), shift(0), d(1) {}
+  __host__ explicit FastDiv(int divisor) : d(divisor) {
+    shift = 0;
+    while ((1LL << shift) < divisor) ++shift;
+    mul = (unsigned)(((1ULL << 32) * ((1ULL << shift) - (unsigned long long)divisor)) /
+                         (unsigned long long)divisor +
+                     1ULL);
+  }
+  __device__ __forceinline__ int div(int n) const {
+    return (int)((__umulhi((unsigned)n, mul) + (unsigned)n) >> shift);
+  }
+  __device__ __forceinline__ int mod(int n) const { return n - div(n) * d; }
+};
+
 constexpr int kMaxStages = 12;
 struct FftPlan {
   int L;      // transform length
   int nst;    // number of Stockham stages
   int radix[kMaxStages];
+  FastDiv mdiv[kMaxStages];  // L / radix of each stage
+  FastDiv pdiv[kMaxStages];  // product of the earlier radices
 };
 
 // Geometry and constants passed by value to kernels.
