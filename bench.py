@@ -257,7 +257,8 @@ def run_simp2d(args):
     """Batch of 2D plane-strain SIMP cells of uneven sizes: sides uniform from
     {64, 128, 256, 512}, E = rho^3 with rho in [1e-3, 1] from blurred noise
     (4 px), nu 0.3, macro strain cycling e11, e22, e12; groups per size on
-    their own streams, mixed precision, 8 PCG iterations per captured graph.
+    their own streams, mixed precision, launch parameters and graph depth per
+    size from the autotuner (tuned during the warm-up step).
     Baseline: the same cells one at a time with the FP64 solver."""
     import torch
 
@@ -270,13 +271,13 @@ def run_simp2d(args):
     fields = [ji.simp_field(int(n), seed=args.seed * 7919 + i) for i, n in enumerate(sizes)]
     macros = [ji.unit_macro_strain(2, i % 3) for i in range(args.cells)]
     dofs = np.array([2 * int(n) ** 2 for n in sizes])
-    for _ in range(args.warmup):
-        solve_cells(fields, macros, tol=1e-8, precision=pkg.MIXED, graph_iterations=8,
-                    want_u=False)
+    # launch parameters per size from the autotuner (measured during warm-up)
+    for _ in range(max(1, args.warmup)):
+        solve_cells(fields, macros, tol=1e-8, precision=pkg.MIXED, want_u=False, autotune=True)
     walls, its = [], None
     for _ in range(args.steps):
-        res, wall = solve_cells(fields, macros, tol=1e-8, precision=pkg.MIXED,
-                                graph_iterations=8, want_u=False)
+        res, wall = solve_cells(fields, macros, tol=1e-8, precision=pkg.MIXED, want_u=False,
+                                autotune=True)
         walls.append(wall)
         its = np.array([r["report"].iters for r in res])
         ok = all(r["report"].status == "ok" for r in res)
@@ -302,8 +303,8 @@ def run_simp2d(args):
         "config": {"workload": (f"{args.cells} 2D plane-strain cells, sides uniform from "
                                 "{64,128,256,512}, SIMP E = rho^3, rho in [1e-3, 1] (blurred "
                                 "noise, 4 px), nu 0.3, one macro strain each, Green-Jacobi "
-                                "PCG to 1e-8, groups per size on concurrent streams, 8 "
-                                "iterations per HIP graph"),
+                                "PCG to 1e-8, groups per size on concurrent streams, "
+                                "autotuned launch parameters and graph depth per size"),
                    "cells": args.cells, "total_dofs": int(dofs.sum())},
         "cells_per_s": args.cells / wall,
         "all_ok": ok, "max_rel_res_true": worst,

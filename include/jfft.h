@@ -165,6 +165,21 @@ jfft_status jfft_solve_batch(jfft_cell_t cell, const double *macro_strains, doub
    capacity or of this setting; a new E field alone keeps it. */
 jfft_status jfft_set_graph_iterations(jfft_cell_t cell, int iterations);
 
+/* Launch parameters that do not change what is computed up to rounding:
+     tz:    z planes per block of the 3D stiffness kernel (2..nz; 2D ignores
+            it).  It sets how the p.q partial sums are grouped, so results
+            may differ in the last bits between settings;
+     ygrid: persistent blocks of the y FFT pass per launch (all components
+            and cells; 1..65535).
+   jfft_get_tunables reports the current values (defaults chosen from the
+   grid size at creation).  A change drops any captured graph. */
+typedef struct {
+  int tz;
+  int ygrid;
+} jfft_tunables;
+jfft_status jfft_set_tunables(jfft_cell_t cell, const jfft_tunables *t);
+jfft_status jfft_get_tunables(jfft_cell_t cell, jfft_tunables *t);
+
 /* Operators, for verification and composition (all FP64, device in/out
    [d][N], stream-ordered, no synchronisation):
    out = K in (eq. lin_system_exp, the current material). */

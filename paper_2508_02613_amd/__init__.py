@@ -34,6 +34,10 @@ _vp = C.c_void_p
 _dp = C.POINTER(C.c_double)
 
 
+class _Tunables(C.Structure):
+    _fields_ = [("tz", C.c_int), ("ygrid", C.c_int)]
+
+
 class _Report(C.Structure):
     _fields_ = [("iters", C.c_int), ("outer", C.c_int), ("status", C.c_int),
                 ("rel_res", C.c_double), ("rel_res_true", C.c_double),
@@ -56,6 +60,8 @@ _SIGS = {
     "jfft_solve_batch": (C.c_int, [_vp, _dp, C.c_double, C.c_int, _vp, _vp, _vp, _dp,
                                    C.POINTER(_Report)]),
     "jfft_set_graph_iterations": (C.c_int, [_vp, C.c_int]),
+    "jfft_set_tunables": (C.c_int, [_vp, C.POINTER(_Tunables)]),
+    "jfft_get_tunables": (C.c_int, [_vp, C.POINTER(_Tunables)]),
     "jfft_apply_stiffness": (C.c_int, [_vp, _vp, _vp]),
     "jfft_apply_precond": (C.c_int, [_vp, _vp, _vp]),
     "jfft_assemble_rhs": (C.c_int, [_vp, _dp, _vp]),
@@ -260,6 +266,17 @@ class Cell:
         if st not in (0, 4, 5):
             _check(st)
         return u, sbar, [_report(r) for r in reps], sig
+
+    def tunables(self):
+        t = _Tunables()
+        _check(self._lib.jfft_get_tunables(self._h, C.byref(t)))
+        return {"tz": int(t.tz), "ygrid": int(t.ygrid)}
+
+    def set_tunables(self, tz=None, ygrid=None):
+        cur = self.tunables()
+        t = _Tunables(int(tz if tz is not None else cur["tz"]),
+                      int(ygrid if ygrid is not None else cur["ygrid"]))
+        _check(self._lib.jfft_set_tunables(self._h, C.byref(t)))
 
     def set_graph_iterations(self, iterations):
         """0: direct launches; even k in [2, 64]: replay k PCG iterations as one HIP graph."""

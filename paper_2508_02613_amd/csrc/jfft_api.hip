@@ -349,7 +349,7 @@ long long max_partials(jfft_cell_s *c) {
   const GridDev &g = c->g;
   long long mx = 4 * 1024;  // vector kernels
   const long long tiles = (long long)((g.nx + TILE - 1) / TILE) * ((g.ny + TILE - 1) / TILE);
-  mx = std::max(mx, tiles * ((g.nz + 4 - 1) / 4));  // smallest z chunk used
+  mx = std::max(mx, tiles * ((g.nz + 2 - 1) / 2));  // smallest z chunk allowed (tz >= 2)
   const int m = g.nx / 2;
   const long long rows = (long long)c->dim * g.ny * g.nz;
   mx = std::max(mx, (rows + x_rows_per_block<double>(m) - 1) / x_rows_per_block<double>(m));
@@ -1212,6 +1212,30 @@ jfft_status jfft_set_graph_iterations(jfft_cell_t c, int iterations) {
     return fail(JFFT_E_INVALID, "graph replay needs a stream other than the legacy default stream");
   c->tun.graph_iters = iterations;
   c->drop_graphs();
+  return JFFT_OK;
+}
+
+jfft_status jfft_set_tunables(jfft_cell_t c, const jfft_tunables *t) {
+  if (!c || !t) return fail(JFFT_E_INVALID, "NULL argument");
+  if (t->ygrid < 1 || t->ygrid > 65535) return fail(JFFT_E_INVALID, "ygrid must lie in [1, 65535]");
+  if (c->dim == 3) {
+    if (t->tz < std::min(2, c->g.nz) || t->tz > c->g.nz)
+      return fail(JFFT_E_INVALID, "tz must lie in [2, nz]");
+    const long long nbz = (c->g.nz + t->tz - 1) / t->tz;
+    const long long tiles = (long long)((c->g.nx + TILE - 1) / TILE) * ((c->g.ny + TILE - 1) / TILE);
+    if (nbz * c->B > 65535) return fail(JFFT_E_INVALID, "tz too small for this group (grid z-dimension)");
+    if (tiles * nbz > c->npart) return fail(JFFT_E_INVALID, "tz too small for the partial-sum buffer");
+    c->tun.tz = t->tz;
+  }
+  c->tun.ygrid = t->ygrid;
+  c->drop_graphs();
+  return JFFT_OK;
+}
+
+jfft_status jfft_get_tunables(jfft_cell_t c, jfft_tunables *t) {
+  if (!c || !t) return fail(JFFT_E_INVALID, "NULL argument");
+  t->tz = c->dim == 3 ? std::min(c->tun.tz, c->g.nz) : 1;
+  t->ygrid = c->tun.ygrid;
   return JFFT_OK;
 }
 

@@ -18,9 +18,10 @@ from . import FP64, PC_GREEN_JACOBI, Cell, _torch
 
 
 def solve_cells(fields, macros, nu=0.3, tol=1e-8, maxit=20000, precision=FP64,
-                pc=PC_GREEN_JACOBI, graph_iterations=0, want_u=True):
+                pc=PC_GREEN_JACOBI, graph_iterations=0, want_u=True, autotune=False):
     """Solve cell i with material fields[i] (numpy or torch, any shape per cell)
-    and macro strain macros[i].
+    and macro strain macros[i].  With autotune, each group takes the launch
+    parameters tune.autotune() measures (cached) for its shape and size.
 
     Returns a list of dicts {u (device tensor or None), sigma_bar, report} in
     input order, and the wall time of the solves (material set-up excluded).
@@ -35,7 +36,11 @@ def solve_cells(fields, macros, nu=0.3, tol=1e-8, maxit=20000, precision=FP64,
     for shape, idx in buckets.items():
         stream = torch.cuda.Stream()
         grp = Cell(shape, precision=precision, pc=pc, stream=stream, batch=len(idx))
-        if graph_iterations:
+        if autotune:
+            from . import tune
+
+            tune.apply(grp, tune.autotune(shape, batch=len(idx), precision=precision, pc=pc))
+        elif graph_iterations:
             grp.set_graph_iterations(graph_iterations)
         Es = torch.stack([torch.as_tensor(np.asarray(fields[i]), dtype=torch.float64)
                           for i in idx]).to(grp.device)

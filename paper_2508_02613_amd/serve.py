@@ -16,7 +16,10 @@ six solves, one per unit macro strain (Sec. 5).  The server
   start as soon as a worker and memory are free and their kernels overlap
   with the running ones;
 * merges requests of one grid shape that are already waiting into one group
-  launch (up to `max_merge` requests, 6 cells each).
+  launch (up to `max_merge` requests, 6 cells each);
+* optionally (autotune) gives each new handle the launch parameters that
+  tune.autotune() measured for its shape and size (tz per shape only, so
+  merging never changes a request's results).
 
 Each cell's results are bitwise independent of what else is in its group or
 on the device (reduction layouts depend on the cell shape only), so a request
@@ -73,8 +76,9 @@ def workspace_bytes(shape, precision, pc, batch) -> int:
 class HandlePool:
     """Warm group handles under a device-memory budget."""
 
-    def __init__(self, budget_bytes, precision, pc, graph_iterations, nu):
+    def __init__(self, budget_bytes, precision, pc, graph_iterations, nu, autotune=False):
         self.budget = int(budget_bytes)
+        self.autotune = autotune
         self.precision, self.pc, self.graph_iterations, self.nu = precision, pc, graph_iterations, nu
         self.cv = threading.Condition()
         self.free = {}       # key -> [Cell]
@@ -114,7 +118,12 @@ class HandlePool:
         shape, k = key
         cell = Cell(shape, precision=self.precision, pc=self.pc, stream=torch.cuda.Stream(),
                     batch=6 * k)
-        if self.graph_iterations:
+        if self.autotune:
+            from . import tune
+
+            tune.apply(cell, tune.autotune(shape, batch=6 * k, precision=self.precision,
+                                           pc=self.pc))
+        elif self.graph_iterations:
             cell.set_graph_iterations(self.graph_iterations)
         cell.key = key
         with self.cv:
@@ -138,11 +147,11 @@ class HandlePool:
 class Server:
     def __init__(self, workers=4, budget_bytes=64 << 30, precision=MIXED, pc=PC_GREEN_JACOBI,
                  tol=1e-8, maxit=20000, graph_iterations=8, nu=0.3, max_merge=4,
-                 merge_max_side=64):
+                 merge_max_side=64, autotune=False):
         self.workers = workers
         self.tol, self.maxit, self.nu = tol, maxit, nu
         self.max_merge, self.merge_max_side = max_merge, merge_max_side
-        self.pool = HandlePool(budget_bytes, precision, pc, graph_iterations, nu)
+        self.pool = HandlePool(budget_bytes, precision, pc, graph_iterations, nu, autotune)
         self.precision = precision
 
     def _solve(self, cell, reqs):

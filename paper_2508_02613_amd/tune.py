@@ -1,0 +1,145 @@
+"""Autotuner for the launch parameters of a cell group.
+
+Tuned by timing a fixed number of PCG iterations on a synthetic smooth
+material of the target shape:
+
+* tz, the z planes per block of the 3D stiffness kernel: it sets how the p.q
+  partial sums are grouped, so it is chosen per (grid shape, precision,
+  preconditioner) only, never per group size; a cell then gives bitwise the
+  same results alone and in any group, tuned or not, as long as the same
+  cache is used;
+* ygrid, the persistent blocks of the y FFT pass, and the number of PCG
+  iterations captured per HIP graph: these do not change what is computed and
+  are chosen per group size as well.
+
+Results are kept in a JSON cache (JFFT_TUNE_CACHE, default
+~/.cache/jfft_mi355x/tunables.json) so each configuration is measured once.
+The search is coordinate-wise (tz, then ygrid, then graph depth), each step
+keeping the best loop time.  Only marshalling happens here: the timed work
+runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import json
+import os
+import threading
+
+import numpy as np
+
+from . import MIXED, PC_GREEN_JACOBI, Cell, _torch
+
+_lock = threading.Lock()
+
+
+def cache_path() -> str:
+    return os.environ.get("JFFT_TUNE_CACHE") or os.path.join(
+        os.path.expanduser("~"), ".cache", "jfft_mi355x", "tunables.json")
+
+
+def _load():
+    try:
+        with open(cache_path()) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(data):
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _shape_key(shape, precision, pc):
+    return "x".join(str(int(s)) for s in shape) + f"|prec{int(precision)}|pc{int(pc)}"
+
+
+def _material(shape):
+    """Smooth synthetic modulus field (contrast about 1e3) for timing."""
+    rng = np.random.default_rng(12345)
+    g = np.zeros(shape)
+    axes = np.meshgrid(*[np.arange(n) / n for n in shape], indexing="ij")
+    for _ in range(4):
+        k = rng.integers(1, 3, size=len(shape))
+        ph = rng.uniform(0, 2 * np.pi)
+        g += np.cos(2 * np.pi * sum(kk * a for kk, a in zip(k, axes)) + ph)
+    g = (g - g.min()) / (g.max() - g.min())
+    return np.exp(np.log(1e3) * g)
+
+
+def _time_loop(cell, iters, macro):
+    """Device time of `iters` PCG iterations (second of two identical runs)."""
+    for _ in range(2):
+        _, _, reps, _ = cell.solve_batch(macro, tol=1e-14, maxit=iters)
+    return max(r.loop_ms for r in reps)
+
+
+def autotune(shape, batch=1, precision=MIXED, pc=PC_GREEN_JACOBI, iters=24, use_cache=True):
+    """Launch parameters for a group of `batch` cells of `shape`: returns
+    {"tz", "ygrid", "graph_iterations", "loop_ms_per_iteration"}."""
+    shape = tuple(int(s) for s in shape)
+    skey = _shape_key(shape, precision, pc)
+    gkey = f"{skey}|b{int(batch)}"
+    with _lock:
+        data = _load() if use_cache else {}
+        if gkey in data.get("groups", {}):
+            return dict(data["groups"][gkey])
+    torch = _torch()
+    dim = len(shape)
+    ds = dim * (dim + 1) // 2
+    cell = Cell(shape, precision=precision, pc=pc, stream=torch.cuda.Stream(), batch=batch)
+    try:
+        E = torch.from_numpy(_material(shape)).to(cell.device)
+        cell.set_material(E.unsqueeze(0).expand((batch,) + shape).contiguous(), nu=0.3)
+        macro = np.tile(np.eye(ds)[0], (batch, 1))
+        cur = cell.tunables()
+        best = None
+
+        def trial(tz, ygrid, graph):
+            nonlocal best
+            cell.set_tunables(tz=tz, ygrid=ygrid)
+            cell.set_graph_iterations(graph)
+            ms = _time_loop(cell, iters, macro) / iters
+            if best is None or ms < best[0]:
+                best = (ms, tz, ygrid, graph)
+            return ms
+
+        # tz: fixed per shape (shared by every group size), measured once
+        shape_tz = data.get("shapes", {}).get(skey) if use_cache else None
+        if dim == 3 and shape_tz is None:
+            nz = shape[0]
+            tzs = sorted({t for t in (4, 8, 16, 32, 64) if t <= nz} | {min(cur["tz"], nz)})
+            for tz in tzs:
+                trial(tz, cur["ygrid"], 0)
+            shape_tz = best[1]
+        elif shape_tz is None:
+            shape_tz = cur["tz"]
+        best = None
+        if dim == 3:
+            for yg in sorted({256, 512, 1024, 2048, 4096, cur["ygrid"]}):
+                trial(shape_tz, yg, 0)
+        else:  # no y pass in 2D (the Green pass runs along y)
+            trial(shape_tz, cur["ygrid"], 0)
+        yg = best[2]
+        for graph in (8, 16):
+            trial(shape_tz, yg, graph)
+        res = {"tz": int(shape_tz), "ygrid": int(best[2]), "graph_iterations": int(best[3]),
+               "loop_ms_per_iteration": float(best[0])}
+    finally:
+        cell.close()
+    with _lock:
+        data = _load() if use_cache else {}
+        data.setdefault("shapes", {})[skey] = res["tz"]
+        data.setdefault("groups", {})[gkey] = res
+        if use_cache:
+            _store(data)
+    return res
+
+
+def apply(cell, params):
+    """Apply autotune() results to a cell group."""
+    cell.set_tunables(tz=params["tz"], ygrid=params["ygrid"])
+    cell.set_graph_iterations(params["graph_iterations"])
