@@ -52,7 +52,8 @@ def test_served_results_equal_alone(precision, budget_handles):
     stats = srv.run(reqs, rate=None)
     srv.close()
     say(f"  {stats}")
-    assert stats["all_ok"] and stats["max_rel_res_true"] <= 1.5e-8
+    assert stats["all_ok"] and 0 < stats["max_rel_res_true"] <= 1.5e-8
+    assert all(r.rel_res_true > 0 for r in reqs)
     if budget_handles < 2:
         assert stats["handles_evicted"] > 0 or stats["handles_created"] <= 2
     for r in reqs:
