@@ -404,20 +404,14 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
     constexpr int TW = TileW<Real>::value;
     static_assert(TW == 8, "tile-major x-pass addressing assumes 8 bins per tile");
     constexpr int SP = XP + 2;  // RB * ntx * TW <= RB * (m + TW) <= SP * FFT_THREADS
-    const int tot = (a.ntx * TW) << a.log2_rb;
     const RowTiles<TW> rt(row0, a.ny, a.ntx);
-#pragma unroll
-    for (int j = 0; j < SP; ++j) {
-      const int f = threadIdx.x + j * FFT_THREADS;
-      const int w = f & (TW - 1), row = (f >> 3) & (RB - 1), kt = f >> (3 + a.log2_rb);
-      const int kx = kt * TW + w;
-      const long long g = row0 + row;
-      if (f >= tot || g >= a.nrows) continue;
+    // bin kx of a row: Z slots kx mod m and (m - kx) mod m (kx <= m)
+    auto split = [&](const C *zrow, int kx) {
       C X;
       X.x = 0;
       X.y = 0;
       if (kx < a.mx) {
-        const C zk = buf[row * sc + kx % m], zm = buf[row * sc + (m - kx) % m];
+        const C zk = zrow[kx == m ? 0 : kx], zm = zrow[kx == 0 ? 0 : m - kx];
         C sm, d;
         sm.x = (Real)0.5 * (zk.x + zm.x);
         sm.y = (Real)0.5 * (zk.y - zm.y);
@@ -427,7 +421,33 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
         X.x = sm.x + wd.y;
         X.y = sm.y - wd.x;
       }
-      spec[rt.offset(row, kt, w)] = X;
+      return X;
+    };
+    if (a.log2_rb <= 5) {
+      // RB <= 32: a thread keeps its row and bin lane in every slot, and the
+      // x-tile steps by 32 / RB, so the address is one increment per slot
+      const int w = threadIdx.x & (TW - 1);
+      const int row = (threadIdx.x >> 3) & (RB - 1);
+      const int kt0 = threadIdx.x >> (3 + a.log2_rb), dkt = 32 >> a.log2_rb;
+      if (row0 + row < a.nrows) {
+        C *dst = spec + rt.offset(row, kt0, w);
+        const long long step = (long long)dkt * a.ny * TW;
+        const C *zrow = buf + row * sc;
+#pragma unroll
+        for (int j = 0; j < SP; ++j) {
+          const int kt = kt0 + j * dkt;
+          if (kt < a.ntx) dst[j * step] = split(zrow, kt * TW + w);
+        }
+      }
+    } else {
+      const int tot = (a.ntx * TW) << a.log2_rb;
+#pragma unroll
+      for (int j = 0; j < SP; ++j) {
+        const int f = threadIdx.x + j * FFT_THREADS;
+        const int w = f & (TW - 1), row = (f >> 3) & (RB - 1), kt = f >> (3 + a.log2_rb);
+        if (f >= tot || row0 + row >= a.nrows) continue;
+        spec[rt.offset(row, kt, w)] = split(buf + row * sc, kt * TW + w);
+      }
     }
   }
   const double s = block_sum<FFT_THREADS>(rr, red);
@@ -467,25 +487,47 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
   static_assert(TW == 8, "tile-major x-pass addressing assumes 8 bins per tile");
   constexpr int SP = XP + 2;              // RB * ntx * TW <= RB * (m + TW) <= SP * FFT_THREADS
   {
-    const int tot = (a.ntx * TW) << a.log2_rb;
     const RowTiles<TW> rt(row0, a.ny, a.ntx);
     const int last_row = (int)min((long long)RB - 1, a.nrows - 1 - row0);
     C sv[SP];
+    if (a.log2_rb <= 5) {
+      // RB <= 32: fixed row and bin lane per thread, x-tile step 32 / RB
+      const int w = threadIdx.x & (TW - 1);
+      const int row = (threadIdx.x >> 3) & (RB - 1);
+      const int kt0 = threadIdx.x >> (3 + a.log2_rb), dkt = 32 >> a.log2_rb;
+      const C *src = spec + rt.offset(min(row, last_row), 0, w);
+      const long long tstep = (long long)a.ny * TW;
 #pragma unroll
-    for (int j = 0; j < SP; ++j) {
-      const int f = min((int)threadIdx.x + j * FFT_THREADS, tot - 1);
-      const int w = f & (TW - 1), row = min((f >> 3) & (RB - 1), last_row), kt = f >> (3 + a.log2_rb);
-      sv[j] = spec[rt.offset(row, kt, w)];
-    }
+      for (int j = 0; j < SP; ++j)  // unconditional loads at clamped (valid) tiles
+        sv[j] = src[min(kt0 + j * dkt, a.ntx - 1) * tstep];
+      const bool rowok = row0 + row < a.nrows;
 #pragma unroll
-    for (int j = 0; j < SP; ++j) {
-      const int f = threadIdx.x + j * FFT_THREADS;
-      const int w = f & (TW - 1), row = (f >> 3) & (RB - 1), kt = f >> (3 + a.log2_rb);
-      const int kx = kt * TW + w;
-      if (f < tot && kx <= m) {
-        C v = sv[j];
-        if (row0 + row >= a.nrows) v.x = v.y = 0;
-        buf[row * sc + kx] = v;
+      for (int j = 0; j < SP; ++j) {
+        const int kt = kt0 + j * dkt, kx = kt * TW + w;
+        if (kt < a.ntx && kx <= m) {
+          C v = sv[j];
+          if (!rowok) v.x = v.y = 0;
+          buf[row * sc + kx] = v;
+        }
+      }
+    } else {
+      const int tot = (a.ntx * TW) << a.log2_rb;
+#pragma unroll
+      for (int j = 0; j < SP; ++j) {
+        const int f = min((int)threadIdx.x + j * FFT_THREADS, tot - 1);
+        const int w = f & (TW - 1), row = min((f >> 3) & (RB - 1), last_row), kt = f >> (3 + a.log2_rb);
+        sv[j] = spec[rt.offset(row, kt, w)];
+      }
+#pragma unroll
+      for (int j = 0; j < SP; ++j) {
+        const int f = threadIdx.x + j * FFT_THREADS;
+        const int w = f & (TW - 1), row = (f >> 3) & (RB - 1), kt = f >> (3 + a.log2_rb);
+        const int kx = kt * TW + w;
+        if (f < tot && kx <= m) {
+          C v = sv[j];
+          if (row0 + row >= a.nrows) v.x = v.y = 0;
+          buf[row * sc + kx] = v;
+        }
       }
     }
   }
