@@ -215,6 +215,15 @@ jfft_status jfft_reset_timing(jfft_cell_t cell);
    default 1.0). */
 jfft_status jfft_set_void_value(jfft_cell_t cell, double value);
 
+/* Stopping rule of jfft_solve / jfft_solve_batch:
+   JFFT_STOP_RELATIVE (default): ||r_k||_2 <= tol ||f||_2;
+   JFFT_STOP_ABSOLUTE: ||r_k||_2^2 <= tol, the rule of the paper's numerical
+   examples (Sec. 4).  The mixed-precision refinement applies the same rule to
+   its FP64 residual. */
+#define JFFT_STOP_RELATIVE 0
+#define JFFT_STOP_ABSOLUTE 1
+jfft_status jfft_set_stop_rule(jfft_cell_t cell, int rule);
+
 /* Mixed precision controls: relative tolerance of each inner FP32 PCG solve
    (default 1e-5) and the cap on refinement sweeps (default 30). */
 jfft_status jfft_set_mixed_params(jfft_cell_t cell, double inner_tol, int max_outer);

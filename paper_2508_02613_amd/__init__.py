@@ -76,6 +76,7 @@ _SIGS = {
     "jfft_reset_timing": (C.c_int, [_vp]),
     "jfft_set_void_value": (C.c_int, [_vp, C.c_double]),
     "jfft_set_mixed_params": (C.c_int, [_vp, C.c_double, C.c_int]),
+    "jfft_set_stop_rule": (C.c_int, [_vp, C.c_int]),
     "jfft_destroy_cell": (None, [_vp]),
     "jfft_last_error": (C.c_char_p, []),
     "jfft_version": (C.c_char_p, []),
@@ -222,6 +223,10 @@ class Cell:
 
     def set_void_value(self, v):
         _check(self._lib.jfft_set_void_value(self._h, float(v)))
+
+    def set_stop_rule(self, absolute=False):
+        """absolute=False: ||r|| <= tol ||f||; True: ||r||^2 <= tol (the paper's runs)."""
+        _check(self._lib.jfft_set_stop_rule(self._h, 1 if absolute else 0))
 
     def set_mixed_params(self, inner_tol=1e-5, max_outer=30):
         _check(self._lib.jfft_set_mixed_params(self._h, float(inner_tol), int(max_outer)))

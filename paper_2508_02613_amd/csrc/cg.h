@@ -118,8 +118,10 @@ __global__ void k_cg_beta(CgState *st, const double *part, long long n, History 
 }
 
 // ||f||^2 and ||f_abs||^2 from partials; the homogeneous-material test.
+// The stopping threshold relative to ||f||: tol itself (relative rule), or
+// sqrt(tol) / ||f|| for the absolute rule ||r||^2 <= tol of the paper's runs.
 __global__ void k_solve_norms(CgState *st, const double *partF, const double *partA, long long n,
-                              long long cs) {
+                              double tol, int absolute, long long cs) {
   __shared__ double sm[CTRL_WAVES];
   st = cshift(st, blockIdx.x, cs);
   partF = cshift(partF, blockIdx.x, cs);
@@ -135,6 +137,7 @@ __global__ void k_solve_norms(CgState *st, const double *partF, const double *pa
     st->total_iters = 0;
     st->final_status = ST_OK;
     st->rn = sqrt(f2);
+    st->tolr = (absolute && f2 > 0.0) ? sqrt(tol / f2) : tol;
   }
 }
 
@@ -142,19 +145,19 @@ __global__ void k_solve_norms(CgState *st, const double *partF, const double *pa
 // Mixed inner solve on r / ||r|| (mixed = 1): stop at relative
 // max(inner_tol, tol ||f|| / (2 ||r||)).  Cells already finished (homogeneous
 // material, or refinement converged) start in the stopped state.
-__global__ void k_cg_init(CgState *st, double tol, double inner_tol, int mixed, int maxit,
-                          int hist_cap, long long cs) {
+__global__ void k_cg_init(CgState *st, double inner_tol, int mixed, int maxit, int hist_cap,
+                          long long cs) {
   st = cshift(st, blockIdx.x, cs);
   if (threadIdx.x != 0) return;
   double t2;
   int mx = maxit;
   if (mixed) {
-    const double rel = fmax(inner_tol, 0.5 * tol * sqrt(st->fnorm2) / st->rn);
+    const double rel = fmax(inner_tol, 0.5 * st->tolr * sqrt(st->fnorm2) / st->rn);
     t2 = rel * rel;
     mx = maxit - st->total_iters;
     if (mx < 1) mx = 1;
   } else {
-    t2 = tol * tol * st->fnorm2;
+    t2 = st->tolr * st->tolr * st->fnorm2;
   }
   st->tol2 = t2;
   st->maxit = mx;
@@ -193,8 +196,8 @@ __global__ void k_cg_start(CgState *st, const double *partRR, long long nRR, con
 
 // Mixed precision: the FP64 residual ||f - K u|| of this sweep decides
 // whether refinement continues.  (The first sweep starts from u = u0.)
-__global__ void k_outer_check(CgState *st, const double *part, long long n, double tol,
-                              int max_outer, int maxit, long long cs) {
+__global__ void k_outer_check(CgState *st, const double *part, long long n, int max_outer,
+                              int maxit, long long cs) {
   __shared__ double sm[CTRL_WAVES];
   st = cshift(st, blockIdx.x, cs);
   part = cshift(part, blockIdx.x, cs);
@@ -203,7 +206,7 @@ __global__ void k_outer_check(CgState *st, const double *part, long long n, doub
     if (st->outer_done) return;
     const double rn = sqrt(rr);
     st->rn = rn;
-    if (rn <= tol * sqrt(st->fnorm2)) {
+    if (rn <= st->tolr * sqrt(st->fnorm2)) {
       st->outer_done = 1;
       st->final_status = ST_OK;
     } else if (st->outer >= max_outer || st->total_iters >= maxit) {

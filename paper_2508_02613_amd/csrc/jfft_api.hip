@@ -158,6 +158,7 @@ struct jfft_cell_s {
   double void_value = 1.0;
   double inner_tol = 1e-5;
   int max_outer = 30;
+  bool stop_abs = false;  // stopping rule ||r||^2 <= tol instead of ||r|| <= tol ||f||
 
   // captured iteration chunks
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // [0] FP64, [1] FP32 inner
@@ -740,12 +741,12 @@ jfft_status fetch_states(jfft_cell_s *c) {
 // PCG loop on prepared buffers (u = start vector, r = f - K u) for every cell
 // of the group; returns when every cell's flag is set.
 template <typename Real>
-jfft_status run_pcg(jfft_cell_s *c, const PcgBufs<Real> &b, double tol, bool mixed, int maxit,
+jfft_status run_pcg(jfft_cell_s *c, const PcgBufs<Real> &b, bool mixed, int maxit,
                     bool record) {
   History h{nullptr, nullptr, nullptr};
   if (record && c->hist_cap > 0) h = {c->hist[0], c->hist[1], c->hist[2]};
   long long nA = 0, nB = 0;
-  LAUNCH(c, KID_CTRL, k_cg_init<<<c->B, 1, 0, c->stream>>>(c->st, tol, c->inner_tol, mixed ? 1 : 0, maxit, record ? c->hist_cap : 0, c->cs));
+  LAUNCH(c, KID_CTRL, k_cg_init<<<c->B, 1, 0, c->stream>>>(c->st, c->inner_tol, mixed ? 1 : 0, maxit, record ? c->hist_cap : 0, c->cs));
   TRY(precond<Real>(c, b.r, nullptr, b.Jh, b.z, b.spec, false, false, &nA, &nB, h));
   LAUNCH(c, KID_CTRL, k_cg_start<<<c->B, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nA, c->partB, nB, c->cs));
   const int gk = sizeof(Real) == 8 ? 0 : 1;
@@ -921,7 +922,7 @@ jfft_status solve_impl(jfft_cell_s *c, const double *macros_h, double tol, int m
   const int nb = vec_blocks(nd);
   LAUNCH(c, KID_VEC, k_dot<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->f, nd, c->partA, c->cs));
   LAUNCH(c, KID_VEC, k_dot<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->q, c->q, nd, c->partB, c->cs));
-  LAUNCH(c, KID_CTRL, k_solve_norms<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, c->partB, nb, c->cs));
+  LAUNCH(c, KID_CTRL, k_solve_norms<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, c->partB, nb, tol, c->stop_abs ? 1 : 0, c->cs));
   LAUNCH(c, KID_VEC, k_start_vector<<<dim3(nb, Bc), 256, 0, c->stream>>>(u0, (long long)sizeof(double) * nd, c->u, nd, c->st, c->cs));
   HIP_TRY(hipEventRecord(c->phase_ev[1], c->stream));
   if (c->prec == JFFT_FP64) {
@@ -932,7 +933,7 @@ jfft_status solve_impl(jfft_cell_s *c, const double *macros_h, double tol, int m
       LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->cs, c->r, c->cs, nd));
     }
     PcgBufs<double> b{c->u, c->r, c->z, c->q, {c->p[0], c->p[1]}, c->E, c->Jh, c->spec};
-    TRY(run_pcg<double>(c, b, tol, false, maxit, true));
+    TRY(run_pcg<double>(c, b, false, maxit, true));
     LAUNCH(c, KID_CTRL, k_fp64_final<<<Bc, 1, 0, c->stream>>>(c->st, c->cs));
   } else {
     // mixed precision: FP64 residual and iterate, FP32 inner PCG on r / ||r||
@@ -943,7 +944,7 @@ jfft_status solve_impl(jfft_cell_s *c, const double *macros_h, double tol, int m
       } else {
         LAUNCH(c, KID_VEC, k_sub_norm<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->u, c->r, nd, c->partA, c->cs));
       }
-      LAUNCH(c, KID_CTRL, k_outer_check<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nb, tol, c->max_outer, maxit, c->cs));
+      LAUNCH(c, KID_CTRL, k_outer_check<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nb, c->max_outer, maxit, c->cs));
       TRY(fetch_states(c));
       bool all = true;
       for (int i = 0; i < Bc; ++i) all = all && c->st_h[i].outer_done;
@@ -951,7 +952,7 @@ jfft_status solve_impl(jfft_cell_s *c, const double *macros_h, double tol, int m
       LAUNCH(c, KID_VEC, (k_convert<double, float><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->r, c->r32, nd, 1.0, c->st, c->cs)));
       LAUNCH(c, KID_VEC, k_fill<float><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->c32, 0.0f, nd, c->cs));
       PcgBufs<float> b{c->c32, c->r32, c->z32, c->q32, {c->p32[0], c->p32[1]}, c->E32, c->Jh32, c->spec32};
-      TRY(run_pcg<float>(c, b, tol, true, maxit, false));
+      TRY(run_pcg<float>(c, b, true, maxit, false));
       LAUNCH(c, KID_CTRL, k_outer_update<<<Bc, 1, 0, c->stream>>>(c->st, c->cs));
       LAUNCH(c, KID_VEC, k_axpy_f32_to_f64<<<dim3(nb, Bc), 256, 0, c->stream>>>(c->c32, c->u, nd, c->st, c->cs));
     }
@@ -1265,6 +1266,13 @@ jfft_status jfft_kernel_stats(jfft_cell_t c, int i, const char **name, long *lau
   if (name) *name = kKernelNames[i];
   if (launches) *launches = c->kcount[i];
   if (total_ms) *total_ms = c->ktime[i];
+  return JFFT_OK;
+}
+
+jfft_status jfft_set_stop_rule(jfft_cell_t c, int rule) {
+  if (!c || (rule != JFFT_STOP_RELATIVE && rule != JFFT_STOP_ABSOLUTE))
+    return fail(JFFT_E_INVALID, "unknown stopping rule");
+  c->stop_abs = rule == JFFT_STOP_ABSOLUTE;
   return JFFT_OK;
 }
 

@@ -49,7 +49,7 @@ struct CgState {
   double rr;        // ||r_k||^2
   double tol2;      // stopping threshold on ||r_k||^2
   double rr0;       // ||r_0||^2 of the current loop (host-side stop prediction)
-  double scratch;
+  double tolr;      // stopping threshold as a fraction of ||f|| (either rule)
   int iter;         // completed updates of u
   int maxit;
   int done;         // 1 once stopped (later kernels of the loop return at once)
