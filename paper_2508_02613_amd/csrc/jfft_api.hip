@@ -346,10 +346,18 @@ size_t layout_workspace(jfft_cell_s *c, unsigned char *base) {
   return T.off;
 }
 
+// Output-node tile of the stiffness kernels (x and y edge) and the tile count of a grid.
+int stencil_tile_x(int dim) { return dim == 3 ? TX3 : TILE; }
+int stencil_tile_y(int dim) { return dim == 3 ? TY3 : TILE; }
+long long stencil_tiles(int dim, int nx, int ny) {
+  const int tx = stencil_tile_x(dim), ty = stencil_tile_y(dim);
+  return (long long)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
+}
+
 long long max_partials(jfft_cell_s *c) {
   const GridDev &g = c->g;
   long long mx = 4 * 1024;  // vector kernels
-  const long long tiles = (long long)((g.nx + TILE - 1) / TILE) * ((g.ny + TILE - 1) / TILE);
+  const long long tiles = stencil_tiles(c->dim, g.nx, g.ny);
   mx = std::max(mx, tiles * ((g.nz + 2 - 1) / 2));  // smallest z chunk allowed (tz >= 2)
   const int m = g.nx / 2;
   const long long rows = (long long)c->dim * g.ny * g.nz;
@@ -454,18 +462,69 @@ StencilArgs<Real> stencil_args(jfft_cell_s *c, const Real *E) {
   return a;
 }
 
+// Blocks of the 3D CG stiffness kernel that the device runs at once, and per CU.
+hipError_t stiffness_slots(int device, bool fp64, int *slots, int *per_cu_out) {
+  int cus = 0, per_cu = 0;
+  hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) return e;
+  if (fp64)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stiffness3d<double, SM_CG>,
+                                                     STENCIL3_THREADS, 0);
+  else
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stiffness3d<float, SM_CG>,
+                                                     STENCIL3_THREADS, 0);
+  *slots = std::max(1, cus * per_cu);
+  *per_cu_out = std::max(1, per_cu);
+  return e;
+}
+
+// z planes per block of the 3D stiffness kernel.  The choice depends on the
+// cell shape, the precision and the device only, never on the group size, so
+// reduction layouts (and results) do not either.
+// * One block per CU (FP64): the launch runs in rounds of co-resident blocks
+//   and a block marches tz + 1 element layers, so the time is modelled as
+//   rounds * (tz + 1), minimised over 4 <= tz <= 64 (ties: the larger tz,
+//   which re-reads fewer halo planes).
+// * Several blocks per CU (FP32): blocks that start together stay in step
+//   over a long march and contend for the same units at the same time; a
+//   march of 16 planes measured best on 256^3 (6: 0.469 ms, 8 and 12: 0.460,
+//   16: 0.448; 32 and longer slower), shortened while the launch would leave
+//   slots empty.
+int pick_tz(const GridDev &g, int slots, int per_cu) {
+  const long long tiles = stencil_tiles(3, g.nx, g.ny);
+  const int lo = std::min(4, g.nz);
+  auto blocks = [&](int tz) { return tiles * ((g.nz + tz - 1) / tz); };
+  if (per_cu > 1) {
+    int tz = std::min(16, g.nz);
+    while (tz > lo && blocks(tz) < slots) --tz;
+    return tz;
+  }
+  const int hi = std::min(64, g.nz);
+  int best = lo;
+  long long best_cost = -1;
+  for (int tz = lo; tz <= hi; ++tz) {
+    const long long cost = (blocks(tz) + slots - 1) / slots * (tz + 1);
+    if (best_cost < 0 || cost <= best_cost) {
+      best_cost = cost;
+      best = tz;
+    }
+  }
+  return best;
+}
+
 long long stencil_blocks_per_cell(jfft_cell_s *c) {
   const GridDev &g = c->g;
   const int tz = c->dim == 3 ? std::min(c->tun.tz, g.nz) : 1;
   const int nbz = c->dim == 3 ? (g.nz + tz - 1) / tz : 1;
-  return (long long)((g.nx + TILE - 1) / TILE) * ((g.ny + TILE - 1) / TILE) * nbz;
+  return stencil_tiles(c->dim, g.nx, g.ny) * nbz;
 }
 
 template <typename Real, int MODE>
 jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a, int cells) {
   const int kid = MODE == SM_CG ? KID_STIFF_CG : (MODE == SM_APPLY ? KID_STIFF_APPLY : KID_STIFF_COMB);
   const GridDev &g = c->g;
-  dim3 gr((g.nx + TILE - 1) / TILE, (g.ny + TILE - 1) / TILE, a.nbz * cells);
+  const int tx = stencil_tile_x(c->dim), ty = stencil_tile_y(c->dim);
+  dim3 gr((g.nx + tx - 1) / tx, (g.ny + ty - 1) / ty, a.nbz * cells);
   if (c->dim == 3) {
     LAUNCH(c, kid, k_stiffness3d<Real, MODE><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a));
   } else {
@@ -1042,21 +1101,20 @@ jfft_status create_impl(int dim, const int n[3], const double len[3], jfft_preci
   factor_plan(g.nx / 2, c->plan_x);
   factor_plan(g.ny, c->plan_y);
   factor_plan(g.nz, c->plan_z);
-  // z planes per stiffness block: enough blocks per cell to fill 256 CUs
-  // several times (from the shape alone, see vec_blocks)
-  if (dim == 3) {
-    const long long tiles = (long long)((g.nx + TILE - 1) / TILE) * ((g.ny + TILE - 1) / TILE);
-    int tz = 32;
-    while (tz > 4 && tiles * ((g.nz + tz - 1) / tz) < 2048) tz /= 2;
-    c->tun.tz = std::min(tz, g.nz);
-    if ((long long)((g.nz + c->tun.tz - 1) / c->tun.tz) * batch > 65535) {
-      delete c;
-      return fail(JFFT_E_INVALID, "batch too large for this grid (stiffness grid z-dimension above 65535)");
-    }
-  }
   c->npart = max_partials(c);
   set_smem_attributes();
   hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess && dim == 3) {
+    int slots = 0, per_cu = 0;
+    e = stiffness_slots(c->device, prec == JFFT_FP64, &slots, &per_cu);
+    if (e == hipSuccess) {
+      c->tun.tz = pick_tz(g, slots, per_cu);
+      if ((long long)((g.nz + c->tun.tz - 1) / c->tun.tz) * batch > 65535) {
+        delete c;
+        return fail(JFFT_E_INVALID, "batch too large for this grid (stiffness grid z-dimension above 65535)");
+      }
+    }
+  }
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&c->st_h), sizeof(CgState) * batch, hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&c->small_h), sizeof(double) * kSmall * batch, hipHostMallocDefault);
   if (e != hipSuccess) {
@@ -1223,7 +1281,7 @@ jfft_status jfft_set_tunables(jfft_cell_t c, const jfft_tunables *t) {
     if (t->tz < std::min(2, c->g.nz) || t->tz > c->g.nz)
       return fail(JFFT_E_INVALID, "tz must lie in [2, nz]");
     const long long nbz = (c->g.nz + t->tz - 1) / t->tz;
-    const long long tiles = (long long)((c->g.nx + TILE - 1) / TILE) * ((c->g.ny + TILE - 1) / TILE);
+    const long long tiles = stencil_tiles(3, c->g.nx, c->g.ny);
     if (nbz * c->B > 65535) return fail(JFFT_E_INVALID, "tz too small for this group (grid z-dimension)");
     if (tiles * nbz > c->npart) return fail(JFFT_E_INVALID, "tz too small for the partial-sum buffer");
     c->tun.tz = t->tz;

@@ -6,13 +6,14 @@
 // sigma = E w (lambda tr(eps) I + 2 mu eps), and the transposed
 // factorisation back to the corners.
 //
-// Kernels are halo-tiled: a block owns a 16 x 16 tile of output nodes in the
-// x-y plane and marches along z through a chunk of planes.  It evaluates the
-// 17 x 17 elements that touch its tile per layer (13% redundant halo work,
-// no atomics, deterministic), keeps a ring of node planes of the input vector
-// in LDS, and sums corner contributions of the four x-y neighbouring elements
-// from LDS; the z neighbour's contribution is carried in registers to the
-// next layer.
+// Kernels are halo-tiled: a block owns a tile of output nodes in the x-y
+// plane (16 x 16 in 2D, 16 x 14 in 3D), evaluates every element that touches
+// the tile (17 x 17, resp. 17 x 15, about 13% redundant halo work, no atomics,
+// deterministic), keeps the node values of the input vector in LDS and sums
+// the corner contributions of the four x-y neighbouring elements from LDS.
+// The 3D kernel marches along z through a chunk of planes with a ring of node
+// planes in LDS; the z neighbour's contribution is carried in registers to
+// the next layer.
 #pragma once
 #include "jfft_common.h"
 
@@ -24,7 +25,23 @@ constexpr int NTILE = TILE + 2;    // nodes per tile edge (with halo)
 constexpr int NELEM = ETILE * ETILE;  // 289
 constexpr int NNODE = NTILE * NTILE;  // 324
 constexpr int STENCIL_THREADS = 320;  // 5 wavefronts (2D kernel)
-constexpr int STENCIL3_THREADS = 384;  // 6 wavefronts: one halo-plane node per thread (3D kernel)
+// 3D kernel: 16 x 14 output nodes, 17 x 15 elements, 18 x 16 node planes.
+// Rows of 16 output nodes start on 64-byte boundaries (FP32; 128 in FP64),
+// so every store covers whole sectors and no sector is written by two blocks.
+constexpr int TX3 = 16, TY3 = 14;
+constexpr int EX3 = TX3 + 1, EY3 = TY3 + 1;
+constexpr int NX3 = TX3 + 2, NY3 = TY3 + 2;
+constexpr int NELEM3 = EX3 * EY3;           // 255
+constexpr int NNODE3 = NX3 * NY3;           // 288
+constexpr int STENCIL3_THREADS = 256;       // 4 wavefronts: one element per thread
+constexpr int NSTRIP3 = NNODE3 - STENCIL3_THREADS;  // 32 nodes beyond one per thread
+static_assert(TX3 == 16 && NY3 == 16 && NSTRIP3 == 32,
+              "the 3D kernel maps threads to nodes with shifts by 4");
+// Register budget of the 3D kernel (waves per SIMD = blocks per CU): three
+// blocks per CU in FP32 (<= 168 VGPRs; at 128 it spills), one in FP64 (at
+// 256 VGPRs it spills, which costs more than the second block gains).
+template <typename Real>
+constexpr int stencil3_waves_per_simd() { return sizeof(Real) == 4 ? 3 : 1; }
 
 // Gauss-point interpolation weights of the linear shape functions:
 // N_0(xi_g) = {A, B}, N_1(xi_g) = {B, A} for xi_g = 1/2 -+ 1/(2 sqrt 3).
@@ -422,12 +439,21 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
 // committed to the third slot of the plane ring after the element work.  Two
 // barriers per layer.  In CG mode p.q is accumulated as the element energies
 // u_e . K_e u_e of the elements the block owns (= p^T K p).
+//
+// Geometry: a block owns TX3 x TY3 = 16 x 14 output nodes and evaluates the
+// 17 x 15 elements that touch them, one element per thread (thread 255
+// repeats element 254 and discards it), so a block is exactly four
+// wavefronts: one per SIMD, and every SIMD of a CU carries the same element
+// work at any occupancy.  Thread t also holds node (t & 15) + 1, t >> 4 of
+// each 18 x 16 node plane (columns 1..16, which hold every owned node) and,
+// if t < 224, output node (t & 15) + 1, (t >> 4) + 1.  Columns 0 and 17 of
+// a plane are loaded by threads 0..31.
 template <typename Real, int MODE>
-__global__ void __launch_bounds__(STENCIL3_THREADS)
+__global__ void __launch_bounds__(STENCIL3_THREADS, stencil3_waves_per_simd<Real>())
     k_stiffness3d(StencilArgs<Real> a) {
-  __shared__ Real P[3][3][NNODE];  // ring of three node planes of the input vector
-  __shared__ Real Y[24][NELEM];    // corner contributions of one element layer
-  __shared__ double red[8];
+  __shared__ Real P[3][3][NNODE3];               // ring of three node planes of the input vector
+  __shared__ Real Y[24][STENCIL3_THREADS];       // corner contributions of one element layer
+  __shared__ double red[STENCIL3_THREADS / 64];
 
   const int tid = threadIdx.x;
   const int nbx = gridDim.x, nby = gridDim.y;
@@ -439,7 +465,7 @@ __global__ void __launch_bounds__(STENCIL3_THREADS)
   shift_args(a, cell);
   if (MODE == SM_CG && a.st->done) return;
   const int bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
-  const int x0 = bx * TILE, y0 = by * TILE;
+  const int x0 = bx * TX3, y0 = by * TY3;
   const int z0 = bz * a.tz;
   const int zend = min(z0 + a.tz, a.nz);
   const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -454,98 +480,105 @@ __global__ void __launch_bounds__(STENCIL3_THREADS)
     alpha_prev = (Real)a.st->alpha;
   }
 
-  // element of this thread in the x-y layer (17 x 17 with the halo)
-  const bool is_elem = tid < NELEM;
-  const int exl = tid % ETILE, eyl = tid / ETILE;
+  // element (halo-extended layer; beyond the grid: E = 0)
+  const int te = min(tid, NELEM3 - 1);
+  const int exl = te % EX3, eyl = te / EX3;
   const int gex = x0 - 1 + exl, gey = y0 - 1 + eyl;
-  const bool elem_valid = is_elem && gex < nx && gey < ny;  // beyond the grid: E = 0
-  const bool elem_owned = elem_valid && exl >= 1 && eyl >= 1;
+  const bool elem_valid = gex < nx && gey < ny;
+  const bool elem_owned = elem_valid && exl >= 1 && eyl >= 1 && tid < NELEM3;
   const long long exy = (long long)wrapi(gex, nx) + (long long)nx * wrapi(gey, ny);
-  // output node of this thread
-  const bool is_node = tid < TILE * TILE;
-  const int oxl = tid % TILE, oyl = tid / TILE;
-  const int gnx = x0 + oxl, gny = y0 + oyl;
-  const bool node_valid = is_node && gnx < nx && gny < ny;
-  const int e00 = oyl * ETILE + oxl;  // element (lx - 1, ly - 1) of node (lx, ly) = (oxl + 1, oyl + 1)
+  const int lie = eyl * NX3 + exl;  // corner (0, 0) of the element in a node plane
+  // output node (ox + 1, oy + 1); its x-y neighbouring elements are e00,
+  // e00 + 1, e00 + EX3 and e00 + EX3 + 1
+  const int ox = tid & 15, oy = tid >> 4;
+  const int e00 = oy * EX3 + ox;
+  const int gnx = x0 + ox, gny = y0 + oy;
+  const bool node_valid = oy < TY3 && gnx < nx && gny < ny;
+  // node slot 0: node (ox + 1, oy) of the plane, global (x0 + ox, y0 - 1 + oy)
+  const int li0 = oy * NX3 + ox + 1;
+  const int w0x = wrapi(x0 + ox, nx), w0y = wrapi(y0 - 1 + oy, ny);
+  const long long n0xy = (long long)w0x + (long long)nx * w0y;
+  const bool own0 = oy >= 1 && oy <= TY3 && x0 + ox < nx && y0 - 1 + oy < ny;
+  const int par0 = (w0x & 1) | ((w0y & 1) << 1);
+  // u is read for every slot-0 node (so that the loads need no branch); a
+  // halo row reads its owned neighbour row instead, and discards the value
+  const long long u0xy =
+      (long long)w0x + (long long)nx * wrapi(y0 - 1 + min(max(oy, 1), TY3), ny);
+  // node slot 1 (threads 0..31): column 0, then column 17; the other threads
+  // load node (0, 0) again (one cache line per wavefront) and discard it
+  const bool has1 = tid < NSTRIP3;
+  const int s1x = (has1 && (tid >> 4)) ? NX3 - 1 : 0;
+  const int s1y = has1 ? (tid & 15) : 0;
+  const int li1 = s1y * NX3 + s1x;
+  const int w1x = wrapi(x0 - 1 + s1x, nx), w1y = wrapi(y0 - 1 + s1y, ny);
+  const long long n1xy = (long long)w1x + (long long)nx * w1y;
+  const int par1 = (w1x & 1) | ((w1y & 1) << 1);
 
-  // node slot of this thread in a plane (NNODE = 324 <= 384 threads)
-  constexpr int NS = (NNODE + STENCIL3_THREADS - 1) / STENCIL3_THREADS;  // = 1
-  long long nxy[NS];
-  bool nown[NS], nval[NS];
-  int npar[NS];
+  // One prefetched plane in registers (z or the APPLY input, p_old and u
+  // for slot 0; z and p_old for slot 1), committed at the top of the next
+  // layer.  Slot 0 is refilled right after its commit; slot 1 only after the
+  // element work, so that its registers are free while the element is
+  // evaluated (its loads then hide behind the node sums).  Every load is
+  // issued unconditionally at a valid address and masked at the commit: with
+  // no load under a branch the compiler knows the exact number of memory
+  // operations in flight and waits only for the ones a value needs.
+  Real fz[3], fp[3], fu[3], hz[3], hp[3];
+  auto fetch0 = [&](int zp) {
+    const long long node0 = (long long)wrapi(zp, nz) * plane + n0xy;
+    // owned u lies in planes z0 .. zend - 1 (< nz, no wrap)
+    const long long nodeu = (long long)min(max(zp, z0), zend - 1) * plane + u0xy;
 #pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    const int idx = tid + k * STENCIL3_THREADS;
-    nval[k] = idx < NNODE;
-    const int lx = idx % NTILE, ly = idx / NTILE;
-    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-    const int wx = wrapi(gx, nx), wy = wrapi(gy, ny);
-    nxy[k] = (long long)wx + (long long)nx * wy;
-    nown[k] = nval[k] && lx >= 1 && lx <= TILE && ly >= 1 && ly <= TILE && gx < nx && gy < ny;
-    npar[k] = (wx & 1) | ((wy & 1) << 1);
-  }
-
-  // Two prefetched planes in registers: set 0 is committed next, set 1 is in
-  // flight (z or the APPLY input, p_old and u).
-  Real fz[2][NS][3], fp[2][NS][3], fu[2][NS][3];
-  auto fetch = [&](int zp, int set) {
-    const long long zoff = (long long)wrapi(zp, nz) * plane;
-    const bool owned_plane = (zp >= z0) && (zp < zend);
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      if (!nval[k]) continue;
-      const long long node = zoff + nxy[k];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if (MODE == SM_APPLY) {
-          fz[set][k][c] = a.in[c * N + node];
-        } else if (MODE == SM_CG) {
-          fz[set][k][c] = a.zin[c * N + node];
-          fp[set][k][c] = first ? (Real)0 : a.in[c * N + node];
-          fu[set][k][c] = (!first && owned_plane && nown[k]) ? a.u[c * N + node] : (Real)0;
-        }
+    for (int c = 0; c < 3; ++c) {
+      if (MODE == SM_APPLY) {
+        fz[c] = a.in[c * N + node0];
+      } else if (MODE == SM_CG) {
+        fz[c] = a.zin[c * N + node0];
+        fp[c] = a.in[c * N + node0];
+        fu[c] = a.u[c * N + nodeu];
       }
     }
   };
-  auto advance = [&]() {  // set 1 becomes set 0
+  auto fetch1 = [&](int zp) {
+    const long long node1 = (long long)wrapi(zp, nz) * plane + n1xy;
 #pragma unroll
-    for (int k = 0; k < NS; ++k)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        fz[0][k][c] = fz[1][k][c];
-        fp[0][k][c] = fp[1][k][c];
-        fu[0][k][c] = fu[1][k][c];
+    for (int c = 0; c < 3; ++c) {
+      if (MODE == SM_APPLY) {
+        hz[c] = a.in[c * N + node1];
+      } else if (MODE == SM_CG) {
+        hz[c] = a.zin[c * N + node1];
+        hp[c] = a.in[c * N + node1];
       }
+    }
+  };
+  auto fetch = [&](int zp) {
+    fetch0(zp);
+    fetch1(zp);
   };
   auto commit = [&](int zp, int slot) {
     const int wz = wrapi(zp, nz);
-    const long long zoff = (long long)wz * plane;
-    const bool owned_plane = (zp >= z0) && (zp < zend);
+    const long long node0 = (long long)wz * plane + n0xy;
+    const bool owned = (zp >= z0) && (zp < zend) && own0;
 #pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      if (!nval[k]) continue;
-      const int idx = tid + k * STENCIL3_THREADS;
-      const long long node = zoff + nxy[k];
-      const bool owned = owned_plane && nown[k];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        Real v;
-        if (MODE == SM_APPLY) {
-          v = fz[0][k][c];
-        } else if (MODE == SM_COMB) {
-          const int par = npar[k] | ((wz & 1) << 2);
-          v = (c == a.comb_comp && par == a.comb_off) ? (Real)1 : (Real)0;
-        } else {
-          if (first) {
-            v = fz[0][k][c];
-          } else {
-            v = fz[0][k][c] + beta * fp[0][k][c];
-            if (owned) a.u[c * N + node] = fu[0][k][c] + alpha_prev * fp[0][k][c];
-          }
-          if (owned) a.pout[c * N + node] = v;
+    for (int c = 0; c < 3; ++c) {
+      Real v, w;
+      if (MODE == SM_APPLY) {
+        v = fz[c];
+        w = hz[c];
+      } else if (MODE == SM_COMB) {
+        const int zb = (wz & 1) << 2;
+        v = (c == a.comb_comp && (par0 | zb) == a.comb_off) ? (Real)1 : (Real)0;
+        w = (c == a.comb_comp && (par1 | zb) == a.comb_off) ? (Real)1 : (Real)0;
+      } else {
+        // p_old and u hold no data before the first iteration: select, not multiply
+        v = first ? fz[c] : fz[c] + beta * fp[c];
+        w = first ? hz[c] : hz[c] + beta * hp[c];
+        if (owned) {
+          if (!first) a.u[c * N + node0] = fu[c] + alpha_prev * fp[c];
+          a.pout[c * N + node0] = v;
         }
-        P[slot][c][idx] = v;
       }
+      P[slot][c][li0] = v;
+      if (has1) P[slot][c][li1] = w;
     }
   };
   auto ring = [&](int zp) { return (zp - z0 + 1) % 3; };
@@ -558,11 +591,11 @@ __global__ void __launch_bounds__(STENCIL3_THREADS)
   Real carry[3] = {0, 0, 0};
   Real qpend[3] = {0, 0, 0};
   long long qnode = -1;  // pending output node (stored at the next layer's top)
-  fetch(z0 - 1, 0);
+  fetch(z0 - 1);
   commit(z0 - 1, ring(z0 - 1));
-  fetch(z0, 0);
+  fetch(z0);
   commit(z0, ring(z0));
-  fetch(z0 + 1, 1);
+  fetch(z0 + 1);  // layer z0 always exists and reads plane z0 + 1
   // the modulus is loaded for every thread and layer (the wrapped address is
   // always valid) and masked at use, so no register is conditionally loaded
   Real Enext = a.E[(long long)wrapi(z0 - 1, nz) * plane + exy];
@@ -582,18 +615,21 @@ __global__ void __launch_bounds__(STENCIL3_THREADS)
     const int s0 = ring(ez), s1 = ring(ez + 1);
     const bool more = ez + 1 < zend;   // layer ez + 1 exists and needs plane ez + 2
     const bool more2 = ez + 2 < zend;  // layer ez + 2 exists and needs plane ez + 3
-    if (more) advance();               // plane ez + 2, in flight since the last layer
-    const Real Ecur = Enext * emask;
+    // Everything loaded during the last layer is consumed first (the modulus
+    // and plane ez + 2); only then are this layer's stores and loads issued,
+    // so no wait below can fall on a load issued in this layer.
+    Real Ecur = Enext * emask;
+    asm volatile("" : "+v"(Ecur)::"memory");
+    if (more) commit(ez + 2, ring(ez + 2));  // plane ez + 2, in flight since the last layer
     flush_q();
-    if (more) commit(ez + 2, ring(ez + 2));
-    if (more2) fetch(ez + 3, 1);
+    if (more2) fetch0(ez + 3);
     Enext = a.E[(long long)wrapi(ez + 1, nz) * plane + exy];
-    if (is_elem) {
+    {
       Real uv[3][8], yv[3][8];
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-        const int li = (eyl + cy) * NTILE + exl + cx;
+        const int li = lie + cy * NX3 + cx;
 #pragma unroll
         for (int i = 0; i < 3; ++i) uv[i][c] = P[cz ? s1 : s0][i][li];
       }
@@ -607,6 +643,7 @@ __global__ void __launch_bounds__(STENCIL3_THREADS)
 #pragma unroll
         for (int i = 0; i < 3; ++i) Y[c * 3 + i][tid] = yv[i][c];
     }
+    if (more2) fetch1(ez + 3);
     __syncthreads();
     if (node_valid) {
       // corners (1,1), (0,1), (1,0), (0,0) of the four x-y neighbouring elements
@@ -614,7 +651,7 @@ __global__ void __launch_bounds__(STENCIL3_THREADS)
 #pragma unroll
         for (int i = 0; i < 3; ++i)
           qpend[i] = carry[i] + Y[3 * 3 + i][e00] + Y[2 * 3 + i][e00 + 1] +
-                     Y[1 * 3 + i][e00 + ETILE] + Y[0 * 3 + i][e00 + ETILE + 1];
+                     Y[1 * 3 + i][e00 + EX3] + Y[0 * 3 + i][e00 + EX3 + 1];
         const long long node = (long long)gnx + (long long)nx * (gny + (long long)ny * ez);
         if (MODE == SM_COMB) {
           const int par = (gnx & 1) | ((gny & 1) << 1) | ((ez & 1) << 2);
@@ -628,8 +665,8 @@ __global__ void __launch_bounds__(STENCIL3_THREADS)
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i)
-        carry[i] = Y[7 * 3 + i][e00] + Y[6 * 3 + i][e00 + 1] + Y[5 * 3 + i][e00 + ETILE] +
-                   Y[4 * 3 + i][e00 + ETILE + 1];
+        carry[i] = Y[7 * 3 + i][e00] + Y[6 * 3 + i][e00 + 1] + Y[5 * 3 + i][e00 + EX3] +
+                   Y[4 * 3 + i][e00 + EX3 + 1];
     }
     __syncthreads();
   }
