@@ -211,6 +211,21 @@ jfft_status jfft_kernel_stats(jfft_cell_t cell, int i, const char **name, long *
                               double *total_ms, int *count);
 jfft_status jfft_reset_timing(jfft_cell_t cell);
 
+/* How set_material forms diag(K) for the Jacobi part of the preconditioner
+   (Sec. 3.2):
+   JFFT_DIAG_CLOSED_FORM (default): for the isotropic Q1 elements of this
+   library, Algorithm 2's result has a closed form, diag_{alpha I} = k_alpha
+   times the sum of the moduli of the 2^d elements around node I, with
+   k_alpha = lam g_alpha + mu (g_alpha + sum_b g_b), g_b = vol_e /
+   (3^(d-1) h_b^2) (exact Gauss integration); one pass over E, equal to the
+   probing result up to rounding;
+   JFFT_DIAG_PROBING: Algorithm 2 as stated, d 2^d applications of K to unit
+   combs.
+   Takes effect at the next set_material (a change clears the material). */
+#define JFFT_DIAG_CLOSED_FORM 0
+#define JFFT_DIAG_PROBING 1
+jfft_status jfft_set_diag_method(jfft_cell_t cell, int method);
+
 /* Value of the void rule replacement for exact zeros of diag(K) (Sec. 3.2,
    default 1.0). */
 jfft_status jfft_set_void_value(jfft_cell_t cell, double value);

@@ -77,6 +77,7 @@ _SIGS = {
     "jfft_set_void_value": (C.c_int, [_vp, C.c_double]),
     "jfft_set_mixed_params": (C.c_int, [_vp, C.c_double, C.c_int]),
     "jfft_set_stop_rule": (C.c_int, [_vp, C.c_int]),
+    "jfft_set_diag_method": (C.c_int, [_vp, C.c_int]),
     "jfft_destroy_cell": (None, [_vp]),
     "jfft_last_error": (C.c_char_p, []),
     "jfft_version": (C.c_char_p, []),
@@ -223,6 +224,15 @@ class Cell:
 
     def set_void_value(self, v):
         _check(self._lib.jfft_set_void_value(self._h, float(v)))
+
+    def set_diag_method(self, method="closed_form"):
+        """How diag(K) is formed for the Jacobi part (Sec. 3.2): "closed_form"
+        (isotropic Q1, one pass over E) or "probing" (Algorithm 2 as stated).
+        Takes effect at the next set_material."""
+        codes = {"closed_form": 0, "probing": 1}
+        if method not in codes:
+            raise ValueError(f"unknown diagonal method {method!r}")
+        _check(self._lib.jfft_set_diag_method(self._h, codes[method]))
 
     def set_stop_rule(self, absolute=False):
         """absolute=False: ||r|| <= tol ||f||; True: ||r||^2 <= tol (the paper's runs)."""

