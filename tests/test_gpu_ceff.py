@@ -86,10 +86,11 @@ def test_ceff_64_bounds_and_symmetry(seed):
 
 
 def test_64_load_case_matches_oracle():
-    """One 64^3 load case (e11): iteration counts at tol 1e-8 (+-1), the
-    fluctuation field near the exact discrete solution at tol 1e-12 (1e-10);
-    at 1e-12 the stopping iteration itself is rounding-sensitive (CG amplifies
-    rounding over 200+ iterations), so only its closeness is checked there."""
+    """One 64^3 load case (e11): iteration counts within +-1 plus the flat
+    stretch of the oracle's convergence curve around the threshold (CG
+    amplifies rounding over 150+ iterations, and where the residual decays
+    slowly the crossing moves), the fluctuation field near the exact discrete
+    solution at tol 1e-12 (1e-10)."""
     pkg = _pkg()
     E = ji.grf_field((64, 64, 64), 1e4, seed=0, ell=0.1)
     macro = ji.unit_macro_strain(3, 0)
@@ -99,15 +100,19 @@ def test_64_load_case_matches_oracle():
         say(f"64^3 GRF contrast 1e4, e11, tol {tol:g} vs oracle")
         u, sbar, rep, _ = cell.solve(macro, tol=tol, maxit=5000)
         ug = u.cpu().numpy()
-        ref = oracle.solve(E, macro, LAM, MU, pc=3, tol=tol, maxit=5000)
+        ref = oracle.solve(E, macro, LAM, MU, pc=3, tol=tol, maxit=5000, hist_len=5000)
         err = np.linalg.norm(ug - ref.u) / np.linalg.norm(ref.u)
-        say(f"  iters gpu={rep.iters} oracle={ref.iters} err(u)={err:.2e}")
+        # +-1, plus the iterations over which the oracle's residual lies within
+        # a factor 3 of the threshold (where the curve is that flat, rounding
+        # moves the crossing)
+        rel = ref.res[:ref.iters] / np.linalg.norm(oracle.rhs(E, macro, LAM, MU))
+        slack = 1 + int(np.count_nonzero((rel >= tol / 3) & (rel <= 3 * tol)))
+        say(f"  iters gpu={rep.iters} oracle={ref.iters} (slack {slack}) err(u)={err:.2e}")
         assert rep.status == "ok" and ref.status == "ok"
+        assert abs(rep.iters - ref.iters) <= slack
         if tol == 1e-8:
-            assert abs(rep.iters - ref.iters) <= 1
             assert err <= 1e-6
         else:
-            assert abs(rep.iters - ref.iters) <= 0.03 * ref.iters
             assert err <= 1e-10
             np.testing.assert_allclose(sbar, ref.sigma_bar, rtol=1e-11,
                                        atol=1e-11 * np.abs(ref.sigma_bar).max())

@@ -76,6 +76,31 @@ def test_closed_form_equals_probing(shape, lengths, voids):
     assert np.abs(probe - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("shape,lengths", CASES)
+@pytest.mark.parametrize("voids", [False, True])
+def test_green_jacobi_closed_form_equals_probing(shape, lengths, voids):
+    """The Green-Jacobi preconditioner built on the closed-form diagonal equals
+    the one built on Algorithm 2's probing, with voids and rectangular
+    elements."""
+    pkg = _pkg()
+    say(f"GJ closed form vs probing {shape} lengths={lengths} voids={voids}")
+    dim = len(shape)
+    E = _field(shape, voids, 11)
+    x = np.random.default_rng(2).standard_normal((dim,) + shape)
+    out = {}
+    for method in ("closed_form", "probing"):
+        cell = pkg.Cell(shape, pc=pkg.PC_GREEN_JACOBI, lengths=lengths)
+        cell.set_void_value(0.4)
+        cell.set_diag_method(method)
+        cell.set_material(E, nu=0.3)
+        out[method] = cell.apply_precond(x).cpu().numpy()
+        cell.close()
+    a, b = out["closed_form"], out["probing"]
+    rel = np.abs(a - b).max() / np.abs(b).max()
+    say(f"  max |closed - probing| / max = {rel:.2e}")
+    assert rel <= 1e-12
+
+
 @pytest.mark.parametrize("shape,lengths,prec", [((12, 10, 18), (1.3, 0.7, 1.0), 0),
                                                 ((16, 16, 16), None, 1),
                                                 ((24, 20), (1.0, 0.6), 0)])
