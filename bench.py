@@ -96,8 +96,8 @@ def algorithmic_bytes(kernel, dim, N, n_x, real_bytes):
         "fft_y_forward": 2 * spec,
         "fft_green_axis": 2 * spec,
         "fft_y_inverse": 2 * spec,
-        # spectrum, J^1/2, r read; z written
-        "fft_x_inverse": spec + 3 * field,
+        # spectrum, J^1/2 read; z written (r.z is formed in the Green pass)
+        "fft_x_inverse": spec + 2 * field,
         "diag_precond": 5 * field,
     }
     return table.get(kernel)

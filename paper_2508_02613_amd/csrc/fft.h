@@ -454,27 +454,22 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
   if (threadIdx.x == 0 && partA) partA[blockIdx.x] = s;
 }
 
-// Inverse: t = irfft(X) (unnormalised), z = J^1/2 t (USE_J); partials of r.z.
+// Inverse: t = irfft(X) (unnormalised), z = J^1/2 t (USE_J).  (r.z is
+// formed in the Green pass, so r is not read here.)
 template <typename Real, bool USE_J>
 __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
   using C = typename CxT<Real>::T;
   using R2 = typename CxT<Real>::R2;
   // cell pointers as locals (see cshift)
   const int cell = blockIdx.y;
-  Real *const r = cshift(a.r, cell, a.cs);
-  const Real *const q = cshift(a.q, cell, a.cs);
   const Real *const Jh = cshift(a.Jh, cell, a.cs);
   Real *const out = cshift(a.out, cell, a.cs);
   C *const spec = cshift(a.spec, cell, a.cs);
-  double *const partA = cshift(a.partA, cell, a.cs);
   const CgState *const st = cshift(a.st, cell, a.cs);
-  (void)q;
-  (void)out;
   if (a.check_done && st->done) return;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C *tw = reinterpret_cast<C *>(smem_raw);
   C *buf = tw + a.nx;
-  __shared__ double red[8];
   const int m = a.nx / 2;
   const int RB = a.rows_per_block;
   const int sc = m + 1;
@@ -531,17 +526,16 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
       }
     }
   }
-  // J^1/2 and r for the epilogue: in flight during the transform
+  // J^1/2 for the epilogue: in flight during the transform
   const int tot = RB * m;
   const long long base = row0 * m;
   const long long lim = a.nrows * (long long)m;
-  R2 jv[XP], rv[XP];
+  R2 jv[XP];
 #pragma unroll
   for (int j = 0; j < XP; ++j) {  // unconditional loads at clamped (valid) offsets
     const int f = threadIdx.x + j * FFT_THREADS;
     const long long off = min(base + min(f, tot - 1), lim - 1);
     if (USE_J) jv[j] = reinterpret_cast<const R2 *>(Jh)[off];
-    rv[j] = reinterpret_cast<const R2 *>(r)[off];
   }
   __syncthreads();
   // Z[k] = (X[k] + conj X[m-k]) + i conj(w^k) (X[k] - conj X[m-k]), k < m.
@@ -577,7 +571,6 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
   }
   __syncthreads();
   lds_fft<Real, true>(buf, a.plan, RB, 1, sc, tw, 2, true);
-  double rz = 0.0;
 #pragma unroll
   for (int j = 0; j < XP; ++j) {
     const int f = threadIdx.x + j * FFT_THREADS;
@@ -593,10 +586,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
       t.y *= jv[j].y;
     }
     reinterpret_cast<R2 *>(out)[off] = t;
-    if (partA) rz += (double)rv[j].x * (double)t.x + (double)rv[j].y * (double)t.y;
   }
-  const double s = block_sum<FFT_THREADS>(rz, red);
-  if (threadIdx.x == 0 && partA) partA[blockIdx.x] = s;
 }
 
 // ------------------------------------------------- strided C2C passes ----
@@ -669,6 +659,7 @@ struct GArgs {
   int dim, mx, ntx, ny, nz;
   int check_done;
   long long cs;           // bytes between the cells of a batch (cell = blockIdx.z)
+  double *partB;          // per-block partials of r.z (Parseval, see k_green_axis)
 };
 
 // Green multiply at one frequency: zh = G^(k) sh with G^ = K^_ref(k)^-1 / N,
@@ -789,13 +780,20 @@ __global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
     }
     __syncthreads();
   }
-  // Green multiply on the points this thread holds
+  // Green multiply on the points this thread holds, and r.z by Parseval:
+  // with s = J^1/2 r, t = F^-1 (G^ F s) and z = J^1/2 t, r.z = s.t =
+  // sum over the full spectrum of conj(s^) (G^ s^) (1/N is folded into G^);
+  // on the half spectrum the bins 0 < kx < nx/2 stand for their conjugate
+  // partners too (weight 2), kx = 0 and kx = nx/2 for themselves (weight 1).
+  double rz = 0.0;
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
     const int f = threadIdx.x + j * NT;
     if (f < npts) {
       const int t = f / LN, l = f % LN;
-      const int kx = min(kt * TW + l % TW, a.mx - 1);
+      const int kxu = kt * TW + l % TW;
+      const double wk = kxu >= a.mx ? 0.0 : (kxu == 0 || kxu == a.mx - 1 ? 1.0 : 2.0);
+      const int kx = min(kxu, a.mx - 1);
       if constexpr (DIM == 3) {
         const int ky = ky0 + l / TW;
         const double A[3] = {a.tx.a[kx], a.ty.a[ky], a.tz.a[t]};
@@ -803,14 +801,24 @@ __global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
         const double S[3] = {a.tx.s[kx], a.ty.s[ky], a.tz.s[t]};
         C v[3] = {stash[0][j], stash[1][j], stash[2][j]};
         green3(A, B, S, a.lam, a.mu, a.invN, kx == 0 && ky == 0 && t == 0, v);
-        for (int c = 0; c < 3; ++c) stash[c][j] = v[c];
+        double e = 0.0;
+        for (int c = 0; c < 3; ++c) {
+          e += (double)stash[c][j].x * (double)v[c].x + (double)stash[c][j].y * (double)v[c].y;
+          stash[c][j] = v[c];
+        }
+        rz += wk * e;
       } else {
         const double A[2] = {a.tx.a[kx], a.ty.a[t]};
         const double B[2] = {a.tx.b[kx], a.ty.b[t]};
         const double S[2] = {a.tx.s[kx], a.ty.s[t]};
         C v[2] = {stash[0][j], stash[1][j]};
         green2(A, B, S, a.lam, a.mu, a.invN, kx == 0 && t == 0, v);
-        for (int c = 0; c < 2; ++c) stash[c][j] = v[c];
+        double e = 0.0;
+        for (int c = 0; c < 2; ++c) {
+          e += (double)stash[c][j].x * (double)v[c].x + (double)stash[c][j].y * (double)v[c].y;
+          stash[c][j] = v[c];
+        }
+        rz += wk * e;
       }
     }
   }
@@ -831,6 +839,9 @@ __global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
     }
     __syncthreads();
   }
+  __shared__ double red[NT / 64];
+  const double srz = block_sum<NT>(rz, red);
+  if (threadIdx.x == 0 && a.partB) cshift(a.partB, blockIdx.z, a.cs)[blockIdx.x] = srz;
 }
 
 // ------------------------------------- diagonal / identity preconditioner -

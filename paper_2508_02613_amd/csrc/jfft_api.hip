@@ -364,6 +364,7 @@ long long max_partials(jfft_cell_s *c) {
   const long long rows = (long long)c->dim * g.ny * g.nz;
   mx = std::max(mx, (rows + x_rows_per_block<double>(m) - 1) / x_rows_per_block<double>(m));
   mx = std::max(mx, (g.N + 255) / 256 * 6);  // stress partials [ds][blocks]
+  mx = std::max(mx, (long long)((g.mx + 7) / 8) * (c->dim == 3 ? g.ny : 1));  // Green-pass r.z partials
   return mx;
 }
 
@@ -392,34 +393,47 @@ jfft_status upload_tables(jfft_cell_s *c) {
   return JFFT_OK;
 }
 
-// Kernels that may need more than 64 KiB of dynamic LDS (512-point axes in FP64).
+// Kernels that may need more than 64 KiB of dynamic LDS (512-point axes in
+// FP64): allow the 160 KiB of a CU, less the kernel's static LDS.
 template <typename K>
-void allow_big_lds(K *kernel) {
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+hipError_t allow_big_lds(K *kernel) {
+  hipFuncAttributes fa{};
+  hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(kernel));
+  if (e != hipSuccess) return e;
+  const int dyn = 160 * 1024 - (int)fa.sharedSizeBytes;
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
 }
 
 template <typename Real>
-void allow_big_lds_all() {
-  allow_big_lds(k_ypass<Real, false, 256>);
-  allow_big_lds(k_ypass<Real, true, 256>);
-  allow_big_lds(k_ypass<Real, false, 512>);
-  allow_big_lds(k_ypass<Real, true, 512>);
-  allow_big_lds(k_green_axis<Real, 3, 2, 256>);
-  allow_big_lds(k_green_axis<Real, 3, 2, 512>);
-  allow_big_lds(k_green_axis<Real, 3, 1, 256>);
-  allow_big_lds(k_green_axis<Real, 3, 1, 512>);
-  allow_big_lds(k_green_axis<Real, 2, 1, 256>);
-  allow_big_lds(k_green_axis<Real, 2, 1, 512>);
+hipError_t allow_big_lds_all() {
+  hipError_t e = hipSuccess;
+  auto keep = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  keep(allow_big_lds(k_ypass<Real, false, 256>));
+  keep(allow_big_lds(k_ypass<Real, true, 256>));
+  keep(allow_big_lds(k_ypass<Real, false, 512>));
+  keep(allow_big_lds(k_ypass<Real, true, 512>));
+  keep(allow_big_lds(k_green_axis<Real, 3, 2, 256>));
+  keep(allow_big_lds(k_green_axis<Real, 3, 2, 512>));
+  keep(allow_big_lds(k_green_axis<Real, 3, 1, 256>));
+  keep(allow_big_lds(k_green_axis<Real, 3, 1, 512>));
+  keep(allow_big_lds(k_green_axis<Real, 2, 1, 256>));
+  keep(allow_big_lds(k_green_axis<Real, 2, 1, 512>));
+  return e;
 }
 
-// Kernels that may need more than 64 KiB of dynamic LDS (512-point axes).
-void set_smem_attributes() {
+// Once per process; the result of the first call is kept.
+hipError_t set_smem_attributes() {
   static std::once_flag once;
+  static hipError_t status = hipSuccess;
   std::call_once(once, [] {
-    allow_big_lds_all<double>();
-    allow_big_lds_all<float>();
+    status = allow_big_lds_all<double>();
+    const hipError_t e2 = allow_big_lds_all<float>();
+    if (status == hipSuccess) status = e2;
   });
+  return status;
 }
 
 jfft_status ensure_ready(jfft_cell_s *c) {
@@ -654,11 +668,15 @@ jfft_status launch_ypass(jfft_cell_s *c, typename CxT<Real>::T *spec, bool inv, 
   return JFFT_OK;
 }
 
+// Green pass (last axis): also writes the r.z partials to partB; *nblk
+// receives their number per cell.
 template <typename Real>
-jfft_status launch_green(jfft_cell_s *c, typename CxT<Real>::T *spec, bool check_done) {
+jfft_status launch_green(jfft_cell_s *c, typename CxT<Real>::T *spec, bool check_done,
+                         long long *nblk) {
   using C = typename CxT<Real>::T;
   GArgs<Real> a{};
   a.spec = spec;
+  a.partB = c->partB;
   a.st = c->st;
   const int La = c->dim == 3 ? 2 : 1;
   a.tw = c->tw[La];
@@ -686,6 +704,7 @@ jfft_status launch_green(jfft_cell_s *c, typename CxT<Real>::T *spec, bool check
     const long long pts = (long long)L * KY * TW;
     const size_t smem = sizeof(C) * ((size_t)L + (size_t)pts);
     dim3 gr((unsigned)(a.ntx * (c->g.ny / KY)), 1, c->B);
+    *nblk = gr.x;
     const int nt = tile_threads<Real>(pts);
     if (KY == 2 && nt == 256)
       LAUNCH(c, KID_GREEN, k_green_axis<Real, 3, 2, 256><<<gr, 256, smem, c->stream>>>(a));
@@ -699,6 +718,7 @@ jfft_status launch_green(jfft_cell_s *c, typename CxT<Real>::T *spec, bool check
     const long long pts = (long long)L * TW;
     const size_t smem = sizeof(C) * ((size_t)L + (size_t)pts);
     dim3 gr((unsigned)a.ntx, 1, c->B);
+    *nblk = gr.x;
     if (tile_threads<Real>(pts) == 256)
       LAUNCH(c, KID_GREEN, k_green_axis<Real, 2, 1, 256><<<gr, 256, smem, c->stream>>>(a));
     else
@@ -743,12 +763,13 @@ jfft_status precond(jfft_cell_s *c, Real *r, const Real *q, const Real *Jh, Real
   if (in_loop) LAUNCH(c, KID_CTRL, k_cg_rr<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, *nA, h, c->cs));
   if (c->dim == 3) {
     TRY(launch_ypass<Real>(c, spec, false, in_loop));
-    TRY(launch_green<Real>(c, spec, in_loop));
+    TRY(launch_green<Real>(c, spec, in_loop, nB));
     TRY(launch_ypass<Real>(c, spec, true, in_loop));
   } else {
-    TRY(launch_green<Real>(c, spec, in_loop));
+    TRY(launch_green<Real>(c, spec, in_loop, nB));
   }
-  TRY(launch_xinv<Real>(c, r, J, spec, z, c->partB, in_loop, nB));
+  long long nx_blocks = 0;
+  TRY(launch_xinv<Real>(c, r, J, spec, z, nullptr, in_loop, &nx_blocks));
   if (in_loop) LAUNCH(c, KID_CTRL, k_cg_beta<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partB, *nB, h, c->cs));
   return JFFT_OK;
 }
@@ -1129,8 +1150,8 @@ jfft_status create_impl(int dim, const int n[3], const double len[3], jfft_preci
   factor_plan(g.ny, c->plan_y);
   factor_plan(g.nz, c->plan_z);
   c->npart = max_partials(c);
-  set_smem_attributes();
-  hipError_t e = hipGetDevice(&c->device);
+  hipError_t e = set_smem_attributes();
+  if (e == hipSuccess) e = hipGetDevice(&c->device);
   if (e == hipSuccess && dim == 3) {
     int slots = 0, per_cu = 0;
     e = stiffness_slots(c->device, prec == JFFT_FP64, &slots, &per_cu);
