@@ -466,6 +466,12 @@ StencilArgs<Real> stencil_args(jfft_cell_s *c, const Real *E) {
   a.ihx = (Real)c->g.ihx;
   a.ihy = (Real)c->g.ihy;
   a.ihz = (Real)c->g.ihz;
+  // cubic elements: half of lam, mu times k_c^2 = ih^2 / 3^c (mode class c)
+  for (int k = 0; k < 3; ++k) {
+    const double kc2 = c->g.ihx * c->g.ihx / (k == 0 ? 1.0 : (k == 1 ? 3.0 : 9.0));
+    a.clam[k] = (Real)(0.5 * c->lam * c->g.w * kc2);
+    a.cmu[k] = (Real)(0.5 * c->mu * c->g.w * kc2);
+  }
   a.nx = c->g.nx;
   a.ny = c->g.ny;
   a.nz = c->g.nz;
@@ -477,17 +483,21 @@ StencilArgs<Real> stencil_args(jfft_cell_s *c, const Real *E) {
   return a;
 }
 
+// 3D cells with equal element edges use the cubic form of the element kernel.
+bool cubic_cells(const jfft_cell_s *c) {
+  return c->dim == 3 && c->g.ihx == c->g.ihy && c->g.ihx == c->g.ihz;
+}
+
 // Blocks of the 3D CG stiffness kernel that the device runs at once, and per CU.
-hipError_t stiffness_slots(int device, bool fp64, int *slots, int *per_cu_out) {
+hipError_t stiffness_slots(int device, bool fp64, bool cubic, int *slots, int *per_cu_out) {
   int cus = 0, per_cu = 0;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return e;
-  if (fp64)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stiffness3d<double, SM_CG>,
-                                                     STENCIL3_THREADS, 0);
-  else
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stiffness3d<float, SM_CG>,
-                                                     STENCIL3_THREADS, 0);
+  const void *k = fp64 ? (cubic ? reinterpret_cast<const void *>(k_stiffness3d<double, SM_CG, true>)
+                                : reinterpret_cast<const void *>(k_stiffness3d<double, SM_CG, false>))
+                       : (cubic ? reinterpret_cast<const void *>(k_stiffness3d<float, SM_CG, true>)
+                                : reinterpret_cast<const void *>(k_stiffness3d<float, SM_CG, false>));
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, STENCIL3_THREADS, 0);
   *slots = std::max(1, cus * per_cu);
   *per_cu_out = std::max(1, per_cu);
   return e;
@@ -540,8 +550,10 @@ jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a, int cel
   const GridDev &g = c->g;
   const int tx = stencil_tile_x(c->dim), ty = stencil_tile_y(c->dim);
   dim3 gr((g.nx + tx - 1) / tx, (g.ny + ty - 1) / ty, a.nbz * cells);
-  if (c->dim == 3) {
-    LAUNCH(c, kid, k_stiffness3d<Real, MODE><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a));
+  if (c->dim == 3 && cubic_cells(c)) {
+    LAUNCH(c, kid, (k_stiffness3d<Real, MODE, true><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
+  } else if (c->dim == 3) {
+    LAUNCH(c, kid, (k_stiffness3d<Real, MODE, false><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
   } else {
     LAUNCH(c, kid, k_stiffness2d<Real, MODE><<<gr, STENCIL_THREADS, 0, c->stream>>>(a));
   }
@@ -1154,7 +1166,7 @@ jfft_status create_impl(int dim, const int n[3], const double len[3], jfft_preci
   if (e == hipSuccess) e = hipGetDevice(&c->device);
   if (e == hipSuccess && dim == 3) {
     int slots = 0, per_cu = 0;
-    e = stiffness_slots(c->device, prec == JFFT_FP64, &slots, &per_cu);
+    e = stiffness_slots(c->device, prec == JFFT_FP64, cubic_cells(c), &slots, &per_cu);
     if (e == hipSuccess) {
       c->tun.tz = pick_tz(g, slots, per_cu);
       if ((long long)((g.nz + c->tun.tz - 1) / c->tun.tz) * batch > 65535) {

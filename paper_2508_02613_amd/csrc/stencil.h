@@ -76,6 +76,7 @@ struct StencilArgs {
   long long cs;          // bytes between the cells of a batch
   Real lam, mu;          // Lame constants of C^ times the Gauss weight
   Real ihx, ihy, ihz;
+  Real clam[3], cmu[3];  // cubic elements: half of lam, mu times k_c^2 (see elem_hex_modes_cubic)
   int nx, ny, nz;
   long long N;
 };
@@ -416,6 +417,151 @@ __device__ __forceinline__ void elem_hex_modes(const Real (&u)[3][8], Real lam, 
   if (ENERGY) en += (double)e;
 }
 
+// Cubic elements (h_x = h_y = h_z = h): every term of strain mode m carries
+// the same factor k_|m| = s^|m| / h, so the stress of mode m is k_|m| times
+// the stress of the unscaled modes and the forces take k_|m|^2 times it.
+// Folding k_|m|^2 into the Lame constants of each class |m| = 0, 1, 2
+// (clam[c] = lam k_c^2, cmu[c] = mu k_c^2, without E_e) leaves no scaling
+// multiply: the unscaled difference modes go in, forces come out, and the
+// element energy is the sum of the folded stress times the unscaled strain.
+// Same operator as elem_hex_modes on cubic elements.
+template <typename Real, bool ENERGY>
+__device__ __forceinline__ void elem_hex_modes_cubic(const Real (&u)[3][8], Real Ee,
+                                                     const Real (&clam)[3], const Real (&cmu)[3],
+                                                     Real (&y)[3][8], double &en) {
+  // strain modes (unscaled): X[i][my][mz] = d_x u_i, Y[i][mx][mz], Z[i][mx][my]
+  Real X[3][2][2], Y[3][2][2], Z[3][2][2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const Real *v = u[i];
+    Real h[2][2];
+    had2(v[1] - v[0], v[5] - v[4], v[3] - v[2], v[7] - v[6], h);  // D[cy][cz]
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) X[i][a][b] = h[a][b];
+    had2(v[2] - v[0], v[6] - v[4], v[3] - v[1], v[7] - v[5], h);  // D[cx][cz]
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) Y[i][a][b] = h[a][b];
+    had2(v[4] - v[0], v[6] - v[2], v[5] - v[1], v[7] - v[3], h);  // D[cx][cy]
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) Z[i][a][b] = h[a][b];
+  }
+  Real lc[3], mc[3], m2c[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    lc[c] = Ee * clam[c];
+    mc[c] = Ee * cmu[c];
+    m2c[c] = mc[c] + mc[c];
+  }
+  Real e = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) y[i][c] = (Real)0;
+  // One family of modes at a time: the x family (modes with m_x = 0) carries
+  // the stresses sigma_1j that the x forces of all three components need, etc.
+  // x family: modes (0, my = a, mz = b)
+  {
+    Real S[3][2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const Real tr = X[0][a][b] + (a == 0 ? Y[1][0][b] : (Real)0) + (b == 0 ? Z[2][0][a] : (Real)0);
+        const Real g12 = X[1][a][b] + (a == 0 ? Y[0][0][b] : (Real)0);
+        const Real g13 = X[2][a][b] + (b == 0 ? Z[0][0][a] : (Real)0);
+        S[0][a][b] = lc[a + b] * tr + m2c[a + b] * X[0][a][b];
+        S[1][a][b] = mc[a + b] * g12;
+        S[2][a][b] = mc[a + b] * g13;
+        if (ENERGY) e += S[0][a][b] * X[0][a][b] + S[1][a][b] * g12 + S[2][a][b] * g13;
+      }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      Real R[2][2];  // R[cy][cz]
+      had2(S[i][0][0], S[i][0][1], S[i][1][0], S[i][1][1], R);
+      y[i][1] += R[0][0];
+      y[i][0] -= R[0][0];
+      y[i][5] += R[0][1];
+      y[i][4] -= R[0][1];
+      y[i][3] += R[1][0];
+      y[i][2] -= R[1][0];
+      y[i][7] += R[1][1];
+      y[i][6] -= R[1][1];
+    }
+  }
+  // y family: modes (mx = a, 0, mz = b); components sigma_21, sigma_22, sigma_23
+  {
+    Real S[3][2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const Real tr = Y[1][a][b] + (a == 0 ? X[0][0][b] : (Real)0) + (b == 0 ? Z[2][a][0] : (Real)0);
+        const Real g12 = Y[0][a][b] + (a == 0 ? X[1][0][b] : (Real)0);
+        const Real g23 = Y[2][a][b] + (b == 0 ? Z[1][a][0] : (Real)0);
+        S[0][a][b] = mc[a + b] * g12;
+        S[1][a][b] = lc[a + b] * tr + m2c[a + b] * Y[1][a][b];
+        S[2][a][b] = mc[a + b] * g23;
+        if (ENERGY) {
+          e += S[1][a][b] * Y[1][a][b] + S[2][a][b] * g23;
+          if (a == 1) e += S[0][a][b] * g12;  // modes (1, 0, mz); (0, 0, mz) counted in x
+        }
+      }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      Real R[2][2];  // R[cx][cz]
+      had2(S[i][0][0], S[i][0][1], S[i][1][0], S[i][1][1], R);
+      y[i][2] += R[0][0];
+      y[i][0] -= R[0][0];
+      y[i][6] += R[0][1];
+      y[i][4] -= R[0][1];
+      y[i][3] += R[1][0];
+      y[i][1] -= R[1][0];
+      y[i][7] += R[1][1];
+      y[i][5] -= R[1][1];
+    }
+  }
+  // z family: modes (mx = a, my = b, 0); components sigma_31, sigma_32, sigma_33
+  {
+    Real S[3][2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const Real tr = Z[2][a][b] + (a == 0 ? X[0][b][0] : (Real)0) + (b == 0 ? Y[1][a][0] : (Real)0);
+        const Real g13 = Z[0][a][b] + (a == 0 ? X[2][b][0] : (Real)0);
+        const Real g23 = Z[1][a][b] + (b == 0 ? Y[2][a][0] : (Real)0);
+        S[0][a][b] = mc[a + b] * g13;
+        S[1][a][b] = mc[a + b] * g23;
+        S[2][a][b] = lc[a + b] * tr + m2c[a + b] * Z[2][a][b];
+        if (ENERGY) {
+          e += S[2][a][b] * Z[2][a][b];
+          if (a == 1) e += S[0][a][b] * g13;  // modes (1, my, 0); (0, my, 0) counted in x
+          if (b == 1) e += S[1][a][b] * g23;  // modes (mx, 1, 0); (mx, 0, 0) counted in y
+        }
+      }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      Real R[2][2];  // R[cx][cy]
+      had2(S[i][0][0], S[i][0][1], S[i][1][0], S[i][1][1], R);
+      y[i][4] += R[0][0];
+      y[i][0] -= R[0][0];
+      y[i][6] += R[0][1];
+      y[i][2] -= R[0][1];
+      y[i][5] += R[1][0];
+      y[i][1] -= R[1][0];
+      y[i][7] += R[1][1];
+      y[i][3] -= R[1][1];
+    }
+  }
+  if (ENERGY) en += (double)e;
+}
+
 // Block reduction of one double per thread; result valid in thread 0.
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double *sm) {
@@ -448,7 +594,7 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
 // each 18 x 16 node plane (columns 1..16, which hold every owned node) and,
 // if t < 224, output node (t & 15) + 1, (t >> 4) + 1.  Columns 0 and 17 of
 // a plane are loaded by threads 0..31.
-template <typename Real, int MODE>
+template <typename Real, int MODE, bool CUBIC = false>
 __global__ void __launch_bounds__(STENCIL3_THREADS, stencil3_waves_per_simd<Real>())
     k_stiffness3d(StencilArgs<Real> a) {
   __shared__ Real P[3][3][NNODE3];               // ring of three node planes of the input vector
@@ -635,8 +781,11 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, stencil3_waves_per_simd<Real
       }
       double en = 0.0;
       // a.lam, a.mu carry the full Gauss weight; the mode form takes half
-      elem_hex_modes<Real, MODE == SM_CG>(uv, Ecur * a.lam * (Real)0.5, Ecur * a.mu * (Real)0.5,
-                                          a.ihx, a.ihy, a.ihz, yv, en);
+      if constexpr (CUBIC)
+        elem_hex_modes_cubic<Real, MODE == SM_CG>(uv, Ecur, a.clam, a.cmu, yv, en);
+      else
+        elem_hex_modes<Real, MODE == SM_CG>(uv, Ecur * a.lam * (Real)0.5, Ecur * a.mu * (Real)0.5,
+                                            a.ihx, a.ihy, a.ihz, yv, en);
       if (elem_owned && ez >= z0) acc += en;
 #pragma unroll
       for (int c = 0; c < 8; ++c)
