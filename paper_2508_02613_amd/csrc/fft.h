@@ -667,35 +667,38 @@ struct GArgs {
 // integration is real symmetric:
 //   K_ii = (lam + 2 mu) a_i prod_{j != i} b_j + mu sum_{j != i} a_j prod_{l != j} b_l
 //   K_ij = (lam + mu) s_i s_j prod_{l != i, j} b_l.
-template <typename C>
-__device__ __forceinline__ void green3(const double (&A)[3], const double (&B)[3],
-                                       const double (&S)[3], double lam, double mu, double invN,
-                                       bool zero, C (&v)[3]) {
+// The symbol is evaluated in the precision of the pass (T: float in the
+// mixed path, whose spectrum is FP32; double otherwise).  K^_ref(k) is SPD
+// for k != 0 with a condition number bounded by the Lame ratio and the
+// symbol's anisotropy, so its cofactor inverse loses only a few bits.
+template <typename T, typename C>
+__device__ __forceinline__ void green3(const T (&A)[3], const T (&B)[3], const T (&S)[3], T lam,
+                                       T mu, T invN, bool zero, C (&v)[3]) {
   if (zero) {
     for (int i = 0; i < 3; ++i) v[i].x = v[i].y = 0;
     return;
   }
-  const double l2m = lam + 2.0 * mu, lm = lam + mu;
-  const double abb = A[0] * B[1] * B[2], bab = B[0] * A[1] * B[2], bba = B[0] * B[1] * A[2];
-  const double k00 = l2m * abb + mu * (bab + bba);
-  const double k11 = l2m * bab + mu * (abb + bba);
-  const double k22 = l2m * bba + mu * (abb + bab);
-  const double k01 = lm * S[0] * S[1] * B[2];
-  const double k02 = lm * S[0] * B[1] * S[2];
-  const double k12 = lm * B[0] * S[1] * S[2];
+  const T l2m = lam + (T)2 * mu, lm = lam + mu;
+  const T abb = A[0] * B[1] * B[2], bab = B[0] * A[1] * B[2], bba = B[0] * B[1] * A[2];
+  const T k00 = l2m * abb + mu * (bab + bba);
+  const T k11 = l2m * bab + mu * (abb + bba);
+  const T k22 = l2m * bba + mu * (abb + bab);
+  const T k01 = lm * S[0] * S[1] * B[2];
+  const T k02 = lm * S[0] * B[1] * S[2];
+  const T k12 = lm * B[0] * S[1] * S[2];
   // symmetric inverse by cofactors
-  const double c00 = k11 * k22 - k12 * k12;
-  const double c01 = k02 * k12 - k01 * k22;
-  const double c02 = k01 * k12 - k02 * k11;
-  const double c11 = k00 * k22 - k02 * k02;
-  const double c12 = k01 * k02 - k00 * k12;
-  const double c22 = k00 * k11 - k01 * k01;
-  const double det = k00 * c00 + k01 * c01 + k02 * c02;
-  const double sc = invN / det;
-  const double g00 = c00 * sc, g01 = c01 * sc, g02 = c02 * sc;
-  const double g11 = c11 * sc, g12 = c12 * sc, g22 = c22 * sc;
-  const double x0 = v[0].x, x1 = v[1].x, x2 = v[2].x;
-  const double y0 = v[0].y, y1 = v[1].y, y2 = v[2].y;
+  const T c00 = k11 * k22 - k12 * k12;
+  const T c01 = k02 * k12 - k01 * k22;
+  const T c02 = k01 * k12 - k02 * k11;
+  const T c11 = k00 * k22 - k02 * k02;
+  const T c12 = k01 * k02 - k00 * k12;
+  const T c22 = k00 * k11 - k01 * k01;
+  const T det = k00 * c00 + k01 * c01 + k02 * c02;
+  const T sc = invN / det;
+  const T g00 = c00 * sc, g01 = c01 * sc, g02 = c02 * sc;
+  const T g11 = c11 * sc, g12 = c12 * sc, g22 = c22 * sc;
+  const T x0 = v[0].x, x1 = v[1].x, x2 = v[2].x;
+  const T y0 = v[0].y, y1 = v[1].y, y2 = v[2].y;
   v[0].x = g00 * x0 + g01 * x1 + g02 * x2;
   v[0].y = g00 * y0 + g01 * y1 + g02 * y2;
   v[1].x = g01 * x0 + g11 * x1 + g12 * x2;
@@ -704,21 +707,20 @@ __device__ __forceinline__ void green3(const double (&A)[3], const double (&B)[3
   v[2].y = g02 * y0 + g12 * y1 + g22 * y2;
 }
 
-template <typename C>
-__device__ __forceinline__ void green2(const double (&A)[2], const double (&B)[2],
-                                       const double (&S)[2], double lam, double mu, double invN,
-                                       bool zero, C (&v)[2]) {
+template <typename T, typename C>
+__device__ __forceinline__ void green2(const T (&A)[2], const T (&B)[2], const T (&S)[2], T lam,
+                                       T mu, T invN, bool zero, C (&v)[2]) {
   if (zero) {
     for (int i = 0; i < 2; ++i) v[i].x = v[i].y = 0;
     return;
   }
-  const double l2m = lam + 2.0 * mu, lm = lam + mu;
-  const double k00 = l2m * A[0] * B[1] + mu * B[0] * A[1];
-  const double k11 = mu * A[0] * B[1] + l2m * B[0] * A[1];
-  const double k01 = lm * S[0] * S[1];
-  const double sc = invN / (k00 * k11 - k01 * k01);
-  const double g00 = k11 * sc, g11 = k00 * sc, g01 = -k01 * sc;
-  const double x0 = v[0].x, x1 = v[1].x, y0 = v[0].y, y1 = v[1].y;
+  const T l2m = lam + (T)2 * mu, lm = lam + mu;
+  const T k00 = l2m * A[0] * B[1] + mu * B[0] * A[1];
+  const T k11 = mu * A[0] * B[1] + l2m * B[0] * A[1];
+  const T k01 = lm * S[0] * S[1];
+  const T sc = invN / (k00 * k11 - k01 * k01);
+  const T g00 = k11 * sc, g11 = k00 * sc, g01 = -k01 * sc;
+  const T x0 = v[0].x, x1 = v[1].x, y0 = v[0].y, y1 = v[1].y;
   v[0].x = g00 * x0 + g01 * x1;
   v[0].y = g00 * y0 + g01 * y1;
   v[1].x = g01 * x0 + g11 * x1;
@@ -796,11 +798,12 @@ __global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
       const int kx = min(kxu, a.mx - 1);
       if constexpr (DIM == 3) {
         const int ky = ky0 + l / TW;
-        const double A[3] = {a.tx.a[kx], a.ty.a[ky], a.tz.a[t]};
-        const double B[3] = {a.tx.b[kx], a.ty.b[ky], a.tz.b[t]};
-        const double S[3] = {a.tx.s[kx], a.ty.s[ky], a.tz.s[t]};
+        const Real A[3] = {(Real)a.tx.a[kx], (Real)a.ty.a[ky], (Real)a.tz.a[t]};
+        const Real B[3] = {(Real)a.tx.b[kx], (Real)a.ty.b[ky], (Real)a.tz.b[t]};
+        const Real S[3] = {(Real)a.tx.s[kx], (Real)a.ty.s[ky], (Real)a.tz.s[t]};
         C v[3] = {stash[0][j], stash[1][j], stash[2][j]};
-        green3(A, B, S, a.lam, a.mu, a.invN, kx == 0 && ky == 0 && t == 0, v);
+        green3<Real>(A, B, S, (Real)a.lam, (Real)a.mu, (Real)a.invN,
+                     kx == 0 && ky == 0 && t == 0, v);
         double e = 0.0;
         for (int c = 0; c < 3; ++c) {
           e += (double)stash[c][j].x * (double)v[c].x + (double)stash[c][j].y * (double)v[c].y;
@@ -808,11 +811,11 @@ __global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
         }
         rz += wk * e;
       } else {
-        const double A[2] = {a.tx.a[kx], a.ty.a[t]};
-        const double B[2] = {a.tx.b[kx], a.ty.b[t]};
-        const double S[2] = {a.tx.s[kx], a.ty.s[t]};
+        const Real A[2] = {(Real)a.tx.a[kx], (Real)a.ty.a[t]};
+        const Real B[2] = {(Real)a.tx.b[kx], (Real)a.ty.b[t]};
+        const Real S[2] = {(Real)a.tx.s[kx], (Real)a.ty.s[t]};
         C v[2] = {stash[0][j], stash[1][j]};
-        green2(A, B, S, a.lam, a.mu, a.invN, kx == 0 && t == 0, v);
+        green2<Real>(A, B, S, (Real)a.lam, (Real)a.mu, (Real)a.invN, kx == 0 && t == 0, v);
         double e = 0.0;
         for (int c = 0; c < 2; ++c) {
           e += (double)stash[c][j].x * (double)v[c].x + (double)stash[c][j].y * (double)v[c].y;
