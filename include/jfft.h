@@ -240,7 +240,7 @@ jfft_status jfft_set_void_value(jfft_cell_t cell, double value);
 jfft_status jfft_set_stop_rule(jfft_cell_t cell, int rule);
 
 /* Mixed precision controls: relative tolerance of each inner FP32 PCG solve
-   (default 1e-5) and the cap on refinement sweeps (default 30). */
+   (default 1e-6) and the cap on refinement sweeps (default 30). */
 jfft_status jfft_set_mixed_params(jfft_cell_t cell, double inner_tol, int max_outer);
 
 void jfft_destroy_cell(jfft_cell_t cell);

@@ -238,7 +238,7 @@ class Cell:
         """absolute=False: ||r|| <= tol ||f||; True: ||r||^2 <= tol (the paper's runs)."""
         _check(self._lib.jfft_set_stop_rule(self._h, 1 if absolute else 0))
 
-    def set_mixed_params(self, inner_tol=1e-5, max_outer=30):
+    def set_mixed_params(self, inner_tol=1e-6, max_outer=30):
         _check(self._lib.jfft_set_mixed_params(self._h, float(inner_tol), int(max_outer)))
 
     def solve(self, macro, tol=1e-8, maxit=1000, u0=None, want_sigma=False, out=None):

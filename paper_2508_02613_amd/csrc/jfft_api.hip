@@ -156,7 +156,7 @@ struct jfft_cell_s {
   bool has_material = false;
   double lam = 0, mu = 0;
   double void_value = 1.0;
-  double inner_tol = 1e-5;
+  double inner_tol = 1e-6;
   int max_outer = 30;
   bool stop_abs = false;  // stopping rule ||r||^2 <= tol instead of ||r|| <= tol ||f||
   int diag_method = JFFT_DIAG_CLOSED_FORM;  // how J^1/2 is formed (Algorithm 2 or its closed form)
