@@ -621,21 +621,18 @@ jfft_status launch_xfwd(jfft_cell_s *c, Real *r, const Real *q, const Real *Jh,
   return JFFT_OK;
 }
 
+// Inverse x pass: out = J^1/2 irfft_x(spec) (r.z comes from the Green pass).
 template <typename Real>
-jfft_status launch_xinv(jfft_cell_s *c, const Real *r, const Real *Jh,
-                        typename CxT<Real>::T *spec, Real *out, double *partB, bool check_done,
-                        long long *nblk) {
+jfft_status launch_xinv(jfft_cell_s *c, const Real *Jh, typename CxT<Real>::T *spec, Real *out,
+                        bool check_done) {
   using C = typename CxT<Real>::T;
   XArgs<Real> a = x_args<Real>(c, check_done);
-  a.r = const_cast<Real *>(r);
   a.Jh = Jh;
   a.out = out;
   a.spec = spec;
-  a.partA = partB;
   const int m = c->g.nx / 2;
   const long long nb = (a.nrows + a.rows_per_block - 1) / a.rows_per_block;
   const size_t smem = sizeof(C) * (c->g.nx + (size_t)a.rows_per_block * (m + 1));
-  *nblk = nb;
   dim3 gr((unsigned)nb, c->B);
   if (Jh)
     LAUNCH(c, KID_XINV, k_xinv<Real, true><<<gr, FFT_THREADS, smem, c->stream>>>(a));
@@ -780,8 +777,7 @@ jfft_status precond(jfft_cell_s *c, Real *r, const Real *q, const Real *Jh, Real
   } else {
     TRY(launch_green<Real>(c, spec, in_loop, nB));
   }
-  long long nx_blocks = 0;
-  TRY(launch_xinv<Real>(c, r, J, spec, z, nullptr, in_loop, &nx_blocks));
+  TRY(launch_xinv<Real>(c, J, spec, z, in_loop));
   if (in_loop) LAUNCH(c, KID_CTRL, k_cg_beta<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partB, *nB, h, c->cs));
   return JFFT_OK;
 }
