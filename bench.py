@@ -352,7 +352,9 @@ def run_contrast_sweep(args):
         row = {"contrast": contrast}
         us = {}
         for name, prec in (("mixed", pkg.MIXED), ("fp64", pkg.FP64)):
-            cell = pkg.Cell(shape, precision=prec)
+            cell = pkg.Cell(shape, precision=prec, stream=torch.cuda.Stream())
+            if args.graph:
+                cell.set_graph_iterations(args.graph)
             cell.set_material(Ed, nu=0.3)
             cell.solve(macro, tol=1e-8, maxit=20000)  # warm-up
             torch.cuda.synchronize()
@@ -368,8 +370,10 @@ def run_contrast_sweep(args):
         d = torch.linalg.vector_norm(us["mixed"] - us["fp64"]) / torch.linalg.vector_norm(us["fp64"])
         row["u_rel_diff_mixed_vs_fp64"] = float(d)
         del us
-        Cm, rm = pkg.effective_stiffness(Ed, nu=0.3, tol=1e-8, precision=pkg.MIXED)
-        C64, r64 = pkg.effective_stiffness(Ed, nu=0.3, tol=1e-8, precision=pkg.FP64)
+        Cm, rm = pkg.effective_stiffness(Ed, nu=0.3, tol=1e-8, precision=pkg.MIXED,
+                                         stream=torch.cuda.Stream(), graph_iterations=args.graph)
+        C64, r64 = pkg.effective_stiffness(Ed, nu=0.3, tol=1e-8, precision=pkg.FP64,
+                                           stream=torch.cuda.Stream(), graph_iterations=args.graph)
         row["ceff_rel_diff_mixed_vs_fp64"] = float(np.abs(Cm - C64).max() / np.abs(C64).max())
         row["ceff_iters_mixed"] = [r.iters for r in rm]
         row["ceff_iters_fp64"] = [r.iters for r in r64]
