@@ -24,6 +24,7 @@ __all__ = [
     "node_coords", "sine_contrast_field", "grf_field", "simp_field",
     "laminate_field", "cosine_void_field", "filtered_inclusion_field",
     "uniform_random_field", "random_start", "unit_macro_strain", "mandel_size",
+    "spherical_inclusions",
 ]
 
 
@@ -164,3 +165,24 @@ def unit_macro_strain(dim: int, gamma: int) -> np.ndarray:
     e = np.zeros(mandel_size(dim))
     e[gamma] = 1.0
     return e
+
+
+def spherical_inclusions(shape, count: int, radius: float, seed: int) -> np.ndarray:
+    """Indicator (1 inside, 0 outside) of `count` spheres of radius `radius`
+    (fraction of the unit cell) at seeded random centres, periodic minimum-image
+    distance, sampled at each element's lowest node: a stand-in for the
+    inclusion geometry of the nonlinear example, which the paper does not give."""
+    rng = np.random.default_rng(seed)
+    shape = tuple(int(s) for s in shape)
+    axes = np.meshgrid(*[np.arange(n) / n for n in shape], indexing="ij")  # (z, y, x)
+    out = np.zeros(shape)
+    for _ in range(int(count)):
+        c = rng.random(len(shape))
+        d2 = np.zeros(shape)
+        for a, ca in zip(axes, c):
+            d = np.abs(a - ca)
+            d = np.minimum(d, 1.0 - d)
+            d2 += d * d
+        out[d2 <= radius * radius] = 1.0
+    return out
+
