@@ -390,8 +390,8 @@ def run_contrast_sweep(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU: --gpus {args.gpus} is not supported (this "
-              "solver build targets a single MI355X; see DESIGN.md for how the path would shard)",
+        print(f"bench.py runs on exactly one GPU: --gpus {args.gpus} is not supported (the "
+              "solver runs each cell or cell group on one MI355X; there is no multi-GPU path)",
               file=sys.stderr)
         sys.exit(2)
     import torch
