@@ -243,6 +243,49 @@ jfft_status jfft_set_stop_rule(jfft_cell_t cell, int rule);
    (default 1e-6) and the cap on refinement sweeps (default 30). */
 jfft_status jfft_set_mixed_params(jfft_cell_t cell, double inner_tol, int max_outer);
 
+/* ---- Power-law material and Newton solve (nonlinear example, Sec. 4;
+   Newton linearisation, Sec. 2.2, eq. lin_system) -------------------------
+   Single 3D FP64 cell only (else JFFT_E_INVALID).
+   jfft_set_material_powerlaw: phase_dev [N] on the device, element phase
+   (entries > 0.5: matrix, else inclusion; negative or non-finite entries:
+   JFFT_E_INVALID); copied, the caller keeps ownership.  Matrix: sigma =
+   K tr(eps) I + g(eps_eq) dev(eps), g(s) = sigma0 (2/3) s^(n-1) / eps0^n,
+   eps_eq = sqrt(2/3 dev(eps):dev(eps)); inclusion: sigma = K_incl tr(eps) I +
+   2 mu_incl dev(eps).  Needs K, sigma0, eps0, K_incl, mu_incl > 0, n >= 1.
+   The Green reference material is the inclusion's (lambda = K_incl -
+   2 mu_incl / 3, mu = mu_incl); the Jacobi factor, if the preconditioner
+   has one, is Algorithm 2 on the tangent K(u) at every Newton step.  The
+   handle allocates one [3][N] iterate on first use (freed with the handle).
+   A later jfft_set_material returns the handle to the linear problem; the
+   linear entry points report JFFT_E_NO_MATERIAL while the power-law
+   material is set. */
+jfft_status jfft_set_material_powerlaw(jfft_cell_t cell, const double *phase_dev, double K,
+                                       double sigma0, double eps0, double n, double K_incl,
+                                       double mu_incl);
+/* Newton from u = 0 on f(u) = -B^T W sigma(E + B u): stop when ||f||_2 <
+   newton_tol, else solve K(u) du = f(u) by PCG from du = 0 to relative
+   residual max(pcg_tol, newton_tol / (10 ||f||)) (at most maxit iterations;
+   a PCG breakdown ends that inner solve and the step goes on) and set
+   u += du; at most max_newton steps.  Outputs: u_dev [3][N] device (mean
+   removed, Sec. 5), sigma_bar[6] host (volume average of sigma(E + B u),
+   Mandel), and optionally (host, may be NULL) pcg_iters[max_newton] (PCG
+   iterations per step), res_norms[max_newton + 1] (||f|| before each step
+   and at the end) and *steps (Newton steps taken).  Returns JFFT_OK when
+   converged, else JFFT_E_NOT_CONVERGED with every output written. */
+jfft_status jfft_solve_newton(jfft_cell_t cell, const double *macro_strain, double newton_tol,
+                              double pcg_tol, int max_newton, int maxit, double *u_dev,
+                              double *sigma_bar, int *pcg_iters, double *res_norms, int *steps);
+/* Operators of a Newton step at the iterate uk_dev [3][N] (device) for the
+   macroscopic strain macro_strain[6] (host): f = -B^T W sigma(E + B uk);
+   out = K(uk) in; diag(K(uk)) by Algorithm 2 (no void rule).  Device
+   outputs [3][N]; synchronous. */
+jfft_status jfft_powerlaw_force(jfft_cell_t cell, const double *macro_strain, const double *uk_dev,
+                                double *f_dev);
+jfft_status jfft_powerlaw_tangent(jfft_cell_t cell, const double *macro_strain, const double *uk_dev,
+                                  const double *in_dev, double *out_dev);
+jfft_status jfft_powerlaw_jacobi_diag(jfft_cell_t cell, const double *macro_strain,
+                                      const double *uk_dev, double *diag_dev);
+
 void jfft_destroy_cell(jfft_cell_t cell);
 const char *jfft_last_error(void);
 const char *jfft_version(void);

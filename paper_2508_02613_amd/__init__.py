@@ -78,6 +78,13 @@ _SIGS = {
     "jfft_set_mixed_params": (C.c_int, [_vp, C.c_double, C.c_int]),
     "jfft_set_stop_rule": (C.c_int, [_vp, C.c_int]),
     "jfft_set_diag_method": (C.c_int, [_vp, C.c_int]),
+    "jfft_set_material_powerlaw": (C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double,
+                                             C.c_double, C.c_double, C.c_double]),
+    "jfft_solve_newton": (C.c_int, [_vp, _dp, C.c_double, C.c_double, C.c_int, C.c_int, _vp, _dp,
+                                    C.POINTER(C.c_int), _dp, C.POINTER(C.c_int)]),
+    "jfft_powerlaw_force": (C.c_int, [_vp, _dp, _vp, _vp]),
+    "jfft_powerlaw_tangent": (C.c_int, [_vp, _dp, _vp, _vp, _vp]),
+    "jfft_powerlaw_jacobi_diag": (C.c_int, [_vp, _dp, _vp, _vp]),
     "jfft_destroy_cell": (None, [_vp]),
     "jfft_last_error": (C.c_char_p, []),
     "jfft_version": (C.c_char_p, []),
@@ -121,6 +128,16 @@ def _check(st):
     if st != 0:
         msg = _lib.jfft_last_error().decode(errors="replace")
         raise JfftError(st, msg)
+
+
+@dataclass
+class NewtonReport:
+    """Outcome of solve_newton: Newton steps, convergence, PCG iterations per
+    step and ||f|| before each step (and at the end)."""
+    steps: int
+    converged: bool
+    pcg_iters: list
+    res: list
 
 
 @dataclass
@@ -322,6 +339,64 @@ class Cell:
         out = self.torch.empty((self.dim,) + self.shape, dtype=self.torch.float64, device=self.device)
         _check(self._lib.jfft_jacobi_diag(self._h, _ptr(out)))
         self.stream.synchronize()
+        return out
+
+    # ------------------------------------------- power-law Newton (Sec. 4)
+    def set_material_powerlaw(self, phase, K=2.0, sigma0=0.5, eps0=0.1, n=5.0, K_incl=2.0,
+                              mu_incl=0.5):
+        """phase [nz, ny, nx]: 1 = power-law matrix, 0 = linear inclusion."""
+        ph = self._dev(phase, self.shape)
+        self._E = ph
+        _check(self._lib.jfft_set_material_powerlaw(self._h, _ptr(ph), float(K), float(sigma0),
+                                                    float(eps0), float(n), float(K_incl),
+                                                    float(mu_incl)))
+
+    def solve_newton(self, macro, newton_tol=1e-5, pcg_tol=1e-8, max_newton=20, maxit=5000,
+                     out=None):
+        """Newton from u = 0.  Returns (u [3, ...] device tensor (mean removed),
+        sigma_bar numpy [6], NewtonReport)."""
+        torch = self.torch
+        u = out if out is not None else torch.empty((3,) + self.shape, dtype=torch.float64,
+                                                    device=self.device)
+        m = (C.c_double * 6)(*[float(v) for v in np.asarray(macro, dtype=float)])
+        sbar = (C.c_double * 6)()
+        its = (C.c_int * max(1, int(max_newton)))()
+        res = (C.c_double * (int(max_newton) + 1))()
+        steps = C.c_int(0)
+        st = self._lib.jfft_solve_newton(self._h, m, float(newton_tol), float(pcg_tol),
+                                         int(max_newton), int(maxit), _ptr(u), sbar, its, res,
+                                         C.byref(steps))
+        if st not in (0, 4):
+            _check(st)
+        k = int(steps.value)
+        rep = NewtonReport(steps=k, converged=st == 0, pcg_iters=[int(v) for v in its[:k]],
+                           res=[float(v) for v in res[:k + 1]])
+        return u, np.array(sbar[:]), rep
+
+    def _pl_args(self, macro, uk):
+        m = (C.c_double * 6)(*[float(v) for v in np.asarray(macro, dtype=float)])
+        return m, self._dev(uk, (3,) + self.shape)
+
+    def powerlaw_force(self, macro, uk):
+        """f = -B^T W sigma(E + B uk)."""
+        m, ukt = self._pl_args(macro, uk)
+        out = self.torch.empty_like(ukt)
+        _check(self._lib.jfft_powerlaw_force(self._h, m, _ptr(ukt), _ptr(out)))
+        return out
+
+    def powerlaw_tangent(self, macro, uk, x):
+        """K(uk) x."""
+        m, ukt = self._pl_args(macro, uk)
+        x = self._dev(x, (3,) + self.shape)
+        out = self.torch.empty_like(x)
+        _check(self._lib.jfft_powerlaw_tangent(self._h, m, _ptr(ukt), _ptr(x), _ptr(out)))
+        return out
+
+    def powerlaw_jacobi_diag(self, macro, uk):
+        """diag(K(uk)) by Algorithm 2."""
+        m, ukt = self._pl_args(macro, uk)
+        out = self.torch.empty_like(ukt)
+        _check(self._lib.jfft_powerlaw_jacobi_diag(self._h, m, _ptr(ukt), _ptr(out)))
         return out
 
     def enable_history(self, cap):

@@ -345,6 +345,14 @@ __global__ void k_copy(const Real *a, long long as, Real *b, long long bs, long 
     b[i] = a[i];
 }
 
+// b += a (single cell).
+template <typename Real>
+__global__ void k_add(const Real *a, Real *b, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    b[i] += a[i];
+}
+
 template <typename Real>
 __global__ void k_fill(Real *a, Real v, long long n, long long cs) {
   a = cshift(a, blockIdx.y, cs);

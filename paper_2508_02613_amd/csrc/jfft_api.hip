@@ -161,6 +161,13 @@ struct jfft_cell_s {
   bool stop_abs = false;  // stopping rule ||r||^2 <= tol instead of ||r|| <= tol ||f||
   int diag_method = JFFT_DIAG_CLOSED_FORM;  // how J^1/2 is formed (Algorithm 2 or its closed form)
 
+  // power-law material (nonlinear example): E holds the phase, lam and mu the
+  // Green reference (the inclusion); uk is the Newton iterate, allocated on
+  // first use and owned by the handle
+  bool nl = false;
+  PowerLawArgs pl{};
+  double *uk = nullptr;
+
   // captured iteration chunks
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // [0] FP64, [1] FP32 inner
   int gexec_iters[2] = {0, 0};
@@ -194,6 +201,7 @@ struct jfft_cell_s {
     for (auto &e : phase_ev)
       if (e) (void)hipEventDestroy(e);
     if (ws_owned && ws) (void)hipFree(ws);
+    if (uk) (void)hipFree(uk);
     if (st_h) (void)hipHostFree(st_h);
     if (small_h) (void)hipHostFree(small_h);
   }
@@ -480,6 +488,13 @@ StencilArgs<Real> stencil_args(jfft_cell_s *c, const Real *E) {
   a.nbz = c->dim == 3 ? (c->g.nz + a.tz - 1) / a.tz : 1;
   a.cs = c->cs;
   a.st = c->st;
+  if constexpr (std::is_same<Real, double>::value) {
+    if (c->nl) {
+      a.uk = c->uk;
+      a.pl = c->pl;
+      a.w = c->g.w;
+    }
+  }
   return a;
 }
 
@@ -550,6 +565,15 @@ jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a, int cel
   const GridDev &g = c->g;
   const int tx = stencil_tile_x(c->dim), ty = stencil_tile_y(c->dim);
   dim3 gr((g.nx + tx - 1) / tx, (g.ny + ty - 1) / ty, a.nbz * cells);
+  if (c->nl) {
+    // the power-law tangent exists for 3D FP64 cells only (checked when the
+    // material is set)
+    if constexpr (std::is_same<Real, double>::value) {
+      LAUNCH(c, kid, (k_stiffness3d<double, MODE, false, 1><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
+      return JFFT_OK;
+    }
+    return fail(JFFT_E_INVALID, "the power-law tangent runs in FP64 only");
+  }
   if (c->dim == 3 && cubic_cells(c)) {
     LAUNCH(c, kid, (k_stiffness3d<Real, MODE, true><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
   } else if (c->dim == 3) {
@@ -951,6 +975,10 @@ jfft_status set_material_impl(jfft_cell_s *c, const double *E_dev, double lam, d
   if (!(mu > 0.0) || !(lam + 2.0 * mu / c->dim > 0.0) || !std::isfinite(lam) || !std::isfinite(mu))
     return fail(JFFT_E_INVALID, "Lame constants must satisfy mu > 0 and lambda + 2 mu / d > 0");
   TRY(ensure_ready(c));
+  if (c->nl) {  // back from the power-law material: its captured kernels differ
+    c->nl = false;
+    c->drop_graphs();
+  }
   // captured iterations carry lambda and mu as kernel arguments; the moduli
   // are read from the workspace, so a new E alone keeps them valid
   if (c->lam != lam || c->mu != mu) c->drop_graphs();
@@ -1100,6 +1128,162 @@ jfft_status solve_impl(jfft_cell_s *c, const double *macros_h, double tol, int m
   if (worst == JFFT_E_NOT_CONVERGED) g_last_error = "PCG reached maxit";
   if (worst == JFFT_E_BREAKDOWN) g_last_error = "PCG breakdown (p.q <= 0 or non-finite scalar)";
   return (jfft_status)worst;
+}
+
+// ------------------------------------------------- power-law Newton solve
+// The nonlinear example of Sec. 4 by Newton linearisation (Sec. 2.2, eq.
+// lin_system): f(u) = -B^T W sigma(E + B u), K(u) = B^T W C(E + B u) B; each
+// step solves K(u) du = f(u) with the library's PCG and preconditioners
+// (Jacobi diagonal by Algorithm 2 on K(u), Green operator of the inclusion's
+// isotropic moduli) and sets u += du.
+
+jfft_status set_material_powerlaw_impl(jfft_cell_s *c, const double *phase_dev, double K,
+                                       double sigma0, double eps0, double n, double K_incl,
+                                       double mu_incl) {
+  if (!phase_dev) return fail(JFFT_E_INVALID, "phase_dev is NULL");
+  if (c->dim != 3 || c->prec != JFFT_FP64 || c->B != 1)
+    return fail(JFFT_E_INVALID, "the power-law material needs a single 3D FP64 cell");
+  const double prm[6] = {K, sigma0, eps0, n, K_incl, mu_incl};
+  for (double v : prm)
+    if (!std::isfinite(v)) return fail(JFFT_E_INVALID, "power-law parameters must be finite");
+  if (!(K > 0.0 && sigma0 > 0.0 && eps0 > 0.0 && n >= 1.0 && K_incl > 0.0 && mu_incl > 0.0))
+    return fail(JFFT_E_INVALID, "need K, sigma0, eps0, K_incl, mu_incl > 0 and n >= 1");
+  TRY(ensure_ready(c));
+  const long long N = c->g.N;
+  if (!c->uk) {
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(double) * 3 * N);
+    if (e != hipSuccess) return fail(JFFT_E_OOM, std::string("hipMalloc Newton iterate: ") + hipGetErrorString(e));
+    c->uk = static_cast<double *>(p);
+  }
+  c->drop_graphs();
+  c->has_material = false;
+  c->nl = false;
+  const int nb = vec_blocks(N);
+  LAUNCH(c, KID_SETUP, k_check_E<<<dim3(nb, 1), 256, 0, c->stream>>>(phase_dev, 0, N, c->partA, c->cs));
+  TRY(reduce_to(c, c->partA, nb, 1, 0, 1));
+  TRY(fetch_small(c));
+  if (c->small_h[0] != 0.0) return fail(JFFT_E_INVALID, "phase contains negative or non-finite entries");
+  LAUNCH(c, KID_SETUP, k_copy<double><<<dim3(nb, 1), 256, 0, c->stream>>>(phase_dev, 0, c->E, 0, N));
+  c->pl = PowerLawArgs{};
+  c->pl.K = K;
+  c->pl.gcoef = sigma0 * (2.0 / 3.0) / std::pow(eps0, n);
+  c->pl.n = n;
+  c->pl.Ki = K_incl;
+  c->pl.mui = mu_incl;
+  c->lam = K_incl - 2.0 * mu_incl / 3.0;  // Green reference: the inclusion
+  c->mu = mu_incl;
+  c->nl = true;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return JFFT_OK;
+}
+
+// Macroscopic strain into the kernel arguments; captured iterations carry
+// it, so a new value drops them.
+void set_macro_pl(jfft_cell_s *c, const double *macro_h) {
+  bool same = true;
+  for (int k = 0; k < 6; ++k) same = same && c->pl.macro[k] == macro_h[k];
+  if (!same) {
+    for (int k = 0; k < 6; ++k) c->pl.macro[k] = macro_h[k];
+    c->drop_graphs();
+  }
+}
+
+long long node_blocks(const jfft_cell_s *c) { return (c->g.N + 255) / 256; }
+
+// f = f(uk) into `f`, ||f||^2 into small[0] (not fetched).
+jfft_status nl_force(jfft_cell_s *c, double *f) {
+  const GridDev &g = c->g;
+  const long long nb = node_blocks(c);
+  LAUNCH(c, KID_RHS, k_nl_force<double><<<(unsigned)nb, 256, 0, c->stream>>>(c->uk, c->E, f, c->partA, c->pl, g.w, g.ihx, g.ihy, g.ihz, g.nx, g.ny, g.nz, g.N));
+  return reduce_to(c, c->partA, nb, 1, 0, 1);
+}
+
+// sum over Gauss points of sigma(E + B uk) / (8 N) into small[16..21] (not fetched).
+jfft_status nl_stress_avg(jfft_cell_s *c) {
+  const GridDev &g = c->g;
+  const long long nb = node_blocks(c);
+  LAUNCH(c, KID_STRESS, k_nl_stress_sum<double><<<(unsigned)nb, 256, 0, c->stream>>>(c->uk, c->E, c->partB, c->pl, g.ihx, g.ihy, g.ihz, g.nx, g.ny, g.nz, g.N));
+  return reduce_to(c, c->partB, nb, 6, 16, 1);
+}
+
+// J^1/2 of the tangent at uk (Algorithm 2, or nothing without a Jacobi factor).
+jfft_status nl_jacobi(jfft_cell_s *c) {
+  if (!useJ(c)) return JFFT_OK;
+  const long long nd = 3 * c->g.N;
+  TRY(run_alg2(c, c->diag, 1));
+  LAUNCH(c, KID_SETUP, k_jhalf<double><<<dim3(vec_blocks(nd), 1), 256, 0, c->stream>>>(c->diag, c->Jh, nd, c->void_value, c->cs));
+  return JFFT_OK;
+}
+
+jfft_status newton_impl(jfft_cell_s *c, const double *macro_h, double newton_tol, double pcg_tol,
+                        int max_newton, int maxit, double *u_out, double *sigma_bar,
+                        int *pcg_iters, double *res_norms, int *steps_out) {
+  if (!c->nl) return fail(JFFT_E_NO_MATERIAL, "set the power-law material first");
+  if (!macro_h || !u_out || !sigma_bar) return fail(JFFT_E_INVALID, "NULL macro_strain, u_dev or sigma_bar");
+  if (!(newton_tol > 0.0) || !(pcg_tol > 0.0 && pcg_tol < 1.0) || max_newton < 0 || maxit < 0)
+    return fail(JFFT_E_INVALID, "need newton_tol > 0, 0 < pcg_tol < 1, max_newton >= 0, maxit >= 0");
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(macro_h[k])) return fail(JFFT_E_INVALID, "macro_strain must be finite");
+  set_macro_pl(c, macro_h);
+  const long long N = c->g.N, nd = 3 * N;
+  const int nb = vec_blocks(nd);
+  LAUNCH(c, KID_VEC, k_fill<double><<<dim3(nb, 1), 256, 0, c->stream>>>(c->uk, 0.0, nd, 0));
+  PcgBufs<double> b{c->u, c->r, c->z, c->q, {c->p[0], c->p[1]}, c->E, c->Jh, c->spec};
+  int steps = 0;
+  bool converged = false, broke = false;
+  for (;;) {
+    TRY(nl_force(c, c->f));
+    TRY(fetch_small(c));
+    const double fn = std::sqrt(c->small_h[0]);
+    if (res_norms) res_norms[steps] = fn;
+    if (!std::isfinite(fn)) return fail(JFFT_E_BREAKDOWN, "Newton residual is not finite");
+    if (fn < newton_tol) {
+      converged = true;
+      break;
+    }
+    if (steps == max_newton) break;
+    TRY(nl_jacobi(c));
+    // inexact Newton: no inner solve below a tenth of the Newton tolerance
+    const double rtol = std::max(pcg_tol, 0.1 * newton_tol / fn);
+    LAUNCH(c, KID_VEC, k_dot<double><<<dim3(nb, 1), 256, 0, c->stream>>>(c->f, c->f, nd, c->partA, c->cs));
+    LAUNCH(c, KID_CTRL, k_solve_norms<<<1, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, c->partA, nb, rtol, 0, c->cs));
+    LAUNCH(c, KID_VEC, k_fill<double><<<dim3(nb, 1), 256, 0, c->stream>>>(c->u, 0.0, nd, 0));
+    LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, 1), 256, 0, c->stream>>>(c->f, 0, c->r, 0, nd));
+    TRY(run_pcg<double>(c, b, false, maxit, false));
+    LAUNCH(c, KID_CTRL, k_fp64_final<<<1, 1, 0, c->stream>>>(c->st, c->cs));
+    LAUNCH(c, KID_VEC, k_add<double><<<nb, 256, 0, c->stream>>>(c->u, c->uk, nd));
+    TRY(fetch_states(c));
+    if (pcg_iters) pcg_iters[steps] = c->st_h[0].total_iters;
+    if (c->st_h[0].final_status == JFFT_E_BREAKDOWN) broke = true;
+    ++steps;
+  }
+  if (steps_out) *steps_out = steps;
+  TRY(nl_stress_avg(c));
+  // mean of u removed (Sec. 5), u to the caller
+  const int nbN = vec_blocks(N);
+  LAUNCH(c, KID_VEC, k_comp_sum<double><<<dim3(nbN, 3, 1), 256, 0, c->stream>>>(c->uk, N, c->partA, c->cs));
+  TRY(reduce_to(c, c->partA, nbN, 3, 8, 1));
+  LAUNCH(c, KID_VEC, k_sub_mean<double><<<dim3(nbN, 3, 1), 256, 0, c->stream>>>(c->uk, N, c->small + 8, c->cs));
+  LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, 1), 256, 0, c->stream>>>(c->uk, 0, u_out, 0, nd));
+  TRY(fetch_small(c));
+  for (int k = 0; k < 6; ++k) sigma_bar[k] = c->small_h[16 + k] / (8.0 * (double)N);
+  if (!converged) {
+    g_last_error = broke ? "Newton did not converge (a PCG solve broke down)"
+                         : "Newton reached max_newton steps";
+    return JFFT_E_NOT_CONVERGED;
+  }
+  return JFFT_OK;
+}
+
+// Operators of the Newton step at a caller's iterate (copied into uk).
+jfft_status nl_operator_prep(jfft_cell_s *c, const double *macro_h, const double *uk_dev) {
+  if (!c->nl) return fail(JFFT_E_NO_MATERIAL, "set the power-law material first");
+  if (!macro_h || !uk_dev) return fail(JFFT_E_INVALID, "NULL argument");
+  set_macro_pl(c, macro_h);
+  const long long nd = 3 * c->g.N;
+  LAUNCH(c, KID_VEC, k_copy<double><<<dim3(vec_blocks(nd), 1), 256, 0, c->stream>>>(uk_dev, 0, c->uk, 0, nd));
+  return JFFT_OK;
 }
 
 bool supported_length(int n) {
@@ -1409,6 +1593,48 @@ jfft_status jfft_set_mixed_params(jfft_cell_t c, double inner_tol, int max_outer
     return fail(JFFT_E_INVALID, "inner_tol must lie in (0, 1) and max_outer >= 1");
   c->inner_tol = inner_tol;
   c->max_outer = max_outer;
+  return JFFT_OK;
+}
+
+jfft_status jfft_set_material_powerlaw(jfft_cell_t c, const double *phase_dev, double K,
+                                       double sigma0, double eps0, double n, double K_incl,
+                                       double mu_incl) {
+  if (!c) return fail(JFFT_E_INVALID, "NULL cell");
+  return set_material_powerlaw_impl(c, phase_dev, K, sigma0, eps0, n, K_incl, mu_incl);
+}
+
+jfft_status jfft_solve_newton(jfft_cell_t c, const double *macro_strain, double newton_tol,
+                              double pcg_tol, int max_newton, int maxit, double *u_dev,
+                              double *sigma_bar, int *pcg_iters, double *res_norms, int *steps) {
+  if (!c) return fail(JFFT_E_INVALID, "NULL cell");
+  return newton_impl(c, macro_strain, newton_tol, pcg_tol, max_newton, maxit, u_dev, sigma_bar,
+                     pcg_iters, res_norms, steps);
+}
+
+jfft_status jfft_powerlaw_force(jfft_cell_t c, const double *macro_strain, const double *uk_dev,
+                                double *f_dev) {
+  if (!c || !f_dev) return fail(JFFT_E_INVALID, "NULL argument");
+  TRY(nl_operator_prep(c, macro_strain, uk_dev));
+  TRY(nl_force(c, f_dev));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return JFFT_OK;
+}
+
+jfft_status jfft_powerlaw_tangent(jfft_cell_t c, const double *macro_strain, const double *uk_dev,
+                                  const double *in_dev, double *out_dev) {
+  if (!c || !in_dev || !out_dev) return fail(JFFT_E_INVALID, "NULL argument");
+  TRY(nl_operator_prep(c, macro_strain, uk_dev));
+  TRY(apply_K<double>(c, c->E, in_dev, out_dev, 1));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return JFFT_OK;
+}
+
+jfft_status jfft_powerlaw_jacobi_diag(jfft_cell_t c, const double *macro_strain,
+                                      const double *uk_dev, double *diag_dev) {
+  if (!c || !diag_dev) return fail(JFFT_E_INVALID, "NULL argument");
+  TRY(nl_operator_prep(c, macro_strain, uk_dev));
+  TRY(run_alg2(c, diag_dev, 1));
+  HIP_TRY(hipStreamSynchronize(c->stream));
   return JFFT_OK;
 }
 

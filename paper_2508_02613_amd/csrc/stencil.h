@@ -59,6 +59,17 @@ __device__ __forceinline__ void interp2(Real v0, Real v1, Real &o0, Real &o1) {
 
 enum StencilMode { SM_APPLY = 0, SM_CG = 1, SM_COMB = 2 };
 
+// Power-law matrix and linear inclusion of the nonlinear example (Sec. 4):
+// matrix sigma = K tr(eps) I + g(eps_eq) e, g(s) = gcoef s^(n-1) with
+// gcoef = sigma0 (2/3) / eps0^n, e = dev(eps), eps_eq = sqrt(2/3 e.e);
+// inclusion sigma = Ki tr(eps) I + 2 mui e.  macro: the macroscopic strain
+// (Mandel), added to the strain of the Newton iterate.
+struct PowerLawArgs {
+  double K, gcoef, n;
+  double Ki, mui;
+  double macro[6];
+};
+
 template <typename Real>
 struct StencilArgs {
   const Real *in;        // APPLY: vector to multiply; CG: p_old
@@ -79,6 +90,10 @@ struct StencilArgs {
   Real clam[3], cmu[3];  // cubic elements: half of lam, mu times k_c^2 (see elem_hex_modes_cubic)
   int nx, ny, nz;
   long long N;
+  // tangent of the power-law problem (power-law kernel variant only)
+  const Real *uk;        // Newton iterate u^(i) [3][N]; E holds the phase (1 = matrix)
+  PowerLawArgs pl;
+  Real w;                // Gauss weight (element volume / 8)
 };
 
 __device__ __forceinline__ int wrapi(int v, int n) {
@@ -254,6 +269,118 @@ __device__ __forceinline__ void elem_hex(const Real (&u)[3][8], Real Elam, Real 
       }
 #pragma unroll
   for (int i = 0; i < 3; ++i) force_hex(SX[i], SY[i], SZ[i], ihx, ihy, ihz, y[i]);
+}
+
+// ---- hex element with the power-law tangent ---------------------------------
+// Tangent of the law above at the strain eps of a Gauss point, applied to a
+// strain increment d (both Mandel): for the matrix
+//   C d = K tr(d) I + g dev(d) + h (e.d) e,  h = g (n - 1) / (e.e),
+// (dg/ds = g (n-1)/s and d eps_eq = (2/3) e.d / eps_eq), for the inclusion
+// C d = Ki tr(d) I + 2 mui dev(d); g(0) = 0 for n > 1.
+template <typename Real>
+__device__ __forceinline__ void powerlaw_tangent(const Real (&eps)[6], const Real (&d)[6],
+                                                 bool matrix, const PowerLawArgs &m,
+                                                 Real (&sg)[6]) {
+  const Real dtr = d[0] + d[1] + d[2];
+  if (matrix) {
+    const Real tr3 = (eps[0] + eps[1] + eps[2]) / (Real)3;
+    Real e[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) e[k] = eps[k] - (k < 3 ? tr3 : (Real)0);
+    Real ee = 0, ed = 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      ee += e[k] * e[k];
+      ed += e[k] * d[k];
+    }
+    const Real seq = sqrt((Real)(2.0 / 3.0) * ee);
+    const Real n = (Real)m.n;
+    Real g = (Real)0;
+    if (n == (Real)1)
+      g = (Real)m.gcoef;
+    else if (seq > (Real)0)
+      g = (Real)m.gcoef * pow(seq, n - (Real)1);
+    const Real h = ee > (Real)0 ? g * (n - (Real)1) / ee : (Real)0;
+    const Real kt = (Real)m.K * dtr, g3 = g * dtr / (Real)3, he = h * ed;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sg[k] = g * d[k] + he * e[k] + (k < 3 ? kt - g3 : (Real)0);
+  } else {
+    const Real m2 = (Real)(2.0 * m.mui), kt = (Real)m.Ki * dtr, m3 = m2 * dtr / (Real)3;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sg[k] = m2 * d[k] + (k < 3 ? kt - m3 : (Real)0);
+  }
+}
+
+// Mandel strain at Gauss point (gx, gy, gz) from the factorised gradients.
+template <typename Real>
+__device__ __forceinline__ void mandel_strain(const Real (&X)[3][2][2], const Real (&Y)[3][2][2],
+                                              const Real (&Z)[3][2][2], int gx, int gy, int gz,
+                                              Real (&eps)[6]) {
+  const Real r2 = (Real)0.70710678118654752440084436210485;  // 1/sqrt2
+  eps[0] = X[0][gy][gz];
+  eps[1] = Y[1][gx][gz];
+  eps[2] = Z[2][gx][gy];
+  eps[3] = (Y[2][gx][gz] + Z[1][gx][gy]) * r2;  // 23
+  eps[4] = (X[2][gy][gz] + Z[0][gx][gy]) * r2;  // 13
+  eps[5] = (X[1][gy][gz] + Y[0][gx][gz]) * r2;  // 12
+}
+
+// Element force y = w B^T C(E + B uk) B u of the power-law tangent at the
+// Newton iterate uk (Gauss-point loop on the factorised gradients).  With
+// ENERGY, en += u . y.
+template <typename Real, bool ENERGY>
+__device__ __forceinline__ void elem_hex_tangent(const Real (&uk)[3][8], const Real (&u)[3][8],
+                                                 bool matrix, const PowerLawArgs &m, Real w,
+                                                 Real ihx, Real ihy, Real ihz, Real (&y)[3][8],
+                                                 double &en) {
+  Real kX[3][2][2], kY[3][2][2], kZ[3][2][2];
+  Real dX[3][2][2], dY[3][2][2], dZ[3][2][2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    grad_hex(uk[i], ihx, ihy, ihz, kX[i], kY[i], kZ[i]);
+    grad_hex(u[i], ihx, ihy, ihz, dX[i], dY[i], dZ[i]);
+  }
+  Real SX[3][2][2], SY[3][2][2], SZ[3][2][2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) SX[i][a][b] = SY[i][a][b] = SZ[i][a][b] = (Real)0;
+  const Real r2 = (Real)0.70710678118654752440084436210485;
+  Real e = 0;
+#pragma unroll
+  for (int gx = 0; gx < 2; ++gx)
+#pragma unroll
+    for (int gy = 0; gy < 2; ++gy)
+#pragma unroll
+      for (int gz = 0; gz < 2; ++gz) {
+        Real es[6], de[6], sg[6];
+        mandel_strain(kX, kY, kZ, gx, gy, gz, es);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) es[k] += (Real)m.macro[k];
+        mandel_strain(dX, dY, dZ, gx, gy, gz, de);
+        powerlaw_tangent(es, de, matrix, m, sg);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sg[k] *= w;
+        if (ENERGY) {
+#pragma unroll
+          for (int k = 0; k < 6; ++k) e += sg[k] * de[k];
+        }
+        const Real s23 = sg[3] * r2, s13 = sg[4] * r2, s12 = sg[5] * r2;
+        SX[0][gy][gz] += sg[0];
+        SY[0][gx][gz] += s12;
+        SZ[0][gx][gy] += s13;
+        SX[1][gy][gz] += s12;
+        SY[1][gx][gz] += sg[1];
+        SZ[1][gx][gy] += s23;
+        SX[2][gy][gz] += s13;
+        SY[2][gx][gz] += s23;
+        SZ[2][gx][gy] += sg[2];
+      }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) force_hex(SX[i], SY[i], SZ[i], ihx, ihy, ihz, y[i]);
+  if (ENERGY) en += (double)e;
 }
 
 // ---- hex element in Hadamard modes of the Gauss points -------------------
@@ -594,10 +721,13 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
 // each 18 x 16 node plane (columns 1..16, which hold every owned node) and,
 // if t < 224, output node (t & 15) + 1, (t >> 4) + 1.  Columns 0 and 17 of
 // a plane are loaded by threads 0..31.
-template <typename Real, int MODE, bool CUBIC = false>
+// MAT = 1: the tangent of the power-law problem at the Newton iterate a.uk
+// (E holds the phase); a second ring of node planes holds the iterate.
+template <typename Real, int MODE, bool CUBIC = false, int MAT = 0>
 __global__ void __launch_bounds__(STENCIL3_THREADS, stencil3_waves_per_simd<Real>())
     k_stiffness3d(StencilArgs<Real> a) {
   __shared__ Real P[3][3][NNODE3];               // ring of three node planes of the input vector
+  __shared__ Real U[MAT ? 3 : 1][3][MAT ? NNODE3 : 1];  // MAT: ring of the Newton iterate
   __shared__ Real Y[24][STENCIL3_THREADS];       // corner contributions of one element layer
   __shared__ double red[STENCIL3_THREADS / 64];
 
@@ -668,7 +798,7 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, stencil3_waves_per_simd<Real
   // issued unconditionally at a valid address and masked at the commit: with
   // no load under a branch the compiler knows the exact number of memory
   // operations in flight and waits only for the ones a value needs.
-  Real fz[3], fp[3], fu[3], hz[3], hp[3];
+  Real fz[3], fp[3], fu[3], hz[3], hp[3], ku[3], kh[3];
   auto fetch0 = [&](int zp) {
     const long long node0 = (long long)wrapi(zp, nz) * plane + n0xy;
     // owned u lies in planes z0 .. zend - 1 (< nz, no wrap)
@@ -682,6 +812,7 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, stencil3_waves_per_simd<Real
         fp[c] = a.in[c * N + node0];
         fu[c] = a.u[c * N + nodeu];
       }
+      if (MAT) ku[c] = a.uk[c * N + node0];
     }
   };
   auto fetch1 = [&](int zp) {
@@ -694,6 +825,7 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, stencil3_waves_per_simd<Real
         hz[c] = a.zin[c * N + node1];
         hp[c] = a.in[c * N + node1];
       }
+      if (MAT) kh[c] = a.uk[c * N + node1];
     }
   };
   auto fetch = [&](int zp) {
@@ -725,6 +857,10 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, stencil3_waves_per_simd<Real
       }
       P[slot][c][li0] = v;
       if (has1) P[slot][c][li1] = w;
+      if (MAT) {
+        U[slot][c][li0] = ku[c];
+        if (has1) U[slot][c][li1] = kh[c];
+      }
     }
   };
   auto ring = [&](int zp) { return (zp - z0 + 1) % 3; };
@@ -780,12 +916,29 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, stencil3_waves_per_simd<Real
         for (int i = 0; i < 3; ++i) uv[i][c] = P[cz ? s1 : s0][i][li];
       }
       double en = 0.0;
-      // a.lam, a.mu carry the full Gauss weight; the mode form takes half
-      if constexpr (CUBIC)
+      if constexpr (MAT == 1) {
+        Real kv[3][8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+          const int li = lie + cy * NX3 + cx;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) kv[i][c] = U[cz ? s1 : s0][i][li];
+        }
+        // Ecur is the phase (0 beyond the grid, where the result is masked)
+        elem_hex_tangent<Real, MODE == SM_CG>(kv, uv, Ecur > (Real)0.5, a.pl, a.w, a.ihx, a.ihy,
+                                              a.ihz, yv, en);
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+#pragma unroll
+          for (int i = 0; i < 3; ++i) yv[i][c] *= emask;
+      } else if constexpr (CUBIC) {
+        // a.lam, a.mu carry the full Gauss weight; the mode form takes half
         elem_hex_modes_cubic<Real, MODE == SM_CG>(uv, Ecur, a.clam, a.cmu, yv, en);
-      else
+      } else {
         elem_hex_modes<Real, MODE == SM_CG>(uv, Ecur * a.lam * (Real)0.5, Ecur * a.mu * (Real)0.5,
                                             a.ihx, a.ihy, a.ihz, yv, en);
+      }
       if (elem_owned && ez >= z0) acc += en;
 #pragma unroll
       for (int c = 0; c < 8; ++c)
@@ -1201,6 +1354,163 @@ __global__ void __launch_bounds__(256)
     diag[i] = k0 * s;
     diag[N + i] = k1 * s;
     if (DIM == 3) diag[2 * N + i] = k2 * s;
+  }
+}
+
+// ----------------------------------------------- power-law Newton pieces ----
+// The law (no tangent): matrix sigma = K tr(eps) I + g(eps_eq) e, inclusion
+// sigma = Ki tr(eps) I + 2 mui e (Mandel).
+template <typename Real>
+__device__ __forceinline__ void powerlaw_stress(const Real (&eps)[6], bool matrix,
+                                                const PowerLawArgs &m, Real (&sg)[6]) {
+  const Real tr = eps[0] + eps[1] + eps[2], tr3 = tr / (Real)3;
+  Real e[6], ee = 0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    e[k] = eps[k] - (k < 3 ? tr3 : (Real)0);
+    ee += e[k] * e[k];
+  }
+  Real g, kt;
+  if (matrix) {
+    const Real seq = sqrt((Real)(2.0 / 3.0) * ee), n = (Real)m.n;
+    g = n == (Real)1 ? (Real)m.gcoef
+                     : (seq > (Real)0 ? (Real)m.gcoef * pow(seq, n - (Real)1) : (Real)0);
+    kt = (Real)m.K * tr;
+  } else {
+    g = (Real)(2.0 * m.mui);
+    kt = (Real)m.Ki * tr;
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) sg[k] = g * e[k] + (k < 3 ? kt : (Real)0);
+}
+
+// Element corner values of the nodal field at the element with lowest node
+// (ex, ey, ez) (periodic).
+template <typename Real>
+__device__ __forceinline__ void gather_hex(const Real *u, long long N, int nx, int ny, int nz,
+                                           int ex, int ey, int ez, Real (&v)[3][8]) {
+  const long long plane = (long long)nx * ny;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int x = ex + (c & 1), y = ey + ((c >> 1) & 1), z = ez + (c >> 2);
+    const long long node = (long long)(x == nx ? 0 : x) + (long long)nx * (y == ny ? 0 : y) +
+                           plane * (z == nz ? 0 : z);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) v[i][c] = u[i * N + node];
+  }
+}
+
+// Gauss-point stresses of one element (weight w) folded into its corner forces.
+template <typename Real>
+__device__ __forceinline__ void elem_hex_law(const Real (&uk)[3][8], bool matrix,
+                                             const PowerLawArgs &m, Real w, Real ihx, Real ihy,
+                                             Real ihz, Real (&y)[3][8], Real (&ssum)[6]) {
+  Real kX[3][2][2], kY[3][2][2], kZ[3][2][2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) grad_hex(uk[i], ihx, ihy, ihz, kX[i], kY[i], kZ[i]);
+  Real SX[3][2][2], SY[3][2][2], SZ[3][2][2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) SX[i][a][b] = SY[i][a][b] = SZ[i][a][b] = (Real)0;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) ssum[k] = (Real)0;
+  const Real r2 = (Real)0.70710678118654752440084436210485;
+#pragma unroll
+  for (int gx = 0; gx < 2; ++gx)
+#pragma unroll
+    for (int gy = 0; gy < 2; ++gy)
+#pragma unroll
+      for (int gz = 0; gz < 2; ++gz) {
+        Real es[6], sg[6];
+        mandel_strain(kX, kY, kZ, gx, gy, gz, es);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) es[k] += (Real)m.macro[k];
+        powerlaw_stress(es, matrix, m, sg);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          ssum[k] += sg[k];
+          sg[k] *= w;
+        }
+        const Real s23 = sg[3] * r2, s13 = sg[4] * r2, s12 = sg[5] * r2;
+        SX[0][gy][gz] += sg[0];
+        SY[0][gx][gz] += s12;
+        SZ[0][gx][gy] += s13;
+        SX[1][gy][gz] += s12;
+        SY[1][gx][gz] += sg[1];
+        SZ[1][gx][gy] += s23;
+        SX[2][gy][gz] += s13;
+        SY[2][gx][gz] += s23;
+        SZ[2][gx][gy] += sg[2];
+      }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) force_hex(SX[i], SY[i], SZ[i], ihx, ihy, ihz, y[i]);
+}
+
+// Newton right-hand side f = -B^T W sigma(E + B uk) (eq. lin_system), one
+// thread per node: the node is corner o of the elements node - o, o in
+// {0,1}^3; each of them is evaluated and its force on corner o taken (every
+// element is evaluated by each of its 8 nodes: no atomics, fixed order).
+// part: per-block ||f||^2 partials.
+template <typename Real>
+__global__ void __launch_bounds__(256)
+    k_nl_force(const Real *uk, const Real *phase, Real *f, double *part, PowerLawArgs m, Real w,
+               Real ihx, Real ihy, Real ihz, int nx, int ny, int nz, long long N) {
+  __shared__ double red[4];
+  const long long plane = (long long)nx * ny;
+  double ff = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int z = (int)(i / plane);
+    const long long rem = i - (long long)z * plane;
+    const int y = (int)(rem / nx), x = (int)(rem - (long long)y * nx);
+    Real acc[3] = {0, 0, 0};
+    for (int o = 0; o < 8; ++o) {
+      const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
+      const int ex = x - ox < 0 ? nx - 1 : x - ox, ey = y - oy < 0 ? ny - 1 : y - oy,
+                ez = z - oz < 0 ? nz - 1 : z - oz;
+      Real v[3][8], yv[3][8], ss[6];
+      gather_hex(uk, N, nx, ny, nz, ex, ey, ez, v);
+      const bool matrix = phase[(long long)ex + (long long)nx * ey + plane * ez] > (Real)0.5;
+      elem_hex_law(v, matrix, m, w, ihx, ihy, ihz, yv, ss);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c] += yv[c][o];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      f[c * N + i] = -acc[c];
+      ff += (double)acc[c] * (double)acc[c];
+    }
+  }
+  const double s = block_sum<256>(ff, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Sum of the Gauss-point stresses sigma(E + B uk) per block: part[k * nblocks
+// + block], k = 0..5 (the volume average is the total / (8 N)).
+template <typename Real>
+__global__ void __launch_bounds__(256)
+    k_nl_stress_sum(const Real *uk, const Real *phase, double *part, PowerLawArgs m, Real ihx,
+                    Real ihy, Real ihz, int nx, int ny, int nz, long long N) {
+  __shared__ double red[4];
+  const long long plane = (long long)nx * ny;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int z = (int)(i / plane);
+    const long long rem = i - (long long)z * plane;
+    const int y = (int)(rem / nx), x = (int)(rem - (long long)y * nx);
+    Real v[3][8], yv[3][8], ss[6];
+    gather_hex(uk, N, nx, ny, nz, x, y, z, v);
+    elem_hex_law(v, phase[i] > (Real)0.5, m, (Real)1, ihx, ihy, ihz, yv, ss);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[k] += (double)ss[k];
+  }
+  for (int k = 0; k < 6; ++k) {
+    const double s = block_sum<256>(acc[k], red);
+    if (threadIdx.x == 0) part[(long long)k * gridDim.x + blockIdx.x] = s;
   }
 }
 

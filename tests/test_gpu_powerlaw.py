@@ -1,0 +1,277 @@
+"""GPU parity of the power-law Newton solve (nonlinear example, Sec. 4;
+Newton linearisation, Sec. 2.2, eq. lin_system) against the FP64 oracle
+oracle/powerlaw.py (itself pinned in test_oracle_powerlaw.py):
+
+* the operators of one Newton step at a random iterate: the force
+  f = -B^T W sigma(E + B u), the tangent action K(u) p and Algorithm 2 on
+  K(u), element by element, on grids of several stiffness tiles with ragged
+  tails, cubic and non-cubic elements;
+* whole Newton solves with the three preconditioners: step count, PCG
+  iterations per step, ||f|| per step, u (mean removed) and sigma_bar;
+* the linear limit (n = 1, proportional inclusion moduli) against the
+  library's own linear solve, graph replay against direct launches, and the
+  argument and state checks of the entry points.
+"""
+import numpy as np
+import pytest
+
+import jfft_inputs as ji
+import oracle
+from oracle import powerlaw as pl
+
+pytestmark = pytest.mark.gpu
+
+PRM = pl.PowerLaw()
+SHEAR = np.array([0.01, 0.0, -0.01, 0.0, 0.0, 0.05 * np.sqrt(2)])
+
+
+def _pkg():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    import paper_2508_02613_amd as pkg
+
+    pkg.load_library()
+    return pkg
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _cell(pkg, shape, pc, lengths=None):
+    return pkg.Cell(shape, pc=pc, lengths=lengths)
+
+
+def _set(cell, phase, prm=PRM):
+    cell.set_material_powerlaw(phase, K=prm.K, sigma0=prm.sigma0, eps0=prm.eps0, n=prm.n,
+                               K_incl=prm.K_incl, mu_incl=prm.mu_incl)
+
+
+OP_CASES = [((12, 16, 18), None), ((16, 16, 16), None), ((10, 30, 20), (1.0, 1.5, 0.5))]
+
+
+@pytest.mark.parametrize("shape,lengths", OP_CASES)
+def test_operators_match_oracle(shape, lengths):
+    pkg = _pkg()
+    say(f"power-law operators {shape} lengths={lengths}")
+    rng = np.random.default_rng(11)
+    phase = 1.0 - ji.spherical_inclusions(shape, 3, 0.22, seed=2)
+    u = 0.02 * rng.standard_normal((3,) + shape)
+    p = rng.standard_normal((3,) + shape)
+    macro = rng.uniform(-0.05, 0.05, 6)
+    cell = _cell(pkg, shape, pkg.PC_GREEN_JACOBI, lengths)
+    _set(cell, phase)
+    f = cell.powerlaw_force(macro, u).cpu().numpy()
+    Kp = cell.powerlaw_tangent(macro, u, p).cpu().numpy()
+    d = cell.powerlaw_jacobi_diag(macro, u).cpu().numpy()
+    cell.close()
+    f_ref = pl.force(u, macro, phase, PRM, lengths)
+    Kp_ref = pl.tangent_op(u, p, macro, phase, PRM, lengths)
+    d_ref = pl.jacobi_diag(u, macro, phase, PRM, lengths)
+    assert np.abs(f - f_ref).max() <= 1e-12 * np.abs(f_ref).max()
+    assert np.abs(Kp - Kp_ref).max() <= 1e-12 * np.abs(Kp_ref).max()
+    assert np.abs(d - d_ref).max() <= 1e-12 * np.abs(d_ref).max()
+    assert d.min() > 0
+
+
+def test_operators_at_zero_iterate_and_matrix_only():
+    """u = 0 in a homogeneous matrix: f = 0 for any macro strain (every
+    element has the same stress, whose divergence vanishes), and the tangent
+    is the same for every element."""
+    pkg = _pkg()
+    shape = (8, 8, 8)
+    say(f"power-law operators at u = 0 {shape}")
+    phase = np.ones(shape)
+    u = np.zeros((3,) + shape)
+    p = np.random.default_rng(3).standard_normal((3,) + shape)
+    cell = _cell(pkg, shape, pkg.PC_GREEN)
+    _set(cell, phase)
+    f = cell.powerlaw_force(SHEAR, u).cpu().numpy()
+    Kp = cell.powerlaw_tangent(SHEAR, u, p).cpu().numpy()
+    cell.close()
+    Kp_ref = pl.tangent_op(u, p, SHEAR, phase, PRM)
+    assert np.abs(f).max() <= 1e-15
+    assert np.abs(Kp - Kp_ref).max() <= 1e-12 * np.abs(Kp_ref).max()
+
+
+def _iters_close(a, b):
+    # GPU reductions round differently from numpy's: where the residual curve
+    # is flat at the stopping threshold the stop can move by an iteration
+    return len(a) == len(b) and all(abs(x - y) <= max(1, round(0.03 * y)) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("pc", ["GJ", "G", "J"])
+def test_newton_matches_oracle(pc):
+    pkg = _pkg()
+    shape = (12, 16, 18)
+    say(f"power-law Newton {shape} pc={pc}")
+    codes = {"GJ": (pkg.PC_GREEN_JACOBI, oracle.PC_GREEN_JACOBI),
+             "G": (pkg.PC_GREEN, oracle.PC_GREEN), "J": (pkg.PC_JACOBI, oracle.PC_JACOBI)}
+    gpc, opc = codes[pc]
+    phase = 1.0 - ji.spherical_inclusions(shape, 3, 0.2, seed=5)
+    kw = dict(newton_tol=1e-10, pcg_tol=1e-10, max_newton=20, maxit=5000)
+    ref = pl.newton(phase, SHEAR, PRM, pc=opc, **kw)
+    cell = _cell(pkg, shape, gpc)
+    _set(cell, phase)
+    u, sbar, rep = cell.solve_newton(SHEAR, **kw)
+    ug = u.cpu().numpy()
+    cell.close()
+    say(f"  gpu {rep}  oracle steps={len(ref.pcg_iters)} iters={ref.pcg_iters}")
+    assert rep.converged and ref.converged
+    assert rep.steps == len(ref.pcg_iters)
+    assert _iters_close(rep.pcg_iters, ref.pcg_iters), (rep.pcg_iters, ref.pcg_iters)
+    assert abs(rep.res[0] - ref.res[0]) <= 1e-12 * ref.res[0]
+    for i in range(1, len(ref.res)):
+        if rep.pcg_iters[:i] == ref.pcg_iters[:i]:
+            assert abs(rep.res[i] - ref.res[i]) <= 1e-6 * ref.res[i] + 1e-14, (i, rep.res, ref.res)
+    assert rep.res[-1] < kw["newton_tol"]
+    uo = ref.u - ref.u.reshape(3, -1).mean(axis=1).reshape(3, 1, 1, 1)
+    assert np.abs(ug.reshape(3, -1).mean(axis=1)).max() <= 1e-15 * np.abs(uo).max() * ug[0].size
+    # the oracle's own solutions with the three preconditioners differ by up
+    # to 6e-9 in u and 5e-11 in sigma_bar (relative to the largest entry):
+    # the room a converged Newton solve leaves
+    assert np.abs(ug - uo).max() <= 2e-8 * np.abs(uo).max()
+    assert np.abs(sbar - ref.sigma_bar).max() <= 2e-10 * np.abs(ref.sigma_bar).max()
+
+
+def test_newton_step_cap_and_paper_tolerance():
+    """max_newton = 1 stops after one step with JFFT_E_NOT_CONVERGED and
+    every output written; the paper's tolerance (||f|| < 1e-5) on the same
+    cell converges in the oracle's number of steps."""
+    pkg = _pkg()
+    shape = (12, 12, 12)
+    say(f"power-law Newton step cap {shape}")
+    phase = 1.0 - ji.spherical_inclusions(shape, 3, 0.2, seed=5)
+    cell = _cell(pkg, shape, pkg.PC_GREEN_JACOBI)
+    _set(cell, phase)
+    u1, s1, r1 = cell.solve_newton(SHEAR, newton_tol=1e-10, max_newton=1)
+    ref1 = pl.newton(phase, SHEAR, PRM, newton_tol=1e-10, max_newton=1)
+    assert not r1.converged and r1.steps == 1 and len(r1.res) == 2
+    assert _iters_close(r1.pcg_iters, ref1.pcg_iters)
+    if r1.pcg_iters == ref1.pcg_iters:
+        assert abs(r1.res[1] - ref1.res[1]) <= 1e-6 * ref1.res[1]
+    assert np.abs(s1 - ref1.sigma_bar).max() <= 1e-6 * np.abs(ref1.sigma_bar).max()
+    u, s, r = cell.solve_newton(SHEAR)
+    ref = pl.newton(phase, SHEAR, PRM)
+    cell.close()
+    assert r.converged and r.steps == len(ref.pcg_iters)
+    assert _iters_close(r.pcg_iters, ref.pcg_iters)
+    same = r.pcg_iters == ref.pcg_iters
+    assert np.abs(s - ref.sigma_bar).max() <= (1e-10 if same else 1e-6) * np.abs(ref.sigma_bar).max()
+
+
+def test_newton_homogeneous_matrix_zero_steps():
+    pkg = _pkg()
+    shape = (8, 8, 8)
+    say(f"power-law Newton homogeneous {shape}")
+    cell = _cell(pkg, shape, pkg.PC_GREEN_JACOBI)
+    _set(cell, np.ones(shape))
+    u, s, r = cell.solve_newton(SHEAR)
+    ug = u.cpu().numpy()
+    cell.close()
+    assert r.converged and r.steps == 0 and r.pcg_iters == [] and r.res[0] <= 1e-15
+    assert np.abs(ug).max() == 0.0
+    np.testing.assert_allclose(s, pl.stress(SHEAR, np.array(1.0), PRM), rtol=1e-13, atol=1e-16)
+
+
+def test_linear_limit_equals_linear_solve():
+    """n = 1 and inclusion moduli t times the matrix's: a linear problem, one
+    Newton step; the result equals the library's linear solve with E = 1 in
+    the matrix and t in the inclusions."""
+    pkg = _pkg()
+    shape = (16, 16, 16)
+    say(f"power-law linear limit {shape}")
+    mu = PRM.sigma0 / (3.0 * PRM.eps0)
+    t = 10.0
+    prm1 = pl.PowerLaw(K=PRM.K, sigma0=PRM.sigma0, eps0=PRM.eps0, n=1.0, K_incl=t * PRM.K,
+                       mu_incl=t * mu)
+    incl = ji.spherical_inclusions(shape, 2, 0.2, seed=1)
+    phase = 1.0 - incl
+    cell = _cell(pkg, shape, pkg.PC_GREEN_JACOBI)
+    _set(cell, phase, prm1)
+    u, s, r = cell.solve_newton(SHEAR, newton_tol=1e-13, pcg_tol=1e-12)
+    un = u.cpu().numpy()
+    assert r.converged and r.steps == 1, r
+    lam = PRM.K - 2 * mu / 3
+    cell.set_material(1.0 + (t - 1.0) * incl, lame=(lam, mu))
+    ul, sl, rl, _ = cell.solve(SHEAR, tol=1e-12, maxit=5000)
+    ulin = ul.cpu().numpy()
+    cell.close()
+    assert np.abs(un - ulin).max() <= 1e-9 * np.abs(ulin).max()
+    np.testing.assert_allclose(s, sl, rtol=1e-10, atol=1e-14)
+
+
+def test_graph_replay_equals_direct_launches():
+    pkg = _pkg()
+    shape = (12, 16, 18)
+    say(f"power-law Newton graph replay {shape}")
+    phase = 1.0 - ji.spherical_inclusions(shape, 3, 0.2, seed=5)
+    import torch
+
+    out = []
+    st = torch.cuda.Stream()  # graphs are captured on a stream of the caller's
+    for G in (0, 8, 8):
+        cell = pkg.Cell(shape, pc=pkg.PC_GREEN_JACOBI, stream=st)
+        cell.set_graph_iterations(G)
+        _set(cell, phase)
+        u, s, r = cell.solve_newton(SHEAR, newton_tol=1e-10, pcg_tol=1e-10)
+        # a second solve on the same handle replays the captured graph again
+        u2, s2, r2 = cell.solve_newton(SHEAR, newton_tol=1e-10, pcg_tol=1e-10)
+        st.synchronize()
+        out.append((u.cpu().numpy(), s, r.pcg_iters, u2.cpu().numpy(), s2, r2.pcg_iters))
+        cell.close()
+    for o in out[1:]:
+        assert o[2] == out[0][2] and o[5] == out[0][2]
+        assert np.array_equal(o[0], out[0][0]) and np.array_equal(o[3], out[0][0])
+        assert np.array_equal(o[1], out[0][1]) and np.array_equal(o[4], out[0][1])
+
+
+def test_argument_and_state_checks():
+    pkg = _pkg()
+    say("power-law argument checks")
+    shape = (8, 8, 8)
+    phase = np.ones(shape)
+    c2 = pkg.Cell((16, 16), pc=pkg.PC_GREEN)
+    with pytest.raises(pkg.JfftError):
+        c2.set_material_powerlaw(np.ones((16, 16)))
+    c2.close()
+    cm = pkg.Cell(shape, precision=pkg.MIXED, pc=pkg.PC_GREEN)
+    with pytest.raises(pkg.JfftError):
+        _set(cm, phase)
+    cm.close()
+    cell = _cell(pkg, shape, pkg.PC_GREEN_JACOBI)
+    with pytest.raises(pkg.JfftError) as e:
+        cell.solve_newton(SHEAR)
+    assert e.value.name == "no_material"
+    for bad in (dict(n=0.5), dict(K=-1.0), dict(mu_incl=0.0), dict(eps0=float("nan"))):
+        args = dict(K=2.0, sigma0=0.5, eps0=0.1, n=5.0, K_incl=2.0, mu_incl=0.5)
+        args.update(bad)
+        with pytest.raises(pkg.JfftError):
+            cell.set_material_powerlaw(phase, **args)
+    bad_phase = phase.copy()
+    bad_phase[1, 2, 3] = -1.0
+    with pytest.raises(pkg.JfftError):
+        _set(cell, bad_phase)
+    _set(cell, phase)
+    with pytest.raises(pkg.JfftError):
+        cell.solve_newton(SHEAR, newton_tol=0.0)
+    with pytest.raises(pkg.JfftError):
+        cell.solve_newton(SHEAR, pcg_tol=1.5)
+    with pytest.raises(pkg.JfftError):
+        cell.solve_newton(np.array([0, 0, 0, 0, 0, np.inf]))
+    # the linear entry points refuse the power-law material, and a linear
+    # material set afterwards works again
+    with pytest.raises(pkg.JfftError) as e:
+        cell.solve(np.zeros(6))
+    assert e.value.name == "no_material"
+    lam, mu = oracle.lame_from_nu(0.3)
+    E = ji.uniform_random_field(shape, 1.0, 10.0, seed=2)
+    cell.set_material(E, nu=0.3)
+    u, sbar, rep, _ = cell.solve(np.array([1.0, 0, 0, 0, 0, 0]), tol=1e-10, maxit=500)
+    ref = oracle.solve(E, np.array([1.0, 0, 0, 0, 0, 0]), lam, mu, pc=oracle.PC_GREEN_JACOBI,
+                       tol=1e-10, maxit=500)
+    cell.close()
+    assert abs(rep.iters - ref.iters) <= 1
+    assert np.abs(u.cpu().numpy() - ref.u).max() <= 1e-9 * np.abs(ref.u).max()
