@@ -18,6 +18,7 @@ kernel and the CPU oracle baseline.
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256]
                        [--contrast 1e4] [--no-cpu] [--no-fp64] [--no-serve]
        python bench.py --workload simp2d [--cells 512]   (batched 2D SIMP cells)
+       python bench.py --workload powerlaw [--pl-n 200]  (nonlinear Newton example)
 """
 from __future__ import annotations
 
@@ -54,7 +55,9 @@ def parse():
     ap.add_argument("--graph", type=int, default=8,
                     help="PCG iterations per captured HIP graph in the timed steps (0: direct launches)")
     ap.add_argument("--serve-requests", type=int, default=40)
-    ap.add_argument("--workload", default="grf256", choices=["grf256", "simp2d", "contrast"],
+    ap.add_argument("--pl-n", type=int, default=200, help="powerlaw: nodes per axis")
+    ap.add_argument("--workload", default="grf256",
+                    choices=["grf256", "simp2d", "contrast", "powerlaw"],
                     help="grf256: the headline 256^3 cell (+ served stream); simp2d: 512 "
                          "batched 2D SIMP cells of uneven sizes")
     ap.add_argument("--cells", type=int, default=512, help="simp2d: number of cells")
@@ -98,6 +101,8 @@ def algorithmic_bytes(kernel, dim, N, n_x, real_bytes):
         "fft_y_inverse": 2 * spec,
         # spectrum, J^1/2 read; z written (r.z is formed in the Green pass)
         "fft_x_inverse": spec + 2 * field,
+        # power-law tangent: the CG stiffness traffic plus the Newton iterate
+        "stiffness_cg_tangent": 7 * field + scalar,
         "diag_precond": 5 * field,
     }
     return table.get(kernel)
@@ -387,6 +392,153 @@ def run_contrast_sweep(args):
             "rows": rows}
 
 
+def run_powerlaw(args):
+    """Nonlinear example of Sec. 4: n^3 nodes (voxels of unit edge), 8
+    spherical linear inclusions (radius 0.15 of the cell, seeded centres; the
+    paper does not give its geometry) in the power-law matrix (K = 2, sigma0 =
+    0.5, eps0 = 0.1, n = 5; inclusions K = 2, mu = 1/2), macro shear
+    e6 = 0.05 sqrt2 in one load step, Newton to ||f|| < 1e-5 with PCG to
+    ||r||^2 <= 1e-10 (the rules of Sec. 4), FP64.  One step = one whole
+    Newton solve (set the material, every Newton step with its Algorithm 2
+    diagonal and PCG solve, sigma_bar).  Headline: Green-Jacobi; the Green
+    preconditioner is timed beside it (PCG iterations per Newton step, the
+    figure of Sec. 4)."""
+    import torch
+
+    import jfft_inputs as ji
+    import paper_2508_02613_amd as pkg
+
+    n = args.pl_n
+    shape = (n, n, n)
+    phase = 1.0 - ji.spherical_inclusions(shape, 8, 0.15, seed=args.seed)
+    macro = np.array([0, 0, 0, 0, 0, 0.05 * np.sqrt(2)])
+    L = (float(n),) * 3
+    N = phase.size
+    dofs = 3 * N
+    ph = torch.from_numpy(phase).to("cuda")
+    stream = torch.cuda.Stream()
+    runs = {}
+    for name, pc in (("green_jacobi", pkg.PC_GREEN_JACOBI), ("green", pkg.PC_GREEN)):
+        cell = pkg.Cell(shape, precision=pkg.FP64, pc=pc, lengths=L, stream=stream)
+        if args.graph:
+            cell.set_graph_iterations(args.graph)
+        cell.set_stop_rule(absolute=True)
+        u = torch.empty((3,) + shape, dtype=torch.float64, device="cuda")
+
+        def step():
+            cell.set_material_powerlaw(ph)
+            return cell.solve_newton(macro, newton_tol=1e-5, pcg_tol=1e-10, max_newton=20,
+                                     maxit=20000, out=u)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = []
+        for _ in range(args.steps):
+            _, sbar, rep = step()
+            reps.append(rep)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        stats = None
+        if name == "green_jacobi":
+            cell.reset_timing()
+            cell.enable_timing(True)
+            step()
+            torch.cuda.synchronize()
+            stats = cell.kernel_stats()
+            cell.enable_timing(False)
+        cell.close()
+        runs[name] = {"wall_s": wall, "reps": reps, "sigma_bar": sbar, "stats": stats}
+    R = runs["green_jacobi"]
+    its = sum(sum(r.pcg_iters) for r in R["reps"])
+    value = dofs * its / R["wall_s"]
+    stats = R["stats"]
+    launches, tot_ms = stats["stiffness_cg"]
+    rep = R["reps"][-1]
+    executed = sum(rep.pcg_iters)
+    bytes_launch = algorithmic_bytes("stiffness_cg_tangent", 3, N, n, 8)
+    avg_ms = tot_ms / launches
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    G = runs["green"]
+    line = {
+        "metric": "DOF·iterations/s (power-law Newton, J-FFT PCG on the tangent)",
+        "value": value, "unit": "DOF·it/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * R["wall_s"] / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": (f"nonlinear example {n}^3 nodes, voxels of unit edge, 8 "
+                                f"spherical linear inclusions (radius 0.15, seed {args.seed}) in a "
+                                "power-law matrix (K 2, sigma0 0.5, eps0 0.1, n 5), macro shear "
+                                "e6 0.05 sqrt2, Newton to ||f|| < 1e-5, Green-Jacobi PCG to "
+                                "||r||^2 <= 1e-10, FP64"),
+                   "n": n, "dofs": dofs, "inclusion_fraction": float(1.0 - phase.mean()),
+                   "graph_iterations": args.graph},
+        "newton": {"green_jacobi": {"steps": rep.steps, "pcg_iters": rep.pcg_iters,
+                                    "res": rep.res, "ms_per_solve": 1e3 * R["wall_s"] / args.steps},
+                   "green": {"steps": G["reps"][-1].steps, "pcg_iters": G["reps"][-1].pcg_iters,
+                             "res": G["reps"][-1].res,
+                             "ms_per_solve": 1e3 * G["wall_s"] / args.steps,
+                             "value": dofs * sum(sum(r.pcg_iters) for r in G["reps"]) / G["wall_s"],
+                             "sigma_bar_rel_diff_vs_gj": float(
+                                 np.abs(G["sigma_bar"] - R["sigma_bar"]).max()
+                                 / np.abs(R["sigma_bar"]).max())}},
+        "sigma_bar": [float(v) for v in R["sigma_bar"]],
+        "roofline": {"bound": "hbm", "kernel": "stiffness_cg (power-law tangent)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": load_traffic(f"powerlaw_{n}", "stiffness_cg"),
+                     "avg_ms": avg_ms, "launches": launches, "launches_with_work": executed,
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "measured": "HIP events on the cell's stream around every launch, one "
+                                 "further Newton solve with direct launches"},
+        "kernels_ms_per_solve": {k: v[1] for k, v in sorted(stats.items())},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_powerlaw(args.seed)
+    return line
+
+
+def cpu_baseline_powerlaw(seed):
+    """The power-law oracle timed on one PCG iteration's operators (tangent
+    K(u) p by its vectorised element loop, Green-Jacobi preconditioner with
+    the naive separable DFT, dots and updates) at 100^3 nodes, an eighth of
+    the 200^3 cell: the full cell's element loop alone takes about a minute.
+    The element loop costs the same per DOF at any size; the naive DFT costs
+    n per point and axis, so the sample overstates the oracle's 200^3 rate
+    somewhat."""
+    import jfft_inputs as ji
+    import oracle
+    from oracle import powerlaw as pl
+
+    n = 100
+    shape = (n, n, n)
+    phase = 1.0 - ji.spherical_inclusions(shape, 8, 0.15, seed=seed)
+    rng = np.random.default_rng(0)
+    u = 0.01 * rng.standard_normal((3,) + shape)
+    p = rng.standard_normal((3,) + shape)
+    macro = np.array([0, 0, 0, 0, 0, 0.05 * np.sqrt(2)])
+    G = np.zeros((3, 3) + shape, dtype=complex)
+    G[0, 0] = 1.0
+    diag = np.ones((3,) + shape)
+    L = (float(n),) * 3
+    t0 = time.perf_counter()
+    q = pl.tangent_op(u, p, macro, phase, pl.PowerLaw(), L)
+    t1 = time.perf_counter()
+    z, _ = oracle.precond(oracle.PC_GREEN_JACOBI, q, diag=diag, G=G)
+    t2 = time.perf_counter()
+    a = float((p * q).sum())
+    p += a * z
+    t3 = time.perf_counter()
+    per_iter = t3 - t0
+    return {"value": 3 * phase.size / per_iter, "unit": "DOF·it/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": (f"one PCG iteration of the power-law oracle at {n}^3 (tangent element "
+                       f"loop {t1 - t0:.1f} s, Green-Jacobi M^-1 with naive DFT {t2 - t1:.1f} s, "
+                       f"dots/axpys {t3 - t2:.1f} s); Newton set-up excluded"),
+            "seconds_per_iteration": per_iter}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -407,6 +559,9 @@ def main():
         return
     if args.workload == "contrast":
         print(json.dumps(run_contrast_sweep(args)), flush=True)
+        return
+    if args.workload == "powerlaw":
+        print(json.dumps(run_powerlaw(args)), flush=True)
         return
     import jfft_inputs as ji
 

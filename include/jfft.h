@@ -221,7 +221,9 @@ jfft_status jfft_reset_timing(jfft_cell_t cell);
    probing result up to rounding;
    JFFT_DIAG_PROBING: Algorithm 2 as stated, d 2^d applications of K to unit
    combs.
-   Takes effect at the next set_material (a change clears the material). */
+   Takes effect at the next set_material (a change clears the material); for
+   the power-law material (jfft_set_material_powerlaw), at the next Newton
+   solve or operator call. */
 #define JFFT_DIAG_CLOSED_FORM 0
 #define JFFT_DIAG_PROBING 1
 jfft_status jfft_set_diag_method(jfft_cell_t cell, int method);
@@ -254,7 +256,11 @@ jfft_status jfft_set_mixed_params(jfft_cell_t cell, double inner_tol, int max_ou
    2 mu_incl dev(eps).  Needs K, sigma0, eps0, K_incl, mu_incl > 0, n >= 1.
    The Green reference material is the inclusion's (lambda = K_incl -
    2 mu_incl / 3, mu = mu_incl); the Jacobi factor, if the preconditioner
-   has one, is Algorithm 2 on the tangent K(u) at every Newton step.  The
+   has one, is Algorithm 2's diagonal of the tangent K(u) at every Newton
+   step: by default in closed form, formed in the pass that evaluates f(u)
+   (per Gauss point, w beta^T C beta for the unit strains beta of each
+   node's displacement components); with JFFT_DIAG_PROBING by the d 2^d
+   applications of K(u) to unit combs.  The
    handle allocates one [3][N] iterate on first use (freed with the handle).
    A later jfft_set_material returns the handle to the linear problem; the
    linear entry points report JFFT_E_NO_MATERIAL while the power-law
@@ -263,10 +269,12 @@ jfft_status jfft_set_material_powerlaw(jfft_cell_t cell, const double *phase_dev
                                        double sigma0, double eps0, double n, double K_incl,
                                        double mu_incl);
 /* Newton from u = 0 on f(u) = -B^T W sigma(E + B u): stop when ||f||_2 <
-   newton_tol, else solve K(u) du = f(u) by PCG from du = 0 to relative
-   residual max(pcg_tol, newton_tol / (10 ||f||)) (at most maxit iterations;
-   a PCG breakdown ends that inner solve and the step goes on) and set
-   u += du; at most max_newton steps.  Outputs: u_dev [3][N] device (mean
+   newton_tol, else solve K(u) du = f(u) by PCG from du = 0 (at most maxit
+   iterations; a PCG breakdown ends that inner solve and the step goes on)
+   and set u += du; at most max_newton steps.  The inner solve stops, under
+   the relative stop rule (default), at ||r|| <= max(pcg_tol, newton_tol /
+   (10 ||f||)) ||f|| (0 < pcg_tol < 1); under JFFT_STOP_ABSOLUTE
+   (jfft_set_stop_rule) at ||r||^2 <= pcg_tol, the rule of Sec. 4.  Outputs: u_dev [3][N] device (mean
    removed, Sec. 5), sigma_bar[6] host (volume average of sigma(E + B u),
    Mandel), and optionally (host, may be NULL) pcg_iters[max_newton] (PCG
    iterations per step), res_norms[max_newton + 1] (||f|| before each step
@@ -278,7 +286,7 @@ jfft_status jfft_solve_newton(jfft_cell_t cell, const double *macro_strain, doub
 /* Operators of a Newton step at the iterate uk_dev [3][N] (device) for the
    macroscopic strain macro_strain[6] (host): f = -B^T W sigma(E + B uk);
    out = K(uk) in; diag(K(uk)) by Algorithm 2 (no void rule).  Device
-   outputs [3][N]; synchronous. */
+   outputs [3][N]; synchronous.  The diagonal follows jfft_set_diag_method. */
 jfft_status jfft_powerlaw_force(jfft_cell_t cell, const double *macro_strain, const double *uk_dev,
                                 double *f_dev);
 jfft_status jfft_powerlaw_tangent(jfft_cell_t cell, const double *macro_strain, const double *uk_dev,

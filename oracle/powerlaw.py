@@ -22,7 +22,8 @@ definitions:
   / eps_eq);
 * Newton: f(u) = -B^T W sigma(E + B u); stop when ||f|| < eta; solve
   K(u) du = f(u) with PCG to max(pcg_tol ||f||, eta / 10) (no inner solve
-  below the Newton tolerance); u += du.
+  below the Newton tolerance), or to ||r||^2 <= pcg_tol (the absolute rule of
+  Sec. 4); u += du.
 """
 from __future__ import annotations
 
@@ -251,9 +252,12 @@ class NewtonResult:
 
 
 def newton(phase, macro, prm: PowerLaw, pc=oracle.PC_GREEN_JACOBI, newton_tol=1e-5,
-           pcg_tol=1e-8, max_newton=20, maxit=5000, lam_ref=None, mu_ref=None, lengths=None):
+           pcg_tol=1e-8, max_newton=20, maxit=5000, lam_ref=None, mu_ref=None, lengths=None,
+           pcg_absolute=False):
     """Newton with PCG inner solves from u^(0) = 0 (Sec. 2.2); the Green
-    reference material defaults to the inclusion's."""
+    reference material defaults to the inclusion's.  pcg_absolute: the inner
+    solve stops at ||r||^2 <= pcg_tol (the stopping rule of Sec. 4) instead
+    of the relative rule with the inexact-Newton floor."""
     shape = phase.shape
     if lam_ref is None:
         lam_ref, mu_ref = prm.K_incl - 2.0 * prm.mu_incl / 3.0, prm.mu_incl
@@ -273,8 +277,11 @@ def newton(phase, macro, prm: PowerLaw, pc=oracle.PC_GREEN_JACOBI, newton_tol=1e
         diag = None
         if pc in (oracle.PC_JACOBI, oracle.PC_GREEN_JACOBI):
             diag = jacobi_diag(u, macro, phase, prm, lengths)
-        # inexact Newton: no inner solve below a tenth of the Newton tolerance
-        rtol = max(pcg_tol, 0.1 * newton_tol / fn)
+        if pcg_absolute:
+            rtol = np.sqrt(pcg_tol) / fn
+        else:
+            # inexact Newton: no inner solve below a tenth of the Newton tolerance
+            rtol = max(pcg_tol, 0.1 * newton_tol / fn)
         du, k = pcg(lambda p: tangent_op(u, p, macro, phase, prm, lengths), f, pc, diag, G,
                     rtol, maxit)
         out.pcg_iters.append(k)

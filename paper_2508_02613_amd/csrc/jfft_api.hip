@@ -1169,6 +1169,7 @@ jfft_status set_material_powerlaw_impl(jfft_cell_s *c, const double *phase_dev, 
   c->pl.K = K;
   c->pl.gcoef = sigma0 * (2.0 / 3.0) / std::pow(eps0, n);
   c->pl.n = n;
+  c->pl.ipow = (n == std::floor(n) && n - 1.0 <= 64.0) ? (int)(n - 1.0) : -1;
   c->pl.Ki = K_incl;
   c->pl.mui = mu_incl;
   c->lam = K_incl - 2.0 * mu_incl / 3.0;  // Green reference: the inclusion
@@ -1191,13 +1192,21 @@ void set_macro_pl(jfft_cell_s *c, const double *macro_h) {
 
 long long node_blocks(const jfft_cell_s *c) { return (c->g.N + 255) / 256; }
 
-// f = f(uk) into `f`, ||f||^2 into small[0] (not fetched).
-jfft_status nl_force(jfft_cell_s *c, double *f) {
+// f = f(uk) into `f`, ||f||^2 into small[0] (not fetched); with diag != NULL
+// also diag(K(uk)) in closed form (the result of Algorithm 2).
+jfft_status nl_force(jfft_cell_s *c, double *f, double *diag) {
   const GridDev &g = c->g;
   const long long nb = node_blocks(c);
-  LAUNCH(c, KID_RHS, k_nl_force<double><<<(unsigned)nb, 256, 0, c->stream>>>(c->uk, c->E, f, c->partA, c->pl, g.w, g.ihx, g.ihy, g.ihz, g.nx, g.ny, g.nz, g.N));
+  if (diag)
+    LAUNCH(c, KID_RHS, (k_nl_force<double, true><<<(unsigned)nb, 256, 0, c->stream>>>(c->uk, c->E, f, diag, c->partA, c->pl, g.w, g.ihx, g.ihy, g.ihz, g.nx, g.ny, g.nz, g.N)));
+  else
+    LAUNCH(c, KID_RHS, (k_nl_force<double, false><<<(unsigned)nb, 256, 0, c->stream>>>(c->uk, c->E, f, nullptr, c->partA, c->pl, g.w, g.ihx, g.ihy, g.ihz, g.nx, g.ny, g.nz, g.N)));
   return reduce_to(c, c->partA, nb, 1, 0, 1);
 }
+
+// diag(K(uk)) is formed with the force (closed form) unless Algorithm 2's
+// probing is selected.
+bool nl_closed_diag(const jfft_cell_s *c) { return c->diag_method == JFFT_DIAG_CLOSED_FORM; }
 
 // sum over Gauss points of sigma(E + B uk) / (8 N) into small[16..21] (not fetched).
 jfft_status nl_stress_avg(jfft_cell_s *c) {
@@ -1207,11 +1216,12 @@ jfft_status nl_stress_avg(jfft_cell_s *c) {
   return reduce_to(c, c->partB, nb, 6, 16, 1);
 }
 
-// J^1/2 of the tangent at uk (Algorithm 2, or nothing without a Jacobi factor).
+// J^1/2 of the tangent at uk from c->diag (formed with the force in closed
+// form, or here by Algorithm 2's probing); nothing without a Jacobi factor.
 jfft_status nl_jacobi(jfft_cell_s *c) {
   if (!useJ(c)) return JFFT_OK;
   const long long nd = 3 * c->g.N;
-  TRY(run_alg2(c, c->diag, 1));
+  if (!nl_closed_diag(c)) TRY(run_alg2(c, c->diag, 1));
   LAUNCH(c, KID_SETUP, k_jhalf<double><<<dim3(vec_blocks(nd), 1), 256, 0, c->stream>>>(c->diag, c->Jh, nd, c->void_value, c->cs));
   return JFFT_OK;
 }
@@ -1221,8 +1231,10 @@ jfft_status newton_impl(jfft_cell_s *c, const double *macro_h, double newton_tol
                         int *pcg_iters, double *res_norms, int *steps_out) {
   if (!c->nl) return fail(JFFT_E_NO_MATERIAL, "set the power-law material first");
   if (!macro_h || !u_out || !sigma_bar) return fail(JFFT_E_INVALID, "NULL macro_strain, u_dev or sigma_bar");
-  if (!(newton_tol > 0.0) || !(pcg_tol > 0.0 && pcg_tol < 1.0) || max_newton < 0 || maxit < 0)
-    return fail(JFFT_E_INVALID, "need newton_tol > 0, 0 < pcg_tol < 1, max_newton >= 0, maxit >= 0");
+  if (!(newton_tol > 0.0) || !(pcg_tol > 0.0) || (!c->stop_abs && !(pcg_tol < 1.0)) ||
+      max_newton < 0 || maxit < 0)
+    return fail(JFFT_E_INVALID, "need newton_tol > 0, pcg_tol > 0 (< 1 for the relative rule), "
+                                "max_newton >= 0, maxit >= 0");
   for (int k = 0; k < 6; ++k)
     if (!std::isfinite(macro_h[k])) return fail(JFFT_E_INVALID, "macro_strain must be finite");
   set_macro_pl(c, macro_h);
@@ -1233,7 +1245,7 @@ jfft_status newton_impl(jfft_cell_s *c, const double *macro_h, double newton_tol
   int steps = 0;
   bool converged = false, broke = false;
   for (;;) {
-    TRY(nl_force(c, c->f));
+    TRY(nl_force(c, c->f, useJ(c) && nl_closed_diag(c) ? c->diag : nullptr));
     TRY(fetch_small(c));
     const double fn = std::sqrt(c->small_h[0]);
     if (res_norms) res_norms[steps] = fn;
@@ -1244,10 +1256,11 @@ jfft_status newton_impl(jfft_cell_s *c, const double *macro_h, double newton_tol
     }
     if (steps == max_newton) break;
     TRY(nl_jacobi(c));
-    // inexact Newton: no inner solve below a tenth of the Newton tolerance
-    const double rtol = std::max(pcg_tol, 0.1 * newton_tol / fn);
+    // relative rule: inexact Newton, no inner solve below a tenth of the
+    // Newton tolerance; absolute rule: ||r||^2 <= pcg_tol as in Sec. 4
+    const double itol = c->stop_abs ? pcg_tol : std::max(pcg_tol, 0.1 * newton_tol / fn);
     LAUNCH(c, KID_VEC, k_dot<double><<<dim3(nb, 1), 256, 0, c->stream>>>(c->f, c->f, nd, c->partA, c->cs));
-    LAUNCH(c, KID_CTRL, k_solve_norms<<<1, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, c->partA, nb, rtol, 0, c->cs));
+    LAUNCH(c, KID_CTRL, k_solve_norms<<<1, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, c->partA, nb, itol, c->stop_abs ? 1 : 0, c->cs));
     LAUNCH(c, KID_VEC, k_fill<double><<<dim3(nb, 1), 256, 0, c->stream>>>(c->u, 0.0, nd, 0));
     LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, 1), 256, 0, c->stream>>>(c->f, 0, c->r, 0, nd));
     TRY(run_pcg<double>(c, b, false, maxit, false));
@@ -1615,7 +1628,7 @@ jfft_status jfft_powerlaw_force(jfft_cell_t c, const double *macro_strain, const
                                 double *f_dev) {
   if (!c || !f_dev) return fail(JFFT_E_INVALID, "NULL argument");
   TRY(nl_operator_prep(c, macro_strain, uk_dev));
-  TRY(nl_force(c, f_dev));
+  TRY(nl_force(c, f_dev, nullptr));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return JFFT_OK;
 }
@@ -1633,7 +1646,10 @@ jfft_status jfft_powerlaw_jacobi_diag(jfft_cell_t c, const double *macro_strain,
                                       const double *uk_dev, double *diag_dev) {
   if (!c || !diag_dev) return fail(JFFT_E_INVALID, "NULL argument");
   TRY(nl_operator_prep(c, macro_strain, uk_dev));
-  TRY(run_alg2(c, diag_dev, 1));
+  if (nl_closed_diag(c))
+    TRY(nl_force(c, c->f, diag_dev));
+  else
+    TRY(run_alg2(c, diag_dev, 1));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return JFFT_OK;
 }

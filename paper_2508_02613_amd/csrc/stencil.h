@@ -68,7 +68,36 @@ struct PowerLawArgs {
   double K, gcoef, n;
   double Ki, mui;
   double macro[6];
+  int ipow;  // n - 1 when it is a whole number in [0, 64] (powers by squaring), else -1
 };
+
+// g = gcoef s^k and h = g k / (e.e) (k = n - 1, s = eps_eq, e.e = 1.5 s^2)
+// from e.e.  A whole k takes products of s^2 (and one sqrt for odd k), and
+// for k >= 2, h = (2/3) k gcoef s^(k-2) without a division; otherwise pow.
+// g(0) = h(0) = 0 for n > 1.
+template <typename Real>
+__device__ __forceinline__ void powerlaw_gh(Real ee, const PowerLawArgs &m, Real &g, Real &h) {
+  const Real s2 = (Real)(2.0 / 3.0) * ee, gc = (Real)m.gcoef;
+  const int k = m.ipow;
+  if (k == 0) {
+    g = gc;
+    h = (Real)0;
+  } else if (k >= 2) {
+    // t = s^(k - 2)
+    Real t = (Real)1, b = s2;
+    for (int e = (k - 2) >> 1; e; e >>= 1) {
+      if (e & 1) t *= b;
+      b *= b;
+    }
+    if (k & 1) t *= sqrt(s2);
+    g = gc * t * s2;
+    h = (Real)(2.0 / 3.0) * (Real)k * gc * t;
+  } else {
+    const Real s = sqrt(s2), kn = (Real)m.n - (Real)1;
+    g = s > (Real)0 ? (k == 1 ? gc * s : gc * pow(s, kn)) : (Real)0;
+    h = ee > (Real)0 ? g * kn / ee : (Real)0;
+  }
+}
 
 template <typename Real>
 struct StencilArgs {
@@ -293,14 +322,8 @@ __device__ __forceinline__ void powerlaw_tangent(const Real (&eps)[6], const Rea
       ee += e[k] * e[k];
       ed += e[k] * d[k];
     }
-    const Real seq = sqrt((Real)(2.0 / 3.0) * ee);
-    const Real n = (Real)m.n;
-    Real g = (Real)0;
-    if (n == (Real)1)
-      g = (Real)m.gcoef;
-    else if (seq > (Real)0)
-      g = (Real)m.gcoef * pow(seq, n - (Real)1);
-    const Real h = ee > (Real)0 ? g * (n - (Real)1) / ee : (Real)0;
+    Real g, h;
+    powerlaw_gh(ee, m, g, h);
     const Real kt = (Real)m.K * dtr, g3 = g * dtr / (Real)3, he = h * ed;
 #pragma unroll
     for (int k = 0; k < 6; ++k) sg[k] = g * d[k] + he * e[k] + (k < 3 ? kt - g3 : (Real)0);
@@ -1358,32 +1381,6 @@ __global__ void __launch_bounds__(256)
 }
 
 // ----------------------------------------------- power-law Newton pieces ----
-// The law (no tangent): matrix sigma = K tr(eps) I + g(eps_eq) e, inclusion
-// sigma = Ki tr(eps) I + 2 mui e (Mandel).
-template <typename Real>
-__device__ __forceinline__ void powerlaw_stress(const Real (&eps)[6], bool matrix,
-                                                const PowerLawArgs &m, Real (&sg)[6]) {
-  const Real tr = eps[0] + eps[1] + eps[2], tr3 = tr / (Real)3;
-  Real e[6], ee = 0;
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    e[k] = eps[k] - (k < 3 ? tr3 : (Real)0);
-    ee += e[k] * e[k];
-  }
-  Real g, kt;
-  if (matrix) {
-    const Real seq = sqrt((Real)(2.0 / 3.0) * ee), n = (Real)m.n;
-    g = n == (Real)1 ? (Real)m.gcoef
-                     : (seq > (Real)0 ? (Real)m.gcoef * pow(seq, n - (Real)1) : (Real)0);
-    kt = (Real)m.K * tr;
-  } else {
-    g = (Real)(2.0 * m.mui);
-    kt = (Real)m.Ki * tr;
-  }
-#pragma unroll
-  for (int k = 0; k < 6; ++k) sg[k] = g * e[k] + (k < 3 ? kt : (Real)0);
-}
-
 // Element corner values of the nodal field at the element with lowest node
 // (ex, ey, ez) (periodic).
 template <typename Real>
@@ -1400,96 +1397,118 @@ __device__ __forceinline__ void gather_hex(const Real *u, long long N, int nx, i
   }
 }
 
-// Gauss-point stresses of one element (weight w) folded into its corner forces.
+// Moduli of the linearised law at a Gauss point with strain eps: sigma =
+// kb tr(eps) I + g e and tangent C = kb I (x) I + g P_dev + h e (x) e, e =
+// dev(eps) (inclusion: kb = Ki, g = 2 mui, h = 0).
 template <typename Real>
-__device__ __forceinline__ void elem_hex_law(const Real (&uk)[3][8], bool matrix,
-                                             const PowerLawArgs &m, Real w, Real ihx, Real ihy,
-                                             Real ihz, Real (&y)[3][8], Real (&ssum)[6]) {
-  Real kX[3][2][2], kY[3][2][2], kZ[3][2][2];
+__device__ __forceinline__ void powerlaw_point(const Real (&eps)[6], bool matrix,
+                                               const PowerLawArgs &m, Real (&e)[6], Real &tr,
+                                               Real &kb, Real &g, Real &h) {
+  tr = eps[0] + eps[1] + eps[2];
+  const Real tr3 = tr / (Real)3;
+  Real ee = 0;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) grad_hex(uk[i], ihx, ihy, ihz, kX[i], kY[i], kZ[i]);
-  Real SX[3][2][2], SY[3][2][2], SZ[3][2][2];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) SX[i][a][b] = SY[i][a][b] = SZ[i][a][b] = (Real)0;
-#pragma unroll
-  for (int k = 0; k < 6; ++k) ssum[k] = (Real)0;
-  const Real r2 = (Real)0.70710678118654752440084436210485;
-#pragma unroll
-  for (int gx = 0; gx < 2; ++gx)
-#pragma unroll
-    for (int gy = 0; gy < 2; ++gy)
-#pragma unroll
-      for (int gz = 0; gz < 2; ++gz) {
-        Real es[6], sg[6];
-        mandel_strain(kX, kY, kZ, gx, gy, gz, es);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) es[k] += (Real)m.macro[k];
-        powerlaw_stress(es, matrix, m, sg);
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          ssum[k] += sg[k];
-          sg[k] *= w;
-        }
-        const Real s23 = sg[3] * r2, s13 = sg[4] * r2, s12 = sg[5] * r2;
-        SX[0][gy][gz] += sg[0];
-        SY[0][gx][gz] += s12;
-        SZ[0][gx][gy] += s13;
-        SX[1][gy][gz] += s12;
-        SY[1][gx][gz] += sg[1];
-        SZ[1][gx][gy] += s23;
-        SX[2][gy][gz] += s13;
-        SY[2][gx][gz] += s23;
-        SZ[2][gx][gy] += sg[2];
-      }
-#pragma unroll
-  for (int i = 0; i < 3; ++i) force_hex(SX[i], SY[i], SZ[i], ihx, ihy, ihz, y[i]);
+  for (int k = 0; k < 6; ++k) {
+    e[k] = eps[k] - (k < 3 ? tr3 : (Real)0);
+    ee += e[k] * e[k];
+  }
+  if (matrix) {
+    powerlaw_gh(ee, m, g, h);
+    kb = (Real)m.K;
+  } else {
+    g = (Real)(2.0 * m.mui);
+    h = (Real)0;
+    kb = (Real)m.Ki;
+  }
 }
 
-// Newton right-hand side f = -B^T W sigma(E + B uk) (eq. lin_system), one
-// thread per node: the node is corner o of the elements node - o, o in
-// {0,1}^3; each of them is evaluated and its force on corner o taken (every
-// element is evaluated by each of its 8 nodes: no atomics, fixed order).
+// Newton right-hand side f = -B^T W sigma(E + B uk) (eq. lin_system) and,
+// with DIAG, the diagonal of the tangent K(uk) = B^T W C B, one thread per
+// node.  The node is corner o of the elements node - o, o in {0,1}^3; at
+// each of their Gauss points q the shape gradient b = grad N_o(q) gives the
+// node's force w sigma(q) b and, for component a, the diagonal entry
+// w beta_a^T C(q) beta_a of the unit strain beta_a = sym(e_a (x) b):
+//   beta^T C beta = kb tr^2 + g (beta.beta - tr^2 / 3) + h (e.beta)^2
+// (what Algorithm 2 returns, in one pass; no atomics, fixed order).
 // part: per-block ||f||^2 partials.
-template <typename Real>
+template <typename Real, bool DIAG>
 __global__ void __launch_bounds__(256)
-    k_nl_force(const Real *uk, const Real *phase, Real *f, double *part, PowerLawArgs m, Real w,
-               Real ihx, Real ihy, Real ihz, int nx, int ny, int nz, long long N) {
+    k_nl_force(const Real *uk, const Real *phase, Real *f, Real *diag, double *part,
+               PowerLawArgs m, Real w, Real ihx, Real ihy, Real ihz, int nx, int ny, int nz,
+               long long N) {
   __shared__ double red[4];
   const long long plane = (long long)nx * ny;
+  const Real r2 = (Real)0.70710678118654752440084436210485;
   double ff = 0.0;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x) {
     const int z = (int)(i / plane);
     const long long rem = i - (long long)z * plane;
     const int y = (int)(rem / nx), x = (int)(rem - (long long)y * nx);
-    Real acc[3] = {0, 0, 0};
+    Real acc[3] = {0, 0, 0}, dg[3] = {0, 0, 0};
     for (int o = 0; o < 8; ++o) {
       const int ox = o & 1, oy = (o >> 1) & 1, oz = o >> 2;
       const int ex = x - ox < 0 ? nx - 1 : x - ox, ey = y - oy < 0 ? ny - 1 : y - oy,
                 ez = z - oz < 0 ? nz - 1 : z - oz;
-      Real v[3][8], yv[3][8], ss[6];
+      Real v[3][8];
       gather_hex(uk, N, nx, ny, nz, ex, ey, ez, v);
       const bool matrix = phase[(long long)ex + (long long)nx * ey + plane * ez] > (Real)0.5;
-      elem_hex_law(v, matrix, m, w, ihx, ihy, ihz, yv, ss);
+      Real kX[3][2][2], kY[3][2][2], kZ[3][2][2];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) acc[c] += yv[c][o];
+      for (int c = 0; c < 3; ++c) grad_hex(v[c], ihx, ihy, ihz, kX[c], kY[c], kZ[c]);
+#pragma unroll
+      for (int gx = 0; gx < 2; ++gx)
+#pragma unroll
+        for (int gy = 0; gy < 2; ++gy)
+#pragma unroll
+          for (int gz = 0; gz < 2; ++gz) {
+            Real es[6], e[6], tr, kb, g, h;
+            mandel_strain(kX, kY, kZ, gx, gy, gz, es);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) es[k] += (Real)m.macro[k];
+            powerlaw_point(es, matrix, m, e, tr, kb, g, h);
+            Real sg[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sg[k] = g * e[k] + (k < 3 ? kb * tr : (Real)0);
+            // grad N_o at the Gauss point
+            const Real lx = gx == ox ? gA<Real>() : gB<Real>();
+            const Real ly = gy == oy ? gA<Real>() : gB<Real>();
+            const Real lz = gz == oz ? gA<Real>() : gB<Real>();
+            const Real bx = (ox ? ihx : -ihx) * ly * lz;
+            const Real by = (oy ? ihy : -ihy) * lx * lz;
+            const Real bz = (oz ? ihz : -ihz) * lx * ly;
+            acc[0] += sg[0] * bx + r2 * (sg[5] * by + sg[4] * bz);
+            acc[1] += sg[1] * by + r2 * (sg[5] * bx + sg[3] * bz);
+            acc[2] += sg[2] * bz + r2 * (sg[4] * bx + sg[3] * by);
+            if (DIAG) {
+              const Real b2x = bx * bx, b2y = by * by, b2z = bz * bz;
+              const Real bb[3] = {b2x + (Real)0.5 * (b2y + b2z), b2y + (Real)0.5 * (b2x + b2z),
+                                  b2z + (Real)0.5 * (b2x + b2y)};
+              const Real t2[3] = {b2x, b2y, b2z};
+              const Real eb[3] = {e[0] * bx + r2 * (e[5] * by + e[4] * bz),
+                                  e[1] * by + r2 * (e[5] * bx + e[3] * bz),
+                                  e[2] * bz + r2 * (e[4] * bx + e[3] * by)};
+#pragma unroll
+              for (int a = 0; a < 3; ++a)
+                dg[a] += kb * t2[a] + g * (bb[a] - t2[a] / (Real)3) + h * eb[a] * eb[a];
+            }
+          }
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      f[c * N + i] = -acc[c];
-      ff += (double)acc[c] * (double)acc[c];
+      const Real fc = -w * acc[c];
+      f[c * N + i] = fc;
+      ff += (double)fc * (double)fc;
+      if (DIAG) diag[c * N + i] = w * dg[c];
     }
   }
   const double s = block_sum<256>(ff, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// Sum of the Gauss-point stresses sigma(E + B uk) per block: part[k * nblocks
-// + block], k = 0..5 (the volume average is the total / (8 N)).
+// Sum of the Gauss-point stresses sigma(E + B uk) per block, one element per
+// thread: part[k * nblocks + block], k = 0..5 (the volume average is the
+// total / (8 N)).
 template <typename Real>
 __global__ void __launch_bounds__(256)
     k_nl_stress_sum(const Real *uk, const Real *phase, double *part, PowerLawArgs m, Real ihx,
@@ -1502,11 +1521,26 @@ __global__ void __launch_bounds__(256)
     const int z = (int)(i / plane);
     const long long rem = i - (long long)z * plane;
     const int y = (int)(rem / nx), x = (int)(rem - (long long)y * nx);
-    Real v[3][8], yv[3][8], ss[6];
+    Real v[3][8];
     gather_hex(uk, N, nx, ny, nz, x, y, z, v);
-    elem_hex_law(v, phase[i] > (Real)0.5, m, (Real)1, ihx, ihy, ihz, yv, ss);
+    const bool matrix = phase[i] > (Real)0.5;
+    Real kX[3][2][2], kY[3][2][2], kZ[3][2][2];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) acc[k] += (double)ss[k];
+    for (int c = 0; c < 3; ++c) grad_hex(v[c], ihx, ihy, ihz, kX[c], kY[c], kZ[c]);
+#pragma unroll
+    for (int gx = 0; gx < 2; ++gx)
+#pragma unroll
+      for (int gy = 0; gy < 2; ++gy)
+#pragma unroll
+        for (int gz = 0; gz < 2; ++gz) {
+          Real es[6], e[6], tr, kb, g, h;
+          mandel_strain(kX, kY, kZ, gx, gy, gz, es);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) es[k] += (Real)m.macro[k];
+          powerlaw_point(es, matrix, m, e, tr, kb, g, h);
+#pragma unroll
+          for (int k = 0; k < 6; ++k) acc[k] += (double)(g * e[k] + (k < 3 ? kb * tr : (Real)0));
+        }
   }
   for (int k = 0; k < 6; ++k) {
     const double s = block_sum<256>(acc[k], red);

@@ -161,3 +161,20 @@ def test_newton_power_law_converges_quadratically():
     q = r[2:] / r[1:-1] ** 2
     assert r[-1] < 1e-6 * r[1] and q.max() < 1e3 * max(q.min(), 1e-3) + 1e6
     assert r[-1] / r[-2] < 1e-2
+
+
+def test_newton_absolute_inner_rule_equals_relative_rule_at_same_threshold():
+    """The absolute inner rule ||r||^2 <= t stops where the relative rule
+    ||r|| <= (sqrt(t) / ||f||) ||f|| does: one linear-limit step, same PCG
+    iterations and result for t = (1e-9 ||f_0||)^2."""
+    prm1, mu = _linear_prm()
+    prm1.K_incl, prm1.mu_incl = 10 * prm1.K, 10 * mu
+    shape = (8, 8, 8)
+    phase = 1.0 - ji.spherical_inclusions(shape, 2, 0.2, seed=1)
+    macro = np.array([0, 0, 0, 0, 0, 0.05 * np.sqrt(2)])
+    f0 = np.linalg.norm(pl.force(np.zeros((3,) + shape), macro, phase, prm1))
+    rel = pl.newton(phase, macro, prm1, newton_tol=1e-30, pcg_tol=1e-9, max_newton=1)
+    ab = pl.newton(phase, macro, prm1, newton_tol=1e-30, pcg_tol=(1e-9 * f0) ** 2, max_newton=1,
+                   pcg_absolute=True)
+    assert rel.pcg_iters == ab.pcg_iters and rel.pcg_iters[0] > 3
+    assert np.abs(rel.u - ab.u).max() <= 1e-12 * np.abs(rel.u).max()
