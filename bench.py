@@ -36,6 +36,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, FP64 vector (no MFMA)
+# FP64 flops of one element evaluation of the power-law tangent stiffness
+# kernel (strain of the iterate and of p at 8 Gauss points, tangent, weighted
+# divergence): 64 lanes x (ADD + MUL + TRANS + 2 FMA) wave instructions of a
+# launch over its element evaluations, from rocprofv3 SQ_INSTS_VALU_*_F64
+# counters (profiles/fp64_ops_powerlaw200.txt)
+TANGENT_FLOPS_PER_ELEMENT = 2267.2
 
 
 def parse():
@@ -458,8 +465,10 @@ def run_powerlaw(args):
     rep = R["reps"][-1]
     executed = sum(rep.pcg_iters)
     bytes_launch = algorithmic_bytes("stiffness_cg_tangent", 3, N, n, 8)
+    flops_launch = TANGENT_FLOPS_PER_ELEMENT * N
     avg_ms = tot_ms / launches
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    tflops = flops_launch / (avg_ms * 1e-3) / 1e12
     G = runs["green"]
     line = {
         "metric": "DOF·iterations/s (power-law Newton, J-FFT PCG on the tangent)",
@@ -484,10 +493,13 @@ def run_powerlaw(args):
                                  np.abs(G["sigma_bar"] - R["sigma_bar"]).max()
                                  / np.abs(R["sigma_bar"]).max())}},
         "sigma_bar": [float(v) for v in R["sigma_bar"]],
-        "roofline": {"bound": "hbm", "kernel": "stiffness_cg (power-law tangent)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
+        "roofline": {"bound": "alu", "kernel": "stiffness_cg (power-law tangent)",
+                     "achieved": tflops, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": tflops / FP64_VECTOR_PEAK_TFLOPS,
                      "traffic": load_traffic(f"powerlaw_{n}", "stiffness_cg"),
+                     "algorithmic_flops_per_launch": flops_launch,
+                     "flops_per_element": TANGENT_FLOPS_PER_ELEMENT,
+                     "hbm_achieved_gbs": achieved, "hbm_frac": achieved / HBM_PEAK_GBS,
                      "avg_ms": avg_ms, "launches": launches, "launches_with_work": executed,
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "measured": "HIP events on the cell's stream around every launch, one "
