@@ -129,7 +129,8 @@ jfft_status jfft_set_material_lame(jfft_cell_t cell, const double *E_dev, double
      u0_dev: start vector [d][N] or NULL for u0 = 0;
      u_dev:  out [d][N], the fluctuation with its per-component mean removed
              (Sec. 5: Green-Jacobi iterates carry a mean);
-     sigma_dev: out [d*][2^d][N] quadrature-point stresses (Mandel) or NULL;
+     sigma_dev: out [d*][2^d][N] quadrature-point stresses (Mandel) or NULL
+             ([3][2][N] for 2D linear triangles, see jfft_set_element);
      sigma_bar: host out, d* homogenised stresses (1/|Y|) sum w sigma_q;
      report: host out (may be NULL).
    A homogeneous material (||f|| <= 1e-13 ||f_abs||, f_abs assembled from
@@ -227,6 +228,19 @@ jfft_status jfft_reset_timing(jfft_cell_t cell);
 #define JFFT_DIAG_CLOSED_FORM 0
 #define JFFT_DIAG_PROBING 1
 jfft_status jfft_set_diag_method(jfft_cell_t cell, int method);
+
+/* 2D element (Sec. 2; the paper's 2D examples use linear triangles):
+   JFFT_ELEM_QUAD (default): bilinear quadrilateral per pixel, 2 x 2 Gauss
+   points; JFFT_ELEM_TRI: the pixel split along its anti-diagonal into two
+   linear triangles (corners (0,0), (1,0), (0,1) and (1,1), (0,1), (1,0) in
+   units of the element edges), one exact quadrature point each.  2D cells
+   only (JFFT_E_INVALID otherwise).  With triangles, diag(K) always comes
+   from Algorithm 2's probing, the Green operator from K_ref of the
+   triangles, and jfft_solve's sigma_dev holds [B][3][2][N] (one point per
+   triangle).  A change clears the material. */
+#define JFFT_ELEM_QUAD 0
+#define JFFT_ELEM_TRI 1
+jfft_status jfft_set_element(jfft_cell_t cell, int element);
 
 /* Value of the void rule replacement for exact zeros of diag(K) (Sec. 3.2,
    default 1.0). */

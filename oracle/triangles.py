@@ -175,6 +175,7 @@ class SolveResult:
     iters: int
     relres_true: float
     status: str
+    res: np.ndarray  # recursive ||r_k||, k = 1..iters
 
 
 def solve(E, macro, lam, mu, pc=oracle.PC_GREEN_JACOBI, lam_ref=None, mu_ref=None, tol=1e-8,
@@ -200,6 +201,7 @@ def solve(E, macro, lam, mu, pc=oracle.PC_GREEN_JACOBI, lam_ref=None, mu_ref=Non
     u = np.zeros((2,) + E.shape)
     r = f.copy()
     k = 0
+    hist = []
     status = "ok"
     homog = fn <= 1e-13 * fan
     if not (homog or done(np.linalg.norm(r))):
@@ -219,7 +221,8 @@ def solve(E, macro, lam, mu, pc=oracle.PC_GREEN_JACOBI, lam_ref=None, mu_ref=Non
             u += alpha * p
             r -= alpha * q
             k += 1
-            if done(np.linalg.norm(r)):
+            hist.append(np.linalg.norm(r))
+            if done(hist[-1]):
                 break
             if k >= maxit:
                 status = "not_converged"
@@ -232,4 +235,5 @@ def solve(E, macro, lam, mu, pc=oracle.PC_GREEN_JACOBI, lam_ref=None, mu_ref=Non
     rt = np.linalg.norm(f - stiffness(E, u, lam, mu, lengths))
     _, sbar = stress(E, macro, u, lam, mu, lengths)
     return SolveResult(u=u, sigma_bar=sbar, iters=k,
-                       relres_true=(rt / fn if fn > 0 and not homog else 0.0), status=status)
+                       relres_true=(rt / fn if fn > 0 and not homog else 0.0), status=status,
+                       res=np.array(hist))

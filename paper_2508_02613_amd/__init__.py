@@ -78,6 +78,7 @@ _SIGS = {
     "jfft_set_mixed_params": (C.c_int, [_vp, C.c_double, C.c_int]),
     "jfft_set_stop_rule": (C.c_int, [_vp, C.c_int]),
     "jfft_set_diag_method": (C.c_int, [_vp, C.c_int]),
+    "jfft_set_element": (C.c_int, [_vp, C.c_int]),
     "jfft_set_material_powerlaw": (C.c_int, [_vp, _vp, C.c_double, C.c_double, C.c_double,
                                              C.c_double, C.c_double, C.c_double]),
     "jfft_solve_newton": (C.c_int, [_vp, _dp, C.c_double, C.c_double, C.c_int, C.c_int, _vp, _dp,
@@ -176,11 +177,12 @@ class Cell:
     precision FP64 or MIXED; pc one of PC_*; stream a torch.cuda.Stream (None =
     current stream).  The workspace is a torch uint8 tensor bound to the cell.
     With batch > 1, material fields and results carry a leading cell index and
-    solve_batch replaces solve.
+    solve_batch replaces solve.  element (2D): "quad" (bilinear, 2 x 2 Gauss
+    points) or "tri" (two linear triangles per pixel, the paper's 2D element).
     """
 
     def __init__(self, shape, precision=FP64, pc=PC_GREEN_JACOBI, lengths=None, stream=None,
-                 device=None, batch=1):
+                 device=None, batch=1, element="quad"):
         torch = _torch()
         lib = load_library()
         self.torch = torch
@@ -198,6 +200,11 @@ class Cell:
                                          C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.batch = int(batch)
         self._h = h
+        if element not in ("quad", "tri"):
+            raise ValueError(f"unknown element {element!r}")
+        self.element = element
+        if element == "tri":
+            _check(lib.jfft_set_element(h, 1))
         self._lib = lib
         nb = C.c_size_t(0)
         _check(lib.jfft_workspace_bytes(h, C.byref(nb)))
@@ -230,6 +237,10 @@ class Cell:
         if shape is not None:
             assert tuple(t.shape) == tuple(shape), (t.shape, shape)
         return t
+
+    def _nq(self):
+        # quadrature points per element: 2^d Gauss points, or one per triangle
+        return 2 if self.element == "tri" else 2 ** self.dim
 
     def set_material(self, E, nu=None, lame=None):
         E = self._dev(E, self.shape if self.batch == 1 else (self.batch,) + self.shape)
@@ -265,7 +276,7 @@ class Cell:
         u = out if out is not None else torch.empty(vshape, dtype=torch.float64, device=self.device)
         sig = None
         if want_sigma:
-            sig = torch.empty((self.ds, 2 ** self.dim) + self.shape, dtype=torch.float64,
+            sig = torch.empty((self.ds, self._nq()) + self.shape, dtype=torch.float64,
                               device=self.device)
         u0t = self._dev(u0, vshape) if u0 is not None else None
         m = (C.c_double * self.ds)(*[float(v) for v in np.asarray(macro, dtype=float)])
@@ -286,7 +297,7 @@ class Cell:
         u = out if out is not None else torch.empty(vshape, dtype=torch.float64, device=self.device)
         sig = None
         if want_sigma:
-            sig = torch.empty((B, self.ds, 2 ** self.dim) + self.shape, dtype=torch.float64,
+            sig = torch.empty((B, self.ds, self._nq()) + self.shape, dtype=torch.float64,
                               device=self.device)
         u0t = self._dev(u0, vshape) if u0 is not None else None
         mac = np.ascontiguousarray(np.asarray(macros, dtype=np.float64).reshape(B, self.ds))

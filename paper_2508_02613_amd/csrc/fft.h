@@ -660,6 +660,11 @@ struct GArgs {
   int check_done;
   long long cs;           // bytes between the cells of a batch (cell = blockIdx.z)
   double *partB;          // per-block partials of r.z (Parseval, see k_green_axis)
+  // 2D linear triangles (tri != 0): K^_ref from its 3 x 3 stencil (see
+  // green2_tri); twx = exp(-2 pi i j / nx) for the x wavenumber
+  int tri;
+  const double2 *twx;
+  double tS[9][3];
 };
 
 // Green multiply at one frequency: zh = G^(k) sh with G^ = K^_ref(k)^-1 / N,
@@ -718,6 +723,44 @@ __device__ __forceinline__ void green2(const T (&A)[2], const T (&B)[2], const T
   const T k00 = l2m * A[0] * B[1] + mu * B[0] * A[1];
   const T k11 = mu * A[0] * B[1] + l2m * B[0] * A[1];
   const T k01 = lm * S[0] * S[1];
+  const T sc = invN / (k00 * k11 - k01 * k01);
+  const T g00 = k11 * sc, g11 = k00 * sc, g01 = -k01 * sc;
+  const T x0 = v[0].x, x1 = v[1].x, y0 = v[0].y, y1 = v[1].y;
+  v[0].x = g00 * x0 + g01 * x1;
+  v[0].y = g00 * y0 + g01 * y1;
+  v[1].x = g01 * x0 + g11 * x1;
+  v[1].y = g01 * y0 + g11 * y1;
+}
+
+// Green multiply for the 2D linear-triangle discretisation.  K_ref is the
+// 3 x 3 stencil (K u)(x) = sum_d S_d u(x + d), d in {-1, 0, 1}^2, so
+// K^(k) = sum_d S_d exp(i theta . d), theta = 2 pi (kx / nx, ky / ny).  The
+// split of every pixel into two triangles is symmetric under the point
+// reflection x -> -x, so S_-d = S_d and K^ = sum_d S_d cos(theta . d) is real
+// symmetric (it is not of the separable quadrilateral form: the split is not
+// symmetric under the reflection of one axis).  S[d] = (S_00, S_11, S_01) of
+// offset d = (dx, dy), index (dy + 1) * 3 + dx + 1.
+template <typename T, typename C>
+__device__ __forceinline__ void green2_tri(T cx, T sx, T cy, T sy, const double (&S)[9][3],
+                                           T invN, bool zero, C (&v)[2]) {
+  if (zero) {
+    for (int i = 0; i < 2; ++i) v[i].x = v[i].y = 0;
+    return;
+  }
+  T k00 = 0, k11 = 0, k01 = 0;
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      // cos(theta_x dx + theta_y dy)
+      const T cxd = dx ? cx : (T)1, sxd = (T)dx * sx;
+      const T cyd = dy ? cy : (T)1, syd = (T)dy * sy;
+      const T cd = cxd * cyd - sxd * syd;
+      const int o = (dy + 1) * 3 + dx + 1;
+      k00 += (T)S[o][0] * cd;
+      k11 += (T)S[o][1] * cd;
+      k01 += (T)S[o][2] * cd;
+    }
   const T sc = invN / (k00 * k11 - k01 * k01);
   const T g00 = k11 * sc, g11 = k00 * sc, g01 = -k01 * sc;
   const T x0 = v[0].x, x1 = v[1].x, y0 = v[0].y, y1 = v[1].y;
@@ -815,7 +858,13 @@ __global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
         const Real B[2] = {(Real)a.tx.b[kx], (Real)a.ty.b[t]};
         const Real S[2] = {(Real)a.tx.s[kx], (Real)a.ty.s[t]};
         C v[2] = {stash[0][j], stash[1][j]};
-        green2<Real>(A, B, S, (Real)a.lam, (Real)a.mu, (Real)a.invN, kx == 0 && t == 0, v);
+        if (a.tri) {
+          const double2 ex = a.twx[kx], ey = a.tw[t];
+          green2_tri<Real>((Real)ex.x, (Real)-ex.y, (Real)ey.x, (Real)-ey.y, a.tS, (Real)a.invN,
+                           kx == 0 && t == 0, v);
+        } else {
+          green2<Real>(A, B, S, (Real)a.lam, (Real)a.mu, (Real)a.invN, kx == 0 && t == 0, v);
+        }
         double e = 0.0;
         for (int c = 0; c < 2; ++c) {
           e += (double)stash[c][j].x * (double)v[c].x + (double)stash[c][j].y * (double)v[c].y;

@@ -160,6 +160,8 @@ struct jfft_cell_s {
   int max_outer = 30;
   bool stop_abs = false;  // stopping rule ||r||^2 <= tol instead of ||r|| <= tol ||f||
   int diag_method = JFFT_DIAG_CLOSED_FORM;  // how J^1/2 is formed (Algorithm 2 or its closed form)
+  int elem = JFFT_ELEM_QUAD;  // 2D element: bilinear quadrilateral or two linear triangles
+  double tS[9][3] = {};       // triangles: stencil of K_ref (see green2_tri)
 
   // power-law material (nonlinear example): E holds the phase, lam and mu the
   // Green reference (the inclusion); uk is the Newton iterate, allocated on
@@ -579,7 +581,10 @@ jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a, int cel
   } else if (c->dim == 3) {
     LAUNCH(c, kid, (k_stiffness3d<Real, MODE, false><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
   } else {
-    LAUNCH(c, kid, k_stiffness2d<Real, MODE><<<gr, STENCIL_THREADS, 0, c->stream>>>(a));
+    if (c->elem == JFFT_ELEM_TRI)
+      LAUNCH(c, kid, (k_stiffness2d<Real, MODE, true><<<gr, STENCIL_THREADS, 0, c->stream>>>(a)));
+    else
+      LAUNCH(c, kid, (k_stiffness2d<Real, MODE, false><<<gr, STENCIL_THREADS, 0, c->stream>>>(a)));
   }
   return JFFT_OK;
 }
@@ -727,6 +732,9 @@ jfft_status launch_green(jfft_cell_s *c, typename CxT<Real>::T *spec, bool check
   a.nz = c->g.nz;
   a.check_done = check_done ? 1 : 0;
   a.cs = c->cs;
+  a.tri = c->elem == JFFT_ELEM_TRI ? 1 : 0;
+  a.twx = c->tw[0];
+  std::memcpy(a.tS, c->tS, sizeof(a.tS));
   constexpr int TW = TileW<Real>::value;
   const int L = c->dim == 3 ? c->g.nz : c->g.ny;
   if (c->dim == 3) {
@@ -928,7 +936,7 @@ jfft_status assemble_rhs(jfft_cell_s *c, const double *macros_h, double *f, doub
   const int ds = c->dim * (c->dim + 1) / 2;
   HIP_TRY(hipMemcpy2DAsync(c->macro, (size_t)c->cs, macros_h, sizeof(double) * ds, sizeof(double) * ds,
                            cells, hipMemcpyHostToDevice, c->stream));
-  LAUNCH(c, KID_RHS, k_unit_force<<<cells, 1, 0, c->stream>>>(c->F, c->macro, c->dim, c->lam * c->g.w, c->mu * c->g.w, c->g.ihx, c->g.ihy, c->g.ihz, c->cs));
+  LAUNCH(c, KID_RHS, k_unit_force<<<cells, 1, 0, c->stream>>>(c->F, c->macro, c->dim, c->lam * c->g.w, c->mu * c->g.w, c->g.ihx, c->g.ihy, c->g.ihz, c->cs, c->elem == JFFT_ELEM_TRI ? 1 : 0));
   const long long N = c->g.N;
   LAUNCH(c, KID_RHS, k_rhs<double><<<dim3((unsigned)((N + 255) / 256), cells), 256, 0, c->stream>>>(c->E, c->F, f, fabs_out, c->dim, c->g.nx, c->g.ny, c->g.nz, N, c->cs));
   return JFFT_OK;
@@ -970,6 +978,43 @@ jfft_status run_diag_closed(jfft_cell_s *c, double *diag_out, int cells) {
   return JFFT_OK;
 }
 
+// Stencil of K_ref (unit modulus, Lame constants lam, mu) for the 2D linear
+// triangles: the pixel matrix Ke (both triangles of elem_tri2, one point of
+// weight A = hx hy / 2 each) folded by corner offset, S_d = sum over corner
+// pairs (a, b) with x_b - x_a = d of the 2 x 2 block Ke[a][b]; stored as
+// (S_00, S_11, S_01) at index (dy + 1) * 3 + dx + 1.
+void tri_stencil(jfft_cell_s *c, double lam, double mu) {
+  const double ix = c->g.ihx, iy = c->g.ihy, A = 0.5 / (ix * iy);
+  // corner gradients per triangle: T0 = (0, 1, 2), T1 = (3, 2, 1)
+  const int corners[2][3] = {{0, 1, 2}, {3, 2, 1}};
+  const double grads[2][3][2] = {{{-ix, -iy}, {ix, 0.0}, {0.0, iy}},
+                                 {{ix, iy}, {-ix, 0.0}, {0.0, -iy}}};
+  double Ke[4][4][2][2] = {};  // [a][b][i][j]
+  for (int t = 0; t < 2; ++t)
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) {
+        const double ax = grads[t][p][0], ay = grads[t][p][1];
+        const double bx = grads[t][q][0], by = grads[t][q][1];
+        // B_a^T C B_b for plane strain: the 2 x 2 block of corner pair (a, b)
+        double k[2][2];
+        k[0][0] = (lam + 2 * mu) * ax * bx + mu * ay * by;
+        k[1][1] = (lam + 2 * mu) * ay * by + mu * ax * bx;
+        k[0][1] = lam * ax * by + mu * ay * bx;
+        k[1][0] = lam * ay * bx + mu * ax * by;
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) Ke[corners[t][p]][corners[t][q]][i][j] += A * k[i][j];
+      }
+  std::memset(c->tS, 0, sizeof(c->tS));
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      const int dx = (b & 1) - (a & 1), dy = (b >> 1) - (a >> 1);
+      const int o = (dy + 1) * 3 + dx + 1;
+      c->tS[o][0] += Ke[a][b][0][0];
+      c->tS[o][1] += Ke[a][b][1][1];
+      c->tS[o][2] += Ke[a][b][0][1];
+    }
+}
+
 jfft_status set_material_impl(jfft_cell_s *c, const double *E_dev, double lam, double mu) {
   if (!E_dev) return fail(JFFT_E_INVALID, "E_dev is NULL");
   if (!(mu > 0.0) || !(lam + 2.0 * mu / c->dim > 0.0) || !std::isfinite(lam) || !std::isfinite(mu))
@@ -985,6 +1030,7 @@ jfft_status set_material_impl(jfft_cell_s *c, const double *E_dev, double lam, d
   c->has_material = false;
   c->lam = lam;
   c->mu = mu;
+  if (c->elem == JFFT_ELEM_TRI) tri_stencil(c, lam, mu);
   const long long N = c->g.N;
   const long long es = (long long)sizeof(double) * N;  // caller's layout [B][N]
   const int nb = vec_blocks(N);
@@ -998,7 +1044,8 @@ jfft_status set_material_impl(jfft_cell_s *c, const double *E_dev, double lam, d
   const long long nd = (long long)c->dim * N;
   const int nbd = vec_blocks(nd);
   if (useJ(c)) {
-    if (c->diag_method == JFFT_DIAG_PROBING)
+    // the closed form is that of the quadrilateral; triangles take Algorithm 2
+    if (c->diag_method == JFFT_DIAG_PROBING || c->elem == JFFT_ELEM_TRI)
       TRY(run_alg2(c, c->diag, c->B));
     else
       TRY(run_diag_closed(c, c->diag, c->B));
@@ -1036,8 +1083,9 @@ jfft_status post_process(jfft_cell_s *c, double *u_out, double *sigma_dev, doubl
   TRY(reduce_to(c, c->partB, nbN, d, 8, Bc));
   LAUNCH(c, KID_VEC, k_sub_mean<double><<<dim3(nbN, d, Bc), 256, 0, c->stream>>>(c->u, N, c->small + 8, c->cs));
   const unsigned nbs = (unsigned)((N + 255) / 256);
-  const long long sig_cs = (long long)sizeof(double) * ds * (1 << d) * N;
-  LAUNCH(c, KID_STRESS, k_stress<double><<<dim3(nbs, Bc), 256, 0, c->stream>>>(c->u, c->E, c->macro, c->lam, c->mu, c->g.w, c->g.ihx, c->g.ihy, c->g.ihz, d, c->g.nx, c->g.ny, c->g.nz, N, sigma_dev, c->partB, c->cs, sig_cs));
+  const int tri = c->elem == JFFT_ELEM_TRI ? 1 : 0;
+  const long long sig_cs = (long long)sizeof(double) * ds * (tri ? 2 : (1 << d)) * N;
+  LAUNCH(c, KID_STRESS, k_stress<double><<<dim3(nbs, Bc), 256, 0, c->stream>>>(c->u, c->E, c->macro, c->lam, c->mu, c->g.w, c->g.ihx, c->g.ihy, c->g.ihz, d, c->g.nx, c->g.ny, c->g.nz, N, sigma_dev, c->partB, c->cs, sig_cs, tri));
   TRY(reduce_to(c, c->partB, nbs, ds, 16, Bc));
   // u to the caller's [B][d][N] array
   LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->u, c->cs, u_out, (long long)sizeof(double) * nd, nd));
@@ -1592,6 +1640,19 @@ jfft_status jfft_set_diag_method(jfft_cell_t c, int method) {
     return fail(JFFT_E_INVALID, "unknown diagonal method");
   if (c->diag_method != method) c->has_material = false;  // J^1/2 must be formed again
   c->diag_method = method;
+  return JFFT_OK;
+}
+
+jfft_status jfft_set_element(jfft_cell_t c, int element) {
+  if (!c || (element != JFFT_ELEM_QUAD && element != JFFT_ELEM_TRI))
+    return fail(JFFT_E_INVALID, "unknown element");
+  if (element == JFFT_ELEM_TRI && c->dim != 2)
+    return fail(JFFT_E_INVALID, "linear triangles are a 2D element");
+  if (c->elem != element) {
+    c->has_material = false;  // K, f, diag(K) and G^ change
+    c->drop_graphs();
+  }
+  c->elem = element;
   return JFFT_OK;
 }
 

@@ -1054,7 +1054,45 @@ __device__ __forceinline__ void elem_quad(const Real (&u)[2][4], Real Elam, Real
   }
 }
 
-template <typename Real, int MODE>
+// Two linear triangles per pixel (the alternative 2D element): the pixel is
+// split along its anti-diagonal into T0 = corners (0, 1, 2) and T1 =
+// corners (3, 2, 1).  The strain is constant on each, so one point of weight
+// A = hx hy / 2 integrates exactly; Elam, Emu carry E and A.
+template <typename Real>
+__device__ __forceinline__ void elem_tri2(const Real (&u)[2][4], Real Elam, Real Emu, Real ihx,
+                                          Real ihy, Real (&y)[2][4]) {
+  const Real m2 = Emu + Emu;
+  {  // T0: grad N_0 = (-1/hx, -1/hy), grad N_1 = (1/hx, 0), grad N_2 = (0, 1/hy)
+    const Real e11 = (u[0][1] - u[0][0]) * ihx, e22 = (u[1][2] - u[1][0]) * ihy;
+    const Real g12 = (u[0][2] - u[0][0]) * ihy + (u[1][1] - u[1][0]) * ihx;
+    const Real lt = Elam * (e11 + e22);
+    const Real s11 = lt + m2 * e11, s22 = lt + m2 * e22, s12 = Emu * g12;
+    const Real ax = s11 * ihx, ay = s12 * ihy, bx = s12 * ihx, by = s22 * ihy;
+    y[0][0] = -ax - ay;
+    y[1][0] = -bx - by;
+    y[0][1] = ax;
+    y[1][1] = bx;
+    y[0][2] = ay;
+    y[1][2] = by;
+  }
+  {  // T1: grad N_3 = (1/hx, 1/hy), grad N_2 = (-1/hx, 0), grad N_1 = (0, -1/hy)
+    const Real e11 = (u[0][3] - u[0][2]) * ihx, e22 = (u[1][3] - u[1][1]) * ihy;
+    const Real g12 = (u[0][3] - u[0][1]) * ihy + (u[1][3] - u[1][2]) * ihx;
+    const Real lt = Elam * (e11 + e22);
+    const Real s11 = lt + m2 * e11, s22 = lt + m2 * e22, s12 = Emu * g12;
+    const Real ax = s11 * ihx, ay = s12 * ihy, bx = s12 * ihx, by = s22 * ihy;
+    y[0][3] = ax + ay;
+    y[1][3] = bx + by;
+    y[0][2] -= ax;
+    y[1][2] -= bx;
+    y[0][1] -= ay;
+    y[1][1] -= by;
+  }
+}
+
+// TRI: the pixel is two linear triangles (elem_tri2) instead of a bilinear
+// quadrilateral.
+template <typename Real, int MODE, bool TRI = false>
 __global__ void __launch_bounds__(STENCIL_THREADS)
     k_stiffness2d(StencilArgs<Real> a) {
   __shared__ Real P[2][NNODE];
@@ -1119,7 +1157,10 @@ __global__ void __launch_bounds__(STENCIL_THREADS)
     }
     Real Ee = (Real)0;
     if (gex < nx && gey < ny) Ee = a.E[(long long)wrapi(gex, nx) + (long long)nx * wrapi(gey, ny)];
-    elem_quad(uv, Ee * a.lam, Ee * a.mu, a.ihx, a.ihy, yv);
+    if constexpr (TRI)  // a.lam, a.mu carry the Gauss weight hx hy / 4; A is twice that
+      elem_tri2(uv, (Real)2 * Ee * a.lam, (Real)2 * Ee * a.mu, a.ihx, a.ihy, yv);
+    else
+      elem_quad(uv, Ee * a.lam, Ee * a.mu, a.ihx, a.ihy, yv);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       Y[c * 2 + 0][tid] = yv[0][c];
@@ -1193,8 +1234,11 @@ __global__ void k_rhs(const Real *E, const double *F /* [d][2^d] */, Real *f, Re
 // Element force of a unit modulus under a constant strain (Mandel macro):
 // F[i][c] = w sum_q sum_j sigma0_ij dphi_c/dx_j, sigma0 = C^ macro.  One
 // thread; evaluated with the same transposed factorisation as the stiffness.
+// tri (2D): the two linear triangles of elem_tri2, weight A = 2 w each; the
+// summed triangle gradients of corners 0..3 are (-ihx, -ihy), (ihx, -ihy),
+// (-ihx, ihy), (ihx, ihy).
 __global__ void k_unit_force(double *F, const double *macro, int dim, double lam, double mu,
-                             double ihx, double ihy, double ihz, long long cs) {
+                             double ihx, double ihy, double ihz, long long cs, int tri) {
   if (threadIdx.x != 0) return;
   F = cshift(F, blockIdx.x, cs);  // one block per cell
   macro = cshift(macro, blockIdx.x, cs);
@@ -1220,6 +1264,15 @@ __global__ void k_unit_force(double *F, const double *macro, int dim, double lam
         }
       force_hex<double>(SX, SY, SZ, ihx, ihy, ihz, y);
       for (int c = 0; c < 8; ++c) F[i * 8 + c] = y[c];
+    }
+  } else if (tri) {
+    const double e11 = macro[0], e22 = macro[1], e12 = macro[2] * r2;
+    const double lt = lam * (e11 + e22);
+    const double s11 = lt + 2 * mu * e11, s22 = lt + 2 * mu * e22, s12 = 2 * mu * e12;
+    for (int c = 0; c < 4; ++c) {
+      const double gx = 2.0 * ((c & 1) ? ihx : -ihx), gy = 2.0 * ((c >> 1) ? ihy : -ihy);
+      F[0 * 4 + c] = s11 * gx + s12 * gy;  // 2.0: A = 2 w (lam, mu carry w)
+      F[1 * 4 + c] = s12 * gx + s22 * gy;
     }
   } else {
     const double e11 = macro[0], e22 = macro[1], e12 = macro[2] * r2;
@@ -1257,7 +1310,7 @@ template <typename Real>
 __global__ void k_stress(const Real *u, const Real *E, const double *macro, double lam, double mu,
                          double w, double ihx, double ihy, double ihz, int dim, int nx, int ny,
                          int nz, long long N, double *sig, double *partial /* [ds][nblocks] */,
-                         long long cs, long long sig_cs) {
+                         long long cs, long long sig_cs, int tri) {
   __shared__ double red[8];
   const int cell = blockIdx.y;
   u = cshift(u, cell, cs);
@@ -1311,6 +1364,27 @@ __global__ void k_stress(const Real *u, const Real *E, const double *macro, doub
             (long long)wrapi(ix + (c & 1), nx) + (long long)nx * wrapi(iy + (c >> 1), ny);
         for (int i = 0; i < 2; ++i) uv[i][c] = u ? (double)u[i * N + nd] : 0.0;
       }
+      if (tri) {
+        // the two triangles of elem_tri2, one point each of weight 2 w:
+        // sig[r][t][e], t = 0, 1
+        const double ex[2] = {(uv[0][1] - uv[0][0]) * ihx, (uv[0][3] - uv[0][2]) * ihx};
+        const double ey[2] = {(uv[1][2] - uv[1][0]) * ihy, (uv[1][3] - uv[1][1]) * ihy};
+        const double gg[2] = {(uv[0][2] - uv[0][0]) * ihy + (uv[1][1] - uv[1][0]) * ihx,
+                              (uv[0][3] - uv[0][1]) * ihy + (uv[1][3] - uv[1][2]) * ihx};
+        for (int t = 0; t < 2; ++t) {
+          const double e11 = macro[0] + ex[t], e22 = macro[1] + ey[t];
+          const double g12 = macro[2] * r2 + gg[t];
+          const double lt = lam * (e11 + e22);
+          double s[3];
+          s[0] = Ee * (lt + 2 * mu * e11);
+          s[1] = Ee * (lt + 2 * mu * e22);
+          s[2] = Ee * mu * g12 * r2;
+          for (int r = 0; r < 3; ++r) {
+            if (sig) sig[((long long)r * 2 + t) * N + e] = s[r];
+            loc[r] += 2.0 * w * s[r];
+          }
+        }
+      } else {
       double dX[2][2], dY[2][2];
       for (int i = 0; i < 2; ++i) {
         interp2(uv[i][1] - uv[i][0], uv[i][3] - uv[i][2], dX[i][0], dX[i][1]);
@@ -1333,6 +1407,7 @@ __global__ void k_stress(const Real *u, const Real *E, const double *macro, doub
           if (sig) sig[((long long)r * 4 + q) * N + e] = s[r];
           loc[r] += w * s[r];
         }
+      }
       }
     }
   }

@@ -1,0 +1,200 @@
+"""GPU parity of the 2D linear-triangle discretisation (two triangles per
+pixel, the paper's own 2D element) against the FP64 oracle
+oracle/triangles.py (pinned in test_oracle_triangles.py): the operators K p,
+f, Algorithm 2's diagonal and M^-1 element by element on grids of several
+tiles with ragged tails and non-square pixels; solves with the four
+preconditioners (iterations, u, sigma_bar, the stress field); the mixed
+path's final residual; the paper's trend on its motivating example under its
+absolute stopping rule; element switching and argument checks.
+"""
+import numpy as np
+import pytest
+
+import jfft_inputs as ji
+import oracle
+from oracle import triangles as tri
+
+pytestmark = pytest.mark.gpu
+
+LAM, MU = oracle.lame_from_nu(0.3)
+
+
+def _pkg():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    import paper_2508_02613_amd as pkg
+
+    pkg.load_library()
+    return pkg
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _slack(res, target, absolute):
+    """+-1, plus the iterations over which the oracle's residual lies within
+    a factor 10 of the threshold (a flat curve lets rounding move the stop)."""
+    v = res ** 2 if absolute else res
+    t = target
+    return 1 + int(np.count_nonzero((v >= t / 10) & (v <= 10 * t)))
+
+
+CASES = [((32, 32), None), ((24, 20), (1.0, 0.6)), ((40, 36), (0.7, 1.3))]
+
+
+@pytest.mark.parametrize("shape,lengths", CASES)
+def test_operators_match_oracle(shape, lengths):
+    pkg = _pkg()
+    say(f"triangle operators {shape} lengths={lengths}")
+    E = ji.uniform_random_field(shape, 1.0, 1e3, seed=3)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((2,) + shape)
+    macro = np.array([0.3, -0.2, 0.5])
+    out = {}
+    for pc in (pkg.PC_GREEN, pkg.PC_GREEN_JACOBI):
+        cell = pkg.Cell(shape, pc=pc, lengths=lengths, element="tri")
+        cell.set_material(E, nu=0.3)
+        out[pc] = cell.apply_precond(x).cpu().numpy()
+        if pc == pkg.PC_GREEN:
+            Kx = cell.apply_stiffness(x).cpu().numpy()
+            f = cell.assemble_rhs(macro).cpu().numpy()
+            d = cell.jacobi_diag().cpu().numpy()
+        cell.close()
+    Kx_ref = tri.stiffness(E, x, LAM, MU, lengths)
+    f_ref = tri.rhs(E, macro, LAM, MU, lengths)
+    d_ref = tri.jacobi_diag(E, LAM, MU, lengths)
+    assert np.abs(Kx - Kx_ref).max() <= 1e-12 * np.abs(Kx_ref).max()
+    assert np.abs(f - f_ref).max() <= 1e-12 * np.abs(f_ref).max()
+    assert np.abs(d - d_ref).max() <= 1e-12 * np.abs(d_ref).max()
+    G = tri.green(shape, LAM, MU, lengths)
+    zG, _ = oracle.precond(oracle.PC_GREEN, x, G=G, lengths=lengths)
+    zGJ, _ = oracle.precond(oracle.PC_GREEN_JACOBI, x, diag=d_ref, G=G, lengths=lengths)
+    assert np.abs(out[pkg.PC_GREEN] - zG).max() <= 1e-11 * np.abs(zG).max()
+    assert np.abs(out[pkg.PC_GREEN_JACOBI] - zGJ).max() <= 1e-11 * np.abs(zGJ).max()
+
+
+@pytest.mark.parametrize("pc", [1, 3, 2, 0])
+@pytest.mark.parametrize("case", ["sine32", "rand24x20"])
+def test_solve_matches_oracle(case, pc):
+    pkg = _pkg()
+    if case == "sine32":
+        E, lengths, tol = ji.sine_contrast_field(32), None, 1e-8
+    else:
+        E, lengths, tol = ji.uniform_random_field((24, 20), 1.0, 1e2, seed=7), (1.0, 0.6), 1e-10
+    macro = np.array([1.0, 0.0, 0.0]) if case == "sine32" else np.array([0.2, -0.1, 0.4])
+    say(f"triangle solve {case} pc={pc}")
+    ref = tri.solve(E, macro, LAM, MU, pc=pc, tol=tol, maxit=20000, lengths=lengths)
+    cell = pkg.Cell(E.shape, pc=pc, lengths=lengths, element="tri")
+    cell.set_material(E, nu=0.3)
+    u, sbar, rep, sig = cell.solve(macro, tol=tol, maxit=20000, want_sigma=True)
+    ug, sg = u.cpu().numpy(), sig.cpu().numpy()
+    cell.close()
+    fn = np.linalg.norm(tri.rhs(E, macro, LAM, MU, lengths))
+    slack = _slack(ref.res, tol * fn, False)
+    say(f"  iters gpu={rep.iters} oracle={ref.iters} (slack {slack})")
+    assert rep.status == "ok" and ref.status == "ok"
+    assert abs(rep.iters - ref.iters) <= slack
+    assert rep.rel_res_true <= 2 * tol
+    if pc in (1, 3):  # the FFT-based preconditioners reach the solution closely
+        # same iterates up to rounding: their difference is a small fraction
+        # of the error left at the stopping tolerance
+        rel = 1e-6 if case == "sine32" else 1e-8
+        assert np.abs(ug - ref.u).max() <= rel * np.abs(ref.u).max()
+        sig_ref, sbar_ref = tri.stress(E, macro, ug, LAM, MU, lengths)
+        assert np.abs(sg - sig_ref).max() <= 1e-12 * np.abs(sig_ref).max()
+        assert np.abs(sbar - sbar_ref).max() <= 1e-12 * np.abs(sbar_ref).max()
+        assert np.abs(sbar - ref.sigma_bar).max() <= 1e-6 * np.abs(ref.sigma_bar).max()
+
+
+def test_tight_solve_u_parity():
+    """At tol 1e-12 the GPU and oracle solutions agree to 1e-10."""
+    pkg = _pkg()
+    E = ji.sine_contrast_field(32)
+    macro = np.array([1.0, 0.0, 0.0])
+    say("triangle tight solve 32^2 GJ")
+    ref = tri.solve(E, macro, LAM, MU, pc=3, tol=1e-12, maxit=20000)
+    cell = pkg.Cell(E.shape, pc=pkg.PC_GREEN_JACOBI, element="tri")
+    cell.set_material(E, nu=0.3)
+    u, sbar, rep, _ = cell.solve(macro, tol=1e-12, maxit=20000)
+    ug = u.cpu().numpy()
+    cell.close()
+    assert abs(rep.iters - ref.iters) <= _slack(ref.res, 1e-12 * np.linalg.norm(
+        tri.rhs(E, macro, LAM, MU)), False)
+    assert np.abs(ug - ref.u).max() <= 1e-10 * np.abs(ref.u).max()
+    assert np.abs(sbar - ref.sigma_bar).max() <= 1e-11 * np.abs(ref.sigma_bar).max()
+
+
+def test_mixed_precision_reaches_fp64_solution():
+    pkg = _pkg()
+    E = ji.grf_field((128, 128), 1e4, seed=2, ell=0.1)
+    macro = np.array([0.0, 0.0, 1.0])
+    say("triangle mixed vs FP64 128^2")
+    res = {}
+    for prec in (pkg.FP64, pkg.MIXED):
+        cell = pkg.Cell(E.shape, precision=prec, element="tri")
+        cell.set_material(E, nu=0.3)
+        u, sbar, rep, _ = cell.solve(macro, tol=1e-8, maxit=20000)
+        res[prec] = (u.cpu().numpy(), sbar, rep)
+        cell.close()
+    (u64, s64, r64), (u32, s32, r32) = res[pkg.FP64], res[pkg.MIXED]
+    assert r64.status == "ok" and r32.status == "ok"
+    assert r32.rel_res_true <= 1e-8 and r64.rel_res_true <= 1e-8
+    assert np.abs(u32 - u64).max() <= 1e-6 * np.abs(u64).max()
+    assert np.abs(s32 - s64).max() <= 1e-7 * np.abs(s64).max()
+
+
+def test_motivating_example_trend_with_triangles():
+    """The paper's motivating example on its own element: a soft disc in a
+    stiff matrix, smoothed by repeated filtering, absolute rule ||r||^2 <=
+    1e-10.  Iteration counts equal the oracle's (within the flatness slack);
+    Green wins on the sharp disc, Green-Jacobi on the smoothed one."""
+    pkg = _pkg()
+    tol = 1e-10
+    macro = np.array([1.0, 0.0, 0.0])
+    its = {}
+    for filters in (0, 8):
+        E = ji.filtered_inclusion_field(64, filters)
+        fn2 = float((tri.rhs(E, macro, LAM, MU) ** 2).sum())
+        for pc in (pkg.PC_GREEN, pkg.PC_GREEN_JACOBI):
+            ref = tri.solve(E, macro, LAM, MU, pc=pc, tol=tol, maxit=20000, stop_absolute=True)
+            cell = pkg.Cell(E.shape, pc=pc, element="tri")
+            cell.set_stop_rule(absolute=True)
+            cell.set_material(E, nu=0.3)
+            _, _, rep, _ = cell.solve(macro, tol=tol, maxit=20000)
+            cell.close()
+            slack = _slack(ref.res, tol, True)
+            say(f"  filters={filters} pc={pc}: gpu={rep.iters} oracle={ref.iters} (slack {slack})")
+            assert rep.status == "ok" and ref.status == "ok"
+            assert abs(rep.iters - ref.iters) <= slack
+            assert (rep.rel_res ** 2) * fn2 <= tol * 1.0001
+            its[(filters, pc)] = rep.iters
+    assert its[(0, pkg.PC_GREEN)] < its[(0, pkg.PC_GREEN_JACOBI)]
+    assert its[(8, pkg.PC_GREEN_JACOBI)] < its[(8, pkg.PC_GREEN)]
+
+
+def test_element_switch_and_errors():
+    pkg = _pkg()
+    say("triangle element switch and errors")
+    with pytest.raises(pkg.JfftError):
+        pkg.Cell((8, 8, 8), element="tri")
+    with pytest.raises(ValueError):
+        pkg.Cell((8, 8), element="hex")
+    E = ji.uniform_random_field((16, 16), 1.0, 10.0, seed=1)
+    cell = pkg.Cell((16, 16))
+    cell.set_material(E, nu=0.3)
+    _, s_quad, _, _ = cell.solve(np.array([1.0, 0, 0]), tol=1e-10)
+    assert cell._lib.jfft_set_element(cell._h, 7) != 0
+    assert cell._lib.jfft_set_element(cell._h, 1) == 0
+    cell.element = "tri"
+    with pytest.raises(pkg.JfftError) as e:  # the element change cleared the material
+        cell.solve(np.array([1.0, 0, 0]), tol=1e-10)
+    assert e.value.name == "no_material"
+    cell.set_material(E, nu=0.3)
+    _, s_tri, rep, _ = cell.solve(np.array([1.0, 0, 0]), tol=1e-10)
+    ref = tri.solve(E, np.array([1.0, 0, 0]), LAM, MU, tol=1e-10)
+    cell.close()
+    assert np.abs(s_tri - ref.sigma_bar).max() <= 1e-8 * np.abs(ref.sigma_bar).max()
+    assert np.abs(s_tri - s_quad).max() > 1e-6 * np.abs(s_quad).max()  # a different element
