@@ -19,6 +19,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256]
                        [--contrast 1e4] [--no-cpu] [--no-fp64] [--no-serve]
        python bench.py --workload simp2d [--cells 512]   (batched 2D SIMP cells)
        python bench.py --workload powerlaw [--pl-n 200]  (nonlinear Newton example)
+       python bench.py --workload tri [--tri-cells 32]   (2D linear triangles)
 """
 from __future__ import annotations
 
@@ -63,8 +64,9 @@ def parse():
                     help="PCG iterations per captured HIP graph in the timed steps (0: direct launches)")
     ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--pl-n", type=int, default=200, help="powerlaw: nodes per axis")
+    ap.add_argument("--tri-cells", type=int, default=32, help="tri: 512^2 cells in the group")
     ap.add_argument("--workload", default="grf256",
-                    choices=["grf256", "simp2d", "contrast", "powerlaw"],
+                    choices=["grf256", "simp2d", "contrast", "powerlaw", "tri"],
                     help="grf256: the headline 256^3 cell (+ served stream); simp2d: 512 "
                          "batched 2D SIMP cells of uneven sizes")
     ap.add_argument("--cells", type=int, default=512, help="simp2d: number of cells")
@@ -511,6 +513,151 @@ def run_powerlaw(args):
     return line
 
 
+def run_tri(args):
+    """2D linear triangles (two per pixel, the paper's own 2D element).
+    Throughput: a group of B plane-strain cells of 512^2 nodes (the largest
+    FFT length of the library) with smooth GRF moduli (ell 0.1, contrast
+    1e4, seeds 0..B-1), nu 0.3, macro e11, Green-Jacobi PCG to relative
+    residual 1e-8, mixed precision as the headline (FP64 beside it); one step
+    = set the materials and solve the group.  Trend: the motivating example
+    of Sec. 1 at 256^2 (soft disc 1e-4, radius 0.25, i filter passes) with
+    the absolute rule ||r||^2 <= 1e-10, Green vs Green-Jacobi iterations."""
+    import torch
+
+    import jfft_inputs as ji
+    import paper_2508_02613_amd as pkg
+
+    n, B = 512, args.tri_cells
+    shape = (n, n)
+    N = n * n
+    Es = np.stack([ji.grf_field(shape, 1e4, seed=s, ell=0.1) for s in range(B)])
+    macros = np.tile(np.array([1.0, 0.0, 0.0]), (B, 1))
+    Ed = torch.from_numpy(Es).to("cuda")
+    stream = torch.cuda.Stream()
+    runs = {}
+    for name, prec in (("mixed", pkg.MIXED), ("fp64", pkg.FP64)):
+        grp = pkg.Cell(shape, precision=prec, pc=pkg.PC_GREEN_JACOBI, stream=stream, batch=B,
+                       element="tri")
+        if args.graph:
+            grp.set_graph_iterations(args.graph)
+        u = torch.empty((B, 2) + shape, dtype=torch.float64, device="cuda")
+
+        def step():
+            grp.set_material(Ed, nu=0.3)
+            return grp.solve_batch(macros, tol=1e-8, maxit=20000, out=u)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its = 0
+        for _ in range(args.steps):
+            _, sbar, reps, _ = step()
+            its += sum(r.iters for r in reps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        grp.reset_timing()
+        grp.enable_timing(True)
+        _, _, reps_ev, _ = step()
+        torch.cuda.synchronize()
+        stats = grp.kernel_stats()
+        grp.enable_timing(False)
+        grp.close()
+        runs[name] = {"wall_s": wall, "iters": its, "reps": reps, "stats": stats, "sbar": sbar,
+                      "ev_iters": sum(r.iters for r in reps_ev)}
+    R = runs["mixed"]
+    dofs = 2 * N * B
+    value = 2 * N * R["iters"] / R["wall_s"]
+    # stiffness roofline: algorithmic bytes of one cell-iteration times the
+    # cell-iterations of the event-timed step, over the kernel's event time
+    launches, tot_ms = R["stats"]["stiffness_cg"]
+    cell_bytes = algorithmic_bytes("stiffness_cg", 2, N, n, 4)
+    achieved = cell_bytes * R["ev_iters"] / (tot_ms * 1e-3) / 1e9
+    # the motivating example's trend
+    trend = []
+    for filters in (0, 1, 2, 4, 8, 16, 32):
+        E = ji.filtered_inclusion_field(256, filters)
+        row = {"filters": filters}
+        for pname, pc in (("green", pkg.PC_GREEN), ("green_jacobi", pkg.PC_GREEN_JACOBI)):
+            cell = pkg.Cell((256, 256), pc=pc, element="tri", stream=stream)
+            cell.set_stop_rule(absolute=True)
+            cell.set_material(E, nu=0.3)
+            _, _, rep, _ = cell.solve(np.array([1.0, 0.0, 0.0]), tol=1e-10, maxit=20000)
+            cell.close()
+            row[pname] = rep.iters
+            row[pname + "_loop_ms"] = rep.loop_ms
+        trend.append(row)
+    F = runs["fp64"]
+    line = {
+        "metric": "DOF·iterations/s (2D linear triangles, J-FFT PCG, group of 512² cells)",
+        "value": value, "unit": "DOF·it/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * R["wall_s"] / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": (f"{B} 2D plane-strain cells of 512^2 nodes, two linear "
+                                "triangles per pixel, GRF E (ell 0.1, contrast 1e4, seeds "
+                                f"0..{B - 1}), nu 0.3, macro e11, Green-Jacobi PCG to relative "
+                                "residual 1e-8, mixed precision, one group on one stream"),
+                   "cells": B, "n": n, "dofs": dofs, "graph_iterations": args.graph},
+        "iters_per_cell": R["iters"] / (args.steps * B),
+        "max_rel_res_true": max(r.rel_res_true for r in R["reps"]),
+        "fp64": {"value": 2 * N * F["iters"] / F["wall_s"],
+                 "ms_per_step": 1e3 * F["wall_s"] / args.steps,
+                 "iters_per_cell": F["iters"] / (args.steps * B),
+                 "sigma_bar_rel_diff_vs_mixed": float(np.abs(F["sbar"] - R["sbar"]).max()
+                                                      / np.abs(F["sbar"]).max())},
+        "roofline": {"bound": "hbm", "kernel": "stiffness_cg (2D triangles, FP32)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": load_traffic(f"tri_mixed_{n}x{B}", "stiffness_cg"),
+                     "avg_ms": tot_ms / launches, "launches": launches,
+                     "cell_iterations": R["ev_iters"],
+                     "algorithmic_bytes_per_cell_iteration": cell_bytes,
+                     # a launch with every cell active (what `traffic` measures)
+                     "algorithmic_bytes_per_launch": cell_bytes * B,
+                     "measured": "HIP events on the group's stream around every launch, one "
+                                 "further step with direct launches"},
+        "kernels_ms_per_step": {k: v[1] for k, v in sorted(R["stats"].items())},
+        "trend_motivating_example_256": trend,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline_tri()
+    return line
+
+
+def cpu_baseline_tri():
+    """The triangle oracle timed on one PCG iteration's operators (element
+    loop K p, Green-Jacobi preconditioner with the naive separable DFT, dots
+    and updates) on one 512^2 cell of the group."""
+    import jfft_inputs as ji
+    import oracle
+    from oracle import triangles as tri
+
+    n = 512
+    E = ji.grf_field((n, n), 1e4, seed=0, ell=0.1)
+    lam, mu = oracle.lame_from_nu(0.3)
+    rng = np.random.default_rng(0)
+    p = rng.standard_normal((2, n, n))
+    G = np.zeros((2, 2, n, n), dtype=complex)
+    G[0, 0] = 1.0
+    diag = np.ones((2, n, n))
+    t0 = time.perf_counter()
+    q = tri.stiffness(E, p, lam, mu)
+    t1 = time.perf_counter()
+    z, _ = oracle.precond(oracle.PC_GREEN_JACOBI, q, diag=diag, G=G)
+    t2 = time.perf_counter()
+    a = float((p * q).sum())
+    p += a * z
+    t3 = time.perf_counter()
+    per_iter = t3 - t0
+    return {"value": 2 * n * n / per_iter, "unit": "DOF·it/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": (f"one PCG iteration of the triangle oracle on one 512^2 cell (element loop "
+                       f"{t1 - t0:.2f} s, Green-Jacobi M^-1 with naive DFT {t2 - t1:.2f} s, "
+                       f"dots/axpys {t3 - t2:.2f} s); set-up excluded"),
+            "seconds_per_iteration": per_iter}
+
+
 def cpu_baseline_powerlaw(seed):
     """The power-law oracle timed on one PCG iteration's operators (tangent
     K(u) p by its vectorised element loop, Green-Jacobi preconditioner with
@@ -574,6 +721,9 @@ def main():
         return
     if args.workload == "powerlaw":
         print(json.dumps(run_powerlaw(args)), flush=True)
+        return
+    if args.workload == "tri":
+        print(json.dumps(run_tri(args)), flush=True)
         return
     import jfft_inputs as ji
 
