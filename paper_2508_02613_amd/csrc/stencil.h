@@ -24,7 +24,7 @@ constexpr int ETILE = TILE + 1;    // elements per tile edge (with halo)
 constexpr int NTILE = TILE + 2;    // nodes per tile edge (with halo)
 constexpr int NELEM = ETILE * ETILE;  // 289
 constexpr int NNODE = NTILE * NTILE;  // 324
-constexpr int STENCIL_THREADS = 320;  // 5 wavefronts (2D kernel)
+constexpr int STENCIL_THREADS = 384;  // 6 wavefronts (2D kernel): one node of the tile each
 // 3D kernel: 16 x 14 output nodes, 17 x 15 elements, 18 x 16 node planes.
 // Rows of 16 output nodes start on 64-byte boundaries (FP32; 128 in FP64),
 // so every store covers whole sectors and no sector is written by two blocks.
@@ -1116,38 +1116,59 @@ __global__ void __launch_bounds__(STENCIL_THREADS)
     beta = (Real)a.st->beta;
     alpha_prev = (Real)a.st->alpha;
   }
-  for (int idx = tid; idx < NNODE; idx += STENCIL_THREADS) {
+  // the element modulus (beyond the grid: 0) is requested first, so that its
+  // latency overlaps the node loads
+  const int exl = tid % ETILE, eyl = tid / ETILE;
+  const int gex = x0 - 1 + exl, gey = y0 - 1 + eyl;
+  Real Ee = (Real)0;
+  if (tid < NELEM && gex < nx && gey < ny)
+    Ee = a.E[(long long)wrapi(gex, nx) + (long long)nx * wrapi(gey, ny)];
+  // one node of the halo-extended tile per thread; every load of the node is
+  // issued before its stores (the compiler cannot reorder loads past stores
+  // to other arrays, which it must assume may alias)
+  if (tid < NNODE) {
+    const int idx = tid;
     const int lx = idx % NTILE, ly = idx / NTILE;
     const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
     const int wx = wrapi(gx, nx), wy = wrapi(gy, ny);
     const long long node = (long long)wx + (long long)nx * wy;
     const bool owned = lx >= 1 && lx <= TILE && ly >= 1 && ly <= TILE && gx < nx && gy < ny;
+    Real v[2];
+    if (MODE == SM_APPLY) {
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      Real v;
-      if (MODE == SM_APPLY) {
-        v = a.in[c * N + node];
-      } else if (MODE == SM_COMB) {
-        const int par = (wx & 1) | ((wy & 1) << 1);
-        v = (c == a.comb_comp && par == a.comb_off) ? (Real)1 : (Real)0;
-      } else {
-        const Real z = a.zin[c * N + node];
-        if (first) {
-          v = z;
-        } else {
-          const Real po = a.in[c * N + node];
-          v = z + beta * po;
-          if (owned) a.u[c * N + node] += alpha_prev * po;
+      for (int c = 0; c < 2; ++c) v[c] = a.in[c * N + node];
+    } else if (MODE == SM_COMB) {
+      const int par = (wx & 1) | ((wy & 1) << 1);
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        v[c] = (c == a.comb_comp && par == a.comb_off) ? (Real)1 : (Real)0;
+    } else {
+      Real z[2], po[2] = {0, 0}, uo[2] = {0, 0};
+#pragma unroll
+      for (int c = 0; c < 2; ++c) z[c] = a.zin[c * N + node];
+      if (!first) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) po[c] = a.in[c * N + node];
+        if (owned) {
+#pragma unroll
+          for (int c = 0; c < 2; ++c) uo[c] = a.u[c * N + node];
         }
-        if (owned) a.pout[c * N + node] = v;
       }
-      P[c][idx] = v;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) v[c] = first ? z[c] : z[c] + beta * po[c];
+      if (owned) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          if (!first) a.u[c * N + node] = uo[c] + alpha_prev * po[c];
+          a.pout[c * N + node] = v[c];
+        }
+      }
     }
+    P[0][idx] = v[0];
+    P[1][idx] = v[1];
   }
   __syncthreads();
-  const int exl = tid % ETILE, eyl = tid / ETILE;
   if (tid < NELEM) {
-    const int gex = x0 - 1 + exl, gey = y0 - 1 + eyl;
     Real uv[2][4], yv[2][4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -1155,8 +1176,6 @@ __global__ void __launch_bounds__(STENCIL_THREADS)
       uv[0][c] = P[0][li];
       uv[1][c] = P[1][li];
     }
-    Real Ee = (Real)0;
-    if (gex < nx && gey < ny) Ee = a.E[(long long)wrapi(gex, nx) + (long long)nx * wrapi(gey, ny)];
     if constexpr (TRI)  // a.lam, a.mu carry the Gauss weight hx hy / 4; A is twice that
       elem_tri2(uv, (Real)2 * Ee * a.lam, (Real)2 * Ee * a.mu, a.ihx, a.ihy, yv);
     else
