@@ -359,7 +359,7 @@ size_t layout_workspace(jfft_cell_s *c, unsigned char *base) {
 
 // Output-node tile of the stiffness kernels (x and y edge) and the tile count of a grid.
 int stencil_tile_x(int dim) { return dim == 3 ? TX3 : TILE; }
-int stencil_tile_y(int dim) { return dim == 3 ? TY3 : TILE; }
+int stencil_tile_y(int dim) { return dim == 3 ? TY3 : TY2; }
 long long stencil_tiles(int dim, int nx, int ny) {
   const int tx = stencil_tile_x(dim), ty = stencil_tile_y(dim);
   return (long long)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);

@@ -22,9 +22,11 @@ namespace jfft {
 constexpr int TILE = 16;           // output nodes per tile edge
 constexpr int ETILE = TILE + 1;    // elements per tile edge (with halo)
 constexpr int NTILE = TILE + 2;    // nodes per tile edge (with halo)
-constexpr int NELEM = ETILE * ETILE;  // 289
-constexpr int NNODE = NTILE * NTILE;  // 324
-constexpr int STENCIL_THREADS = 384;  // 6 wavefronts (2D kernel): one node of the tile each
+constexpr int STENCIL_THREADS = 384;  // 6 wavefronts (2D kernel)
+constexpr int TY2 = 2 * TILE;          // output rows of a 2D block (two tiles in y)
+constexpr int NNODE2 = NTILE * (TY2 + 2);  // 612 nodes with halo
+constexpr int NELEM2 = ETILE * (TY2 + 1);  // 561 elements with halo
+constexpr int NOUT2 = TILE * TY2;          // 512 outputs
 // 3D kernel: 16 x 14 output nodes, 17 x 15 elements, 18 x 16 node planes.
 // Rows of 16 output nodes start on 64-byte boundaries (FP32; 128 in FP64),
 // so every store covers whole sectors and no sector is written by two blocks.
@@ -1090,13 +1092,19 @@ __device__ __forceinline__ void elem_tri2(const Real (&u)[2][4], Real Elam, Real
   }
 }
 
+// One block: TILE x TY2 output nodes (two 16 x 16 tiles stacked in y, which
+// share a halo row), 384 threads; every thread owns up to two nodes of the
+// halo-extended tile, two elements and two outputs (index tid + r * 384).
+// All loads of both nodes (and both element moduli) are issued before any
+// store, so a thread keeps a dozen loads in flight.  Loads use clamped,
+// valid addresses and are masked where the value is committed.
 // TRI: the pixel is two linear triangles (elem_tri2) instead of a bilinear
 // quadrilateral.
 template <typename Real, int MODE, bool TRI = false>
 __global__ void __launch_bounds__(STENCIL_THREADS)
     k_stiffness2d(StencilArgs<Real> a) {
-  __shared__ Real P[2][NNODE];
-  __shared__ Real Y[8][NELEM];
+  __shared__ Real P[2][NNODE2];
+  __shared__ Real Y[8][NELEM2];
   __shared__ double red[8];
   const int tid = threadIdx.x;
   const int per_cell = gridDim.x * gridDim.y;
@@ -1106,7 +1114,7 @@ __global__ void __launch_bounds__(STENCIL_THREADS)
   const int lb = lbg - cell * per_cell;
   shift_args(a, cell);
   if (MODE == SM_CG && a.st->done) return;
-  const int x0 = (lb % gridDim.x) * TILE, y0 = (lb / gridDim.x) * TILE;
+  const int x0 = (lb % gridDim.x) * TILE, y0 = (lb / gridDim.x) * TY2;
   const int nx = a.nx, ny = a.ny;
   const long long N = a.N;
   bool first = false;
@@ -1116,96 +1124,135 @@ __global__ void __launch_bounds__(STENCIL_THREADS)
     beta = (Real)a.st->beta;
     alpha_prev = (Real)a.st->alpha;
   }
-  // the element modulus (beyond the grid: 0) is requested first, so that its
-  // latency overlaps the node loads
-  const int exl = tid % ETILE, eyl = tid / ETILE;
-  const int gex = x0 - 1 + exl, gey = y0 - 1 + eyl;
-  Real Ee = (Real)0;
-  if (tid < NELEM && gex < nx && gey < ny)
-    Ee = a.E[(long long)wrapi(gex, nx) + (long long)nx * wrapi(gey, ny)];
-  // one node of the halo-extended tile per thread; every load of the node is
-  // issued before its stores (the compiler cannot reorder loads past stores
-  // to other arrays, which it must assume may alias)
-  if (tid < NNODE) {
-    const int idx = tid;
-    const int lx = idx % NTILE, ly = idx / NTILE;
+  constexpr int R = 2;  // items per thread
+  static_assert(R * STENCIL_THREADS >= NNODE2 && R * STENCIL_THREADS >= NELEM2 &&
+                    R * STENCIL_THREADS >= NOUT2,
+                "two items per thread cover the tile");
+  // element moduli (beyond the grid: 0)
+  Real Ee[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int e = min(tid + r * STENCIL_THREADS, NELEM2 - 1);
+    const int gex = x0 - 1 + e % ETILE, gey = y0 - 1 + e / ETILE;
+    const Real v = a.E[(long long)wrapi(gex, nx) + (long long)nx * wrapi(gey, ny)];
+    Ee[r] = (gex < nx && gey < ny) ? v : (Real)0;
+  }
+  // nodes: loads of both first
+  long long node[R];
+  bool owned[R], valid[R];
+  int par[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int idx = tid + r * STENCIL_THREADS;
+    valid[r] = idx < NNODE2;
+    const int ci = min(idx, NNODE2 - 1);
+    const int lx = ci % NTILE, ly = ci / NTILE;
     const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
     const int wx = wrapi(gx, nx), wy = wrapi(gy, ny);
-    const long long node = (long long)wx + (long long)nx * wy;
-    const bool owned = lx >= 1 && lx <= TILE && ly >= 1 && ly <= TILE && gx < nx && gy < ny;
-    Real v[2];
-    if (MODE == SM_APPLY) {
+    node[r] = (long long)wx + (long long)nx * wy;
+    owned[r] = valid[r] && lx >= 1 && lx <= TILE && ly >= 1 && ly <= TY2 && gx < nx && gy < ny;
+    par[r] = (wx & 1) | ((wy & 1) << 1);
+  }
+  Real v[R][2];
+  if (MODE == SM_APPLY) {
 #pragma unroll
-      for (int c = 0; c < 2; ++c) v[c] = a.in[c * N + node];
-    } else if (MODE == SM_COMB) {
-      const int par = (wx & 1) | ((wy & 1) << 1);
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) v[r][c] = a.in[c * N + node[r]];
+  } else if (MODE == SM_COMB) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
 #pragma unroll
       for (int c = 0; c < 2; ++c)
-        v[c] = (c == a.comb_comp && par == a.comb_off) ? (Real)1 : (Real)0;
-    } else {
-      Real z[2], po[2] = {0, 0}, uo[2] = {0, 0};
+        v[r][c] = (c == a.comb_comp && par[r] == a.comb_off) ? (Real)1 : (Real)0;
+  } else {
+    Real z[R][2], po[R][2], uo[R][2];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) z[c] = a.zin[c * N + node];
-      if (!first) {
+    for (int r = 0; r < R; ++r)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) po[c] = a.in[c * N + node];
-        if (owned) {
-#pragma unroll
-          for (int c = 0; c < 2; ++c) uo[c] = a.u[c * N + node];
-        }
+      for (int c = 0; c < 2; ++c) {
+        z[r][c] = a.zin[c * N + node[r]];
+        po[r][c] = (Real)0;
+        uo[r][c] = (Real)0;
       }
+    if (!first) {
 #pragma unroll
-      for (int c = 0; c < 2; ++c) v[c] = first ? z[c] : z[c] + beta * po[c];
-      if (owned) {
+      for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          if (!first) a.u[c * N + node] = uo[c] + alpha_prev * po[c];
-          a.pout[c * N + node] = v[c];
+          po[r][c] = a.in[c * N + node[r]];
+          if (owned[r]) uo[r][c] = a.u[c * N + node[r]];  // u of owned nodes only
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) v[r][c] = first ? z[r][c] : z[r][c] + beta * po[r][c];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (owned[r]) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          if (!first) a.u[c * N + node[r]] = uo[r][c] + alpha_prev * po[r][c];
+          a.pout[c * N + node[r]] = v[r][c];
         }
       }
-    }
-    P[0][idx] = v[0];
-    P[1][idx] = v[1];
   }
-  __syncthreads();
-  if (tid < NELEM) {
-    Real uv[2][4], yv[2][4];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int li = (eyl + (c >> 1)) * NTILE + exl + (c & 1);
-      uv[0][c] = P[0][li];
-      uv[1][c] = P[1][li];
+  for (int r = 0; r < R; ++r)
+    if (valid[r]) {
+      P[0][tid + r * STENCIL_THREADS] = v[r][0];
+      P[1][tid + r * STENCIL_THREADS] = v[r][1];
     }
-    if constexpr (TRI)  // a.lam, a.mu carry the Gauss weight hx hy / 4; A is twice that
-      elem_tri2(uv, (Real)2 * Ee * a.lam, (Real)2 * Ee * a.mu, a.ihx, a.ihy, yv);
-    else
-      elem_quad(uv, Ee * a.lam, Ee * a.mu, a.ihx, a.ihy, yv);
+  __syncthreads();
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      Y[c * 2 + 0][tid] = yv[0][c];
-      Y[c * 2 + 1][tid] = yv[1][c];
+  for (int r = 0; r < R; ++r) {
+    const int e = tid + r * STENCIL_THREADS;
+    if (e < NELEM2) {
+      const int exl = e % ETILE, eyl = e / ETILE;
+      Real uv[2][4], yv[2][4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int li = (eyl + (c >> 1)) * NTILE + exl + (c & 1);
+        uv[0][c] = P[0][li];
+        uv[1][c] = P[1][li];
+      }
+      if constexpr (TRI)  // a.lam, a.mu carry the Gauss weight hx hy / 4; A is twice that
+        elem_tri2(uv, (Real)2 * Ee[r] * a.lam, (Real)2 * Ee[r] * a.mu, a.ihx, a.ihy, yv);
+      else
+        elem_quad(uv, Ee[r] * a.lam, Ee[r] * a.mu, a.ihx, a.ihy, yv);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        Y[c * 2 + 0][e] = yv[0][c];
+        Y[c * 2 + 1][e] = yv[1][c];
+      }
     }
   }
   __syncthreads();
   double acc = 0.0;
-  const int oxl = tid % TILE, oyl = tid / TILE;
-  const int gnx = x0 + oxl, gny = y0 + oyl;
-  if (tid < TILE * TILE && gnx < nx && gny < ny) {
-    const int e00 = oyl * ETILE + oxl;
-    Real q[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-      q[i] = Y[3 * 2 + i][e00] + Y[2 * 2 + i][e00 + 1] + Y[1 * 2 + i][e00 + ETILE] +
-             Y[0 * 2 + i][e00 + ETILE + 1];
-    const long long node = (long long)gnx + (long long)nx * gny;
-    const int li = (oyl + 1) * NTILE + oxl + 1;
-    if (MODE == SM_COMB) {
-      const int par = (gnx & 1) | ((gny & 1) << 1);
-      if (par == a.comb_off) a.diag[a.comb_comp * N + node] = q[a.comb_comp];
-    } else {
-      a.out[node] = q[0];
-      a.out[N + node] = q[1];
-      if (MODE == SM_CG) acc = (double)P[0][li] * (double)q[0] + (double)P[1][li] * (double)q[1];
+  for (int r = 0; r < R; ++r) {
+    const int o = tid + r * STENCIL_THREADS;
+    const int oxl = o % TILE, oyl = o / TILE;
+    const int gnx = x0 + oxl, gny = y0 + oyl;
+    if (o < NOUT2 && gnx < nx && gny < ny) {
+      const int e00 = oyl * ETILE + oxl;
+      Real q[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        q[i] = Y[3 * 2 + i][e00] + Y[2 * 2 + i][e00 + 1] + Y[1 * 2 + i][e00 + ETILE] +
+               Y[0 * 2 + i][e00 + ETILE + 1];
+      const long long nd = (long long)gnx + (long long)nx * gny;
+      const int li = (oyl + 1) * NTILE + oxl + 1;
+      if (MODE == SM_COMB) {
+        const int pr = (gnx & 1) | ((gny & 1) << 1);
+        if (pr == a.comb_off) a.diag[a.comb_comp * N + nd] = q[a.comb_comp];
+      } else {
+        a.out[nd] = q[0];
+        a.out[N + nd] = q[1];
+        if (MODE == SM_CG)
+          acc += (double)P[0][li] * (double)q[0] + (double)P[1][li] * (double)q[1];
+      }
     }
   }
   if (MODE == SM_CG) {
