@@ -38,12 +38,13 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, FP64 vector (no MFMA)
-# FP64 flops of one element evaluation of the power-law tangent stiffness
-# kernel (strain of the iterate and of p at 8 Gauss points, tangent, weighted
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X, FP32 vector (no MFMA)
+# Flops of one element evaluation of the power-law tangent stiffness kernel
+# (strain of the iterate and of p at 8 Gauss points, tangent, weighted
 # divergence): 64 lanes x (ADD + MUL + TRANS + 2 FMA) wave instructions of a
-# launch over its element evaluations, from rocprofv3 SQ_INSTS_VALU_*_F64
-# counters (profiles/fp64_ops_powerlaw200.txt)
-TANGENT_FLOPS_PER_ELEMENT = 2267.2
+# launch over its element evaluations, from rocprofv3 SQ_INSTS_VALU_*_F64 /
+# _F32 counters (profiles/valu_ops_powerlaw200.txt)
+TANGENT_FLOPS_PER_ELEMENT = {"f64": 2267.2, "f32": 2193.3}
 
 
 def parse():
@@ -407,11 +408,12 @@ def run_powerlaw(args):
     paper does not give its geometry) in the power-law matrix (K = 2, sigma0 =
     0.5, eps0 = 0.1, n = 5; inclusions K = 2, mu = 1/2), macro shear
     e6 = 0.05 sqrt2 in one load step, Newton to ||f|| < 1e-5 with PCG to
-    ||r||^2 <= 1e-10 (the rules of Sec. 4), FP64.  One step = one whole
-    Newton solve (set the material, every Newton step with its Algorithm 2
-    diagonal and PCG solve, sigma_bar).  Headline: Green-Jacobi; the Green
-    preconditioner is timed beside it (PCG iterations per Newton step, the
-    figure of Sec. 4)."""
+    ||r||^2 <= 1e-10 (the rules of Sec. 4).  One step = one whole Newton
+    solve (set the material, every Newton step with its Algorithm 2 diagonal
+    and PCG solve, sigma_bar).  Headline: Green-Jacobi in mixed precision
+    (FP32 tangent solves refined against the FP64 tangent residual); FP64
+    Green-Jacobi and FP64 Green beside it (PCG iterations per Newton step,
+    the figure of Sec. 4)."""
     import torch
 
     import jfft_inputs as ji
@@ -427,8 +429,10 @@ def run_powerlaw(args):
     ph = torch.from_numpy(phase).to("cuda")
     stream = torch.cuda.Stream()
     runs = {}
-    for name, pc in (("green_jacobi", pkg.PC_GREEN_JACOBI), ("green", pkg.PC_GREEN)):
-        cell = pkg.Cell(shape, precision=pkg.FP64, pc=pc, lengths=L, stream=stream)
+    for name, pc, prec in (("green_jacobi", pkg.PC_GREEN_JACOBI, pkg.FP64),
+                           ("green", pkg.PC_GREEN, pkg.FP64),
+                           ("mixed_green_jacobi", pkg.PC_GREEN_JACOBI, pkg.MIXED)):
+        cell = pkg.Cell(shape, precision=prec, pc=pc, lengths=L, stream=stream)
         if args.graph:
             cell.set_graph_iterations(args.graph)
         cell.set_stop_rule(absolute=True)
@@ -450,7 +454,7 @@ def run_powerlaw(args):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         stats = None
-        if name == "green_jacobi":
+        if name != "green":
             cell.reset_timing()
             cell.enable_timing(True)
             step()
@@ -459,54 +463,69 @@ def run_powerlaw(args):
             cell.enable_timing(False)
         cell.close()
         runs[name] = {"wall_s": wall, "reps": reps, "sigma_bar": sbar, "stats": stats}
-    R = runs["green_jacobi"]
-    its = sum(sum(r.pcg_iters) for r in R["reps"])
-    value = dofs * its / R["wall_s"]
-    stats = R["stats"]
-    launches, tot_ms = stats["stiffness_cg"]
-    rep = R["reps"][-1]
-    executed = sum(rep.pcg_iters)
-    bytes_launch = algorithmic_bytes("stiffness_cg_tangent", 3, N, n, 8)
-    flops_launch = TANGENT_FLOPS_PER_ELEMENT * N
-    avg_ms = tot_ms / launches
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    tflops = flops_launch / (avg_ms * 1e-3) / 1e12
+    M = runs["mixed_green_jacobi"]  # headline: mixed precision, as the linear headline
+    F = runs["green_jacobi"]
     G = runs["green"]
+
+    def iters(run):
+        return sum(sum(r.pcg_iters) for r in run["reps"])
+
+    def roofline(run, prec):
+        # tangent CG stiffness kernel: FP32 in the mixed path's inner solves
+        launches, tot_ms = run["stats"]["stiffness_cg"]
+        rb = 4 if prec == "f32" else 8
+        bytes_launch = algorithmic_bytes("stiffness_cg_tangent", 3, N, n, rb)
+        flops_launch = TANGENT_FLOPS_PER_ELEMENT[prec] * N
+        avg_ms = tot_ms / launches
+        gbs = bytes_launch / (avg_ms * 1e-3) / 1e9
+        tf = flops_launch / (avg_ms * 1e-3) / 1e12
+        peak = FP32_VECTOR_PEAK_TFLOPS if prec == "f32" else FP64_VECTOR_PEAK_TFLOPS
+        return {"bound": "alu", "kernel": f"stiffness_cg (power-law tangent, {prec.upper()})",
+                "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
+                "traffic": load_traffic(f"powerlaw_{n}", f"stiffness_cg_{prec}"),
+                "algorithmic_flops_per_launch": flops_launch,
+                "flops_per_element": TANGENT_FLOPS_PER_ELEMENT[prec],
+                "hbm_achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                "avg_ms": avg_ms, "launches": launches,
+                "algorithmic_bytes_per_launch": bytes_launch,
+                "measured": "HIP events on the cell's stream around every launch, one "
+                            "further Newton solve with direct launches"}
+
+    def newton(run):
+        r = run["reps"][-1]
+        return {"steps": r.steps, "pcg_iters": r.pcg_iters, "res": r.res,
+                "ms_per_solve": 1e3 * run["wall_s"] / args.steps,
+                "value": dofs * iters(run) / run["wall_s"]}
+
     line = {
         "metric": "DOF·iterations/s (power-law Newton, J-FFT PCG on the tangent)",
-        "value": value, "unit": "DOF·it/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * R["wall_s"] / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "value": dofs * iters(M) / M["wall_s"], "unit": "DOF·it/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * M["wall_s"] / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": (f"nonlinear example {n}^3 nodes, voxels of unit edge, 8 "
                                 f"spherical linear inclusions (radius 0.15, seed {args.seed}) in a "
                                 "power-law matrix (K 2, sigma0 0.5, eps0 0.1, n 5), macro shear "
                                 "e6 0.05 sqrt2, Newton to ||f|| < 1e-5, Green-Jacobi PCG to "
-                                "||r||^2 <= 1e-10, FP64"),
+                                "||r||^2 <= 1e-10; mixed precision: FP32 tangent solves refined "
+                                "against the FP64 tangent residual"),
                    "n": n, "dofs": dofs, "inclusion_fraction": float(1.0 - phase.mean()),
                    "graph_iterations": args.graph},
-        "newton": {"green_jacobi": {"steps": rep.steps, "pcg_iters": rep.pcg_iters,
-                                    "res": rep.res, "ms_per_solve": 1e3 * R["wall_s"] / args.steps},
-                   "green": {"steps": G["reps"][-1].steps, "pcg_iters": G["reps"][-1].pcg_iters,
-                             "res": G["reps"][-1].res,
-                             "ms_per_solve": 1e3 * G["wall_s"] / args.steps,
-                             "value": dofs * sum(sum(r.pcg_iters) for r in G["reps"]) / G["wall_s"],
-                             "sigma_bar_rel_diff_vs_gj": float(
-                                 np.abs(G["sigma_bar"] - R["sigma_bar"]).max()
-                                 / np.abs(R["sigma_bar"]).max())}},
-        "sigma_bar": [float(v) for v in R["sigma_bar"]],
-        "roofline": {"bound": "alu", "kernel": "stiffness_cg (power-law tangent)",
-                     "achieved": tflops, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": tflops / FP64_VECTOR_PEAK_TFLOPS,
-                     "traffic": load_traffic(f"powerlaw_{n}", "stiffness_cg"),
-                     "algorithmic_flops_per_launch": flops_launch,
-                     "flops_per_element": TANGENT_FLOPS_PER_ELEMENT,
-                     "hbm_achieved_gbs": achieved, "hbm_frac": achieved / HBM_PEAK_GBS,
-                     "avg_ms": avg_ms, "launches": launches, "launches_with_work": executed,
-                     "algorithmic_bytes_per_launch": bytes_launch,
-                     "measured": "HIP events on the cell's stream around every launch, one "
-                                 "further Newton solve with direct launches"},
-        "kernels_ms_per_solve": {k: v[1] for k, v in sorted(stats.items())},
+        "newton": {"mixed_green_jacobi": newton(M),
+                   "green_jacobi": newton(F),
+                   "green": dict(newton(G), sigma_bar_rel_diff_vs_gj=float(
+                       np.abs(G["sigma_bar"] - F["sigma_bar"]).max()
+                       / np.abs(F["sigma_bar"]).max()))},
+        "sigma_bar": [float(v) for v in M["sigma_bar"]],
+        "sigma_bar_rel_diff_mixed_vs_fp64": float(
+            np.abs(M["sigma_bar"] - F["sigma_bar"]).max() / np.abs(F["sigma_bar"]).max()),
+        "roofline": roofline(M, "f32"),
+        "fp64": {"value": dofs * iters(F) / F["wall_s"],
+                 "ms_per_step": 1e3 * F["wall_s"] / args.steps,
+                 "roofline": roofline(F, "f64"),
+                 "kernels_ms_per_solve": {k: v[1] for k, v in sorted(F["stats"].items())}},
+        "kernels_ms_per_solve": {k: v[1] for k, v in sorted(M["stats"].items())},
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline_powerlaw(args.seed)

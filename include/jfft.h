@@ -261,7 +261,11 @@ jfft_status jfft_set_mixed_params(jfft_cell_t cell, double inner_tol, int max_ou
 
 /* ---- Power-law material and Newton solve (nonlinear example, Sec. 4;
    Newton linearisation, Sec. 2.2, eq. lin_system) -------------------------
-   Single 3D FP64 cell only (else JFFT_E_INVALID).
+   Single 3D cell only (else JFFT_E_INVALID).  FP64 cells solve every
+   Newton step's tangent system by FP64 PCG; JFFT_MIXED cells by FP32 PCG
+   (FP32 tangent at an FP32 copy of u, FP64 dots and CG scalars) refined
+   against the FP64 tangent residual, as jfft_solve does, so their inner
+   stopping rule applies to the true FP64 residual.
    jfft_set_material_powerlaw: phase_dev [N] on the device, element phase
    (entries > 0.5: matrix, else inclusion; negative or non-finite entries:
    JFFT_E_INVALID); copied, the caller keeps ownership.  Matrix: sigma =

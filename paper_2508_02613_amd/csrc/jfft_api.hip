@@ -169,6 +169,7 @@ struct jfft_cell_s {
   bool nl = false;
   PowerLawArgs pl{};
   double *uk = nullptr;
+  float *uk32 = nullptr;  // FP32 copy of uk for the inner solves of a mixed-precision cell
 
   // captured iteration chunks
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // [0] FP64, [1] FP32 inner
@@ -204,6 +205,7 @@ struct jfft_cell_s {
       if (e) (void)hipEventDestroy(e);
     if (ws_owned && ws) (void)hipFree(ws);
     if (uk) (void)hipFree(uk);
+    if (uk32) (void)hipFree(uk32);
     if (st_h) (void)hipHostFree(st_h);
     if (small_h) (void)hipHostFree(small_h);
   }
@@ -490,12 +492,13 @@ StencilArgs<Real> stencil_args(jfft_cell_s *c, const Real *E) {
   a.nbz = c->dim == 3 ? (c->g.nz + a.tz - 1) / a.tz : 1;
   a.cs = c->cs;
   a.st = c->st;
-  if constexpr (std::is_same<Real, double>::value) {
-    if (c->nl) {
+  if (c->nl) {
+    if constexpr (std::is_same<Real, double>::value)
       a.uk = c->uk;
-      a.pl = c->pl;
-      a.w = c->g.w;
-    }
+    else
+      a.uk = c->uk32;
+    a.pl = c->pl;
+    a.w = (Real)c->g.w;
   }
   return a;
 }
@@ -568,13 +571,13 @@ jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a, int cel
   const int tx = stencil_tile_x(c->dim), ty = stencil_tile_y(c->dim);
   dim3 gr((g.nx + tx - 1) / tx, (g.ny + ty - 1) / ty, a.nbz * cells);
   if (c->nl) {
-    // the power-law tangent exists for 3D FP64 cells only (checked when the
-    // material is set)
-    if constexpr (std::is_same<Real, double>::value) {
-      LAUNCH(c, kid, (k_stiffness3d<double, MODE, false, 1><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
+    // the power-law tangent (3D cells, checked when the material is set);
+    // Algorithm 2's combs run in FP64 only
+    if constexpr (std::is_same<Real, double>::value || MODE != SM_COMB) {
+      LAUNCH(c, kid, (k_stiffness3d<Real, MODE, false, 1><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
       return JFFT_OK;
     }
-    return fail(JFFT_E_INVALID, "the power-law tangent runs in FP64 only");
+    return fail(JFFT_E_INVALID, "the power-law combs run in FP64 only");
   }
   if (c->dim == 3 && cubic_cells(c)) {
     LAUNCH(c, kid, (k_stiffness3d<Real, MODE, true><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
@@ -1095,6 +1098,36 @@ jfft_status post_process(jfft_cell_s *c, double *u_out, double *sigma_dev, doubl
   return JFFT_OK;
 }
 
+// Mixed precision: FP64 residual r = f - K u and iterate u, FP32 inner PCG
+// on r / ||r|| (FP64 dots and CG scalars), u += ||r|| c, until the FP64
+// residual meets the cell's stopping rule (state set by k_solve_norms).
+// have_u: u holds a start vector (else u = 0 and r = f).
+jfft_status mixed_refine(jfft_cell_s *c, int maxit, bool have_u) {
+  const long long nd = (long long)c->dim * c->g.N;
+  const int nb = vec_blocks(nd);
+  const int Bc = c->B;
+  for (int sweep = 0;; ++sweep) {
+    if (sweep > 0 || have_u) {
+      TRY(apply_K<double>(c, c->E, c->u, c->q, Bc));
+      LAUNCH(c, KID_VEC, k_sub_norm<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->q, c->r, nd, c->partA, c->cs));
+    } else {
+      LAUNCH(c, KID_VEC, k_sub_norm<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->u, c->r, nd, c->partA, c->cs));
+    }
+    LAUNCH(c, KID_CTRL, k_outer_check<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nb, c->max_outer, maxit, c->cs));
+    TRY(fetch_states(c));
+    bool all = true;
+    for (int i = 0; i < Bc; ++i) all = all && c->st_h[i].outer_done;
+    if (all) break;
+    LAUNCH(c, KID_VEC, (k_convert<double, float><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->r, c->r32, nd, 1.0, c->st, c->cs)));
+    LAUNCH(c, KID_VEC, k_fill<float><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->c32, 0.0f, nd, c->cs));
+    PcgBufs<float> b{c->c32, c->r32, c->z32, c->q32, {c->p32[0], c->p32[1]}, c->E32, c->Jh32, c->spec32};
+    TRY(run_pcg<float>(c, b, true, maxit, false));
+    LAUNCH(c, KID_CTRL, k_outer_update<<<Bc, 1, 0, c->stream>>>(c->st, c->cs));
+    LAUNCH(c, KID_VEC, k_axpy_f32_to_f64<<<dim3(nb, Bc), 256, 0, c->stream>>>(c->c32, c->u, nd, c->st, c->cs));
+  }
+  return JFFT_OK;
+}
+
 jfft_status solve_impl(jfft_cell_s *c, const double *macros_h, double tol, int maxit,
                        const double *u0, double *u_out, double *sigma_dev, double *sigma_bar,
                        jfft_report *reps) {
@@ -1127,26 +1160,7 @@ jfft_status solve_impl(jfft_cell_s *c, const double *macros_h, double tol, int m
     TRY(run_pcg<double>(c, b, false, maxit, true));
     LAUNCH(c, KID_CTRL, k_fp64_final<<<Bc, 1, 0, c->stream>>>(c->st, c->cs));
   } else {
-    // mixed precision: FP64 residual and iterate, FP32 inner PCG on r / ||r||
-    for (int sweep = 0;; ++sweep) {
-      if (sweep > 0 || u0) {
-        TRY(apply_K<double>(c, c->E, c->u, c->q, Bc));
-        LAUNCH(c, KID_VEC, k_sub_norm<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->q, c->r, nd, c->partA, c->cs));
-      } else {
-        LAUNCH(c, KID_VEC, k_sub_norm<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->u, c->r, nd, c->partA, c->cs));
-      }
-      LAUNCH(c, KID_CTRL, k_outer_check<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nb, c->max_outer, maxit, c->cs));
-      TRY(fetch_states(c));
-      bool all = true;
-      for (int i = 0; i < Bc; ++i) all = all && c->st_h[i].outer_done;
-      if (all) break;
-      LAUNCH(c, KID_VEC, (k_convert<double, float><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->r, c->r32, nd, 1.0, c->st, c->cs)));
-      LAUNCH(c, KID_VEC, k_fill<float><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->c32, 0.0f, nd, c->cs));
-      PcgBufs<float> b{c->c32, c->r32, c->z32, c->q32, {c->p32[0], c->p32[1]}, c->E32, c->Jh32, c->spec32};
-      TRY(run_pcg<float>(c, b, true, maxit, false));
-      LAUNCH(c, KID_CTRL, k_outer_update<<<Bc, 1, 0, c->stream>>>(c->st, c->cs));
-      LAUNCH(c, KID_VEC, k_axpy_f32_to_f64<<<dim3(nb, Bc), 256, 0, c->stream>>>(c->c32, c->u, nd, c->st, c->cs));
-    }
+    TRY(mixed_refine(c, maxit, u0 != nullptr));
   }
   HIP_TRY(hipEventRecord(c->phase_ev[2], c->stream));
   TRY(post_process(c, u_out, sigma_dev, sigma_bar));
@@ -1189,8 +1203,8 @@ jfft_status set_material_powerlaw_impl(jfft_cell_s *c, const double *phase_dev, 
                                        double sigma0, double eps0, double n, double K_incl,
                                        double mu_incl) {
   if (!phase_dev) return fail(JFFT_E_INVALID, "phase_dev is NULL");
-  if (c->dim != 3 || c->prec != JFFT_FP64 || c->B != 1)
-    return fail(JFFT_E_INVALID, "the power-law material needs a single 3D FP64 cell");
+  if (c->dim != 3 || c->B != 1)
+    return fail(JFFT_E_INVALID, "the power-law material needs a single 3D cell");
   const double prm[6] = {K, sigma0, eps0, n, K_incl, mu_incl};
   for (double v : prm)
     if (!std::isfinite(v)) return fail(JFFT_E_INVALID, "power-law parameters must be finite");
@@ -1204,6 +1218,12 @@ jfft_status set_material_powerlaw_impl(jfft_cell_s *c, const double *phase_dev, 
     if (e != hipSuccess) return fail(JFFT_E_OOM, std::string("hipMalloc Newton iterate: ") + hipGetErrorString(e));
     c->uk = static_cast<double *>(p);
   }
+  if (c->prec == JFFT_MIXED && !c->uk32) {
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(float) * 3 * N);
+    if (e != hipSuccess) return fail(JFFT_E_OOM, std::string("hipMalloc Newton iterate: ") + hipGetErrorString(e));
+    c->uk32 = static_cast<float *>(p);
+  }
   c->drop_graphs();
   c->has_material = false;
   c->nl = false;
@@ -1213,6 +1233,8 @@ jfft_status set_material_powerlaw_impl(jfft_cell_s *c, const double *phase_dev, 
   TRY(fetch_small(c));
   if (c->small_h[0] != 0.0) return fail(JFFT_E_INVALID, "phase contains negative or non-finite entries");
   LAUNCH(c, KID_SETUP, k_copy<double><<<dim3(nb, 1), 256, 0, c->stream>>>(phase_dev, 0, c->E, 0, N));
+  if (c->prec == JFFT_MIXED)
+    LAUNCH(c, KID_SETUP, (k_convert<double, float><<<dim3(nb, 1), 256, 0, c->stream>>>(c->E, c->E32, N, 1.0, nullptr, c->cs)));
   c->pl = PowerLawArgs{};
   c->pl.K = K;
   c->pl.gcoef = sigma0 * (2.0 / 3.0) / std::pow(eps0, n);
@@ -1270,7 +1292,10 @@ jfft_status nl_jacobi(jfft_cell_s *c) {
   if (!useJ(c)) return JFFT_OK;
   const long long nd = 3 * c->g.N;
   if (!nl_closed_diag(c)) TRY(run_alg2(c, c->diag, 1));
-  LAUNCH(c, KID_SETUP, k_jhalf<double><<<dim3(vec_blocks(nd), 1), 256, 0, c->stream>>>(c->diag, c->Jh, nd, c->void_value, c->cs));
+  if (c->prec == JFFT_MIXED)  // only the FP32 inner solves use J^1/2
+    LAUNCH(c, KID_SETUP, k_jhalf<float><<<dim3(vec_blocks(nd), 1), 256, 0, c->stream>>>(c->diag, c->Jh32, nd, c->void_value, c->cs));
+  else
+    LAUNCH(c, KID_SETUP, k_jhalf<double><<<dim3(vec_blocks(nd), 1), 256, 0, c->stream>>>(c->diag, c->Jh, nd, c->void_value, c->cs));
   return JFFT_OK;
 }
 
@@ -1310,9 +1335,15 @@ jfft_status newton_impl(jfft_cell_s *c, const double *macro_h, double newton_tol
     LAUNCH(c, KID_VEC, k_dot<double><<<dim3(nb, 1), 256, 0, c->stream>>>(c->f, c->f, nd, c->partA, c->cs));
     LAUNCH(c, KID_CTRL, k_solve_norms<<<1, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, c->partA, nb, itol, c->stop_abs ? 1 : 0, c->cs));
     LAUNCH(c, KID_VEC, k_fill<double><<<dim3(nb, 1), 256, 0, c->stream>>>(c->u, 0.0, nd, 0));
-    LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, 1), 256, 0, c->stream>>>(c->f, 0, c->r, 0, nd));
-    TRY(run_pcg<double>(c, b, false, maxit, false));
-    LAUNCH(c, KID_CTRL, k_fp64_final<<<1, 1, 0, c->stream>>>(c->st, c->cs));
+    if (c->prec == JFFT_MIXED) {
+      // FP32 tangent solves refined against the FP64 tangent residual
+      LAUNCH(c, KID_VEC, (k_convert<double, float><<<dim3(nb, 1), 256, 0, c->stream>>>(c->uk, c->uk32, nd, 1.0, nullptr, c->cs)));
+      TRY(mixed_refine(c, maxit, false));
+    } else {
+      LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, 1), 256, 0, c->stream>>>(c->f, 0, c->r, 0, nd));
+      TRY(run_pcg<double>(c, b, false, maxit, false));
+      LAUNCH(c, KID_CTRL, k_fp64_final<<<1, 1, 0, c->stream>>>(c->st, c->cs));
+    }
     LAUNCH(c, KID_VEC, k_add<double><<<nb, 256, 0, c->stream>>>(c->u, c->uk, nd));
     TRY(fetch_states(c));
     if (pcg_iters) pcg_iters[steps] = c->st_h[0].total_iters;

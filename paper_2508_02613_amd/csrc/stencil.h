@@ -42,8 +42,12 @@ static_assert(TX3 == 16 && NY3 == 16 && NSTRIP3 == 32,
 // Register budget of the 3D kernel (waves per SIMD = blocks per CU): three
 // blocks per CU in FP32 (<= 168 VGPRs; at 128 it spills), one in FP64 (at
 // 256 VGPRs it spills, which costs more than the second block gains).
-template <typename Real>
-constexpr int stencil3_waves_per_simd() { return sizeof(Real) == 4 ? 3 : 1; }
+// The power-law tangent (MAT = 1) holds two gradient sets: two blocks per CU
+// in FP32, one in FP64.
+template <typename Real, int MAT = 0>
+constexpr int stencil3_waves_per_simd() {
+  return MAT ? (sizeof(Real) == 4 ? 2 : 1) : (sizeof(Real) == 4 ? 3 : 1);
+}
 
 // Gauss-point interpolation weights of the linear shape functions:
 // N_0(xi_g) = {A, B}, N_1(xi_g) = {B, A} for xi_g = 1/2 -+ 1/(2 sqrt 3).
@@ -749,7 +753,7 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
 // MAT = 1: the tangent of the power-law problem at the Newton iterate a.uk
 // (E holds the phase); a second ring of node planes holds the iterate.
 template <typename Real, int MODE, bool CUBIC = false, int MAT = 0>
-__global__ void __launch_bounds__(STENCIL3_THREADS, stencil3_waves_per_simd<Real>())
+__global__ void __launch_bounds__(STENCIL3_THREADS, (stencil3_waves_per_simd<Real, MAT>()))
     k_stiffness3d(StencilArgs<Real> a) {
   __shared__ Real P[3][3][NNODE3];               // ring of three node planes of the input vector
   __shared__ Real U[MAT ? 3 : 1][3][MAT ? NNODE3 : 1];  // MAT: ring of the Newton iterate

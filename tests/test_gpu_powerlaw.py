@@ -171,6 +171,50 @@ def test_newton_unit_voxels_absolute_rule():
     assert np.abs(s - ref.sigma_bar).max() <= (1e-10 if same else 1e-6) * np.abs(ref.sigma_bar).max()
 
 
+@pytest.mark.parametrize("rule", ["relative", "absolute"])
+def test_newton_mixed_precision_matches_fp64(rule):
+    """FP32 tangent solves refined against the FP64 tangent residual reach
+    the FP64 Newton solution: the same steps and ||f|| history to the
+    accuracy the inner tolerances leave, u and sigma_bar close."""
+    pkg = _pkg()
+    n = 16
+    shape = (n, n, n)
+    say(f"power-law Newton mixed vs FP64 {shape} {rule} rule")
+    phase = 1.0 - ji.spherical_inclusions(shape, 8, 0.15, seed=5)
+    macro = np.array([0, 0, 0, 0, 0, 0.05 * np.sqrt(2)])
+    if rule == "absolute":
+        L, kw = (float(n),) * 3, dict(newton_tol=1e-5, pcg_tol=1e-10)
+    else:
+        L, kw = None, dict(newton_tol=1e-10, pcg_tol=1e-10)
+    out = {}
+    for prec in (pkg.FP64, pkg.MIXED):
+        cell = pkg.Cell(shape, precision=prec, pc=pkg.PC_GREEN_JACOBI, lengths=L)
+        cell.set_stop_rule(absolute=rule == "absolute")
+        _set(cell, phase)
+        u, s, r = cell.solve_newton(macro, **kw)
+        out[prec] = (u.cpu().numpy(), s, r)
+        cell.close()
+    (u64, s64, r64), (u32, s32, r32) = out[pkg.FP64], out[pkg.MIXED]
+    say(f"  fp64 {r64}\n  mixed {r32}")
+    assert r64.converged and r32.converged
+    assert abs(r32.res[0] - r64.res[0]) <= 1e-12 * r64.res[0]
+    for a, b in zip(r32.res[1:-1], r64.res[1:-1]):
+        assert abs(a - b) <= 1e-3 * b
+    if rule == "relative":
+        assert r32.steps == r64.steps
+        assert np.abs(u32 - u64).max() <= 1e-5 * np.abs(u64).max()
+        assert np.abs(s32 - s64).max() <= 1e-7 * np.abs(s64).max()
+    else:
+        # Sec. 4's rules put the inner tolerance (||r|| <= 1e-5) at the Newton
+        # tolerance (||f|| < 1e-5): the last step's residual sits at the
+        # threshold.  The mixed inner solves stop on the true FP64 residual,
+        # the FP64 ones on the recursive residual, one iteration apart; that
+        # can decide one Newton step either way; both meet ||f|| < 1e-5
+        assert abs(r32.steps - r64.steps) <= 1
+        assert np.abs(u32 - u64).max() <= 1e-4 * np.abs(u64).max()
+        assert np.abs(s32 - s64).max() <= 1e-5 * np.abs(s64).max()
+
+
 def test_newton_probing_diagonal_equals_closed_form():
     pkg = _pkg()
     shape = (12, 16, 18)
@@ -292,10 +336,10 @@ def test_argument_and_state_checks():
     with pytest.raises(pkg.JfftError):
         c2.set_material_powerlaw(np.ones((16, 16)))
     c2.close()
-    cm = pkg.Cell(shape, precision=pkg.MIXED, pc=pkg.PC_GREEN)
+    cb = pkg.Cell(shape, pc=pkg.PC_GREEN, batch=2)
     with pytest.raises(pkg.JfftError):
-        _set(cm, phase)
-    cm.close()
+        cb.set_material_powerlaw(np.ones(shape))
+    cb.close()
     cell = _cell(pkg, shape, pkg.PC_GREEN_JACOBI)
     with pytest.raises(pkg.JfftError) as e:
         cell.solve_newton(SHEAR)
