@@ -312,6 +312,42 @@ jfft_status jfft_powerlaw_tangent(jfft_cell_t cell, const double *macro_strain, 
 jfft_status jfft_powerlaw_jacobi_diag(jfft_cell_t cell, const double *macro_strain,
                                       const double *uk_dev, double *diag_dev);
 
+/* ---- Phase-field topology optimisation (Sec. 4, eq. aim_fun and eq.
+   lin_system_topopt) ------------------------------------------------------
+   The handle is a group of 3 2D cells with JFFT_ELEM_TRI (jfft_create_batch
+   with batch 3, then jfft_set_element; else JFFT_E_INVALID); cell g holds the
+   unit load case e_g (Mandel) on the common density rho_dev [N] (device,
+   node-sampled: pixel e takes rho of its lowest node; C = rho C0 with Lame
+   constants lambda0, mu0).
+   jfft_topopt_eval: f = sum_g ||sigma_bar_g - t_g||^2 + f_pf with targets t
+   (host, 9 values, row g = t_g in Mandel form) and f_pf = eta int |grad
+   rho|^2 + (1/eta) int rho^2 (1 - rho)^2 (rho linear on the triangles for
+   the gradient term, the double well by nodal quadrature).  Solves the three
+   load cases from u = 0 to relative residual tol (at most maxit iterations,
+   the cell's stop rule and precision), then writes f_out[3] = (f, f_sigma,
+   f_pf) (host), grad_dev [N] (device; f_sigma's part by the mutual-energy
+   identity, no adjoint solve) and iters[3] (host, may be NULL).  Returns the
+   solve's status (JFFT_E_NOT_CONVERGED, JFFT_E_BREAKDOWN) if a solve fails.
+   jfft_topopt_lbfgs: projected L-BFGS on [0, 1] from rho_dev (in: start, out:
+   the last accepted iterate), memory m (1..64), at most n_iter steps: bound
+   variables held by their gradient are frozen for a step; the trial
+   clip(rho + alpha d), alpha halved from 1 (at most 30 times) until
+   f(trial) <= f + 1e-4 g . (trial - rho); a pair (s, y) is kept when
+   y.s > 1e-12 |s| |y|; the first direction is -g scaled to a largest entry
+   of 0.1, later ones use H0 = s.y / y.y of the newest pair; stops early when
+   no halving decreases f.  Host outputs (each may be NULL): f_hist and
+   gnorm_hist (max |g|) of the accepted iterates [n_iter + 1], iters_hist
+   [(n_iter + 1) * 3] (the three solves' iterations), *steps, *evals
+   (objective evaluations).  The handle allocates (6 + 2 m) N doubles on
+   first use (freed with the handle). */
+jfft_status jfft_topopt_eval(jfft_cell_t group, const double *rho_dev, double lambda0, double mu0,
+                             const double *targets, double eta, double tol, int maxit,
+                             double *f_out, double *grad_dev, int *iters);
+jfft_status jfft_topopt_lbfgs(jfft_cell_t group, double *rho_dev, double lambda0, double mu0,
+                              const double *targets, double eta, double tol, int maxit,
+                              int n_iter, int m, double *f_hist, double *gnorm_hist,
+                              int *iters_hist, int *steps, int *evals);
+
 void jfft_destroy_cell(jfft_cell_t cell);
 const char *jfft_last_error(void);
 const char *jfft_version(void);

@@ -86,6 +86,11 @@ _SIGS = {
     "jfft_powerlaw_force": (C.c_int, [_vp, _dp, _vp, _vp]),
     "jfft_powerlaw_tangent": (C.c_int, [_vp, _dp, _vp, _vp, _vp]),
     "jfft_powerlaw_jacobi_diag": (C.c_int, [_vp, _dp, _vp, _vp]),
+    "jfft_topopt_eval": (C.c_int, [_vp, _vp, C.c_double, C.c_double, _dp, C.c_double, C.c_double,
+                                   C.c_int, _dp, _vp, C.POINTER(C.c_int)]),
+    "jfft_topopt_lbfgs": (C.c_int, [_vp, _vp, C.c_double, C.c_double, _dp, C.c_double, C.c_double,
+                                    C.c_int, C.c_int, C.c_int, _dp, _dp, C.POINTER(C.c_int),
+                                    C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "jfft_destroy_cell": (None, [_vp]),
     "jfft_last_error": (C.c_char_p, []),
     "jfft_version": (C.c_char_p, []),
@@ -409,6 +414,39 @@ class Cell:
         out = self.torch.empty_like(ukt)
         _check(self._lib.jfft_powerlaw_jacobi_diag(self._h, m, _ptr(ukt), _ptr(out)))
         return out
+
+    # ------------------------ phase-field topology optimisation (Sec. 4)
+    def topopt_eval(self, rho, targets, eta=0.01, tol=1e-8, maxit=20000, lame0=(2 / 3, 0.5)):
+        """Group of 3 triangle cells: f = (f, f_sigma, f_pf), gradient [ny, nx]
+        (device tensor) and the three solves' iterations."""
+        r = self._dev(rho, self.shape)
+        grad = self.torch.empty_like(r)
+        t = np.ascontiguousarray(np.asarray(targets, dtype=np.float64).reshape(9))
+        f = (C.c_double * 3)()
+        its = (C.c_int * 3)()
+        _check(self._lib.jfft_topopt_eval(self._h, _ptr(r), float(lame0[0]), float(lame0[1]),
+                                          t.ctypes.data_as(_dp), float(eta), float(tol),
+                                          int(maxit), f, _ptr(grad), its))
+        return np.array(f[:]), grad, list(its)
+
+    def topopt_lbfgs(self, rho0, targets, n_iter, eta=0.01, tol=1e-8, maxit=20000, m=10,
+                     lame0=(2 / 3, 0.5)):
+        """Projected L-BFGS from rho0.  Returns (rho device tensor, dict with
+        f, gnorm, iters per accepted iterate, steps, evals)."""
+        r = self._dev(rho0, self.shape).clone()
+        t = np.ascontiguousarray(np.asarray(targets, dtype=np.float64).reshape(9))
+        fh = (C.c_double * (n_iter + 1))()
+        gh = (C.c_double * (n_iter + 1))()
+        ih = (C.c_int * (3 * (n_iter + 1)))()
+        steps, evals = C.c_int(0), C.c_int(0)
+        _check(self._lib.jfft_topopt_lbfgs(self._h, _ptr(r), float(lame0[0]), float(lame0[1]),
+                                           t.ctypes.data_as(_dp), float(eta), float(tol),
+                                           int(maxit), int(n_iter), int(m), fh, gh, ih,
+                                           C.byref(steps), C.byref(evals)))
+        k = int(steps.value)
+        return r, {"f": list(fh[:k + 1]), "gnorm": list(gh[:k + 1]),
+                   "iters": [list(ih[3 * i:3 * i + 3]) for i in range(k + 1)], "steps": k,
+                   "evals": int(evals.value)}
 
     def enable_history(self, cap):
         _check(self._lib.jfft_enable_history(self._h, int(cap)))

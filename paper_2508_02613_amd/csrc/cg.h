@@ -430,4 +430,71 @@ __global__ void k_axpy_f32_to_f64(const float *c, double *u, long long n, const 
     u[i] += scale * (double)c[i];
 }
 
+// ------------------------------------------- projected L-BFGS on [0, 1] ----
+// A variable held at a bound by its gradient (x = 0 with g > 0, x = 1 with
+// g < 0) is frozen for the step.
+__device__ __forceinline__ bool topo_free(double x, double g) {
+  return !((x <= 0.0 && g > 0.0) || (x >= 1.0 && g < 0.0));
+}
+
+// q = g on the free variables, 0 on the frozen ones.
+__global__ void k_topo_free(const double *x, const double *g, double *q, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    q[i] = topo_free(x[i], g[i]) ? g[i] : 0.0;
+}
+
+// d = -z on the free variables, 0 on the frozen ones.
+__global__ void k_topo_dir(const double *x, const double *g, const double *z, double *d,
+                           long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    d[i] = topo_free(x[i], g[i]) ? -z[i] : 0.0;
+}
+
+// xt = clip(x + alpha d, 0, 1), st = xt - x.
+__global__ void k_topo_trial(const double *x, const double *d, double alpha, double *xt,
+                             double *st, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double v = fmin(1.0, fmax(0.0, x[i] + alpha * d[i]));
+    xt[i] = v;
+    st[i] = v - x[i];
+  }
+}
+
+// y = a x + b y (a, b host scalars).
+__global__ void k_axpby(double a, const double *x, double b, double *y, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+
+// out = a - b.
+__global__ void k_sub(const double *a, const double *b, double *out, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = a[i] - b[i];
+}
+
+// Per-block maxima of |x|.
+__global__ void k_absmax(const double *x, long long n, double *part) {
+  __shared__ double sm[4];
+  double m = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    m = fmax(m, fabs(x[i]));
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sm[wid] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) r = fmax(r, sm[w]);
+    part[blockIdx.x] = r;
+  }
+}
+
+
 }  // namespace jfft

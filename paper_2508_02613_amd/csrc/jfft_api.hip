@@ -171,6 +171,11 @@ struct jfft_cell_s {
   double *uk = nullptr;
   float *uk32 = nullptr;  // FP32 copy of uk for the inner solves of a mixed-precision cell
 
+  // topology optimisation (three-cell 2D triangle groups): L-BFGS vectors,
+  // allocated on first use and owned by the handle
+  double *topo = nullptr;
+  int topo_m = 0;
+
   // captured iteration chunks
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // [0] FP64, [1] FP32 inner
   int gexec_iters[2] = {0, 0};
@@ -206,6 +211,7 @@ struct jfft_cell_s {
     if (ws_owned && ws) (void)hipFree(ws);
     if (uk) (void)hipFree(uk);
     if (uk32) (void)hipFree(uk32);
+    if (topo) (void)hipFree(topo);
     if (st_h) (void)hipHostFree(st_h);
     if (small_h) (void)hipHostFree(small_h);
   }
@@ -1018,7 +1024,10 @@ void tri_stencil(jfft_cell_s *c, double lam, double mu) {
     }
 }
 
-jfft_status set_material_impl(jfft_cell_s *c, const double *E_dev, double lam, double mu) {
+// E_dev holds the moduli of the cells one after another ([B][N]), or with
+// broadcast one field for every cell of the group.
+jfft_status set_material_impl(jfft_cell_s *c, const double *E_dev, double lam, double mu,
+                              bool broadcast = false) {
   if (!E_dev) return fail(JFFT_E_INVALID, "E_dev is NULL");
   if (!(mu > 0.0) || !(lam + 2.0 * mu / c->dim > 0.0) || !std::isfinite(lam) || !std::isfinite(mu))
     return fail(JFFT_E_INVALID, "Lame constants must satisfy mu > 0 and lambda + 2 mu / d > 0");
@@ -1035,7 +1044,7 @@ jfft_status set_material_impl(jfft_cell_s *c, const double *E_dev, double lam, d
   c->mu = mu;
   if (c->elem == JFFT_ELEM_TRI) tri_stencil(c, lam, mu);
   const long long N = c->g.N;
-  const long long es = (long long)sizeof(double) * N;  // caller's layout [B][N]
+  const long long es = broadcast ? 0 : (long long)sizeof(double) * N;  // caller's layout
   const int nb = vec_blocks(N);
   LAUNCH(c, KID_SETUP, k_check_E<<<dim3(nb, c->B), 256, 0, c->stream>>>(E_dev, es, N, c->partA, c->cs));
   TRY(reduce_to(c, c->partA, nb, 1, 0, c->B));
@@ -1091,7 +1100,8 @@ jfft_status post_process(jfft_cell_s *c, double *u_out, double *sigma_dev, doubl
   LAUNCH(c, KID_STRESS, k_stress<double><<<dim3(nbs, Bc), 256, 0, c->stream>>>(c->u, c->E, c->macro, c->lam, c->mu, c->g.w, c->g.ihx, c->g.ihy, c->g.ihz, d, c->g.nx, c->g.ny, c->g.nz, N, sigma_dev, c->partB, c->cs, sig_cs, tri));
   TRY(reduce_to(c, c->partB, nbs, ds, 16, Bc));
   // u to the caller's [B][d][N] array
-  LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->u, c->cs, u_out, (long long)sizeof(double) * nd, nd));
+  if (u_out)  // internal callers read the fluctuations from the workspace
+    LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->u, c->cs, u_out, (long long)sizeof(double) * nd, nd));
   TRY(fetch_small(c));
   for (int i = 0; i < Bc; ++i)
     for (int r = 0; r < ds; ++r) sigma_bar[(size_t)i * ds + r] = c->small_h[(size_t)i * kSmall + 16 + r] / c->g.vol;
@@ -1132,7 +1142,7 @@ jfft_status solve_impl(jfft_cell_s *c, const double *macros_h, double tol, int m
                        const double *u0, double *u_out, double *sigma_dev, double *sigma_bar,
                        jfft_report *reps) {
   if (!c->has_material) return fail(JFFT_E_NO_MATERIAL, "set the material first");
-  if (!macros_h || !u_out || !sigma_bar) return fail(JFFT_E_INVALID, "NULL macro_strain, u_dev or sigma_bar");
+  if (!macros_h || !sigma_bar) return fail(JFFT_E_INVALID, "NULL macro_strain or sigma_bar");
   if (!(tol > 0.0) || maxit < 0) return fail(JFFT_E_INVALID, "tol must be > 0 and maxit >= 0");
   const long long N = c->g.N;
   const int d = c->dim;
@@ -1378,6 +1388,206 @@ jfft_status nl_operator_prep(jfft_cell_s *c, const double *macro_h, const double
   return JFFT_OK;
 }
 
+// ------------------------------------------ phase-field topology optimisation
+// The workload of eq. aim_fun / eq. lin_system_topopt: a group of three 2D
+// triangle cells holds the unit load cases e_g on one density rho (E = rho,
+// C = rho C0); f = sum_g ||sigma_bar_g - t_g||^2 + f_pf(rho), its gradient
+// from the three solutions (mutual-energy identity) and the phase field, and
+// a projected L-BFGS on [0, 1] driving it.
+
+jfft_status topo_check(jfft_cell_s *c) {
+  if (c->dim != 2 || c->B != 3 || c->elem != JFFT_ELEM_TRI)
+    return fail(JFFT_E_INVALID, "topology optimisation needs a group of 3 2D triangle cells");
+  return JFFT_OK;
+}
+
+double dev_dot(jfft_cell_s *c, const double *a, const double *b, long long n, jfft_status *st) {
+  const int nb = vec_blocks(n);
+  k_dot<double><<<dim3(nb, 1), 256, 0, c->stream>>>(a, b, n, c->partA, c->cs);
+  k_reduce_groups<<<1, CTRL_THREADS, 0, c->stream>>>(c->partA, nb, 1, c->small, c->cs);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(c->small_h, c->small, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) *st = fail(JFFT_E_HIP, std::string("dot: ") + hipGetErrorString(e));
+  return c->small_h[0];
+}
+
+double dev_absmax(jfft_cell_s *c, const double *x, long long n, jfft_status *st) {
+  const int nb = vec_blocks(n);
+  k_absmax<<<nb, 256, 0, c->stream>>>(x, n, c->partA);
+  std::vector<double> h(nb);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), c->partA, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) *st = fail(JFFT_E_HIP, std::string("absmax: ") + hipGetErrorString(e));
+  double m = 0.0;
+  for (double v : h) m = std::max(m, v);
+  return m;
+}
+
+// f = (f, f_sigma, f_pf), grad [N] (device), iters[3] of the three solves.
+jfft_status topo_eval_impl(jfft_cell_s *c, const double *rho, double lam0, double mu0,
+                           const double *t, double eta, double tol, int maxit, double *f,
+                           double *grad, int *iters) {
+  TRY(topo_check(c));
+  if (!rho || !t || !f || !grad) return fail(JFFT_E_INVALID, "NULL argument");
+  if (!(eta > 0.0)) return fail(JFFT_E_INVALID, "eta must be > 0");
+  TRY(set_material_impl(c, rho, lam0, mu0, true));
+  const double macros[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  double sb[9];
+  jfft_report reps[3];
+  const jfft_status st = solve_impl(c, macros, tol, maxit, nullptr, nullptr, nullptr, sb, reps);
+  if (st != JFFT_OK) return st;
+  const GridDev &g = c->g;
+  const long long N = g.N;
+  TopoW W{};
+  double fs = 0.0;
+  for (int gm = 0; gm < 3; ++gm)
+    for (int a = 0; a < 3; ++a) {
+      const double d = sb[gm * 3 + a] - t[gm * 3 + a];
+      fs += d * d;
+      W.w[gm][a] = 2.0 * d / g.vol;
+    }
+  const unsigned nb = (unsigned)((N + 255) / 256);
+  const double A = 2.0 * g.w, cell = 4.0 * g.w;  // triangle area, pixel area
+  LAUNCH(c, KID_VEC, k_topo_sens_tri<<<nb, 256, 0, c->stream>>>(c->u, c->cs, W, lam0, mu0, A, g.ihx, g.ihy, g.nx, g.ny, N, grad));
+  LAUNCH(c, KID_VEC, k_topo_pf_tri<<<nb, 256, 0, c->stream>>>(rho, eta, A, cell, g.ihx, g.ihy, g.nx, g.ny, N, grad, c->partB));
+  TRY(reduce_to(c, c->partB, nb, 1, 0, 1));
+  HIP_TRY(hipMemcpyAsync(c->small_h, c->small, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const double fpf = c->small_h[0];
+  f[0] = fs + fpf;
+  f[1] = fs;
+  f[2] = fpf;
+  if (iters)
+    for (int i = 0; i < 3; ++i) iters[i] = reps[i].iters;
+  return JFFT_OK;
+}
+
+jfft_status topo_lbfgs_impl(jfft_cell_s *c, double *x, double lam0, double mu0, const double *t,
+                            double eta, double tol, int maxit, int n_iter, int m, double *f_hist,
+                            double *gnorm_hist, int *iters_hist, int *steps_out, int *evals_out) {
+  TRY(topo_check(c));
+  if (!x || !t) return fail(JFFT_E_INVALID, "NULL argument");
+  if (n_iter < 0 || m < 1 || m > 64) return fail(JFFT_E_INVALID, "need n_iter >= 0 and 1 <= m <= 64");
+  const long long n = c->g.N;
+  // vectors: g, gt, q (also z), d, xt, st, then m slots of s and of y
+  const long long nvec = 6 + 2 * (long long)m;
+  if (!c->topo || c->topo_m < m) {
+    if (c->topo) {
+      (void)hipStreamSynchronize(c->stream);
+      (void)hipFree(c->topo);
+      c->topo = nullptr;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(double) * n * nvec);
+    if (e != hipSuccess) return fail(JFFT_E_OOM, std::string("hipMalloc L-BFGS vectors: ") + hipGetErrorString(e));
+    c->topo = static_cast<double *>(p);
+    c->topo_m = m;
+  }
+  double *g = c->topo, *gt = g + n, *q = gt + n, *d = q + n, *xt = d + n, *st = xt + n;
+  double *S = st + n, *Y = S + (long long)m * n;
+  const int nb = vec_blocks(n);
+  jfft_status err = JFFT_OK;
+  // x on the box
+  LAUNCH(c, KID_VEC, k_topo_trial<<<nb, 256, 0, c->stream>>>(x, x, 0.0, xt, st, n));
+  LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, 1), 256, 0, c->stream>>>(xt, 0, x, 0, n));
+  double fv[3];
+  int its[3];
+  TRY(topo_eval_impl(c, x, lam0, mu0, t, eta, tol, maxit, fv, g, its));
+  int evals = 1, steps = 0;
+  auto record = [&](int k, double fk, const double *gk, const int *ik) {
+    if (f_hist) f_hist[k] = fk;
+    if (gnorm_hist) gnorm_hist[k] = dev_absmax(c, gk, n, &err);
+    if (iters_hist)
+      for (int i = 0; i < 3; ++i) iters_hist[3 * k + i] = ik[i];
+  };
+  double f = fv[0];
+  record(0, f, g, its);
+  TRY(err);
+  // pair history (oldest first): slot index, 1 / y.s, s.y, y.y
+  std::vector<int> slot;
+  std::vector<double> rinv, sy_h, yy_h;
+  const double c1 = 1e-4;
+  const int max_halvings = 30;
+  for (int k = 0; k < n_iter; ++k) {
+    LAUNCH(c, KID_VEC, k_topo_free<<<nb, 256, 0, c->stream>>>(x, g, q, n));
+    const int np = (int)slot.size();
+    std::vector<double> al(np);
+    for (int i = np - 1; i >= 0; --i) {
+      const double *si = S + (long long)slot[i] * n, *yi = Y + (long long)slot[i] * n;
+      al[i] = rinv[i] * dev_dot(c, si, q, n, &err);
+      LAUNCH(c, KID_VEC, k_axpby<<<nb, 256, 0, c->stream>>>(-al[i], yi, 1.0, q, n));
+    }
+    TRY(err);
+    double h0;
+    if (np)
+      h0 = sy_h[np - 1] / yy_h[np - 1];
+    else
+      h0 = 0.1 / std::max(dev_absmax(c, q, n, &err), 1e-300);
+    TRY(err);
+    LAUNCH(c, KID_VEC, k_axpby<<<nb, 256, 0, c->stream>>>(0.0, q, h0, q, n));  // z = h0 q (in q)
+    for (int i = 0; i < np; ++i) {
+      const double *si = S + (long long)slot[i] * n, *yi = Y + (long long)slot[i] * n;
+      const double b = rinv[i] * dev_dot(c, yi, q, n, &err);
+      LAUNCH(c, KID_VEC, k_axpby<<<nb, 256, 0, c->stream>>>(al[i] - b, si, 1.0, q, n));
+    }
+    TRY(err);
+    LAUNCH(c, KID_VEC, k_topo_dir<<<nb, 256, 0, c->stream>>>(x, g, q, d, n));
+    double alpha = 1.0, ft = 0.0, gs = 0.0;
+    bool accepted = false;
+    for (int h = 0; h < max_halvings; ++h) {
+      LAUNCH(c, KID_VEC, k_topo_trial<<<nb, 256, 0, c->stream>>>(x, d, alpha, xt, st, n));
+      gs = dev_dot(c, g, st, n, &err);
+      TRY(err);
+      if (gs < 0.0) {
+        TRY(topo_eval_impl(c, xt, lam0, mu0, t, eta, tol, maxit, fv, gt, its));
+        ++evals;
+        ft = fv[0];
+        if (ft <= f + c1 * gs) {
+          accepted = true;
+          break;
+        }
+      }
+      alpha *= 0.5;
+    }
+    if (!accepted) break;
+    // candidate pair s = st, y = gt - g (y formed in q, free once d exists);
+    // kept in the next free slot, or in place of the oldest pair
+    LAUNCH(c, KID_VEC, k_sub<<<nb, 256, 0, c->stream>>>(gt, g, q, n));
+    const double sy = dev_dot(c, st, q, n, &err);
+    const double ss = dev_dot(c, st, st, n, &err);
+    const double yy = dev_dot(c, q, q, n, &err);
+    TRY(err);
+    if (sy > 1e-12 * std::sqrt(ss) * std::sqrt(yy)) {
+      const int cand = np < m ? np : slot[0];
+      double *sc = S + (long long)cand * n, *yc = Y + (long long)cand * n;
+      LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, 1), 256, 0, c->stream>>>(st, 0, sc, 0, n));
+      LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, 1), 256, 0, c->stream>>>(q, 0, yc, 0, n));
+      if (np == m) {
+        slot.erase(slot.begin());
+        rinv.erase(rinv.begin());
+        sy_h.erase(sy_h.begin());
+        yy_h.erase(yy_h.begin());
+      }
+      slot.push_back(cand);
+      rinv.push_back(1.0 / sy);
+      sy_h.push_back(sy);
+      yy_h.push_back(yy);
+    }
+    LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, 1), 256, 0, c->stream>>>(xt, 0, x, 0, n));
+    std::swap(g, gt);
+    f = ft;
+    ++steps;
+    record(steps, f, g, its);
+    TRY(err);
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (steps_out) *steps_out = steps;
+  if (evals_out) *evals_out = evals;
+  return JFFT_OK;
+}
+
 bool supported_length(int n) {
   if (n < 2 || n > 512 || n % 2) return false;
   FftPlan p;
@@ -1519,6 +1729,7 @@ jfft_status jfft_solve(jfft_cell_t c, const double *macro_strain, double tol, in
                        jfft_report *report) {
   if (!c) return fail(JFFT_E_INVALID, "NULL cell");
   if (c->B != 1) return fail(JFFT_E_INVALID, "batched handle: use jfft_solve_batch");
+  if (!u_dev) return fail(JFFT_E_INVALID, "NULL u_dev");
   return solve_impl(c, macro_strain, tol, maxit, u0_dev, u_dev, sigma_dev, sigma_bar, report);
 }
 
@@ -1526,6 +1737,7 @@ jfft_status jfft_solve_batch(jfft_cell_t c, const double *macro_strains, double 
                              const double *u0_dev, double *u_dev, double *sigma_dev,
                              double *sigma_bars, jfft_report *reports) {
   if (!c) return fail(JFFT_E_INVALID, "NULL cell");
+  if (!u_dev) return fail(JFFT_E_INVALID, "NULL u_dev");
   return solve_impl(c, macro_strains, tol, maxit, u0_dev, u_dev, sigma_dev, sigma_bars, reports);
 }
 
@@ -1744,6 +1956,22 @@ jfft_status jfft_powerlaw_jacobi_diag(jfft_cell_t c, const double *macro_strain,
     TRY(run_alg2(c, diag_dev, 1));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return JFFT_OK;
+}
+
+jfft_status jfft_topopt_eval(jfft_cell_t c, const double *rho_dev, double lambda0, double mu0,
+                             const double *targets, double eta, double tol, int maxit,
+                             double *f_out, double *grad_dev, int *iters) {
+  if (!c) return fail(JFFT_E_INVALID, "NULL cell");
+  return topo_eval_impl(c, rho_dev, lambda0, mu0, targets, eta, tol, maxit, f_out, grad_dev, iters);
+}
+
+jfft_status jfft_topopt_lbfgs(jfft_cell_t c, double *rho_dev, double lambda0, double mu0,
+                              const double *targets, double eta, double tol, int maxit,
+                              int n_iter, int m, double *f_hist, double *gnorm_hist,
+                              int *iters_hist, int *steps, int *evals) {
+  if (!c) return fail(JFFT_E_INVALID, "NULL cell");
+  return topo_lbfgs_impl(c, rho_dev, lambda0, mu0, targets, eta, tol, maxit, n_iter, m, f_hist,
+                         gnorm_hist, iters_hist, steps, evals);
 }
 
 void jfft_destroy_cell(jfft_cell_t c) {

@@ -1693,4 +1693,100 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// ------------------------------------- topology optimisation (2D triangles) ----
+// Weights of the objective's gradient: W[g][a] = 2 (sigma_bar_g - t_g)_a / |Y|.
+struct TopoW {
+  double w[3][3];
+};
+
+// Gradient of f_sigma = sum_g ||sigma_bar_g - t_g||^2 (eq. aim_fun) in the
+// pixel densities, for a group of three cells holding the unit load cases
+// e_g on the same density (E = rho, C = rho C0).  By the mutual-energy
+// identity, d (sigma_bar_g)_a / d rho_e = (1/|Y|) sum over the pixel's two
+// triangles of A eps_a^T C0 eps_g with eps_g = e_g + B u_g, so no adjoint
+// solve is needed: grad_e = sum_t A sum_g (sum_a W[g][a] eps_a)^T C0 eps_g.
+// One thread per pixel; u of cell g at u + g * cs bytes.
+__global__ void __launch_bounds__(256)
+    k_topo_sens_tri(const double *u, long long cs, TopoW W, double lam, double mu, double A,
+                    double ihx, double ihy, int nx, int ny, long long N, double *grad) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N) return;
+  const int x = (int)(e % nx), y = (int)(e / nx);
+  const int x1 = x + 1 == nx ? 0 : x + 1, y1 = y + 1 == ny ? 0 : y + 1;
+  const long long nd[4] = {(long long)x + (long long)nx * y, (long long)x1 + (long long)nx * y,
+                           (long long)x + (long long)nx * y1, (long long)x1 + (long long)nx * y1};
+  const double r2 = 0.70710678118654752440;
+  double eps[3][2][3];  // [load case][triangle][Mandel]
+  for (int g = 0; g < 3; ++g) {
+    const double *ug = cshift(u, g, cs);
+    double v[2][4];
+    for (int c = 0; c < 4; ++c) {
+      v[0][c] = ug[nd[c]];
+      v[1][c] = ug[N + nd[c]];
+    }
+    // T0 = corners (0, 1, 2), T1 = corners (3, 2, 1) (elem_tri2)
+    const double e11[2] = {(v[0][1] - v[0][0]) * ihx, (v[0][3] - v[0][2]) * ihx};
+    const double e22[2] = {(v[1][2] - v[1][0]) * ihy, (v[1][3] - v[1][1]) * ihy};
+    const double g12[2] = {(v[0][2] - v[0][0]) * ihy + (v[1][1] - v[1][0]) * ihx,
+                           (v[0][3] - v[0][1]) * ihy + (v[1][3] - v[1][2]) * ihx};
+    for (int t = 0; t < 2; ++t) {
+      eps[g][t][0] = (g == 0 ? 1.0 : 0.0) + e11[t];
+      eps[g][t][1] = (g == 1 ? 1.0 : 0.0) + e22[t];
+      eps[g][t][2] = (g == 2 ? 1.0 : 0.0) + g12[t] * r2;
+    }
+  }
+  double acc = 0.0;
+  for (int t = 0; t < 2; ++t)
+    for (int g = 0; g < 3; ++g) {
+      double v[3] = {0, 0, 0};
+      for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 3; ++k) v[k] += W.w[g][a] * eps[a][t][k];
+      const double *eg = eps[g][t];
+      // v^T C0 eg, C0 = [[lam + 2 mu, lam, 0], [lam, lam + 2 mu, 0], [0, 0, 2 mu]] (Mandel)
+      acc += v[0] * ((lam + 2 * mu) * eg[0] + lam * eg[1]) +
+             v[1] * (lam * eg[0] + (lam + 2 * mu) * eg[1]) + v[2] * (2 * mu * eg[2]);
+    }
+  grad[e] = A * acc;
+}
+
+// Phase-field term f_pf = eta int |grad rho|^2 + (1/eta) int rho^2 (1 - rho)^2
+// with rho linear on the triangles of elem_tri2 and the double well by
+// nodal quadrature (one pixel area per node).  One thread per node I: its
+// gradient entry (added to grad) sums the corner-o terms 2 eta A grad N_o .
+// grad rho_T of the triangles T of the four pixels I - o; its energy share
+// is pixel I's two triangles and node I's well.  part: per-block energy.
+__global__ void __launch_bounds__(256)
+    k_topo_pf_tri(const double *rho, double eta, double A, double cell, double ihx, double ihy,
+                  int nx, int ny, long long N, double *grad, double *part) {
+  __shared__ double red[4];
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double en = 0.0;
+  if (i < N) {
+    const int x = (int)(i % nx), y = (int)(i / nx);
+    double dg = 0.0;
+    for (int o = 0; o < 4; ++o) {
+      const int ox = o & 1, oy = o >> 1;
+      const int ex = x - ox < 0 ? nx - 1 : x - ox, ey = y - oy < 0 ? ny - 1 : y - oy;
+      const int ex1 = ex + 1 == nx ? 0 : ex + 1, ey1 = ey + 1 == ny ? 0 : ey + 1;
+      const double r0 = rho[(long long)ex + (long long)nx * ey];
+      const double r1 = rho[(long long)ex1 + (long long)nx * ey];
+      const double r2v = rho[(long long)ex + (long long)nx * ey1];
+      const double r3 = rho[(long long)ex1 + (long long)nx * ey1];
+      const double t0x = (r1 - r0) * ihx, t0y = (r2v - r0) * ihy;  // T0 = (0, 1, 2)
+      const double t1x = (r3 - r2v) * ihx, t1y = (r3 - r1) * ihy;  // T1 = (3, 2, 1)
+      // grad N_o on T0 and T1 (zero where corner o is not a vertex)
+      const double n0x[4] = {-ihx, ihx, 0.0, 0.0}, n0y[4] = {-ihy, 0.0, ihy, 0.0};
+      const double n1x[4] = {0.0, 0.0, -ihx, ihx}, n1y[4] = {0.0, -ihy, 0.0, ihy};
+      dg += 2.0 * eta * A * (n0x[o] * t0x + n0y[o] * t0y + n1x[o] * t1x + n1y[o] * t1y);
+      if (o == 0) en = eta * A * (t0x * t0x + t0y * t0y + t1x * t1x + t1y * t1y);
+    }
+    const double r = rho[i];
+    en += cell / eta * r * r * (1.0 - r) * (1.0 - r);
+    grad[i] += dg + cell / eta * 2.0 * r * (1.0 - r) * (1.0 - 2.0 * r);
+  }
+  const double s = block_sum<256>(en, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+
 }  // namespace jfft
