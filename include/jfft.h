@@ -338,15 +338,19 @@ jfft_status jfft_powerlaw_jacobi_diag(jfft_cell_t cell, const double *macro_stra
    no halving decreases f.  Host outputs (each may be NULL): f_hist and
    gnorm_hist (max |g|) of the accepted iterates [n_iter + 1], iters_hist
    [(n_iter + 1) * 3] (the three solves' iterations), *steps, *evals
-   (objective evaluations).  The handle allocates (6 + 2 m) N doubles on
-   first use (freed with the handle). */
+   (objective evaluations), *pcg_total (PCG iterations of every evaluation,
+   rejected trials included).  The handle allocates (6 + 2 m) N doubles on
+   first use (freed with the handle).  Mixed-precision groups follow the
+   refinement loop of jfft_solve; once the density has exact voids their
+   FP32 inner solves can stall short of the refinement's tolerance (then
+   JFFT_E_NOT_CONVERGED): use FP64 groups for whole optimisation runs. */
 jfft_status jfft_topopt_eval(jfft_cell_t group, const double *rho_dev, double lambda0, double mu0,
                              const double *targets, double eta, double tol, int maxit,
                              double *f_out, double *grad_dev, int *iters);
 jfft_status jfft_topopt_lbfgs(jfft_cell_t group, double *rho_dev, double lambda0, double mu0,
                               const double *targets, double eta, double tol, int maxit,
                               int n_iter, int m, double *f_hist, double *gnorm_hist,
-                              int *iters_hist, int *steps, int *evals);
+                              int *iters_hist, int *steps, int *evals, long long *pcg_total);
 
 void jfft_destroy_cell(jfft_cell_t cell);
 const char *jfft_last_error(void);

@@ -90,7 +90,8 @@ _SIGS = {
                                    C.c_int, _dp, _vp, C.POINTER(C.c_int)]),
     "jfft_topopt_lbfgs": (C.c_int, [_vp, _vp, C.c_double, C.c_double, _dp, C.c_double, C.c_double,
                                     C.c_int, C.c_int, C.c_int, _dp, _dp, C.POINTER(C.c_int),
-                                    C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+                                    C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                    C.POINTER(C.c_longlong)]),
     "jfft_destroy_cell": (None, [_vp]),
     "jfft_last_error": (C.c_char_p, []),
     "jfft_version": (C.c_char_p, []),
@@ -438,15 +439,15 @@ class Cell:
         fh = (C.c_double * (n_iter + 1))()
         gh = (C.c_double * (n_iter + 1))()
         ih = (C.c_int * (3 * (n_iter + 1)))()
-        steps, evals = C.c_int(0), C.c_int(0)
+        steps, evals, total = C.c_int(0), C.c_int(0), C.c_longlong(0)
         _check(self._lib.jfft_topopt_lbfgs(self._h, _ptr(r), float(lame0[0]), float(lame0[1]),
                                            t.ctypes.data_as(_dp), float(eta), float(tol),
                                            int(maxit), int(n_iter), int(m), fh, gh, ih,
-                                           C.byref(steps), C.byref(evals)))
+                                           C.byref(steps), C.byref(evals), C.byref(total)))
         k = int(steps.value)
         return r, {"f": list(fh[:k + 1]), "gnorm": list(gh[:k + 1]),
                    "iters": [list(ih[3 * i:3 * i + 3]) for i in range(k + 1)], "steps": k,
-                   "evals": int(evals.value)}
+                   "evals": int(evals.value), "pcg_total": int(total.value)}
 
     def enable_history(self, cap):
         _check(self._lib.jfft_enable_history(self._h, int(cap)))

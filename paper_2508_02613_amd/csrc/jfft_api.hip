@@ -1466,7 +1466,8 @@ jfft_status topo_eval_impl(jfft_cell_s *c, const double *rho, double lam0, doubl
 
 jfft_status topo_lbfgs_impl(jfft_cell_s *c, double *x, double lam0, double mu0, const double *t,
                             double eta, double tol, int maxit, int n_iter, int m, double *f_hist,
-                            double *gnorm_hist, int *iters_hist, int *steps_out, int *evals_out) {
+                            double *gnorm_hist, int *iters_hist, int *steps_out, int *evals_out,
+                            long long *pcg_total) {
   TRY(topo_check(c));
   if (!x || !t) return fail(JFFT_E_INVALID, "NULL argument");
   if (n_iter < 0 || m < 1 || m > 64) return fail(JFFT_E_INVALID, "need n_iter >= 0 and 1 <= m <= 64");
@@ -1496,6 +1497,7 @@ jfft_status topo_lbfgs_impl(jfft_cell_s *c, double *x, double lam0, double mu0, 
   int its[3];
   TRY(topo_eval_impl(c, x, lam0, mu0, t, eta, tol, maxit, fv, g, its));
   int evals = 1, steps = 0;
+  long long total = (long long)its[0] + its[1] + its[2];
   auto record = [&](int k, double fk, const double *gk, const int *ik) {
     if (f_hist) f_hist[k] = fk;
     if (gnorm_hist) gnorm_hist[k] = dev_absmax(c, gk, n, &err);
@@ -1543,6 +1545,7 @@ jfft_status topo_lbfgs_impl(jfft_cell_s *c, double *x, double lam0, double mu0, 
       if (gs < 0.0) {
         TRY(topo_eval_impl(c, xt, lam0, mu0, t, eta, tol, maxit, fv, gt, its));
         ++evals;
+        total += (long long)its[0] + its[1] + its[2];
         ft = fv[0];
         if (ft <= f + c1 * gs) {
           accepted = true;
@@ -1585,6 +1588,7 @@ jfft_status topo_lbfgs_impl(jfft_cell_s *c, double *x, double lam0, double mu0, 
   HIP_TRY(hipStreamSynchronize(c->stream));
   if (steps_out) *steps_out = steps;
   if (evals_out) *evals_out = evals;
+  if (pcg_total) *pcg_total = total;
   return JFFT_OK;
 }
 
@@ -1968,10 +1972,10 @@ jfft_status jfft_topopt_eval(jfft_cell_t c, const double *rho_dev, double lambda
 jfft_status jfft_topopt_lbfgs(jfft_cell_t c, double *rho_dev, double lambda0, double mu0,
                               const double *targets, double eta, double tol, int maxit,
                               int n_iter, int m, double *f_hist, double *gnorm_hist,
-                              int *iters_hist, int *steps, int *evals) {
+                              int *iters_hist, int *steps, int *evals, long long *pcg_total) {
   if (!c) return fail(JFFT_E_INVALID, "NULL cell");
   return topo_lbfgs_impl(c, rho_dev, lambda0, mu0, targets, eta, tol, maxit, n_iter, m, f_hist,
-                         gnorm_hist, iters_hist, steps, evals);
+                         gnorm_hist, iters_hist, steps, evals, pcg_total);
 }
 
 void jfft_destroy_cell(jfft_cell_t c) {
