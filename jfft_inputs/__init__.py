@@ -174,15 +174,17 @@ def spherical_inclusions(shape, count: int, radius: float, seed: int) -> np.ndar
     inclusion geometry of the nonlinear example, which the paper does not give."""
     rng = np.random.default_rng(seed)
     shape = tuple(int(s) for s in shape)
-    axes = np.meshgrid(*[np.arange(n) / n for n in shape], indexing="ij")  # (z, y, x)
+    coords = [np.arange(n) / n for n in shape]  # (z, y, x), broadcast per axis
     out = np.zeros(shape)
     for _ in range(int(count)):
         c = rng.random(len(shape))
         d2 = np.zeros(shape)
-        for a, ca in zip(axes, c):
+        for ax, (a, ca) in enumerate(zip(coords, c)):
             d = np.abs(a - ca)
             d = np.minimum(d, 1.0 - d)
-            d2 += d * d
+            sh = [1] * len(shape)
+            sh[ax] = shape[ax]
+            d2 = d2 + (d * d).reshape(sh)
         out[d2 <= radius * radius] = 1.0
     return out
 

@@ -187,6 +187,49 @@ def tangent_op(u, p, macro, phase, prm: PowerLaw, lengths=None):
     return w * _scatter(ye)
 
 
+def at_nodes(u, p, macro, phase, prm: PowerLaw, nodes, lengths=None):
+    """Force f, tangent action K(u) p and diag(K(u)) at the listed nodes only
+    (flat indices into (nz, ny, nx)), from the 8 elements around each: node I
+    is corner o of element I - o; the element's force, tangent action and
+    diagonal entries at that corner are summed over o.  For checks on grids
+    too large for the whole-field functions above."""
+    shape = u.shape[1:]
+    nz, ny, nx = shape
+    nodes = np.asarray(nodes)
+    z, rem = np.divmod(nodes, nx * ny)
+    y, x = np.divmod(rem, nx)
+    Bq, w = gauss_B(_h(shape, lengths))
+    mac = np.asarray(macro, dtype=float).reshape(6, 1)
+    S = nodes.size
+    f = np.zeros((3, S))
+    kp = np.zeros((3, S))
+    dg = np.zeros((3, S))
+    for o in range(8):
+        ox, oy, oz = o & 1, (o >> 1) & 1, o >> 2
+        ex, ey, ez = (x - ox) % nx, (y - oy) % ny, (z - oz) % nz
+        ue = np.empty((24, S))
+        pe = np.empty((24, S))
+        for i in range(3):
+            for c in range(8):
+                cx, cy, cz = c & 1, (c >> 1) & 1, c >> 2
+                idx = (((ez + cz) % nz), ((ey + cy) % ny), ((ex + cx) % nx))
+                ue[8 * i + c] = u[i][idx]
+                pe[8 * i + c] = p[i][idx]
+        ph = phase[ez, ey, ex]
+        for q in range(8):
+            B = Bq[q]
+            eps = B @ ue + mac
+            sig = stress(eps, ph, prm)
+            tp = tangent_apply(eps, B @ pe, ph, prm)
+            for i in range(3):
+                col = B[:, 8 * i + o]
+                f[i] -= w * (col @ sig)
+                kp[i] += w * (col @ tp)
+                cd = tangent_apply(eps, np.repeat(col[:, None], S, axis=1), ph, prm)
+                dg[i] += w * (col @ cd)
+    return f, kp, dg
+
+
 def stress_average(u, macro, phase, prm: PowerLaw, lengths=None):
     """sigma_bar = sum_e sum_q w sigma_q / |Y|."""
     eps = strains(u, macro, lengths)

@@ -374,3 +374,30 @@ def test_argument_and_state_checks():
     cell.close()
     assert abs(rep.iters - ref.iters) <= 1
     assert np.abs(u.cpu().numpy() - ref.u).max() <= 1e-9 * np.abs(ref.u).max()
+
+
+def test_operators_full_size_sampled():
+    """The bench configuration (200^3 nodes, voxels of unit edge, 8 spherical
+    inclusions): force, tangent action and the closed-form diagonal at 3000
+    seeded nodes against the oracle's evaluation at those nodes."""
+    pkg = _pkg()
+    n = 200
+    shape = (n, n, n)
+    say(f"power-law operators full size {shape}, sampled")
+    phase = 1.0 - ji.spherical_inclusions(shape, 8, 0.15, seed=0)
+    rng = np.random.default_rng(21)
+    u = 0.01 * rng.standard_normal((3,) + shape)
+    p = rng.standard_normal((3,) + shape)
+    macro = np.array([0, 0, 0, 0, 0, 0.05 * np.sqrt(2)])
+    L = (float(n),) * 3
+    cell = _cell(pkg, shape, pkg.PC_GREEN_JACOBI, L)
+    _set(cell, phase)
+    f = cell.powerlaw_force(macro, u).cpu().numpy().reshape(3, -1)
+    Kp = cell.powerlaw_tangent(macro, u, p).cpu().numpy().reshape(3, -1)
+    d = cell.powerlaw_jacobi_diag(macro, u).cpu().numpy().reshape(3, -1)
+    cell.close()
+    nodes = rng.choice(n ** 3, 3000, replace=False)
+    fr, kr, dr = pl.at_nodes(u, p, macro, phase, PRM, nodes, L)
+    assert np.abs(f[:, nodes] - fr).max() <= 1e-12 * np.abs(fr).max()
+    assert np.abs(Kp[:, nodes] - kr).max() <= 1e-12 * np.abs(kr).max()
+    assert np.abs(d[:, nodes] - dr).max() <= 1e-12 * np.abs(dr).max()

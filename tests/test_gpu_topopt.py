@@ -113,3 +113,18 @@ def test_argument_checks():
     with pytest.raises(pkg.JfftError):
         grp.topopt_lbfgs(rho, T, 2, m=0)
     grp.close()
+
+
+def test_full_size_phase_field_part():
+    """The bench size (256^2): the phase-field part of the objective against
+    the oracle (the mechanical part's solves are checked on small grids)."""
+    pkg = _pkg()
+    n = 256
+    say(f"topopt phase field full size {n}^2")
+    rho = np.random.default_rng(0).uniform(0.0, 1.0, (n, n))
+    grp = _group(pkg, (n, n))
+    f, grad, its = grp.topopt_eval(rho, T, eta=0.01, tol=1e-8, maxit=200000)
+    grp.close()
+    fpf, _ = to.phase_field(rho, 0.01)
+    assert f[2] == pytest.approx(fpf, rel=1e-12)
+    assert f[0] == pytest.approx(f[1] + f[2], rel=1e-15)

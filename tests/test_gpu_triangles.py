@@ -198,3 +198,41 @@ def test_element_switch_and_errors():
     cell.close()
     assert np.abs(s_tri - ref.sigma_bar).max() <= 1e-8 * np.abs(ref.sigma_bar).max()
     assert np.abs(s_tri - s_quad).max() > 1e-6 * np.abs(s_quad).max()  # a different element
+
+
+def test_full_size_operators_and_group():
+    """The bench configuration (512^2 nodes, GRF contrast 1e4): K p, f,
+    Algorithm 2's diagonal and the Green-Jacobi M^-1 against the oracle on
+    the whole field, and a group of four 512^2 cells giving bitwise the
+    single-cell solve."""
+    pkg = _pkg()
+    n = 512
+    shape = (n, n)
+    say(f"triangle operators full size {shape}")
+    E = ji.grf_field(shape, 1e4, seed=0, ell=0.1)
+    x = np.random.default_rng(4).standard_normal((2,) + shape)
+    macro = np.array([1.0, 0.0, 0.0])
+    cell = pkg.Cell(shape, pc=pkg.PC_GREEN_JACOBI, element="tri")
+    cell.set_material(E, nu=0.3)
+    Kx = cell.apply_stiffness(x).cpu().numpy()
+    f = cell.assemble_rhs(macro).cpu().numpy()
+    d = cell.jacobi_diag().cpu().numpy()
+    z = cell.apply_precond(x).cpu().numpy()
+    u1, s1, r1, _ = cell.solve(macro, tol=1e-8, maxit=20000)
+    u1 = u1.cpu().numpy()
+    cell.close()
+    assert np.abs(Kx - tri.stiffness(E, x, LAM, MU)).max() <= 1e-12 * np.abs(Kx).max()
+    assert np.abs(f - tri.rhs(E, macro, LAM, MU)).max() <= 1e-12 * np.abs(f).max()
+    d_ref = tri.jacobi_diag(E, LAM, MU)
+    assert np.abs(d - d_ref).max() <= 1e-12 * np.abs(d_ref).max()
+    zr, _ = oracle.precond(oracle.PC_GREEN_JACOBI, x, diag=d_ref, G=tri.green(shape, LAM, MU))
+    assert np.abs(z - zr).max() <= 1e-11 * np.abs(zr).max()
+    say("  group of four 512^2 cells")
+    Es = np.stack([E] + [ji.grf_field(shape, 1e4, seed=s, ell=0.1) for s in (1, 2, 3)])
+    grp = pkg.Cell(shape, pc=pkg.PC_GREEN_JACOBI, batch=4, element="tri")
+    grp.set_material(Es, nu=0.3)
+    ug, sg, rg, _ = grp.solve_batch(np.tile(macro, (4, 1)), tol=1e-8, maxit=20000)
+    ug = ug.cpu().numpy()
+    grp.close()
+    assert rg[0].iters == r1.iters and all(r.status == "ok" for r in rg)
+    assert np.array_equal(ug[0], u1) and np.array_equal(sg[0], s1)

@@ -178,3 +178,23 @@ def test_newton_absolute_inner_rule_equals_relative_rule_at_same_threshold():
                    pcg_absolute=True)
     assert rel.pcg_iters == ab.pcg_iters and rel.pcg_iters[0] > 3
     assert np.abs(rel.u - ab.u).max() <= 1e-12 * np.abs(rel.u).max()
+
+
+def test_at_nodes_equals_whole_field_functions():
+    """The sampled-node evaluation (for large grids) equals the whole-field
+    force, tangent action and Algorithm 2 diagonal at every node."""
+    shape = (4, 6, 4)
+    rng = np.random.default_rng(9)
+    phase = (rng.random(shape) > 0.4).astype(float)
+    macro = rng.uniform(-0.05, 0.05, 6)
+    u = 0.02 * rng.standard_normal((3,) + shape)
+    p = rng.standard_normal((3,) + shape)
+    L = (1.0, 1.3, 0.8)
+    nodes = np.arange(int(np.prod(shape)))
+    f, kp, dg = pl.at_nodes(u, p, macro, phase, PRM, nodes, L)
+    ff = pl.force(u, macro, phase, PRM, L).reshape(3, -1)
+    kk = pl.tangent_op(u, p, macro, phase, PRM, L).reshape(3, -1)
+    dd = pl.jacobi_diag(u, macro, phase, PRM, L).reshape(3, -1)
+    assert np.abs(f - ff).max() <= 1e-13 * np.abs(ff).max()
+    assert np.abs(kp - kk).max() <= 1e-13 * np.abs(kk).max()
+    assert np.abs(dg - dd).max() <= 1e-13 * np.abs(dd).max()
