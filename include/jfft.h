@@ -258,6 +258,12 @@ jfft_status jfft_set_stop_rule(jfft_cell_t cell, int rule);
 /* Mixed precision controls: relative tolerance of each inner FP32 PCG solve
    (default 1e-6) and the cap on refinement sweeps (default 30). */
 jfft_status jfft_set_mixed_params(jfft_cell_t cell, double inner_tol, int max_outer);
+/* Cap on the iterations of one FP32 inner solve of the mixed refinement
+   (default 2000; 0: none).  An inner solve that stalls short of its
+   tolerance (FP32 rounding on a very ill-conditioned cell, e.g. with voids)
+   then ends and the next FP64 sweep restarts from the corrected residual;
+   the maxit of the solve still bounds the inner iterations of all sweeps. */
+jfft_status jfft_set_mixed_inner_cap(jfft_cell_t cell, int cap);
 
 /* ---- Power-law material and Newton solve (nonlinear example, Sec. 4;
    Newton linearisation, Sec. 2.2, eq. lin_system) -------------------------
@@ -341,9 +347,10 @@ jfft_status jfft_powerlaw_jacobi_diag(jfft_cell_t cell, const double *macro_stra
    (objective evaluations), *pcg_total (PCG iterations of every evaluation,
    rejected trials included).  The handle allocates (6 + 2 m) N doubles on
    first use (freed with the handle).  Mixed-precision groups follow the
-   refinement loop of jfft_solve; once the density has exact voids their
-   FP32 inner solves can stall short of the refinement's tolerance (then
-   JFFT_E_NOT_CONVERGED): use FP64 groups for whole optimisation runs. */
+   refinement loop of jfft_solve; on rough densities of very high contrast
+   (or with exact voids) the FP32 operator's rounding exceeds what the
+   refinement can correct (then JFFT_E_NOT_CONVERGED): use FP64 groups for
+   whole optimisation runs. */
 jfft_status jfft_topopt_eval(jfft_cell_t group, const double *rho_dev, double lambda0, double mu0,
                              const double *targets, double eta, double tol, int maxit,
                              double *f_out, double *grad_dev, int *iters);

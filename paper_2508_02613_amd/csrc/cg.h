@@ -143,10 +143,12 @@ __global__ void k_solve_norms(CgState *st, const double *partF, const double *pa
 
 // Inner PCG set-up.  FP64 solve (mixed = 0): stop at ||r|| <= tol ||f||.
 // Mixed inner solve on r / ||r|| (mixed = 1): stop at relative
-// max(inner_tol, tol ||f|| / (2 ||r||)).  Cells already finished (homogeneous
+// max(inner_tol, tol ||f|| / (2 ||r||)), or after inner_cap iterations
+// (> 0): an FP32 solve that stalls short of its tolerance then hands its
+// progress to the next FP64 refinement sweep instead of running on.  Cells already finished (homogeneous
 // material, or refinement converged) start in the stopped state.
 __global__ void k_cg_init(CgState *st, double inner_tol, int mixed, int maxit, int hist_cap,
-                          long long cs) {
+                          int inner_cap, long long cs) {
   st = cshift(st, blockIdx.x, cs);
   if (threadIdx.x != 0) return;
   double t2;
@@ -156,6 +158,7 @@ __global__ void k_cg_init(CgState *st, double inner_tol, int mixed, int maxit, i
     t2 = rel * rel;
     mx = maxit - st->total_iters;
     if (mx < 1) mx = 1;
+    if (inner_cap > 0 && mx > inner_cap) mx = inner_cap;
   } else {
     t2 = st->tolr * st->tolr * st->fnorm2;
   }

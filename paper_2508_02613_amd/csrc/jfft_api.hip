@@ -158,6 +158,7 @@ struct jfft_cell_s {
   double void_value = 1.0;
   double inner_tol = 1e-6;
   int max_outer = 30;
+  int inner_cap = 2000;  // iterations of one FP32 inner solve (0: no cap)
   bool stop_abs = false;  // stopping rule ||r||^2 <= tol instead of ||r|| <= tol ||f||
   int diag_method = JFFT_DIAG_CLOSED_FORM;  // how J^1/2 is formed (Algorithm 2 or its closed form)
   int elem = JFFT_ELEM_QUAD;  // 2D element: bilinear quadrilateral or two linear triangles
@@ -876,7 +877,7 @@ jfft_status run_pcg(jfft_cell_s *c, const PcgBufs<Real> &b, bool mixed, int maxi
   History h{nullptr, nullptr, nullptr};
   if (record && c->hist_cap > 0) h = {c->hist[0], c->hist[1], c->hist[2]};
   long long nA = 0, nB = 0;
-  LAUNCH(c, KID_CTRL, k_cg_init<<<c->B, 1, 0, c->stream>>>(c->st, c->inner_tol, mixed ? 1 : 0, maxit, record ? c->hist_cap : 0, c->cs));
+  LAUNCH(c, KID_CTRL, k_cg_init<<<c->B, 1, 0, c->stream>>>(c->st, c->inner_tol, mixed ? 1 : 0, maxit, record ? c->hist_cap : 0, c->inner_cap, c->cs));
   TRY(precond<Real>(c, b.r, nullptr, b.Jh, b.z, b.spec, false, false, &nA, &nB, h));
   LAUNCH(c, KID_CTRL, k_cg_start<<<c->B, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nA, c->partB, nB, c->cs));
   const int gk = sizeof(Real) == 8 ? 0 : 1;
@@ -1906,6 +1907,12 @@ jfft_status jfft_set_element(jfft_cell_t c, int element) {
 jfft_status jfft_set_void_value(jfft_cell_t c, double value) {
   if (!c || !(value > 0.0) || !std::isfinite(value)) return fail(JFFT_E_INVALID, "void value must be positive");
   c->void_value = value;
+  return JFFT_OK;
+}
+
+jfft_status jfft_set_mixed_inner_cap(jfft_cell_t c, int cap) {
+  if (!c || cap < 0) return fail(JFFT_E_INVALID, "the inner iteration cap must be >= 0");
+  c->inner_cap = cap;
   return JFFT_OK;
 }
 
