@@ -368,16 +368,19 @@ size_t layout_workspace(jfft_cell_s *c, unsigned char *base) {
 
 // Output-node tile of the stiffness kernels (x and y edge) and the tile count of a grid.
 int stencil_tile_x(int dim) { return dim == 3 ? TX3 : TILE; }
-int stencil_tile_y(int dim) { return dim == 3 ? TY3 : TY2; }
-long long stencil_tiles(int dim, int nx, int ny) {
-  const int tx = stencil_tile_x(dim), ty = stencil_tile_y(dim);
+int stencil_tile_y(int dim, bool fp64) {
+  return dim == 3 ? TY3 : (fp64 ? ty2<double>() : ty2<float>());
+}
+long long stencil_tiles(int dim, int nx, int ny, bool fp64) {
+  const int tx = stencil_tile_x(dim), ty = stencil_tile_y(dim, fp64);
   return (long long)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
 }
 
 long long max_partials(jfft_cell_s *c) {
   const GridDev &g = c->g;
   long long mx = 4 * 1024;  // vector kernels
-  const long long tiles = stencil_tiles(c->dim, g.nx, g.ny);
+  const long long tiles = std::max(stencil_tiles(c->dim, g.nx, g.ny, true),
+                                   stencil_tiles(c->dim, g.nx, g.ny, false));
   mx = std::max(mx, tiles * ((g.nz + 2 - 1) / 2));  // smallest z chunk allowed (tz >= 2)
   const int m = g.nx / 2;
   const long long rows = (long long)c->dim * g.ny * g.nz;
@@ -543,7 +546,7 @@ hipError_t stiffness_slots(int device, bool fp64, bool cubic, int *slots, int *p
 //   16: 0.448; 32 and longer slower), shortened while the launch would leave
 //   slots empty.
 int pick_tz(const GridDev &g, int slots, int per_cu) {
-  const long long tiles = stencil_tiles(3, g.nx, g.ny);
+  const long long tiles = stencil_tiles(3, g.nx, g.ny, true);
   const int lo = std::min(4, g.nz);
   auto blocks = [&](int tz) { return tiles * ((g.nz + tz - 1) / tz); };
   if (per_cu > 1) {
@@ -564,18 +567,18 @@ int pick_tz(const GridDev &g, int slots, int per_cu) {
   return best;
 }
 
-long long stencil_blocks_per_cell(jfft_cell_s *c) {
+long long stencil_blocks_per_cell(jfft_cell_s *c, bool fp64) {
   const GridDev &g = c->g;
   const int tz = c->dim == 3 ? std::min(c->tun.tz, g.nz) : 1;
   const int nbz = c->dim == 3 ? (g.nz + tz - 1) / tz : 1;
-  return stencil_tiles(c->dim, g.nx, g.ny) * nbz;
+  return stencil_tiles(c->dim, g.nx, g.ny, fp64) * nbz;
 }
 
 template <typename Real, int MODE>
 jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a, int cells) {
   const int kid = MODE == SM_CG ? KID_STIFF_CG : (MODE == SM_APPLY ? KID_STIFF_APPLY : KID_STIFF_COMB);
   const GridDev &g = c->g;
-  const int tx = stencil_tile_x(c->dim), ty = stencil_tile_y(c->dim);
+  const int tx = stencil_tile_x(c->dim), ty = stencil_tile_y(c->dim, sizeof(Real) == 8);
   dim3 gr((g.nx + tx - 1) / tx, (g.ny + ty - 1) / ty, a.nbz * cells);
   if (c->nl) {
     // the power-law tangent (3D cells, checked when the material is set);
@@ -835,7 +838,7 @@ jfft_status pcg_iteration(jfft_cell_s *c, const PcgBufs<Real> &b, int j, History
   a.out = b.q;
   a.partial = c->partA;
   TRY((launch_stiffness<Real, SM_CG>(c, a, c->B)));
-  const long long nK = stencil_blocks_per_cell(c);
+  const long long nK = stencil_blocks_per_cell(c, sizeof(Real) == 8);
   LAUNCH(c, KID_CTRL, k_cg_alpha<<<c->B, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nK, h, (j + 1) & 1, c->cs));
   long long nA, nB;
   return precond<Real>(c, b.r, b.q, b.Jh, b.z, b.spec, true, true, &nA, &nB, h);
@@ -1830,7 +1833,7 @@ jfft_status jfft_set_tunables(jfft_cell_t c, const jfft_tunables *t) {
     if (t->tz < std::min(2, c->g.nz) || t->tz > c->g.nz)
       return fail(JFFT_E_INVALID, "tz must lie in [2, nz]");
     const long long nbz = (c->g.nz + t->tz - 1) / t->tz;
-    const long long tiles = stencil_tiles(3, c->g.nx, c->g.ny);
+    const long long tiles = stencil_tiles(3, c->g.nx, c->g.ny, true);
     if (nbz * c->B > 65535) return fail(JFFT_E_INVALID, "tz too small for this group (grid z-dimension)");
     if (tiles * nbz > c->npart) return fail(JFFT_E_INVALID, "tz too small for the partial-sum buffer");
     c->tun.tz = t->tz;

@@ -23,10 +23,14 @@ constexpr int TILE = 16;           // output nodes per tile edge
 constexpr int ETILE = TILE + 1;    // elements per tile edge (with halo)
 constexpr int NTILE = TILE + 2;    // nodes per tile edge (with halo)
 constexpr int STENCIL_THREADS = 384;  // 6 wavefronts (2D kernel)
-constexpr int TY2 = 2 * TILE;          // output rows of a 2D block (two tiles in y)
-constexpr int NNODE2 = NTILE * (TY2 + 2);  // 612 nodes with halo
-constexpr int NELEM2 = ETILE * (TY2 + 1);  // 561 elements with halo
-constexpr int NOUT2 = TILE * TY2;          // 512 outputs
+// Output rows of a 2D block: 16 x 16 tiles stacked in y, two in FP32 (twice
+// the loads in flight per thread; three measured slower), one in FP64 (a
+// two-tile FP64 block's 46 KB of LDS cuts occupancy to 3 blocks per CU,
+// 8 % slower).
+template <typename Real>
+constexpr int ty2() {
+  return (sizeof(Real) == 8 ? 1 : 2) * TILE;
+}
 // 3D kernel: 16 x 14 output nodes, 17 x 15 elements, 18 x 16 node planes.
 // Rows of 16 output nodes start on 64-byte boundaries (FP32; 128 in FP64),
 // so every store covers whole sectors and no sector is written by two blocks.
@@ -1096,17 +1100,21 @@ __device__ __forceinline__ void elem_tri2(const Real (&u)[2][4], Real Elam, Real
   }
 }
 
-// One block: TILE x TY2 output nodes (two 16 x 16 tiles stacked in y, which
-// share a halo row), 384 threads; every thread owns up to two nodes of the
-// halo-extended tile, two elements and two outputs (index tid + r * 384).
-// All loads of both nodes (and both element moduli) are issued before any
-// store, so a thread keeps a dozen loads in flight.  Loads use clamped,
+// One block: TILE x TY2 output nodes (ty2: one or two 16 x 16 tiles stacked
+// in y, which then share a halo row), 384 threads; every thread owns up to R
+// nodes of the halo-extended tile, R elements and R outputs (index tid +
+// r * 384).  All loads of its nodes (and element moduli) are issued before
+// any store, so a thread keeps up to a dozen loads in flight.  Loads use clamped,
 // valid addresses and are masked where the value is committed.
 // TRI: the pixel is two linear triangles (elem_tri2) instead of a bilinear
 // quadrilateral.
 template <typename Real, int MODE, bool TRI = false>
 __global__ void __launch_bounds__(STENCIL_THREADS)
     k_stiffness2d(StencilArgs<Real> a) {
+  constexpr int TY2 = ty2<Real>();
+  constexpr int NNODE2 = NTILE * (TY2 + 2);  // nodes with halo
+  constexpr int NELEM2 = ETILE * (TY2 + 1);  // elements with halo
+  constexpr int NOUT2 = TILE * TY2;          // outputs
   __shared__ Real P[2][NNODE2];
   __shared__ Real Y[8][NELEM2];
   __shared__ double red[8];
@@ -1128,10 +1136,10 @@ __global__ void __launch_bounds__(STENCIL_THREADS)
     beta = (Real)a.st->beta;
     alpha_prev = (Real)a.st->alpha;
   }
-  constexpr int R = 2;  // items per thread
+  constexpr int R = (NNODE2 + STENCIL_THREADS - 1) / STENCIL_THREADS;  // items per thread
   static_assert(R * STENCIL_THREADS >= NNODE2 && R * STENCIL_THREADS >= NELEM2 &&
                     R * STENCIL_THREADS >= NOUT2,
-                "two items per thread cover the tile");
+                "R items per thread cover the tile");
   // element moduli (beyond the grid: 0)
   Real Ee[R];
 #pragma unroll
