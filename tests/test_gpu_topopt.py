@@ -60,14 +60,17 @@ def test_objective_and_gradient_match_oracle(shape, lengths, voids):
     assert all(abs(a - b) <= max(2, round(0.05 * b)) for a, b in zip(its, ref.iters))
 
 
-def test_lbfgs_trajectory_matches_oracle():
+# one full block of 256 nodes; ragged tails of the L-BFGS vector kernels on
+# non-square pixels; several blocks with a tail
+@pytest.mark.parametrize("shape,lengths,seed,K", [((16, 16), None, 0, 8),
+                                                  ((24, 20), (1.0, 0.6), 1, 6),
+                                                  ((40, 36), None, 1, 6)])
+def test_lbfgs_trajectory_matches_oracle(shape, lengths, seed, K):
     pkg = _pkg()
-    shape = (16, 16)
-    say(f"topopt L-BFGS {shape}")
-    rho0 = np.random.default_rng(0).uniform(0.0, 1.0, shape)
-    K = 8
-    ref = to.lbfgs(lambda r: to.evaluate(r, eta=0.01, tol=1e-12), rho0, K)
-    grp = _group(pkg, shape)
+    say(f"topopt L-BFGS {shape} lengths={lengths} seed={seed} steps={K}")
+    rho0 = np.random.default_rng(seed).uniform(0.0, 1.0, shape)
+    ref = to.lbfgs(lambda r: to.evaluate(r, eta=0.01, tol=1e-12, lengths=lengths), rho0, K)
+    grp = _group(pkg, shape, lengths)
     rho, out = grp.topopt_lbfgs(rho0, T, K, eta=0.01, tol=1e-12)
     r = rho.cpu().numpy()
     grp.close()
@@ -128,3 +131,28 @@ def test_full_size_phase_field_part():
     fpf, _ = to.phase_field(rho, 0.01)
     assert f[2] == pytest.approx(fpf, rel=1e-12)
     assert f[0] == pytest.approx(f[1] + f[2], rel=1e-15)
+
+
+def test_full_size_lbfgs_properties():
+    """The bench size (256^2), two L-BFGS steps: properties that hold at any
+    size -- f decreases, the density stays in [0, 1], and the reported f and
+    ||g||_inf are those of a fresh evaluation at the final density."""
+    pkg = _pkg()
+    n = 256
+    say(f"topopt L-BFGS properties full size {n}^2")
+    rho0 = np.random.default_rng(0).uniform(0.0, 1.0, (n, n))
+    grp = _group(pkg, (n, n))
+    rho, out = grp.topopt_lbfgs(rho0, T, 2, eta=0.01, tol=1e-8, maxit=200000)
+    r = rho.cpu().numpy()
+    f, grad, its = grp.topopt_eval(r, T, eta=0.01, tol=1e-8, maxit=200000)
+    g = grad.cpu().numpy()
+    grp.close()
+    say(f"  steps={out['steps']} evals={out['evals']} f={out['f']} eval f={f[0]}")
+    assert out["steps"] == 2
+    assert out["f"][2] < out["f"][1] < out["f"][0]
+    assert r.min() >= 0.0 and r.max() <= 1.0
+    assert f[0] == pytest.approx(out["f"][-1], rel=1e-12)
+    assert np.abs(g).max() == pytest.approx(out["gnorm"][-1], rel=1e-12)
+    assert its == out["iters"][-1]
+    fpf, _ = to.phase_field(r, 0.01)
+    assert f[2] == pytest.approx(fpf, rel=1e-12)
