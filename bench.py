@@ -643,7 +643,7 @@ def run_tri(args):
         "trend_motivating_example_256": trend,
     }
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline_tri()
+        line["cpu_baseline"] = cpu_baseline_tri(reps=100)
     return line
 
 
@@ -783,16 +783,13 @@ def cpu_baseline_tri(n=512, E=None, lame=None, cells=1, reps=1):
 def cpu_baseline_powerlaw(seed):
     """The power-law oracle timed on one PCG iteration's operators (tangent
     K(u) p by its vectorised element loop, Green-Jacobi preconditioner with
-    the naive separable DFT, dots and updates) at 100^3 nodes, an eighth of
-    the 200^3 cell: the full cell's element loop alone takes about a minute.
-    The element loop costs the same per DOF at any size; the naive DFT costs
-    n per point and axis, so the sample overstates the oracle's 200^3 rate
-    somewhat."""
+    the naive separable DFT, dots and updates) on the bench's 200^3 cell
+    (about 20 s with 16 threads)."""
     import jfft_inputs as ji
     import oracle
     from oracle import powerlaw as pl
 
-    n = 100
+    n = 200
     shape = (n, n, n)
     phase = 1.0 - ji.spherical_inclusions(shape, 8, 0.15, seed=seed)
     rng = np.random.default_rng(0)
