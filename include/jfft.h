@@ -141,6 +141,7 @@ jfft_status jfft_solve(jfft_cell_t cell, const double *macro_strain, double tol,
                        const double *u0_dev, double *u_dev, double *sigma_dev,
                        double *sigma_bar, jfft_report *report);
 
+
 /* jfft_solve for every cell of a group at once.  Arrays are those of
    jfft_solve with a leading cell index:
      macro_strains: host [batch][d*];
@@ -187,6 +188,11 @@ jfft_status jfft_get_tunables(jfft_cell_t cell, jfft_tunables *t);
 jfft_status jfft_apply_stiffness(jfft_cell_t cell, const double *in_dev, double *out_dev);
 /* out = M^-1 in for the cell's preconditioner. */
 jfft_status jfft_apply_precond(jfft_cell_t cell, const double *in_dev, double *out_dev);
+/* out = M^-1 in as the inner FP32 solves of a JFFT_MIXED cell apply it
+   (Sec. 3.3, eq. prec_lin_systemJG_2, with the FP32 J^1/2, spectrum and FFT
+   passes): in is rounded to FP32, out widened to FP64 (device [d][N] each).
+   JFFT_E_INVALID for an FP64 cell or a group handle. */
+jfft_status jfft_apply_precond_fp32(jfft_cell_t cell, const double *in_dev, double *out_dev);
 /* f = -B^T W C(E) macro (no mean projection). */
 jfft_status jfft_assemble_rhs(jfft_cell_t cell, const double *macro_strain, double *f_dev);
 /* diag(K) from Algorithm 2 before the void rule (zero entries kept). */

@@ -24,7 +24,7 @@ __all__ = [
     "node_coords", "sine_contrast_field", "grf_field", "simp_field",
     "laminate_field", "cosine_void_field", "filtered_inclusion_field",
     "uniform_random_field", "random_start", "unit_macro_strain", "mandel_size",
-    "spherical_inclusions",
+    "spherical_inclusions", "ulp_perturbed", "sketch_vectors", "sample_nodes",
 ]
 
 
@@ -188,3 +188,30 @@ def spherical_inclusions(shape, count: int, radius: float, seed: int) -> np.ndar
         out[d2 <= radius * radius] = 1.0
     return out
 
+
+
+def ulp_perturbed(a, seed: int) -> np.ndarray:
+    """Copy of `a` with every entry moved by one unit in the last place, up or
+    down with equal probability (seeded); exact zeros stay zero.  Used to
+    measure how far rounding-level changes of the input move a solver's
+    stopping iteration."""
+    a = np.asarray(a, dtype=np.float64)
+    up = np.random.default_rng(seed).random(a.shape) < 0.5
+    out = np.where(up, np.nextafter(a, np.inf), np.nextafter(a, -np.inf))
+    return np.where(a == 0.0, 0.0, out)
+
+
+def sketch_vectors(shape, count: int, seed: int):
+    """Yield `count` seeded i.i.d. N(0, 1) arrays of `shape`, one at a time.
+    For any array x of that shape, E[(w . x)^2] = ||x||^2, so the mean square
+    of the projections estimates a squared norm (a sketch of a field too large
+    to store)."""
+    rng = np.random.default_rng(seed)
+    for _ in range(int(count)):
+        yield rng.standard_normal(tuple(shape))
+
+
+def sample_nodes(n_nodes: int, count: int, seed: int) -> np.ndarray:
+    """Sorted seeded sample of `count` distinct flat node indices."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(int(n_nodes), size=int(count), replace=False))

@@ -46,7 +46,8 @@ def _load():
         "or_precond": [C.c_int, _ip, _dp, C.c_int, _dp, C.c_double, _dp, _dp, _dp, _dp, _dp],
         "or_solve": [C.c_int, _ip, _dp, C.c_double, C.c_double, _dp, _dp, C.c_int, C.c_double,
                      C.c_double, C.c_double, C.c_double, C.c_int, C.c_int, _dp, _dp, _dp, _ip,
-                     _dp, _dp, _dp, _dp, _dp, C.c_int, C.c_int, _dp, _dp, C.c_int],
+                     _dp, _dp, _dp, _dp, _dp, C.c_int, C.c_int, _dp, _dp, C.c_int,
+                     C.c_ulonglong, C.c_int],
         "or_time_iterations": [C.c_int, _ip, _dp, C.c_double, C.c_double, _dp, _dp, C.c_int,
                                C.c_double, C.c_double, C.c_int, _dp],
         "or_num_threads": [],
@@ -55,6 +56,8 @@ def _load():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = C.c_int
+    lib.or_dot.argtypes = [C.c_int, C.c_long, _dp, _dp]
+    lib.or_dot.restype = C.c_double
     _lib = lib
     return lib
 
@@ -213,8 +216,14 @@ class SolveResult:
 
 def solve(E, macro, lam, mu, pc=PC_GREEN_JACOBI, lam_ref=None, mu_ref=None, tol=1e-8,
           maxit=1000, u0=None, void_value=1.0, stop_mode=0, hist_len=0, lengths=None,
-          remove_mean=True, f=None, project_rhs=False) -> SolveResult:
-    """Full PCG solve of K u = f (mean-projected f); see or_solve."""
+          remove_mean=True, f=None, project_rhs=False, noise_seed=0, dot_mode=0) -> SolveResult:
+    """Full PCG solve of K u = f; see or_solve.  f defaults to the assembled
+    right-hand side, not projected to zero mean (project_rhs=True projects
+    it).  noise_seed != 0 moves every entry of each K p and M^-1 r result by
+    one ulp in a seeded direction, and dot_mode = 1 forms the inner products
+    and norms as if in twice the working precision (Dot2) instead of the
+    serial sum: rounding-difference models for parity windows (0, 0 = plain
+    arithmetic)."""
     lib = _load()
     E = np.ascontiguousarray(E, dtype=np.float64)
     dim, n, ln = _grid(E, lengths)
@@ -236,7 +245,8 @@ def solve(E, macro, lam, mu, pc=PC_GREEN_JACOBI, lam_ref=None, mu_ref=None, tol=
     st = lib.or_solve(dim, n, ln, lam, mu, _d(E), _d(macro), int(pc), lam_ref, mu_ref,
                       float(void_value), float(tol), int(stop_mode), int(maxit), _d(u0), _d(u),
                       _d(sbar), C.byref(it), C.byref(rr), C.byref(rt), _d(ah), _d(bh), _d(rh), h,
-                      1 if remove_mean else 0, _d(tm), _d(f), 1 if project_rhs else 0)
+                      1 if remove_mean else 0, _d(tm), _d(f), 1 if project_rhs else 0,
+                      int(noise_seed), int(dot_mode))
     if st not in (0, 4, 5):
         raise RuntimeError(f"oracle solve failed: {STATUS.get(st, st)}")
     k = int(it.value)
@@ -244,6 +254,14 @@ def solve(E, macro, lam, mu, pc=PC_GREEN_JACOBI, lam_ref=None, mu_ref=None, tol=
                        relres_true=float(rt.value), status=STATUS[st],
                        alpha=ah[:min(k, h)], beta=bh[:min(max(k - 1, 0), h)],
                        res=rh[:min(k, h)], timing=tm)
+
+
+def dot(a, b, mode=0):
+    """The oracle's inner product: mode 0 serial sum in index order, 1 Dot2."""
+    a = np.ascontiguousarray(a, dtype=np.float64).ravel()
+    b = np.ascontiguousarray(b, dtype=np.float64).ravel()
+    assert a.size == b.size
+    return float(_load().or_dot(int(mode), a.size, _d(a), _d(b)))
 
 
 def time_iterations(E, macro, lam, mu, pc=PC_GREEN_JACOBI, iters=1, lengths=None):

@@ -16,6 +16,13 @@
  *     (Jacobi diagonal from d*2^d comb applications) taken step by step;
  *   - textbook PCG (Saad, Alg. 9.1) with the split Green-Jacobi operator
  *     J^1/2 F^-1 G^ F J^1/2 (eq. prec_lin_systemJG_2).
+ * or_solve has two options that no paper passage asks for, both used only to
+ * measure how far rounding moves the stopping iteration (two FP64 programs of
+ * the same method round differently): a nonzero noise_seed moves every entry
+ * of each K p and M^-1 r result by one ulp in a seeded direction (ulp_noise);
+ * dot_mode = 1 forms every inner product and norm with Dot2 (as if in twice
+ * the working precision) instead of the serial sum in index order.  With
+ * noise_seed = 0 and dot_mode = 0 the arithmetic is plain.
  * The only parallelism is OpenMP over independent DFT lines and over
  * same-colour elements (elements that share no node), which changes no
  * arithmetic result.  Reductions are serial and in index order.
@@ -33,6 +40,7 @@
  *   DFT: forward sum x_j exp(-2 pi i jk/n) (unnormalised), inverse exp(+...) / N.
  */
 #include <complex.h>
+#include <stdint.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -622,6 +630,34 @@ static double dot(long n, const double *a, const double *b) {
   return s;
 }
 
+/* Dot product as if accumulated in twice the working precision and then
+   rounded: algorithm Dot2 of Ogita, Rump and Oishi, "Accurate sum and dot
+   product" (SIAM J. Sci. Comput. 26, 2005), with the error-free product from
+   fma and Knuth's error-free sum.  Used by or_solve when dot_mode = 1. */
+static double dot2(long n, const double *a, const double *b) {
+  if (n <= 0) return 0.0;
+  double p = a[0] * b[0];
+  double s = fma(a[0], b[0], -p);
+  for (long i = 1; i < n; ++i) {
+    const double h = a[i] * b[i];
+    const double r = fma(a[i], b[i], -h);
+    const double t = p + h;
+    const double z = t - p;
+    const double q = (p - (t - z)) + (h - z);
+    p = t;
+    s += q + r;
+  }
+  return p + s;
+}
+
+static double dotm(int mode, long n, const double *a, const double *b) {
+  return mode == 1 ? dot2(n, a, b) : dot(n, a, b);
+}
+
+/* The inner product of or_solve's dot_mode (0 serial, 1 Dot2), exported so
+   that the tests can pin it. */
+double or_dot(int mode, long n, const double *a, const double *b) { return dotm(mode, n, a, b); }
+
 /* Full solve: assemble f, set up the preconditioner, run PCG (Saad Alg. 9.1
    in the split form of the footnote to eq. prec_lin_system_general), then
    remove the mean of u per component and compute sigma_bar.
@@ -642,12 +678,35 @@ static double now_s(void) {
   return ts.tv_sec + 1e-9 * ts.tv_nsec;
 }
 
+/* Rounding-difference model for measuring how far the stopping iteration
+   moves between two FP64 evaluations of the same method (two programs round
+   every operator application differently): every entry of v moves by one
+   unit in the last place, up or down.  The direction is the top bit of
+   splitmix64 (Steele, Lea and Flood, 2014) applied to a counter built from
+   the seed, the iteration, the operator and the entry index.  Zeros stay. */
+static uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ULL;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+  return x ^ (x >> 31);
+}
+
+static void ulp_noise(double *v, long n, uint64_t seed, int iter, int op) {
+  const uint64_t base = splitmix64(seed) ^ ((uint64_t)(unsigned)iter << 33) ^ ((uint64_t)op << 32);
+  for (long i = 0; i < n; ++i) {
+    if (v[i] == 0.0) continue;
+    const uint64_t h = splitmix64(base + (uint64_t)i);
+    v[i] = nextafter(v[i], (h >> 63) ? INFINITY : -INFINITY);
+  }
+}
+
 int or_solve(int dim, const int *n, const double *len, double lam, double mu, const double *E,
              const double *macro, int pc, double lam_ref, double mu_ref, double void_value,
              double tol, int stop_mode, int maxit, const double *u0, double *u_out,
              double *sigma_bar, int *iters, double *relres_rec, double *relres_true,
              double *alpha_hist, double *beta_hist, double *res_hist, int hist_len,
-             int remove_mean, double *timing, const double *f_in, int project_rhs) {
+             int remove_mean, double *timing, const double *f_in, int project_rhs,
+             unsigned long long noise_seed, int dot_mode) {
   grid_t g;
   int st = grid_init(&g, dim, n, len);
   if (st) return st;
@@ -699,8 +758,8 @@ int or_solve(int dim, const int *n, const double *len, double lam, double mu, co
       m /= (double)N;
       for (long i = 0; i < N; ++i) f[a * N + i] -= m;
     }
-  double fnorm = sqrt(dot(nd, f, f));
-  double fabsnorm = sqrt(dot(nd, fabs_, fabs_));
+  double fnorm = sqrt(dotm(dot_mode, nd, f, f));
+  double fabsnorm = sqrt(dotm(dot_mode, nd, fabs_, fabs_));
 
   /* preconditioner set-up */
   if (pc == PC_JACOBI || pc == PC_GREEN_JACOBI) {
@@ -724,7 +783,7 @@ int or_solve(int dim, const int *n, const double *len, double lam, double mu, co
     memcpy(r, f, sizeof(double) * nd);
   }
   int k = 0;
-  double rnorm = sqrt(dot(nd, r, r));
+  double rnorm = sqrt(dotm(dot_mode, nd, r, r));
   int converged;
   if (stop_mode == 0)
     converged = (fnorm <= 1e-13 * fabsnorm) || (rnorm <= tol * fnorm);
@@ -739,15 +798,17 @@ int or_solve(int dim, const int *n, const double *len, double lam, double mu, co
   if (!converged) {
     st = precond_apply(&g, pc, diag, Gre, Gim, r, z, NULL, work);
     if (st) goto cleanup;
+    if (noise_seed) ulp_noise(z, nd, noise_seed, 0, 1);
     memcpy(p, z, sizeof(double) * nd);
-    double rz = dot(nd, r, z);
+    double rz = dotm(dot_mode, nd, r, z);
     for (;;) {
       if (k >= maxit) {
         st = OR_E_NOT_CONVERGED;
         break;
       }
       stiffness_apply(&g, lam, mu, E, p, q);
-      double pq = dot(nd, p, q);
+      if (noise_seed) ulp_noise(q, nd, noise_seed, k + 1, 0);
+      double pq = dotm(dot_mode, nd, p, q);
       double alpha = rz / pq;
       if (!(pq > 0.0) || !isfinite(alpha)) {
         st = OR_E_BREAKDOWN;
@@ -756,7 +817,7 @@ int or_solve(int dim, const int *n, const double *len, double lam, double mu, co
       for (long i = 0; i < nd; ++i) u_out[i] += alpha * p[i];
       for (long i = 0; i < nd; ++i) r[i] -= alpha * q[i];
       ++k;
-      rnorm = sqrt(dot(nd, r, r));
+      rnorm = sqrt(dotm(dot_mode, nd, r, r));
       if (alpha_hist && k <= hist_len) alpha_hist[k - 1] = alpha;
       if (res_hist && k <= hist_len) res_hist[k - 1] = rnorm;
       if (stop_mode == 0 ? (rnorm <= tol * fnorm) : (rnorm * rnorm <= tol)) break;
@@ -766,7 +827,8 @@ int or_solve(int dim, const int *n, const double *len, double lam, double mu, co
       }
       st = precond_apply(&g, pc, diag, Gre, Gim, r, z, NULL, work);
       if (st) goto cleanup;
-      double rz_new = dot(nd, r, z);
+      if (noise_seed) ulp_noise(z, nd, noise_seed, k, 1);
+      double rz_new = dotm(dot_mode, nd, r, z);
       double beta = rz_new / rz;
       if (!isfinite(beta)) {
         st = OR_E_BREAKDOWN;
@@ -784,7 +846,7 @@ int or_solve(int dim, const int *n, const double *len, double lam, double mu, co
   /* true residual of the returned iterate */
   stiffness_apply(&g, lam, mu, E, u_out, q);
   for (long i = 0; i < nd; ++i) q[i] = f[i] - q[i];
-  if (relres_true) *relres_true = (fnorm > 0.0) ? sqrt(dot(nd, q, q)) / fnorm : 0.0;
+  if (relres_true) *relres_true = (fnorm > 0.0) ? sqrt(dotm(dot_mode, nd, q, q)) / fnorm : 0.0;
 
   /* zero-mean fluctuation (Sec. 5 on mean shifts) and homogenised stress */
   if (remove_mean)

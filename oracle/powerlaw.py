@@ -257,19 +257,36 @@ def jacobi_diag(u, macro, phase, prm: PowerLaw, lengths=None):
 
 
 # ------------------------------------------------------------- solvers ----
-def pcg(Kop, f, pc, diag=None, G=None, tol=1e-8, maxit=5000):
+def _ulp_noise(rng):
+    """One-ulp moves of every nonzero entry in seeded random directions (the
+    C oracle's rounding-difference model for parity windows); identity when
+    rng is None."""
+    def noisy(x):
+        if rng is None:
+            return x
+        up = rng.random(x.shape) < 0.5
+        moved = np.where(up, np.nextafter(x, np.inf), np.nextafter(x, -np.inf))
+        return np.where(x == 0.0, 0.0, moved)
+    return noisy
+
+
+def pcg(Kop, f, pc, diag=None, G=None, tol=1e-8, maxit=5000, noise=None):
     """Textbook PCG on K du = f from du = 0, stop at ||r|| <= tol ||f||
-    (recursive residual); the preconditioner is oracle.precond."""
+    (recursive residual); the preconditioner is oracle.precond.  noise: a
+    function applied to every K p and M^-1 r result (rounding-difference
+    model), or None."""
+    if noise is None:
+        noise = _ulp_noise(None)
     x = np.zeros_like(f)
     r = f.copy()
     fn = np.linalg.norm(f)
     if fn == 0.0:
         return x, 0
-    z, _ = oracle.precond(pc, r, diag=diag, G=G)
+    z = noise(oracle.precond(pc, r, diag=diag, G=G)[0])
     p = z.copy()
     rz = float((r * z).sum())
     for k in range(maxit):
-        q = Kop(p)
+        q = noise(Kop(p))
         pq = float((p * q).sum())
         if not pq > 0.0:  # breakdown (nothing left that the preconditioner sees)
             return x, k
@@ -278,7 +295,7 @@ def pcg(Kop, f, pc, diag=None, G=None, tol=1e-8, maxit=5000):
         r -= alpha * q
         if np.linalg.norm(r) <= tol * fn:
             return x, k + 1
-        z, _ = oracle.precond(pc, r, diag=diag, G=G)
+        z = noise(oracle.precond(pc, r, diag=diag, G=G)[0])
         rz_new = float((r * z).sum())
         p = z + (rz_new / rz) * p
         rz = rz_new
@@ -296,11 +313,13 @@ class NewtonResult:
 
 def newton(phase, macro, prm: PowerLaw, pc=oracle.PC_GREEN_JACOBI, newton_tol=1e-5,
            pcg_tol=1e-8, max_newton=20, maxit=5000, lam_ref=None, mu_ref=None, lengths=None,
-           pcg_absolute=False):
+           pcg_absolute=False, noise_seed=0):
     """Newton with PCG inner solves from u^(0) = 0 (Sec. 2.2); the Green
     reference material defaults to the inclusion's.  pcg_absolute: the inner
     solve stops at ||r||^2 <= pcg_tol (the stopping rule of Sec. 4) instead
-    of the relative rule with the inexact-Newton floor."""
+    of the relative rule with the inexact-Newton floor.  noise_seed != 0
+    turns on the rounding-difference model in every PCG solve."""
+    noise = _ulp_noise(np.random.default_rng(noise_seed) if noise_seed else None)
     shape = phase.shape
     if lam_ref is None:
         lam_ref, mu_ref = prm.K_incl - 2.0 * prm.mu_incl / 3.0, prm.mu_incl
@@ -326,7 +345,7 @@ def newton(phase, macro, prm: PowerLaw, pc=oracle.PC_GREEN_JACOBI, newton_tol=1e
             # inexact Newton: no inner solve below a tenth of the Newton tolerance
             rtol = max(pcg_tol, 0.1 * newton_tol / fn)
         du, k = pcg(lambda p: tangent_op(u, p, macro, phase, prm, lengths), f, pc, diag, G,
-                    rtol, maxit)
+                    rtol, maxit, noise)
         out.pcg_iters.append(k)
         u = u + du
     out.u = u

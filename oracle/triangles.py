@@ -30,6 +30,7 @@ the product library.  The preconditioner application is the C oracle's
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -179,21 +180,47 @@ class SolveResult:
 
 
 def solve(E, macro, lam, mu, pc=oracle.PC_GREEN_JACOBI, lam_ref=None, mu_ref=None, tol=1e-8,
-          maxit=5000, void_value=1.0, stop_absolute=False, lengths=None):
+          maxit=5000, void_value=1.0, stop_absolute=False, lengths=None, f=None, noise_seed=0,
+          dot_mode=0):
     """PCG on K u = f from u = 0 (the C oracle's loop, with the triangle
-    operators), then mean removal and sigma_bar."""
+    operators), then mean removal and sigma_bar.  f defaults to the assembled
+    right-hand side; a given f replaces it (the cancellation test of the
+    homogeneous case still uses the assembled |f|).  noise_seed != 0 moves
+    every entry of each K p and M^-1 r result by one ulp in a seeded random
+    direction, the C oracle's rounding-difference model for parity windows;
+    dot_mode = 1 sums the products of every inner product and norm with
+    math.fsum (correctly rounded) instead of numpy's pairwise sum."""
     E = np.asarray(E, dtype=np.float64)
     if lam_ref is None:
         lam_ref, mu_ref = lam, mu
-    f, fa = rhs(E, macro, lam, mu, lengths, with_abs=True)
+    f_asm, fa = rhs(E, macro, lam, mu, lengths, with_abs=True)
+    f = f_asm if f is None else np.asarray(f, dtype=np.float64)
     fn, fan = np.linalg.norm(f), np.linalg.norm(fa)
+    if dot_mode == 1:
+        fn = math.sqrt(math.fsum((f * f).ravel()))
     diag = jacobi_diag(E, lam, mu, lengths) if pc in (oracle.PC_JACOBI,
                                                       oracle.PC_GREEN_JACOBI) else None
     G = green(E.shape, lam_ref, mu_ref, lengths) if pc in (oracle.PC_GREEN,
                                                            oracle.PC_GREEN_JACOBI) else None
 
+    rng = np.random.default_rng(noise_seed) if noise_seed else None
+
+    def noisy(x):
+        if rng is None:
+            return x
+        up = rng.random(x.shape) < 0.5
+        moved = np.where(up, np.nextafter(x, np.inf), np.nextafter(x, -np.inf))
+        return np.where(x == 0.0, 0.0, moved)
+
     def M(r):
-        return oracle.precond(pc, r, diag=diag, G=G, void_value=void_value, lengths=lengths)[0]
+        return noisy(oracle.precond(pc, r, diag=diag, G=G, void_value=void_value,
+                                    lengths=lengths)[0])
+
+    def dot(a, b):
+        return math.fsum((a * b).ravel()) if dot_mode == 1 else float((a * b).sum())
+
+    def norm(a):
+        return math.sqrt(dot(a, a)) if dot_mode == 1 else np.linalg.norm(a)
 
     def done(rn):
         return rn * rn <= tol if stop_absolute else rn <= tol * fn
@@ -204,16 +231,16 @@ def solve(E, macro, lam, mu, pc=oracle.PC_GREEN_JACOBI, lam_ref=None, mu_ref=Non
     hist = []
     status = "ok"
     homog = fn <= 1e-13 * fan
-    if not (homog or done(np.linalg.norm(r))):
+    if not (homog or done(norm(r))):
         z = M(r)
         p = z.copy()
-        rz = float((r * z).sum())
+        rz = dot(r, z)
         while True:
             if k >= maxit:
                 status = "not_converged"
                 break
-            q = stiffness(E, p, lam, mu, lengths)
-            pq = float((p * q).sum())
+            q = noisy(stiffness(E, p, lam, mu, lengths))
+            pq = dot(p, q)
             alpha = rz / pq
             if not (pq > 0.0) or not np.isfinite(alpha):
                 status = "breakdown"
@@ -221,14 +248,14 @@ def solve(E, macro, lam, mu, pc=oracle.PC_GREEN_JACOBI, lam_ref=None, mu_ref=Non
             u += alpha * p
             r -= alpha * q
             k += 1
-            hist.append(np.linalg.norm(r))
+            hist.append(norm(r))
             if done(hist[-1]):
                 break
             if k >= maxit:
                 status = "not_converged"
                 break
             z = M(r)
-            rz_new = float((r * z).sum())
+            rz_new = dot(r, z)
             p = z + (rz_new / rz) * p
             rz = rz_new
     u -= u.reshape(2, -1).mean(axis=1).reshape(2, 1, 1)

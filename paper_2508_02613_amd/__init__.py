@@ -64,6 +64,7 @@ _SIGS = {
     "jfft_get_tunables": (C.c_int, [_vp, C.POINTER(_Tunables)]),
     "jfft_apply_stiffness": (C.c_int, [_vp, _vp, _vp]),
     "jfft_apply_precond": (C.c_int, [_vp, _vp, _vp]),
+    "jfft_apply_precond_fp32": (C.c_int, [_vp, _vp, _vp]),
     "jfft_assemble_rhs": (C.c_int, [_vp, _dp, _vp]),
     "jfft_jacobi_diag": (C.c_int, [_vp, _vp]),
     "jfft_enable_history": (C.c_int, [_vp, C.c_int]),
@@ -341,10 +342,13 @@ class Cell:
         self.stream.synchronize()
         return out
 
-    def apply_precond(self, x):
+    def apply_precond(self, x, fp32=False):
+        """M^-1 x in FP64, or (fp32=True, mixed cells) as the FP32 inner
+        solves apply it (x rounded to FP32, the result widened to FP64)."""
         x = self._dev(x, (self.dim,) + self.shape)
         out = self.torch.empty_like(x)
-        _check(self._lib.jfft_apply_precond(self._h, _ptr(x), _ptr(out)))
+        fn = self._lib.jfft_apply_precond_fp32 if fp32 else self._lib.jfft_apply_precond
+        _check(fn(self._h, _ptr(x), _ptr(out)))
         self.stream.synchronize()
         return out
 

@@ -541,33 +541,34 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
   // Z[k] = (X[k] + conj X[m-k]) + i conj(w^k) (X[k] - conj X[m-k]), k < m.
   // A thread owns the pair (k, m - k) of one row: it reads and writes only
   // those two slots, so no barrier is needed inside the loop.
+  // (Straight-line code: a small array indexed by a run-time count would be
+  // placed in per-lane scratch memory.)
   const int half = m / 2 + 1;
+  auto unsplit = [&](C xk, C xm, int q) {
+    C e, d;
+    e.x = xk.x + xm.x;
+    e.y = xk.y - xm.y;
+    d.x = xk.x - xm.x;
+    d.y = xk.y + xm.y;
+    C wc = tw[q];
+    wc.y = -wc.y;
+    const C o = cmul(wc, d);
+    C z;
+    z.x = e.x - o.y;  // e + i o
+    z.y = e.y + o.x;
+    return z;
+  };
   for (int f = threadIdx.x; f < RB * half; f += FFT_THREADS) {
     const int row = a.dhalf.div(f), k = f - row * half;
     const C xa = buf[row * sc + k];
     const C xb = buf[row * sc + (m - k)];
-    C zk[2];
-    int kk[2];
-    int cnt = 0;
-    for (int t = 0; t < 2; ++t) {
-      const int q = t == 0 ? k : m - k;
-      if (t == 1 && (q == k || q == m)) break;  // self pair, or k = 0 (no Z[m])
-      const C xk = t == 0 ? xa : xb;
-      const C xm = t == 0 ? xb : xa;
-      C e, d;
-      e.x = xk.x + xm.x;
-      e.y = xk.y - xm.y;
-      d.x = xk.x - xm.x;
-      d.y = xk.y + xm.y;
-      C wc = tw[q];
-      wc.y = -wc.y;
-      const C o = cmul(wc, d);
-      zk[cnt].x = e.x - o.y;  // e + i o
-      zk[cnt].y = e.y + o.x;
-      kk[cnt] = q;
-      ++cnt;
-    }
-    for (int t = 0; t < cnt; ++t) buf[row * sc + kk[t]] = zk[t];
+    const C z0 = unsplit(xa, xb, k);
+    // the partner slot m - k, unless it is k itself or k = 0 (no Z[m])
+    const bool two = k != 0 && 2 * k != m;
+    C z1 = z0;
+    if (two) z1 = unsplit(xb, xa, m - k);
+    buf[row * sc + k] = z0;
+    if (two) buf[row * sc + (m - k)] = z1;
   }
   __syncthreads();
   lds_fft<Real, true>(buf, a.plan, RB, 1, sc, tw, 2, true);
@@ -620,11 +621,18 @@ __global__ void __launch_bounds__(NT) k_ypass(YArgs<Real> a) {
   const int npts = L * TW;
   const long long per_comp = (long long)a.nz * a.ntx;  // gridDim.y = components
   C *const comp_base = spec + (long long)blockIdx.y * per_comp * npts;
-  C pre[PPT];
+  // The prefetch is held as separate real and imaginary arrays: an array of
+  // double-complex values here is placed in per-lane scratch memory by the
+  // compiler, which doubles the pass's memory traffic.
+  Real pre_re[PPT], pre_im[PPT];
   auto load = [&](long long t) {  // unconditional loads at clamped positions
     const C *base = comp_base + t * npts;
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) pre[j] = base[min((int)threadIdx.x + j * NT, npts - 1)];
+    for (int j = 0; j < PPT; ++j) {
+      const C v = base[min((int)threadIdx.x + j * NT, npts - 1)];
+      pre_re[j] = v.x;
+      pre_im[j] = v.y;
+    }
   };
   long long t = blockIdx.x;
   if (t < per_comp) load(t);
@@ -632,7 +640,12 @@ __global__ void __launch_bounds__(NT) k_ypass(YArgs<Real> a) {
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const int f = threadIdx.x + j * NT;
-      if (f < npts) buf[f] = pre[j];
+      if (f < npts) {
+        C v;
+        v.x = pre_re[j];
+        v.y = pre_im[j];
+        buf[f] = v;
+      }
     }
     __syncthreads();
     if (t + gridDim.x < per_comp) load(t + gridDim.x);
@@ -661,10 +674,10 @@ struct GArgs {
   long long cs;           // bytes between the cells of a batch (cell = blockIdx.z)
   double *partB;          // per-block partials of r.z (Parseval, see k_green_axis)
   // 2D linear triangles (tri != 0): K^_ref from its 3 x 3 stencil (see
-  // green2_tri); twx = exp(-2 pi i j / nx) for the x wavenumber
+  // green2_tri)
   int tri;
-  const double2 *twx;
   double tS[9][3];
+  double hx, hy;  // node spacings (the triangles' symbol reads cos - 1 off the a tables)
 };
 
 // Green multiply at one frequency: zh = G^(k) sh with G^ = K^_ref(k)^-1 / N,
@@ -740,8 +753,15 @@ __device__ __forceinline__ void green2(const T (&A)[2], const T (&B)[2], const T
 // symmetric (it is not of the separable quadrilateral form: the split is not
 // symmetric under the reflection of one axis).  S[d] = (S_00, S_11, S_01) of
 // offset d = (dx, dy), index (dy + 1) * 3 + dx + 1.
+// Rigid translations lie in the kernel of K_ref, so sum_d S_d = 0 and
+// K^ = sum_d S_d (cos(theta . d) - 1).  That form is evaluated from
+// cm = cos(theta) - 1 and s = sin(theta) per axis (cm from the accurate
+// 4 sin^2(theta / 2) table): every term is O(theta^2), where the plain cosine
+// sum would cancel O(1) terms down to O(theta^2) and lose the low
+// frequencies' accuracy (in FP32 about 1e-3 relative at the lowest
+// frequency of a 512-point axis).
 template <typename T, typename C>
-__device__ __forceinline__ void green2_tri(T cx, T sx, T cy, T sy, const double (&S)[9][3],
+__device__ __forceinline__ void green2_tri(T cmx, T sx, T cmy, T sy, const double (&S)[9][3],
                                            T invN, bool zero, C (&v)[2]) {
   if (zero) {
     for (int i = 0; i < 2; ++i) v[i].x = v[i].y = 0;
@@ -752,10 +772,12 @@ __device__ __forceinline__ void green2_tri(T cx, T sx, T cy, T sy, const double 
   for (int dy = -1; dy <= 1; ++dy)
 #pragma unroll
     for (int dx = -1; dx <= 1; ++dx) {
-      // cos(theta_x dx + theta_y dy)
-      const T cxd = dx ? cx : (T)1, sxd = (T)dx * sx;
-      const T cyd = dy ? cy : (T)1, syd = (T)dy * sy;
-      const T cd = cxd * cyd - sxd * syd;
+      if (dx == 0 && dy == 0) continue;  // cos(0) - 1 = 0
+      // cos(theta_x dx + theta_y dy) - 1
+      //   = cmx' cmy' + cmx' + cmy' - sx' sy',  cm' = cm (d != 0) or 0, s' = d s
+      const T cxd = dx ? cmx : (T)0, sxd = (T)dx * sx;
+      const T cyd = dy ? cmy : (T)0, syd = (T)dy * sy;
+      const T cd = cxd * cyd + cxd + cyd - sxd * syd;
       const int o = (dy + 1) * 3 + dx + 1;
       k00 += (T)S[o][0] * cd;
       k11 += (T)S[o][1] * cd;
@@ -797,13 +819,16 @@ __global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
   const long long axis_stride = DIM == 3 ? (long long)a.ntx * a.ny * TW : TW;
   C *const base = spec + (DIM == 3 ? ((long long)kt * a.ny + ky0) * TW : (long long)kt * a.ny * TW);
   const int npts = L * LN;
-  C pre[PPT];
+  // prefetch as separate real and imaginary arrays (see k_ypass)
+  Real pre_re[PPT], pre_im[PPT];
   auto load = [&](int c) {  // unconditional loads at clamped positions
     const C *bc = base + c * comp_stride;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const int f = min((int)threadIdx.x + j * NT, npts - 1);
-      pre[j] = bc[(long long)(f / LN) * axis_stride + f % LN];
+      const C v = bc[(long long)(f / LN) * axis_stride + f % LN];
+      pre_re[j] = v.x;
+      pre_im[j] = v.y;
     }
   };
   C stash[DIM][PPT];
@@ -813,7 +838,12 @@ __global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const int f = threadIdx.x + j * NT;
-      if (f < npts) buf[f] = pre[j];
+      if (f < npts) {
+        C v;
+        v.x = pre_re[j];
+        v.y = pre_im[j];
+        buf[f] = v;
+      }
     }
     __syncthreads();
     if (c + 1 < DIM) load(c + 1);
@@ -859,8 +889,9 @@ __global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
         const Real S[2] = {(Real)a.tx.s[kx], (Real)a.ty.s[t]};
         C v[2] = {stash[0][j], stash[1][j]};
         if (a.tri) {
-          const double2 ex = a.twx[kx], ey = a.tw[t];
-          green2_tri<Real>((Real)ex.x, (Real)-ex.y, (Real)ey.x, (Real)-ey.y, a.tS, (Real)a.invN,
+          // cos(theta) - 1 = -a h / 2 with a = 4 sin^2(theta / 2) / h
+          const Real cmx = (Real)(-0.5 * a.tx.a[kx] * a.hx), cmy = (Real)(-0.5 * a.ty.a[t] * a.hy);
+          green2_tri<Real>(cmx, (Real)a.tx.s[kx], cmy, (Real)a.ty.s[t], a.tS, (Real)a.invN,
                            kx == 0 && t == 0, v);
         } else {
           green2<Real>(A, B, S, (Real)a.lam, (Real)a.mu, (Real)a.invN, kx == 0 && t == 0, v);

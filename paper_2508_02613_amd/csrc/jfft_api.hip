@@ -402,7 +402,9 @@ jfft_status upload_tables(jfft_cell_s *c) {
       const double cs = std::cos(t), sn = std::sin(t);
       tw[j].x = cs;
       tw[j].y = -sn;
-      A[j] = (2.0 - 2.0 * cs) / hs[a];
+      // 2 - 2 cos(t) = 4 sin^2(t / 2), without the cancellation at small t
+      const double sh = std::sin(M_PI * (double)j / (double)n);
+      A[j] = 4.0 * sh * sh / hs[a];
       Bt[j] = hs[a] * (2.0 + cs) / 3.0;
       S[j] = sn;
     }
@@ -746,8 +748,9 @@ jfft_status launch_green(jfft_cell_s *c, typename CxT<Real>::T *spec, bool check
   a.check_done = check_done ? 1 : 0;
   a.cs = c->cs;
   a.tri = c->elem == JFFT_ELEM_TRI ? 1 : 0;
-  a.twx = c->tw[0];
   std::memcpy(a.tS, c->tS, sizeof(a.tS));
+  a.hx = c->len[0] / c->n[0];
+  a.hy = c->len[1] / c->n[1];
   constexpr int TW = TileW<Real>::value;
   const int L = c->dim == 3 ? c->g.nz : c->g.ny;
   if (c->dim == 3) {
@@ -1667,6 +1670,9 @@ jfft_status create_impl(int dim, const int n[3], const double len[3], jfft_preci
   }
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&c->st_h), sizeof(CgState) * batch, hipHostMallocDefault);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&c->small_h), sizeof(double) * kSmall * batch, hipHostMallocDefault);
+  // the solve's phase events, created here so that a solve creates none
+  for (auto &pe : c->phase_ev)
+    if (e == hipSuccess) e = hipEventCreate(&pe);
   if (e != hipSuccess) {
     delete c;
     return fail(JFFT_E_HIP, std::string("create: ") + hipGetErrorString(e));
@@ -1766,6 +1772,20 @@ jfft_status jfft_apply_precond(jfft_cell_t c, const double *in_dev, double *out_
   History h{nullptr, nullptr, nullptr};
   TRY(precond<double>(c, c->r, nullptr, c->Jh, c->z, c->spec, false, false, &nA, &nB, h));
   LAUNCH(c, KID_VEC, k_copy<double><<<dim3(vec_blocks(nd), 1), 256, 0, c->stream>>>(c->z, 0, out_dev, 0, nd));
+  return JFFT_OK;
+}
+
+jfft_status jfft_apply_precond_fp32(jfft_cell_t c, const double *in_dev, double *out_dev) {
+  if (!c || !in_dev || !out_dev) return fail(JFFT_E_INVALID, "NULL argument");
+  if (!c->has_material) return fail(JFFT_E_NO_MATERIAL, "set the material first");
+  if (c->B != 1) return fail(JFFT_E_INVALID, "operator entry points take a single-cell handle");
+  if (c->prec != JFFT_MIXED) return fail(JFFT_E_INVALID, "the FP32 preconditioner belongs to a mixed-precision cell");
+  const long long nd = (long long)c->dim * c->g.N;
+  LAUNCH(c, KID_VEC, (k_convert<double, float><<<dim3(vec_blocks(nd), 1), 256, 0, c->stream>>>(in_dev, c->r32, nd, 1.0, nullptr, 0)));
+  long long nA, nB;
+  History h{nullptr, nullptr, nullptr};
+  TRY(precond<float>(c, c->r32, nullptr, c->Jh32, c->z32, c->spec32, false, false, &nA, &nB, h));
+  LAUNCH(c, KID_VEC, (k_convert<float, double><<<dim3(vec_blocks(nd), 1), 256, 0, c->stream>>>(c->z32, out_dev, nd, 1.0, nullptr, 0)));
   return JFFT_OK;
 }
 

@@ -15,7 +15,7 @@ LIB = os.path.join(ROOT, "paper_2508_02613_amd", "libjfft.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(jfft_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(jfft_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_core_entry_points():

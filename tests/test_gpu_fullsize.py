@@ -6,6 +6,11 @@ one by one or on properties that hold at any size:
 * the Algorithm 2 diagonal against its closed form for isotropic Q1/hex
   elements, diag = k * (sum of the moduli of the elements around the node),
   with k read off the oracle on a small grid;
+* the Green-Jacobi preconditioner element by element against the oracle's
+  (Algorithm 1's G^ from impulse responses and its naive DFT, Algorithm 2's
+  diagonal; Sec. 3.3, eq. prec_lin_systemJG_2): FP64 to 1e-12, and the
+  mixed path's FP32 preconditioner (the kernels the headline runs) to 1e-5;
+  at 512^2 for the bilinear quadrilateral and for the linear triangles;
 * the Green-Jacobi preconditioner: symmetry x.M^-1 y = y.M^-1 x and
   positivity by random probes;
 * full solves (mixed and FP64): the oracle recomputes f - K u at sampled
@@ -17,6 +22,7 @@ import pytest
 
 import jfft_inputs as ji
 import oracle
+from oracle import triangles as tri
 
 pytestmark = pytest.mark.gpu
 
@@ -112,6 +118,80 @@ def test_jacobi_diag_closed_form(big):
     rel = np.abs(dg - k * s[None]).max() / np.abs(dg).max()
     say(f"  {shape}: max |diag - k sum E| / max diag = {rel:.2e}")
     assert rel <= 1e-12
+
+
+# Error bounds for M^-1 r = J^1/2 F^-1 G^ F J^1/2 r.  The FFT passes and the
+# Green multiply have normwise error bounds relative to the transformed
+# field, so the comparison is made on t = J^-1/2 z, the output of the Green
+# operator before the outer scaling (the outer J^1/2 only rescales each
+# entry by a value both sides share; on the 512^2 SIMP field, contrast 1e9,
+# it spans four decades and would carry the Green operator's normwise error
+# into the entries where J^1/2 is large).  FP32: unit roundoff 2^-24 = 6e-8
+# times the rounding steps along a value's path, added linearly (worst
+# case): about 2 log2(n) radix stages per FFT axis and direction at
+# n = 256 (48 in 3D), ~20 operations of the Green symbol and its inverse,
+# two J^1/2 scalings and the input rounding: ~75 x 6e-8 = 4.5e-6 < 1e-5.
+# FP64: the same count at 2^-53 is below 1e-14; the bar is 1e-12.
+FP32_PRECOND_TOL = 1e-5
+FP64_PRECOND_TOL = 1e-12
+
+
+def _precond_case(shape, element="quad"):
+    """Input, oracle M^-1 r (Green-Jacobi) and the oracle's J^1/2 for one grid."""
+    E = _field(shape)
+    dim = len(shape)
+    r = np.random.default_rng(11).standard_normal((dim,) + shape)
+    if element == "tri":
+        dg = tri.jacobi_diag(E, LAM, MU)
+        G = tri.green(shape, LAM, MU)
+    else:
+        dg, _ = oracle.jacobi_diag(E, LAM, MU)
+        G = oracle.green(shape, LAM, MU)
+    zr, ratio = oracle.precond(oracle.PC_GREEN_JACOBI, r, diag=dg, G=G)
+    del G
+    # the oracle's own check: the inverse transform of a real field's
+    # spectrum times G^ is real up to the naive DFT's rounding, which grows
+    # with the transform length (~1e-12 of max |Re| at 512 points)
+    say(f"  oracle max |Im| / max |Re| = {ratio:.1e}")
+    assert ratio <= 1e-10
+    jh = 1.0 / np.sqrt(np.where(dg == 0.0, 1.0, dg))  # the void rule, replacement 1
+    return E, r, zr, jh
+
+
+def _errors(z, zr, jh):
+    """(relative 2-norm, max / max) errors of t = z / J^1/2, and the max / max
+    error of z itself."""
+    t, tr = z / jh, zr / jh
+    return (np.linalg.norm(t - tr) / np.linalg.norm(tr), np.abs(t - tr).max() / np.abs(tr).max(),
+            np.abs(z - zr).max() / np.abs(zr).max())
+
+
+@pytest.mark.parametrize("shape,element", [((256, 256, 256), "quad"), ((512, 512), "quad"),
+                                           ((512, 512), "tri")],
+                         ids=["256x256x256", "512x512", "512x512-tri"])
+def test_precond_matches_oracle_full_size(shape, element):
+    """M^-1 r (Green-Jacobi) at the benchmark sizes against the oracle's,
+    element by element on t = J^-1/2 M^-1 r (see the bounds above): the FP64
+    path to FP64_PRECOND_TOL of max |t|; a mixed cell's FP32 preconditioner
+    (256- and 512-point FFT stages, the 512-thread Green pass of the 3D
+    headline) to FP32_PRECOND_TOL in the relative 2-norm and element-wise
+    against max |t|."""
+    pkg = _pkg()
+    say(f"full-size M^-1 vs oracle {shape} {element}")
+    E, r, zr, jh = _precond_case(shape, element)
+    for prec in (pkg.FP64, pkg.MIXED):
+        cell = pkg.Cell(shape, precision=prec, pc=pkg.PC_GREEN_JACOBI, element=element)
+        cell.set_material(E, nu=0.3)
+        z64 = cell.apply_precond(r).cpu().numpy()
+        e2, em, ez = _errors(z64, zr, jh)
+        say(f"  precision={prec}: FP64 M^-1: t 2-norm {e2:.2e} t max {em:.2e} (z max {ez:.2e})")
+        assert em <= FP64_PRECOND_TOL
+        if prec == pkg.MIXED:
+            z32 = cell.apply_precond(r, fp32=True).cpu().numpy()
+            e2, em, ez = _errors(z32, zr, jh)
+            say(f"  FP32 M^-1: t 2-norm {e2:.2e} t max {em:.2e} (z max {ez:.2e})")
+            assert e2 <= FP32_PRECOND_TOL and em <= FP32_PRECOND_TOL
+        cell.close()
 
 
 def test_green_jacobi_symmetric_positive(big):

@@ -1,11 +1,19 @@
 """GPU parity: the HIP path (through the C ABI) against the plain CPU oracle on
 the same seeded inputs.  Operators element by element; full solves by the
-mean-free fluctuation, iteration counts (+-1), early CG scalars and sigma_bar.
+mean-free fluctuation, iteration counts, early CG scalars and sigma_bar.
 
 Tolerances (FP64 path): operators 1e-12 relative to the field's max (a few
-hundred rounding steps of O(1e-16)); solutions 1e-10 relative in the
-mean-free 2-norm at tol 1e-8 when both codes follow the same recurrence (the
-build's parity bar), early alpha_k / beta_k 1e-10 while ||r_k|| > 1e-4 ||r_0||.
+hundred rounding steps of O(1e-16)).  Solves: at the configurations' tol 1e-8
+the iteration count lies in the oracle's own window (min - 1 .. max + 1 of
+its ten counts with serial and with Dot2 inner products, on the input, on
+inputs changed by one ulp and with its rounding-difference model on, see
+oracle_spread.py), sigma_bar agrees to 1e-8, the distance of the GPU
+solution from the exact discrete solution is at most 10x the largest such
+distance of those oracle runs, and alpha_k / beta_k agree to 1e-9 on the
+prefix where the oracle agrees with its own perturbed run.  The 1e-10 bar on
+the mean-free fluctuation applies at tol 1e-12, where both codes sit next to
+the exact discrete solution: at tol 1e-8 each stops about 1e-8 away from it,
+in directions that rounding decides.
 """
 import os
 
@@ -14,6 +22,7 @@ import pytest
 
 import jfft_inputs as ji
 import oracle
+from oracle_spread import iteration_window
 
 pytestmark = pytest.mark.gpu
 
@@ -119,52 +128,58 @@ def stable_prefix(x, y, thresh=1e-12):
     return int(bad[0]) if len(bad) else n
 
 
-def check_parity(pkg, E, macro, pc, u0=None, maxit=20000, it_tol=1, tight=True, tol_u_tight=1e-10):
+def check_parity(pkg, E, macro, pc, u0=None, maxit=20000, tight=True, tol_u_tight=1e-10):
     """Parity of one solve, following the same recurrence on both sides.
 
-    At tol 1e-8: iteration counts within it_tol, sigma_bar to 1e-8, the true
-    residual <= 1.5e-8, and alpha_k / beta_k to 1e-9 on the prefix where the
-    oracle agrees with its own run from a start perturbed by one ulp (CG
-    amplifies rounding; later scalars are not reproducible even by the
-    oracle).  At tol 1e-12 (both near the exact discrete solution) the
-    mean-free fluctuations agree to tol_u_tight."""
+    At tol 1e-8: the iteration count in the oracle's window (oracle_spread),
+    sigma_bar to 1e-8, the true residual <= 1.5e-8, the distance from the
+    exact discrete solution (the oracle's tol-1e-12 solution) at most 10x the
+    largest distance of the ten oracle runs at tol 1e-8, and alpha_k /
+    beta_k to 1e-9 on the prefix where the oracle agrees with its own run on
+    f (1 + 2^-52) (CG amplifies rounding; later scalars are not reproducible
+    even by the oracle).  At tol 1e-12 (both near the exact discrete solution)
+    the mean-free fluctuations agree to tol_u_tight (unless tight=False)."""
     hist = 256
     ug, sbar, rep, (a, b, res) = _gpu_solve(pkg, E, macro, pc, 1e-8, maxit, u0, hist)
-    ref = oracle.solve(E, macro, LAM, MU, pc=pc, tol=1e-8, maxit=maxit, u0=u0, hist_len=hist)
-    if u0 is None:
-        f = oracle.rhs(E, macro, LAM, MU) * (1 + 2.0 ** -52)
-        ref2 = oracle.solve(E, macro, LAM, MU, pc=pc, tol=1e-8, maxit=maxit, f=f, hist_len=hist)
-    else:
-        ref2 = oracle.solve(E, macro, LAM, MU, pc=pc, tol=1e-8, maxit=maxit,
-                            u0=u0 * (1 + 2.0 ** -52), hist_len=hist)
+    f = oracle.rhs(E, macro, LAM, MU)
+    lo, hi, counts, runs = iteration_window(
+        lambda Ev, fv, ns, dm: oracle.solve(Ev, macro, LAM, MU, pc=pc, tol=1e-8, maxit=maxit,
+                                        u0=u0, f=fv, hist_len=hist, noise_seed=ns, dot_mode=dm), E, f)
+    ref, ref2 = runs[0], runs[1]
+    exact = oracle.solve(E, macro, LAM, MU, pc=pc, tol=1e-12, maxit=maxit, u0=u0)
+    un = np.linalg.norm(exact.u)
+    e_or = max(np.linalg.norm(r.u - exact.u) / un for r in runs)
+    e_gpu = np.linalg.norm(ug - exact.u) / un
     ka = stable_prefix(ref.alpha, ref2.alpha)
     da = np.abs(a[:ka] / ref.alpha[:ka] - 1).max() if ka else 0.0
     kb = min(stable_prefix(ref.beta, ref2.beta), len(b))
     db = np.abs(b[:kb] / ref.beta[:kb] - 1).max() if kb else 0.0
     err8 = np.linalg.norm(ug - ref.u) / np.linalg.norm(ref.u)
     ds = np.abs(sbar - ref.sigma_bar).max() / np.abs(ref.sigma_bar).max()
-    say(f"  tol 1e-8: iters gpu={rep.iters} oracle={ref.iters} err(u)={err8:.2e} "
+    say(f"  tol 1e-8: iters gpu={rep.iters} oracle={counts} window [{lo}, {hi}] "
+        f"|u-u_or|={err8:.2e} |u-u*| gpu={e_gpu:.2e} oracle max={e_or:.2e} "
         f"d_alpha={da:.1e} (first {ka}) d_beta={db:.1e} d_sigma={ds:.1e} "
         f"true_res gpu={rep.rel_res_true:.2e} oracle={ref.relres_true:.2e}")
-    assert rep.status == "ok" and ref.status == "ok", (rep.status, ref.status)
-    assert abs(rep.iters - ref.iters) <= it_tol, (rep.iters, ref.iters)
+    assert rep.status == "ok" and all(r.status == "ok" for r in runs), rep.status
+    assert lo <= rep.iters <= hi, (rep.iters, counts)
     assert ds <= 1e-8
     assert rep.rel_res_true <= 1.5e-8
     assert ka >= min(5, ref.iters) and da <= 1e-9 and db <= 1e-9
-    assert err8 <= 1e-6
+    assert e_gpu <= 10 * e_or + 1e-14
     if tight:
         ug, sbar, rep, _ = _gpu_solve(pkg, E, macro, pc, 1e-12, maxit, u0, hist)
-        ref = oracle.solve(E, macro, LAM, MU, pc=pc, tol=1e-12, maxit=maxit, u0=u0)
-        err12 = np.linalg.norm(ug - ref.u) / np.linalg.norm(ref.u)
-        say(f"  tol 1e-12: iters gpu={rep.iters} oracle={ref.iters} err(u)={err12:.2e}")
-        assert rep.status == "ok" and ref.status == "ok"
+        err12 = np.linalg.norm(ug - exact.u) / un
+        say(f"  tol 1e-12: iters gpu={rep.iters} oracle={exact.iters} err(u)={err12:.2e}")
+        assert rep.status == "ok" and exact.status == "ok"
         assert err12 <= tol_u_tight, err12
     return rep, ref
 
 
 def test_sine_contrast_32x32_green_jacobi():
     """2D 32x32 plane strain, E = 10^(2 sin 2pi x sin 2pi y), macro (1,0,0),
-    tol 1e-8, Green-Jacobi (J-FFT), u0 = 0: +-1 iteration, 1e-10 fluctuation."""
+    Green-Jacobi (J-FFT), u0 = 0: at tol 1e-8 the iteration count in the
+    oracle's window, sigma_bar to 1e-8; at tol 1e-12 the fluctuation to 1e-10
+    (check_parity)."""
     pkg = _pkg()
     say("sine contrast 32x32 J-FFT")
     check_parity(pkg, ji.sine_contrast_field(32), np.array([1.0, 0, 0]), 3)
@@ -172,13 +187,11 @@ def test_sine_contrast_32x32_green_jacobi():
 
 def test_sine_contrast_32x32_green():
     """Same problem with the Green preconditioner: about 550 iterations on an
-    ill-conditioned system, where the stopping iteration drifts with rounding
-    order; counts agree within 2 %."""
+    ill-conditioned system, where rounding moves the stopping iteration; the
+    count must lie in the oracle's own window."""
     pkg = _pkg()
     say("sine contrast 32x32 Green")
-    E = ji.sine_contrast_field(32)
-    ref_its = oracle.solve(E, np.array([1.0, 0, 0]), LAM, MU, pc=1, tol=1e-8, maxit=5000).iters
-    check_parity(pkg, E, np.array([1.0, 0, 0]), 1, it_tol=max(1, int(0.02 * ref_its)))
+    check_parity(pkg, ji.sine_contrast_field(32), np.array([1.0, 0, 0]), 1)
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
@@ -196,9 +209,7 @@ def test_3d_grf_solves(shape, pc):
     say(f"3D GRF solve {shape} pc={pc}")
     E = ji.grf_field(shape, 1e4, seed=0)
     macro = np.array([1.0, 0.0, 0.0, 0.0, 0.0, 0.0])
-    ref_its = oracle.solve(E, macro, LAM, MU, pc=pc, tol=1e-8, maxit=20000).iters
-    it_tol = 1 if pc == 3 else max(1, int(0.02 * ref_its))
-    check_parity(pkg, E, macro, pc, it_tol=it_tol, tight=(pc == 3 or max(shape) <= 8))
+    check_parity(pkg, E, macro, pc, tight=(pc == 3 or max(shape) <= 8))
 
 
 def test_homogeneous_zero_iterations():
@@ -293,3 +304,29 @@ def test_mixed_precision_reaches_1e8():
     assert err <= 1e-6, err
     assert np.abs(sbar - ref.sigma_bar).max() <= 1e-8 * np.abs(ref.sigma_bar).max()
     cell.close()
+
+
+@pytest.mark.parametrize("shape", [(24, 20), (12, 10, 18), (16, 16, 16)])
+def test_stress_field_matches_oracle(shape):
+    """The quadrature-point stresses sigma_q = C_e (macro + B_q u_e) that
+    jfft_solve returns (the field whose average is sigma_bar, Sec. 4), at the
+    GPU's own solution, against the oracle's element loop: to 1e-12 of
+    max |sigma|, and sigma_bar from the same field to 1e-12."""
+    pkg = _pkg()
+    say(f"stress field {shape}")
+    dim = len(shape)
+    E = ji.grf_field(shape, 1e3, seed=5, ell=0.2)
+    macro = np.linspace(0.7, -0.4, dim * (dim + 1) // 2)
+    cell = pkg.Cell(shape, pc=pkg.PC_GREEN_JACOBI)
+    cell.set_material(E, nu=0.3)
+    u, sbar, rep, sig = cell.solve(macro, tol=1e-8, maxit=5000, want_sigma=True)
+    ug = u.cpu().numpy()
+    sg = sig.cpu().numpy().reshape(dim * (dim + 1) // 2, 2 ** dim, -1)
+    cell.close()
+    assert rep.status == "ok"
+    sbar_ref, sq_ref = oracle.stress(E, macro, ug, LAM, MU, want_field=True)
+    err = np.abs(sg - sq_ref).max() / np.abs(sq_ref).max()
+    es = np.abs(sbar - sbar_ref).max() / np.abs(sbar_ref).max()
+    say(f"  max |sigma_q - oracle| / max |sigma| = {err:.2e}; sigma_bar {es:.2e}")
+    assert err <= 1e-12
+    assert es <= 1e-12

@@ -3,13 +3,15 @@ its numerical examples) and of its main trend on the motivating example (a
 soft inclusion in a stiff matrix, smoothed by repeated 3x3 filtering): the
 Green preconditioner wins for the sharp inclusion, Green-Jacobi wins by a
 wide margin once the data are smooth.  Iteration counts are compared with the
-oracle run under the same rule, for the four preconditioner switches.
+oracle run under the same rule, for the four preconditioner switches: the GPU
+count must lie in the oracle's own window (oracle_spread).
 """
 import numpy as np
 import pytest
 
 import jfft_inputs as ji
 import oracle
+from oracle_spread import iteration_window
 
 pytestmark = pytest.mark.gpu
 
@@ -41,14 +43,6 @@ def _gpu_iters(pkg, E, pc, tol, precision=0):
     return rep, un, sbar
 
 
-def _slack(ref, fnorm2, tol):
-    """+-1, plus the iterations over which the oracle's squared residual lies
-    within a factor 10 of the threshold (a flat convergence curve lets
-    rounding move the crossing)."""
-    rr = ref.res[:ref.iters] ** 2
-    return 1 + int(np.count_nonzero((rr >= tol / 10) & (rr <= 10 * tol)))
-
-
 @pytest.mark.parametrize("field,pc", [("sine", 1), ("sine", 3), ("sine", 2), ("sine", 0),
                                       ("incl0", 1), ("incl0", 3), ("incl8", 1), ("incl8", 3)])
 def test_absolute_rule_matches_oracle(field, pc):
@@ -57,13 +51,15 @@ def test_absolute_rule_matches_oracle(field, pc):
         ji.filtered_inclusion_field(64, int(field[4:]))
     tol = 1e-10
     rep, u, sbar = _gpu_iters(pkg, E, pc, tol)
-    ref = oracle.solve(E, [1.0, 0.0, 0.0], LAM, MU, pc=pc, tol=tol, stop_mode=1, maxit=20000,
-                       hist_len=20000)
-    f = oracle.rhs(E, [1.0, 0.0, 0.0], LAM, MU)
-    slack = _slack(ref, float((f * f).sum()), tol)
-    say(f"{field} pc={pc}: iters gpu={rep.iters} oracle={ref.iters} (slack {slack})")
+    macro = np.array([1.0, 0.0, 0.0])
+    f = oracle.rhs(E, macro, LAM, MU)
+    lo, hi, counts, runs = iteration_window(
+        lambda Ev, fv, ns, dm: oracle.solve(Ev, macro, LAM, MU, pc=pc, tol=tol, stop_mode=1,
+                                        maxit=20000, f=fv, noise_seed=ns, dot_mode=dm), E, f)
+    ref = runs[0]
+    say(f"{field} pc={pc}: iters gpu={rep.iters} oracle={counts} window [{lo}, {hi}]")
     assert rep.status == "ok" and ref.status == "ok"
-    assert abs(rep.iters - ref.iters) <= slack
+    assert lo <= rep.iters <= hi
     # the absolute rule was applied: the final recursive ||r||^2 is <= tol
     assert (rep.rel_res ** 2) * float((f * f).sum()) <= tol * 1.0001
     # with the FFT-based preconditioners the two solutions agree closely (the

@@ -559,3 +559,70 @@ def test_trend_green_vs_green_jacobi_sine_contrast_32x32():
     g = oracle.solve(E, np.array([1.0, 0, 0]), LAM, MU, pc=oracle.PC_GREEN, tol=1e-8, maxit=5000)
     gj = oracle.solve(E, np.array([1.0, 0, 0]), LAM, MU, pc=oracle.PC_GREEN_JACOBI, tol=1e-8)
     assert gj.iters < g.iters
+
+
+# ------------------------------------------------- rounding-difference models
+def test_dot2_matches_correctly_rounded_sum():
+    """Dot2 (Ogita, Rump, Oishi 2005) is as accurate as a sum in twice the
+    working precision: on ill-conditioned dot products (the terms cancel to
+    one part in ~1e16) it agrees with the exact dot product (rational
+    arithmetic, then rounded) to a few ulps, where the serial sum loses
+    digits."""
+    from fractions import Fraction
+    rng = np.random.default_rng(5)
+    worst_serial = 0.0
+    for trial in range(10):
+        n = 300
+        x = rng.standard_normal(n) * 10.0 ** rng.integers(-8, 8, n)
+        y = rng.standard_normal(n)
+        x = np.concatenate([x, -x * (1 + 2.0 ** -40), [1e-3]])
+        y = np.concatenate([y, y, [1.0]])
+        exact = float(sum(Fraction(a) * Fraction(b) for a, b in zip(x, y)))
+        d2 = oracle.dot(x, y, mode=1)
+        assert abs(d2 - exact) <= 4 * 2.0 ** -52 * abs(exact), (trial, d2, exact)
+        worst_serial = max(worst_serial, abs(oracle.dot(x, y, mode=0) - exact) / abs(exact))
+    assert worst_serial > 1e-6  # the serial sum does lose digits on these
+    # the plain dot is the serial sum in index order
+    a = rng.standard_normal(1000)
+    b = rng.standard_normal(1000)
+    s = 0.0
+    for u, v in zip(a, b):
+        s += u * v
+    assert oracle.dot(a, b, mode=0) == s
+
+
+def test_rounding_models_keep_the_solution():
+    """The parity-window options change rounding only: with Dot2 inner
+    products or one-ulp noise on every K p and M^-1 r result the solve
+    reaches the same solution (to the tolerance) and the early CG scalars
+    agree to rounding; the noisy run's scalars differ from the plain run's
+    (the noise is on); noise_seed = 0 with dot_mode = 0 is the plain
+    arithmetic bit for bit."""
+    E = ji.sine_contrast_field(32)
+    m = np.array([1.0, 0.0, 0.0])
+    base = oracle.solve(E, m, LAM, MU, pc=3, tol=1e-12, maxit=500, hist_len=100)
+    for kw in (dict(dot_mode=1), dict(noise_seed=7), dict(noise_seed=7, dot_mode=1)):
+        r = oracle.solve(E, m, LAM, MU, pc=3, tol=1e-12, maxit=500, hist_len=100, **kw)
+        assert r.status == "ok"
+        assert np.linalg.norm(r.u - base.u) <= 1e-10 * np.linalg.norm(base.u)
+        assert np.abs(r.alpha[:3] / base.alpha[:3] - 1).max() <= 1e-12
+        assert abs(r.iters - base.iters) <= 2
+        if "noise_seed" in kw:
+            assert not np.array_equal(r.alpha[:5], base.alpha[:5])
+    again = oracle.solve(E, m, LAM, MU, pc=3, tol=1e-12, maxit=500, hist_len=100, noise_seed=0,
+                         dot_mode=0)
+    assert np.array_equal(again.u, base.u) and np.array_equal(again.alpha, base.alpha)
+
+
+def test_triangle_and_powerlaw_rounding_models():
+    """The same options in the numpy oracles: a Dot2-like (math.fsum) or noisy
+    triangle solve reaches the plain solution; a noisy power-law PCG solve
+    reaches the plain one."""
+    from oracle import triangles as tri
+    E = ji.sine_contrast_field(16)
+    m = np.array([1.0, 0.0, 0.0])
+    base = tri.solve(E, m, LAM, MU, pc=3, tol=1e-12, maxit=500)
+    for kw in (dict(dot_mode=1), dict(noise_seed=3)):
+        r = tri.solve(E, m, LAM, MU, pc=3, tol=1e-12, maxit=500, **kw)
+        assert r.status == "ok" and abs(r.iters - base.iters) <= 2
+        assert np.linalg.norm(r.u - base.u) <= 1e-10 * np.linalg.norm(base.u)
