@@ -141,6 +141,27 @@ jfft_status jfft_solve(jfft_cell_t cell, const double *macro_strain, double tol,
                        const double *u0_dev, double *u_dev, double *sigma_dev,
                        double *sigma_bar, jfft_report *report);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc):
+   jfft_set_material (E_dev, nu) followed by jfft_solve, with the cell's
+   workspace taken from a static array of the library instead of a bound or
+   library-allocated one.  The call makes no hipMalloc, hipFree, graph or
+   event creation: kernels, copies of small host tables and one stream
+   synchronisation only.  Limit: the cell's jfft_workspace_bytes must not
+   exceed 128 MiB (a 64^3 cell in FP64 or mixed precision, 2D cells up to
+   512^2); larger cells, group handles, cells whose workspace the library
+   allocated itself and cells with kernel timing on return JFFT_E_INVALID
+   before any device work.  The array exists once per GPU for the life of
+   the process and keeps the last call's contents; every call lays the
+   workspace out again, uploads its tables and sets the material, and no
+   part of it has to start at zero.  Calls that overlap on one GPU (two
+   streams, two threads) race on it.  The cell stays bound to the array
+   until jfft_bind_workspace.  Arguments and results as for jfft_solve;
+   PCG iterations are launched directly (no graph replay). */
+jfft_status jfft_solve_static(jfft_cell_t cell, const double *E_dev, double nu,
+                              const double *macro_strain, double tol, int maxit,
+                              const double *u0_dev, double *u_dev, double *sigma_dev,
+                              double *sigma_bar, jfft_report *report);
 
 /* jfft_solve for every cell of a group at once.  Arrays are those of
    jfft_solve with a leading cell index:

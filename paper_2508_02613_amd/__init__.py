@@ -57,6 +57,8 @@ _SIGS = {
     "jfft_set_material_lame": (C.c_int, [_vp, _vp, C.c_double, C.c_double]),
     "jfft_solve": (C.c_int, [_vp, _dp, C.c_double, C.c_int, _vp, _vp, _vp, _dp,
                              C.POINTER(_Report)]),
+    "jfft_solve_static": (C.c_int, [_vp, _vp, C.c_double, _dp, C.c_double, C.c_int, _vp, _vp,
+                                    _vp, _dp, C.POINTER(_Report)]),
     "jfft_solve_batch": (C.c_int, [_vp, _dp, C.c_double, C.c_int, _vp, _vp, _vp, _dp,
                                    C.POINTER(_Report)]),
     "jfft_set_graph_iterations": (C.c_int, [_vp, C.c_int]),
@@ -190,7 +192,7 @@ class Cell:
     """
 
     def __init__(self, shape, precision=FP64, pc=PC_GREEN_JACOBI, lengths=None, stream=None,
-                 device=None, batch=1, element="quad"):
+                 device=None, batch=1, element="quad", workspace=True):
         torch = _torch()
         lib = load_library()
         self.torch = torch
@@ -217,11 +219,14 @@ class Cell:
         nb = C.c_size_t(0)
         _check(lib.jfft_workspace_bytes(h, C.byref(nb)))
         self.workspace_bytes = int(nb.value)
-        with torch.cuda.stream(self.stream):
-            self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
-        base = self._ws.data_ptr()
-        aligned = (base + 255) // 256 * 256
-        _check(lib.jfft_bind_workspace(h, C.c_void_p(aligned), self.workspace_bytes))
+        self._ws = None
+        if workspace:  # workspace=False: for solve_static only (no device memory here)
+            with torch.cuda.stream(self.stream):
+                self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8,
+                                       device=self.device)
+            base = self._ws.data_ptr()
+            aligned = (base + 255) // 256 * 256
+            _check(lib.jfft_bind_workspace(h, C.c_void_p(aligned), self.workspace_bytes))
         self.N = int(np.prod(self.shape))
         self.ds = self.dim * (self.dim + 1) // 2
 
@@ -297,6 +302,27 @@ class Cell:
         if st not in (0, 4, 5):
             _check(st)
         return u, np.array(sbar[:]), _report(rep), sig
+
+    def solve_static(self, E, nu, macro, tol=1e-8, maxit=1000, u0=None, u=None, sigma=None):
+        """jfft_solve_static: set the material and solve in the library's
+        static workspace (no device allocation inside the call).  u (and sigma,
+        if given) are caller-owned device tensors; allocated here when None.
+        Returns (u, sigma_bar, Report, sigma)."""
+        torch = self.torch
+        vshape = (self.dim,) + self.shape
+        E = self._dev(E, self.shape)
+        self._E = E
+        if u is None:
+            u = torch.empty(vshape, dtype=torch.float64, device=self.device)
+        u0t = self._dev(u0, vshape) if u0 is not None else None
+        m = (C.c_double * self.ds)(*[float(v) for v in np.asarray(macro, dtype=float)])
+        sbar = (C.c_double * self.ds)()
+        rep = _Report()
+        st = self._lib.jfft_solve_static(self._h, _ptr(E), float(nu), m, float(tol), int(maxit),
+                                         _ptr(u0t), _ptr(u), _ptr(sigma), sbar, C.byref(rep))
+        if st not in (0, 4, 5):
+            _check(st)
+        return u, np.array(sbar[:]), _report(rep), sigma
 
     def solve_batch(self, macros, tol=1e-8, maxit=1000, u0=None, want_sigma=False, out=None):
         """All cells of the group: macros [B, d*].  Returns (u [B, d, ...],

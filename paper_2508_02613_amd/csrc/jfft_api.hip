@@ -1681,6 +1681,34 @@ jfft_status create_impl(int dim, const int n[3], const double len[3], jfft_preci
   return JFFT_OK;
 }
 
+// Static workspace of jfft_solve_static: one per GPU, held until the process
+// ends.  In host code `scratch` only names the symbol; its device address
+// (a different one on every GPU) comes from hipGetSymbolAddress, taken once
+// per device with that device current and kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+jfft_status scratch_address(int device, unsigned char **out) {
+  if (device < 0 || device >= kMaxDevices) return fail(JFFT_E_INVALID, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != device) HIP_TRY(hipSetDevice(device));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) HIP_TRY(hipSetDevice(cur));
+    if (e != hipSuccess || !p)
+      return fail(JFFT_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<unsigned char *>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return JFFT_OK;
+}
+
 }  // namespace
 
 // ============================================================== C ABI ====
@@ -1745,6 +1773,42 @@ jfft_status jfft_solve(jfft_cell_t c, const double *macro_strain, double tol, in
   if (c->B != 1) return fail(JFFT_E_INVALID, "batched handle: use jfft_solve_batch");
   if (!u_dev) return fail(JFFT_E_INVALID, "NULL u_dev");
   return solve_impl(c, macro_strain, tol, maxit, u0_dev, u_dev, sigma_dev, sigma_bar, report);
+}
+
+jfft_status jfft_solve_static(jfft_cell_t c, const double *E_dev, double nu,
+                              const double *macro_strain, double tol, int maxit,
+                              const double *u0_dev, double *u_dev, double *sigma_dev,
+                              double *sigma_bar, jfft_report *report) {
+  if (!c) return fail(JFFT_E_INVALID, "NULL cell");
+  if (c->B != 1) return fail(JFFT_E_INVALID, "batched handle: the static workspace serves single cells");
+  if (!E_dev || !u_dev) return fail(JFFT_E_INVALID, "NULL E_dev or u_dev");
+  if (!(nu > -1.0 && nu < 0.5)) return fail(JFFT_E_INVALID, "nu must lie in (-1, 0.5)");
+  if (c->ws_owned) return fail(JFFT_E_INVALID, "the cell owns a library-allocated workspace; use a fresh cell");
+  if (c->timing) return fail(JFFT_E_INVALID, "kernel timing creates events; switch it off for jfft_solve_static");
+  const size_t need = layout_workspace(c, nullptr);
+  if (need > kScratchBytes)
+    return fail(JFFT_E_INVALID, "the cell needs " + std::to_string(need) +
+                                    " bytes of workspace; the static workspace holds " +
+                                    std::to_string(kScratchBytes));
+  unsigned char *ws = nullptr;
+  TRY(scratch_address(c->device, &ws));
+  // another cell may have used the array since this one did: lay the
+  // workspace out again and upload the tables (no allocation, ws is set)
+  c->ws = ws;
+  c->ws_bytes = kScratchBytes;
+  c->ws_owned = false;
+  c->ready = false;
+  c->has_material = false;
+  TRY(ensure_ready(c));
+  const double lam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  const double mu = 1.0 / (2.0 * (1.0 + nu));
+  TRY(set_material_impl(c, E_dev, lam, mu));
+  // direct launches: instantiating a graph may allocate
+  const int graph_iters = c->tun.graph_iters;
+  c->tun.graph_iters = 0;
+  const jfft_status st = solve_impl(c, macro_strain, tol, maxit, u0_dev, u_dev, sigma_dev, sigma_bar, report);
+  c->tun.graph_iters = graph_iters;
+  return st;
 }
 
 jfft_status jfft_solve_batch(jfft_cell_t c, const double *macro_strains, double tol, int maxit,
