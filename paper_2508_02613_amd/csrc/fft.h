@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
       if (UPDATE) {
         v.x -= alpha * qv[j].x;
         v.y -= alpha * qv[j].y;
-        reinterpret_cast<R2 *>(r)[off] = v;
+        st_stream(reinterpret_cast<R2 *>(r) + off, v);
       }
       rr += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
       if (USE_J) {
@@ -436,7 +436,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
 #pragma unroll
         for (int j = 0; j < SP; ++j) {
           const int kt = kt0 + j * dkt;
-          if (kt < a.ntx) dst[j * step] = split(zrow, kt * TW + w);
+          if (kt < a.ntx) st_stream(dst + j * step, split(zrow, kt * TW + w));
         }
       }
     } else {
@@ -446,7 +446,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
         const int f = threadIdx.x + j * FFT_THREADS;
         const int w = f & (TW - 1), row = (f >> 3) & (RB - 1), kt = f >> (3 + a.log2_rb);
         if (f >= tot || row0 + row >= a.nrows) continue;
-        spec[rt.offset(row, kt, w)] = split(buf + row * sc, kt * TW + w);
+        st_stream(spec + rt.offset(row, kt, w), split(buf + row * sc, kt * TW + w));
       }
     }
   }
@@ -586,7 +586,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
       t.x *= jv[j].x;
       t.y *= jv[j].y;
     }
-    reinterpret_cast<R2 *>(out)[off] = t;
+    st_stream(reinterpret_cast<R2 *>(out) + off, t);
   }
 }
 
@@ -654,7 +654,13 @@ __global__ void __launch_bounds__(NT) k_ypass(YArgs<Real> a) {
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const int f = threadIdx.x + j * NT;
-      if (f < npts) base[f] = buf[f];
+      if (f < npts) {
+        // the forward pass's output is read next by the Green pass and stays
+        // cached; the inverse pass's output streams out (measured: the other
+        // choices slow the consumer by 3-5 %)
+        if (INV) st_stream(base + f, buf[f]);
+        else base[f] = buf[f];
+      }
     }
     __syncthreads();
   }
@@ -684,26 +690,33 @@ struct GArgs {
 // G^(0) = 0 (Alg. 1 step 3).  K^_ref of Q1 elements with exact Gauss
 // integration is real symmetric:
 //   K_ii = (lam + 2 mu) a_i prod_{j != i} b_j + mu sum_{j != i} a_j prod_{l != j} b_l
-//   K_ij = (lam + mu) s_i s_j prod_{l != i, j} b_l.
-// The symbol is evaluated in the precision of the pass (T: float in the
-// mixed path, whose spectrum is FP32; double otherwise).  K^_ref(k) is SPD
-// for k != 0 with a condition number bounded by the Lame ratio and the
-// symbol's anisotropy, so its cofactor inverse loses only a few bits.
+//   K_ij = (lam + mu) s_i s_j prod_{l != i, j} b_l
+// (a = 4 sin^2(theta / 2) / h, b = h (2 + cos theta) / 3, s = sin theta per
+// axis; the caller forms the entries).  The symbol is evaluated in the
+// precision of the pass (T: float in the mixed path, whose spectrum is FP32;
+// double otherwise).  K^_ref(k) is SPD for k != 0 with a condition number
+// bounded by the Lame ratio and the symbol's anisotropy, so its cofactor
+// inverse loses only a few bits.  In FP32 the reciprocal of the determinant
+// is the hardware's (1 ulp), a relative change of G^ per frequency far below
+// the FP32 path's own rounding.
+
+// s / d: exact division in FP64, s times the hardware reciprocal in FP32
+template <typename T>
+__device__ __forceinline__ T scaled_recip(T s, T d) {
+  if constexpr (sizeof(T) == 4) {
+    return s * __builtin_amdgcn_rcpf(d);
+  } else {
+    return s / d;
+  }
+}
+
 template <typename T, typename C>
-__device__ __forceinline__ void green3(const T (&A)[3], const T (&B)[3], const T (&S)[3], T lam,
-                                       T mu, T invN, bool zero, C (&v)[3]) {
+__device__ __forceinline__ void green3_apply(T k00, T k11, T k22, T k01, T k02, T k12, T invN,
+                                             bool zero, C (&v)[3]) {
   if (zero) {
     for (int i = 0; i < 3; ++i) v[i].x = v[i].y = 0;
     return;
   }
-  const T l2m = lam + (T)2 * mu, lm = lam + mu;
-  const T abb = A[0] * B[1] * B[2], bab = B[0] * A[1] * B[2], bba = B[0] * B[1] * A[2];
-  const T k00 = l2m * abb + mu * (bab + bba);
-  const T k11 = l2m * bab + mu * (abb + bba);
-  const T k22 = l2m * bba + mu * (abb + bab);
-  const T k01 = lm * S[0] * S[1] * B[2];
-  const T k02 = lm * S[0] * B[1] * S[2];
-  const T k12 = lm * B[0] * S[1] * S[2];
   // symmetric inverse by cofactors
   const T c00 = k11 * k22 - k12 * k12;
   const T c01 = k02 * k12 - k01 * k22;
@@ -712,7 +725,7 @@ __device__ __forceinline__ void green3(const T (&A)[3], const T (&B)[3], const T
   const T c12 = k01 * k02 - k00 * k12;
   const T c22 = k00 * k11 - k01 * k01;
   const T det = k00 * c00 + k01 * c01 + k02 * c02;
-  const T sc = invN / det;
+  const T sc = scaled_recip(invN, det);
   const T g00 = c00 * sc, g01 = c01 * sc, g02 = c02 * sc;
   const T g11 = c11 * sc, g12 = c12 * sc, g22 = c22 * sc;
   const T x0 = v[0].x, x1 = v[1].x, x2 = v[2].x;
@@ -726,17 +739,12 @@ __device__ __forceinline__ void green3(const T (&A)[3], const T (&B)[3], const T
 }
 
 template <typename T, typename C>
-__device__ __forceinline__ void green2(const T (&A)[2], const T (&B)[2], const T (&S)[2], T lam,
-                                       T mu, T invN, bool zero, C (&v)[2]) {
+__device__ __forceinline__ void green2_apply(T k00, T k11, T k01, T invN, bool zero, C (&v)[2]) {
   if (zero) {
     for (int i = 0; i < 2; ++i) v[i].x = v[i].y = 0;
     return;
   }
-  const T l2m = lam + (T)2 * mu, lm = lam + mu;
-  const T k00 = l2m * A[0] * B[1] + mu * B[0] * A[1];
-  const T k11 = mu * A[0] * B[1] + l2m * B[0] * A[1];
-  const T k01 = lm * S[0] * S[1];
-  const T sc = invN / (k00 * k11 - k01 * k01);
+  const T sc = scaled_recip(invN, k00 * k11 - k01 * k01);
   const T g00 = k11 * sc, g11 = k00 * sc, g01 = -k01 * sc;
   const T x0 = v[0].x, x1 = v[1].x, y0 = v[0].y, y1 = v[1].y;
   v[0].x = g00 * x0 + g01 * x1;
@@ -783,13 +791,7 @@ __device__ __forceinline__ void green2_tri(T cmx, T sx, T cmy, T sy, const doubl
       k11 += (T)S[o][1] * cd;
       k01 += (T)S[o][2] * cd;
     }
-  const T sc = invN / (k00 * k11 - k01 * k01);
-  const T g00 = k11 * sc, g11 = k00 * sc, g01 = -k01 * sc;
-  const T x0 = v[0].x, x1 = v[1].x, y0 = v[0].y, y1 = v[1].y;
-  v[0].x = g00 * x0 + g01 * x1;
-  v[0].y = g00 * y0 + g01 * y1;
-  v[1].x = g01 * x0 + g11 * x1;
-  v[1].y = g01 * y0 + g11 * y1;
+  green2_apply<T>(k00, k11, k01, invN, false, v);
 }
 
 // Last axis: forward C2C, Green multiply, inverse C2C for every component of
@@ -810,7 +812,16 @@ __global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
   C *tw = reinterpret_cast<C *>(smem_raw);
   const int L = DIM == 3 ? a.nz : a.ny;
   C *buf = tw + L;  // [L][LN]
+  Real *tab = reinterpret_cast<Real *>(buf + L * LN);  // [L][3]: a, b, s of the transform axis
   load_twiddles<Real>(tw, a.tw, L);
+  {
+    const AxisTables &ta = DIM == 3 ? a.tz : a.ty;
+    for (int j = threadIdx.x; j < L; j += NT) {
+      tab[3 * j] = (Real)ta.a[j];
+      tab[3 * j + 1] = (Real)ta.b[j];
+      tab[3 * j + 2] = (Real)ta.s[j];
+    }
+  }
   const int kt = blockIdx.x % a.ntx;
   const int ky0 = DIM == 3 ? (int)(blockIdx.x / a.ntx) * KY : 0;
   // element (position t along the axis, line l) of component c:
@@ -860,41 +871,68 @@ __global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
   // sum over the full spectrum of conj(s^) (G^ s^) (1/N is folded into G^);
   // on the half spectrum the bins 0 < kx < nx/2 stand for their conjugate
   // partners too (weight 2), kx = 0 and kx = nx/2 for themselves (weight 1).
+  // NT is a multiple of LN, so a thread's points share their line l (one kx,
+  // ky) and differ only in the position t along the axis: the symbol's
+  // factors of the other axes are formed once per thread, and per point only
+  // the transform axis' a, b, s (staged in LDS) enter.
+  static_assert(NT % LN == 0, "a thread's points must share their tile line");
   double rz = 0.0;
+  const int l = threadIdx.x % LN;
+  const int kxu = kt * TW + l % TW;
+  const double wk = kxu >= a.mx ? 0.0 : (kxu == 0 || kxu == a.mx - 1 ? 1.0 : 2.0);
+  const int kx = min(kxu, a.mx - 1);
+  const Real lam = (Real)a.lam, mu = (Real)a.mu, invN = (Real)a.invN;
+  const Real l2m = lam + (Real)2 * mu, lm = lam + mu;
+  if constexpr (DIM == 3) {
+    const int ky = ky0 + l / TW;
+    const Real A0 = (Real)a.tx.a[kx], B0 = (Real)a.tx.b[kx], S0 = (Real)a.tx.s[kx];
+    const Real A1 = (Real)a.ty.a[ky], B1 = (Real)a.ty.b[ky], S1 = (Real)a.ty.s[ky];
+    // K^_ij as affine functions of the z factors (a2, b2, s2):
+    //   k00 = c00a b2 + c00b a2, k11 = c11a b2 + c00b a2, k22 = c22a a2 + c22b b2,
+    //   k01 = c01 b2, k02 = c02 s2, k12 = c12 s2
+    const Real c00a = l2m * A0 * B1 + mu * B0 * A1, c00b = mu * B0 * B1;
+    const Real c11a = l2m * B0 * A1 + mu * A0 * B1;
+    const Real c22a = l2m * B0 * B1, c22b = mu * (A0 * B1 + B0 * A1);
+    const Real c01 = lm * S0 * S1, c02 = lm * S0 * B1, c12 = lm * B0 * S1;
+    const bool kxy0 = kx == 0 && ky == 0;
 #pragma unroll
-  for (int j = 0; j < PPT; ++j) {
-    const int f = threadIdx.x + j * NT;
-    if (f < npts) {
-      const int t = f / LN, l = f % LN;
-      const int kxu = kt * TW + l % TW;
-      const double wk = kxu >= a.mx ? 0.0 : (kxu == 0 || kxu == a.mx - 1 ? 1.0 : 2.0);
-      const int kx = min(kxu, a.mx - 1);
-      if constexpr (DIM == 3) {
-        const int ky = ky0 + l / TW;
-        const Real A[3] = {(Real)a.tx.a[kx], (Real)a.ty.a[ky], (Real)a.tz.a[t]};
-        const Real B[3] = {(Real)a.tx.b[kx], (Real)a.ty.b[ky], (Real)a.tz.b[t]};
-        const Real S[3] = {(Real)a.tx.s[kx], (Real)a.ty.s[ky], (Real)a.tz.s[t]};
+    for (int j = 0; j < PPT; ++j) {
+      const int f = threadIdx.x + j * NT;
+      if (f < npts) {
+        const int t = f / LN;
+        const Real A2 = tab[3 * t], B2 = tab[3 * t + 1], S2 = tab[3 * t + 2];
+        const Real k00 = c00a * B2 + c00b * A2, k11 = c11a * B2 + c00b * A2;
+        const Real k22 = c22a * A2 + c22b * B2;
+        const Real k01 = c01 * B2, k02 = c02 * S2, k12 = c12 * S2;
         C v[3] = {stash[0][j], stash[1][j], stash[2][j]};
-        green3<Real>(A, B, S, (Real)a.lam, (Real)a.mu, (Real)a.invN,
-                     kx == 0 && ky == 0 && t == 0, v);
+        green3_apply<Real>(k00, k11, k22, k01, k02, k12, invN, kxy0 && t == 0, v);
         double e = 0.0;
         for (int c = 0; c < 3; ++c) {
           e += (double)stash[c][j].x * (double)v[c].x + (double)stash[c][j].y * (double)v[c].y;
           stash[c][j] = v[c];
         }
         rz += wk * e;
-      } else {
-        const Real A[2] = {(Real)a.tx.a[kx], (Real)a.ty.a[t]};
-        const Real B[2] = {(Real)a.tx.b[kx], (Real)a.ty.b[t]};
-        const Real S[2] = {(Real)a.tx.s[kx], (Real)a.ty.s[t]};
+      }
+    }
+  } else {
+    const Real A0 = (Real)a.tx.a[kx], B0 = (Real)a.tx.b[kx], S0 = (Real)a.tx.s[kx];
+    // quadrilaterals: k00 = mu b0 a1 + l2m a0 b1, k11 = l2m b0 a1 + mu a0 b1, k01 = lm s0 s1
+    const Real q00a = mu * B0, q00b = l2m * A0, q11a = l2m * B0, q11b = mu * A0, q01 = lm * S0;
+    // triangles: cos(theta_x) - 1 = -a0 h / 2
+    const Real cmx = (Real)(-0.5 * a.tx.a[kx] * a.hx);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int f = threadIdx.x + j * NT;
+      if (f < npts) {
+        const int t = f / LN;
+        const Real A1 = tab[3 * t], B1 = tab[3 * t + 1], S1 = tab[3 * t + 2];
         C v[2] = {stash[0][j], stash[1][j]};
         if (a.tri) {
-          // cos(theta) - 1 = -a h / 2 with a = 4 sin^2(theta / 2) / h
-          const Real cmx = (Real)(-0.5 * a.tx.a[kx] * a.hx), cmy = (Real)(-0.5 * a.ty.a[t] * a.hy);
-          green2_tri<Real>(cmx, (Real)a.tx.s[kx], cmy, (Real)a.ty.s[t], a.tS, (Real)a.invN,
-                           kx == 0 && t == 0, v);
+          const Real cmy = (Real)-0.5 * A1 * (Real)a.hy;
+          green2_tri<Real>(cmx, S0, cmy, S1, a.tS, invN, kx == 0 && t == 0, v);
         } else {
-          green2<Real>(A, B, S, (Real)a.lam, (Real)a.mu, (Real)a.invN, kx == 0 && t == 0, v);
+          green2_apply<Real>(q00a * A1 + q00b * B1, q11a * A1 + q11b * B1, q01 * S1, invN,
+                             kx == 0 && t == 0, v);
         }
         double e = 0.0;
         for (int c = 0; c < 2; ++c) {
@@ -918,7 +956,7 @@ __global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const int f = threadIdx.x + j * NT;
-      if (f < npts) bc[(long long)(f / LN) * axis_stride + f % LN] = buf[f];
+      if (f < npts) bc[(long long)(f / LN) * axis_stride + f % LN] = buf[f];  // read next by the y pass: keep it cached
     }
     __syncthreads();
   }

@@ -759,7 +759,7 @@ jfft_status launch_green(jfft_cell_s *c, typename CxT<Real>::T *spec, bool check
                        ? ZRows<Real>::value
                        : 1;
     const long long pts = (long long)L * KY * TW;
-    const size_t smem = sizeof(C) * ((size_t)L + (size_t)pts);
+    const size_t smem = sizeof(C) * ((size_t)L + (size_t)pts) + sizeof(Real) * 3 * (size_t)L;
     dim3 gr((unsigned)(a.ntx * (c->g.ny / KY)), 1, c->B);
     *nblk = gr.x;
     const int nt = tile_threads<Real>(pts);
@@ -773,7 +773,7 @@ jfft_status launch_green(jfft_cell_s *c, typename CxT<Real>::T *spec, bool check
       LAUNCH(c, KID_GREEN, k_green_axis<Real, 3, 1, 512><<<gr, 512, smem, c->stream>>>(a));
   } else {
     const long long pts = (long long)L * TW;
-    const size_t smem = sizeof(C) * ((size_t)L + (size_t)pts);
+    const size_t smem = sizeof(C) * ((size_t)L + (size_t)pts) + sizeof(Real) * 3 * (size_t)L;
     dim3 gr((unsigned)a.ntx, 1, c->B);
     *nblk = gr.x;
     if (tile_threads<Real>(pts) == 256)

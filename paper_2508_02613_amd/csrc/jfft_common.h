@@ -32,6 +32,31 @@ struct CxT<float> {
 // loses track of the global address space and falls back to flat accesses,
 // which share the LDS wait counter, so that every LDS wait also waits for the
 // outstanding HBM loads.
+// Streaming (non-temporal) store of one value: for the large per-iteration
+// outputs that the next kernel reads once.  Measured on the 256^3 solve:
+// with plain stores the dirty lines of one pass are written back while the
+// next pass streams its own inputs, which slows the next pass by 5-15 %.
+template <typename T>
+__device__ __forceinline__ void st_stream(T *p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+template <>
+__device__ __forceinline__ void st_stream<float2>(float2 *p, float2 v) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  f2v w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<f2v *>(p));
+}
+template <>
+__device__ __forceinline__ void st_stream<double2>(double2 *p, double2 v) {
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  d2v w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<d2v *>(p));
+}
+
 template <typename T>
 __device__ __forceinline__ T *cshift(T *p, int cell, long long cs) {
   using Byte = typename std::conditional<std::is_const<T>::value, const char, char>::type;

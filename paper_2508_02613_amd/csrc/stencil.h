@@ -586,6 +586,13 @@ __device__ __forceinline__ void elem_hex_modes(const Real (&u)[3][8], Real lam, 
 // element energy is the sum of the folded stress times the unscaled strain.
 // Same operator as elem_hex_modes on cubic elements.
 template <typename Real, bool ENERGY>
+__device__ __forceinline__ void stress_force_cubic(const Real (&X)[3][2][2],
+                                                   const Real (&Y)[3][2][2],
+                                                   const Real (&Z)[3][2][2], Real Ee,
+                                                   const Real (&clam)[3], const Real (&cmu)[3],
+                                                   Real (&y)[3][8], double &en);
+
+template <typename Real, bool ENERGY>
 __device__ __forceinline__ void elem_hex_modes_cubic(const Real (&u)[3][8], Real Ee,
                                                      const Real (&clam)[3], const Real (&cmu)[3],
                                                      Real (&y)[3][8], double &en) {
@@ -611,6 +618,65 @@ __device__ __forceinline__ void elem_hex_modes_cubic(const Real (&u)[3][8], Real
 #pragma unroll
       for (int b = 0; b < 2; ++b) Z[i][a][b] = h[a][b];
   }
+  stress_force_cubic<Real, ENERGY>(X, Y, Z, Ee, clam, cmu, y, en);
+}
+
+// In-plane differences of one element face (4 nodes, index cx + 2 cy), per
+// component: F[0] = sum over cy of the x differences, F[1] = their
+// difference (cy = 0 minus cy = 1), F[2], F[3] the same for the y
+// differences over cx.  The x and y strain modes of an element are
+// X[my][mz] = F_bottom[my] +- F_top[my] (sign (-1)^mz) and likewise for y,
+// so an element column marching in z reuses its top face's F as the next
+// element's bottom face.
+template <typename Real>
+__device__ __forceinline__ void face_diffs(const Real (&v)[4], Real (&F)[4]) {
+  const Real x0 = v[1] - v[0], x1 = v[3] - v[2];
+  const Real y0 = v[2] - v[0], y1 = v[3] - v[1];
+  F[0] = x0 + x1;
+  F[1] = x0 - x1;
+  F[2] = y0 + y1;
+  F[3] = y0 - y1;
+}
+
+// elem_hex_modes_cubic with the bottom face given by its node values and
+// in-plane differences (carried from the element below) and the top face by
+// its node values; returns the top face's differences for the next element.
+template <typename Real, bool ENERGY>
+__device__ __forceinline__ void elem_hex_modes_cubic_faces(const Real (&bot)[3][4],
+                                                           const Real (&botF)[3][4],
+                                                           const Real (&top)[3][4],
+                                                           Real (&topF)[3][4], Real Ee,
+                                                           const Real (&clam)[3],
+                                                           const Real (&cmu)[3],
+                                                           Real (&y)[3][8], double &en) {
+  Real X[3][2][2], Y[3][2][2], Z[3][2][2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    face_diffs(top[i], topF[i]);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      X[i][a][0] = botF[i][a] + topF[i][a];
+      X[i][a][1] = botF[i][a] - topF[i][a];
+      Y[i][a][0] = botF[i][2 + a] + topF[i][2 + a];
+      Y[i][a][1] = botF[i][2 + a] - topF[i][2 + a];
+    }
+    Real h[2][2];
+    had2(top[i][0] - bot[i][0], top[i][2] - bot[i][2], top[i][1] - bot[i][1],
+         top[i][3] - bot[i][3], h);  // D[cx][cy]
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) Z[i][a][b] = h[a][b];
+  }
+  stress_force_cubic<Real, ENERGY>(X, Y, Z, Ee, clam, cmu, y, en);
+}
+
+template <typename Real, bool ENERGY>
+__device__ __forceinline__ void stress_force_cubic(const Real (&X)[3][2][2],
+                                                   const Real (&Y)[3][2][2],
+                                                   const Real (&Z)[3][2][2], Real Ee,
+                                                   const Real (&clam)[3], const Real (&cmu)[3],
+                                                   Real (&y)[3][8], double &en) {
   Real lc[3], mc[3], m2c[3];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -884,8 +950,8 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, (stencil3_waves_per_simd<Rea
         v = first ? fz[c] : fz[c] + beta * fp[c];
         w = first ? hz[c] : hz[c] + beta * hp[c];
         if (owned) {
-          if (!first) a.u[c * N + node0] = fu[c] + alpha_prev * fp[c];
-          a.pout[c * N + node0] = v;
+          if (!first) st_stream(&a.u[c * N + node0], fu[c] + alpha_prev * fp[c]);
+          st_stream(&a.pout[c * N + node0], v);
         }
       }
       P[slot][c][li0] = v;
@@ -905,6 +971,9 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, (stencil3_waves_per_simd<Rea
   double acc = 0.0;
   Real carry[3] = {0, 0, 0};
   Real qpend[3] = {0, 0, 0};
+  // cubic elements: the bottom face of the next element (its node values and
+  // in-plane differences) is this element's top face, carried in registers
+  Real fbot[3][4], fbotF[3][4];
   long long qnode = -1;  // pending output node (stored at the next layer's top)
   fetch(z0 - 1);
   commit(z0 - 1, ring(z0 - 1));
@@ -922,7 +991,7 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, (stencil3_waves_per_simd<Rea
       a.diag[a.comb_comp * N + qnode] = qpend[0];
     } else {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) a.out[i * N + qnode] = qpend[i];
+      for (int i = 0; i < 3; ++i) st_stream(&a.out[i * N + qnode], qpend[i]);
     }
     qnode = -1;
   };
@@ -937,9 +1006,43 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, (stencil3_waves_per_simd<Rea
     asm volatile("" : "+v"(Ecur)::"memory");
     if (more) commit(ez + 2, ring(ez + 2));  // plane ez + 2, in flight since the last layer
     flush_q();
-    if (more2) fetch0(ez + 3);
+    if (more2) {
+      fetch0(ez + 3);
+      if (sizeof(Real) == 4) fetch1(ez + 3);  // FP32: the strip one layer ahead as well
+    }
     Enext = a.E[(long long)wrapi(ez + 1, nz) * plane + exy];
-    {
+    if constexpr (CUBIC && MAT == 0 && sizeof(Real) == 4) {
+      // (FP32 only: in FP64 the 24 carried registers would halve occupancy)
+      Real top[3][4], topF[3][4], yv[3][8];
+      if (ez == z0 - 1) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int i = 0; i < 3; ++i) fbot[i][k] = P[s0][i][lie + (k >> 1) * NX3 + (k & 1)];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) face_diffs(fbot[i], fbotF[i]);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) top[i][k] = P[s1][i][lie + (k >> 1) * NX3 + (k & 1)];
+      double en = 0.0;
+      // a.lam, a.mu carry the full Gauss weight; the mode form takes half
+      elem_hex_modes_cubic_faces<Real, MODE == SM_CG>(fbot, fbotF, top, topF, Ecur, a.clam, a.cmu,
+                                                      yv, en);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          fbot[i][k] = top[i][k];
+          fbotF[i][k] = topF[i][k];
+        }
+      if (elem_owned && ez >= z0) acc += en;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) Y[c * 3 + i][tid] = yv[i][c];
+    } else {
       Real uv[3][8], yv[3][8];
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
@@ -978,7 +1081,7 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, (stencil3_waves_per_simd<Rea
 #pragma unroll
         for (int i = 0; i < 3; ++i) Y[c * 3 + i][tid] = yv[i][c];
     }
-    if (more2) fetch1(ez + 3);
+    if (sizeof(Real) == 8 && more2) fetch1(ez + 3);  // FP64: after the element (registers)
     __syncthreads();
     if (node_valid) {
       // corners (1,1), (0,1), (1,0), (0,0) of the four x-y neighbouring elements
