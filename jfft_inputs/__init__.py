@@ -25,6 +25,7 @@ __all__ = [
     "laminate_field", "cosine_void_field", "filtered_inclusion_field",
     "uniform_random_field", "random_start", "unit_macro_strain", "mandel_size",
     "spherical_inclusions", "ulp_perturbed", "sketch_vectors", "sample_nodes",
+    "refine_geometry",
 ]
 
 
@@ -215,3 +216,16 @@ def sample_nodes(n_nodes: int, count: int, seed: int) -> np.ndarray:
     """Sorted seeded sample of `count` distinct flat node indices."""
     rng = np.random.default_rng(seed)
     return np.sort(rng.choice(int(n_nodes), size=int(count), replace=False))
+
+
+def refine_geometry(rho_p, n: int) -> np.ndarray:
+    """A geometry of p x p pixels (Sec. 4: G_p, the density sampled at the
+    geometry's nodal points and assigned to the whole pixel) on the finer
+    discretisation grid T_n, n a multiple of p: every geometry pixel covers
+    (n / p)^2 elements of the same density."""
+    rho_p = np.asarray(rho_p, dtype=np.float64)
+    p = rho_p.shape[0]
+    if rho_p.shape != (p, p) or n % p:
+        raise ValueError("a square p x p geometry and n a multiple of p are needed")
+    r = n // p
+    return np.kron(rho_p, np.ones((r, r)))

@@ -264,6 +264,133 @@ def dot(a, b, mode=0):
     return float(_load().or_dot(int(mode), a.size, _d(a), _d(b)))
 
 
+def precond_fft(pc, r, diag=None, G=None, void_value=1.0):
+    """z = M^-1 r as `precond` computes it (eq. prec_lin_systemJG_2 and its
+    Green / Jacobi / identity special cases), with numpy's FFT as the
+    transform step instead of the naive DFT: a second rounding of the same
+    operator, used as a rounding variant for parity windows (an FFT's
+    rounding grows like log n, the naive DFT's like n)."""
+    r = np.asarray(r, dtype=np.float64)
+    d = r.shape[0]
+    axes = tuple(range(1, r.ndim))
+    if pc == PC_NONE:
+        return r.copy()
+    dg = None
+    if diag is not None:
+        dg = np.where(np.asarray(diag) == 0.0, void_value, diag)
+    if pc == PC_JACOBI:
+        return r / dg
+    jh = 1.0 / np.sqrt(dg) if pc == PC_GREEN_JACOBI else np.ones_like(r)
+    S = np.fft.fftn(jh * r, axes=axes)
+    Z = np.einsum("ba...,a...->b...", G, S)
+    return jh * np.real(np.fft.ifftn(Z, axes=axes))
+
+
+def solve_py(E, macro, lam, mu, pc=PC_GREEN_JACOBI, tol=1e-8, maxit=1000, u0=None,
+             void_value=1.0, stop_mode=0, lengths=None, f=None, noise_seed=0, dot_mode=0,
+             transform="fft", hist_len=0) -> SolveResult:
+    """The PCG loop of or_solve written out in Python over the oracle's
+    operators (K by element loops, f, Algorithm 2's diagonal, Algorithm 1's
+    G^), for rounding variants that the C loop does not have: the transform
+    step by numpy's FFT (transform="fft") or the naive DFT ("dft"), inner
+    products by numpy's pairwise sum (dot_mode 0) or math.fsum (1,
+    correctly rounded), and the one-ulp noise on every K p and M^-1 r result
+    (noise_seed != 0).  Same stopping rules, breakdown test, iteration count
+    and post-processing as or_solve."""
+    import math
+
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    dim = E.ndim
+    f_asm, fa = rhs(E, macro, lam, mu, lengths, with_abs=True)
+    f = f_asm if f is None else np.asarray(f, dtype=np.float64)
+    diag = jacobi_diag(E, lam, mu, lengths)[0] if pc in (PC_JACOBI, PC_GREEN_JACOBI) else None
+    G = green(E.shape, lam, mu, lengths) if pc in (PC_GREEN, PC_GREEN_JACOBI) else None
+    rng = np.random.default_rng(noise_seed) if noise_seed else None
+
+    def noisy(x):
+        if rng is None:
+            return x
+        up = rng.random(x.shape) < 0.5
+        moved = np.where(up, np.nextafter(x, np.inf), np.nextafter(x, -np.inf))
+        return np.where(x == 0.0, 0.0, moved)
+
+    def dot(a, b):
+        return math.fsum((a * b).ravel()) if dot_mode == 1 else float((a * b).sum())
+
+    def M(r):
+        if transform == "fft":
+            z = precond_fft(pc, r, diag=diag, G=G, void_value=void_value)
+        else:
+            z = precond(pc, r, diag=diag, G=G, void_value=void_value, lengths=lengths)[0]
+        return noisy(z)
+
+    def K(x):
+        return stiffness(E, x, lam, mu, lengths)
+
+    fnorm = math.sqrt(dot(f, f))
+    fabsnorm = math.sqrt(dot(fa, fa))
+    homog = fnorm <= 1e-13 * fabsnorm
+    if u0 is not None:
+        u = np.array(u0, dtype=np.float64)
+        r = f - K(u)
+    else:
+        u = np.zeros_like(f)
+        r = f.copy()
+    rnorm = math.sqrt(dot(r, r))
+
+    def done(rn):
+        return rn <= tol * fnorm if stop_mode == 0 else rn * rn <= tol
+
+    k, status = 0, "ok"
+    alphas, betas, hist = [], [], []
+    if homog:
+        u[:] = 0.0
+        rnorm = 0.0
+    elif not done(rnorm):
+        z = M(r)
+        p = z.copy()
+        rz = dot(r, z)
+        while True:
+            if k >= maxit:
+                status = "not_converged"
+                break
+            q = noisy(K(p))
+            pq = dot(p, q)
+            alpha = rz / pq if pq != 0.0 else float("inf")
+            if not (pq > 0.0) or not math.isfinite(alpha):
+                status = "breakdown"
+                break
+            u += alpha * p
+            r -= alpha * q
+            k += 1
+            rnorm = math.sqrt(dot(r, r))
+            alphas.append(alpha)
+            hist.append(rnorm)
+            if done(rnorm):
+                break
+            if k >= maxit:
+                status = "not_converged"
+                break
+            z = M(r)
+            rz_new = dot(r, z)
+            beta = rz_new / rz
+            if not math.isfinite(beta):
+                status = "breakdown"
+                break
+            betas.append(beta)
+            rz = rz_new
+            p = z + beta * p
+    rt = math.sqrt(dot(f - K(u), f - K(u)))
+    u -= u.reshape(dim, -1).mean(axis=1).reshape((dim,) + (1,) * dim)
+    sbar = stress(E, macro, u, lam, mu, lengths)
+    h = max(int(hist_len), 0)
+    return SolveResult(u=u, sigma_bar=sbar, iters=k,
+                       relres=(rnorm / fnorm if fnorm > 0 and not homog else 0.0),
+                       relres_true=(rt / fnorm if fnorm > 0 and not homog else 0.0), status=status,
+                       alpha=np.array(alphas[:h]), beta=np.array(betas[:h]),
+                       res=np.array(hist[:h]), timing=np.zeros(3))
+
+
 def time_iterations(E, macro, lam, mu, pc=PC_GREEN_JACOBI, iters=1, lengths=None):
     """Wall seconds (setup, `iters` PCG iterations, first preconditioner apply)."""
     lib = _load()

@@ -181,7 +181,7 @@ class SolveResult:
 
 def solve(E, macro, lam, mu, pc=oracle.PC_GREEN_JACOBI, lam_ref=None, mu_ref=None, tol=1e-8,
           maxit=5000, void_value=1.0, stop_absolute=False, lengths=None, f=None, noise_seed=0,
-          dot_mode=0):
+          dot_mode=0, transform="dft"):
     """PCG on K u = f from u = 0 (the C oracle's loop, with the triangle
     operators), then mean removal and sigma_bar.  f defaults to the assembled
     right-hand side; a given f replaces it (the cancellation test of the
@@ -189,7 +189,9 @@ def solve(E, macro, lam, mu, pc=oracle.PC_GREEN_JACOBI, lam_ref=None, mu_ref=Non
     every entry of each K p and M^-1 r result by one ulp in a seeded random
     direction, the C oracle's rounding-difference model for parity windows;
     dot_mode = 1 sums the products of every inner product and norm with
-    math.fsum (correctly rounded) instead of numpy's pairwise sum."""
+    math.fsum (correctly rounded) instead of numpy's pairwise sum;
+    transform="fft" applies the preconditioner with numpy's FFT
+    (oracle.precond_fft) instead of the naive DFT."""
     E = np.asarray(E, dtype=np.float64)
     if lam_ref is None:
         lam_ref, mu_ref = lam, mu
@@ -213,6 +215,8 @@ def solve(E, macro, lam, mu, pc=oracle.PC_GREEN_JACOBI, lam_ref=None, mu_ref=Non
         return np.where(x == 0.0, 0.0, moved)
 
     def M(r):
+        if transform == "fft":
+            return noisy(oracle.precond_fft(pc, r, diag=diag, G=G, void_value=void_value))
         return noisy(oracle.precond(pc, r, diag=diag, G=G, void_value=void_value,
                                     lengths=lengths)[0])
 

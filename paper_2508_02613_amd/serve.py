@@ -254,6 +254,7 @@ class Server:
             "requests_per_s": len(requests) / makespan,
             "solves_per_s": 6 * len(requests) / makespan,
             "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+            "p95_latency_ms": float(np.percentile(lat, 95) * 1e3),
             "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_latency_ms": float(lat.mean() * 1e3),
             "offered_rate": rate,

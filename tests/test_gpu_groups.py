@@ -9,7 +9,7 @@ import pytest
 
 import jfft_inputs as ji
 import oracle
-from oracle_spread import iteration_window
+from oracle_spread import c_oracle, iteration_window
 
 pytestmark = pytest.mark.gpu
 
@@ -80,9 +80,7 @@ def test_simp_member_matches_oracle():
         for i in range(3):
             E, m = fields[i], macros[i]
             lo, hi, counts, runs = iteration_window(
-                lambda Ev, fv, ns, dm: oracle.solve(Ev, m, LAM, MU, pc=3, tol=tol, maxit=20000, f=fv,
-                                                noise_seed=ns, dot_mode=dm),
-                E, oracle.rhs(E, m, LAM, MU))
+                c_oracle(m, LAM, MU, pc=3, tol=tol, maxit=20000), E, oracle.rhs(E, m, LAM, MU))
             ref = runs[0]
             u = res[i]["u"].cpu().numpy()
             it = res[i]["report"].iters
@@ -123,9 +121,7 @@ def test_green_jacobi_beats_green_on_simp():
         cell.close()
     ref_g = oracle.solve(E, m, LAM, MU, pc=1, tol=1e-8, maxit=20000)
     lo, hi, counts, _ = iteration_window(
-        lambda Ev, fv, ns, dm: oracle.solve(Ev, m, LAM, MU, pc=3, tol=1e-8, maxit=20000, f=fv,
-                                        noise_seed=ns, dot_mode=dm), E,
-        oracle.rhs(E, m, LAM, MU))
+        c_oracle(m, LAM, MU, pc=3, tol=1e-8, maxit=20000), E, oracle.rhs(E, m, LAM, MU))
     say(f"  gpu Green {its[pkg.PC_GREEN]} GJ {its[pkg.PC_GREEN_JACOBI]}; oracle Green {ref_g.iters} "
         f"GJ {counts} window [{lo}, {hi}]")
     assert lo <= its[pkg.PC_GREEN_JACOBI] <= hi

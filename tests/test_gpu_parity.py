@@ -5,9 +5,9 @@ mean-free fluctuation, iteration counts, early CG scalars and sigma_bar.
 Tolerances (FP64 path): operators 1e-12 relative to the field's max (a few
 hundred rounding steps of O(1e-16)).  Solves: at the configurations' tol 1e-8
 the iteration count lies in the oracle's own window (min - 1 .. max + 1 of
-its ten counts with serial and with Dot2 inner products, on the input, on
-inputs changed by one ulp and with its rounding-difference model on, see
-oracle_spread.py), sigma_bar agrees to 1e-8, the distance of the GPU
+its thirteen counts over its rounding variants: serial or Dot2 inner
+products, naive DFT or library FFT, inputs changed by one ulp, one-ulp
+operator noise, see oracle_spread.py), sigma_bar agrees to 1e-8, the distance of the GPU
 solution from the exact discrete solution is at most 10x the largest such
 distance of those oracle runs, and alpha_k / beta_k agree to 1e-9 on the
 prefix where the oracle agrees with its own perturbed run.  The 1e-10 bar on
@@ -22,7 +22,7 @@ import pytest
 
 import jfft_inputs as ji
 import oracle
-from oracle_spread import iteration_window
+from oracle_spread import c_oracle, iteration_window
 
 pytestmark = pytest.mark.gpu
 
@@ -134,7 +134,7 @@ def check_parity(pkg, E, macro, pc, u0=None, maxit=20000, tight=True, tol_u_tigh
     At tol 1e-8: the iteration count in the oracle's window (oracle_spread),
     sigma_bar to 1e-8, the true residual <= 1.5e-8, the distance from the
     exact discrete solution (the oracle's tol-1e-12 solution) at most 10x the
-    largest distance of the ten oracle runs at tol 1e-8, and alpha_k /
+    largest distance of the thirteen oracle runs at tol 1e-8, and alpha_k /
     beta_k to 1e-9 on the prefix where the oracle agrees with its own run on
     f (1 + 2^-52) (CG amplifies rounding; later scalars are not reproducible
     even by the oracle).  At tol 1e-12 (both near the exact discrete solution)
@@ -143,8 +143,7 @@ def check_parity(pkg, E, macro, pc, u0=None, maxit=20000, tight=True, tol_u_tigh
     ug, sbar, rep, (a, b, res) = _gpu_solve(pkg, E, macro, pc, 1e-8, maxit, u0, hist)
     f = oracle.rhs(E, macro, LAM, MU)
     lo, hi, counts, runs = iteration_window(
-        lambda Ev, fv, ns, dm: oracle.solve(Ev, macro, LAM, MU, pc=pc, tol=1e-8, maxit=maxit,
-                                        u0=u0, f=fv, hist_len=hist, noise_seed=ns, dot_mode=dm), E, f)
+        c_oracle(macro, LAM, MU, pc=pc, tol=1e-8, maxit=maxit, u0=u0, hist_len=hist), E, f)
     ref, ref2 = runs[0], runs[1]
     exact = oracle.solve(E, macro, LAM, MU, pc=pc, tol=1e-12, maxit=maxit, u0=u0)
     un = np.linalg.norm(exact.u)

@@ -11,7 +11,7 @@ import pytest
 
 import jfft_inputs as ji
 import oracle
-from oracle_spread import iteration_window
+from oracle_spread import c_oracle, iteration_window
 
 pytestmark = pytest.mark.gpu
 
@@ -54,8 +54,7 @@ def test_absolute_rule_matches_oracle(field, pc):
     macro = np.array([1.0, 0.0, 0.0])
     f = oracle.rhs(E, macro, LAM, MU)
     lo, hi, counts, runs = iteration_window(
-        lambda Ev, fv, ns, dm: oracle.solve(Ev, macro, LAM, MU, pc=pc, tol=tol, stop_mode=1,
-                                        maxit=20000, f=fv, noise_seed=ns, dot_mode=dm), E, f)
+        c_oracle(macro, LAM, MU, pc=pc, tol=tol, stop_mode=1, maxit=20000), E, f)
     ref = runs[0]
     say(f"{field} pc={pc}: iters gpu={rep.iters} oracle={counts} window [{lo}, {hi}]")
     assert rep.status == "ok" and ref.status == "ok"

@@ -40,9 +40,9 @@ def _window(E, macro, pc, tol, lengths=None, stop_absolute=False):
     unperturbed oracle result)."""
     f = tri.rhs(E, macro, LAM, MU, lengths)
     lo, hi, counts, runs = iteration_window(
-        lambda Ev, fv, ns, dm: tri.solve(Ev, macro, LAM, MU, pc=pc, tol=tol, maxit=20000,
-                                     lengths=lengths, stop_absolute=stop_absolute, f=fv,
-                                     noise_seed=ns, dot_mode=dm), E, f)
+        lambda Ev, fv, ns, dm, tr: tri.solve(Ev, macro, LAM, MU, pc=pc, tol=tol, maxit=20000,
+                                             lengths=lengths, stop_absolute=stop_absolute, f=fv,
+                                             noise_seed=ns, dot_mode=dm, transform=tr), E, f)
     return lo, hi, counts, runs[0]
 
 

@@ -626,3 +626,42 @@ def test_triangle_and_powerlaw_rounding_models():
         r = tri.solve(E, m, LAM, MU, pc=3, tol=1e-12, maxit=500, **kw)
         assert r.status == "ok" and abs(r.iters - base.iters) <= 2
         assert np.linalg.norm(r.u - base.u) <= 1e-10 * np.linalg.norm(base.u)
+
+
+def test_precond_fft_equals_naive_dft_precond():
+    """oracle.precond_fft (numpy's FFT as the transform step) is the same
+    operator as the naive-DFT precond: agreement to 1e-13 for the four
+    preconditioners, 2D and 3D, with a void."""
+    rng = np.random.default_rng(9)
+    for shape in ((12, 10), (6, 8, 4)):
+        dim = len(shape)
+        E = ji.uniform_random_field(shape, 1.0, 1e3, seed=2)
+        E.flat[3] = 0.0
+        dg, _ = oracle.jacobi_diag(E, LAM, MU)
+        G = oracle.green(shape, LAM, MU)
+        r = rng.standard_normal((dim,) + shape)
+        for pc in (0, 1, 2, 3):
+            z, _ = oracle.precond(pc, r, diag=dg, G=G, void_value=2.0)
+            zf = oracle.precond_fft(pc, r, diag=dg, G=G, void_value=2.0)
+            assert np.abs(z - zf).max() <= 1e-13 * np.abs(z).max(), (shape, pc)
+
+
+def test_python_loop_equals_c_loop():
+    """oracle.solve_py follows or_solve's loop: with the naive DFT its early
+    CG scalars equal the C loop's to rounding, and both (and the FFT
+    variant) reach the same solution and sigma_bar; the iteration counts
+    agree within a few iterations (summation order only)."""
+    E = ji.grf_field((12, 10, 8), 1e3, seed=4)
+    m = np.array([1.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+    c = oracle.solve(E, m, LAM, MU, pc=3, tol=1e-12, maxit=2000, hist_len=50)
+    for tr in ("dft", "fft"):
+        p = oracle.solve_py(E, m, LAM, MU, pc=3, tol=1e-12, maxit=2000, hist_len=50,
+                            transform=tr)
+        assert p.status == "ok"
+        assert abs(p.iters - c.iters) <= 3
+        assert np.abs(p.alpha[:5] / c.alpha[:5] - 1).max() <= 1e-12
+        assert np.linalg.norm(p.u - c.u) <= 1e-10 * np.linalg.norm(c.u)
+        assert np.abs(p.sigma_bar - c.sigma_bar).max() <= 1e-11 * np.abs(c.sigma_bar).max()
+    # homogeneous material: zero iterations, u = 0
+    h = oracle.solve_py(np.full((6, 4), 2.0), np.array([1.0, 0.5, 0.2]), LAM, MU, pc=3)
+    assert h.iters == 0 and np.abs(h.u).max() == 0.0
