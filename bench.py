@@ -39,13 +39,23 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X, FP64 vector (no MFMA)
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X, FP32 vector (no MFMA)
-# Flops of one element evaluation of the power-law tangent stiffness kernel
-# (strain of the iterate and of p at 8 Gauss points, tangent, weighted
-# divergence): 64 lanes x (ADD + MUL + TRANS + 2 FMA) wave instructions of a
-# launch over its element evaluations, from rocprofv3 SQ_INSTS_VALU_*_F64 /
-# _F32 counters (profiles/valu_ops_powerlaw200.txt)
-TANGENT_FLOPS_PER_ELEMENT = {"f64": 2267.2, "f32": 2193.3}
+# FP32 vector peak without packed FP32 instructions (this build does not use
+# them): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz.  The 157.3
+# TFLOP/s of the data sheet counts packed (two-wide) FP32 FMAs.
+FP32_VECTOR_PEAK_TFLOPS = 78.6
+# Algorithmic flops of one element of the power-law tangent operator
+# (Sec. 2.2, Sec. 4) in the factorised Gauss-point form, counted from the
+# method's operations (a*x + b*y = 3 flops, FMA = 2): gradients of the
+# iterate and of p at the 8 Gauss points (2 fields x 3 components x 3
+# directions x [4 differences + 4 two-point interpolations x 6 + 4 scalings]
+# = 576); per Gauss point the two Mandel strains (12), the macro strain (6),
+# the tangent (matrix 64: trace, deviator, e.e, e.d, g and h for the integer
+# exponent, the 6 stress components; inclusion 17), the weight (6), the
+# element energy p.Kp (12), the shear factors (3) and the family sums (9);
+# the corner forces (3 components x 3 directions x [4 interpolations x 6 +
+# 4 scalings + 8 additions] = 324).  Matrix element 1796, inclusion 1420.
+TANGENT_FLOPS_MATRIX = 576 + 8 * (12 + 6 + 64 + 6 + 12 + 3 + 9) + 324
+TANGENT_FLOPS_INCLUSION = 576 + 8 * (12 + 6 + 17 + 6 + 12 + 3 + 9) + 324
 
 
 def parse():
@@ -151,6 +161,31 @@ def load_traffic(workload_key, kernel):
     return ent.get("bytes_per_launch")
 
 
+def run_restarted(args, E, nu, macro, tol, maxit):
+    """One mixed-precision solve with the FP32 CG restarted at every
+    refinement sweep (the alternative to the default continued CG), for the
+    iteration and time-to-solution comparison in the bench line."""
+    import torch
+
+    import paper_2508_02613_amd as pkg
+
+    stream = torch.cuda.Stream()
+    cell = pkg.Cell(E.shape, precision=pkg.MIXED, pc=pkg.PC_GREEN_JACOBI, stream=stream)
+    if args.graph:
+        cell.set_graph_iterations(args.graph)
+    cell.set_mixed_params(continue_cg=False)
+    Ed = torch.from_numpy(E).to("cuda")
+    reps = []
+    for _ in range(2):  # the first solve warms up the graph
+        cell.set_material(Ed, nu=nu)
+        _, _, rep, _ = cell.solve(macro, tol=tol, maxit=maxit)
+        reps.append(rep)
+    cell.close()
+    rep = reps[-1]
+    return {"iters": rep.iters, "outer_sweeps": rep.outer, "loop_ms": rep.loop_ms,
+            "rel_res_true": rep.rel_res_true}
+
+
 def run_gpu(args, precision_name, E, nu, macro, tol, maxit):
     """Timed steps as a production caller runs them (own stream, PCG
     iterations replayed from captured HIP graphs, no per-kernel events), then
@@ -234,13 +269,27 @@ def cpu_baseline(E, macro, nu):
     return {
         "value": dofs / per_iter,
         "unit": "DOF·it/s",
-        "cores": oracle.num_threads(),
+        "cores": oracle.num_threads(), "cpu": host_cpu(),
         "kind": "oracle",
         "sample": (f"one PCG iteration of the FP64 C oracle (element-loop K·p {t1 - t0:.1f} s, "
                    f"Green-Jacobi M^-1 with naive separable DFT {t2 - t1:.1f} s, dots/axpys "
                    f"{t3 - t2:.1f} s) on the same {shape[0]}^3 input; set-up excluded"),
         "seconds_per_iteration": per_iter,
     }
+
+
+def host_cpu():
+    """Model name of the host CPU (from /proc/cpuinfo) and its logical CPUs."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
 
 
 def serve_field_pool(count, seed):
@@ -560,12 +609,14 @@ def run_powerlaw(args):
     def iters(run):
         return sum(sum(r.pcg_iters) for r in run["reps"])
 
+    n_matrix = int(np.count_nonzero(phase > 0.5))  # elements of the power-law matrix
+
     def roofline(run, prec):
         # tangent CG stiffness kernel: FP32 in the mixed path's inner solves
         launches, tot_ms = run["stats"]["stiffness_cg"]
         rb = 4 if prec == "f32" else 8
         bytes_launch = algorithmic_bytes("stiffness_cg_tangent", 3, N, n, rb)
-        flops_launch = TANGENT_FLOPS_PER_ELEMENT[prec] * N
+        flops_launch = TANGENT_FLOPS_MATRIX * n_matrix + TANGENT_FLOPS_INCLUSION * (N - n_matrix)
         avg_ms = tot_ms / launches
         gbs = bytes_launch / (avg_ms * 1e-3) / 1e9
         tf = flops_launch / (avg_ms * 1e-3) / 1e12
@@ -574,7 +625,10 @@ def run_powerlaw(args):
                 "achieved": tf, "peak": peak, "unit": "TFLOP/s", "frac": tf / peak,
                 "traffic": load_traffic(f"powerlaw_{n}", f"stiffness_cg_{prec}"),
                 "algorithmic_flops_per_launch": flops_launch,
-                "flops_per_element": TANGENT_FLOPS_PER_ELEMENT[prec],
+                "flops_per_element": {"matrix": TANGENT_FLOPS_MATRIX,
+                                      "inclusion": TANGENT_FLOPS_INCLUSION},
+                "peak_basis": ("FP32 vector without packed math" if prec == "f32"
+                               else "FP64 vector"),
                 "hbm_achieved_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
                 "avg_ms": avg_ms, "launches": launches,
                 "algorithmic_bytes_per_launch": bytes_launch,
@@ -859,7 +913,7 @@ def cpu_baseline_tri(n=512, E=None, lame=None, cells=1, reps=1):
     per_iter = (tk + tm + tv) / (cells * reps)
     what = "cell" if cells == 1 else f"load case, each of {cells}"
     count = "one PCG iteration" if reps == 1 else f"{reps} PCG iterations"
-    return {"value": 2 * n * n / per_iter, "unit": "DOF·it/s", "cores": oracle.num_threads(),
+    return {"value": 2 * n * n / per_iter, "unit": "DOF·it/s", "cores": oracle.num_threads(), "cpu": host_cpu(),
             "kind": "oracle",
             "sample": (f"{count} of the triangle oracle per {n}^2 {what} (element loop "
                        f"{tk:.2f} s, Green-Jacobi M^-1 with naive DFT {tm:.2f} s, "
@@ -897,7 +951,7 @@ def cpu_baseline_powerlaw(seed):
     t3 = time.perf_counter()
     per_iter = t3 - t0
     return {"value": 3 * phase.size / per_iter, "unit": "DOF·it/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
+            "cores": oracle.num_threads(), "cpu": host_cpu(), "kind": "oracle",
             "sample": (f"one PCG iteration of the power-law oracle at {n}^3 (tangent element "
                        f"loop {t1 - t0:.1f} s, Green-Jacobi M^-1 with naive DFT {t2 - t1:.1f} s, "
                        f"dots/axpys {t3 - t2:.1f} s); Newton set-up excluded"),
@@ -996,6 +1050,7 @@ def main():
         "outer_sweeps": R["reps"][-1].outer,
         "rel_res_true": R["reps"][-1].rel_res_true,
         "loop_ms": R["reps"][-1].loop_ms,
+        "time_to_solution_ms": R["reps"][-1].loop_ms,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "avg_ms": avg_ms, "launches": launches,
@@ -1014,11 +1069,15 @@ def main():
                         "iters_per_step": F["iters"] / args.steps,
                         "rel_res_true": F["reps"][-1].rel_res_true,
                         "loop_ms": F["reps"][-1].loop_ms,
+                        "time_to_solution_ms": F["reps"][-1].loop_ms,
                         "sigma_bar_rel_diff_vs_mixed": float(
                             np.abs(F["sigma_bar"] - R["sigma_bar"]).max()
                             / np.abs(F["sigma_bar"]).max()),
                         "kernels_ms_per_step": {k: v[1] / args.steps
                                                 for k, v in sorted(F["stats"].items())}}
+        line["time_to_solution_speedup_vs_fp64"] = F["reps"][-1].loop_ms / R["reps"][-1].loop_ms
+    if head == "mixed":
+        line["mixed_restarted"] = run_restarted(args, E, nu, macro, tol, maxit)
     if not args.no_serve:
         line["serving"] = run_serving(args)
     if not args.no_cpu:

@@ -291,6 +291,18 @@ jfft_status jfft_set_mixed_params(jfft_cell_t cell, double inner_tol, int max_ou
    then ends and the next FP64 sweep restarts from the corrected residual;
    the maxit of the solve still bounds the inner iterations of all sweeps. */
 jfft_status jfft_set_mixed_inner_cap(jfft_cell_t cell, int cap);
+/* Refinement sweeps after the first continue the FP32 CG of the previous
+   sweep (on = 1, the default: its search direction is kept, rescaled to the
+   new residual's norm, and only the residual is replaced by the FP64 one, a
+   "reliable update"; in exact arithmetic the iterates are those of one
+   uninterrupted CG run) or restart it from the new residual (on = 0, each
+   sweep then reduces the residual by the inner tolerance of
+   jfft_set_mixed_params).  With on = 1 a sweep ends after the residual has
+   dropped by `reduction` (in (0, 1), default 1e-2): the FP32 recursive
+   residual drifts from the true one by FP32 rounding times the residual the
+   sweep started from, so the replacement must come while that drift is
+   still small against the current residual. */
+jfft_status jfft_set_mixed_continue(jfft_cell_t cell, int on, double reduction);
 
 /* ---- Power-law material and Newton solve (nonlinear example, Sec. 4;
    Newton linearisation, Sec. 2.2, eq. lin_system) -------------------------

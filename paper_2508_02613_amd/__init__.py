@@ -80,6 +80,7 @@ _SIGS = {
     "jfft_set_void_value": (C.c_int, [_vp, C.c_double]),
     "jfft_set_mixed_params": (C.c_int, [_vp, C.c_double, C.c_int]),
     "jfft_set_mixed_inner_cap": (C.c_int, [_vp, C.c_int]),
+    "jfft_set_mixed_continue": (C.c_int, [_vp, C.c_int, C.c_double]),
     "jfft_set_stop_rule": (C.c_int, [_vp, C.c_int]),
     "jfft_set_diag_method": (C.c_int, [_vp, C.c_int]),
     "jfft_set_element": (C.c_int, [_vp, C.c_int]),
@@ -279,10 +280,18 @@ class Cell:
         """absolute=False: ||r|| <= tol ||f||; True: ||r||^2 <= tol (the paper's runs)."""
         _check(self._lib.jfft_set_stop_rule(self._h, 1 if absolute else 0))
 
-    def set_mixed_params(self, inner_tol=1e-6, max_outer=30, inner_cap=None):
+    def set_mixed_params(self, inner_tol=1e-6, max_outer=30, inner_cap=None, continue_cg=None,
+                         reduction=1e-2):
+        """Mixed refinement: inner tolerance of a restarted sweep, sweep cap,
+        FP32 iteration cap per sweep, and whether later sweeps continue the
+        FP32 CG (reliable updates every `reduction` of the residual, the
+        default) or restart it."""
         _check(self._lib.jfft_set_mixed_params(self._h, float(inner_tol), int(max_outer)))
         if inner_cap is not None:
             _check(self._lib.jfft_set_mixed_inner_cap(self._h, int(inner_cap)))
+        if continue_cg is not None:
+            _check(self._lib.jfft_set_mixed_continue(self._h, 1 if continue_cg else 0,
+                                                     float(reduction)))
 
     def solve(self, macro, tol=1e-8, maxit=1000, u0=None, want_sigma=False, out=None):
         """Returns (u [d, ...] device tensor, sigma_bar numpy, Report, sigma or None)."""

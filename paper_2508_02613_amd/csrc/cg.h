@@ -197,6 +197,86 @@ __global__ void k_cg_start(CgState *st, const double *partRR, long long nRR, con
   }
 }
 
+// Mixed precision, refinement sweeps after the first: the FP32 CG of the
+// previous sweep is continued instead of restarted (a "reliable update":
+// the recursive residual is replaced by the true FP64 residual, the search
+// direction is kept).  In exact arithmetic the replacement changes nothing,
+// so the iterates are those of one uninterrupted CG run; a restart would
+// drop the Krylov space built so far and repeat much of its convergence.
+// The FP32 vectors of a sweep are scaled by 1 / ||r|| of that sweep, so the
+// kept direction is rescaled by s = rn_prev / rn and beta = (r.z)_new /
+// (s^2 (r.z)_old).  A cell continues when its previous inner solve formed a
+// direction and did not break down; otherwise it restarts.  alpha = 0: the
+// previous sweep's last update of the correction was already applied.
+__global__ void k_cg_init_continue(CgState *st, double inner_tol, int maxit, int inner_cap,
+                                   long long cs) {
+  st = cshift(st, blockIdx.x, cs);
+  if (threadIdx.x != 0) return;
+  const bool cont = st->outer >= 1 && st->iter > 0 && st->status != ST_BREAKDOWN;
+  const double rel = fmax(inner_tol, 0.5 * st->tolr * sqrt(st->fnorm2) / st->rn);
+  int mx = maxit - st->total_iters;
+  if (mx < 1) mx = 1;
+  if (inner_cap > 0 && mx > inner_cap) mx = inner_cap;
+  st->tol2 = rel * rel;
+  st->maxit = mx;
+  st->hist_cap = 0;
+  st->iter = 0;
+  st->done = st->outer_done;
+  st->status = ST_OK;
+  st->pending = 0;
+  st->alpha = 0.0;
+  st->first = cont ? 0 : 1;
+  // parity is kept: k_scale_direction reads the buffer that holds p
+}
+
+// The kept direction, rescaled to this sweep's FP32 scale, into p1 (the
+// buffer the first iteration of a loop reads p_old from).
+template <typename Real>
+__global__ void k_scale_direction(const Real *p0, Real *p1, long long n, const CgState *st,
+                                  long long cs) {
+  const int cell = blockIdx.y;
+  st = cshift(st, cell, cs);
+  if (st->done || st->first) return;
+  const Real *src = cshift(st->parity ? (const Real *)p1 : p0, cell, cs);
+  Real *dst = cshift(p1, cell, cs);
+  const Real s = (Real)(st->rn_prev / st->rn);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = s * src[i];
+}
+
+// k_cg_start for a continued loop: also beta of the kept direction.
+__global__ void k_cg_start_continue(CgState *st, const double *partRR, long long nRR,
+                                    const double *partRZ, long long nRZ, long long cs) {
+  __shared__ double sm[CTRL_WAVES];
+  st = cshift(st, blockIdx.x, cs);
+  partRR = cshift(partRR, blockIdx.x, cs);
+  partRZ = cshift(partRZ, blockIdx.x, cs);
+  const double rr = fixed_sum(partRR, nRR, sm);
+  const double rz = fixed_sum(partRZ, nRZ, sm);
+  if (threadIdx.x == 0) {
+    if (st->done) return;
+    if (!st->first) {
+      const double s = st->rn_prev / st->rn;
+      const double beta = rz / (s * s * st->rz);
+      if (isfinite(beta)) {
+        st->beta = beta;
+      } else {
+        st->first = 1;  // restart from z
+      }
+    }
+    st->rr = rr;
+    st->rr0 = rr;
+    st->rz = rz;
+    if (rr <= st->tol2) {
+      st->done = 1;
+    } else if (st->maxit <= 0) {
+      st->done = 1;
+      st->status = ST_NOT_CONVERGED;
+    }
+  }
+}
+
 // Mixed precision: the FP64 residual ||f - K u|| of this sweep decides
 // whether refinement continues.  (The first sweep starts from u = u0.)
 __global__ void k_outer_check(CgState *st, const double *part, long long n, int max_outer,
@@ -208,6 +288,7 @@ __global__ void k_outer_check(CgState *st, const double *part, long long n, int 
   if (threadIdx.x == 0) {
     if (st->outer_done) return;
     const double rn = sqrt(rr);
+    st->rn_prev = st->rn;
     st->rn = rn;
     if (rn <= st->tolr * sqrt(st->fnorm2)) {
       st->outer_done = 1;

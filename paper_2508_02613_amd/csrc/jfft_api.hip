@@ -159,6 +159,8 @@ struct jfft_cell_s {
   double inner_tol = 1e-6;
   int max_outer = 30;
   int inner_cap = 2000;  // iterations of one FP32 inner solve (0: no cap)
+  bool mixed_continue = true;  // refinement sweeps continue the FP32 CG (reliable updates)
+  double update_tol = 1e-2;    // continued sweeps: residual reduction between reliable updates
   bool stop_abs = false;  // stopping rule ||r||^2 <= tol instead of ||r|| <= tol ||f||
   int diag_method = JFFT_DIAG_CLOSED_FORM;  // how J^1/2 is formed (Algorithm 2 or its closed form)
   int elem = JFFT_ELEM_QUAD;  // 2D element: bilinear quadrilateral or two linear triangles
@@ -877,15 +879,27 @@ jfft_status fetch_states(jfft_cell_s *c) {
 
 // PCG loop on prepared buffers (u = start vector, r = f - K u) for every cell
 // of the group; returns when every cell's flag is set.
+// cont (mixed refinement sweeps after the first): continue the previous
+// sweep's CG with its rescaled search direction (k_cg_init_continue).
 template <typename Real>
 jfft_status run_pcg(jfft_cell_s *c, const PcgBufs<Real> &b, bool mixed, int maxit,
-                    bool record) {
+                    bool record, bool cont = false) {
   History h{nullptr, nullptr, nullptr};
   if (record && c->hist_cap > 0) h = {c->hist[0], c->hist[1], c->hist[2]};
   long long nA = 0, nB = 0;
-  LAUNCH(c, KID_CTRL, k_cg_init<<<c->B, 1, 0, c->stream>>>(c->st, c->inner_tol, mixed ? 1 : 0, maxit, record ? c->hist_cap : 0, c->inner_cap, c->cs));
+  const double itol = c->mixed_continue ? c->update_tol : c->inner_tol;
+  if (cont) {
+    LAUNCH(c, KID_CTRL, k_cg_init_continue<<<c->B, 1, 0, c->stream>>>(c->st, itol, maxit, c->inner_cap, c->cs));
+    const long long n = (long long)c->dim * c->g.N;
+    LAUNCH(c, KID_VEC, k_scale_direction<Real><<<dim3(vec_blocks(n), c->B), 256, 0, c->stream>>>(b.p[0], b.p[1], n, c->st, c->cs));
+  } else {
+    LAUNCH(c, KID_CTRL, k_cg_init<<<c->B, 1, 0, c->stream>>>(c->st, itol, mixed ? 1 : 0, maxit, record ? c->hist_cap : 0, c->inner_cap, c->cs));
+  }
   TRY(precond<Real>(c, b.r, nullptr, b.Jh, b.z, b.spec, false, false, &nA, &nB, h));
-  LAUNCH(c, KID_CTRL, k_cg_start<<<c->B, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nA, c->partB, nB, c->cs));
+  if (cont)
+    LAUNCH(c, KID_CTRL, k_cg_start_continue<<<c->B, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nA, c->partB, nB, c->cs));
+  else
+    LAUNCH(c, KID_CTRL, k_cg_start<<<c->B, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nA, c->partB, nB, c->cs));
   const int gk = sizeof(Real) == 8 ? 0 : 1;
   const int G = c->tun.graph_iters;
   const bool graph = G > 0 && !c->timing;
@@ -1138,7 +1152,7 @@ jfft_status mixed_refine(jfft_cell_s *c, int maxit, bool have_u) {
     LAUNCH(c, KID_VEC, (k_convert<double, float><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->r, c->r32, nd, 1.0, c->st, c->cs)));
     LAUNCH(c, KID_VEC, k_fill<float><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->c32, 0.0f, nd, c->cs));
     PcgBufs<float> b{c->c32, c->r32, c->z32, c->q32, {c->p32[0], c->p32[1]}, c->E32, c->Jh32, c->spec32};
-    TRY(run_pcg<float>(c, b, true, maxit, false));
+    TRY(run_pcg<float>(c, b, true, maxit, false, sweep > 0 && c->mixed_continue));
     LAUNCH(c, KID_CTRL, k_outer_update<<<Bc, 1, 0, c->stream>>>(c->st, c->cs));
     LAUNCH(c, KID_VEC, k_axpy_f32_to_f64<<<dim3(nb, Bc), 256, 0, c->stream>>>(c->c32, c->u, nd, c->st, c->cs));
   }
@@ -2000,6 +2014,14 @@ jfft_status jfft_set_void_value(jfft_cell_t c, double value) {
 jfft_status jfft_set_mixed_inner_cap(jfft_cell_t c, int cap) {
   if (!c || cap < 0) return fail(JFFT_E_INVALID, "the inner iteration cap must be >= 0");
   c->inner_cap = cap;
+  return JFFT_OK;
+}
+
+jfft_status jfft_set_mixed_continue(jfft_cell_t c, int on, double reduction) {
+  if (!c || (on != 0 && on != 1) || !(reduction > 0.0 && reduction < 1.0))
+    return fail(JFFT_E_INVALID, "on must be 0 or 1 and reduction in (0, 1)");
+  c->mixed_continue = on == 1;
+  c->update_tol = reduction;
   return JFFT_OK;
 }
 

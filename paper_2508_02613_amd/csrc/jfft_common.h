@@ -87,6 +87,7 @@ struct CgState {
   double fnorm2;    // ||f||^2
   double fabs2;     // ||f_abs||^2 (scale of the homogeneous-material test)
   double rn;        // ||r||, FP64 refinement residual of the current sweep
+  double rn_prev;   // ||r|| of the previous sweep (the scale of its FP32 vectors)
   int homog;        // 1 if f vanishes to rounding: u = 0 after zero iterations
   int outer_done;   // refinement finished (mixed precision)
   int outer;        // refinement sweeps taken
@@ -96,8 +97,8 @@ struct CgState {
 };
 
 // Fourier tables of one axis for the Green symbol of K_ref (Q1 elements,
-// exact 2-point Gauss integration): a = (2 - 2 cos t)/h, b = h (2 + cos t)/3,
-// s = sin t, t = 2 pi k / n.
+// exact 2-point Gauss integration): a = (2 - 2 cos t)/h = 4 sin^2(t/2)/h,
+// b = h (2 + cos t)/3, s = sin t, t = 2 pi k / n.
 struct AxisTables {
   const double *a, *b, *s;
 };

@@ -329,3 +329,44 @@ def test_stress_field_matches_oracle(shape):
     say(f"  max |sigma_q - oracle| / max |sigma| = {err:.2e}; sigma_bar {es:.2e}")
     assert err <= 1e-12
     assert es <= 1e-12
+
+
+@pytest.mark.parametrize("case", ["grf16", "simp64", "voids16", "tri48"])
+def test_mixed_refinement_continued_vs_restarted(case):
+    """Mixed precision with the FP32 CG continued across refinement sweeps
+    (reliable updates, the default) and restarted at every sweep: both reach
+    the final true residual <= 1e-8 and the FP64 oracle's solution to the
+    accuracy that residual allows; the continued run takes no more inner
+    iterations than the restarted one plus one sweep's start-up."""
+    pkg = _pkg()
+    say(f"mixed refinement continued vs restarted: {case}")
+    element = "quad"
+    if case == "grf16":
+        E, macro = ji.grf_field((16, 16, 16), 1e4, seed=0), ji.unit_macro_strain(3, 0)
+    elif case == "simp64":
+        E, macro = ji.simp_field(64, seed=3), ji.unit_macro_strain(2, 2)
+    elif case == "voids16":
+        E, macro = ji.cosine_void_field(16, None), np.array([1.0, 1.0, 1.0])
+    else:
+        E, macro, element = ji.grf_field((48, 48), 1e4, seed=5, ell=0.1), ji.unit_macro_strain(2, 0), "tri"
+    if element == "tri":
+        from oracle import triangles as tri
+        ref = tri.solve(E, macro, LAM, MU, pc=3, tol=1e-12, maxit=20000)
+    else:
+        ref = oracle.solve(E, macro, LAM, MU, pc=3, tol=1e-12, maxit=20000)
+    out = {}
+    for cont in (True, False):
+        cell = pkg.Cell(E.shape, precision=pkg.MIXED, pc=pkg.PC_GREEN_JACOBI, element=element)
+        cell.set_mixed_params(continue_cg=cont)
+        cell.set_material(E, nu=0.3)
+        u, sbar, rep, _ = cell.solve(macro, tol=1e-8, maxit=20000)
+        out[cont] = (u.cpu().numpy(), sbar, rep)
+        cell.close()
+    for cont, (u, sbar, rep) in out.items():
+        err = np.linalg.norm(u - ref.u) / np.linalg.norm(ref.u)
+        say(f"  continue={cont}: iters {rep.iters} sweeps {rep.outer} true res "
+            f"{rep.rel_res_true:.2e} err(u) {err:.1e}")
+        assert rep.status == "ok" and rep.rel_res_true <= 1e-8
+        assert err <= 1e-6
+        assert np.abs(sbar - ref.sigma_bar).max() <= 1e-7 * np.abs(ref.sigma_bar).max()
+    assert out[True][2].iters <= out[False][2].iters + 2
