@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream measurement")
+    ap.add_argument("--serve-mode", choices=("slots", "handles", "both"), default="both",
+                    help="serving runs: continuous batching over group slots, whole handles "
+                         "per worker, or both")
     ap.add_argument("--graph", type=int, default=8,
                     help="PCG iterations per captured HIP graph in the timed steps (0: direct launches)")
     ap.add_argument("--serve-requests", type=int, default=400)
@@ -320,6 +323,12 @@ def serve_requests(pool, count, seed):
 LOAD_FRACTIONS = (0.5, 0.8, 0.95)
 
 
+def slots_per_group(shape):
+    """Requests per slot group (6 slots each) by cell size: more for small cells."""
+    n = max(shape)
+    return 8 if n <= 48 else (4 if n <= 64 else 2)
+
+
 def run_serving(args):
     """Saturated capacity (all requests at t = 0), then Poisson arrivals at
     0.5, 0.8 and 0.95 x that capacity, for the mixed and the FP64 solver at
@@ -327,18 +336,32 @@ def run_serving(args):
     case).  p99 is reported only for runs of at least 200 requests (at least
     two samples above it)."""
     import paper_2508_02613_amd as pkg
-    from paper_2508_02613_amd.serve import Server
+    from paper_2508_02613_amd.serve import Server, SlotServer
 
     nreq = args.serve_requests
     pool = serve_field_pool(80, 7)
     out = {"workload": (f"{nreq} requests per run, 3D side uniform from {{32,48,64,96,128}}, GRF "
                         "contrast log-uniform 1e2-1e4 (drawn from 80 distinct fields), 6 load "
-                        "cases -> C_eff each; 4 workers, 64 GiB admission budget, merge <= 4 "
-                        "requests of side <= 64, 8 PCG iterations per graph; Poisson arrivals "
-                        "at 0.5, 0.8 and 0.95 x the measured capacity"),
+                        "cases -> C_eff each, 64 GiB admission budget, 8 PCG iterations per "
+                        "graph; Poisson arrivals at 0.5, 0.8 and 0.95 x the measured capacity. "
+                        "slots_*: continuous batching over group slots (one group per shape, "
+                        "8 / 4 / 2 requests per group for side <= 48 / 64 / larger, admission "
+                        "and harvest every 8 iterations); mixed, fp64: 4 workers with whole "
+                        "handles, merge <= 4 waiting requests of side <= 64"),
            "unit": "requests/s (6 solves each); latency ms"}
-    for name, prec in (("mixed", pkg.MIXED), ("fp64", pkg.FP64)):
-        srv = Server(workers=4, budget_bytes=64 << 30, precision=prec, graph_iterations=8)
+    runs = []
+    if args.serve_mode in ("slots", "both"):
+        runs += [("slots_mixed", pkg.MIXED, True), ("slots_fp64", pkg.FP64, True)]
+    if args.serve_mode in ("handles", "both"):
+        runs += [("mixed", pkg.MIXED, False), ("fp64", pkg.FP64, False)]
+    for name, prec, slots in runs:
+        print(f"[serving] {name}: warm-up, capacity, then Poisson loads {LOAD_FRACTIONS}",
+              file=sys.stderr, flush=True)
+        if slots:
+            srv = SlotServer(budget_bytes=64 << 30, precision=prec, graph_iterations=8,
+                             slots_per_group=slots_per_group)
+        else:
+            srv = Server(workers=4, budget_bytes=64 << 30, precision=prec, graph_iterations=8)
         srv.run(serve_requests(pool, 8, 99), rate=None)  # warm-up: handles, graphs, kernels
         sat = srv.run(serve_requests(pool, nreq, 1), rate=None)
         row = {"capacity_requests_per_s": sat["requests_per_s"],
@@ -347,13 +370,18 @@ def run_serving(args):
         worst = sat["max_rel_res_true"]
         for frac in LOAD_FRACTIONS:
             lam = frac * sat["requests_per_s"]
+            print(f"[serving] {name}: capacity {sat['requests_per_s']:.1f} req/s; load {frac}",
+                  file=sys.stderr, flush=True)
             po = srv.run(serve_requests(pool, nreq, 2), rate=lam, seed=3)
             row["loads"][str(frac)] = {
                 "poisson_rate": lam, "requests": po["requests"],
                 "requests_per_s": po["requests_per_s"], "solves_per_s": po["solves_per_s"],
                 "p50_latency_ms": po["p50_latency_ms"], "p95_latency_ms": po["p95_latency_ms"],
-                "p99_latency_ms": po["p99_latency_ms"] if po["requests"] >= 200 else None,
-                "mean_merged": po["mean_merged"]}
+                "p99_latency_ms": po["p99_latency_ms"] if po["requests"] >= 200 else None}
+            if slots:
+                row["loads"][str(frac)]["mean_busy_slots_per_chunk"] = po["mean_busy_slots_per_chunk"]
+            else:
+                row["loads"][str(frac)]["mean_merged"] = po["mean_merged"]
             ok = ok and po["all_ok"]
             worst = max(worst, po["max_rel_res_true"])
         srv.close()
@@ -393,6 +421,31 @@ def run_simp2d(args):
         ok = all(r["report"].status == "ok" for r in res)
         worst = max(r["report"].rel_res_true for r in res)
     wall = float(np.mean(walls))
+    # roofline of the dominant kernel: the group of the largest cells alone,
+    # event-timed (its launch parameters from the autotuner's cache), so no
+    # other group's kernels overlap the timed launches
+    from paper_2508_02613_amd import tune
+
+    n_big = int(sizes.max())
+    idx = [i for i, n in enumerate(sizes) if n == n_big]
+    grp = pkg.Cell((n_big, n_big), precision=pkg.MIXED, batch=len(idx),
+                   stream=torch.cuda.Stream())
+    tune.apply(grp, tune.autotune((n_big, n_big), batch=len(idx), precision=pkg.MIXED))
+    grp.set_material(np.stack([fields[i] for i in idx]), nu=0.3)
+    mac = np.stack([macros[i] for i in idx])
+    grp.solve_batch(mac, tol=1e-8, maxit=20000)
+    grp.reset_timing()
+    grp.enable_timing(True)
+    _, _, reps_ev, _ = grp.solve_batch(mac, tol=1e-8, maxit=20000)
+    torch.cuda.synchronize()
+    stats = grp.kernel_stats()
+    tun = grp.tunables()
+    grp.close()
+    ev_iters = sum(r.iters for r in reps_ev)
+    launches, tot_ms = stats["stiffness_cg"]
+    N_big = n_big * n_big
+    cell_bytes = algorithmic_bytes("stiffness_cg", 2, N_big, n_big, 4)
+    achieved = cell_bytes * ev_iters / (tot_ms * 1e-3) / 1e9
     # one at a time, FP64, same cells and tolerance
     t0 = time.perf_counter()
     its64 = []
@@ -423,6 +476,19 @@ def run_simp2d(args):
                                "value": float((dofs * np.array(its64)).sum() / wall64),
                                "iterations_mean": float(np.mean(its64))},
         "speedup_vs_one_at_a_time_fp64": wall64 / wall,
+        "roofline": {"bound": "hbm", "kernel": f"stiffness_cg (2D Q1, FP32, {n_big}^2 group)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": load_traffic(f"simp2d_mixed_{n_big}x{len(idx)}", "stiffness_cg"),
+                     "avg_ms": tot_ms / launches, "launches": launches,
+                     "cell_iterations": ev_iters,
+                     "algorithmic_bytes_per_cell_iteration": cell_bytes,
+                     "algorithmic_bytes_per_launch": cell_bytes * len(idx),
+                     "tunables": tun,
+                     "measured": (f"HIP events on the group's stream around every launch: the "
+                                  f"{len(idx)} cells of side {n_big} as one group alone, one "
+                                  "further solve with direct launches")},
+        "kernels_ms_largest_group": {k: v[1] for k, v in sorted(stats.items())},
     }
 
 

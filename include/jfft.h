@@ -177,6 +177,45 @@ jfft_status jfft_solve_batch(jfft_cell_t cell, const double *macro_strains, doub
                              const double *u0_dev, double *u_dev, double *sigma_dev,
                              double *sigma_bars, jfft_report *reports);
 
+/* Continuous batching (serving): the cells of a group as slots that solves
+   enter and leave between chunks of PCG iterations, so a solve that arrives
+   while others run joins the next chunk instead of waiting for the group to
+   drain.  Every cell keeps its own CG state, stopping test and fixed-order
+   reductions, and each chunk starts on the same search-direction buffer, so
+   a slot's results are bitwise those of the same cell solved alone (same
+   grid, precision, preconditioner, element, options and tunables),
+   whatever the other slots hold and whenever it was admitted.  The
+   algorithm per slot is that of jfft_solve (Sec. 3.3 and Alg. 1/2; the
+   mixed-precision refinement sweeps run per slot as its inner solves stop).
+   Slot states (the `states` array): 0 free, 1 running, 2 finished (results
+   waiting for jfft_slot_harvest).  While any slot is running or finished,
+   calls that act on the whole group (jfft_set_material*, jfft_solve*,
+   operators, power-law and topology calls) fail with JFFT_E_INVALID.
+
+   jfft_slot_admit: material E_dev (device, [N] moduli of this slot's cell),
+     Poisson ratio nu (the running slots share the Lame constants: a
+     different nu is refused while another slot runs), macro strain (host,
+     d* values), tol and maxit as in jfft_solve (stopping rule and options of
+     the group apply).  The slot must be free.  Synchronises the stream (the
+     material check).  Errors: JFFT_E_INVALID (slot out of range or busy,
+     bad arguments, bad E), JFFT_E_HIP.
+   jfft_slots_step: at least `iterations` (>= 1) PCG iterations of every
+     running slot (whole replays of the captured chunk when graph replay is
+     on, else an even number of direct launches), then the bookkeeping of
+     slots whose loop stopped (FP64: the owed update; mixed: the next
+     refinement sweep, or the end); writes the group's slot states to
+     `states` (host, batch ints) if not NULL.  Synchronises the stream.
+   jfft_slot_harvest: post-processing of a finished slot as in jfft_solve:
+     u_dev (device out [d][N], mean-free fluctuation, or NULL),
+     sigma_dev (device out [d*][2^d][N] or NULL), sigma_bar (host out d*),
+     report (host out or NULL; loop_ms = host time from admission to the
+     stop).  Frees the slot.  Returns the solve's status. */
+jfft_status jfft_slot_admit(jfft_cell_t group, int slot, const double *E_dev, double nu,
+                            const double *macro_strain, double tol, int maxit);
+jfft_status jfft_slots_step(jfft_cell_t group, int iterations, int *states);
+jfft_status jfft_slot_harvest(jfft_cell_t group, int slot, double *u_dev, double *sigma_dev,
+                              double *sigma_bar, jfft_report *report);
+
 /* Launch mode of the PCG loop.  iterations = 0 (default): kernels are
    launched one by one and the host polls the stop flags after 2, 4, ..., 32
    iterations.  An even iterations in [2, 64]: the loop body of that many
@@ -193,12 +232,35 @@ jfft_status jfft_set_graph_iterations(jfft_cell_t cell, int iterations);
             it).  It sets how the p.q partial sums are grouped, so results
             may differ in the last bits between settings;
      ygrid: persistent blocks of the y FFT pass per launch (all components
-            and cells; 1..65535).
-   jfft_get_tunables reports the current values (defaults chosen from the
-   grid size at creation).  A change drops any captured graph. */
+            and cells; 1..65535);
+     tiles2d: 16 x 16 element tiles per block of the 2D stiffness kernel
+            (1 or 2; 0 restores the default, two in FP32 and one in FP64;
+            3D ignores it).  Like tz it regroups the p.q partial sums;
+     xrows: grid rows per block of the x FFT passes, a power of two; values
+            above the most that fit in LDS are clamped to it (0 restores the
+            default, the most that fit).  It regroups the ||r||^2 partial
+            sums;
+     fused_control: 0 (default) launches a single-block kernel for each
+            scalar step of a PCG iteration (alpha, the stopping test, beta);
+            1 runs each step in the last block to finish of the kernel that
+            produces its partial sums (stiffness, x-forward and Green passes;
+            Green and Green-Jacobi preconditioners), saving three launches
+            per iteration.  Every block then makes its partial visible with
+            a device-scope fence, which on a multi-XCD GPU writes back the
+            block's L2 and costs more than a launch on large grids; it can
+            pay on small ones.  The two sum the partials in different fixed
+            orders.
+   tiles2d and xrows act on the kernels of the PCG loop's precision (the
+   FP32 kernels of a mixed-precision cell; its FP64 residual and
+   post-processing kernels keep the defaults).  jfft_get_tunables reports
+   the values in effect (tiles2d and xrows as resolved for the grid and the
+   loop's precision).  A change drops any captured graph. */
 typedef struct {
   int tz;
   int ygrid;
+  int tiles2d;
+  int xrows;
+  int fused_control;
 } jfft_tunables;
 jfft_status jfft_set_tunables(jfft_cell_t cell, const jfft_tunables *t);
 jfft_status jfft_get_tunables(jfft_cell_t cell, jfft_tunables *t);

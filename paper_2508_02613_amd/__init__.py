@@ -35,7 +35,8 @@ _dp = C.POINTER(C.c_double)
 
 
 class _Tunables(C.Structure):
-    _fields_ = [("tz", C.c_int), ("ygrid", C.c_int)]
+    _fields_ = [("tz", C.c_int), ("ygrid", C.c_int), ("tiles2d", C.c_int), ("xrows", C.c_int),
+                ("fused_control", C.c_int)]
 
 
 class _Report(C.Structure):
@@ -61,6 +62,9 @@ _SIGS = {
                                     _vp, _dp, C.POINTER(_Report)]),
     "jfft_solve_batch": (C.c_int, [_vp, _dp, C.c_double, C.c_int, _vp, _vp, _vp, _dp,
                                    C.POINTER(_Report)]),
+    "jfft_slot_admit": (C.c_int, [_vp, C.c_int, _vp, C.c_double, _dp, C.c_double, C.c_int]),
+    "jfft_slots_step": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int)]),
+    "jfft_slot_harvest": (C.c_int, [_vp, C.c_int, _vp, _vp, _dp, C.POINTER(_Report)]),
     "jfft_set_graph_iterations": (C.c_int, [_vp, C.c_int]),
     "jfft_set_tunables": (C.c_int, [_vp, C.POINTER(_Tunables)]),
     "jfft_get_tunables": (C.c_int, [_vp, C.POINTER(_Tunables)]),
@@ -355,15 +359,57 @@ class Cell:
             _check(st)
         return u, sbar, [_report(r) for r in reps], sig
 
+    # ------------------------------------------- continuous batching (slots)
+    SLOT_FREE, SLOT_RUNNING, SLOT_FINISHED = 0, 1, 2
+
+    def slot_admit(self, slot, E, nu, macro, tol=1e-8, maxit=1000):
+        """Start one cell's solve in slot `slot` of the group
+        (jfft_slot_admit): E [shape], macro [d*]."""
+        E = self._dev(E, self.shape)
+        m = (C.c_double * self.ds)(*[float(v) for v in np.asarray(macro, dtype=float)])
+        _check(self._lib.jfft_slot_admit(self._h, int(slot), _ptr(E), float(nu), m, float(tol),
+                                         int(maxit)))
+
+    def slots_step(self, iterations=8):
+        """At least `iterations` PCG iterations of every running slot; returns
+        the slot states (SLOT_FREE / SLOT_RUNNING / SLOT_FINISHED) as an array."""
+        st = (C.c_int * self.batch)()
+        _check(self._lib.jfft_slots_step(self._h, int(iterations), st))
+        return np.array(st[:], dtype=np.int32)
+
+    def slot_harvest(self, slot, want_u=True, want_sigma=False):
+        """Results of a finished slot, which becomes free: (u [d, ...] or
+        None, sigma_bar [d*], Report, sigma [d*, 2^d, ...] or None)."""
+        torch = self.torch
+        u = sig = None
+        if want_u:
+            u = torch.empty((self.dim,) + self.shape, dtype=torch.float64, device=self.device)
+        if want_sigma:
+            sig = torch.empty((self.ds, self._nq()) + self.shape, dtype=torch.float64,
+                              device=self.device)
+        sbar = (C.c_double * self.ds)()
+        rep = _Report()
+        st = self._lib.jfft_slot_harvest(self._h, int(slot), _ptr(u), _ptr(sig), sbar,
+                                         C.byref(rep))
+        if st not in (0, 4, 5):
+            _check(st)
+        return u, np.array(sbar[:]), _report(rep), sig
+
     def tunables(self):
         t = _Tunables()
         _check(self._lib.jfft_get_tunables(self._h, C.byref(t)))
-        return {"tz": int(t.tz), "ygrid": int(t.ygrid)}
+        return {"tz": int(t.tz), "ygrid": int(t.ygrid), "tiles2d": int(t.tiles2d),
+                "xrows": int(t.xrows), "fused_control": int(t.fused_control)}
 
-    def set_tunables(self, tz=None, ygrid=None):
+    def set_tunables(self, tz=None, ygrid=None, tiles2d=None, xrows=None, fused_control=None):
+        """Launch parameters (None keeps the current value; see jfft_tunables)."""
         cur = self.tunables()
         t = _Tunables(int(tz if tz is not None else cur["tz"]),
-                      int(ygrid if ygrid is not None else cur["ygrid"]))
+                      int(ygrid if ygrid is not None else cur["ygrid"]),
+                      int(tiles2d if tiles2d is not None else cur["tiles2d"]),
+                      int(xrows if xrows is not None else cur["xrows"]),
+                      int(fused_control if fused_control is not None
+                          else cur["fused_control"]))
         _check(self._lib.jfft_set_tunables(self._h, C.byref(t)))
 
     def set_graph_iterations(self, iterations):

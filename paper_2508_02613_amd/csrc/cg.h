@@ -33,18 +33,6 @@ __device__ __forceinline__ double fixed_sum(const double *p, long long n, double
   return block_sum<CTRL_THREADS>(v, sm);
 }
 
-enum StatusCode { ST_OK = 0, ST_NOT_CONVERGED = 4, ST_BREAKDOWN = 5 };
-
-struct History {
-  double *alpha, *beta, *res;
-};
-
-__device__ __forceinline__ void shift_hist(History &h, int cell, long long cs) {
-  h.alpha = cshift(h.alpha, cell, cs);
-  h.beta = cshift(h.beta, cell, cs);
-  h.res = cshift(h.res, cell, cs);
-}
-
 // alpha_k = (r.z) / (p.q); breakdown if p.q <= 0 or alpha not finite.
 // parity: which of the two search-direction buffers holds p_k.
 __global__ void k_cg_alpha(CgState *st, const double *part, long long n, History h, int parity,
@@ -55,20 +43,7 @@ __global__ void k_cg_alpha(CgState *st, const double *part, long long n, History
   shift_hist(h, blockIdx.x, cs);
   if (st->done) return;
   const double pq = fixed_sum(part, n, sm);
-  if (threadIdx.x == 0) {
-    st->pq = pq;
-    st->parity = parity;
-    const double alpha = st->rz / pq;
-    if (!(pq > 0.0) || !isfinite(alpha)) {
-      st->done = 1;
-      st->status = ST_BREAKDOWN;
-      st->pending = 0;
-    } else {
-      st->alpha = alpha;
-      st->pending = 1;
-      if (h.alpha && st->iter < st->hist_cap) h.alpha[st->iter] = alpha;
-    }
-  }
+  if (threadIdx.x == 0) cg_alpha_step(st, pq, h, parity);
 }
 
 // ||r_{k+1}||^2; count the update of u; stop on tolerance or maxit.
@@ -79,20 +54,7 @@ __global__ void k_cg_rr(CgState *st, const double *part, long long n, History h,
   shift_hist(h, blockIdx.x, cs);
   if (st->done) return;
   const double rr = fixed_sum(part, n, sm);
-  if (threadIdx.x == 0) {
-    st->rr = rr;
-    st->iter += 1;
-    if (h.res && st->iter - 1 < st->hist_cap) h.res[st->iter - 1] = sqrt(rr);
-    if (rr <= st->tol2) {
-      st->done = 1;
-      st->status = ST_OK;
-    } else if (st->iter >= st->maxit) {
-      st->done = 1;
-      st->status = ST_NOT_CONVERGED;
-    }
-    // the last iteration forms no beta: its history entry is NaN
-    if (st->done && h.beta && st->iter - 1 < st->hist_cap) h.beta[st->iter - 1] = __builtin_nan("");
-  }
+  if (threadIdx.x == 0) cg_rr_step(st, rr, h);
 }
 
 // beta_k = (r.z)_new / (r.z)_old.
@@ -103,18 +65,7 @@ __global__ void k_cg_beta(CgState *st, const double *part, long long n, History 
   shift_hist(h, blockIdx.x, cs);
   if (st->done) return;
   const double rz = fixed_sum(part, n, sm);
-  if (threadIdx.x == 0) {
-    const double beta = rz / st->rz;
-    if (!isfinite(beta)) {
-      st->done = 1;
-      st->status = ST_BREAKDOWN;
-    } else {
-      st->beta = beta;
-      st->rz = rz;
-      st->first = 0;
-      if (h.beta && st->iter - 1 < st->hist_cap) h.beta[st->iter - 1] = beta;
-    }
-  }
+  if (threadIdx.x == 0) cg_beta_step(st, rz, h);
 }
 
 // ||f||^2 and ||f_abs||^2 from partials; the homogeneous-material test.
@@ -166,6 +117,7 @@ __global__ void k_cg_init(CgState *st, double inner_tol, int mixed, int maxit, i
   st->maxit = mx;
   st->hist_cap = hist_cap;
   st->iter = 0;
+  st->arrive[0] = st->arrive[1] = st->arrive[2] = 0;
   st->done = st->outer_done;
   st->status = ST_OK;
   st->pending = 0;
@@ -221,6 +173,7 @@ __global__ void k_cg_init_continue(CgState *st, double inner_tol, int maxit, int
   st->maxit = mx;
   st->hist_cap = 0;
   st->iter = 0;
+  st->arrive[0] = st->arrive[1] = st->arrive[2] = 0;
   st->done = st->outer_done;
   st->status = ST_OK;
   st->pending = 0;
@@ -311,6 +264,17 @@ __global__ void k_outer_update(CgState *st, long long cs) {
     st->outer_done = 1;
     st->final_status = ST_BREAKDOWN;
   }
+}
+
+// A free slot of a continuously batched group: stopped, so every kernel of
+// the captured iterations returns at once for it.
+__global__ void k_slot_park(CgState *st, long long cs) {
+  st = cshift(st, blockIdx.x, cs);
+  if (threadIdx.x != 0) return;
+  st->done = 1;
+  st->outer_done = 1;
+  st->pending = 0;
+  st->arrive[0] = st->arrive[1] = st->arrive[2] = 0;
 }
 
 // FP64 solve: final status from the loop state.

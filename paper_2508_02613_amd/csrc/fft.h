@@ -287,6 +287,8 @@ struct XArgs {
   typename CxT<Real>::T *spec;  // half spectrum, tile-major (see TileW)
   double *partA;       // ||r||^2 partials (forward), r.z partials (inverse)
   const CgState *st;
+  CgState *ctl;        // forward pass in the loop: the same state when the ||r||^2 step is fused
+  History h;
   const double2 *tw;   // exp(-2 pi i j / nx), j < nx
   FftPlan plan;        // length nx / 2
   int nx, mx, ntx, ny;
@@ -452,6 +454,9 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
   }
   const double s = block_sum<FFT_THREADS>(rr, red);
   if (threadIdx.x == 0 && partA) partA[blockIdx.x] = s;
+  if (a.ctl)
+    fused_ctrl<FFT_THREADS, CTRL_RR>(cshift(a.ctl, cell, a.cs), partA, gridDim.x, a.h, cell,
+                                     a.cs, 0, red);
 }
 
 // Inverse: t = irfft(X) (unnormalised), z = J^1/2 t (USE_J).  (r.z is
@@ -670,6 +675,8 @@ template <typename Real>
 struct GArgs {
   typename CxT<Real>::T *spec;
   const CgState *st;
+  CgState *ctl;       // in the loop: the same state when the beta step is fused (else NULL)
+  History h;
   const double2 *tw;  // exp(-2 pi i j / L), L = length of the last axis
   FftPlan plan;
   AxisTables tx, ty, tz;  // Fourier tables of K_ref
@@ -963,6 +970,9 @@ __global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
   __shared__ double red[NT / 64];
   const double srz = block_sum<NT>(rz, red);
   if (threadIdx.x == 0 && a.partB) cshift(a.partB, blockIdx.z, a.cs)[blockIdx.x] = srz;
+  if (a.ctl)
+    fused_ctrl<NT, CTRL_BETA>(cshift(a.ctl, blockIdx.z, a.cs), cshift(a.partB, blockIdx.z, a.cs),
+                              gridDim.x, a.h, blockIdx.z, a.cs, 0, red);
 }
 
 // ------------------------------------- diagonal / identity preconditioner -

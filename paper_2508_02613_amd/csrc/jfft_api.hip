@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -107,6 +108,9 @@ struct Tunables {
   int tz = 32;          // z planes per stiffness block (3D)
   int ygrid = 2048;     // persistent blocks of the y pass (all components and cells)
   int graph_iters = 0;  // iterations per captured graph (0: launch kernels directly)
+  int tiles2d = 0;      // 16 x 16 tiles per 2D stiffness block (1 or 2; 0: by precision)
+  int xrows = 0;        // rows per block of the x passes (power of two; 0: the most that fit)
+  int fused_control = 0;  // CG scalar steps in the last block of their producers (0: own launches)
 };
 
 }  // namespace
@@ -178,6 +182,12 @@ struct jfft_cell_s {
   // allocated on first use and owned by the handle
   double *topo = nullptr;
   int topo_m = 0;
+
+  // continuous batching: per-cell slot state (empty until the first admission)
+  std::vector<int> slot_state, slot_maxit, slot_sweep;
+  std::vector<std::chrono::steady_clock::time_point> slot_t0;
+  std::vector<double> slot_ms;
+  bool in_view = false;  // per-cell pointers moved to one slot (CellView)
 
   // captured iteration chunks
   hipGraphExec_t gexec[2] = {nullptr, nullptr};  // [0] FP64, [1] FP32 inner
@@ -288,6 +298,8 @@ struct Layout {
   }
 };
 
+// The most rows an x-pass block holds; the xrows tunable may lower it to
+// any power of two down to 1 (more, smaller blocks for small grids).
 template <typename Real>
 int x_rows_per_block(int m) {  // a power of two (tile-major index math uses shifts)
   const int cap = std::max(1, std::min(64, MaxPt<Real>::value * FFT_THREADS / std::max(1, m)));
@@ -370,23 +382,28 @@ size_t layout_workspace(jfft_cell_s *c, unsigned char *base) {
 
 // Output-node tile of the stiffness kernels (x and y edge) and the tile count of a grid.
 int stencil_tile_x(int dim) { return dim == 3 ? TX3 : TILE; }
-int stencil_tile_y(int dim, bool fp64) {
-  return dim == 3 ? TY3 : (fp64 ? ty2<double>() : ty2<float>());
+// 2D: tiles per block from the tunable, else two in FP32 and one in FP64
+// (measured best on the 512^2 groups)
+int tiles2d_of(const jfft_cell_s *c, bool fp64);
+int stencil_tile_y(int dim, bool fp64, int tiles2d = 0) {
+  if (dim == 3) return TY3;
+  if (tiles2d == 0) return fp64 ? ty2<double>() : ty2<float>();
+  return tiles2d * TILE;
 }
-long long stencil_tiles(int dim, int nx, int ny, bool fp64) {
-  const int tx = stencil_tile_x(dim), ty = stencil_tile_y(dim, fp64);
+long long stencil_tiles(int dim, int nx, int ny, bool fp64, int tiles2d = 0) {
+  const int tx = stencil_tile_x(dim), ty = stencil_tile_y(dim, fp64, tiles2d);
   return (long long)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
 }
 
 long long max_partials(jfft_cell_s *c) {
   const GridDev &g = c->g;
   long long mx = 4 * 1024;  // vector kernels
-  const long long tiles = std::max(stencil_tiles(c->dim, g.nx, g.ny, true),
-                                   stencil_tiles(c->dim, g.nx, g.ny, false));
+  // the most blocks any tile shape gives (one 16 x 16 tile per 2D block)
+  const long long tiles = std::max(stencil_tiles(c->dim, g.nx, g.ny, true, c->dim == 2 ? 1 : 0),
+                                   stencil_tiles(c->dim, g.nx, g.ny, false, c->dim == 2 ? 1 : 0));
   mx = std::max(mx, tiles * ((g.nz + 2 - 1) / 2));  // smallest z chunk allowed (tz >= 2)
-  const int m = g.nx / 2;
   const long long rows = (long long)c->dim * g.ny * g.nz;
-  mx = std::max(mx, (rows + x_rows_per_block<double>(m) - 1) / x_rows_per_block<double>(m));
+  mx = std::max(mx, rows);  // x passes at one row per block (the smallest xrows)
   mx = std::max(mx, (g.N + 255) / 256 * 6);  // stress partials [ds][blocks]
   mx = std::max(mx, (long long)((g.mx + 7) / 8) * (c->dim == 3 ? g.ny : 1));  // Green-pass r.z partials
   return mx;
@@ -571,18 +588,29 @@ int pick_tz(const GridDev &g, int slots, int per_cu) {
   return best;
 }
 
+// The tile-shape tunables apply to the kernels of the PCG loop's precision
+// (FP32 in a mixed-precision cell); a mixed cell's FP64 kernels (residuals,
+// post-processing) keep their defaults.
+bool loop_precision(const jfft_cell_s *c, bool fp64) { return fp64 == (c->prec == JFFT_FP64); }
+
+int tiles2d_of(const jfft_cell_s *c, bool fp64) {
+  if (c->tun.tiles2d && loop_precision(c, fp64)) return c->tun.tiles2d;
+  return (fp64 ? ty2<double>() : ty2<float>()) / TILE;
+}
+
 long long stencil_blocks_per_cell(jfft_cell_s *c, bool fp64) {
   const GridDev &g = c->g;
   const int tz = c->dim == 3 ? std::min(c->tun.tz, g.nz) : 1;
   const int nbz = c->dim == 3 ? (g.nz + tz - 1) / tz : 1;
-  return stencil_tiles(c->dim, g.nx, g.ny, fp64) * nbz;
+  return stencil_tiles(c->dim, g.nx, g.ny, fp64, c->dim == 2 ? tiles2d_of(c, fp64) : 0) * nbz;
 }
 
 template <typename Real, int MODE>
 jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a, int cells) {
   const int kid = MODE == SM_CG ? KID_STIFF_CG : (MODE == SM_APPLY ? KID_STIFF_APPLY : KID_STIFF_COMB);
   const GridDev &g = c->g;
-  const int tx = stencil_tile_x(c->dim), ty = stencil_tile_y(c->dim, sizeof(Real) == 8);
+  const int tt = c->dim == 2 ? tiles2d_of(c, sizeof(Real) == 8) : 0;
+  const int tx = stencil_tile_x(c->dim), ty = stencil_tile_y(c->dim, sizeof(Real) == 8, tt);
   dim3 gr((g.nx + tx - 1) / tx, (g.ny + ty - 1) / ty, a.nbz * cells);
   if (c->nl) {
     // the power-law tangent (3D cells, checked when the material is set);
@@ -597,11 +625,16 @@ jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a, int cel
     LAUNCH(c, kid, (k_stiffness3d<Real, MODE, true><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
   } else if (c->dim == 3) {
     LAUNCH(c, kid, (k_stiffness3d<Real, MODE, false><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
-  } else {
-    if (c->elem == JFFT_ELEM_TRI)
-      LAUNCH(c, kid, (k_stiffness2d<Real, MODE, true><<<gr, STENCIL_THREADS, 0, c->stream>>>(a)));
+  } else if (c->elem == JFFT_ELEM_TRI) {
+    if (tt == 2)
+      LAUNCH(c, kid, (k_stiffness2d<Real, MODE, true, 2><<<gr, STENCIL_THREADS, 0, c->stream>>>(a)));
     else
-      LAUNCH(c, kid, (k_stiffness2d<Real, MODE, false><<<gr, STENCIL_THREADS, 0, c->stream>>>(a)));
+      LAUNCH(c, kid, (k_stiffness2d<Real, MODE, true, 1><<<gr, STENCIL_THREADS, 0, c->stream>>>(a)));
+  } else {
+    if (tt == 2)
+      LAUNCH(c, kid, (k_stiffness2d<Real, MODE, false, 2><<<gr, STENCIL_THREADS, 0, c->stream>>>(a)));
+    else
+      LAUNCH(c, kid, (k_stiffness2d<Real, MODE, false, 1><<<gr, STENCIL_THREADS, 0, c->stream>>>(a)));
   }
   return JFFT_OK;
 }
@@ -627,6 +660,8 @@ XArgs<Real> x_args(jfft_cell_s *c, bool check_done) {
   a.ny = c->g.ny;
   a.nrows = (long long)c->dim * c->g.ny * c->g.nz;
   a.rows_per_block = x_rows_per_block<Real>(c->g.nx / 2);
+  if (c->tun.xrows && c->tun.xrows < a.rows_per_block && loop_precision(c, sizeof(Real) == 8))
+    a.rows_per_block = c->tun.xrows;
   a.log2_rb = 0;
   while ((1 << a.log2_rb) < a.rows_per_block) ++a.log2_rb;
   a.dm = FastDiv(c->g.nx / 2);
@@ -640,9 +675,11 @@ XArgs<Real> x_args(jfft_cell_s *c, bool check_done) {
 template <typename Real>
 jfft_status launch_xfwd(jfft_cell_s *c, Real *r, const Real *q, const Real *Jh,
                         typename CxT<Real>::T *spec, double *partA, bool update, bool check_done,
-                        long long *nblk) {
+                        long long *nblk, bool fuse = false, History h = {nullptr, nullptr, nullptr}) {
   using C = typename CxT<Real>::T;
   XArgs<Real> a = x_args<Real>(c, check_done);
+  a.ctl = fuse ? c->st : nullptr;
+  a.h = h;
   a.r = r;
   a.q = q;
   a.Jh = Jh;
@@ -727,12 +764,14 @@ jfft_status launch_ypass(jfft_cell_s *c, typename CxT<Real>::T *spec, bool inv, 
 // receives their number per cell.
 template <typename Real>
 jfft_status launch_green(jfft_cell_s *c, typename CxT<Real>::T *spec, bool check_done,
-                         long long *nblk) {
+                         long long *nblk, bool fuse = false, History h = {nullptr, nullptr, nullptr}) {
   using C = typename CxT<Real>::T;
   GArgs<Real> a{};
   a.spec = spec;
   a.partB = c->partB;
   a.st = c->st;
+  a.ctl = fuse ? c->st : nullptr;
+  a.h = h;
   const int La = c->dim == 3 ? 2 : 1;
   a.tw = c->tw[La];
   a.plan = c->dim == 3 ? c->plan_z : c->plan_y;
@@ -787,7 +826,9 @@ jfft_status launch_green(jfft_cell_s *c, typename CxT<Real>::T *spec, bool check
 }
 
 // z = M^-1 r.  update: r <- r - alpha q first.  Partials: partA = ||r||^2,
-// partB = r.z.  In the loop, the CG control kernels run between the pieces.
+// partB = r.z.  In the loop, the CG control steps run between the pieces:
+// in the last blocks of the x-forward and Green passes (fused control), or
+// as single-block kernels.
 template <typename Real>
 jfft_status precond(jfft_cell_s *c, Real *r, const Real *q, const Real *Jh, Real *z,
                     typename CxT<Real>::T *spec, bool update, bool in_loop, long long *nA,
@@ -818,17 +859,18 @@ jfft_status precond(jfft_cell_s *c, Real *r, const Real *q, const Real *Jh, Real
     return JFFT_OK;
   }
   const Real *J = useJ(c) ? Jh : nullptr;
-  TRY(launch_xfwd<Real>(c, r, q, J, spec, c->partA, update, in_loop, nA));
-  if (in_loop) LAUNCH(c, KID_CTRL, k_cg_rr<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, *nA, h, c->cs));
+  const bool fuse = in_loop && c->tun.fused_control;
+  TRY(launch_xfwd<Real>(c, r, q, J, spec, c->partA, update, in_loop, nA, fuse, h));
+  if (in_loop && !fuse) LAUNCH(c, KID_CTRL, k_cg_rr<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, *nA, h, c->cs));
   if (c->dim == 3) {
     TRY(launch_ypass<Real>(c, spec, false, in_loop));
-    TRY(launch_green<Real>(c, spec, in_loop, nB));
+    TRY(launch_green<Real>(c, spec, in_loop, nB, fuse, h));
     TRY(launch_ypass<Real>(c, spec, true, in_loop));
   } else {
-    TRY(launch_green<Real>(c, spec, in_loop, nB));
+    TRY(launch_green<Real>(c, spec, in_loop, nB, fuse, h));
   }
   TRY(launch_xinv<Real>(c, J, spec, z, in_loop));
-  if (in_loop) LAUNCH(c, KID_CTRL, k_cg_beta<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partB, *nB, h, c->cs));
+  if (in_loop && !fuse) LAUNCH(c, KID_CTRL, k_cg_beta<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partB, *nB, h, c->cs));
   return JFFT_OK;
 }
 
@@ -842,9 +884,16 @@ jfft_status pcg_iteration(jfft_cell_s *c, const PcgBufs<Real> &b, int j, History
   a.u = b.u;
   a.out = b.q;
   a.partial = c->partA;
+  // the Green path fuses the alpha step into the stiffness kernel (the
+  // diagonal preconditioners launch all three steps on their own)
+  const bool fuse = c->tun.fused_control && useG(c);
+  a.ctl = fuse ? c->st : nullptr;
+  a.h = h;
+  a.parity = (j + 1) & 1;
   TRY((launch_stiffness<Real, SM_CG>(c, a, c->B)));
   const long long nK = stencil_blocks_per_cell(c, sizeof(Real) == 8);
-  LAUNCH(c, KID_CTRL, k_cg_alpha<<<c->B, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nK, h, (j + 1) & 1, c->cs));
+  if (!fuse)
+    LAUNCH(c, KID_CTRL, k_cg_alpha<<<c->B, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nK, h, (j + 1) & 1, c->cs));
   long long nA, nB;
   return precond<Real>(c, b.r, b.q, b.Jh, b.z, b.spec, true, true, &nA, &nB, h);
 }
@@ -877,15 +926,13 @@ jfft_status fetch_states(jfft_cell_s *c) {
   return JFFT_OK;
 }
 
-// PCG loop on prepared buffers (u = start vector, r = f - K u) for every cell
-// of the group; returns when every cell's flag is set.
+// Start of the PCG loop on prepared buffers (u = start vector, r = f - K u)
+// for every cell of the group: state, z_0 = M^-1 r_0, ||r_0||^2 and r.z.
 // cont (mixed refinement sweeps after the first): continue the previous
 // sweep's CG with its rescaled search direction (k_cg_init_continue).
 template <typename Real>
-jfft_status run_pcg(jfft_cell_s *c, const PcgBufs<Real> &b, bool mixed, int maxit,
-                    bool record, bool cont = false) {
-  History h{nullptr, nullptr, nullptr};
-  if (record && c->hist_cap > 0) h = {c->hist[0], c->hist[1], c->hist[2]};
+jfft_status pcg_begin(jfft_cell_s *c, const PcgBufs<Real> &b, bool mixed, int maxit, History h,
+                      bool cont) {
   long long nA = 0, nB = 0;
   const double itol = c->mixed_continue ? c->update_tol : c->inner_tol;
   if (cont) {
@@ -893,58 +940,83 @@ jfft_status run_pcg(jfft_cell_s *c, const PcgBufs<Real> &b, bool mixed, int maxi
     const long long n = (long long)c->dim * c->g.N;
     LAUNCH(c, KID_VEC, k_scale_direction<Real><<<dim3(vec_blocks(n), c->B), 256, 0, c->stream>>>(b.p[0], b.p[1], n, c->st, c->cs));
   } else {
-    LAUNCH(c, KID_CTRL, k_cg_init<<<c->B, 1, 0, c->stream>>>(c->st, itol, mixed ? 1 : 0, maxit, record ? c->hist_cap : 0, c->inner_cap, c->cs));
+    LAUNCH(c, KID_CTRL, k_cg_init<<<c->B, 1, 0, c->stream>>>(c->st, itol, mixed ? 1 : 0, maxit, h.alpha ? c->hist_cap : 0, c->inner_cap, c->cs));
   }
   TRY(precond<Real>(c, b.r, nullptr, b.Jh, b.z, b.spec, false, false, &nA, &nB, h));
   if (cont)
     LAUNCH(c, KID_CTRL, k_cg_start_continue<<<c->B, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nA, c->partB, nB, c->cs));
   else
     LAUNCH(c, KID_CTRL, k_cg_start<<<c->B, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nA, c->partB, nB, c->cs));
+  return JFFT_OK;
+}
+
+// The captured chunk of G = tun.graph_iters iterations for this precision,
+// (re)built when missing or of another depth.  Its arguments never change
+// (the buffers of this handle are fixed) and the CG state lives in device
+// memory, so one capture serves every later loop.
+template <typename Real>
+jfft_status ensure_graph(jfft_cell_s *c, const PcgBufs<Real> &b, History h) {
   const int gk = sizeof(Real) == 8 ? 0 : 1;
   const int G = c->tun.graph_iters;
-  const bool graph = G > 0 && !c->timing;
-  if (graph && (!c->gexec[gk] || c->gexec_iters[gk] != G)) {
-    // capture G iterations once; their arguments never change (the buffers of
-    // this handle are fixed) and the CG state lives in device memory
-    if (c->gexec[gk]) {
-      (void)hipGraphExecDestroy(c->gexec[gk]);
-      c->gexec[gk] = nullptr;
-    }
-    hipGraph_t gr = nullptr;
-    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    c->capturing = true;
-    jfft_status s = JFFT_OK;
-    for (int j = 1; j <= G && s == JFFT_OK; ++j) s = pcg_iteration<Real>(c, b, j, h);
-    c->capturing = false;
-    hipError_t e = hipStreamEndCapture(c->stream, &gr);
-    if (s) return s;
-    if (e != hipSuccess) return fail(JFFT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&c->gexec[gk], gr, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(gr);
-    if (e != hipSuccess) return fail(JFFT_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
-    c->gexec_iters[gk] = G;
+  if (c->gexec[gk] && c->gexec_iters[gk] == G) return JFFT_OK;
+  if (c->gexec[gk]) {
+    (void)hipGraphExecDestroy(c->gexec[gk]);
+    c->gexec[gk] = nullptr;
   }
-  int it = 0;
+  hipGraph_t gr = nullptr;
+  HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  c->capturing = true;
+  jfft_status s = JFFT_OK;
+  for (int j = 1; j <= G && s == JFFT_OK; ++j) s = pcg_iteration<Real>(c, b, j, h);
+  c->capturing = false;
+  hipError_t e = hipStreamEndCapture(c->stream, &gr);
+  if (s) return s;
+  if (e != hipSuccess) return fail(JFFT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&c->gexec[gk], gr, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(gr);
+  if (e != hipSuccess) return fail(JFFT_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+  c->gexec_iters[gk] = G;
+  return JFFT_OK;
+}
+
+// At least `iters` PCG iterations of every running cell of the group: whole
+// replays of the captured chunk, or direct launches (an even count, so that
+// every chunk starts on the same search-direction buffer).
+template <typename Real>
+jfft_status pcg_iterations(jfft_cell_s *c, const PcgBufs<Real> &b, int iters, History h) {
+  const int G = c->tun.graph_iters;
+  if (G > 0 && !c->timing) {
+    TRY(ensure_graph<Real>(c, b, h));
+    const int reps = std::max(1, (iters + G / 2) / G);
+    for (int k = 0; k < reps; ++k) HIP_TRY(hipGraphLaunch(c->gexec[sizeof(Real) == 8 ? 0 : 1], c->stream));
+  } else {
+    const int n = iters + (iters & 1);
+    for (int j = 1; j <= n; ++j) TRY(pcg_iteration<Real>(c, b, j, h));
+  }
+  return JFFT_OK;
+}
+
+// the owed update u += alpha p_k of every cell after its loop stopped
+template <typename Real>
+jfft_status pcg_finish(jfft_cell_s *c, const PcgBufs<Real> &b) {
+  const long long n = (long long)c->dim * c->g.N;
+  LAUNCH(c, KID_VEC, k_finish_u<Real><<<dim3(vec_blocks(n), c->B), 256, 0, c->stream>>>(b.u, b.p[0], b.p[1], n, c->st, c->cs));
+  return JFFT_OK;
+}
+
+// PCG loop after pcg_begin for every cell of the group; returns when every
+// cell's flag is set, with the owed updates applied.
+template <typename Real>
+jfft_status pcg_loop(jfft_cell_s *c, const PcgBufs<Real> &b, History h) {
   int chunk = 2;
   for (;;) {
-    if (graph) {
-      const int reps = std::max(1, (chunk + G / 2) / G);
-      for (int k = 0; k < reps; ++k) HIP_TRY(hipGraphLaunch(c->gexec[gk], c->stream));
-    } else {
-      for (int k = 0; k < chunk; ++k) {
-        ++it;
-        TRY(pcg_iteration<Real>(c, b, it, h));
-      }
-    }
+    TRY(pcg_iterations<Real>(c, b, chunk, h));
     TRY(fetch_states(c));
     const int need = predict_remaining(c);
     if (need == 0) break;
     chunk = std::max(1, std::min(need, std::min(chunk * 2, 32)));
   }
-  // the owed update u += alpha p_k of every cell
-  const long long n = (long long)c->dim * c->g.N;
-  LAUNCH(c, KID_VEC, k_finish_u<Real><<<dim3(vec_blocks(n), c->B), 256, 0, c->stream>>>(b.u, b.p[0], b.p[1], n, c->st, c->cs));
-  return JFFT_OK;
+  return pcg_finish<Real>(c, b);
 }
 
 jfft_status reduce_to(jfft_cell_s *c, const double *part, long long n, int groups, int slot,
@@ -1047,9 +1119,13 @@ void tri_stencil(jfft_cell_s *c, double lam, double mu) {
 
 // E_dev holds the moduli of the cells one after another ([B][N]), or with
 // broadcast one field for every cell of the group.
+bool slots_busy(const jfft_cell_s *c);
+constexpr const char *kSlotsBusy = "the group's slots hold running or unharvested solves";
+
 jfft_status set_material_impl(jfft_cell_s *c, const double *E_dev, double lam, double mu,
                               bool broadcast = false) {
   if (!E_dev) return fail(JFFT_E_INVALID, "E_dev is NULL");
+  if (slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   if (!(mu > 0.0) || !(lam + 2.0 * mu / c->dim > 0.0) || !std::isfinite(lam) || !std::isfinite(mu))
     return fail(JFFT_E_INVALID, "Lame constants must satisfy mu > 0 and lambda + 2 mu / d > 0");
   TRY(ensure_ready(c));
@@ -1129,34 +1205,104 @@ jfft_status post_process(jfft_cell_s *c, double *u_out, double *sigma_dev, doubl
   return JFFT_OK;
 }
 
+PcgBufs<double> bufs64(jfft_cell_s *c) {
+  return {c->u, c->r, c->z, c->q, {c->p[0], c->p[1]}, c->E, c->Jh, c->spec};
+}
+PcgBufs<float> bufs32(jfft_cell_s *c) {
+  return {c->c32, c->r32, c->z32, c->q32, {c->p32[0], c->p32[1]}, c->E32, c->Jh32, c->spec32};
+}
+
+// Mixed refinement, first half of a sweep: the FP64 residual r = f - K u
+// (from_u; else u = 0 and r = f) and its stopping test (k_outer_check).
+jfft_status sweep_residual(jfft_cell_s *c, int maxit, bool from_u) {
+  const long long nd = (long long)c->dim * c->g.N;
+  const int nb = vec_blocks(nd);
+  if (from_u) {
+    TRY(apply_K<double>(c, c->E, c->u, c->q, c->B));
+    LAUNCH(c, KID_VEC, k_sub_norm<double><<<dim3(nb, c->B), 256, 0, c->stream>>>(c->f, c->q, c->r, nd, c->partA, c->cs));
+  } else {
+    LAUNCH(c, KID_VEC, k_sub_norm<double><<<dim3(nb, c->B), 256, 0, c->stream>>>(c->f, c->u, c->r, nd, c->partA, c->cs));
+  }
+  LAUNCH(c, KID_CTRL, k_outer_check<<<c->B, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nb, c->max_outer, maxit, c->cs));
+  return JFFT_OK;
+}
+
+// Second half: the FP32 inner solve for the correction c on r / ||r||
+// (c = 0), started (pcg_begin), or continued (cont).
+jfft_status sweep_start(jfft_cell_s *c, int maxit, bool cont) {
+  const long long nd = (long long)c->dim * c->g.N;
+  const int nb = vec_blocks(nd);
+  LAUNCH(c, KID_VEC, (k_convert<double, float><<<dim3(nb, c->B), 256, 0, c->stream>>>(c->r, c->r32, nd, 1.0, c->st, c->cs)));
+  LAUNCH(c, KID_VEC, k_fill<float><<<dim3(nb, c->B), 256, 0, c->stream>>>(c->c32, 0.0f, nd, c->cs));
+  return pcg_begin<float>(c, bufs32(c), true, maxit, History{nullptr, nullptr, nullptr}, cont);
+}
+
+// After the inner solve stopped (its owed update of c applied): count it,
+// u += ||r|| c.
+jfft_status sweep_end(jfft_cell_s *c) {
+  const long long nd = (long long)c->dim * c->g.N;
+  LAUNCH(c, KID_CTRL, k_outer_update<<<c->B, 1, 0, c->stream>>>(c->st, c->cs));
+  LAUNCH(c, KID_VEC, k_axpy_f32_to_f64<<<dim3(vec_blocks(nd), c->B), 256, 0, c->stream>>>(c->c32, c->u, nd, c->st, c->cs));
+  return JFFT_OK;
+}
+
 // Mixed precision: FP64 residual r = f - K u and iterate u, FP32 inner PCG
 // on r / ||r|| (FP64 dots and CG scalars), u += ||r|| c, until the FP64
 // residual meets the cell's stopping rule (state set by k_solve_norms).
 // have_u: u holds a start vector (else u = 0 and r = f).
 jfft_status mixed_refine(jfft_cell_s *c, int maxit, bool have_u) {
-  const long long nd = (long long)c->dim * c->g.N;
-  const int nb = vec_blocks(nd);
-  const int Bc = c->B;
   for (int sweep = 0;; ++sweep) {
-    if (sweep > 0 || have_u) {
-      TRY(apply_K<double>(c, c->E, c->u, c->q, Bc));
-      LAUNCH(c, KID_VEC, k_sub_norm<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->q, c->r, nd, c->partA, c->cs));
-    } else {
-      LAUNCH(c, KID_VEC, k_sub_norm<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->u, c->r, nd, c->partA, c->cs));
-    }
-    LAUNCH(c, KID_CTRL, k_outer_check<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, nb, c->max_outer, maxit, c->cs));
+    TRY(sweep_residual(c, maxit, sweep > 0 || have_u));
     TRY(fetch_states(c));
     bool all = true;
-    for (int i = 0; i < Bc; ++i) all = all && c->st_h[i].outer_done;
+    for (int i = 0; i < c->B; ++i) all = all && c->st_h[i].outer_done;
     if (all) break;
-    LAUNCH(c, KID_VEC, (k_convert<double, float><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->r, c->r32, nd, 1.0, c->st, c->cs)));
-    LAUNCH(c, KID_VEC, k_fill<float><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->c32, 0.0f, nd, c->cs));
-    PcgBufs<float> b{c->c32, c->r32, c->z32, c->q32, {c->p32[0], c->p32[1]}, c->E32, c->Jh32, c->spec32};
-    TRY(run_pcg<float>(c, b, true, maxit, false, sweep > 0 && c->mixed_continue));
-    LAUNCH(c, KID_CTRL, k_outer_update<<<Bc, 1, 0, c->stream>>>(c->st, c->cs));
-    LAUNCH(c, KID_VEC, k_axpy_f32_to_f64<<<dim3(nb, Bc), 256, 0, c->stream>>>(c->c32, c->u, nd, c->st, c->cs));
+    TRY(sweep_start(c, maxit, sweep > 0 && c->mixed_continue));
+    TRY(pcg_loop<float>(c, bufs32(c), History{nullptr, nullptr, nullptr}));
+    TRY(sweep_end(c));
   }
   return JFFT_OK;
+}
+
+// Right-hand side f = -B^T W C E_bar (|f| into q), the norms and the
+// homogeneous test, and the start vector u (u0, else zero), for every cell.
+jfft_status solve_setup(jfft_cell_s *c, const double *macros_h, double tol, const double *u0) {
+  const long long nd = (long long)c->dim * c->g.N;
+  const int Bc = c->B;
+  TRY(assemble_rhs(c, macros_h, c->f, c->q, Bc));
+  const int nb = vec_blocks(nd);
+  LAUNCH(c, KID_VEC, k_dot<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->f, nd, c->partA, c->cs));
+  LAUNCH(c, KID_VEC, k_dot<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->q, c->q, nd, c->partB, c->cs));
+  LAUNCH(c, KID_CTRL, k_solve_norms<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, c->partB, nb, tol, c->stop_abs ? 1 : 0, c->cs));
+  LAUNCH(c, KID_VEC, k_start_vector<<<dim3(nb, Bc), 256, 0, c->stream>>>(u0, (long long)sizeof(double) * nd, c->u, nd, c->st, c->cs));
+  return JFFT_OK;
+}
+
+// FP64 solve: r = f - K u (or f) and the start of the PCG loop.
+jfft_status fp64_start(jfft_cell_s *c, int maxit, bool have_u, History h) {
+  const long long nd = (long long)c->dim * c->g.N;
+  const int nb = vec_blocks(nd);
+  if (have_u) {
+    TRY(apply_K<double>(c, c->E, c->u, c->q, c->B));
+    LAUNCH(c, KID_VEC, k_sub_norm<double><<<dim3(nb, c->B), 256, 0, c->stream>>>(c->f, c->q, c->r, nd, c->partA, c->cs));
+  } else {
+    LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, c->B), 256, 0, c->stream>>>(c->f, c->cs, c->r, c->cs, nd));
+  }
+  return pcg_begin<double>(c, bufs64(c), false, maxit, h, false);
+}
+
+// Report of cell i from the fetched state and reduction results.
+jfft_report make_report(const jfft_cell_s *c, int i) {
+  const CgState &s = c->st_h[i];
+  const double fn = std::sqrt(s.fnorm2);
+  jfft_report R{};
+  R.iters = s.total_iters;
+  R.outer = s.outer;
+  R.status = s.final_status;
+  R.rel_res = (c->prec == JFFT_FP64) ? (fn > 0 && !s.homog ? std::sqrt(s.rr) / fn : 0.0)
+                                     : (fn > 0 && !s.homog ? s.rn / fn : 0.0);
+  R.rel_res_true = (fn > 0 && !s.homog) ? std::sqrt(c->small_h[(size_t)i * kSmall]) / fn : 0.0;
+  return R;
 }
 
 jfft_status solve_impl(jfft_cell_s *c, const double *macros_h, double tol, int maxit,
@@ -1165,30 +1311,18 @@ jfft_status solve_impl(jfft_cell_s *c, const double *macros_h, double tol, int m
   if (!c->has_material) return fail(JFFT_E_NO_MATERIAL, "set the material first");
   if (!macros_h || !sigma_bar) return fail(JFFT_E_INVALID, "NULL macro_strain or sigma_bar");
   if (!(tol > 0.0) || maxit < 0) return fail(JFFT_E_INVALID, "tol must be > 0 and maxit >= 0");
-  const long long N = c->g.N;
-  const int d = c->dim;
-  const long long nd = (long long)d * N;
+  if (slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   const int Bc = c->B;
   for (auto &e : c->phase_ev)
     if (!e) HIP_TRY(hipEventCreate(&e));
   HIP_TRY(hipEventRecord(c->phase_ev[0], c->stream));
-  // f, |f| (into q), norms and the homogeneous test, all on the device
-  TRY(assemble_rhs(c, macros_h, c->f, c->q, Bc));
-  const int nb = vec_blocks(nd);
-  LAUNCH(c, KID_VEC, k_dot<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->f, nd, c->partA, c->cs));
-  LAUNCH(c, KID_VEC, k_dot<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->q, c->q, nd, c->partB, c->cs));
-  LAUNCH(c, KID_CTRL, k_solve_norms<<<Bc, CTRL_THREADS, 0, c->stream>>>(c->st, c->partA, c->partB, nb, tol, c->stop_abs ? 1 : 0, c->cs));
-  LAUNCH(c, KID_VEC, k_start_vector<<<dim3(nb, Bc), 256, 0, c->stream>>>(u0, (long long)sizeof(double) * nd, c->u, nd, c->st, c->cs));
+  TRY(solve_setup(c, macros_h, tol, u0));
   HIP_TRY(hipEventRecord(c->phase_ev[1], c->stream));
   if (c->prec == JFFT_FP64) {
-    if (u0) {
-      TRY(apply_K<double>(c, c->E, c->u, c->q, Bc));
-      LAUNCH(c, KID_VEC, k_sub_norm<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->q, c->r, nd, c->partA, c->cs));
-    } else {
-      LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->f, c->cs, c->r, c->cs, nd));
-    }
-    PcgBufs<double> b{c->u, c->r, c->z, c->q, {c->p[0], c->p[1]}, c->E, c->Jh, c->spec};
-    TRY(run_pcg<double>(c, b, false, maxit, true));
+    History h{nullptr, nullptr, nullptr};
+    if (c->hist_cap > 0) h = {c->hist[0], c->hist[1], c->hist[2]};
+    TRY(fp64_start(c, maxit, u0 != nullptr, h));
+    TRY(pcg_loop<double>(c, bufs64(c), h));
     LAUNCH(c, KID_CTRL, k_fp64_final<<<Bc, 1, 0, c->stream>>>(c->st, c->cs));
   } else {
     TRY(mixed_refine(c, maxit, u0 != nullptr));
@@ -1202,25 +1336,193 @@ jfft_status solve_impl(jfft_cell_s *c, const double *macros_h, double tol, int m
   const double post_ms = elapsed_ms(c->phase_ev[2], c->phase_ev[3]);
   int worst = JFFT_OK;
   for (int i = 0; i < Bc; ++i) {
-    const CgState &s = c->st_h[i];
-    const double fn = std::sqrt(s.fnorm2);
-    jfft_report R{};
-    R.iters = s.total_iters;
-    R.outer = s.outer;
-    R.status = s.final_status;
-    R.rel_res = (c->prec == JFFT_FP64) ? (fn > 0 && !s.homog ? std::sqrt(s.rr) / fn : 0.0)
-                                       : (fn > 0 && !s.homog ? s.rn / fn : 0.0);
-    R.rel_res_true = (fn > 0 && !s.homog) ? std::sqrt(c->small_h[(size_t)i * kSmall]) / fn : 0.0;
+    jfft_report R = make_report(c, i);
     R.setup_ms = setup_ms;
     R.loop_ms = loop_ms;
     R.post_ms = post_ms;
     if (reps) reps[i] = R;
-    if (s.final_status != JFFT_OK && worst == JFFT_OK) worst = s.final_status;
-    if (s.final_status == JFFT_E_BREAKDOWN) worst = JFFT_E_BREAKDOWN;
+    if (R.status != JFFT_OK && worst == JFFT_OK) worst = R.status;
+    if (R.status == JFFT_E_BREAKDOWN) worst = JFFT_E_BREAKDOWN;
   }
   if (worst == JFFT_E_NOT_CONVERGED) g_last_error = "PCG reached maxit";
   if (worst == JFFT_E_BREAKDOWN) g_last_error = "PCG breakdown (p.q <= 0 or non-finite scalar)";
   return (jfft_status)worst;
+}
+
+// ------------------------------------------ continuous batching over slots
+// The cells of a group as slots that solves enter and leave between chunks
+// of PCG iterations (serving: a request admitted while others run joins the
+// next chunk).  Each cell has its own CG state, stopping flag and
+// fixed-order reductions, and every chunk starts on the same
+// search-direction buffer, so a cell computes the same iterates whatever
+// the other slots hold and whenever it was admitted: a slot's result is
+// bitwise that of the same cell solved alone with the same tile shapes.
+
+enum { SLOT_FREE = 0, SLOT_RUNNING = 1, SLOT_FINISHED = 2 };
+
+bool slots_busy(const jfft_cell_s *c) {
+  if (c->in_view) return false;
+  for (int s : c->slot_state)
+    if (s != SLOT_FREE) return true;
+  return false;
+}
+
+// The group's per-cell pointers moved to cell i, with B = 1, for the
+// lifetime of the view: the set-up, sweep and post-processing code then runs
+// on that slot alone.  The shared tables stay.
+class CellView {
+ public:
+  CellView(jfft_cell_s *c, int i)
+      : c_(c), off_((long long)i * c->cs), B_(c->B), st_h_(c->st_h), small_h_(c->small_h) {
+    shift(off_);
+    c->B = 1;
+    c->st_h += i;
+    c->small_h += (size_t)i * kSmall;
+    c->in_view = true;
+  }
+  ~CellView() {
+    shift(-off_);
+    c_->B = B_;
+    c_->st_h = st_h_;
+    c_->small_h = small_h_;
+    c_->in_view = false;
+  }
+  CellView(const CellView &) = delete;
+  CellView &operator=(const CellView &) = delete;
+
+ private:
+  template <typename T>
+  static void mv(T *&p, long long d) {
+    if (p) p = reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(p) + d);
+  }
+  void shift(long long d) {
+    jfft_cell_s *c = c_;
+    mv(c->E, d), mv(c->Jh, d), mv(c->diag, d), mv(c->f, d), mv(c->r, d), mv(c->z, d);
+    mv(c->q, d), mv(c->p[0], d), mv(c->p[1], d), mv(c->u, d), mv(c->spec, d);
+    mv(c->E32, d), mv(c->Jh32, d), mv(c->r32, d), mv(c->z32, d), mv(c->q32, d);
+    mv(c->p32[0], d), mv(c->p32[1], d), mv(c->c32, d), mv(c->spec32, d);
+    mv(c->F, d), mv(c->macro, d), mv(c->st, d), mv(c->partA, d), mv(c->partB, d);
+    mv(c->small, d);
+    for (auto &h : c->hist) mv(h, d);
+  }
+  jfft_cell_s *c_;
+  long long off_;
+  int B_;
+  CgState *st_h_;
+  double *small_h_;
+};
+
+jfft_status slots_init(jfft_cell_s *c) {
+  if (!c->slot_state.empty()) return JFFT_OK;
+  TRY(ensure_ready(c));
+  LAUNCH(c, KID_CTRL, k_slot_park<<<c->B, 1, 0, c->stream>>>(c->st, c->cs));
+  c->slot_state.assign(c->B, SLOT_FREE);
+  c->slot_maxit.assign(c->B, 0);
+  c->slot_sweep.assign(c->B, 0);
+  c->slot_t0.assign(c->B, {});
+  c->slot_ms.assign(c->B, 0.0);
+  return JFFT_OK;
+}
+
+jfft_status slot_admit(jfft_cell_s *c, int slot, const double *E_dev, double lam, double mu,
+                       const double *macro_h, double tol, int maxit) {
+  if (c->nl) return fail(JFFT_E_INVALID, "slots take the linear material only");
+  if (!macro_h) return fail(JFFT_E_INVALID, "NULL macro_strain");
+  if (!(tol > 0.0) || maxit < 0) return fail(JFFT_E_INVALID, "tol must be > 0 and maxit >= 0");
+  if (slot < 0 || slot >= c->B) return fail(JFFT_E_INVALID, "slot out of range");
+  TRY(slots_init(c));
+  if (c->slot_state[slot] != SLOT_FREE)
+    return fail(JFFT_E_INVALID, "slot " + std::to_string(slot) + " is not free (harvest it first)");
+  // captured iterations carry the Lame constants: one pair for all running slots
+  if ((c->lam != lam || c->mu != mu) && slots_busy(c))
+    return fail(JFFT_E_INVALID, "another slot runs with other elastic constants");
+  {
+    CellView v(c, slot);
+    TRY(set_material_impl(c, E_dev, lam, mu));
+    TRY(solve_setup(c, macro_h, tol, nullptr));
+    if (c->prec == JFFT_FP64) {
+      TRY(fp64_start(c, maxit, false, History{nullptr, nullptr, nullptr}));
+    } else {
+      TRY(sweep_residual(c, maxit, false));
+      TRY(fetch_states(c));
+      if (!c->st_h[0].outer_done) TRY(sweep_start(c, maxit, false));
+    }
+  }
+  c->slot_state[slot] = SLOT_RUNNING;
+  c->slot_maxit[slot] = maxit;
+  c->slot_sweep[slot] = 0;
+  c->slot_t0[slot] = std::chrono::steady_clock::now();
+  return JFFT_OK;
+}
+
+jfft_status slots_step(jfft_cell_s *c, int iters, int *states) {
+  if (iters < 1) return fail(JFFT_E_INVALID, "iterations must be >= 1");
+  TRY(slots_init(c));
+  bool any = false;
+  for (int s : c->slot_state) any = any || s == SLOT_RUNNING;
+  if (any) {
+    if (c->prec == JFFT_FP64)
+      TRY(pcg_iterations<double>(c, bufs64(c), iters, History{nullptr, nullptr, nullptr}));
+    else
+      TRY(pcg_iterations<float>(c, bufs32(c), iters, History{nullptr, nullptr, nullptr}));
+    TRY(fetch_states(c));
+    std::vector<int> ended;
+    for (int i = 0; i < c->B; ++i) {
+      if (c->slot_state[i] != SLOT_RUNNING || !c->st_h[i].done) continue;
+      CellView v(c, i);
+      if (c->prec == JFFT_FP64) {
+        TRY(pcg_finish<double>(c, bufs64(c)));
+        LAUNCH(c, KID_CTRL, k_fp64_final<<<1, 1, 0, c->stream>>>(c->st, c->cs));
+        ended.push_back(i);
+      } else if (c->st_h[0].outer_done) {
+        ended.push_back(i);  // stopped at admission (homogeneous, or f already small)
+      } else {
+        TRY(pcg_finish<float>(c, bufs32(c)));
+        TRY(sweep_end(c));
+        TRY(sweep_residual(c, c->slot_maxit[i], true));
+        ended.push_back(i);
+      }
+    }
+    if (!ended.empty()) {
+      TRY(fetch_states(c));
+      for (int i : ended) {
+        if (c->prec == JFFT_MIXED && !c->st_h[i].outer_done) {
+          CellView v(c, i);
+          TRY(sweep_start(c, c->slot_maxit[i], c->mixed_continue));
+          ++c->slot_sweep[i];
+          continue;
+        }
+        c->slot_state[i] = SLOT_FINISHED;
+        c->slot_ms[i] = std::chrono::duration<double, std::milli>(
+                            std::chrono::steady_clock::now() - c->slot_t0[i]).count();
+      }
+    }
+  }
+  if (states)
+    for (int i = 0; i < c->B; ++i) states[i] = c->slot_state[i];
+  return JFFT_OK;
+}
+
+jfft_status slot_harvest(jfft_cell_s *c, int slot, double *u_out, double *sigma_dev,
+                         double *sigma_bar, jfft_report *rep) {
+  if (slot < 0 || slot >= c->B) return fail(JFFT_E_INVALID, "slot out of range");
+  if (!sigma_bar) return fail(JFFT_E_INVALID, "NULL sigma_bar");
+  if (c->slot_state.empty() || c->slot_state[slot] != SLOT_FINISHED)
+    return fail(JFFT_E_INVALID, "slot " + std::to_string(slot) + " holds no finished solve");
+  jfft_report R{};
+  {
+    CellView v(c, slot);
+    TRY(post_process(c, u_out, sigma_dev, sigma_bar));
+    TRY(fetch_states(c));
+    R = make_report(c, 0);
+    LAUNCH(c, KID_CTRL, k_slot_park<<<1, 1, 0, c->stream>>>(c->st, c->cs));
+  }
+  R.loop_ms = c->slot_ms[slot];
+  if (rep) *rep = R;
+  c->slot_state[slot] = SLOT_FREE;
+  if (R.status == JFFT_E_NOT_CONVERGED) g_last_error = "PCG reached maxit";
+  if (R.status == JFFT_E_BREAKDOWN) g_last_error = "PCG breakdown (p.q <= 0 or non-finite scalar)";
+  return (jfft_status)R.status;
 }
 
 // ------------------------------------------------- power-law Newton solve
@@ -1234,6 +1536,7 @@ jfft_status set_material_powerlaw_impl(jfft_cell_s *c, const double *phase_dev, 
                                        double sigma0, double eps0, double n, double K_incl,
                                        double mu_incl) {
   if (!phase_dev) return fail(JFFT_E_INVALID, "phase_dev is NULL");
+  if (slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   if (c->dim != 3 || c->B != 1)
     return fail(JFFT_E_INVALID, "the power-law material needs a single 3D cell");
   const double prm[6] = {K, sigma0, eps0, n, K_incl, mu_incl};
@@ -1372,7 +1675,8 @@ jfft_status newton_impl(jfft_cell_s *c, const double *macro_h, double newton_tol
       TRY(mixed_refine(c, maxit, false));
     } else {
       LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, 1), 256, 0, c->stream>>>(c->f, 0, c->r, 0, nd));
-      TRY(run_pcg<double>(c, b, false, maxit, false));
+      TRY(pcg_begin<double>(c, b, false, maxit, History{nullptr, nullptr, nullptr}, false));
+      TRY(pcg_loop<double>(c, b, History{nullptr, nullptr, nullptr}));
       LAUNCH(c, KID_CTRL, k_fp64_final<<<1, 1, 0, c->stream>>>(c->st, c->cs));
     }
     LAUNCH(c, KID_VEC, k_add<double><<<nb, 256, 0, c->stream>>>(c->u, c->uk, nd));
@@ -1419,6 +1723,7 @@ jfft_status nl_operator_prep(jfft_cell_s *c, const double *macro_h, const double
 jfft_status topo_check(jfft_cell_s *c) {
   if (c->dim != 2 || c->B != 3 || c->elem != JFFT_ELEM_TRI)
     return fail(JFFT_E_INVALID, "topology optimisation needs a group of 3 2D triangle cells");
+  if (slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   return JFFT_OK;
 }
 
@@ -1833,10 +2138,31 @@ jfft_status jfft_solve_batch(jfft_cell_t c, const double *macro_strains, double 
   return solve_impl(c, macro_strains, tol, maxit, u0_dev, u_dev, sigma_dev, sigma_bars, reports);
 }
 
+jfft_status jfft_slot_admit(jfft_cell_t c, int slot, const double *E_dev, double nu,
+                            const double *macro_strain, double tol, int maxit) {
+  if (!c) return fail(JFFT_E_INVALID, "NULL cell");
+  if (!(nu > -1.0 && nu < 0.5)) return fail(JFFT_E_INVALID, "nu must lie in (-1, 0.5)");
+  const double lam = nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+  const double mu = 1.0 / (2.0 * (1.0 + nu));
+  return slot_admit(c, slot, E_dev, lam, mu, macro_strain, tol, maxit);
+}
+
+jfft_status jfft_slots_step(jfft_cell_t c, int iterations, int *states) {
+  if (!c) return fail(JFFT_E_INVALID, "NULL cell");
+  return slots_step(c, iterations, states);
+}
+
+jfft_status jfft_slot_harvest(jfft_cell_t c, int slot, double *u_dev, double *sigma_dev,
+                              double *sigma_bar, jfft_report *report) {
+  if (!c) return fail(JFFT_E_INVALID, "NULL cell");
+  return slot_harvest(c, slot, u_dev, sigma_dev, sigma_bar, report);
+}
+
 jfft_status jfft_apply_stiffness(jfft_cell_t c, const double *in_dev, double *out_dev) {
   if (!c || !in_dev || !out_dev) return fail(JFFT_E_INVALID, "NULL argument");
   if (!c->has_material) return fail(JFFT_E_NO_MATERIAL, "set the material first");
   if (c->B != 1) return fail(JFFT_E_INVALID, "operator entry points take a single-cell handle");
+  if (slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   return apply_K<double>(c, c->E, in_dev, out_dev, 1);
 }
 
@@ -1844,6 +2170,7 @@ jfft_status jfft_apply_precond(jfft_cell_t c, const double *in_dev, double *out_
   if (!c || !in_dev || !out_dev) return fail(JFFT_E_INVALID, "NULL argument");
   if (!c->has_material) return fail(JFFT_E_NO_MATERIAL, "set the material first");
   if (c->B != 1) return fail(JFFT_E_INVALID, "operator entry points take a single-cell handle");
+  if (slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   const long long nd = (long long)c->dim * c->g.N;
   LAUNCH(c, KID_VEC, k_copy<double><<<dim3(vec_blocks(nd), 1), 256, 0, c->stream>>>(in_dev, 0, c->r, 0, nd));
   long long nA, nB;
@@ -1857,6 +2184,7 @@ jfft_status jfft_apply_precond_fp32(jfft_cell_t c, const double *in_dev, double 
   if (!c || !in_dev || !out_dev) return fail(JFFT_E_INVALID, "NULL argument");
   if (!c->has_material) return fail(JFFT_E_NO_MATERIAL, "set the material first");
   if (c->B != 1) return fail(JFFT_E_INVALID, "operator entry points take a single-cell handle");
+  if (slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   if (c->prec != JFFT_MIXED) return fail(JFFT_E_INVALID, "the FP32 preconditioner belongs to a mixed-precision cell");
   const long long nd = (long long)c->dim * c->g.N;
   LAUNCH(c, KID_VEC, (k_convert<double, float><<<dim3(vec_blocks(nd), 1), 256, 0, c->stream>>>(in_dev, c->r32, nd, 1.0, nullptr, 0)));
@@ -1871,6 +2199,7 @@ jfft_status jfft_assemble_rhs(jfft_cell_t c, const double *macro_strain, double 
   if (!c || !macro_strain || !f_dev) return fail(JFFT_E_INVALID, "NULL argument");
   if (!c->has_material) return fail(JFFT_E_NO_MATERIAL, "set the material first");
   if (c->B != 1) return fail(JFFT_E_INVALID, "operator entry points take a single-cell handle");
+  if (slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   TRY(assemble_rhs(c, macro_strain, f_dev, nullptr, 1));
   HIP_TRY(hipStreamSynchronize(c->stream));  // macro_strain is a host pointer
   return JFFT_OK;
@@ -1880,6 +2209,7 @@ jfft_status jfft_jacobi_diag(jfft_cell_t c, double *diag_dev) {
   if (!c || !diag_dev) return fail(JFFT_E_INVALID, "NULL argument");
   if (!c->has_material) return fail(JFFT_E_NO_MATERIAL, "set the material first");
   if (c->B != 1) return fail(JFFT_E_INVALID, "operator entry points take a single-cell handle");
+  if (slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   return run_alg2(c, diag_dev, 1);
 }
 
@@ -1936,7 +2266,13 @@ jfft_status jfft_set_tunables(jfft_cell_t c, const jfft_tunables *t) {
     if (tiles * nbz > c->npart) return fail(JFFT_E_INVALID, "tz too small for the partial-sum buffer");
     c->tun.tz = t->tz;
   }
+  if (t->tiles2d < 0 || t->tiles2d > 2) return fail(JFFT_E_INVALID, "tiles2d must be 0, 1 or 2");
+  if (t->xrows < 0 || (t->xrows & (t->xrows - 1)) != 0)
+    return fail(JFFT_E_INVALID, "xrows must be 0 or a power of two");
   c->tun.ygrid = t->ygrid;
+  c->tun.tiles2d = c->dim == 2 ? t->tiles2d : 0;
+  c->tun.xrows = t->xrows;
+  c->tun.fused_control = t->fused_control ? 1 : 0;
   c->drop_graphs();
   return JFFT_OK;
 }
@@ -1945,6 +2281,11 @@ jfft_status jfft_get_tunables(jfft_cell_t c, jfft_tunables *t) {
   if (!c || !t) return fail(JFFT_E_INVALID, "NULL argument");
   t->tz = c->dim == 3 ? std::min(c->tun.tz, c->g.nz) : 1;
   t->ygrid = c->tun.ygrid;
+  t->tiles2d = c->dim == 2 ? tiles2d_of(c, c->prec == JFFT_FP64) : 0;
+  const int rb = c->prec == JFFT_FP64 ? x_rows_per_block<double>(c->g.nx / 2)
+                                      : x_rows_per_block<float>(c->g.nx / 2);
+  t->xrows = c->tun.xrows && c->tun.xrows < rb ? c->tun.xrows : rb;
+  t->fused_control = c->tun.fused_control;
   return JFFT_OK;
 }
 

@@ -64,8 +64,22 @@ __device__ __forceinline__ T *cshift(T *p, int cell, long long cs) {
   return reinterpret_cast<T *>(reinterpret_cast<Byte *>(p) + off);
 }
 
+enum StatusCode { ST_OK = 0, ST_NOT_CONVERGED = 4, ST_BREAKDOWN = 5 };
+
+// Per-iteration CG history (alpha_k, beta_k, ||r_k||) of a cell, or NULLs.
+struct History {
+  double *alpha, *beta, *res;
+};
+
+__device__ __forceinline__ void shift_hist(History &h, int cell, long long cs) {
+  h.alpha = cshift(h.alpha, cell, cs);
+  h.beta = cshift(h.beta, cell, cs);
+  h.res = cshift(h.res, cell, cs);
+}
+
 // CG scalars kept on the device so that the whole loop runs without host
-// round trips; written only by the single-block control kernels.
+// round trips; written by the single-block control kernels and by the last
+// block of a kernel that runs a fused control step.
 struct CgState {
   double rz;        // r_k . z_k
   double pq;        // p_k . K p_k
@@ -93,7 +107,7 @@ struct CgState {
   int outer;        // refinement sweeps taken
   int total_iters;  // inner iterations over all sweeps
   int final_status; // jfft_status of the whole solve
-  int pad2[3];
+  int arrive[3];    // arrival counters of the fused control steps (alpha, ||r||^2, beta); 0 between launches
 };
 
 // Fourier tables of one axis for the Green symbol of K_ref (Q1 elements,

@@ -119,6 +119,9 @@ struct StencilArgs {
   Real *out;             // q = K p (APPLY / CG)
   double *partial;       // CG: per-block partial of p_new . q
   const CgState *st;     // CG: scalars
+  CgState *ctl;          // CG: the same state when the alpha step is fused (else NULL)
+  History h;             // CG: history arrays of the fused step
+  int parity;            // CG: buffer parity of p_new (fused alpha step)
   Real *diag;            // COMB: diag(K) output
   int comb_comp, comb_off;  // COMB: component and sub-grid offset bits (x, y, z)
   int tz;                // z planes per block (3D)
@@ -161,6 +164,7 @@ __device__ __forceinline__ void shift_args(StencilArgs<Real> &a, int cell) {
   a.out = cshift(a.out, cell, a.cs);
   a.partial = cshift(a.partial, cell, a.cs);
   a.st = cshift(a.st, cell, a.cs);
+  a.ctl = cshift(a.ctl, cell, a.cs);
   a.diag = cshift(a.diag, cell, a.cs);
 }
 
@@ -805,6 +809,107 @@ __device__ __forceinline__ double block_sum(double v, double *sm) {
   return r;
 }
 
+// ------------------------------------------------------ CG control steps
+// The scalar steps of a PCG iteration (Sec. 3.3): alpha after p.q, the
+// update count and stopping test after ||r||^2, beta after r.z.  Run by
+// thread 0 of a single-block control kernel (cg.h), or fused into the
+// kernel that produces the step's partial sums: every block of a cell
+// writes its partial, makes it visible (device-scope fence) and counts its
+// arrival on the cell's counter; the block that arrives last (fence again)
+// sums the partials in a fixed order, runs the step and resets the counter.
+// Which block is last does not change the result.
+
+// alpha_k = (r.z) / (p.q); breakdown if p.q <= 0 or alpha not finite.
+// parity: which of the two search-direction buffers holds p_k.
+__device__ __forceinline__ void cg_alpha_step(CgState *st, double pq, const History &h, int parity) {
+  st->pq = pq;
+  st->parity = parity;
+  const double alpha = st->rz / pq;
+  if (!(pq > 0.0) || !isfinite(alpha)) {
+    st->done = 1;
+    st->status = ST_BREAKDOWN;
+    st->pending = 0;
+  } else {
+    st->alpha = alpha;
+    st->pending = 1;
+    if (h.alpha && st->iter < st->hist_cap) h.alpha[st->iter] = alpha;
+  }
+}
+
+// ||r_{k+1}||^2; count the update of u; stop on tolerance or maxit.
+__device__ __forceinline__ void cg_rr_step(CgState *st, double rr, const History &h) {
+  st->rr = rr;
+  st->iter += 1;
+  if (h.res && st->iter - 1 < st->hist_cap) h.res[st->iter - 1] = sqrt(rr);
+  if (rr <= st->tol2) {
+    st->done = 1;
+    st->status = ST_OK;
+  } else if (st->iter >= st->maxit) {
+    st->done = 1;
+    st->status = ST_NOT_CONVERGED;
+  }
+  // the last iteration forms no beta: its history entry is NaN
+  if (st->done && h.beta && st->iter - 1 < st->hist_cap) h.beta[st->iter - 1] = __builtin_nan("");
+}
+
+// beta_k = (r.z)_new / (r.z)_old.
+__device__ __forceinline__ void cg_beta_step(CgState *st, double rz, const History &h) {
+  const double beta = rz / st->rz;
+  if (!isfinite(beta)) {
+    st->done = 1;
+    st->status = ST_BREAKDOWN;
+  } else {
+    st->beta = beta;
+    st->rz = rz;
+    st->first = 0;
+    if (h.beta && st->iter - 1 < st->hist_cap) h.beta[st->iter - 1] = beta;
+  }
+}
+
+// Fixed-order sum of n partials by the NT threads of a block (thread 0
+// gets the result).
+template <int NT>
+__device__ __forceinline__ double block_fixed_sum(const double *p, long long n, double *sm) {
+  double v = 0.0;
+  long long i = threadIdx.x;
+  for (; i + 7LL * NT < n; i += 8LL * NT) {
+    double t[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t[k] = p[i + (long long)k * NT];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v += t[k];
+  }
+  for (; i < n; i += NT) v += p[i];
+  return block_sum<NT>(v, sm);
+}
+
+enum CtrlStep { CTRL_ALPHA = 0, CTRL_RR = 1, CTRL_BETA = 2 };
+
+// Called by every thread of every block of the cell after thread 0 stored
+// the block's partial: the last block to arrive sums the `total` partials
+// and runs the step.
+template <int NT, int STEP>
+__device__ __forceinline__ void fused_ctrl(CgState *st, const double *part, int total,
+                                           History h, int cell, long long cs, int parity,
+                                           double *sm) {
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    __threadfence();  // this block's partial before its arrival
+    last = atomicAdd(&st->arrive[STEP], 1) == total - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();  // every other block's partial before the sum
+  const double v = block_fixed_sum<NT>(part, total, sm);
+  if (threadIdx.x == 0) {
+    shift_hist(h, cell, cs);
+    if (STEP == CTRL_ALPHA) cg_alpha_step(st, v, h, parity);
+    if (STEP == CTRL_RR) cg_rr_step(st, v, h);
+    if (STEP == CTRL_BETA) cg_beta_step(st, v, h);
+    st->arrive[STEP] = 0;
+  }
+}
+
 // Software-pipelined layer march: while the elements of layer ez are
 // evaluated from node planes ez and ez + 1 (LDS), the global loads of plane
 // ez + 2 and of the next element moduli are in flight in registers; they are
@@ -1112,6 +1217,9 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, (stencil3_waves_per_simd<Rea
   if (MODE == SM_CG) {
     const double s = block_sum<STENCIL3_THREADS>(acc, red);
     if (tid == 0) a.partial[lb] = s;
+    if (a.ctl)
+      fused_ctrl<STENCIL3_THREADS, CTRL_ALPHA>(a.ctl, a.partial, per_cell, a.h, cell, a.cs,
+                                               a.parity, red);
   }
 }
 
@@ -1211,10 +1319,10 @@ __device__ __forceinline__ void elem_tri2(const Real (&u)[2][4], Real Elam, Real
 // valid addresses and are masked where the value is committed.
 // TRI: the pixel is two linear triangles (elem_tri2) instead of a bilinear
 // quadrilateral.
-template <typename Real, int MODE, bool TRI = false>
+template <typename Real, int MODE, bool TRI = false, int TT = ty2<Real>() / TILE>
 __global__ void __launch_bounds__(STENCIL_THREADS)
     k_stiffness2d(StencilArgs<Real> a) {
-  constexpr int TY2 = ty2<Real>();
+  constexpr int TY2 = TT * TILE;  // TT tiles of 16 x 16 per block (a tunable tile shape)
   constexpr int NNODE2 = NTILE * (TY2 + 2);  // nodes with halo
   constexpr int NELEM2 = ETILE * (TY2 + 1);  // elements with halo
   constexpr int NOUT2 = TILE * TY2;          // outputs
@@ -1373,6 +1481,9 @@ __global__ void __launch_bounds__(STENCIL_THREADS)
   if (MODE == SM_CG) {
     const double s = block_sum<STENCIL_THREADS>(acc, red);
     if (tid == 0) a.partial[lb] = s;
+    if (a.ctl)
+      fused_ctrl<STENCIL_THREADS, CTRL_ALPHA>(a.ctl, a.partial, per_cell, a.h, cell, a.cs,
+                                              a.parity, red);
   }
 }
 

@@ -25,6 +25,15 @@ Each cell's results are bitwise independent of what else is in its group or
 on the device (reduction layouts depend on the cell shape only), so a request
 gets the same C_eff alone and in the mix.  Only marshalling and scheduling
 happen here: every step of a solve runs in the library's kernels.
+
+SlotServer batches below handle granularity: one group handle per grid
+shape whose cells are slots (jfft_slot_admit / jfft_slots_step /
+jfft_slot_harvest).  A driver thread per active shape admits arrived
+requests of its shape into free slots (six per request) between chunks of
+PCG iterations, runs a chunk for every running slot, and harvests the load
+cases that stopped; a request is done when its six slots are.  A request
+thus joins the running group at the next chunk boundary instead of waiting
+for the group to drain, and leaves as soon as its own solves stop.
 """
 from __future__ import annotations
 
@@ -259,6 +268,150 @@ class Server:
             "mean_latency_ms": float(lat.mean() * 1e3),
             "offered_rate": rate,
             "mean_merged": float(np.mean([r.merged for r in requests])),
+            "handles_created": self.pool.created,
+            "handles_evicted": self.pool.evicted,
+            "all_ok": all(r.status == "ok" for r in requests),
+            "max_rel_res_true": float(max(r.rel_res_true for r in requests)),
+        }
+
+    def close(self):
+        self.pool.close()
+
+
+class SlotServer:
+    """Continuous batching over the slots of one group handle per grid shape.
+
+    slots_per_group: requests a group holds at once (6 slots each), or a
+    function of the grid shape that returns it; the group's device bytes
+    count against budget_bytes like any handle, and a shape waits for memory
+    like a worker does in Server.  chunk: PCG
+    iterations between admission and harvest points (the captured graph
+    depth when graph_iterations > 0)."""
+
+    def __init__(self, budget_bytes=64 << 30, precision=MIXED, pc=PC_GREEN_JACOBI, tol=1e-8,
+                 maxit=20000, graph_iterations=8, nu=0.3, slots_per_group=4, chunk=None,
+                 autotune=False):
+        self.tol, self.maxit, self.nu = tol, maxit, nu
+        self.slots_per_group = slots_per_group
+        self.chunk = chunk or max(2, graph_iterations)
+        self.pool = HandlePool(budget_bytes, precision, pc, graph_iterations, nu, autotune)
+        self.precision = precision
+
+    def run(self, requests, rate=None, seed=0):
+        """Serve `requests` (rate as in Server.run).  Returns a summary dict."""
+        rng = np.random.default_rng(seed)
+        t = 0.0
+        for r in requests:
+            if rate:
+                t += rng.exponential(1.0 / rate)
+            r.arrival = t
+        arrivals = sorted(requests, key=lambda r: r.arrival)
+        queues = {}          # shape -> [Request] arrived, not yet admitted
+        drivers = {}         # shape -> Thread
+        lock = threading.Lock()
+        errors = []
+        chunks = {"n": 0, "slots": 0}
+        t0 = time.perf_counter()
+        spg = self.slots_per_group
+
+        def drive(shape):
+            torch = _torch()
+            k = int(spg(shape)) if callable(spg) else int(spg)
+            cell = self.pool.acquire((shape, k))
+            owner = [None] * (6 * k)    # slot -> (request, load case)
+            left = {}                   # rid -> solves not yet harvested
+            eye = np.eye(6)
+            try:
+                with torch.cuda.stream(cell.stream):
+                    while True:
+                        with lock:
+                            q = queues[shape]
+                            free = [s for s in range(6 * k) if owner[s] is None]
+                            take = []
+                            while q and len(free) >= 6 * (len(take) + 1):
+                                take.append(q.pop(0))
+                            if not take and all(o is None for o in owner):
+                                # back to the pool before a new driver of this
+                                # shape can look for a handle
+                                self.pool.release(cell)
+                                cell = None
+                                del drivers[shape]
+                                return
+                        now = time.perf_counter() - t0
+                        for r in take:
+                            r.start = now
+                            r.C = np.zeros((6, 6))
+                            r.iters = [0] * 6
+                            r._st = [""] * 6
+                            r._res = [0.0] * 6
+                            left[r.rid] = 6
+                            E = torch.from_numpy(r.E).to(cell.device)
+                            for g in range(6):
+                                s = free.pop(0)
+                                cell.slot_admit(s, E, self.nu, eye[g], tol=self.tol,
+                                                maxit=self.maxit)
+                                owner[s] = (r, g)
+                        states = cell.slots_step(self.chunk)
+                        with lock:
+                            chunks["n"] += 1
+                            chunks["slots"] += sum(o is not None for o in owner)
+                        for s in np.nonzero(states == cell.SLOT_FINISHED)[0]:
+                            r, g = owner[s]
+                            _, sbar, rep, _ = cell.slot_harvest(int(s), want_u=False)
+                            owner[s] = None
+                            r.C[:, g] = sbar
+                            r.iters[g] = rep.iters
+                            r._st[g] = rep.status
+                            r._res[g] = rep.rel_res_true
+                            left[r.rid] -= 1
+                            if left[r.rid] == 0:
+                                r.done = time.perf_counter() - t0
+                                r.rel_res_true = max(r._res)
+                                r.status = ("ok" if all(x == "ok" for x in r._st)
+                                            else ",".join(sorted(set(r._st))))
+                                r.merged = 1
+            except Exception as e:  # reported by run()
+                errors.append(e)
+                with lock:
+                    drivers.pop(shape, None)
+            finally:
+                if cell is not None:
+                    self.pool.release(cell)
+
+        i = 0
+        while i < len(arrivals) or drivers:
+            if errors:
+                break
+            now = time.perf_counter() - t0
+            with lock:
+                while i < len(arrivals) and arrivals[i].arrival <= now:
+                    r = arrivals[i]
+                    queues.setdefault(r.E.shape, []).append(r)
+                    i += 1
+                for shape, q in queues.items():
+                    if q and shape not in drivers:
+                        th = threading.Thread(target=drive, args=(shape,))
+                        drivers[shape] = th
+                        th.start()
+            time.sleep(0.0005)
+        for th in list(drivers.values()):
+            th.join()
+        makespan = time.perf_counter() - t0
+        if errors:
+            raise errors[0]
+        lat = np.array([r.latency for r in requests])
+        return {
+            "requests": len(requests),
+            "makespan_s": makespan,
+            "requests_per_s": len(requests) / makespan,
+            "solves_per_s": 6 * len(requests) / makespan,
+            "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+            "p95_latency_ms": float(np.percentile(lat, 95) * 1e3),
+            "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_latency_ms": float(lat.mean() * 1e3),
+            "offered_rate": rate,
+            "chunks": chunks["n"],
+            "mean_busy_slots_per_chunk": chunks["slots"] / max(1, chunks["n"]),
             "handles_created": self.pool.created,
             "handles_evicted": self.pool.evicted,
             "all_ok": all(r.status == "ok" for r in requests),

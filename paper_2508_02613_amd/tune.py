@@ -3,19 +3,23 @@
 Tuned by timing a fixed number of PCG iterations on a synthetic smooth
 material of the target shape:
 
-* tz, the z planes per block of the 3D stiffness kernel: it sets how the p.q
-  partial sums are grouped, so it is chosen per (grid shape, precision,
-  preconditioner) only, never per group size; a cell then gives bitwise the
-  same results alone and in any group, tuned or not, as long as the same
-  cache is used;
+* the tile shapes: tz, the z planes per block of the 3D stiffness kernel,
+  tiles2d, the 16 x 16 tiles per block of the 2D one, and xrows, the grid
+  rows per block of the x FFT passes; and fused_control, whether the CG
+  scalar steps run in the last block of their producer kernels.  They set
+  how the p.q, ||r||^2 and r.z partial sums are grouped, so they are chosen
+  per (grid shape, precision, preconditioner) only, never per group size; a
+  cell then gives bitwise the same results alone and in any group, tuned or
+  not, as long as the same cache is used;
 * ygrid, the persistent blocks of the y FFT pass, and the number of PCG
   iterations captured per HIP graph: these do not change what is computed and
   are chosen per group size as well.
 
 Results are kept in a JSON cache (JFFT_TUNE_CACHE, default
 ~/.cache/jfft_mi355x/tunables.json) so each configuration is measured once.
-The search is coordinate-wise (tz, then ygrid, then graph depth), each step
-keeping the best loop time.  Only marshalling happens here: the timed work
+The search is coordinate-wise (tz or tiles2d, xrows, fused control, then
+ygrid, then graph depth), each step keeping the best loop time; the shape-level choice is
+measured on the first group size tuned and reused for the others.  Only marshalling happens here: the timed work
 runs in the library's kernels.
 """
 from __future__ import annotations
@@ -29,6 +33,9 @@ import numpy as np
 from . import MIXED, PC_GREEN_JACOBI, Cell, _torch
 
 _lock = threading.Lock()
+
+# launch parameters that regroup partial sums: chosen per grid shape only
+SHAPE_KEYS = ("tz", "tiles2d", "xrows", "fused_control")
 
 
 def cache_path() -> str:
@@ -79,7 +86,8 @@ def _time_loop(cell, iters, macro):
 
 def autotune(shape, batch=1, precision=MIXED, pc=PC_GREEN_JACOBI, iters=24, use_cache=True):
     """Launch parameters for a group of `batch` cells of `shape`: returns
-    {"tz", "ygrid", "graph_iterations", "loop_ms_per_iteration"}."""
+    {"tz", "tiles2d", "xrows", "ygrid", "graph_iterations",
+    "loop_ms_per_iteration"}."""
     shape = tuple(int(s) for s in shape)
     skey = _shape_key(shape, precision, pc)
     gkey = f"{skey}|b{int(batch)}"
@@ -98,41 +106,51 @@ def autotune(shape, batch=1, precision=MIXED, pc=PC_GREEN_JACOBI, iters=24, use_
         cur = cell.tunables()
         best = None
 
-        def trial(tz, ygrid, graph):
+        def trial(tiles, ygrid, graph):
             nonlocal best
-            cell.set_tunables(tz=tz, ygrid=ygrid)
+            cell.set_tunables(ygrid=ygrid, **tiles)
             cell.set_graph_iterations(graph)
             ms = _time_loop(cell, iters, macro) / iters
             if best is None or ms < best[0]:
-                best = (ms, tz, ygrid, graph)
+                best = (ms, dict(tiles), ygrid, graph)
             return ms
 
-        # tz: fixed per shape (shared by every group size), measured once
-        shape_tz = data.get("shapes", {}).get(skey) if use_cache else None
-        if dim == 3 and shape_tz is None:
-            nz = shape[0]
-            tzs = sorted({t for t in (4, 8, 16, 32, 64) if t <= nz} | {min(cur["tz"], nz)})
-            for tz in tzs:
-                trial(tz, cur["ygrid"], 0)
-            shape_tz = best[1]
-        elif shape_tz is None:
-            shape_tz = cur["tz"]
+        # tile shapes: fixed per shape (shared by every group size), measured once
+        tiles = data.get("shapes", {}).get(skey) if use_cache else None
+        if not isinstance(tiles, dict):
+            tiles = {"tz": cur["tz"], "tiles2d": cur["tiles2d"], "xrows": cur["xrows"],
+                     "fused_control": cur["fused_control"]}
+            if dim == 3:
+                nz = shape[0]
+                for tz in sorted({t for t in (4, 8, 16, 32, 64) if t <= nz} | {cur["tz"]}):
+                    trial(dict(tiles, tz=tz), cur["ygrid"], 0)
+            else:
+                for t2 in (1, 2):
+                    trial(dict(tiles, tiles2d=t2), cur["ygrid"], 0)
+            tiles = dict(best[1])
+            xr = cur["xrows"]
+            while xr >= 2 and xr >= cur["xrows"] // 8:
+                xr //= 2
+                trial(dict(tiles, xrows=xr), cur["ygrid"], 0)
+            tiles = dict(best[1])
+            trial(dict(tiles, fused_control=1 - tiles["fused_control"]), cur["ygrid"], 0)
+            tiles = dict(best[1])
         best = None
         if dim == 3:
             for yg in sorted({256, 512, 1024, 2048, 4096, cur["ygrid"]}):
-                trial(shape_tz, yg, 0)
+                trial(tiles, yg, 0)
         else:  # no y pass in 2D (the Green pass runs along y)
-            trial(shape_tz, cur["ygrid"], 0)
+            trial(tiles, cur["ygrid"], 0)
         yg = best[2]
         for graph in (8, 16):
-            trial(shape_tz, yg, graph)
-        res = {"tz": int(shape_tz), "ygrid": int(best[2]), "graph_iterations": int(best[3]),
-               "loop_ms_per_iteration": float(best[0])}
+            trial(tiles, yg, graph)
+        res = dict(tiles, ygrid=int(best[2]), graph_iterations=int(best[3]),
+                   loop_ms_per_iteration=float(best[0]))
     finally:
         cell.close()
     with _lock:
         data = _load() if use_cache else {}
-        data.setdefault("shapes", {})[skey] = res["tz"]
+        data.setdefault("shapes", {})[skey] = {k: int(res[k]) for k in SHAPE_KEYS}
         data.setdefault("groups", {})[gkey] = res
         if use_cache:
             _store(data)
@@ -141,5 +159,7 @@ def autotune(shape, batch=1, precision=MIXED, pc=PC_GREEN_JACOBI, iters=24, use_
 
 def apply(cell, params):
     """Apply autotune() results to a cell group."""
-    cell.set_tunables(tz=params["tz"], ygrid=params["ygrid"])
+    cell.set_tunables(tz=params["tz"], ygrid=params["ygrid"], tiles2d=params.get("tiles2d", 0),
+                      xrows=params.get("xrows", 0),
+                      fused_control=params.get("fused_control", 0))
     cell.set_graph_iterations(params["graph_iterations"])

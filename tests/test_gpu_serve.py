@@ -76,3 +76,31 @@ def test_poisson_arrivals_complete_in_order_of_capacity():
     assert stats["p99_latency_ms"] >= stats["p50_latency_ms"] > 0
     arr = sorted(r.arrival for r in reqs)
     assert arr[-1] > 0.05  # arrivals are spread in time
+
+
+@pytest.mark.parametrize("precision,budget_groups", [(0, 100), (1, 100), (1, 1.2)])
+def test_slot_server_results_equal_alone(precision, budget_groups):
+    """Continuous batching below handle granularity (SlotServer): requests of
+    two shapes stream through groups of 2 x 6 slots at Poisson arrivals, so
+    load cases of different requests enter and leave one group between
+    chunks; each C_eff equals the cell solved alone, bitwise.  With a budget
+    of about one group the two shapes take turns (eviction)."""
+    pkg = _pkg()
+    from paper_2508_02613_amd.serve import SlotServer, workspace_bytes
+
+    reqs = _requests(9, 5, (32, 48))
+    one = workspace_bytes((48, 48, 48), precision, pkg.PC_GREEN_JACOBI, 12)
+    budget = int(budget_groups * one)
+    say(f"slot server: 9 requests (32/48), precision={precision}, budget {budget / 2**20:.0f} MiB")
+    srv = SlotServer(budget_bytes=budget, precision=precision, slots_per_group=2,
+                     graph_iterations=8)
+    stats = srv.run(reqs, rate=60.0, seed=2)
+    srv.close()
+    say(f"  {stats}")
+    assert stats["all_ok"] and 0 < stats["max_rel_res_true"] <= 1.5e-8
+    assert stats["chunks"] > 0 and stats["mean_busy_slots_per_chunk"] > 0
+    for r in reqs:
+        Ca, reps = pkg.effective_stiffness(r.E, nu=0.3, tol=1e-8, precision=precision)
+        assert [x.iters for x in reps] == r.iters, (r.rid, r.iters)
+        assert np.array_equal(Ca, r.C), f"request {r.rid}: C_eff differs alone vs slot-served"
+        assert r.latency > 0 and r.done >= r.start >= r.arrival - 1e-9

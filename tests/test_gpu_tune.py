@@ -1,5 +1,6 @@
 """GPU tests of the launch-parameter autotuner: valid, cached, and neutral
-for results (a tuned group equals single cells run with the same tz)."""
+for results (a tuned group equals single cells run with the same tile
+shapes), and every tile shape solves the same problem."""
 import numpy as np
 import pytest
 
@@ -35,11 +36,14 @@ def test_autotune_cached_and_result_neutral(shape, batch, tmp_path, monkeypatch)
     assert p["ygrid"] >= 1 and p["graph_iterations"] in (0, 8, 16)
     if len(shape) == 3:
         assert 2 <= p["tz"] <= shape[0]
+    else:
+        assert p["tiles2d"] in (1, 2)
+    assert p["xrows"] >= 1 and p["xrows"] & (p["xrows"] - 1) == 0
     assert (tmp_path / "tunables.json").exists()
     assert tune.autotune(shape, batch=batch, precision=pkg.MIXED) == p  # from the cache
-    # another group size reuses the shape's tz
+    # another group size reuses the shape's tile shapes
     p2 = tune.autotune(shape, batch=batch + 1, precision=pkg.MIXED, iters=12)
-    assert p2["tz"] == p["tz"]
+    assert all(p2[k] == p[k] for k in tune.SHAPE_KEYS)
     dim = len(shape)
     Es = [ji.grf_field(shape, 1e3, seed=s, ell=0.15) for s in range(batch)]
     macros = np.random.default_rng(1).uniform(-1, 1, (batch, dim * (dim + 1) // 2))
@@ -51,7 +55,8 @@ def test_autotune_cached_and_result_neutral(shape, batch, tmp_path, monkeypatch)
     grp.close()
     for i in range(batch):
         c = pkg.Cell(shape, precision=pkg.MIXED)
-        c.set_tunables(tz=p["tz"])
+        c.set_tunables(tz=p["tz"], tiles2d=p["tiles2d"], xrows=p["xrows"],
+                       fused_control=p["fused_control"])
         c.set_material(Es[i], nu=0.3)
         ui, si, ri, _ = c.solve(macros[i], tol=1e-8)
         c.close()
@@ -71,6 +76,96 @@ def test_tunables_validation():
         c.set_tunables(tz=17)
     with pytest.raises(pkg.JfftError):
         c.set_tunables(ygrid=0)
-    c.set_tunables(tz=8, ygrid=300)
-    assert c.tunables() == {"tz": 8, "ygrid": 300}
+    with pytest.raises(pkg.JfftError):
+        c.set_tunables(xrows=3)
+    with pytest.raises(pkg.JfftError):
+        c.set_tunables(tiles2d=3)
+    c.set_tunables(tz=8, ygrid=300, xrows=2)
+    assert c.tunables() == {"tz": 8, "ygrid": 300, "tiles2d": 0, "xrows": 2, "fused_control": 0}
+    c.set_tunables(xrows=1 << 20)  # clamped to the most rows that fit
+    assert 2 <= c.tunables()["xrows"] < 1 << 20
     c.close()
+    c = pkg.Cell((64, 64), precision=pkg.FP64)
+    assert c.tunables()["tiles2d"] == 1
+    c.set_tunables(tiles2d=2)
+    assert c.tunables()["tiles2d"] == 2
+    c.set_tunables(tiles2d=0)
+    assert c.tunables()["tiles2d"] == 1
+    c.close()
+
+
+@pytest.mark.parametrize("shape,prec", [((90, 72), "FP64"), ((90, 72), "MIXED"),
+                                        ((30, 20, 18), "FP64")])
+def test_tile_shapes_solve_the_same_problem(shape, prec):
+    """Every tile shape (2D tiles per block, x-pass rows per block, down to
+    one row) gives the same solution up to the regrouping of partial sums:
+    iteration counts within one, fields within the solver tolerance.  The
+    grids leave ragged tiles and blocks in every direction."""
+    pkg = _pkg()
+    dim = len(shape)
+    E = ji.grf_field(shape, 1e3, seed=3, ell=0.15)
+    macro = np.random.default_rng(2).uniform(-1, 1, dim * (dim + 1) // 2)
+    ref = None
+    c = pkg.Cell(shape, precision=getattr(pkg, prec))
+    c.set_material(E, nu=0.3)
+    rb = c.tunables()["xrows"]
+    shapes = [(t2, xr) for t2 in ((1, 2) if dim == 2 else (0,)) for xr in (rb, 4, 1)]
+    for t2, xr in shapes:
+        c.set_tunables(tiles2d=t2, xrows=xr)
+        u, sbar, rep, _ = c.solve(macro, tol=1e-10, maxit=5000)
+        u = u.cpu().numpy()
+        say(f"{shape} {prec} tiles2d {t2} xrows {xr}: iters {rep.iters} res {rep.rel_res_true:.1e}")
+        assert rep.status == "ok" and rep.rel_res_true <= 1.5e-10
+        if ref is None:
+            ref = (u, sbar, rep.iters)
+            continue
+        assert abs(rep.iters - ref[2]) <= 1
+        assert np.abs(u - ref[0]).max() <= 1e-7 * np.abs(ref[0]).max()
+        assert np.abs(sbar - ref[1]).max() <= 1e-8 * np.abs(ref[1]).max()
+    c.close()
+
+
+@pytest.mark.parametrize("shape,prec,graph", [((48, 40), "FP64", 0), ((48, 40), "MIXED", 8),
+                                              ((20, 16, 18), "FP64", 8),
+                                              ((20, 16, 18), "MIXED", 0)])
+def test_fused_control_matches_separate_launches(shape, prec, graph):
+    """The CG scalar steps run in the last block of their producer kernels
+    or as single-block kernels (default): the same solve up to the order of
+    the partial sums (iteration counts within one, fields within the
+    tolerance), for a group of three cells that stop at different
+    iterations, with and without graph replay; the history (alpha, beta,
+    residuals) agrees to rounding on the common prefix."""
+    import torch
+
+    pkg = _pkg()
+    dim = len(shape)
+    ds = dim * (dim + 1) // 2
+    Es = np.stack([ji.grf_field(shape, 10.0 ** (2 + k), seed=60 + k, ell=0.15) for k in range(3)])
+    macros = np.random.default_rng(5).uniform(-1, 1, (3, ds))
+    out = {}
+    for fused in (1, 0):
+        g = pkg.Cell(shape, precision=getattr(pkg, prec), batch=3, stream=torch.cuda.Stream())
+        g.set_tunables(fused_control=fused)
+        assert g.tunables()["fused_control"] == fused
+        if graph:
+            g.set_graph_iterations(graph)
+        if prec == "FP64":
+            g.enable_history(200)
+        g.set_material(Es, nu=0.3)
+        u, sbar, reps, _ = g.solve_batch(macros, tol=1e-10, maxit=5000)
+        hist = [g.history(200, i) for i in range(3)] if prec == "FP64" else None
+        out[fused] = (u.cpu().numpy(), sbar, reps, hist)
+        g.close()
+    (u1, s1, r1, h1), (u0, s0, r0, h0) = out[1], out[0]
+    for i in range(3):
+        say(f"{shape} {prec} graph {graph} cell {i}: iters fused {r1[i].iters} separate "
+            f"{r0[i].iters}")
+        assert r1[i].status == "ok" and r0[i].status == "ok"
+        assert abs(r1[i].iters - r0[i].iters) <= 1
+        assert np.abs(u1[i] - u0[i]).max() <= 1e-7 * np.abs(u0[i]).max()
+        assert np.abs(s1[i] - s0[i]).max() <= 1e-8 * np.abs(s0[i]).max()
+        if h1 is not None:
+            k = min(len(h1[i][0]), len(h0[i][0]), 15)
+            assert k >= 10
+            for a, b in zip(h1[i], h0[i]):
+                np.testing.assert_allclose(a[:k - 1], b[:k - 1], rtol=1e-9)
