@@ -6,8 +6,14 @@ and lies between the Reuss and Voigt bounds in the Loewner order.  With
 C(x) = E(x) C^, Voigt = <E> C^ (u = 0 is admissible, and the 2-point Gauss
 rule integrates the pixel-constant E exactly) and Reuss = <1/E>^-1 C^ (a lower
 bound of the continuum problem, which the FE solution exceeds).  Parity with
-the oracle: all 36 entries at 32^3, and one 64^3 load case field by field.
+the oracle: all 36 entries at 32^3; at 64^3 all six load cases of GRF seeds
+0-2 against stored oracle results (tests/golden/config2_oracle.json, written
+by tests/golden/make_config2_oracle.py, which calls only the oracle), and one
+load case field by field against an oracle solve run here.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -85,35 +91,127 @@ def test_ceff_64_bounds_and_symmetry(seed):
     assert dm <= 1e-7
 
 
-def test_64_load_case_matches_oracle():
-    """One 64^3 load case (e11): iteration counts within +-1 plus the flat
-    stretch of the oracle's convergence curve around the threshold (CG
-    amplifies rounding over 150+ iterations, and where the residual decays
-    slowly the crossing moves), the fluctuation field near the exact discrete
-    solution at tol 1e-12 (1e-10)."""
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "config2_oracle.json")
+
+
+def _golden():
+    with open(GOLDEN) as fh:
+        return json.load(fh)
+
+
+def _window(case):
+    counts = [r["iters"] for r in case["runs"]]
+    return min(counts) - 1, max(counts) + 1, counts
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_config2_matches_oracle(seed):
+    """64^3 GRF cell (contrast 1e4, ell 0.1, nu 0.3), the six unit macro
+    strains, FP64 Green-Jacobi, against the oracle's stored results.
+
+    At tol 1e-8: the iteration count in the oracle's window (min - 1 ..
+    max + 1 of its thirteen counts over its rounding variants, see
+    oracle_spread.py);
+    sigma_bar to 1e-8 of the oracle's; the distance from the exact discrete
+    solution u* (the oracle's tol-1e-12 solution) at most 10x the largest
+    such distance of the thirteen oracle runs.  At tol 1e-12: u at the sampled
+    nodes to 1e-10 of max |u*|, the relative distance from u* below 1e-10,
+    sigma_bar (a column of C_eff) to 1e-11.  Distances from u* are estimated
+    from 24 seeded Gaussian projections (E[(w.x)^2] = ||x||^2; the stored
+    sketch of u* uses the same vectors); the estimate's relative standard
+    deviation is about 1/sqrt(48) = 0.14."""
     pkg = _pkg()
+    data = _golden()
+    wl = data["workload"]
+    cases = [c for c in data["cases"] if c["seed"] == seed]
+    nvar = len(data["cases"][0]["runs"]) if data["cases"] else 0
+    if len(cases) < 6 or any(len(c["runs"]) < nvar for c in cases):
+        pytest.skip(f"tests/golden/config2_oracle.json holds {len(cases)} of the 6 load cases of "
+                    f"seed {seed} (written by tests/golden/make_config2_oracle.py)")
+    n = wl["n"]
+    shape = (n, n, n)
+    E = ji.grf_field(shape, wl["contrast"], seed=seed, ell=wl["ell"])
+    cell = pkg.Cell(shape, pc=pkg.PC_GREEN_JACOBI)
+    cell.set_material(E, nu=wl["nu"])
+    sols = {}
+    for case in cases:
+        g = case["load_case"]
+        m = ji.unit_macro_strain(3, g)
+        u8, s8, r8, _ = cell.solve(m, tol=wl["tol"], maxit=wl["maxit"])
+        u12, s12, r12, _ = cell.solve(m, tol=wl["tol_tight"], maxit=wl["maxit"])
+        sols[g] = (u8.cpu().numpy(), s8, r8, u12.cpu().numpy(), s12, r12)
+    cell.close()
+    # project every solution on the sketch vectors, one vector at a time
+    proj = {g: ([], []) for g in sols}
+    for w in ji.sketch_vectors((3,) + shape, wl["n_sketch"], wl["sketch_seed"]):
+        wf = w.ravel()
+        for g, (u8, _, _, u12, _, _) in sols.items():
+            proj[g][0].append(float(np.dot(wf, u8.ravel())))
+            proj[g][1].append(float(np.dot(wf, u12.ravel())))
+    Cg, Co = np.zeros((6, 6)), np.zeros((6, 6))
+    for case in cases:
+        g = case["load_case"]
+        u8, s8, r8, u12, s12, r12 = sols[g]
+        tight = case["tight"]
+        star = np.array(tight["sketch"])
+        un = tight["u_norm"]
+        e8 = float(np.sqrt(np.mean((np.array(proj[g][0]) - star) ** 2))) / un
+        e12 = float(np.sqrt(np.mean((np.array(proj[g][1]) - star) ** 2))) / un
+        lo, hi, counts = _window(case)
+        e_or = max(r["err_vs_tight"] for r in case["runs"])
+        s_or = np.array(case["runs"][0]["sigma_bar"])
+        s_star = np.array(tight["sigma_bar"])
+        ds8 = np.abs(s8 - s_or).max() / np.abs(s_star).max()
+        ds12 = np.abs(s12 - s_star).max() / np.abs(s_star).max()
+        nodes = np.array(tight["nodes"])
+        u_nodes = np.array(tight["u_nodes"])
+        dn = np.abs(u12.reshape(3, -1)[:, nodes] - u_nodes).max() / np.abs(u_nodes).max()
+        say(f"seed {seed} e{g + 1}: tol 1e-8 iters gpu={r8.iters} oracle={counts} "
+            f"window [{lo}, {hi}] |u-u*| gpu~{e8:.2e} oracle max={e_or:.2e} d_sigma={ds8:.1e}; "
+            f"tol 1e-12 iters gpu={r12.iters} oracle={tight['iters']} |u-u*|~{e12:.1e} "
+            f"nodes {dn:.1e} d_sigma={ds12:.1e}")
+        assert r8.status == "ok" and r12.status == "ok"
+        assert lo <= r8.iters <= hi
+        assert r8.rel_res_true <= 1.5e-8
+        assert ds8 <= 1e-8
+        assert e8 <= 10 * e_or
+        assert dn <= 1e-10 and e12 <= 1e-10
+        assert ds12 <= 1e-11
+        Cg[:, g] = s12
+        Co[:, g] = s_star
+    dc = np.abs(Cg - Co).max() / np.abs(Co).max()
+    say(f"seed {seed}: max |C_eff - C_eff oracle| / max |C_eff oracle| = {dc:.1e}")
+    assert dc <= 1e-11
+
+
+def test_64_load_case_matches_oracle():
+    """One 64^3 load case (e11, seed 0) field by field against an oracle solve
+    run here at tol 1e-12: the GPU's tol-1e-12 fluctuation to 1e-10 in the
+    mean-free 2-norm; at tol 1e-8 the iteration count in the stored oracle
+    window.  The oracle run here must reproduce the stored tight solve
+    exactly (same iteration count and sigma_bar): the oracle build is
+    deterministic."""
+    pkg = _pkg()
+    case = [c for c in _golden()["cases"] if c["seed"] == 0 and c["load_case"] == 0][0]
     E = ji.grf_field((64, 64, 64), 1e4, seed=0, ell=0.1)
     macro = ji.unit_macro_strain(3, 0)
     cell = pkg.Cell(E.shape, pc=pkg.PC_GREEN_JACOBI)
     cell.set_material(E, nu=0.3)
-    for tol in (1e-8, 1e-12):
-        say(f"64^3 GRF contrast 1e4, e11, tol {tol:g} vs oracle")
-        u, sbar, rep, _ = cell.solve(macro, tol=tol, maxit=5000)
-        ug = u.cpu().numpy()
-        ref = oracle.solve(E, macro, LAM, MU, pc=3, tol=tol, maxit=5000, hist_len=5000)
-        err = np.linalg.norm(ug - ref.u) / np.linalg.norm(ref.u)
-        # +-1, plus the iterations over which the oracle's residual lies within
-        # a factor 3 of the threshold (where the curve is that flat, rounding
-        # moves the crossing)
-        rel = ref.res[:ref.iters] / np.linalg.norm(oracle.rhs(E, macro, LAM, MU))
-        slack = 1 + int(np.count_nonzero((rel >= tol / 3) & (rel <= 3 * tol)))
-        say(f"  iters gpu={rep.iters} oracle={ref.iters} (slack {slack}) err(u)={err:.2e}")
-        assert rep.status == "ok" and ref.status == "ok"
-        assert abs(rep.iters - ref.iters) <= slack
-        if tol == 1e-8:
-            assert err <= 1e-6
-        else:
-            assert err <= 1e-10
-            np.testing.assert_allclose(sbar, ref.sigma_bar, rtol=1e-11,
-                                       atol=1e-11 * np.abs(ref.sigma_bar).max())
+    say("64^3 GRF contrast 1e4, e11, tol 1e-8 and 1e-12 vs oracle")
+    _, _, rep8, _ = cell.solve(macro, tol=1e-8, maxit=5000)
+    u, sbar, rep, _ = cell.solve(macro, tol=1e-12, maxit=5000)
+    ug = u.cpu().numpy()
     cell.close()
+    ref = oracle.solve(E, macro, LAM, MU, pc=3, tol=1e-12, maxit=5000)
+    err = np.linalg.norm(ug - ref.u) / np.linalg.norm(ref.u)
+    lo, hi, counts = _window(case)
+    say(f"  tol 1e-8 iters gpu={rep8.iters} window [{lo}, {hi}]; tol 1e-12 iters gpu={rep.iters} "
+        f"oracle={ref.iters} err(u)={err:.2e}")
+    assert ref.iters == case["tight"]["iters"]
+    assert np.array_equal(ref.sigma_bar, np.array(case["tight"]["sigma_bar"]))
+    assert rep8.status == "ok" and rep.status == "ok" and ref.status == "ok"
+    assert lo <= rep8.iters <= hi
+    assert err <= 1e-10
+    np.testing.assert_allclose(sbar, ref.sigma_bar, rtol=1e-11,
+                               atol=1e-11 * np.abs(ref.sigma_bar).max())
