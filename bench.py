@@ -323,10 +323,6 @@ def serve_requests(pool, count, seed):
 LOAD_FRACTIONS = (0.5, 0.8, 0.95)
 
 
-def slots_per_group(shape):
-    """Requests per slot group (6 slots each) by cell size: more for small cells."""
-    n = max(shape)
-    return 8 if n <= 48 else (4 if n <= 64 else 2)
 
 
 def run_serving(args):
@@ -344,22 +340,22 @@ def run_serving(args):
                         "contrast log-uniform 1e2-1e4 (drawn from 80 distinct fields), 6 load "
                         "cases -> C_eff each, 64 GiB admission budget, 8 PCG iterations per "
                         "graph; Poisson arrivals at 0.5, 0.8 and 0.95 x the measured capacity. "
-                        "slots_*: continuous batching over group slots (one group per shape, "
-                        "8 / 4 / 2 requests per group for side <= 48 / 64 / larger, admission "
-                        "and harvest every 8 iterations); mixed, fp64: 4 workers with whole "
-                        "handles, merge <= 4 waiting requests of side <= 64"),
+                        "mixed, fp64: 4 workers with whole handles, merge <= 4 waiting requests "
+                        "of side <= 64; slots_mixed: continuous batching over group slots (one "
+                        "group of 2 requests = 12 slots per shape, admission and harvest every "
+                        "4 iterations)"),
            "unit": "requests/s (6 solves each); latency ms"}
     runs = []
-    if args.serve_mode in ("slots", "both"):
-        runs += [("slots_mixed", pkg.MIXED, True), ("slots_fp64", pkg.FP64, True)]
     if args.serve_mode in ("handles", "both"):
         runs += [("mixed", pkg.MIXED, False), ("fp64", pkg.FP64, False)]
+    if args.serve_mode in ("slots", "both"):
+        runs += [("slots_mixed", pkg.MIXED, True)]
     for name, prec, slots in runs:
         print(f"[serving] {name}: warm-up, capacity, then Poisson loads {LOAD_FRACTIONS}",
               file=sys.stderr, flush=True)
         if slots:
-            srv = SlotServer(budget_bytes=64 << 30, precision=prec, graph_iterations=8,
-                             slots_per_group=slots_per_group)
+            srv = SlotServer(budget_bytes=64 << 30, precision=prec, graph_iterations=4,
+                             slots_per_group=2)
         else:
             srv = Server(workers=4, budget_bytes=64 << 30, precision=prec, graph_iterations=8)
         srv.run(serve_requests(pool, 8, 99), rate=None)  # warm-up: handles, graphs, kernels
