@@ -196,9 +196,12 @@ jfft_status jfft_solve_batch(jfft_cell_t cell, const double *macro_strains, doub
      Poisson ratio nu (the running slots share the Lame constants: a
      different nu is refused while another slot runs), macro strain (host,
      d* values), tol and maxit as in jfft_solve (stopping rule and options of
-     the group apply).  The slot must be free.  Synchronises the stream (the
-     material check).  Errors: JFFT_E_INVALID (slot out of range or busy,
-     bad arguments, bad E), JFFT_E_HIP.
+     the group apply).  The slot must be free.  Enqueues the slot's set-up
+     on the group's stream without synchronising: E is checked on the
+     device, and an E with negative or non-finite entries finishes the slot
+     at once with the status JFFT_E_INVALID (returned by its harvest).
+     Errors: JFFT_E_INVALID (slot out of range or busy, bad arguments),
+     JFFT_E_HIP.
    jfft_slots_step: at least `iterations` (>= 1) PCG iterations of every
      running slot (whole replays of the captured chunk when graph replay is
      on, else an even number of direct launches), then the bookkeeping of

@@ -277,10 +277,22 @@ __global__ void k_slot_park(CgState *st, long long cs) {
   st->arrive[0] = st->arrive[1] = st->arrive[2] = 0;
 }
 
+// A slot's material check, run after its solve set-up: E with negative or
+// non-finite entries (count in small[0], see k_check_E) stops the slot
+// before any iteration with the status JFFT_E_INVALID.
+__global__ void k_slot_validate(CgState *st, const double *small, long long cs) {
+  st = cshift(st, blockIdx.x, cs);
+  small = cshift(small, blockIdx.x, cs);
+  if (threadIdx.x != 0 || small[0] == 0.0) return;
+  st->outer_done = 1;
+  st->done = 1;
+  st->final_status = ST_INVALID;
+}
+
 // FP64 solve: final status from the loop state.
 __global__ void k_fp64_final(CgState *st, long long cs) {
   st = cshift(st, blockIdx.x, cs);
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x != 0 || st->final_status == ST_INVALID) return;
   st->total_iters = st->iter;
   st->outer = st->homog ? 0 : 1;
   st->final_status = st->homog ? ST_OK : st->status;

@@ -190,8 +190,13 @@ struct jfft_cell_s {
   bool in_view = false;  // per-cell pointers moved to one slot (CellView)
 
   // captured iteration chunks
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};  // [0] FP64, [1] FP32 inner
-  int gexec_iters[2] = {0, 0};
+  // one per (precision, cells launched, depth): the whole group, or a
+  // prefix of its slots (continuous batching)
+  struct Graph {
+    int fp64, cells, iters;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
   bool capturing = false;
 
   // timing
@@ -207,12 +212,8 @@ struct jfft_cell_s {
   hipEvent_t phase_ev[4] = {nullptr, nullptr, nullptr, nullptr};
 
   void drop_graphs() {
-    for (int k = 0; k < 2; ++k)
-      if (gexec[k]) {
-        (void)hipGraphExecDestroy(gexec[k]);
-        gexec[k] = nullptr;
-        gexec_iters[k] = 0;
-      }
+    for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
   }
 
   ~jfft_cell_s() {
@@ -950,19 +951,20 @@ jfft_status pcg_begin(jfft_cell_s *c, const PcgBufs<Real> &b, bool mixed, int ma
   return JFFT_OK;
 }
 
-// The captured chunk of G = tun.graph_iters iterations for this precision,
-// (re)built when missing or of another depth.  Its arguments never change
-// (the buffers of this handle are fixed) and the CG state lives in device
-// memory, so one capture serves every later loop.
+// The captured chunk of G = tun.graph_iters iterations for this precision
+// and the c->B cells launched, built when missing.  Its arguments never
+// change (the buffers of this handle are fixed) and the CG state lives in
+// device memory, so one capture serves every later loop.
 template <typename Real>
-jfft_status ensure_graph(jfft_cell_s *c, const PcgBufs<Real> &b, History h) {
-  const int gk = sizeof(Real) == 8 ? 0 : 1;
+jfft_status ensure_graph(jfft_cell_s *c, const PcgBufs<Real> &b, History h,
+                         hipGraphExec_t *out) {
+  const int fp64 = sizeof(Real) == 8 ? 1 : 0;
   const int G = c->tun.graph_iters;
-  if (c->gexec[gk] && c->gexec_iters[gk] == G) return JFFT_OK;
-  if (c->gexec[gk]) {
-    (void)hipGraphExecDestroy(c->gexec[gk]);
-    c->gexec[gk] = nullptr;
-  }
+  for (const auto &g : c->graphs)
+    if (g.fp64 == fp64 && g.cells == c->B && g.iters == G) {
+      *out = g.exec;
+      return JFFT_OK;
+    }
   hipGraph_t gr = nullptr;
   HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   c->capturing = true;
@@ -972,23 +974,27 @@ jfft_status ensure_graph(jfft_cell_s *c, const PcgBufs<Real> &b, History h) {
   hipError_t e = hipStreamEndCapture(c->stream, &gr);
   if (s) return s;
   if (e != hipSuccess) return fail(JFFT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
-  e = hipGraphInstantiate(&c->gexec[gk], gr, nullptr, nullptr, 0);
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
   (void)hipGraphDestroy(gr);
   if (e != hipSuccess) return fail(JFFT_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
-  c->gexec_iters[gk] = G;
+  c->graphs.push_back({fp64, c->B, G, ex});
+  *out = ex;
   return JFFT_OK;
 }
 
-// At least `iters` PCG iterations of every running cell of the group: whole
-// replays of the captured chunk, or direct launches (an even count, so that
-// every chunk starts on the same search-direction buffer).
+// At least `iters` PCG iterations of every running cell among the c->B
+// launched: whole replays of the captured chunk, or direct launches (an
+// even count, so that every chunk starts on the same search-direction
+// buffer).
 template <typename Real>
 jfft_status pcg_iterations(jfft_cell_s *c, const PcgBufs<Real> &b, int iters, History h) {
   const int G = c->tun.graph_iters;
   if (G > 0 && !c->timing) {
-    TRY(ensure_graph<Real>(c, b, h));
+    hipGraphExec_t ex = nullptr;
+    TRY(ensure_graph<Real>(c, b, h, &ex));
     const int reps = std::max(1, (iters + G / 2) / G);
-    for (int k = 0; k < reps; ++k) HIP_TRY(hipGraphLaunch(c->gexec[sizeof(Real) == 8 ? 0 : 1], c->stream));
+    for (int k = 0; k < reps; ++k) HIP_TRY(hipGraphLaunch(ex, c->stream));
   } else {
     const int n = iters + (iters & 1);
     for (int j = 1; j <= n; ++j) TRY(pcg_iteration<Real>(c, b, j, h));
@@ -1022,6 +1028,16 @@ jfft_status pcg_loop(jfft_cell_s *c, const PcgBufs<Real> &b, History h) {
 jfft_status reduce_to(jfft_cell_s *c, const double *part, long long n, int groups, int slot,
                       int cells) {
   LAUNCH(c, KID_REDUCE, k_reduce_groups<<<cells, CTRL_THREADS, 0, c->stream>>>(part, n, groups, c->small + slot, c->cs));
+  return JFFT_OK;
+}
+
+// CG states and reduction results of every cell, with one synchronisation.
+jfft_status fetch_all(jfft_cell_s *c) {
+  HIP_TRY(hipMemcpy2DAsync(c->st_h, sizeof(CgState), c->st, (size_t)c->cs, sizeof(CgState), c->B,
+                           hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpy2DAsync(c->small_h, sizeof(double) * kSmall, c->small, (size_t)c->cs,
+                           sizeof(double) * kSmall, c->B, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
   return JFFT_OK;
 }
 
@@ -1122,8 +1138,11 @@ void tri_stencil(jfft_cell_s *c, double lam, double mu) {
 bool slots_busy(const jfft_cell_s *c);
 constexpr const char *kSlotsBusy = "the group's slots hold running or unharvested solves";
 
+// defer_check (slot admission): the count of bad entries of E stays in the
+// cell's reduction results (small[0]) for k_slot_validate instead of being
+// read back here, so that admission does not synchronise.
 jfft_status set_material_impl(jfft_cell_s *c, const double *E_dev, double lam, double mu,
-                              bool broadcast = false) {
+                              bool broadcast = false, bool defer_check = false) {
   if (!E_dev) return fail(JFFT_E_INVALID, "E_dev is NULL");
   if (slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   if (!(mu > 0.0) || !(lam + 2.0 * mu / c->dim > 0.0) || !std::isfinite(lam) || !std::isfinite(mu))
@@ -1145,10 +1164,12 @@ jfft_status set_material_impl(jfft_cell_s *c, const double *E_dev, double lam, d
   const int nb = vec_blocks(N);
   LAUNCH(c, KID_SETUP, k_check_E<<<dim3(nb, c->B), 256, 0, c->stream>>>(E_dev, es, N, c->partA, c->cs));
   TRY(reduce_to(c, c->partA, nb, 1, 0, c->B));
-  TRY(fetch_small(c));
-  for (int i = 0; i < c->B; ++i)
-    if (c->small_h[(size_t)i * kSmall] != 0.0)
-      return fail(JFFT_E_INVALID, "E contains negative or non-finite entries (cell " + std::to_string(i) + ")");
+  if (!defer_check) {
+    TRY(fetch_small(c));
+    for (int i = 0; i < c->B; ++i)
+      if (c->small_h[(size_t)i * kSmall] != 0.0)
+        return fail(JFFT_E_INVALID, "E contains negative or non-finite entries (cell " + std::to_string(i) + ")");
+  }
   LAUNCH(c, KID_SETUP, k_copy<double><<<dim3(nb, c->B), 256, 0, c->stream>>>(E_dev, es, c->E, c->cs, N));
   const long long nd = (long long)c->dim * N;
   const int nbd = vec_blocks(nd);
@@ -1175,9 +1196,19 @@ double elapsed_ms(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
+// sigma_bar of every cell from the fetched reduction results.
+void read_sigma_bar(const jfft_cell_s *c, double *sigma_bar) {
+  const int ds = c->dim * (c->dim + 1) / 2;
+  for (int i = 0; i < c->B; ++i)
+    for (int r = 0; r < ds; ++r)
+      sigma_bar[(size_t)i * ds + r] = c->small_h[(size_t)i * kSmall + 16 + r] / c->g.vol;
+}
+
 // True residual, mean removal (Sec. 5), stresses and sigma_bar; results to
-// the caller's arrays.
-jfft_status post_process(jfft_cell_s *c, double *u_out, double *sigma_dev, double *sigma_bar) {
+// the caller's arrays.  fetch = false: the caller fetches the results
+// (fetch_all) and reads sigma_bar (read_sigma_bar) itself.
+jfft_status post_process(jfft_cell_s *c, double *u_out, double *sigma_dev, double *sigma_bar,
+                         bool fetch = true) {
   const long long N = c->g.N;
   const int d = c->dim;
   const long long nd = (long long)d * N;
@@ -1199,9 +1230,10 @@ jfft_status post_process(jfft_cell_s *c, double *u_out, double *sigma_dev, doubl
   // u to the caller's [B][d][N] array
   if (u_out)  // internal callers read the fluctuations from the workspace
     LAUNCH(c, KID_VEC, k_copy<double><<<dim3(nb, Bc), 256, 0, c->stream>>>(c->u, c->cs, u_out, (long long)sizeof(double) * nd, nd));
-  TRY(fetch_small(c));
-  for (int i = 0; i < Bc; ++i)
-    for (int r = 0; r < ds; ++r) sigma_bar[(size_t)i * ds + r] = c->small_h[(size_t)i * kSmall + 16 + r] / c->g.vol;
+  if (fetch) {
+    TRY(fetch_small(c));
+    read_sigma_bar(c, sigma_bar);
+  }
   return JFFT_OK;
 }
 
@@ -1328,9 +1360,10 @@ jfft_status solve_impl(jfft_cell_s *c, const double *macros_h, double tol, int m
     TRY(mixed_refine(c, maxit, u0 != nullptr));
   }
   HIP_TRY(hipEventRecord(c->phase_ev[2], c->stream));
-  TRY(post_process(c, u_out, sigma_dev, sigma_bar));
+  TRY(post_process(c, u_out, sigma_dev, sigma_bar, false));
   HIP_TRY(hipEventRecord(c->phase_ev[3], c->stream));
-  TRY(fetch_states(c));
+  TRY(fetch_all(c));
+  read_sigma_bar(c, sigma_bar);
   const double setup_ms = elapsed_ms(c->phase_ev[0], c->phase_ev[1]);
   const double loop_ms = elapsed_ms(c->phase_ev[1], c->phase_ev[2]);
   const double post_ms = elapsed_ms(c->phase_ev[2], c->phase_ev[3]);
@@ -1437,15 +1470,17 @@ jfft_status slot_admit(jfft_cell_s *c, int slot, const double *E_dev, double lam
   if ((c->lam != lam || c->mu != mu) && slots_busy(c))
     return fail(JFFT_E_INVALID, "another slot runs with other elastic constants");
   {
+    // no synchronisation: a bad E is reported by the slot's harvest, and a
+    // cell that needs no iteration (homogeneous) starts stopped
     CellView v(c, slot);
-    TRY(set_material_impl(c, E_dev, lam, mu));
+    TRY(set_material_impl(c, E_dev, lam, mu, false, true));
     TRY(solve_setup(c, macro_h, tol, nullptr));
+    LAUNCH(c, KID_CTRL, k_slot_validate<<<1, 1, 0, c->stream>>>(c->st, c->small, c->cs));
     if (c->prec == JFFT_FP64) {
       TRY(fp64_start(c, maxit, false, History{nullptr, nullptr, nullptr}));
     } else {
       TRY(sweep_residual(c, maxit, false));
-      TRY(fetch_states(c));
-      if (!c->st_h[0].outer_done) TRY(sweep_start(c, maxit, false));
+      TRY(sweep_start(c, maxit, false));
     }
   }
   c->slot_state[slot] = SLOT_RUNNING;
@@ -1458,13 +1493,23 @@ jfft_status slot_admit(jfft_cell_s *c, int slot, const double *E_dev, double lam
 jfft_status slots_step(jfft_cell_s *c, int iters, int *states) {
   if (iters < 1) return fail(JFFT_E_INVALID, "iterations must be >= 1");
   TRY(slots_init(c));
-  bool any = false;
-  for (int s : c->slot_state) any = any || s == SLOT_RUNNING;
-  if (any) {
+  int hi = 0;  // slots [0, hi) hold every running one
+  for (int i = 0; i < c->B; ++i)
+    if (c->slot_state[i] == SLOT_RUNNING) hi = i + 1;
+  if (hi > 0) {
+    // launch over a prefix of the group (a power of two of slots, or all):
+    // empty slots past it cost no blocks; one captured graph per prefix
+    int pb = 1;
+    while (pb < hi) pb *= 2;
+    const int B = c->B;
+    c->B = std::min(pb, B);
+    jfft_status st;
     if (c->prec == JFFT_FP64)
-      TRY(pcg_iterations<double>(c, bufs64(c), iters, History{nullptr, nullptr, nullptr}));
+      st = pcg_iterations<double>(c, bufs64(c), iters, History{nullptr, nullptr, nullptr});
     else
-      TRY(pcg_iterations<float>(c, bufs32(c), iters, History{nullptr, nullptr, nullptr}));
+      st = pcg_iterations<float>(c, bufs32(c), iters, History{nullptr, nullptr, nullptr});
+    c->B = B;
+    TRY(st);
     TRY(fetch_states(c));
     std::vector<int> ended;
     for (int i = 0; i < c->B; ++i) {
@@ -1484,7 +1529,7 @@ jfft_status slots_step(jfft_cell_s *c, int iters, int *states) {
       }
     }
     if (!ended.empty()) {
-      TRY(fetch_states(c));
+      if (c->prec == JFFT_MIXED) TRY(fetch_states(c));  // the sweeps' outer tests
       for (int i : ended) {
         if (c->prec == JFFT_MIXED && !c->st_h[i].outer_done) {
           CellView v(c, i);
@@ -1512,14 +1557,16 @@ jfft_status slot_harvest(jfft_cell_s *c, int slot, double *u_out, double *sigma_
   jfft_report R{};
   {
     CellView v(c, slot);
-    TRY(post_process(c, u_out, sigma_dev, sigma_bar));
-    TRY(fetch_states(c));
+    TRY(post_process(c, u_out, sigma_dev, sigma_bar, false));
+    TRY(fetch_all(c));
+    read_sigma_bar(c, sigma_bar);
     R = make_report(c, 0);
     LAUNCH(c, KID_CTRL, k_slot_park<<<1, 1, 0, c->stream>>>(c->st, c->cs));
   }
   R.loop_ms = c->slot_ms[slot];
   if (rep) *rep = R;
   c->slot_state[slot] = SLOT_FREE;
+  if (R.status == JFFT_E_INVALID) g_last_error = "E contains negative or non-finite entries";
   if (R.status == JFFT_E_NOT_CONVERGED) g_last_error = "PCG reached maxit";
   if (R.status == JFFT_E_BREAKDOWN) g_last_error = "PCG breakdown (p.q <= 0 or non-finite scalar)";
   return (jfft_status)R.status;

@@ -64,7 +64,7 @@ __device__ __forceinline__ T *cshift(T *p, int cell, long long cs) {
   return reinterpret_cast<T *>(reinterpret_cast<Byte *>(p) + off);
 }
 
-enum StatusCode { ST_OK = 0, ST_NOT_CONVERGED = 4, ST_BREAKDOWN = 5 };
+enum StatusCode { ST_OK = 0, ST_INVALID = 1, ST_NOT_CONVERGED = 4, ST_BREAKDOWN = 5 };
 
 // Per-iteration CG history (alpha_k, beta_k, ||r_k||) of a cell, or NULLs.
 struct History {

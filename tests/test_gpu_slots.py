@@ -113,9 +113,13 @@ def test_slot_states_and_errors():
     with pytest.raises(pkg.JfftError):
         grp.slot_admit(0, E, 0.25, [1.0, 0.0, 0.0])     # other Lame constants while one runs
     with pytest.raises(pkg.JfftError):
-        grp.slot_admit(0, -E, 0.3, [1.0, 0.0, 0.0])     # negative moduli
-    with pytest.raises(pkg.JfftError):
         grp.slot_harvest(1)                              # still running
+    grp.slot_admit(0, -E, 0.3, [1.0, 0.0, 0.0])          # negative moduli: checked on the device
+    st = grp.slots_step(2)
+    assert st[0] == grp.SLOT_FINISHED
+    with pytest.raises(pkg.JfftError, match="negative or non-finite"):
+        grp.slot_harvest(0)
+    assert grp.slots_step(2)[0] == grp.SLOT_FREE
     with pytest.raises(pkg.JfftError):
         grp.solve_batch(np.zeros((2, 3)))                # whole-group call while busy
     with pytest.raises(pkg.JfftError):
