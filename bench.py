@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream measurement")
+    ap.add_argument("--fused-control", type=int, default=-1,
+                    help="topopt: run the CG scalar steps in the last block of their producer "
+                         "kernels (1) or as their own launches (0); -1: the library default")
     ap.add_argument("--serve-mode", choices=("slots", "handles", "both"), default="both",
                     help="serving runs: continuous batching over group slots, whole handles "
                          "per worker, or both")
@@ -875,6 +878,8 @@ def run_topopt(args):
                    element="tri")
     if args.graph:
         grp.set_graph_iterations(args.graph)
+    if args.fused_control >= 0:
+        grp.set_tunables(fused_control=args.fused_control)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rho, out = grp.topopt_lbfgs(rho0, T, K, eta=0.01, tol=1e-8, maxit=200000)
@@ -921,7 +926,8 @@ def run_topopt(args):
                                 f"0.15, eta 0.01, rho_0 ~ U(0,1) seed {args.seed}, projected "
                                 f"L-BFGS (m 10) for {K} steps, Green-Jacobi PCG to 1e-8 from u = 0, "
                                 "FP64"),
-                   "n": n, "lbfgs_steps": K, "graph_iterations": args.graph},
+                   "n": n, "lbfgs_steps": K, "graph_iterations": args.graph,
+                   "fused_control": args.fused_control},
         "lbfgs": {"steps": out["steps"], "evals": out["evals"], "pcg_total": out["pcg_total"],
                   "f": out["f"], "gnorm": out["gnorm"],
                   "pcg_iters_per_step_max_over_load_cases": per_step,
