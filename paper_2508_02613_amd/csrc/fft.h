@@ -252,6 +252,84 @@ __device__ void lds_fft(typename CxT<Real>::T *buf, const FftPlan &pl, int W, in
   }
 }
 
+// The same transform with the length L and the line count W known at compile
+// time, for W lines held as buf[p * W + c] (the y and last-axis passes).
+// The radices are those factor_plan picks (8 first, then 4, 2, 3, 5), so the
+// arithmetic, and the result, are those of lds_fft; what changes is that
+// the index math (divisions by W, p and L / R, the twiddle strides) reduces
+// to shifts and constants, the stage loop and its radix switch unroll, and
+// the first stage skips its unit twiddles.
+constexpr int ct_radix(int rem) {
+  return rem % 8 == 0 ? 8 : (rem % 4 == 0 ? 4 : (rem % 2 == 0 ? 2 : (rem % 3 == 0 ? 3 : 5)));
+}
+
+template <typename Real, int R, bool INV, int NT, int L, int P, int W>
+__device__ __forceinline__ void stockham_stage_ct(typename CxT<Real>::T *buf,
+                                                  const typename CxT<Real>::T *tw) {
+  using C = typename CxT<Real>::T;
+  constexpr int M = L / R;
+  constexpr int NB = M * W;                 // butterflies of the stage
+  constexpr int MB = (NB + NT - 1) / NT;    // per thread
+  constexpr int STEP = L / (P * R);
+  C v[MB][R];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int f = (int)threadIdx.x + b * NT;
+    const int i = f / W, c = f % W;
+    if (NB % NT == 0 || f < NB) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = buf[(i + r * M) * W + c];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int f = (int)threadIdx.x + b * NT;
+    if (NB % NT == 0 || f < NB) {
+      const int i = f / W, c = f % W;
+      const int ip = i / P, k = i % P;
+      if (P > 1) {  // the first stage's twiddles are all exp(0) = 1
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C t = tw[r * k * STEP];
+          if (INV) t.y = -t.y;
+          v[b][r] = cmul(v[b][r], t);
+        }
+      }
+      Dft<Real, R, INV>::run(v[b]);
+      const int j = ip * P * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[(j + r * P) * W + c] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename Real, bool INV, int NT, int L, int W, int P = 1>
+__device__ __forceinline__ void lds_fft_ct(typename CxT<Real>::T *buf,
+                                           const typename CxT<Real>::T *tw) {
+  if constexpr (P < L) {
+    constexpr int R = ct_radix(L / P);
+    stockham_stage_ct<Real, R, INV, NT, L, P, W>(buf, tw);
+    lds_fft_ct<Real, INV, NT, L, W, P * R>(buf, tw);
+  }
+}
+
+// W lines of length L at buf[p * W + c]: the compile-time transform for the
+// common lengths, else the plan's.
+template <typename Real, bool INV, int NPT, int NT, int W>
+__device__ __forceinline__ void lds_fft_lines(typename CxT<Real>::T *buf, const FftPlan &pl,
+                                              const typename CxT<Real>::T *tw) {
+  if (pl.L == 256 && 256 * W <= NPT * NT)
+    lds_fft_ct<Real, INV, NT, 256, W>(buf, tw);
+  else if (pl.L == 128 && 128 * W <= NPT * NT)
+    lds_fft_ct<Real, INV, NT, 128, W>(buf, tw);
+  else if (pl.L == 512 && 512 * W <= NPT * NT)
+    lds_fft_ct<Real, INV, NT, 512, W>(buf, tw);
+  else
+    lds_fft<Real, INV, NPT, NT>(buf, pl, W, W, 1, tw, 1, false);
+}
+
 // Half-spectrum layout, tile-major: [d][nz][ntx][ny][TW] complex, where the
 // mx = nx/2 + 1 bins of an x row are cut into ntx tiles of TW = 8 bins.  A
 // y-pass tile (component, z, x-tile) is then one contiguous block, the x
@@ -654,7 +732,7 @@ __global__ void __launch_bounds__(NT) k_ypass(YArgs<Real> a) {
     }
     __syncthreads();
     if (t + gridDim.x < per_comp) load(t + gridDim.x);
-    lds_fft<Real, INV, PPT, NT>(buf, a.plan, TW, TW, 1, tw, 1, false);
+    lds_fft_lines<Real, INV, PPT, NT, TW>(buf, a.plan, tw);
     C *base = comp_base + t * npts;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
@@ -807,8 +885,15 @@ __device__ __forceinline__ void green2_tri(T cmx, T sx, T cmy, T sy, const doubl
 // an x-tile along y (2D, KY = 1).  The transformed components stay in
 // registers for the Green multiply; the next component's loads are in flight
 // while the current one is transformed.  L * KY * TW <= MaxPt * NT.
+// FP32: at most 128 VGPRs (four waves per SIMD, two 512-thread blocks per
+// CU); the unrolled transforms would otherwise take more and cut the
+// resident blocks, which costs this pass more than the leaner index math
+// saves (measured at 256^3: 174 us unbounded, 122 us bounded, 146 us with
+// the run-time plan).  Not for the one-row 3D tiles of 512-point axes, which
+// would spill.
 template <typename Real, int DIM, int KY, int NT>
-__global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
+__global__ void __launch_bounds__(NT, (sizeof(Real) == 4 && !(DIM == 3 && KY == 1)) ? 4 : 1)
+    k_green_axis(GArgs<Real> a) {
   using C = typename CxT<Real>::T;
   constexpr int PPT = MaxPt<Real>::value;
   constexpr int TW = TileW<Real>::value;
@@ -865,7 +950,7 @@ __global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
     }
     __syncthreads();
     if (c + 1 < DIM) load(c + 1);
-    lds_fft<Real, false, PPT, NT>(buf, a.plan, LN, LN, 1, tw, 1, false);
+    lds_fft_lines<Real, false, PPT, NT, LN>(buf, a.plan, tw);
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const int f = threadIdx.x + j * NT;
@@ -958,7 +1043,7 @@ __global__ void __launch_bounds__(NT) k_green_axis(GArgs<Real> a) {
       if (f < npts) buf[f] = stash[c][j];
     }
     __syncthreads();
-    lds_fft<Real, true, PPT, NT>(buf, a.plan, LN, LN, 1, tw, 1, false);
+    lds_fft_lines<Real, true, PPT, NT, LN>(buf, a.plan, tw);
     C *bc = base + c * comp_stride;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
