@@ -345,8 +345,9 @@ def run_serving(args):
                         "graph; Poisson arrivals at 0.5, 0.8 and 0.95 x the measured capacity. "
                         "mixed, fp64: 4 workers with whole handles, merge <= 4 waiting requests "
                         "of side <= 64; slots_mixed: continuous batching over group slots (one "
-                        "group of 2 requests = 12 slots per shape, admission and harvest every "
-                        "4 iterations)"),
+                        "group of 2 requests = 12 slots per shape; the library runs 4-iteration "
+                        "chunks until a load case finishes or 2 ms pass, then the driver "
+                        "harvests and admits)"),
            "unit": "requests/s (6 solves each); latency ms"}
     runs = []
     if args.serve_mode in ("handles", "both"):
@@ -378,7 +379,7 @@ def run_serving(args):
                 "p50_latency_ms": po["p50_latency_ms"], "p95_latency_ms": po["p95_latency_ms"],
                 "p99_latency_ms": po["p99_latency_ms"] if po["requests"] >= 200 else None}
             if slots:
-                row["loads"][str(frac)]["mean_busy_slots_per_chunk"] = po["mean_busy_slots_per_chunk"]
+                row["loads"][str(frac)]["mean_busy_slots_per_wakeup"] = po["mean_busy_slots_per_wakeup"]
             else:
                 row["loads"][str(frac)]["mean_merged"] = po["mean_merged"]
             ok = ok and po["all_ok"]

@@ -208,6 +208,12 @@ jfft_status jfft_solve_batch(jfft_cell_t cell, const double *macro_strains, doub
      slots whose loop stopped (FP64: the owed update; mixed: the next
      refinement sweep, or the end); writes the group's slot states to
      `states` (host, batch ints) if not NULL.  Synchronises the stream.
+   jfft_slots_run: chunks of PCG iterations (the captured graph's depth when
+     graph replay is on, else 2) with the bookkeeping of jfft_slots_step,
+     until at least one slot has finished, no slot runs, or max_ms (>= 0)
+     of wall time have passed, checked after each chunk; writes the states
+     like jfft_slots_step.  For serving loops: the host wakes only to harvest,
+     or every max_ms to admit arrivals.
    jfft_slot_harvest: post-processing of a finished slot as in jfft_solve:
      u_dev (device out [d][N], mean-free fluctuation, or NULL),
      sigma_dev (device out [d*][2^d][N] or NULL), sigma_bar (host out d*),
@@ -216,6 +222,7 @@ jfft_status jfft_solve_batch(jfft_cell_t cell, const double *macro_strains, doub
 jfft_status jfft_slot_admit(jfft_cell_t group, int slot, const double *E_dev, double nu,
                             const double *macro_strain, double tol, int maxit);
 jfft_status jfft_slots_step(jfft_cell_t group, int iterations, int *states);
+jfft_status jfft_slots_run(jfft_cell_t group, double max_ms, int *states);
 jfft_status jfft_slot_harvest(jfft_cell_t group, int slot, double *u_dev, double *sigma_dev,
                               double *sigma_bar, jfft_report *report);
 

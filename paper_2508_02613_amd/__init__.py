@@ -64,6 +64,7 @@ _SIGS = {
                                    C.POINTER(_Report)]),
     "jfft_slot_admit": (C.c_int, [_vp, C.c_int, _vp, C.c_double, _dp, C.c_double, C.c_int]),
     "jfft_slots_step": (C.c_int, [_vp, C.c_int, C.POINTER(C.c_int)]),
+    "jfft_slots_run": (C.c_int, [_vp, C.c_double, C.POINTER(C.c_int)]),
     "jfft_slot_harvest": (C.c_int, [_vp, C.c_int, _vp, _vp, _dp, C.POINTER(_Report)]),
     "jfft_set_graph_iterations": (C.c_int, [_vp, C.c_int]),
     "jfft_set_tunables": (C.c_int, [_vp, C.POINTER(_Tunables)]),
@@ -375,6 +376,13 @@ class Cell:
         the slot states (SLOT_FREE / SLOT_RUNNING / SLOT_FINISHED) as an array."""
         st = (C.c_int * self.batch)()
         _check(self._lib.jfft_slots_step(self._h, int(iterations), st))
+        return np.array(st[:], dtype=np.int32)
+
+    def slots_run(self, max_ms=2.0):
+        """Chunks of PCG iterations until a slot finishes, none runs, or
+        max_ms have passed (jfft_slots_run); returns the slot states."""
+        st = (C.c_int * self.batch)()
+        _check(self._lib.jfft_slots_run(self._h, float(max_ms), st))
         return np.array(st[:], dtype=np.int32)
 
     def slot_harvest(self, slot, want_u=True, want_sigma=False):

@@ -1548,6 +1548,31 @@ jfft_status slots_step(jfft_cell_s *c, int iters, int *states) {
   return JFFT_OK;
 }
 
+// Chunks of PCG iterations (the captured graph's depth, else 2) until a slot
+// finishes, none runs, or max_ms of wall time have passed (checked after
+// each chunk): a serving loop then wakes only when there is something to
+// harvest, or to admit arrivals at that interval.
+jfft_status slots_run(jfft_cell_s *c, double max_ms, int *states) {
+  if (!(max_ms >= 0.0)) return fail(JFFT_E_INVALID, "max_ms must be >= 0");
+  TRY(slots_init(c));
+  const int chunk = c->tun.graph_iters > 0 ? c->tun.graph_iters : 2;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    bool running = false;
+    for (int s : c->slot_state) running = running || s == SLOT_RUNNING;
+    if (!running) break;
+    TRY(slots_step(c, chunk, nullptr));
+    bool finished = false;
+    for (int s : c->slot_state) finished = finished || s == SLOT_FINISHED;
+    if (finished) break;
+    if (std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() >= max_ms)
+      break;
+  }
+  if (states)
+    for (int i = 0; i < c->B; ++i) states[i] = c->slot_state[i];
+  return JFFT_OK;
+}
+
 jfft_status slot_harvest(jfft_cell_s *c, int slot, double *u_out, double *sigma_dev,
                          double *sigma_bar, jfft_report *rep) {
   if (slot < 0 || slot >= c->B) return fail(JFFT_E_INVALID, "slot out of range");
@@ -2197,6 +2222,11 @@ jfft_status jfft_slot_admit(jfft_cell_t c, int slot, const double *E_dev, double
 jfft_status jfft_slots_step(jfft_cell_t c, int iterations, int *states) {
   if (!c) return fail(JFFT_E_INVALID, "NULL cell");
   return slots_step(c, iterations, states);
+}
+
+jfft_status jfft_slots_run(jfft_cell_t c, double max_ms, int *states) {
+  if (!c) return fail(JFFT_E_INVALID, "NULL cell");
+  return slots_run(c, max_ms, states);
 }
 
 jfft_status jfft_slot_harvest(jfft_cell_t c, int slot, double *u_dev, double *sigma_dev,

@@ -27,11 +27,12 @@ gets the same C_eff alone and in the mix.  Only marshalling and scheduling
 happen here: every step of a solve runs in the library's kernels.
 
 SlotServer batches below handle granularity: one group handle per grid
-shape whose cells are slots (jfft_slot_admit / jfft_slots_step /
+shape whose cells are slots (jfft_slot_admit / jfft_slots_run /
 jfft_slot_harvest).  A driver thread per active shape admits arrived
 requests of its shape into free slots (six per request) between chunks of
-PCG iterations, runs a chunk for every running slot, and harvests the load
-cases that stopped; a request is done when its six slots are.  A request
+PCG iterations, lets the library run chunks for every running slot until
+one finishes (or a polling interval passes), and harvests the load cases
+that stopped; a request is done when its six slots are.  A request
 thus joins the running group at the next chunk boundary instead of waiting
 for the group to drain, and leaves as soon as its own solves stop.
 """
@@ -284,16 +285,17 @@ class SlotServer:
     slots_per_group: requests a group holds at once (6 slots each), or a
     function of the grid shape that returns it; the group's device bytes
     count against budget_bytes like any handle, and a shape waits for memory
-    like a worker does in Server.  chunk: PCG
-    iterations between admission and harvest points (the captured graph
-    depth when graph_iterations > 0)."""
+    like a worker does in Server.  A driver runs its group's iterations in
+    the library (jfft_slots_run, chunks of the captured graph depth) until a
+    load case finishes or poll_ms have passed, so it wakes only to harvest or
+    to admit arrivals."""
 
     def __init__(self, budget_bytes=64 << 30, precision=MIXED, pc=PC_GREEN_JACOBI, tol=1e-8,
-                 maxit=20000, graph_iterations=8, nu=0.3, slots_per_group=4, chunk=None,
+                 maxit=20000, graph_iterations=8, nu=0.3, slots_per_group=4, poll_ms=2.0,
                  autotune=False):
         self.tol, self.maxit, self.nu = tol, maxit, nu
         self.slots_per_group = slots_per_group
-        self.chunk = chunk or max(2, graph_iterations)
+        self.poll_ms = poll_ms
         self.pool = HandlePool(budget_bytes, precision, pc, graph_iterations, nu, autotune)
         self.precision = precision
 
@@ -310,7 +312,7 @@ class SlotServer:
         drivers = {}         # shape -> Thread
         lock = threading.Lock()
         errors = []
-        chunks = {"n": 0, "slots": 0}
+        wakes = {"n": 0, "slots": 0}
         t0 = time.perf_counter()
         spg = self.slots_per_group
 
@@ -351,10 +353,10 @@ class SlotServer:
                                 cell.slot_admit(s, E, self.nu, eye[g], tol=self.tol,
                                                 maxit=self.maxit)
                                 owner[s] = (r, g)
-                        states = cell.slots_step(self.chunk)
+                        states = cell.slots_run(self.poll_ms)
                         with lock:
-                            chunks["n"] += 1
-                            chunks["slots"] += sum(o is not None for o in owner)
+                            wakes["n"] += 1
+                            wakes["slots"] += sum(o is not None for o in owner)
                         for s in np.nonzero(states == cell.SLOT_FINISHED)[0]:
                             r, g = owner[s]
                             _, sbar, rep, _ = cell.slot_harvest(int(s), want_u=False)
@@ -410,8 +412,8 @@ class SlotServer:
             "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
             "mean_latency_ms": float(lat.mean() * 1e3),
             "offered_rate": rate,
-            "chunks": chunks["n"],
-            "mean_busy_slots_per_chunk": chunks["slots"] / max(1, chunks["n"]),
+            "driver_wakeups": wakes["n"],
+            "mean_busy_slots_per_wakeup": wakes["slots"] / max(1, wakes["n"]),
             "handles_created": self.pool.created,
             "handles_evicted": self.pool.evicted,
             "all_ok": all(r.status == "ok" for r in requests),

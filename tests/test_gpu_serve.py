@@ -98,7 +98,7 @@ def test_slot_server_results_equal_alone(precision, budget_groups):
     srv.close()
     say(f"  {stats}")
     assert stats["all_ok"] and 0 < stats["max_rel_res_true"] <= 1.5e-8
-    assert stats["chunks"] > 0 and stats["mean_busy_slots_per_chunk"] > 0
+    assert stats["driver_wakeups"] > 0 and stats["mean_busy_slots_per_wakeup"] > 0
     for r in reqs:
         Ca, reps = pkg.effective_stiffness(r.E, nu=0.3, tol=1e-8, precision=precision)
         assert [x.iters for x in reps] == r.iters, (r.rid, r.iters)

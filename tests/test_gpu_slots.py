@@ -37,13 +37,18 @@ def _solo(pkg, shape, prec, E, macro, tun, tol, maxit):
     return out
 
 
-@pytest.mark.parametrize("shape,prec,graph", [((40, 48), "FP64", 8), ((40, 48), "MIXED", 8),
-                                              ((16, 18, 20), "FP64", 0),
-                                              ((16, 18, 20), "MIXED", 16)])
-def test_slots_match_solo_solves(shape, prec, graph):
+@pytest.mark.parametrize("shape,prec,graph,run", [((40, 48), "FP64", 8, False),
+                                                  ((40, 48), "MIXED", 8, False),
+                                                  ((16, 18, 20), "FP64", 0, False),
+                                                  ((16, 18, 20), "MIXED", 16, False),
+                                                  ((40, 48), "MIXED", 4, True),
+                                                  ((16, 18, 20), "FP64", 0, True)])
+def test_slots_match_solo_solves(shape, prec, graph, run):
     """Seven cells through a group of three slots: two admitted at once, one
     a chunk later, the rest as slots free up; each harvested result (u,
-    sigma field, sigma_bar, iteration count) equals the solo solve bitwise."""
+    sigma field, sigma_bar, iteration count) equals the solo solve bitwise.
+    run: the library loops the chunks until a slot finishes (jfft_slots_run)
+    instead of one call per chunk."""
     import torch
 
     pkg = _pkg()
@@ -57,7 +62,8 @@ def test_slots_match_solo_solves(shape, prec, graph):
     if graph:
         grp.set_graph_iterations(graph)
     tun = grp.tunables()
-    say(f"slots {shape} {prec} graph {graph}: {ncell} cells through {B} slots, tunables {tun}")
+    say(f"slots {shape} {prec} graph {graph} run {run}: {ncell} cells through {B} slots, "
+        f"tunables {tun}")
     pending = list(range(ncell))
     owner = [None] * B
     results = {}
@@ -67,7 +73,7 @@ def test_slots_match_solo_solves(shape, prec, graph):
     pending = pending[2:]
     steps = 0
     while len(results) < ncell:
-        states = grp.slots_step(8)
+        states = grp.slots_run(5.0) if run else grp.slots_step(8)
         steps += 1
         assert steps < 2000
         for s in range(B):

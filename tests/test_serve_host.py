@@ -81,6 +81,13 @@ class FakeGroup:
                     self.state[s] = self.SLOT_FINISHED
         return np.array(self.state)
 
+    def slots_run(self, max_ms=2.0):
+        for _ in range(8):  # a few chunks, or until a slot finishes
+            st = self.slots_step(4)
+            if (st == self.SLOT_FINISHED).any() or not (st == self.SLOT_RUNNING).any():
+                break
+        return np.array(self.state)
+
     def slot_harvest(self, slot, want_u=True, want_sigma=False):
         assert self.state[slot] == self.SLOT_FINISHED
         rid, g = self.tag[slot]
@@ -149,7 +156,7 @@ def test_slot_server_schedules_every_request(fake, rate):
     for r in reqs:
         assert r.iters == [5 + (r.rid * 7) % 23 + g for g in range(6)]
     assert st["requests"] == 40 and st["all_ok"]
-    assert 0 < st["mean_busy_slots_per_chunk"] <= 12
+    assert 0 < st["mean_busy_slots_per_wakeup"] <= 12
     assert st["handles_created"] == 3          # one group per shape, reused
     assert FakeGroup.live == 0
 
