@@ -18,7 +18,7 @@ six solves, one per unit macro strain (Sec. 5).  The server
 * merges requests of one grid shape that are already waiting into one group
   launch (up to `max_merge` requests, 6 cells each);
 * optionally (autotune) gives each new handle the launch parameters that
-  tune.autotune() measured for its shape and size (tz per shape only, so
+  tune.autotune() measured for its shape and size (tile shapes per shape only, so
   merging never changes a request's results).
 
 Each cell's results are bitwise independent of what else is in its group or
