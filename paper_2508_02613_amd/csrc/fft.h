@@ -330,6 +330,77 @@ __device__ __forceinline__ void lds_fft_lines(typename CxT<Real>::T *buf, const 
     lds_fft<Real, INV, NPT, NT>(buf, pl, W, W, 1, tw, 1, false);
 }
 
+// The x passes' layout: W rows (a run-time count) of a compile-time length
+// L, row c at buf[c * (L + 1) + i], twiddles of the 2L-point table at
+// stride 2.  Same stages and arithmetic as lds_fft with i_fastest.
+template <typename Real, int R, bool INV, int NPT, int NT, int L, int P>
+__device__ __forceinline__ void stockham_stage_rows_ct(typename CxT<Real>::T *buf, int W,
+                                                       const typename CxT<Real>::T *tw) {
+  using C = typename CxT<Real>::T;
+  constexpr int M = L / R;
+  constexpr int SC = L + 1;
+  constexpr int MB = (NPT + R - 1) / R;
+  constexpr int STEP = L / (P * R);
+  const int nb = M * W;
+  C v[MB][R];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int f = (int)threadIdx.x + b * NT;
+    const int c = f / M, i = f % M;
+    if (f < nb) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = buf[i + r * M + c * SC];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int f = (int)threadIdx.x + b * NT;
+    if (f < nb) {
+      const int c = f / M, i = f % M;
+      const int ip = i / P, k = i % P;
+      if (P > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C t = tw[(r * k * STEP) * 2];
+          if (INV) t.y = -t.y;
+          v[b][r] = cmul(v[b][r], t);
+        }
+      }
+      Dft<Real, R, INV>::run(v[b]);
+      const int j = ip * P * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[j + r * P + c * SC] = v[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename Real, bool INV, int NPT, int NT, int L, int P = 1>
+__device__ __forceinline__ void lds_fft_rows_ct(typename CxT<Real>::T *buf, int W,
+                                                const typename CxT<Real>::T *tw) {
+  if constexpr (P < L) {
+    constexpr int R = ct_radix(L / P);
+    stockham_stage_rows_ct<Real, R, INV, NPT, NT, L, P>(buf, W, tw);
+    lds_fft_rows_ct<Real, INV, NPT, NT, L, P * R>(buf, W, tw);
+  }
+}
+
+// W rows of the x passes: the compile-time transform for the common half
+// lengths, else the plan's.
+template <typename Real, bool INV, int NPT = MaxPt<Real>::value, int NT = FFT_THREADS>
+__device__ __forceinline__ void lds_fft_rows(typename CxT<Real>::T *buf, const FftPlan &pl,
+                                             int W, const typename CxT<Real>::T *tw) {
+  if (pl.L == 128)
+    lds_fft_rows_ct<Real, INV, NPT, NT, 128>(buf, W, tw);
+  else if (pl.L == 256)
+    lds_fft_rows_ct<Real, INV, NPT, NT, 256>(buf, W, tw);
+  else if (pl.L == 64)
+    lds_fft_rows_ct<Real, INV, NPT, NT, 64>(buf, W, tw);
+  else
+    lds_fft<Real, INV, NPT, NT>(buf, pl, W, 1, pl.L + 1, tw, 2, true);
+}
+
 // Half-spectrum layout, tile-major: [d][nz][ntx][ny][TW] complex, where the
 // mx = nx/2 + 1 bins of an x row are cut into ntx tiles of TW = 8 bins.  A
 // y-pass tile (component, z, x-tile) is then one contiguous block, the x
@@ -475,7 +546,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xfwd(XArgs<Real> a) {
     buf[fr * sc + (f - fr * m)] = z;
   }
   __syncthreads();
-  lds_fft<Real, false>(buf, a.plan, RB, 1, sc, tw, 2, true);
+  lds_fft_rows<Real, false>(buf, a.plan, RB, tw);
   // split X[k] = (Z[k] + conj Z[m-k])/2 - i w^k (Z[k] - conj Z[m-k])/2 (Z
   // indices mod m; k = m is the Nyquist bin), evaluated bin by bin in the
   // order of the tile-major stores: a run of RB x TW consecutive complex
@@ -654,7 +725,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_xinv(XArgs<Real> a) {
     if (two) buf[row * sc + (m - k)] = z1;
   }
   __syncthreads();
-  lds_fft<Real, true>(buf, a.plan, RB, 1, sc, tw, 2, true);
+  lds_fft_rows<Real, true>(buf, a.plan, RB, tw);
 #pragma unroll
   for (int j = 0; j < XP; ++j) {
     const int f = threadIdx.x + j * FFT_THREADS;
