@@ -190,7 +190,11 @@ jfft_status jfft_solve_batch(jfft_cell_t cell, const double *macro_strains, doub
    Slot states (the `states` array): 0 free, 1 running, 2 finished (results
    waiting for jfft_slot_harvest).  While any slot is running or finished,
    calls that act on the whole group (jfft_set_material*, jfft_solve*,
-   operators, power-law and topology calls) fail with JFFT_E_INVALID.
+   operators, power-law and topology calls) and the option setters that
+   would change a running slot's arithmetic (tunables, stopping rule,
+   diagonal method, element, void value, mixed-precision parameters,
+   history, workspace binding) fail with JFFT_E_INVALID;
+   jfft_set_graph_iterations stays allowed (it changes no result).
 
    jfft_slot_admit: material E_dev (device, [N] moduli of this slot's cell),
      Poisson ratio nu (the running slots share the Lame constants: a

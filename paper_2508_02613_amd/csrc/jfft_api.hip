@@ -2128,6 +2128,7 @@ jfft_status jfft_workspace_bytes(jfft_cell_t c, size_t *bytes) {
 }
 
 jfft_status jfft_bind_workspace(jfft_cell_t c, void *dev_ptr, size_t bytes) {
+  if (c && slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   if (!c || !dev_ptr) return fail(JFFT_E_INVALID, "NULL argument");
   if (reinterpret_cast<uintptr_t>(dev_ptr) % 256) return fail(JFFT_E_INVALID, "workspace must be 256-byte aligned");
   const size_t need = layout_workspace(c, nullptr);
@@ -2291,6 +2292,7 @@ jfft_status jfft_jacobi_diag(jfft_cell_t c, double *diag_dev) {
 }
 
 jfft_status jfft_enable_history(jfft_cell_t c, int cap) {
+  if (c && slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   if (!c || cap < 0 || cap > kHistMax) return fail(JFFT_E_INVALID, "history capacity must lie in [0, 4096]");
   c->hist_cap = cap;
   c->drop_graphs();
@@ -2332,6 +2334,7 @@ jfft_status jfft_set_graph_iterations(jfft_cell_t c, int iterations) {
 }
 
 jfft_status jfft_set_tunables(jfft_cell_t c, const jfft_tunables *t) {
+  if (c && slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   if (!c || !t) return fail(JFFT_E_INVALID, "NULL argument");
   if (t->ygrid < 1 || t->ygrid > 65535) return fail(JFFT_E_INVALID, "ygrid must lie in [1, 65535]");
   if (c->dim == 3) {
@@ -2396,6 +2399,7 @@ jfft_status jfft_kernel_stats(jfft_cell_t c, int i, const char **name, long *lau
 }
 
 jfft_status jfft_set_stop_rule(jfft_cell_t c, int rule) {
+  if (c && slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   if (!c || (rule != JFFT_STOP_RELATIVE && rule != JFFT_STOP_ABSOLUTE))
     return fail(JFFT_E_INVALID, "unknown stopping rule");
   c->stop_abs = rule == JFFT_STOP_ABSOLUTE;
@@ -2403,6 +2407,7 @@ jfft_status jfft_set_stop_rule(jfft_cell_t c, int rule) {
 }
 
 jfft_status jfft_set_diag_method(jfft_cell_t c, int method) {
+  if (c && slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   if (!c || (method != JFFT_DIAG_CLOSED_FORM && method != JFFT_DIAG_PROBING))
     return fail(JFFT_E_INVALID, "unknown diagonal method");
   if (c->diag_method != method) c->has_material = false;  // J^1/2 must be formed again
@@ -2411,6 +2416,7 @@ jfft_status jfft_set_diag_method(jfft_cell_t c, int method) {
 }
 
 jfft_status jfft_set_element(jfft_cell_t c, int element) {
+  if (c && slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   if (!c || (element != JFFT_ELEM_QUAD && element != JFFT_ELEM_TRI))
     return fail(JFFT_E_INVALID, "unknown element");
   if (element == JFFT_ELEM_TRI && c->dim != 2)
@@ -2424,18 +2430,21 @@ jfft_status jfft_set_element(jfft_cell_t c, int element) {
 }
 
 jfft_status jfft_set_void_value(jfft_cell_t c, double value) {
+  if (c && slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   if (!c || !(value > 0.0) || !std::isfinite(value)) return fail(JFFT_E_INVALID, "void value must be positive");
   c->void_value = value;
   return JFFT_OK;
 }
 
 jfft_status jfft_set_mixed_inner_cap(jfft_cell_t c, int cap) {
+  if (c && slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   if (!c || cap < 0) return fail(JFFT_E_INVALID, "the inner iteration cap must be >= 0");
   c->inner_cap = cap;
   return JFFT_OK;
 }
 
 jfft_status jfft_set_mixed_continue(jfft_cell_t c, int on, double reduction) {
+  if (c && slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   if (!c || (on != 0 && on != 1) || !(reduction > 0.0 && reduction < 1.0))
     return fail(JFFT_E_INVALID, "on must be 0 or 1 and reduction in (0, 1)");
   c->mixed_continue = on == 1;
@@ -2444,6 +2453,7 @@ jfft_status jfft_set_mixed_continue(jfft_cell_t c, int on, double reduction) {
 }
 
 jfft_status jfft_set_mixed_params(jfft_cell_t c, double inner_tol, int max_outer) {
+  if (c && slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   if (!c || !(inner_tol > 0.0 && inner_tol < 1.0) || max_outer < 1)
     return fail(JFFT_E_INVALID, "inner_tol must lie in (0, 1) and max_outer >= 1");
   c->inner_tol = inner_tol;

@@ -130,6 +130,11 @@ def test_slot_states_and_errors():
         grp.solve_batch(np.zeros((2, 3)))                # whole-group call while busy
     with pytest.raises(pkg.JfftError):
         grp.set_material(np.stack([E, E]), nu=0.3)
+    with pytest.raises(pkg.JfftError):
+        grp.set_tunables(xrows=4)                        # would regroup a running slot's sums
+    with pytest.raises(pkg.JfftError):
+        grp.set_stop_rule(absolute=True)
+    grp.set_graph_iterations(4)                          # changes no result: allowed
     # a homogeneous cell stops at once
     grp.slot_admit(0, np.ones(shape), 0.3, [0.0, 1.0, 0.0], tol=1e-8)
     for _ in range(500):
