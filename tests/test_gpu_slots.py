@@ -152,3 +152,63 @@ def test_slot_states_and_errors():
     assert np.array_equal(u[1].cpu().numpy(), u1.cpu().numpy())
     assert np.array_equal(sbar[1], s1) and reps[1].iters == r1.iters
     grp.close()
+
+
+@pytest.mark.parametrize("shape,prec,pc,element,absolute", [
+    ((36, 40), "FP64", "PC_GREEN", "tri", True),
+    ((36, 40), "MIXED", "PC_JACOBI", "quad", False),
+    ((12, 16, 18), "MIXED", "PC_GREEN", "quad", True)])
+def test_slots_options_match_solo(shape, prec, pc, element, absolute):
+    """The group's options apply to its slots as to a solo cell: other
+    preconditioners (Green alone, Jacobi alone), the triangle element and
+    the paper's absolute stopping rule; four cells through two slots, each
+    bitwise equal to the solo solve with the same options."""
+    import torch
+
+    pkg = _pkg()
+    P, PC = getattr(pkg, prec), getattr(pkg, pc)
+    dim = len(shape)
+    ds = dim * (dim + 1) // 2
+    Es = [ji.grf_field(shape, 10.0 ** (1 + k % 2), seed=70 + k, ell=0.2) for k in range(4)]
+    macros = np.random.default_rng(11).uniform(-1, 1, (4, ds))
+    tol = 1e-10 if absolute else 1e-9
+
+    def configure(c):
+        c.set_stop_rule(absolute=absolute)
+
+    grp = pkg.Cell(shape, precision=P, pc=PC, batch=2, stream=torch.cuda.Stream(),
+                   element=element)
+    grp.set_graph_iterations(8)
+    configure(grp)
+    tun = grp.tunables()
+    owner, pending, results, steps = [None, None], list(range(4)), {}, 0
+    while len(results) < 4:
+        for s in range(2):
+            if owner[s] is None and pending:
+                k = pending.pop(0)
+                grp.slot_admit(s, Es[k], 0.3, macros[k], tol=tol, maxit=20000)
+                owner[s] = k
+        st = grp.slots_run(5.0)
+        steps += 1
+        assert steps < 5000
+        for s in range(2):
+            if st[s] == grp.SLOT_FINISHED:
+                u, sbar, rep, _ = grp.slot_harvest(s)
+                results[owner[s]] = (u.cpu().numpy(), sbar, rep)
+                owner[s] = None
+    grp.close()
+    for k in range(4):
+        c = pkg.Cell(shape, precision=P, pc=PC, element=element)
+        configure(c)
+        c.set_tunables(tz=tun["tz"], tiles2d=tun["tiles2d"], xrows=tun["xrows"],
+                       fused_control=tun["fused_control"])
+        c.set_material(Es[k], nu=0.3)
+        us, ss, rs, _ = c.solve(macros[k], tol=tol, maxit=20000)
+        us = us.cpu().numpy()
+        c.close()
+        u, sbar, rep = results[k]
+        say(f"{shape} {prec} {pc} {element} abs={absolute} cell {k}: iters {rep.iters} "
+            f"(solo {rs.iters}) status {rep.status}")
+        assert rep.status == rs.status == "ok"
+        assert rep.iters == rs.iters
+        assert np.array_equal(u, us) and np.array_equal(sbar, ss)
