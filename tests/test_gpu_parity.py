@@ -370,3 +370,34 @@ def test_mixed_refinement_continued_vs_restarted(case):
         assert err <= 1e-6
         assert np.abs(sbar - ref.sigma_bar).max() <= 1e-7 * np.abs(ref.sigma_bar).max()
     assert out[True][2].iters <= out[False][2].iters + 2
+
+
+@pytest.mark.parametrize("shape", [(128, 128), (128, 8, 16), (8, 128, 16), (16, 8, 128),
+                                   (512, 8, 8), (8, 512, 8), (64, 256)])
+def test_precond_parity_compile_time_lengths(shape):
+    """Every transform length the FFT passes run through a compile-time plan
+    (y and last-axis passes: 128, 256, 512 points; x passes: half lengths
+    64, 128, 256), on each axis it can occur on, FP64 and the FP32
+    preconditioner of a mixed cell, element-wise against the oracle's
+    Green-Jacobi M^-1 (on t = J^-1/2 M^-1 r, whose rounding bound is
+    relative to the transformed field: 1e-12 in FP64, 1e-5 in FP32)."""
+    pkg = _pkg()
+    dim = len(shape)
+    E = ji.grf_field(shape, 1e3, seed=5, ell=0.2)
+    r = np.random.default_rng(9).standard_normal((dim,) + shape)
+    dg, _ = oracle.jacobi_diag(E, LAM, MU)
+    zr, _ = oracle.precond(3, r, diag=dg, G=oracle.green(shape, LAM, MU))
+    jh = 1.0 / np.sqrt(dg)
+    tr = zr / jh
+    for prec in (pkg.FP64, pkg.MIXED):
+        cell = pkg.Cell(shape, precision=prec, pc=pkg.PC_GREEN_JACOBI)
+        cell.set_material(E, nu=0.3)
+        outs = [("fp64", cell.apply_precond(r).cpu().numpy(), 1e-12)]
+        if prec == pkg.MIXED:
+            outs.append(("fp32", cell.apply_precond(r, fp32=True).cpu().numpy(), 1e-5))
+        cell.close()
+        for name, z, tol in outs:
+            t = z / jh
+            err = float(np.abs(t - tr).max() / np.abs(tr).max())
+            say(f"precond {shape} precision {prec} {name}: max |t - t_oracle| / max |t| = {err:.2e}")
+            assert err <= tol
