@@ -247,9 +247,10 @@ jfft_status jfft_set_graph_iterations(jfft_cell_t cell, int iterations);
             may differ in the last bits between settings;
      ygrid: persistent blocks of the y FFT pass per launch (all components
             and cells; 1..65535);
-     tiles2d: 16 x 16 element tiles per block of the 2D stiffness kernel
-            (1 or 2; 0 restores the default, two in FP32 and one in FP64;
-            3D ignores it).  Like tz it regroups the p.q partial sums;
+     tiles2d: output nodes per block of the 2D stiffness kernel: 1 = 16 x 16,
+            2 = 16 wide x 32 high, 3 = 32 wide x 16, 4 = 32 x 32 (0 restores
+            the default, 2 in FP32 and 1 in FP64; 3D ignores it).  Like tz
+            it regroups the p.q partial sums;
      xrows: grid rows per block of the x FFT passes, a power of two; values
             above the most that fit in LDS are clamped to it (0 restores the
             default, the most that fit).  It regroups the ||r||^2 partial

@@ -108,7 +108,7 @@ struct Tunables {
   int tz = 32;          // z planes per stiffness block (3D)
   int ygrid = 2048;     // persistent blocks of the y pass (all components and cells)
   int graph_iters = 0;  // iterations per captured graph (0: launch kernels directly)
-  int tiles2d = 0;      // 16 x 16 tiles per 2D stiffness block (1 or 2; 0: by precision)
+  int tiles2d = 0;      // 2D stiffness block shape (1..4, see jfft_tunables; 0: by precision)
   int xrows = 0;        // rows per block of the x passes (power of two; 0: the most that fit)
   int fused_control = 0;  // CG scalar steps in the last block of their producers (0: own launches)
 };
@@ -382,17 +382,24 @@ size_t layout_workspace(jfft_cell_s *c, unsigned char *base) {
 }
 
 // Output-node tile of the stiffness kernels (x and y edge) and the tile count of a grid.
-int stencil_tile_x(int dim) { return dim == 3 ? TX3 : TILE; }
-// 2D: tiles per block from the tunable, else two in FP32 and one in FP64
-// (measured best on the 512^2 groups)
+// 2D block shapes (the tiles2d tunable): 1 = 16 x 16 nodes, 2 = 16 wide x 32,
+// 3 = 32 wide x 16, 4 = 32 x 32.
+// Code 0 stands for the precision's default (measured best on the 512^2
+// groups).
+int resolve_tiles2d(bool fp64, int tiles2d) {
+  return tiles2d ? tiles2d : (fp64 ? default_tiles2d<double>() : default_tiles2d<float>());
+}
+int stencil_tile_x(int dim, bool fp64, int tiles2d = 0) {
+  return dim == 3 ? TX3 : (resolve_tiles2d(fp64, tiles2d) >= 3 ? 2 * TILE : TILE);
+}
 int tiles2d_of(const jfft_cell_s *c, bool fp64);
 int stencil_tile_y(int dim, bool fp64, int tiles2d = 0) {
   if (dim == 3) return TY3;
-  if (tiles2d == 0) return fp64 ? ty2<double>() : ty2<float>();
-  return tiles2d * TILE;
+  const int t = resolve_tiles2d(fp64, tiles2d);
+  return (t == 2 || t == 4) ? 2 * TILE : TILE;
 }
 long long stencil_tiles(int dim, int nx, int ny, bool fp64, int tiles2d = 0) {
-  const int tx = stencil_tile_x(dim), ty = stencil_tile_y(dim, fp64, tiles2d);
+  const int tx = stencil_tile_x(dim, fp64, tiles2d), ty = stencil_tile_y(dim, fp64, tiles2d);
   return (long long)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
 }
 
@@ -596,7 +603,7 @@ bool loop_precision(const jfft_cell_s *c, bool fp64) { return fp64 == (c->prec =
 
 int tiles2d_of(const jfft_cell_s *c, bool fp64) {
   if (c->tun.tiles2d && loop_precision(c, fp64)) return c->tun.tiles2d;
-  return (fp64 ? ty2<double>() : ty2<float>()) / TILE;
+  return fp64 ? default_tiles2d<double>() : default_tiles2d<float>();
 }
 
 long long stencil_blocks_per_cell(jfft_cell_s *c, bool fp64) {
@@ -611,7 +618,8 @@ jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a, int cel
   const int kid = MODE == SM_CG ? KID_STIFF_CG : (MODE == SM_APPLY ? KID_STIFF_APPLY : KID_STIFF_COMB);
   const GridDev &g = c->g;
   const int tt = c->dim == 2 ? tiles2d_of(c, sizeof(Real) == 8) : 0;
-  const int tx = stencil_tile_x(c->dim), ty = stencil_tile_y(c->dim, sizeof(Real) == 8, tt);
+  const int tx = stencil_tile_x(c->dim, sizeof(Real) == 8, tt),
+            ty = stencil_tile_y(c->dim, sizeof(Real) == 8, tt);
   dim3 gr((g.nx + tx - 1) / tx, (g.ny + ty - 1) / ty, a.nbz * cells);
   if (c->nl) {
     // the power-law tangent (3D cells, checked when the material is set);
@@ -627,15 +635,19 @@ jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a, int cel
   } else if (c->dim == 3) {
     LAUNCH(c, kid, (k_stiffness3d<Real, MODE, false><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
   } else if (c->elem == JFFT_ELEM_TRI) {
-    if (tt == 2)
-      LAUNCH(c, kid, (k_stiffness2d<Real, MODE, true, 2><<<gr, STENCIL_THREADS, 0, c->stream>>>(a)));
-    else
-      LAUNCH(c, kid, (k_stiffness2d<Real, MODE, true, 1><<<gr, STENCIL_THREADS, 0, c->stream>>>(a)));
+    switch (tt) {
+      case 2: LAUNCH(c, kid, (k_stiffness2d<Real, MODE, true, 2, TILE><<<gr, STENCIL_THREADS, 0, c->stream>>>(a))); break;
+      case 3: LAUNCH(c, kid, (k_stiffness2d<Real, MODE, true, 1, 2 * TILE><<<gr, STENCIL_THREADS, 0, c->stream>>>(a))); break;
+      case 4: LAUNCH(c, kid, (k_stiffness2d<Real, MODE, true, 2, 2 * TILE><<<gr, STENCIL_THREADS, 0, c->stream>>>(a))); break;
+      default: LAUNCH(c, kid, (k_stiffness2d<Real, MODE, true, 1, TILE><<<gr, STENCIL_THREADS, 0, c->stream>>>(a))); break;
+    }
   } else {
-    if (tt == 2)
-      LAUNCH(c, kid, (k_stiffness2d<Real, MODE, false, 2><<<gr, STENCIL_THREADS, 0, c->stream>>>(a)));
-    else
-      LAUNCH(c, kid, (k_stiffness2d<Real, MODE, false, 1><<<gr, STENCIL_THREADS, 0, c->stream>>>(a)));
+    switch (tt) {
+      case 2: LAUNCH(c, kid, (k_stiffness2d<Real, MODE, false, 2, TILE><<<gr, STENCIL_THREADS, 0, c->stream>>>(a))); break;
+      case 3: LAUNCH(c, kid, (k_stiffness2d<Real, MODE, false, 1, 2 * TILE><<<gr, STENCIL_THREADS, 0, c->stream>>>(a))); break;
+      case 4: LAUNCH(c, kid, (k_stiffness2d<Real, MODE, false, 2, 2 * TILE><<<gr, STENCIL_THREADS, 0, c->stream>>>(a))); break;
+      default: LAUNCH(c, kid, (k_stiffness2d<Real, MODE, false, 1, TILE><<<gr, STENCIL_THREADS, 0, c->stream>>>(a))); break;
+    }
   }
   return JFFT_OK;
 }
@@ -2346,7 +2358,7 @@ jfft_status jfft_set_tunables(jfft_cell_t c, const jfft_tunables *t) {
     if (tiles * nbz > c->npart) return fail(JFFT_E_INVALID, "tz too small for the partial-sum buffer");
     c->tun.tz = t->tz;
   }
-  if (t->tiles2d < 0 || t->tiles2d > 2) return fail(JFFT_E_INVALID, "tiles2d must be 0, 1 or 2");
+  if (t->tiles2d < 0 || t->tiles2d > 4) return fail(JFFT_E_INVALID, "tiles2d must lie in [0, 4]");
   if (t->xrows < 0 || (t->xrows & (t->xrows - 1)) != 0)
     return fail(JFFT_E_INVALID, "xrows must be 0 or a power of two");
   c->tun.ygrid = t->ygrid;

@@ -23,13 +23,18 @@ constexpr int TILE = 16;           // output nodes per tile edge
 constexpr int ETILE = TILE + 1;    // elements per tile edge (with halo)
 constexpr int NTILE = TILE + 2;    // nodes per tile edge (with halo)
 constexpr int STENCIL_THREADS = 384;  // 6 wavefronts (2D kernel)
-// Output rows of a 2D block: 16 x 16 tiles stacked in y, two in FP32 (twice
-// the loads in flight per thread; three measured slower), one in FP64 (a
-// two-tile FP64 block's 46 KB of LDS cuts occupancy to 3 blocks per CU,
-// 8 % slower).
+// Default shape of a 2D block (the tiles2d codes of the tunables: 1 = 16 x
+// 16 output nodes, 2 = 16 wide x 32, 3 = 32 wide x 16, 4 = 32 x 32): in FP32
+// one row of 32 x 16 (whole 128-byte rows; 5-7 % faster than 16 x 32 on the
+// 512^2 groups, which beat 16 x 16 by 13 %), in FP64 16 x 16 (a larger FP64
+// block's LDS cuts occupancy to 3 blocks per CU, 8 % slower).
 template <typename Real>
-constexpr int ty2() {
-  return (sizeof(Real) == 8 ? 1 : 2) * TILE;
+constexpr int default_tiles2d() {
+  return sizeof(Real) == 8 ? 1 : 3;
+}
+template <typename Real>
+constexpr int ty2() {  // rows of the default block
+  return TILE;
 }
 // 3D kernel: 16 x 14 output nodes, 17 x 15 elements, 18 x 16 node planes.
 // Rows of 16 output nodes start on 64-byte boundaries (FP32; 128 in FP64),
@@ -1311,21 +1316,24 @@ __device__ __forceinline__ void elem_tri2(const Real (&u)[2][4], Real Elam, Real
   }
 }
 
-// One block: TILE x TY2 output nodes (ty2: one or two 16 x 16 tiles stacked
-// in y, which then share a halo row), 384 threads; every thread owns up to R
+// One block: TX x TY2 output nodes (TX 16 or 32 wide, TY2 one or two 16-node
+// rows of tiles, which then share a halo row), 384 threads; every thread owns up to R
 // nodes of the halo-extended tile, R elements and R outputs (index tid +
 // r * 384).  All loads of its nodes (and element moduli) are issued before
 // any store, so a thread keeps up to a dozen loads in flight.  Loads use clamped,
 // valid addresses and are masked where the value is committed.
 // TRI: the pixel is two linear triangles (elem_tri2) instead of a bilinear
 // quadrilateral.
-template <typename Real, int MODE, bool TRI = false, int TT = ty2<Real>() / TILE>
+template <typename Real, int MODE, bool TRI = false, int TT = 1, int TX = TILE>
 __global__ void __launch_bounds__(STENCIL_THREADS)
     k_stiffness2d(StencilArgs<Real> a) {
-  constexpr int TY2 = TT * TILE;  // TT tiles of 16 x 16 per block (a tunable tile shape)
-  constexpr int NNODE2 = NTILE * (TY2 + 2);  // nodes with halo
-  constexpr int NELEM2 = ETILE * (TY2 + 1);  // elements with halo
-  constexpr int NOUT2 = TILE * TY2;          // outputs
+  // TT rows of 16-node tiles, TX (16 or 32) nodes wide: a tunable tile shape
+  // (32-wide rows are whole 128-byte lines in FP32)
+  constexpr int TY2 = TT * TILE;
+  constexpr int ETX = TX + 1, NTX = TX + 2;  // elements / nodes per row with halo
+  constexpr int NNODE2 = NTX * (TY2 + 2);  // nodes with halo
+  constexpr int NELEM2 = ETX * (TY2 + 1);  // elements with halo
+  constexpr int NOUT2 = TX * TY2;          // outputs
   __shared__ Real P[2][NNODE2];
   __shared__ Real Y[8][NELEM2];
   __shared__ double red[8];
@@ -1337,7 +1345,7 @@ __global__ void __launch_bounds__(STENCIL_THREADS)
   const int lb = lbg - cell * per_cell;
   shift_args(a, cell);
   if (MODE == SM_CG && a.st->done) return;
-  const int x0 = (lb % gridDim.x) * TILE, y0 = (lb / gridDim.x) * TY2;
+  const int x0 = (lb % gridDim.x) * TX, y0 = (lb / gridDim.x) * TY2;
   const int nx = a.nx, ny = a.ny;
   const long long N = a.N;
   bool first = false;
@@ -1356,7 +1364,7 @@ __global__ void __launch_bounds__(STENCIL_THREADS)
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int e = min(tid + r * STENCIL_THREADS, NELEM2 - 1);
-    const int gex = x0 - 1 + e % ETILE, gey = y0 - 1 + e / ETILE;
+    const int gex = x0 - 1 + e % ETX, gey = y0 - 1 + e / ETX;
     const Real v = a.E[(long long)wrapi(gex, nx) + (long long)nx * wrapi(gey, ny)];
     Ee[r] = (gex < nx && gey < ny) ? v : (Real)0;
   }
@@ -1369,11 +1377,11 @@ __global__ void __launch_bounds__(STENCIL_THREADS)
     const int idx = tid + r * STENCIL_THREADS;
     valid[r] = idx < NNODE2;
     const int ci = min(idx, NNODE2 - 1);
-    const int lx = ci % NTILE, ly = ci / NTILE;
+    const int lx = ci % NTX, ly = ci / NTX;
     const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
     const int wx = wrapi(gx, nx), wy = wrapi(gy, ny);
     node[r] = (long long)wx + (long long)nx * wy;
-    owned[r] = valid[r] && lx >= 1 && lx <= TILE && ly >= 1 && ly <= TY2 && gx < nx && gy < ny;
+    owned[r] = valid[r] && lx >= 1 && lx <= TX && ly >= 1 && ly <= TY2 && gx < nx && gy < ny;
     par[r] = (wx & 1) | ((wy & 1) << 1);
   }
   Real v[R][2];
@@ -1432,11 +1440,11 @@ __global__ void __launch_bounds__(STENCIL_THREADS)
   for (int r = 0; r < R; ++r) {
     const int e = tid + r * STENCIL_THREADS;
     if (e < NELEM2) {
-      const int exl = e % ETILE, eyl = e / ETILE;
+      const int exl = e % ETX, eyl = e / ETX;
       Real uv[2][4], yv[2][4];
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const int li = (eyl + (c >> 1)) * NTILE + exl + (c & 1);
+        const int li = (eyl + (c >> 1)) * NTX + exl + (c & 1);
         uv[0][c] = P[0][li];
         uv[1][c] = P[1][li];
       }
@@ -1456,17 +1464,17 @@ __global__ void __launch_bounds__(STENCIL_THREADS)
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int o = tid + r * STENCIL_THREADS;
-    const int oxl = o % TILE, oyl = o / TILE;
+    const int oxl = o % TX, oyl = o / TX;
     const int gnx = x0 + oxl, gny = y0 + oyl;
     if (o < NOUT2 && gnx < nx && gny < ny) {
-      const int e00 = oyl * ETILE + oxl;
+      const int e00 = oyl * ETX + oxl;
       Real q[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
-        q[i] = Y[3 * 2 + i][e00] + Y[2 * 2 + i][e00 + 1] + Y[1 * 2 + i][e00 + ETILE] +
-               Y[0 * 2 + i][e00 + ETILE + 1];
+        q[i] = Y[3 * 2 + i][e00] + Y[2 * 2 + i][e00 + 1] + Y[1 * 2 + i][e00 + ETX] +
+               Y[0 * 2 + i][e00 + ETX + 1];
       const long long nd = (long long)gnx + (long long)nx * gny;
-      const int li = (oyl + 1) * NTILE + oxl + 1;
+      const int li = (oyl + 1) * NTX + oxl + 1;
       if (MODE == SM_COMB) {
         const int pr = (gnx & 1) | ((gny & 1) << 1);
         if (pr == a.comb_off) a.diag[a.comb_comp * N + nd] = q[a.comb_comp];

@@ -4,7 +4,8 @@ Tuned by timing a fixed number of PCG iterations on a synthetic smooth
 material of the target shape:
 
 * the tile shapes: tz, the z planes per block of the 3D stiffness kernel,
-  tiles2d, the 16 x 16 tiles per block of the 2D one, and xrows, the grid
+  tiles2d, the block shape of the 2D one (16 or 32 nodes wide and high),
+  and xrows, the grid
   rows per block of the x FFT passes; and fused_control, whether the CG
   scalar steps run in the last block of their producer kernels.  They set
   how the p.q, ||r||^2 and r.z partial sums are grouped, so they are chosen
@@ -125,7 +126,7 @@ def autotune(shape, batch=1, precision=MIXED, pc=PC_GREEN_JACOBI, iters=24, use_
                 for tz in sorted({t for t in (4, 8, 16, 32, 64) if t <= nz} | {cur["tz"]}):
                     trial(dict(tiles, tz=tz), cur["ygrid"], 0)
             else:
-                for t2 in (1, 2):
+                for t2 in (1, 2, 3, 4):
                     trial(dict(tiles, tiles2d=t2), cur["ygrid"], 0)
             tiles = dict(best[1])
             xr = cur["xrows"]
