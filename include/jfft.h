@@ -249,11 +249,16 @@ jfft_status jfft_set_graph_iterations(jfft_cell_t cell, int iterations);
             and cells; 1..65535);
      tiles2d: output nodes per block of the 2D stiffness kernel: 1 = 16 x 16,
             2 = 16 wide x 32 high, 3 = 32 wide x 16, 4 = 32 x 32 (0 restores
-            the default, 2 in FP32 and 1 in FP64; 3D ignores it).  Like tz
+            the default, 3 in FP32 and 1 in FP64; 3D ignores it).  Like tz
             it regroups the p.q partial sums;
      xrows: grid rows per block of the x FFT passes, a power of two; values
             above the most that fit in LDS are clamped to it (0 restores the
             default, the most that fit).  It regroups the ||r||^2 partial
+            sums;
+     tiles3d: output nodes per block of the 3D stiffness kernel: 1 = 16
+            wide x 14 high, 2 = 32 x 6 (whole 128-byte rows in FP32; the
+            power-law tangent always runs 1).  0 restores the default, 2 in
+            FP32 and 1 in FP64; 2D ignores it.  It regroups the p.q partial
             sums;
      fused_control: 0 (default) launches a single-block kernel for each
             scalar step of a PCG iteration (alpha, the stopping test, beta);
@@ -265,17 +270,18 @@ jfft_status jfft_set_graph_iterations(jfft_cell_t cell, int iterations);
             block's L2 and costs more than a launch on large grids; it can
             pay on small ones.  The two sum the partials in different fixed
             orders.
-   tiles2d and xrows act on the kernels of the PCG loop's precision (the
-   FP32 kernels of a mixed-precision cell; its FP64 residual and
+   tiles2d, tiles3d and xrows act on the kernels of the PCG loop's precision
+   (the FP32 kernels of a mixed-precision cell; its FP64 residual and
    post-processing kernels keep the defaults).  jfft_get_tunables reports
-   the values in effect (tiles2d and xrows as resolved for the grid and the
-   loop's precision).  A change drops any captured graph. */
+   the values in effect (tiles2d, tiles3d and xrows as resolved for the
+   grid and the loop's precision).  A change drops any captured graph. */
 typedef struct {
   int tz;
   int ygrid;
   int tiles2d;
   int xrows;
   int fused_control;
+  int tiles3d;
 } jfft_tunables;
 jfft_status jfft_set_tunables(jfft_cell_t cell, const jfft_tunables *t);
 jfft_status jfft_get_tunables(jfft_cell_t cell, jfft_tunables *t);

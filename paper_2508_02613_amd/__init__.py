@@ -36,7 +36,7 @@ _dp = C.POINTER(C.c_double)
 
 class _Tunables(C.Structure):
     _fields_ = [("tz", C.c_int), ("ygrid", C.c_int), ("tiles2d", C.c_int), ("xrows", C.c_int),
-                ("fused_control", C.c_int)]
+                ("fused_control", C.c_int), ("tiles3d", C.c_int)]
 
 
 class _Report(C.Structure):
@@ -407,9 +407,11 @@ class Cell:
         t = _Tunables()
         _check(self._lib.jfft_get_tunables(self._h, C.byref(t)))
         return {"tz": int(t.tz), "ygrid": int(t.ygrid), "tiles2d": int(t.tiles2d),
-                "xrows": int(t.xrows), "fused_control": int(t.fused_control)}
+                "xrows": int(t.xrows), "fused_control": int(t.fused_control),
+                "tiles3d": int(t.tiles3d)}
 
-    def set_tunables(self, tz=None, ygrid=None, tiles2d=None, xrows=None, fused_control=None):
+    def set_tunables(self, tz=None, ygrid=None, tiles2d=None, xrows=None, fused_control=None,
+                     tiles3d=None):
         """Launch parameters (None keeps the current value; see jfft_tunables)."""
         cur = self.tunables()
         t = _Tunables(int(tz if tz is not None else cur["tz"]),
@@ -417,7 +419,8 @@ class Cell:
                       int(tiles2d if tiles2d is not None else cur["tiles2d"]),
                       int(xrows if xrows is not None else cur["xrows"]),
                       int(fused_control if fused_control is not None
-                          else cur["fused_control"]))
+                          else cur["fused_control"]),
+                      int(tiles3d if tiles3d is not None else cur["tiles3d"]))
         _check(self._lib.jfft_set_tunables(self._h, C.byref(t)))
 
     def set_graph_iterations(self, iterations):

@@ -109,6 +109,7 @@ struct Tunables {
   int ygrid = 2048;     // persistent blocks of the y pass (all components and cells)
   int graph_iters = 0;  // iterations per captured graph (0: launch kernels directly)
   int tiles2d = 0;      // 2D stiffness block shape (1..4, see jfft_tunables; 0: by precision)
+  int tiles3d = 0;      // 3D stiffness block shape of the FP32 kernels (1..2; 0: the default)
   int xrows = 0;        // rows per block of the x passes (power of two; 0: the most that fit)
   int fused_control = 0;  // CG scalar steps in the last block of their producers (0: own launches)
 };
@@ -383,32 +384,40 @@ size_t layout_workspace(jfft_cell_s *c, unsigned char *base) {
 
 // Output-node tile of the stiffness kernels (x and y edge) and the tile count of a grid.
 // 2D block shapes (the tiles2d tunable): 1 = 16 x 16 nodes, 2 = 16 wide x 32,
-// 3 = 32 wide x 16, 4 = 32 x 32.
-// Code 0 stands for the precision's default (measured best on the 512^2
-// groups).
-int resolve_tiles2d(bool fp64, int tiles2d) {
-  return tiles2d ? tiles2d : (fp64 ? default_tiles2d<double>() : default_tiles2d<float>());
+// 3 = 32 wide x 16, 4 = 32 x 32.  3D block shapes (the tiles3d tunable): 1 =
+// 16 x 14, 2 = 32 x 6.  Code 0 stands for the precision's
+// default (measured best on the 512^2 groups and the 256^3 cell).
+int resolve_tiles(int dim, bool fp64, int code) {
+  if (code) return code;
+  if (dim == 3) return fp64 ? default_tiles3d<double>() : default_tiles3d<float>();
+  return fp64 ? default_tiles2d<double>() : default_tiles2d<float>();
 }
-int stencil_tile_x(int dim, bool fp64, int tiles2d = 0) {
-  return dim == 3 ? TX3 : (resolve_tiles2d(fp64, tiles2d) >= 3 ? 2 * TILE : TILE);
+int stencil_tile_x(int dim, bool fp64, int code = 0) {
+  const int t = resolve_tiles(dim, fp64, code);
+  if (dim == 3) return t == 2 ? Geo3<2>::TX : Geo3<1>::TX;
+  return t >= 3 ? 2 * TILE : TILE;
 }
-int tiles2d_of(const jfft_cell_s *c, bool fp64);
-int stencil_tile_y(int dim, bool fp64, int tiles2d = 0) {
-  if (dim == 3) return TY3;
-  const int t = resolve_tiles2d(fp64, tiles2d);
+int stencil_tile_y(int dim, bool fp64, int code = 0) {
+  const int t = resolve_tiles(dim, fp64, code);
+  if (dim == 3) return t == 2 ? Geo3<2>::TY : Geo3<1>::TY;
   return (t == 2 || t == 4) ? 2 * TILE : TILE;
 }
-long long stencil_tiles(int dim, int nx, int ny, bool fp64, int tiles2d = 0) {
-  const int tx = stencil_tile_x(dim, fp64, tiles2d), ty = stencil_tile_y(dim, fp64, tiles2d);
+long long stencil_tiles(int dim, int nx, int ny, bool fp64, int code = 0) {
+  const int tx = stencil_tile_x(dim, fp64, code), ty = stencil_tile_y(dim, fp64, code);
   return (long long)((nx + tx - 1) / tx) * ((ny + ty - 1) / ty);
+}
+// the most tiles any block shape of the dimension gives
+long long stencil_tiles_max(int dim, int nx, int ny) {
+  long long m = 0;
+  for (int code = 1; code <= (dim == 3 ? 2 : 4); ++code)
+    m = std::max(m, stencil_tiles(dim, nx, ny, false, code));
+  return m;
 }
 
 long long max_partials(jfft_cell_s *c) {
   const GridDev &g = c->g;
   long long mx = 4 * 1024;  // vector kernels
-  // the most blocks any tile shape gives (one 16 x 16 tile per 2D block)
-  const long long tiles = std::max(stencil_tiles(c->dim, g.nx, g.ny, true, c->dim == 2 ? 1 : 0),
-                                   stencil_tiles(c->dim, g.nx, g.ny, false, c->dim == 2 ? 1 : 0));
+  const long long tiles = stencil_tiles_max(c->dim, g.nx, g.ny);
   mx = std::max(mx, tiles * ((g.nz + 2 - 1) / 2));  // smallest z chunk allowed (tz >= 2)
   const long long rows = (long long)c->dim * g.ny * g.nz;
   mx = std::max(mx, rows);  // x passes at one row per block (the smallest xrows)
@@ -547,15 +556,22 @@ bool cubic_cells(const jfft_cell_s *c) {
   return c->dim == 3 && c->g.ihx == c->g.ihy && c->g.ihx == c->g.ihz;
 }
 
-// Blocks of the 3D CG stiffness kernel that the device runs at once, and per CU.
+// Blocks of the 3D CG stiffness kernel (the precision's default block shape)
+// that the device runs at once, and per CU.
 hipError_t stiffness_slots(int device, bool fp64, bool cubic, int *slots, int *per_cu_out) {
   int cus = 0, per_cu = 0;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return e;
-  const void *k = fp64 ? (cubic ? reinterpret_cast<const void *>(k_stiffness3d<double, SM_CG, true>)
-                                : reinterpret_cast<const void *>(k_stiffness3d<double, SM_CG, false>))
-                       : (cubic ? reinterpret_cast<const void *>(k_stiffness3d<float, SM_CG, true>)
-                                : reinterpret_cast<const void *>(k_stiffness3d<float, SM_CG, false>));
+  const bool wide = (fp64 ? default_tiles3d<double>() : default_tiles3d<float>()) == 2;
+  const void *k =
+      fp64 ? (wide ? (cubic ? reinterpret_cast<const void *>(k_stiffness3d<double, SM_CG, true, 0, 2>)
+                            : reinterpret_cast<const void *>(k_stiffness3d<double, SM_CG, false, 0, 2>))
+                   : (cubic ? reinterpret_cast<const void *>(k_stiffness3d<double, SM_CG, true>)
+                            : reinterpret_cast<const void *>(k_stiffness3d<double, SM_CG, false>)))
+           : (wide ? (cubic ? reinterpret_cast<const void *>(k_stiffness3d<float, SM_CG, true, 0, 2>)
+                            : reinterpret_cast<const void *>(k_stiffness3d<float, SM_CG, false, 0, 2>))
+                   : (cubic ? reinterpret_cast<const void *>(k_stiffness3d<float, SM_CG, true>)
+                            : reinterpret_cast<const void *>(k_stiffness3d<float, SM_CG, false>)));
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, STENCIL3_THREADS, 0);
   *slots = std::max(1, cus * per_cu);
   *per_cu_out = std::max(1, per_cu);
@@ -569,17 +585,20 @@ hipError_t stiffness_slots(int device, bool fp64, bool cubic, int *slots, int *p
 //   and a block marches tz + 1 element layers, so the time is modelled as
 //   rounds * (tz + 1), minimised over 4 <= tz <= 64 (ties: the larger tz,
 //   which re-reads fewer halo planes).
-// * Several blocks per CU (FP32): blocks that start together stay in step
-//   over a long march and contend for the same units at the same time; a
-//   march of 16 planes measured best on 256^3 (6: 0.469 ms, 8 and 12: 0.460,
-//   16: 0.448; 32 and longer slower), shortened while the launch would leave
-//   slots empty.
-int pick_tz(const GridDev &g, int slots, int per_cu) {
-  const long long tiles = stencil_tiles(3, g.nx, g.ny, true);
+// * Several blocks per CU: blocks that start together stay in step over a
+//   long march and contend for the same units at the same time.  Measured
+//   on 256^3 (FP32, ms per launch): 16 x 14 blocks 0.469 (tz 6), 0.460 (8
+//   and 12), 0.448 (16), slower from 32 on; 32 x 6 blocks, which hold fewer
+//   rows and re-read the two halo planes relatively more, 0.383 (8), 0.346
+//   (16), 0.341 (20), 0.338 (32), 0.347 (64).  So 16 or 32 planes by the
+//   block shape, shortened while the launch would leave slots empty.
+int pick_tz(const GridDev &g, bool fp64, int slots, int per_cu) {
+  const long long tiles = stencil_tiles(3, g.nx, g.ny, fp64);
   const int lo = std::min(4, g.nz);
   auto blocks = [&](int tz) { return tiles * ((g.nz + tz - 1) / tz); };
   if (per_cu > 1) {
-    int tz = std::min(16, g.nz);
+    const int shape = fp64 ? default_tiles3d<double>() : default_tiles3d<float>();
+    int tz = std::min(shape == 2 ? 32 : 16, g.nz);
     while (tz > lo && blocks(tz) < slots) --tz;
     return tz;
   }
@@ -606,18 +625,30 @@ int tiles2d_of(const jfft_cell_s *c, bool fp64) {
   return fp64 ? default_tiles2d<double>() : default_tiles2d<float>();
 }
 
+// 3D: shape 2 exists for the linear-elastic kernels only.
+int tiles3d_of(const jfft_cell_s *c, bool fp64) {
+  if (c->nl) return 1;
+  if (c->tun.tiles3d && loop_precision(c, fp64)) return c->tun.tiles3d;
+  return fp64 ? default_tiles3d<double>() : default_tiles3d<float>();
+}
+
+// The resolved block shape of the stiffness kernels of a precision.
+int tiles_of(const jfft_cell_s *c, bool fp64) {
+  return c->dim == 3 ? tiles3d_of(c, fp64) : tiles2d_of(c, fp64);
+}
+
 long long stencil_blocks_per_cell(jfft_cell_s *c, bool fp64) {
   const GridDev &g = c->g;
   const int tz = c->dim == 3 ? std::min(c->tun.tz, g.nz) : 1;
   const int nbz = c->dim == 3 ? (g.nz + tz - 1) / tz : 1;
-  return stencil_tiles(c->dim, g.nx, g.ny, fp64, c->dim == 2 ? tiles2d_of(c, fp64) : 0) * nbz;
+  return stencil_tiles(c->dim, g.nx, g.ny, fp64, tiles_of(c, fp64)) * nbz;
 }
 
 template <typename Real, int MODE>
 jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a, int cells) {
   const int kid = MODE == SM_CG ? KID_STIFF_CG : (MODE == SM_APPLY ? KID_STIFF_APPLY : KID_STIFF_COMB);
   const GridDev &g = c->g;
-  const int tt = c->dim == 2 ? tiles2d_of(c, sizeof(Real) == 8) : 0;
+  const int tt = tiles_of(c, sizeof(Real) == 8);
   const int tx = stencil_tile_x(c->dim, sizeof(Real) == 8, tt),
             ty = stencil_tile_y(c->dim, sizeof(Real) == 8, tt);
   dim3 gr((g.nx + tx - 1) / tx, (g.ny + ty - 1) / ty, a.nbz * cells);
@@ -630,10 +661,19 @@ jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a, int cel
     }
     return fail(JFFT_E_INVALID, "the power-law combs run in FP64 only");
   }
-  if (c->dim == 3 && cubic_cells(c)) {
-    LAUNCH(c, kid, (k_stiffness3d<Real, MODE, true><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
-  } else if (c->dim == 3) {
-    LAUNCH(c, kid, (k_stiffness3d<Real, MODE, false><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
+  if (c->dim == 3) {
+    const bool cubic = cubic_cells(c);
+    if (tt == 2) {
+      if (cubic)
+        LAUNCH(c, kid, (k_stiffness3d<Real, MODE, true, 0, 2><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
+      else
+        LAUNCH(c, kid, (k_stiffness3d<Real, MODE, false, 0, 2><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
+      return JFFT_OK;
+    }
+    if (cubic)
+      LAUNCH(c, kid, (k_stiffness3d<Real, MODE, true><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
+    else
+      LAUNCH(c, kid, (k_stiffness3d<Real, MODE, false><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
   } else if (c->elem == JFFT_ELEM_TRI) {
     switch (tt) {
       case 2: LAUNCH(c, kid, (k_stiffness2d<Real, MODE, true, 2, TILE><<<gr, STENCIL_THREADS, 0, c->stream>>>(a))); break;
@@ -2064,7 +2104,7 @@ jfft_status create_impl(int dim, const int n[3], const double len[3], jfft_preci
     int slots = 0, per_cu = 0;
     e = stiffness_slots(c->device, prec == JFFT_FP64, cubic_cells(c), &slots, &per_cu);
     if (e == hipSuccess) {
-      c->tun.tz = pick_tz(g, slots, per_cu);
+      c->tun.tz = pick_tz(g, prec == JFFT_FP64, slots, per_cu);
       if ((long long)((g.nz + c->tun.tz - 1) / c->tun.tz) * batch > 65535) {
         delete c;
         return fail(JFFT_E_INVALID, "batch too large for this grid (stiffness grid z-dimension above 65535)");
@@ -2353,16 +2393,18 @@ jfft_status jfft_set_tunables(jfft_cell_t c, const jfft_tunables *t) {
     if (t->tz < std::min(2, c->g.nz) || t->tz > c->g.nz)
       return fail(JFFT_E_INVALID, "tz must lie in [2, nz]");
     const long long nbz = (c->g.nz + t->tz - 1) / t->tz;
-    const long long tiles = stencil_tiles(3, c->g.nx, c->g.ny, true);
+    const long long tiles = stencil_tiles_max(3, c->g.nx, c->g.ny);
     if (nbz * c->B > 65535) return fail(JFFT_E_INVALID, "tz too small for this group (grid z-dimension)");
     if (tiles * nbz > c->npart) return fail(JFFT_E_INVALID, "tz too small for the partial-sum buffer");
     c->tun.tz = t->tz;
   }
   if (t->tiles2d < 0 || t->tiles2d > 4) return fail(JFFT_E_INVALID, "tiles2d must lie in [0, 4]");
+  if (t->tiles3d < 0 || t->tiles3d > 2) return fail(JFFT_E_INVALID, "tiles3d must lie in [0, 2]");
   if (t->xrows < 0 || (t->xrows & (t->xrows - 1)) != 0)
     return fail(JFFT_E_INVALID, "xrows must be 0 or a power of two");
   c->tun.ygrid = t->ygrid;
   c->tun.tiles2d = c->dim == 2 ? t->tiles2d : 0;
+  c->tun.tiles3d = c->dim == 3 ? t->tiles3d : 0;
   c->tun.xrows = t->xrows;
   c->tun.fused_control = t->fused_control ? 1 : 0;
   c->drop_graphs();
@@ -2374,6 +2416,7 @@ jfft_status jfft_get_tunables(jfft_cell_t c, jfft_tunables *t) {
   t->tz = c->dim == 3 ? std::min(c->tun.tz, c->g.nz) : 1;
   t->ygrid = c->tun.ygrid;
   t->tiles2d = c->dim == 2 ? tiles2d_of(c, c->prec == JFFT_FP64) : 0;
+  t->tiles3d = c->dim == 3 ? tiles3d_of(c, c->prec == JFFT_FP64) : 0;
   const int rb = c->prec == JFFT_FP64 ? x_rows_per_block<double>(c->g.nx / 2)
                                       : x_rows_per_block<float>(c->g.nx / 2);
   t->xrows = c->tun.xrows && c->tun.xrows < rb ? c->tun.xrows : rb;

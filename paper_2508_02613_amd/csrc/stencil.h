@@ -36,18 +36,38 @@ template <typename Real>
 constexpr int ty2() {  // rows of the default block
   return TILE;
 }
-// 3D kernel: 16 x 14 output nodes, 17 x 15 elements, 18 x 16 node planes.
-// Rows of 16 output nodes start on 64-byte boundaries (FP32; 128 in FP64),
-// so every store covers whole sectors and no sector is written by two blocks.
-constexpr int TX3 = 16, TY3 = 14;
-constexpr int EX3 = TX3 + 1, EY3 = TY3 + 1;
-constexpr int NX3 = TX3 + 2, NY3 = TY3 + 2;
-constexpr int NELEM3 = EX3 * EY3;           // 255
-constexpr int NNODE3 = NX3 * NY3;           // 288
-constexpr int STENCIL3_THREADS = 256;       // 4 wavefronts: one element per thread
-constexpr int NSTRIP3 = NNODE3 - STENCIL3_THREADS;  // 32 nodes beyond one per thread
-static_assert(TX3 == 16 && NY3 == 16 && NSTRIP3 == 32,
-              "the 3D kernel maps threads to nodes with shifts by 4");
+// 3D block shapes (the tiles3d codes of the tunables), both on four
+// wavefronts.  Code 1: 16 x 14 output nodes, 17 x 15 elements, 18 x 16 node
+// planes.  Code 2: 32 x 6 output nodes, 33 x 7 elements, 34 x 8
+// node planes, so that a row of output nodes is one whole 128-byte line: a
+// wavefront's load or store of a plane touches two whole lines instead of
+// four halves, which more than pays for the larger halo (measured at 256^3:
+// 0.44 ms per launch for code 1, 0.35 for code 2; a 32 x 10 block on six
+// wavefronts took 0.51).  Rows start on 64-byte boundaries (code 1, FP32;
+// 128 in FP64) or 128-byte ones (code 2), so every store covers whole
+// sectors and no sector is written by two blocks.  A block has one thread
+// per node of columns 1..TX of a node plane (TX x NY = threads) and at
+// least one per element; columns 0 and NX - 1 are loaded by 2 NY further
+// threads.
+template <int SHAPE>
+struct Geo3 {
+  static constexpr int TX = SHAPE == 2 ? 32 : 16, TY = SHAPE == 2 ? 6 : 14;
+  static constexpr int EX = TX + 1, EY = TY + 1;
+  static constexpr int NX = TX + 2, NY = TY + 2;
+  static constexpr int NELEM = EX * EY;  // 255 or 231
+  static constexpr int NNODE = NX * NY;  // 288 or 272
+  static constexpr int NT = TX * NY;     // 256 threads
+  static constexpr int NSTRIP = NNODE - NT;
+  static_assert(NSTRIP == 2 * NY && NELEM <= NT && NT == 256 && (TX & (TX - 1)) == 0,
+                "four wavefronts: one thread per node of columns 1..TX, one per element");
+};
+constexpr int STENCIL3_THREADS = 256;
+// Default 3D block shape of the precision (the power-law tangent has shape 1
+// only).
+template <typename Real>
+constexpr int default_tiles3d() {
+  return sizeof(Real) == 4 ? 2 : 1;
+}
 // Register budget of the 3D kernel (waves per SIMD = blocks per CU): three
 // blocks per CU in FP32 (<= 168 VGPRs; at 128 it spills), one in FP64 (at
 // 256 VGPRs it spills, which costs more than the second block gains).
@@ -922,23 +942,27 @@ __device__ __forceinline__ void fused_ctrl(CgState *st, const double *part, int 
 // barriers per layer.  In CG mode p.q is accumulated as the element energies
 // u_e . K_e u_e of the elements the block owns (= p^T K p).
 //
-// Geometry: a block owns TX3 x TY3 = 16 x 14 output nodes and evaluates the
-// 17 x 15 elements that touch them, one element per thread (thread 255
-// repeats element 254 and discards it), so a block is exactly four
+// Geometry (Geo3<SHAPE>): a block owns TX x TY output nodes and evaluates
+// the EX x EY elements that touch them, one element per thread (threads past
+// the last element repeat it and discard it).  A block is exactly four
 // wavefronts: one per SIMD, and every SIMD of a CU carries the same element
-// work at any occupancy.  Thread t also holds node (t & 15) + 1, t >> 4 of
-// each 18 x 16 node plane (columns 1..16, which hold every owned node) and,
-// if t < 224, output node (t & 15) + 1, (t >> 4) + 1.  Columns 0 and 17 of
-// a plane are loaded by threads 0..31.
+// work at any occupancy.  Thread t also
+// holds node (t % TX) + 1, t / TX of each NX x NY node plane (columns 1..TX,
+// which hold every owned node) and, if t < TX TY, output node (t % TX) + 1,
+// t / TX + 1.  Columns 0 and NX - 1 of a plane are loaded by threads
+// 0 .. 2 NY - 1.
 // MAT = 1: the tangent of the power-law problem at the Newton iterate a.uk
 // (E holds the phase); a second ring of node planes holds the iterate.
-template <typename Real, int MODE, bool CUBIC = false, int MAT = 0>
-__global__ void __launch_bounds__(STENCIL3_THREADS, (stencil3_waves_per_simd<Real, MAT>()))
+template <typename Real, int MODE, bool CUBIC = false, int MAT = 0, int SHAPE = 1>
+__global__ void __launch_bounds__(Geo3<SHAPE>::NT, (stencil3_waves_per_simd<Real, MAT>()))
     k_stiffness3d(StencilArgs<Real> a) {
-  __shared__ Real P[3][3][NNODE3];               // ring of three node planes of the input vector
-  __shared__ Real U[MAT ? 3 : 1][3][MAT ? NNODE3 : 1];  // MAT: ring of the Newton iterate
-  __shared__ Real Y[24][STENCIL3_THREADS];       // corner contributions of one element layer
-  __shared__ double red[STENCIL3_THREADS / 64];
+  using G = Geo3<SHAPE>;
+  constexpr int NT = G::NT, TX = G::TX, TY = G::TY, EX = G::EX, NX = G::NX, NY = G::NY;
+  static_assert(SHAPE == 1 || MAT == 0, "the power-law tangent has shape 1 only");
+  __shared__ Real P[3][3][G::NNODE];               // ring of three node planes of the input vector
+  __shared__ Real U[MAT ? 3 : 1][3][MAT ? G::NNODE : 1];  // MAT: ring of the Newton iterate
+  __shared__ Real Y[24][NT];                       // corner contributions of one element layer
+  __shared__ double red[NT / 64];
 
   const int tid = threadIdx.x;
   const int nbx = gridDim.x, nby = gridDim.y;
@@ -950,7 +974,7 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, (stencil3_waves_per_simd<Rea
   shift_args(a, cell);
   if (MODE == SM_CG && a.st->done) return;
   const int bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
-  const int x0 = bx * TX3, y0 = by * TY3;
+  const int x0 = bx * TX, y0 = by * TY;
   const int z0 = bz * a.tz;
   const int zend = min(z0 + a.tz, a.nz);
   const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -966,35 +990,36 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, (stencil3_waves_per_simd<Rea
   }
 
   // element (halo-extended layer; beyond the grid: E = 0)
-  const int te = min(tid, NELEM3 - 1);
-  const int exl = te % EX3, eyl = te / EX3;
+  const int te = min(tid, G::NELEM - 1);
+  const int exl = te % EX, eyl = te / EX;
   const int gex = x0 - 1 + exl, gey = y0 - 1 + eyl;
   const bool elem_valid = gex < nx && gey < ny;
-  const bool elem_owned = elem_valid && exl >= 1 && eyl >= 1 && tid < NELEM3;
+  const bool elem_owned = elem_valid && exl >= 1 && eyl >= 1 && tid < G::NELEM;
   const long long exy = (long long)wrapi(gex, nx) + (long long)nx * wrapi(gey, ny);
-  const int lie = eyl * NX3 + exl;  // corner (0, 0) of the element in a node plane
+  const int lie = eyl * NX + exl;  // corner (0, 0) of the element in a node plane
   // output node (ox + 1, oy + 1); its x-y neighbouring elements are e00,
-  // e00 + 1, e00 + EX3 and e00 + EX3 + 1
-  const int ox = tid & 15, oy = tid >> 4;
-  const int e00 = oy * EX3 + ox;
+  // e00 + 1, e00 + EX and e00 + EX + 1
+  const int ox = tid % TX, oy = tid / TX;
+  const int e00 = oy * EX + ox;
   const int gnx = x0 + ox, gny = y0 + oy;
-  const bool node_valid = oy < TY3 && gnx < nx && gny < ny;
+  const bool node_valid = oy < TY && gnx < nx && gny < ny;
   // node slot 0: node (ox + 1, oy) of the plane, global (x0 + ox, y0 - 1 + oy)
-  const int li0 = oy * NX3 + ox + 1;
+  const int li0 = oy * NX + ox + 1;
   const int w0x = wrapi(x0 + ox, nx), w0y = wrapi(y0 - 1 + oy, ny);
   const long long n0xy = (long long)w0x + (long long)nx * w0y;
-  const bool own0 = oy >= 1 && oy <= TY3 && x0 + ox < nx && y0 - 1 + oy < ny;
+  const bool own0 = oy >= 1 && oy <= TY && x0 + ox < nx && y0 - 1 + oy < ny;
   const int par0 = (w0x & 1) | ((w0y & 1) << 1);
   // u is read for every slot-0 node (so that the loads need no branch); a
   // halo row reads its owned neighbour row instead, and discards the value
   const long long u0xy =
-      (long long)w0x + (long long)nx * wrapi(y0 - 1 + min(max(oy, 1), TY3), ny);
-  // node slot 1 (threads 0..31): column 0, then column 17; the other threads
-  // load node (0, 0) again (one cache line per wavefront) and discard it
-  const bool has1 = tid < NSTRIP3;
-  const int s1x = (has1 && (tid >> 4)) ? NX3 - 1 : 0;
-  const int s1y = has1 ? (tid & 15) : 0;
-  const int li1 = s1y * NX3 + s1x;
+      (long long)w0x + (long long)nx * wrapi(y0 - 1 + min(max(oy, 1), TY), ny);
+  // node slot 1 (threads 0 .. 2 NY - 1): column 0, then column NX - 1; the
+  // other threads load node (0, 0) again (one cache line per wavefront) and
+  // discard it
+  const bool has1 = tid < G::NSTRIP;
+  const int s1x = (has1 && tid >= NY) ? NX - 1 : 0;
+  const int s1y = has1 ? tid % NY : 0;
+  const int li1 = s1y * NX + s1x;
   const int w1x = wrapi(x0 - 1 + s1x, nx), w1y = wrapi(y0 - 1 + s1y, ny);
   const long long n1xy = (long long)w1x + (long long)nx * w1y;
   const int par1 = (w1x & 1) | ((w1y & 1) << 1);
@@ -1128,14 +1153,14 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, (stencil3_waves_per_simd<Rea
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
-          for (int i = 0; i < 3; ++i) fbot[i][k] = P[s0][i][lie + (k >> 1) * NX3 + (k & 1)];
+          for (int i = 0; i < 3; ++i) fbot[i][k] = P[s0][i][lie + (k >> 1) * NX + (k & 1)];
 #pragma unroll
         for (int i = 0; i < 3; ++i) face_diffs(fbot[i], fbotF[i]);
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int i = 0; i < 3; ++i) top[i][k] = P[s1][i][lie + (k >> 1) * NX3 + (k & 1)];
+        for (int i = 0; i < 3; ++i) top[i][k] = P[s1][i][lie + (k >> 1) * NX + (k & 1)];
       double en = 0.0;
       // a.lam, a.mu carry the full Gauss weight; the mode form takes half
       elem_hex_modes_cubic_faces<Real, MODE == SM_CG>(fbot, fbotF, top, topF, Ecur, a.clam, a.cmu,
@@ -1157,7 +1182,7 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, (stencil3_waves_per_simd<Rea
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-        const int li = lie + cy * NX3 + cx;
+        const int li = lie + cy * NX + cx;
 #pragma unroll
         for (int i = 0; i < 3; ++i) uv[i][c] = P[cz ? s1 : s0][i][li];
       }
@@ -1167,7 +1192,7 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, (stencil3_waves_per_simd<Rea
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
           const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-          const int li = lie + cy * NX3 + cx;
+          const int li = lie + cy * NX + cx;
 #pragma unroll
           for (int i = 0; i < 3; ++i) kv[i][c] = U[cz ? s1 : s0][i][li];
         }
@@ -1199,7 +1224,7 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, (stencil3_waves_per_simd<Rea
 #pragma unroll
         for (int i = 0; i < 3; ++i)
           qpend[i] = carry[i] + Y[3 * 3 + i][e00] + Y[2 * 3 + i][e00 + 1] +
-                     Y[1 * 3 + i][e00 + EX3] + Y[0 * 3 + i][e00 + EX3 + 1];
+                     Y[1 * 3 + i][e00 + EX] + Y[0 * 3 + i][e00 + EX + 1];
         const long long node = (long long)gnx + (long long)nx * (gny + (long long)ny * ez);
         if (MODE == SM_COMB) {
           const int par = (gnx & 1) | ((gny & 1) << 1) | ((ez & 1) << 2);
@@ -1213,17 +1238,17 @@ __global__ void __launch_bounds__(STENCIL3_THREADS, (stencil3_waves_per_simd<Rea
       }
 #pragma unroll
       for (int i = 0; i < 3; ++i)
-        carry[i] = Y[7 * 3 + i][e00] + Y[6 * 3 + i][e00 + 1] + Y[5 * 3 + i][e00 + EX3] +
-                   Y[4 * 3 + i][e00 + EX3 + 1];
+        carry[i] = Y[7 * 3 + i][e00] + Y[6 * 3 + i][e00 + 1] + Y[5 * 3 + i][e00 + EX] +
+                   Y[4 * 3 + i][e00 + EX + 1];
     }
     __syncthreads();
   }
   flush_q();
   if (MODE == SM_CG) {
-    const double s = block_sum<STENCIL3_THREADS>(acc, red);
+    const double s = block_sum<NT>(acc, red);
     if (tid == 0) a.partial[lb] = s;
     if (a.ctl)
-      fused_ctrl<STENCIL3_THREADS, CTRL_ALPHA>(a.ctl, a.partial, per_cell, a.h, cell, a.cs,
+      fused_ctrl<NT, CTRL_ALPHA>(a.ctl, a.partial, per_cell, a.h, cell, a.cs,
                                                a.parity, red);
   }
 }

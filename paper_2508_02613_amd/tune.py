@@ -4,8 +4,8 @@ Tuned by timing a fixed number of PCG iterations on a synthetic smooth
 material of the target shape:
 
 * the tile shapes: tz, the z planes per block of the 3D stiffness kernel,
-  tiles2d, the block shape of the 2D one (16 or 32 nodes wide and high),
-  and xrows, the grid
+  tiles3d, its block shape (16 x 14 or 32 x 6 nodes), tiles2d, the block shape of the 2D one (16 or 32
+  nodes wide and high), and xrows, the grid
   rows per block of the x FFT passes; and fused_control, whether the CG
   scalar steps run in the last block of their producer kernels.  They set
   how the p.q, ||r||^2 and r.z partial sums are grouped, so they are chosen
@@ -18,7 +18,7 @@ material of the target shape:
 
 Results are kept in a JSON cache (JFFT_TUNE_CACHE, default
 ~/.cache/jfft_mi355x/tunables.json) so each configuration is measured once.
-The search is coordinate-wise (tz or tiles2d, xrows, fused control, then
+The search is coordinate-wise (tz and tiles3d, or tiles2d; xrows, fused control, then
 ygrid, then graph depth), each step keeping the best loop time; the shape-level choice is
 measured on the first group size tuned and reused for the others.  Only marshalling happens here: the timed work
 runs in the library's kernels.
@@ -36,7 +36,7 @@ from . import MIXED, PC_GREEN_JACOBI, Cell, _torch
 _lock = threading.Lock()
 
 # launch parameters that regroup partial sums: chosen per grid shape only
-SHAPE_KEYS = ("tz", "tiles2d", "xrows", "fused_control")
+SHAPE_KEYS = ("tz", "tiles2d", "tiles3d", "xrows", "fused_control")
 
 
 def cache_path() -> str:
@@ -87,8 +87,8 @@ def _time_loop(cell, iters, macro):
 
 def autotune(shape, batch=1, precision=MIXED, pc=PC_GREEN_JACOBI, iters=24, use_cache=True):
     """Launch parameters for a group of `batch` cells of `shape`: returns
-    {"tz", "tiles2d", "xrows", "ygrid", "graph_iterations",
-    "loop_ms_per_iteration"}."""
+    {"tz", "tiles2d", "tiles3d", "xrows", "fused_control", "ygrid",
+    "graph_iterations", "loop_ms_per_iteration"}."""
     shape = tuple(int(s) for s in shape)
     skey = _shape_key(shape, precision, pc)
     gkey = f"{skey}|b{int(batch)}"
@@ -118,13 +118,14 @@ def autotune(shape, batch=1, precision=MIXED, pc=PC_GREEN_JACOBI, iters=24, use_
 
         # tile shapes: fixed per shape (shared by every group size), measured once
         tiles = data.get("shapes", {}).get(skey) if use_cache else None
-        if not isinstance(tiles, dict):
-            tiles = {"tz": cur["tz"], "tiles2d": cur["tiles2d"], "xrows": cur["xrows"],
-                     "fused_control": cur["fused_control"]}
+        if not isinstance(tiles, dict) or any(k not in tiles for k in SHAPE_KEYS):
+            tiles = {k: cur[k] for k in SHAPE_KEYS}
             if dim == 3:
                 nz = shape[0]
                 for tz in sorted({t for t in (4, 8, 16, 32, 64) if t <= nz} | {cur["tz"]}):
                     trial(dict(tiles, tz=tz), cur["ygrid"], 0)
+                tiles = dict(best[1])
+                trial(dict(tiles, tiles3d=3 - tiles["tiles3d"]), cur["ygrid"], 0)
             else:
                 for t2 in (1, 2, 3, 4):
                     trial(dict(tiles, tiles2d=t2), cur["ygrid"], 0)
@@ -161,6 +162,6 @@ def autotune(shape, batch=1, precision=MIXED, pc=PC_GREEN_JACOBI, iters=24, use_
 def apply(cell, params):
     """Apply autotune() results to a cell group."""
     cell.set_tunables(tz=params["tz"], ygrid=params["ygrid"], tiles2d=params.get("tiles2d", 0),
-                      xrows=params.get("xrows", 0),
+                      tiles3d=params.get("tiles3d", 0), xrows=params.get("xrows", 0),
                       fused_control=params.get("fused_control", 0))
     cell.set_graph_iterations(params["graph_iterations"])

@@ -28,7 +28,7 @@ def say(msg):
 
 def _solo(pkg, shape, prec, E, macro, tun, tol, maxit):
     c = pkg.Cell(shape, precision=prec)
-    c.set_tunables(tz=tun["tz"], tiles2d=tun["tiles2d"], xrows=tun["xrows"],
+    c.set_tunables(tz=tun["tz"], tiles2d=tun["tiles2d"], tiles3d=tun["tiles3d"], xrows=tun["xrows"],
                    fused_control=tun["fused_control"])
     c.set_material(E, nu=0.3)
     u, sbar, rep, sig = c.solve(macro, tol=tol, maxit=maxit, want_sigma=True)
@@ -200,7 +200,7 @@ def test_slots_options_match_solo(shape, prec, pc, element, absolute):
     for k in range(4):
         c = pkg.Cell(shape, precision=P, pc=PC, element=element)
         configure(c)
-        c.set_tunables(tz=tun["tz"], tiles2d=tun["tiles2d"], xrows=tun["xrows"],
+        c.set_tunables(tz=tun["tz"], tiles2d=tun["tiles2d"], tiles3d=tun["tiles3d"], xrows=tun["xrows"],
                        fused_control=tun["fused_control"])
         c.set_material(Es[k], nu=0.3)
         us, ss, rs, _ = c.solve(macros[k], tol=tol, maxit=20000)

@@ -35,7 +35,7 @@ def test_autotune_cached_and_result_neutral(shape, batch, tmp_path, monkeypatch)
     say(f"  {p}")
     assert p["ygrid"] >= 1 and p["graph_iterations"] in (0, 8, 16)
     if len(shape) == 3:
-        assert 2 <= p["tz"] <= shape[0]
+        assert 2 <= p["tz"] <= shape[0] and p["tiles3d"] in (1, 2)
     else:
         assert p["tiles2d"] in (1, 2, 3, 4)
     assert p["xrows"] >= 1 and p["xrows"] & (p["xrows"] - 1) == 0
@@ -55,7 +55,7 @@ def test_autotune_cached_and_result_neutral(shape, batch, tmp_path, monkeypatch)
     grp.close()
     for i in range(batch):
         c = pkg.Cell(shape, precision=pkg.MIXED)
-        c.set_tunables(tz=p["tz"], tiles2d=p["tiles2d"], xrows=p["xrows"],
+        c.set_tunables(tz=p["tz"], tiles2d=p["tiles2d"], tiles3d=p["tiles3d"], xrows=p["xrows"],
                        fused_control=p["fused_control"])
         c.set_material(Es[i], nu=0.3)
         ui, si, ri, _ = c.solve(macros[i], tol=1e-8)
@@ -80,8 +80,17 @@ def test_tunables_validation():
         c.set_tunables(xrows=3)
     with pytest.raises(pkg.JfftError):
         c.set_tunables(tiles2d=5)
+    with pytest.raises(pkg.JfftError):
+        c.set_tunables(tiles3d=3)
+    with pytest.raises(pkg.JfftError):
+        c.set_tunables(tiles3d=-1)
     c.set_tunables(tz=8, ygrid=300, xrows=2)
-    assert c.tunables() == {"tz": 8, "ygrid": 300, "tiles2d": 0, "xrows": 2, "fused_control": 0}
+    assert c.tunables() == {"tz": 8, "ygrid": 300, "tiles2d": 0, "xrows": 2, "fused_control": 0,
+                            "tiles3d": 1}
+    c.set_tunables(tiles3d=2)
+    assert c.tunables()["tiles3d"] == 2
+    c.set_tunables(tiles3d=0)
+    assert c.tunables()["tiles3d"] == 1
     c.set_tunables(xrows=1 << 20)  # clamped to the most rows that fit
     assert 2 <= c.tunables()["xrows"] < 1 << 20
     c.close()
@@ -92,15 +101,29 @@ def test_tunables_validation():
     c.set_tunables(tiles2d=0)
     assert c.tunables()["tiles2d"] == 1
     c.close()
+    c = pkg.Cell((16, 16, 16), precision=pkg.MIXED)
+    d3 = c.tunables()["tiles3d"]
+    assert d3 == 2 and c.tunables()["tiles2d"] == 0
+    for t3 in (1, 2):
+        c.set_tunables(tiles3d=t3)
+        assert c.tunables()["tiles3d"] == t3
+    c.set_tunables(tiles3d=0)
+    assert c.tunables()["tiles3d"] == d3
+    c.close()
 
 
 @pytest.mark.parametrize("shape,prec", [((90, 72), "FP64"), ((90, 72), "MIXED"),
-                                        ((30, 20, 18), "FP64")])
+                                        ((30, 20, 18), "FP64"), ((30, 20, 18), "MIXED"),
+                                        ((18, 36, 40), "MIXED"), ((40, 40, 40), "MIXED")])
 def test_tile_shapes_solve_the_same_problem(shape, prec):
-    """Every tile shape (2D block shapes 16 or 32 nodes wide and high, x-pass
-    rows per block, down to one row) gives the same solution up to the regrouping of partial sums:
+    """Every tile shape (2D block shapes 16 or 32 nodes wide and high, 3D
+    blocks of 16 x 14 or 32 x 6 nodes, x-pass rows per block, down
+    to one row) gives the same solution up to the regrouping of partial sums:
     iteration counts within one, fields within the solver tolerance.  The
-    grids leave ragged tiles and blocks in every direction."""
+    grids leave ragged tiles and blocks in every direction (3D shapes are
+    (nz, ny, nx): 18 nodes in x are less than one 32-wide block; the cube
+    runs the cubic form of the 3D element kernel, the others the general
+    one)."""
     pkg = _pkg()
     dim = len(shape)
     E = ji.grf_field(shape, 1e3, seed=3, ell=0.15)
@@ -109,12 +132,14 @@ def test_tile_shapes_solve_the_same_problem(shape, prec):
     c = pkg.Cell(shape, precision=getattr(pkg, prec))
     c.set_material(E, nu=0.3)
     rb = c.tunables()["xrows"]
-    shapes = [(t2, xr) for t2 in ((1, 2, 3, 4) if dim == 2 else (0,)) for xr in (rb, 4, 1)]
-    for t2, xr in shapes:
-        c.set_tunables(tiles2d=t2, xrows=xr)
+    codes = (1, 2, 3, 4) if dim == 2 else (1, 2)
+    key = "tiles2d" if dim == 2 else "tiles3d"
+    shapes = [(t, xr) for t in codes for xr in (rb, 4, 1)]
+    for t, xr in shapes:
+        c.set_tunables(xrows=xr, **{key: t})
         u, sbar, rep, _ = c.solve(macro, tol=1e-10, maxit=5000)
         u = u.cpu().numpy()
-        say(f"{shape} {prec} tiles2d {t2} xrows {xr}: iters {rep.iters} res {rep.rel_res_true:.1e}")
+        say(f"{shape} {prec} {key} {t} xrows {xr}: iters {rep.iters} res {rep.rel_res_true:.1e}")
         assert rep.status == "ok" and rep.rel_res_true <= 1.5e-10
         if ref is None:
             ref = (u, sbar, rep.iters)
