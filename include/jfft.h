@@ -244,7 +244,12 @@ jfft_status jfft_set_graph_iterations(jfft_cell_t cell, int iterations);
 /* Launch parameters that do not change what is computed up to rounding:
      tz:    z planes per block of the 3D stiffness kernel (2..nz; 2D ignores
             it).  It sets how the p.q partial sums are grouped, so results
-            may differ in the last bits between settings;
+            may differ in the last bits between settings.  By default it is
+            chosen from the device's occupancy, the block shape in effect and
+            the material kind (linear or power-law), and re-chosen when the
+            material kind changes; a value other than the one in effect
+            fixes it, and 0 restores (and re-makes) the automatic choice for
+            the block shape in effect;
      ygrid: persistent blocks of the y FFT pass per launch (all components
             and cells; 1..65535);
      tiles2d: output nodes per block of the 2D stiffness kernel: 1 = 16 x 16,
@@ -256,10 +261,11 @@ jfft_status jfft_set_graph_iterations(jfft_cell_t cell, int iterations);
             default, the most that fit).  It regroups the ||r||^2 partial
             sums;
      tiles3d: output nodes per block of the 3D stiffness kernel: 1 = 16
-            wide x 14 high, 2 = 32 x 6 (whole 128-byte rows in FP32; the
-            power-law tangent always runs 1).  0 restores the default, 2 in
-            FP32 and 1 in FP64; 2D ignores it.  It regroups the p.q partial
-            sums;
+            wide x 14 high, 2 = 32 x 6 (whole 128-byte rows in FP32).  The
+            default is 2 for the FP32 linear-elastic kernels and 1 for FP64
+            and the power-law tangent (it follows the material kind); as for
+            tz, a value other than the one in effect fixes it and 0 restores
+            the default; 2D ignores it.  It regroups the p.q partial sums;
      fused_control: 0 (default) launches a single-block kernel for each
             scalar step of a PCG iteration (alpha, the stopping test, beta);
             1 runs each step in the last block to finish of the kernel that

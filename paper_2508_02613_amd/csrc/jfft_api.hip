@@ -112,6 +112,7 @@ struct Tunables {
   int tiles3d = 0;      // 3D stiffness block shape of the FP32 kernels (1..2; 0: the default)
   int xrows = 0;        // rows per block of the x passes (power of two; 0: the most that fit)
   int fused_control = 0;  // CG scalar steps in the last block of their producers (0: own launches)
+  bool tz_auto = true;    // tz follows the material kind and block shape (until set explicitly)
 };
 
 }  // namespace
@@ -556,22 +557,25 @@ bool cubic_cells(const jfft_cell_s *c) {
   return c->dim == 3 && c->g.ihx == c->g.ihy && c->g.ihx == c->g.ihz;
 }
 
-// Blocks of the 3D CG stiffness kernel (the precision's default block shape)
-// that the device runs at once, and per CU.
-hipError_t stiffness_slots(int device, bool fp64, bool cubic, int *slots, int *per_cu_out) {
+// The 3D CG stiffness kernel of a precision, element form (cubic), material
+// kind (mat: the power-law tangent) and block shape.
+template <typename Real>
+const void *stiffness_cg_kernel(bool cubic, bool mat, int shape) {
+  if (mat)
+    return shape == 2 ? reinterpret_cast<const void *>(k_stiffness3d<Real, SM_CG, false, 1, 2>)
+                      : reinterpret_cast<const void *>(k_stiffness3d<Real, SM_CG, false, 1>);
+  if (shape == 2)
+    return cubic ? reinterpret_cast<const void *>(k_stiffness3d<Real, SM_CG, true, 0, 2>)
+                 : reinterpret_cast<const void *>(k_stiffness3d<Real, SM_CG, false, 0, 2>);
+  return cubic ? reinterpret_cast<const void *>(k_stiffness3d<Real, SM_CG, true>)
+               : reinterpret_cast<const void *>(k_stiffness3d<Real, SM_CG, false>);
+}
+
+// Blocks of a 3D CG stiffness kernel that the device runs at once, and per CU.
+hipError_t stiffness_slots(int device, const void *k, int *slots, int *per_cu_out) {
   int cus = 0, per_cu = 0;
   hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (e != hipSuccess) return e;
-  const bool wide = (fp64 ? default_tiles3d<double>() : default_tiles3d<float>()) == 2;
-  const void *k =
-      fp64 ? (wide ? (cubic ? reinterpret_cast<const void *>(k_stiffness3d<double, SM_CG, true, 0, 2>)
-                            : reinterpret_cast<const void *>(k_stiffness3d<double, SM_CG, false, 0, 2>))
-                   : (cubic ? reinterpret_cast<const void *>(k_stiffness3d<double, SM_CG, true>)
-                            : reinterpret_cast<const void *>(k_stiffness3d<double, SM_CG, false>)))
-           : (wide ? (cubic ? reinterpret_cast<const void *>(k_stiffness3d<float, SM_CG, true, 0, 2>)
-                            : reinterpret_cast<const void *>(k_stiffness3d<float, SM_CG, false, 0, 2>))
-                   : (cubic ? reinterpret_cast<const void *>(k_stiffness3d<float, SM_CG, true>)
-                            : reinterpret_cast<const void *>(k_stiffness3d<float, SM_CG, false>)));
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, STENCIL3_THREADS, 0);
   *slots = std::max(1, cus * per_cu);
   *per_cu_out = std::max(1, per_cu);
@@ -591,13 +595,14 @@ hipError_t stiffness_slots(int device, bool fp64, bool cubic, int *slots, int *p
 //   and 12), 0.448 (16), slower from 32 on; 32 x 6 blocks, which hold fewer
 //   rows and re-read the two halo planes relatively more, 0.383 (8), 0.346
 //   (16), 0.341 (20), 0.338 (32), 0.347 (64).  So 16 or 32 planes by the
-//   block shape, shortened while the launch would leave slots empty.
-int pick_tz(const GridDev &g, bool fp64, int slots, int per_cu) {
-  const long long tiles = stencil_tiles(3, g.nx, g.ny, fp64);
+//   block shape, shortened while the launch would leave slots empty.  (The
+//   power-law tangent, two blocks per CU: 0.52 ms at 16 x 14 and 16 planes,
+//   0.59 at 32 planes, 0.61 and 0.67 with 32 x 6 blocks; 200^3, FP32.)
+int pick_tz(const GridDev &g, bool fp64, int shape, int slots, int per_cu) {
+  const long long tiles = stencil_tiles(3, g.nx, g.ny, fp64, shape);
   const int lo = std::min(4, g.nz);
   auto blocks = [&](int tz) { return tiles * ((g.nz + tz - 1) / tz); };
   if (per_cu > 1) {
-    const int shape = fp64 ? default_tiles3d<double>() : default_tiles3d<float>();
     int tz = std::min(shape == 2 ? 32 : 16, g.nz);
     while (tz > lo && blocks(tz) < slots) --tz;
     return tz;
@@ -625,11 +630,40 @@ int tiles2d_of(const jfft_cell_s *c, bool fp64) {
   return fp64 ? default_tiles2d<double>() : default_tiles2d<float>();
 }
 
-// 3D: shape 2 exists for the linear-elastic kernels only.
+// The power-law tangent keeps 16 x 14 blocks unless told otherwise (its two
+// gradient sets leave two blocks per CU, where the wider block loses).
 int tiles3d_of(const jfft_cell_s *c, bool fp64) {
-  if (c->nl) return 1;
   if (c->tun.tiles3d && loop_precision(c, fp64)) return c->tun.tiles3d;
+  if (c->nl) return 1;
   return fp64 ? default_tiles3d<double>() : default_tiles3d<float>();
+}
+
+// z planes per block for the cell's material kind and block shape (see
+// pick_tz), or 0 on a HIP error.
+int auto_tz(const jfft_cell_s *c, hipError_t *err) {
+  const bool fp64 = c->prec == JFFT_FP64;
+  const int shape = tiles3d_of(c, fp64);
+  const bool cubic = cubic_cells(c);
+  const void *k = fp64 ? stiffness_cg_kernel<double>(cubic, c->nl, shape)
+                       : stiffness_cg_kernel<float>(cubic, c->nl, shape);
+  int slots = 0, per_cu = 0;
+  *err = stiffness_slots(c->device, k, &slots, &per_cu);
+  return *err == hipSuccess ? pick_tz(c->g, fp64, shape, slots, per_cu) : 0;
+}
+
+// Re-picks tz after a change of material kind (or when the automatic choice
+// is restored), unless tz was set explicitly (and unless the group would
+// exceed the grid's z-dimension).
+jfft_status refresh_tz(jfft_cell_s *c) {
+  if (c->dim != 3 || !c->tun.tz_auto) return JFFT_OK;
+  hipError_t e = hipSuccess;
+  const int tz = auto_tz(c, &e);
+  if (e != hipSuccess) return fail(JFFT_E_HIP, std::string("occupancy query: ") + hipGetErrorString(e));
+  if (tz != c->tun.tz && (long long)((c->g.nz + tz - 1) / tz) * c->B <= 65535) {
+    c->tun.tz = tz;
+    c->drop_graphs();
+  }
+  return JFFT_OK;
 }
 
 // The resolved block shape of the stiffness kernels of a precision.
@@ -656,7 +690,10 @@ jfft_status launch_stiffness(jfft_cell_s *c, const StencilArgs<Real> &a, int cel
     // the power-law tangent (3D cells, checked when the material is set);
     // Algorithm 2's combs run in FP64 only
     if constexpr (std::is_same<Real, double>::value || MODE != SM_COMB) {
-      LAUNCH(c, kid, (k_stiffness3d<Real, MODE, false, 1><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
+      if (tt == 2)
+        LAUNCH(c, kid, (k_stiffness3d<Real, MODE, false, 1, 2><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
+      else
+        LAUNCH(c, kid, (k_stiffness3d<Real, MODE, false, 1><<<gr, STENCIL3_THREADS, 0, c->stream>>>(a)));
       return JFFT_OK;
     }
     return fail(JFFT_E_INVALID, "the power-law combs run in FP64 only");
@@ -1203,6 +1240,7 @@ jfft_status set_material_impl(jfft_cell_s *c, const double *E_dev, double lam, d
   if (c->nl) {  // back from the power-law material: its captured kernels differ
     c->nl = false;
     c->drop_graphs();
+    TRY(refresh_tz(c));
   }
   // captured iterations carry lambda and mu as kernel arguments; the moduli
   // are read from the workspace, so a new E alone keeps them valid
@@ -1703,6 +1741,7 @@ jfft_status set_material_powerlaw_impl(jfft_cell_s *c, const double *phase_dev, 
   c->lam = K_incl - 2.0 * mu_incl / 3.0;  // Green reference: the inclusion
   c->mu = mu_incl;
   c->nl = true;
+  TRY(refresh_tz(c));
   HIP_TRY(hipStreamSynchronize(c->stream));
   return JFFT_OK;
 }
@@ -2101,10 +2140,9 @@ jfft_status create_impl(int dim, const int n[3], const double len[3], jfft_preci
   hipError_t e = set_smem_attributes();
   if (e == hipSuccess) e = hipGetDevice(&c->device);
   if (e == hipSuccess && dim == 3) {
-    int slots = 0, per_cu = 0;
-    e = stiffness_slots(c->device, prec == JFFT_FP64, cubic_cells(c), &slots, &per_cu);
+    const int tz = auto_tz(c, &e);
     if (e == hipSuccess) {
-      c->tun.tz = pick_tz(g, prec == JFFT_FP64, slots, per_cu);
+      c->tun.tz = tz;
       if ((long long)((g.nz + c->tun.tz - 1) / c->tun.tz) * batch > 65535) {
         delete c;
         return fail(JFFT_E_INVALID, "batch too large for this grid (stiffness grid z-dimension above 65535)");
@@ -2389,26 +2427,36 @@ jfft_status jfft_set_tunables(jfft_cell_t c, const jfft_tunables *t) {
   if (c && slots_busy(c)) return fail(JFFT_E_INVALID, kSlotsBusy);
   if (!c || !t) return fail(JFFT_E_INVALID, "NULL argument");
   if (t->ygrid < 1 || t->ygrid > 65535) return fail(JFFT_E_INVALID, "ygrid must lie in [1, 65535]");
-  if (c->dim == 3) {
+  // tz: 0 restores the automatic choice; a value other than the one in
+  // effect fixes it
+  const bool tz_set = c->dim == 3 && t->tz != 0 && t->tz != std::min(c->tun.tz, c->g.nz);
+  if (tz_set) {
     if (t->tz < std::min(2, c->g.nz) || t->tz > c->g.nz)
-      return fail(JFFT_E_INVALID, "tz must lie in [2, nz]");
+      return fail(JFFT_E_INVALID, "tz must be 0 or lie in [2, nz]");
     const long long nbz = (c->g.nz + t->tz - 1) / t->tz;
     const long long tiles = stencil_tiles_max(3, c->g.nx, c->g.ny);
     if (nbz * c->B > 65535) return fail(JFFT_E_INVALID, "tz too small for this group (grid z-dimension)");
     if (tiles * nbz > c->npart) return fail(JFFT_E_INVALID, "tz too small for the partial-sum buffer");
-    c->tun.tz = t->tz;
   }
   if (t->tiles2d < 0 || t->tiles2d > 4) return fail(JFFT_E_INVALID, "tiles2d must lie in [0, 4]");
   if (t->tiles3d < 0 || t->tiles3d > 2) return fail(JFFT_E_INVALID, "tiles3d must lie in [0, 2]");
   if (t->xrows < 0 || (t->xrows & (t->xrows - 1)) != 0)
     return fail(JFFT_E_INVALID, "xrows must be 0 or a power of two");
+  if (tz_set) {
+    c->tun.tz = t->tz;
+    c->tun.tz_auto = false;
+  } else if (c->dim == 3 && t->tz == 0) {
+    c->tun.tz_auto = true;
+  }
   c->tun.ygrid = t->ygrid;
   c->tun.tiles2d = c->dim == 2 ? t->tiles2d : 0;
-  c->tun.tiles3d = c->dim == 3 ? t->tiles3d : 0;
+  // tiles3d: like tz, the value in effect (as reported) keeps the automatic
+  // choice (which follows the material kind); another one fixes it, 0 restores it
+  if (c->dim == 3 && t->tiles3d != tiles3d_of(c, c->prec == JFFT_FP64)) c->tun.tiles3d = t->tiles3d;
   c->tun.xrows = t->xrows;
   c->tun.fused_control = t->fused_control ? 1 : 0;
   c->drop_graphs();
-  return JFFT_OK;
+  return c->dim == 3 && t->tz == 0 ? refresh_tz(c) : JFFT_OK;
 }
 
 jfft_status jfft_get_tunables(jfft_cell_t c, jfft_tunables *t) {

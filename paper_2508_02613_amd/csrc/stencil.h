@@ -62,8 +62,7 @@ struct Geo3 {
                 "four wavefronts: one thread per node of columns 1..TX, one per element");
 };
 constexpr int STENCIL3_THREADS = 256;
-// Default 3D block shape of the precision (the power-law tangent has shape 1
-// only).
+// Default 3D block shape of the precision.
 template <typename Real>
 constexpr int default_tiles3d() {
   return sizeof(Real) == 4 ? 2 : 1;
@@ -958,7 +957,6 @@ __global__ void __launch_bounds__(Geo3<SHAPE>::NT, (stencil3_waves_per_simd<Real
     k_stiffness3d(StencilArgs<Real> a) {
   using G = Geo3<SHAPE>;
   constexpr int NT = G::NT, TX = G::TX, TY = G::TY, EX = G::EX, NX = G::NX, NY = G::NY;
-  static_assert(SHAPE == 1 || MAT == 0, "the power-law tangent has shape 1 only");
   __shared__ Real P[3][3][G::NNODE];               // ring of three node planes of the input vector
   __shared__ Real U[MAT ? 3 : 1][3][MAT ? G::NNODE : 1];  // MAT: ring of the Newton iterate
   __shared__ Real Y[24][NT];                       // corner contributions of one element layer

@@ -78,6 +78,30 @@ def test_stiffness_rhs_diag_parity(shape):
     cell.close()
 
 
+@pytest.mark.parametrize("shape", [(8, 8, 8), (12, 10, 18), (16, 32, 24), (6, 4, 10), (2, 4, 6),
+                                   (4, 10, 60)])
+def test_stiffness_wide_block_parity(shape):
+    """The 32 x 6 node block of the 3D stiffness kernel (the FP32 default; here
+    selected for the FP64 kernels, which default to 16 x 14): K u and
+    Algorithm 2's probing diagonal (the kernel's comb mode) against the
+    oracle, on grids narrower than one block and with ragged tiles in x and
+    y."""
+    pkg = _pkg()
+    say(f"stiffness 32 x 6 blocks {shape}")
+    E = ji.uniform_random_field(shape, 1.0, 1e3, seed=sum(shape) + 1)
+    u = np.random.default_rng(3).standard_normal((3,) + shape)
+    cell = pkg.Cell(shape, pc=pkg.PC_GREEN_JACOBI)
+    cell.set_tunables(tiles3d=2)
+    assert cell.tunables()["tiles3d"] == 2
+    cell.set_diag_method("probing")
+    cell.set_material(E, nu=0.3)
+    Ku = cell.apply_stiffness(u).cpu().numpy()
+    assert relmax(Ku, oracle.stiffness(E, u, LAM, MU)) <= 1e-12
+    dr, _ = oracle.jacobi_diag(E, LAM, MU)
+    assert relmax(cell.jacobi_diag().cpu().numpy(), dr) <= 1e-13
+    cell.close()
+
+
 @pytest.mark.parametrize("shape", [(32, 32), (24, 20), (8, 8, 8), (12, 10, 18), (6, 4, 10),
                                    (2, 4, 6), (16, 16, 16)])
 @pytest.mark.parametrize("pc", [1, 2, 3])

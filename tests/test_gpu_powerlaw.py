@@ -52,16 +52,19 @@ def _set(cell, phase, prm=PRM):
 OP_CASES = [((12, 16, 18), None), ((16, 16, 16), None), ((10, 30, 20), (1.0, 1.5, 0.5))]
 
 
+@pytest.mark.parametrize("tiles3d", [1, 2])
 @pytest.mark.parametrize("shape,lengths", OP_CASES)
-def test_operators_match_oracle(shape, lengths):
+def test_operators_match_oracle(shape, lengths, tiles3d):
+    """Both 3D block shapes of the tangent kernel (16 x 14 and 32 x 6 nodes)."""
     pkg = _pkg()
-    say(f"power-law operators {shape} lengths={lengths}")
+    say(f"power-law operators {shape} lengths={lengths} tiles3d={tiles3d}")
     rng = np.random.default_rng(11)
     phase = 1.0 - ji.spherical_inclusions(shape, 3, 0.22, seed=2)
     u = 0.02 * rng.standard_normal((3,) + shape)
     p = rng.standard_normal((3,) + shape)
     macro = rng.uniform(-0.05, 0.05, 6)
     cell = _cell(pkg, shape, pkg.PC_GREEN_JACOBI, lengths)
+    cell.set_tunables(tiles3d=tiles3d)
     _set(cell, phase)
     f = cell.powerlaw_force(macro, u).cpu().numpy()
     Kp = cell.powerlaw_tangent(macro, u, p).cpu().numpy()

@@ -84,9 +84,13 @@ def test_tunables_validation():
         c.set_tunables(tiles3d=3)
     with pytest.raises(pkg.JfftError):
         c.set_tunables(tiles3d=-1)
+    tz_auto = t["tz"]
     c.set_tunables(tz=8, ygrid=300, xrows=2)
     assert c.tunables() == {"tz": 8, "ygrid": 300, "tiles2d": 0, "xrows": 2, "fused_control": 0,
                             "tiles3d": 1}
+    c.set_tunables(tz=0)  # back to the automatic choice
+    assert c.tunables()["tz"] == tz_auto
+    c.set_tunables(tz=8)
     c.set_tunables(tiles3d=2)
     assert c.tunables()["tiles3d"] == 2
     c.set_tunables(tiles3d=0)
@@ -194,3 +198,36 @@ def test_fused_control_matches_separate_launches(shape, prec, graph):
             assert k >= 10
             for a, b in zip(h1[i], h0[i]):
                 np.testing.assert_allclose(a[:k - 1], b[:k - 1], rtol=1e-9)
+
+
+def test_tz_follows_material_kind():
+    """The automatic z march: 32 planes for the FP32 32 x 6 block on a 256^3
+    cell, 16 for the 16 x 14 block (tz 0 re-makes the choice after a change
+    of block shape) and for the power-law tangent (re-chosen when the
+    material kind changes); a tz set explicitly stays."""
+    pkg = _pkg()
+    n = 256
+    shape = (n, n, n)
+    c = pkg.Cell(shape, precision=pkg.MIXED)
+    t = c.tunables()
+    say(f"256^3 mixed cell tunables {t}")
+    assert t["tiles3d"] == 2 and t["tz"] == 32
+    c.set_tunables(tiles3d=1)
+    assert c.tunables()["tz"] == 32  # a shape change alone keeps tz
+    c.set_tunables(tz=0)
+    assert c.tunables()["tz"] == 16
+    c.set_tunables(tiles3d=0, tz=0)
+    assert c.tunables()["tz"] == 32
+    phase = np.ones(shape)
+    phase[:, :, : n // 4] = 0.0
+    c.set_material_powerlaw(phase)
+    assert c.tunables()["tiles3d"] == 1 and c.tunables()["tz"] == 16
+    c.set_material(ji.grf_field((32, 32, 32), 10.0, seed=1, ell=0.2).repeat(8, 0).repeat(8, 1)
+                   .repeat(8, 2), nu=0.3)
+    assert c.tunables()["tiles3d"] == 2 and c.tunables()["tz"] == 32
+    c.set_tunables(tz=24)
+    c.set_material_powerlaw(phase)
+    assert c.tunables()["tz"] == 24
+    c.set_tunables(tz=0)
+    assert c.tunables()["tz"] == 16
+    c.close()
