@@ -1531,11 +1531,13 @@ __global__ void k_rhs(const Real *E, const double *F /* [d][2^d] */, Real *f, Re
   F = cshift(F, cell, cs);
   f = cshift(f, cell, cs);
   fabs_out = cshift(fabs_out, cell, cs);
-  const long long node = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= N) return;
-  const int ix = (int)(node % nx);
-  const int iy = (int)((node / nx) % ny);
-  const int iz = (int)(node / ((long long)nx * ny));
+  // 32-bit index arithmetic: a cell holds at most 512^3 nodes
+  const unsigned node = blockIdx.x * blockDim.x + threadIdx.x;
+  if ((long long)node >= N) return;
+  const unsigned row = node / (unsigned)nx;
+  const int ix = (int)(node - row * (unsigned)nx);
+  const int iz = (int)(row / (unsigned)ny);
+  const int iy = (int)(row - (unsigned)iz * (unsigned)ny);
   const int nloc = 1 << dim;
   double acc[3] = {0, 0, 0}, aab[3] = {0, 0, 0};
   for (int c = 0; c < nloc; ++c) {
@@ -1630,7 +1632,7 @@ __global__ void k_unit_force(double *F, const double *macro, int dim, double lam
 // form to sig[r][q][e] when sig != NULL, and per-block partial sums of
 // w sigma_q for the homogenised stress.  Element-parallel, one thread each.
 template <typename Real>
-__global__ void k_stress(const Real *u, const Real *E, const double *macro, double lam, double mu,
+__global__ void __launch_bounds__(256) k_stress(const Real *u, const Real *E, const double *macro, double lam, double mu,
                          double w, double ihx, double ihy, double ihz, int dim, int nx, int ny,
                          int nz, long long N, double *sig, double *partial /* [ds][nblocks] */,
                          long long cs, long long sig_cs, int tri) {
@@ -1641,25 +1643,36 @@ __global__ void k_stress(const Real *u, const Real *E, const double *macro, doub
   macro = cshift(macro, cell, cs);
   partial = cshift(partial, cell, cs);
   sig = cshift(sig, cell, sig_cs);
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // 32-bit index arithmetic (a cell holds at most 512^3 nodes); every loop
+  // over corners, components and Gauss points is unrolled so that the
+  // per-element arrays stay in registers
+  const unsigned eu = blockIdx.x * blockDim.x + threadIdx.x;
+  const long long e = eu;
   const int ds = dim == 3 ? 6 : 3;
   double loc[6] = {0, 0, 0, 0, 0, 0};
   const double r2 = 1.41421356237309504880;
   if (e < N) {
-    const int ix = (int)(e % nx), iy = (int)((e / nx) % ny), iz = (int)(e / ((long long)nx * ny));
+    const unsigned row = eu / (unsigned)nx;
+    const int ix = (int)(eu - row * (unsigned)nx);
+    const int iz = (int)(row / (unsigned)ny);
+    const int iy = (int)(row - (unsigned)iz * (unsigned)ny);
     const double Ee = (double)E[e];
     if (dim == 3) {
       double uv[3][8];
+#pragma unroll
       for (int c = 0; c < 8; ++c) {
         const long long nd = (long long)wrapi(ix + (c & 1), nx) +
                              (long long)nx * (wrapi(iy + ((c >> 1) & 1), ny) +
                                               (long long)ny * wrapi(iz + (c >> 2), nz));
+#pragma unroll
         for (int i = 0; i < 3; ++i) uv[i][c] = u ? (double)u[i * N + nd] : 0.0;
       }
       double dX[3][2][2], dY[3][2][2], dZ[3][2][2];
+#pragma unroll
       for (int i = 0; i < 3; ++i) grad_hex<double>(uv[i], ihx, ihy, ihz, dX[i], dY[i], dZ[i]);
       const double m11 = macro[0], m22 = macro[1], m33 = macro[2];
       const double m23 = macro[3] * r2, m13 = macro[4] * r2, m12 = macro[5] * r2;  // engineering
+#pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int gx = q & 1, gy = (q >> 1) & 1, gz = q >> 2;
         const double e11 = m11 + dX[0][gy][gz], e22 = m22 + dY[1][gx][gz],
@@ -1675,6 +1688,7 @@ __global__ void k_stress(const Real *u, const Real *E, const double *macro, doub
         s[3] = Ee * mu * g23 * r2;  // Mandel: sqrt2 sigma_23 = sqrt2 mu gamma_23
         s[4] = Ee * mu * g13 * r2;
         s[5] = Ee * mu * g12 * r2;
+#pragma unroll
         for (int r = 0; r < 6; ++r) {
           if (sig) sig[((long long)r * 8 + q) * N + e] = s[r];
           loc[r] += w * s[r];
@@ -1694,6 +1708,7 @@ __global__ void k_stress(const Real *u, const Real *E, const double *macro, doub
         const double ey[2] = {(uv[1][2] - uv[1][0]) * ihy, (uv[1][3] - uv[1][1]) * ihy};
         const double gg[2] = {(uv[0][2] - uv[0][0]) * ihy + (uv[1][1] - uv[1][0]) * ihx,
                               (uv[0][3] - uv[0][1]) * ihy + (uv[1][3] - uv[1][2]) * ihx};
+#pragma unroll
         for (int t = 0; t < 2; ++t) {
           const double e11 = macro[0] + ex[t], e22 = macro[1] + ey[t];
           const double g12 = macro[2] * r2 + gg[t];
@@ -1702,6 +1717,7 @@ __global__ void k_stress(const Real *u, const Real *E, const double *macro, doub
           s[0] = Ee * (lt + 2 * mu * e11);
           s[1] = Ee * (lt + 2 * mu * e22);
           s[2] = Ee * mu * g12 * r2;
+#pragma unroll
           for (int r = 0; r < 3; ++r) {
             if (sig) sig[((long long)r * 2 + t) * N + e] = s[r];
             loc[r] += 2.0 * w * s[r];
@@ -1717,6 +1733,7 @@ __global__ void k_stress(const Real *u, const Real *E, const double *macro, doub
           dY[i][g] *= ihy;
         }
       }
+#pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int gx = q & 1, gy = q >> 1;
         const double e11 = macro[0] + dX[0][gy], e22 = macro[1] + dY[1][gx];
@@ -1726,6 +1743,7 @@ __global__ void k_stress(const Real *u, const Real *E, const double *macro, doub
         s[0] = Ee * (lt + 2 * mu * e11);
         s[1] = Ee * (lt + 2 * mu * e22);
         s[2] = Ee * mu * g12 * r2;
+#pragma unroll
         for (int r = 0; r < 3; ++r) {
           if (sig) sig[((long long)r * 4 + q) * N + e] = s[r];
           loc[r] += w * s[r];
@@ -1734,9 +1752,12 @@ __global__ void k_stress(const Real *u, const Real *E, const double *macro, doub
       }
     }
   }
-  for (int r = 0; r < ds; ++r) {
-    const double s = block_sum<256>(loc[r], red);
-    if (threadIdx.x == 0) partial[(long long)r * gridDim.x + blockIdx.x] = s;
+#pragma unroll
+  for (int r = 0; r < 6; ++r) {
+    if (r < ds) {  // uniform
+      const double s = block_sum<256>(loc[r], red);
+      if (threadIdx.x == 0) partial[(long long)r * gridDim.x + blockIdx.x] = s;
+    }
   }
 }
 
