@@ -977,7 +977,34 @@ __global__ void __launch_bounds__(Geo3<SHAPE>::NT, (stencil3_waves_per_simd<Real
   const int zend = min(z0 + a.tz, a.nz);
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const long long N = a.N;
-  const long long plane = (long long)nx * ny;
+  // Addresses: a uniform base per array and component, held in scalar
+  // registers, plus a 32-bit byte offset per node (a cell holds at most
+  // 512^3 nodes, so offsets stay below 2^32 even in FP64): every access is a
+  // scalar-base load or store with one vector offset shared by the arrays,
+  // instead of a 64-bit address per array and component.  The empty asm
+  // keeps each base opaque, so that the compiler does not fold the component
+  // stride back into the vector address.
+  const unsigned uplane = (unsigned)nx * (unsigned)ny;
+  typedef __attribute__((address_space(1))) char gchar;  // global memory
+  struct Bases {
+    gchar *p[3];
+  };
+  auto bases = [&](const Real *p) {
+    Bases b;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      gchar *q = (gchar *)(const_cast<Real *>(p) + (long long)c * N);
+      asm volatile("" : "+s"(q));
+      b.p[c] = q;
+    }
+    return b;
+  };
+  auto ld = [&](const Bases &b, int c, unsigned off) -> Real {
+    return *reinterpret_cast<const __attribute__((address_space(1))) Real *>(b.p[c] + off);
+  };
+  auto st = [&](const Bases &b, int c, unsigned off, Real v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<__attribute__((address_space(1))) Real *>(b.p[c] + off));
+  };
 
   bool first = false;
   Real beta = 0, alpha_prev = 0;
@@ -993,7 +1020,8 @@ __global__ void __launch_bounds__(Geo3<SHAPE>::NT, (stencil3_waves_per_simd<Real
   const int gex = x0 - 1 + exl, gey = y0 - 1 + eyl;
   const bool elem_valid = gex < nx && gey < ny;
   const bool elem_owned = elem_valid && exl >= 1 && eyl >= 1 && tid < G::NELEM;
-  const long long exy = (long long)wrapi(gex, nx) + (long long)nx * wrapi(gey, ny);
+  const unsigned exy_b = ((unsigned)wrapi(gex, nx) + (unsigned)nx * (unsigned)wrapi(gey, ny)) *
+                        (unsigned)sizeof(Real);
   const int lie = eyl * NX + exl;  // corner (0, 0) of the element in a node plane
   // output node (ox + 1, oy + 1); its x-y neighbouring elements are e00,
   // e00 + 1, e00 + EX and e00 + EX + 1
@@ -1004,13 +1032,13 @@ __global__ void __launch_bounds__(Geo3<SHAPE>::NT, (stencil3_waves_per_simd<Real
   // node slot 0: node (ox + 1, oy) of the plane, global (x0 + ox, y0 - 1 + oy)
   const int li0 = oy * NX + ox + 1;
   const int w0x = wrapi(x0 + ox, nx), w0y = wrapi(y0 - 1 + oy, ny);
-  const long long n0xy = (long long)w0x + (long long)nx * w0y;
+  const unsigned n0xy = (unsigned)w0x + (unsigned)nx * (unsigned)w0y;
   const bool own0 = oy >= 1 && oy <= TY && x0 + ox < nx && y0 - 1 + oy < ny;
   const int par0 = (w0x & 1) | ((w0y & 1) << 1);
   // u is read for every slot-0 node (so that the loads need no branch); a
   // halo row reads its owned neighbour row instead, and discards the value
-  const long long u0xy =
-      (long long)w0x + (long long)nx * wrapi(y0 - 1 + min(max(oy, 1), TY), ny);
+  const unsigned u0xy =
+      (unsigned)w0x + (unsigned)nx * (unsigned)wrapi(y0 - 1 + min(max(oy, 1), TY), ny);
   // node slot 1 (threads 0 .. 2 NY - 1): column 0, then column NX - 1; the
   // other threads load node (0, 0) again (one cache line per wavefront) and
   // discard it
@@ -1019,7 +1047,7 @@ __global__ void __launch_bounds__(Geo3<SHAPE>::NT, (stencil3_waves_per_simd<Real
   const int s1y = has1 ? tid % NY : 0;
   const int li1 = s1y * NX + s1x;
   const int w1x = wrapi(x0 - 1 + s1x, nx), w1y = wrapi(y0 - 1 + s1y, ny);
-  const long long n1xy = (long long)w1x + (long long)nx * w1y;
+  const unsigned n1xy = (unsigned)w1x + (unsigned)nx * (unsigned)w1y;
   const int par1 = (w1x & 1) | ((w1y & 1) << 1);
 
   // One prefetched plane in registers (z or the APPLY input, p_old and u
@@ -1030,34 +1058,39 @@ __global__ void __launch_bounds__(Geo3<SHAPE>::NT, (stencil3_waves_per_simd<Real
   // issued unconditionally at a valid address and masked at the commit: with
   // no load under a branch the compiler knows the exact number of memory
   // operations in flight and waits only for the ones a value needs.
+  const Bases b_in = bases(a.in), b_zin = bases(MODE == SM_CG ? a.zin : a.in);
+  const Bases b_u = bases(MODE == SM_CG ? a.u : a.in), b_pout = bases(MODE == SM_CG ? a.pout : a.in);
+  const Bases b_out = bases(MODE == SM_COMB ? a.in : a.out), b_uk = bases(MAT ? a.uk : a.in);
+  const Bases b_E = bases(a.E);
   Real fz[3], fp[3], fu[3], hz[3], hp[3], ku[3], kh[3];
   auto fetch0 = [&](int zp) {
-    const long long node0 = (long long)wrapi(zp, nz) * plane + n0xy;
+    const unsigned o0 = ((unsigned)wrapi(zp, nz) * uplane + n0xy) * (unsigned)sizeof(Real);
     // owned u lies in planes z0 .. zend - 1 (< nz, no wrap)
-    const long long nodeu = (long long)min(max(zp, z0), zend - 1) * plane + u0xy;
+    const unsigned ou =
+        ((unsigned)min(max(zp, z0), zend - 1) * uplane + u0xy) * (unsigned)sizeof(Real);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (MODE == SM_APPLY) {
-        fz[c] = a.in[c * N + node0];
+        fz[c] = ld(b_in, c, o0);
       } else if (MODE == SM_CG) {
-        fz[c] = a.zin[c * N + node0];
-        fp[c] = a.in[c * N + node0];
-        fu[c] = a.u[c * N + nodeu];
+        fz[c] = ld(b_zin, c, o0);
+        fp[c] = ld(b_in, c, o0);
+        fu[c] = ld(b_u, c, ou);
       }
-      if (MAT) ku[c] = a.uk[c * N + node0];
+      if (MAT) ku[c] = ld(b_uk, c, o0);
     }
   };
   auto fetch1 = [&](int zp) {
-    const long long node1 = (long long)wrapi(zp, nz) * plane + n1xy;
+    const unsigned o1 = ((unsigned)wrapi(zp, nz) * uplane + n1xy) * (unsigned)sizeof(Real);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (MODE == SM_APPLY) {
-        hz[c] = a.in[c * N + node1];
+        hz[c] = ld(b_in, c, o1);
       } else if (MODE == SM_CG) {
-        hz[c] = a.zin[c * N + node1];
-        hp[c] = a.in[c * N + node1];
+        hz[c] = ld(b_zin, c, o1);
+        hp[c] = ld(b_in, c, o1);
       }
-      if (MAT) kh[c] = a.uk[c * N + node1];
+      if (MAT) kh[c] = ld(b_uk, c, o1);
     }
   };
   auto fetch = [&](int zp) {
@@ -1066,7 +1099,7 @@ __global__ void __launch_bounds__(Geo3<SHAPE>::NT, (stencil3_waves_per_simd<Real
   };
   auto commit = [&](int zp, int slot) {
     const int wz = wrapi(zp, nz);
-    const long long node0 = (long long)wz * plane + n0xy;
+    const unsigned o0 = ((unsigned)wz * uplane + n0xy) * (unsigned)sizeof(Real);
     const bool owned = (zp >= z0) && (zp < zend) && own0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -1083,8 +1116,8 @@ __global__ void __launch_bounds__(Geo3<SHAPE>::NT, (stencil3_waves_per_simd<Real
         v = first ? fz[c] : fz[c] + beta * fp[c];
         w = first ? hz[c] : hz[c] + beta * hp[c];
         if (owned) {
-          if (!first) st_stream(&a.u[c * N + node0], fu[c] + alpha_prev * fp[c]);
-          st_stream(&a.pout[c * N + node0], v);
+          if (!first) st(b_u, c, o0, fu[c] + alpha_prev * fp[c]);
+          st(b_pout, c, o0, v);
         }
       }
       P[slot][c][li0] = v;
@@ -1107,7 +1140,10 @@ __global__ void __launch_bounds__(Geo3<SHAPE>::NT, (stencil3_waves_per_simd<Real
   // cubic elements: the bottom face of the next element (its node values and
   // in-plane differences) is this element's top face, carried in registers
   Real fbot[3][4], fbotF[3][4];
-  long long qnode = -1;  // pending output node (stored at the next layer's top)
+  // pending output node (stored at the next layer's top): its index, valid
+  // while qpending
+  unsigned qnode = 0;
+  bool qpending = false;
   fetch(z0 - 1);
   commit(z0 - 1, ring(z0 - 1));
   fetch(z0);
@@ -1115,18 +1151,18 @@ __global__ void __launch_bounds__(Geo3<SHAPE>::NT, (stencil3_waves_per_simd<Real
   fetch(z0 + 1);  // layer z0 always exists and reads plane z0 + 1
   // the modulus is loaded for every thread and layer (the wrapped address is
   // always valid) and masked at use, so no register is conditionally loaded
-  Real Enext = a.E[(long long)wrapi(z0 - 1, nz) * plane + exy];
+  Real Enext = ld(b_E, 0, (unsigned)wrapi(z0 - 1, nz) * uplane * (unsigned)sizeof(Real) + exy_b);
   const Real emask = elem_valid ? (Real)1 : (Real)0;
   __syncthreads();
   auto flush_q = [&]() {
-    if (qnode < 0) return;
+    if (!qpending) return;
     if (MODE == SM_COMB) {
       a.diag[a.comb_comp * N + qnode] = qpend[0];
     } else {
 #pragma unroll
-      for (int i = 0; i < 3; ++i) st_stream(&a.out[i * N + qnode], qpend[i]);
+      for (int i = 0; i < 3; ++i) st(b_out, i, qnode * (unsigned)sizeof(Real), qpend[i]);
     }
-    qnode = -1;
+    qpending = false;
   };
   for (int ez = z0 - 1; ez < zend; ++ez) {
     const int s0 = ring(ez), s1 = ring(ez + 1);
@@ -1143,7 +1179,7 @@ __global__ void __launch_bounds__(Geo3<SHAPE>::NT, (stencil3_waves_per_simd<Real
       fetch0(ez + 3);
       if (sizeof(Real) == 4) fetch1(ez + 3);  // FP32: the strip one layer ahead as well
     }
-    Enext = a.E[(long long)wrapi(ez + 1, nz) * plane + exy];
+    Enext = ld(b_E, 0, (unsigned)wrapi(ez + 1, nz) * uplane * (unsigned)sizeof(Real) + exy_b);
     if constexpr (CUBIC && MAT == 0 && sizeof(Real) == 4) {
       // (FP32 only: in FP64 the 24 carried registers would halve occupancy)
       Real top[3][4], topF[3][4], yv[3][8];
@@ -1223,15 +1259,17 @@ __global__ void __launch_bounds__(Geo3<SHAPE>::NT, (stencil3_waves_per_simd<Real
         for (int i = 0; i < 3; ++i)
           qpend[i] = carry[i] + Y[3 * 3 + i][e00] + Y[2 * 3 + i][e00 + 1] +
                      Y[1 * 3 + i][e00 + EX] + Y[0 * 3 + i][e00 + EX + 1];
-        const long long node = (long long)gnx + (long long)nx * (gny + (long long)ny * ez);
+        const unsigned node = (unsigned)ez * uplane + (unsigned)gny * (unsigned)nx + (unsigned)gnx;
         if (MODE == SM_COMB) {
           const int par = (gnx & 1) | ((gny & 1) << 1) | ((ez & 1) << 2);
           if (par == a.comb_off) {
             qpend[0] = qpend[a.comb_comp];
             qnode = node;
+            qpending = true;
           }
         } else {
           qnode = node;
+          qpending = true;
         }
       }
 #pragma unroll
